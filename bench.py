@@ -1,0 +1,189 @@
+"""Benchmark: weighted minwise hashes/s at k=500 on the histogram-shaped workload
+(N=100000 rows, D=4096, each cell nonzero with probability 0.3, LogNormal(0,1) weights in Q8.8),
+batched persistent launch vs plain one-launch-per-8192-rows, on one GPU.
+
+A step is one wmh_hash call over the whole batch (validation, shared position stream, walk),
+with the rows already resident in HBM.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_INT_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3
+HBM_PEAK_GBS = 8000.0
+OPS_PER_TEST = 2  # one lookup of x at the draw's component and one compare
+
+
+def log(msg: str):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--rows", type=int, default=100_000)
+    ap.add_argument("--plain-steps", type=int, default=None,
+                    help="timed steps of the plain form (default: same as --steps, at most 5)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle sample")
+    ap.add_argument("--rows-per-block", type=int, default=0)
+    ap.add_argument("--hashes-per-tile", type=int, default=0)
+    ap.add_argument("--stream-depth", type=int, default=0)
+    ap.add_argument("--waves-per-block", type=int, default=0)
+    ap.add_argument("--only", choices=["batched", "plain", "both"], default="both")
+    return ap.parse_args()
+
+
+def timed_steps(ctx, rows, k, sig, opts, steps, warmup, torch):
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        ctx.hash_into(rows, k, 0, sig, opts=opts)
+    torch.cuda.synchronize()
+    walk = []
+    build = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.hash_into(rows, k, 0, sig, stream=stream.cuda_stream, opts=opts)
+        if opts.profile:
+            w, s = ctx.last_kernel_ms()
+            walk.append(w)
+            build.append(s)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    return elapsed, walk, build
+
+
+def cpu_baseline(ds, k, target_s):
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    n = 64
+    sample = ds.head(n)
+    t0 = time.perf_counter()
+    oracle.hash_csr(sample.m, sample.row_ptr, sample.col, sample.val, k, seed=0, threads=threads)
+    dt = time.perf_counter() - t0
+    n = int(min(ds.n_rows, max(n, n * target_s / max(dt, 1e-3))))
+    n = max(threads, n - n % threads)
+    sample = ds.head(n)
+    t0 = time.perf_counter()
+    sig, steps = oracle.hash_csr(sample.m, sample.row_ptr, sample.col, sample.val, k, seed=0,
+                                 threads=threads, return_steps=True)
+    dt = time.perf_counter() - t0
+    return {"value": n * k / dt, "unit": "hashes/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} rows of the workload, k={k} ({steps} membership tests, "
+                      f"{dt:.1f} s, {steps / dt:.3g} tests/s)"}, sig
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the hash walk "
+              "shards by rows with no exchange step, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1602_08393_amd import synth, wmh
+
+    if not os.path.exists(wmh.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    t = time.perf_counter()
+    ds = synth.config2(n_rows=args.rows)
+    k = ds.k
+    log(f"generated {ds.name}: N={ds.n_rows} D={ds.D} nnz={ds.nnz} in {time.perf_counter() - t:.1f}s")
+    ctx = wmh.Context(0)
+    ctx.set_bounds(ds.m)
+    rows = wmh.upload_dataset(ds, "cuda:0")
+    sig = torch.empty((ds.n_rows, k), dtype=torch.int16, device="cuda:0")
+    sig_plain = torch.empty_like(sig)
+    M = int(ds.m.astype(np.uint64).sum())
+    hashes = ds.n_rows * k
+
+    plan = dict(rows_per_block=args.rows_per_block, hashes_per_tile=args.hashes_per_tile,
+                stream_depth=args.stream_depth, waves_per_block=args.waves_per_block)
+    result = {}
+    if args.only in ("batched", "both"):
+        opts = ctx.make_opts(mode="batched", profile=True, **plan)
+        log("batched: warmup + timed steps")
+        el, walk, build = timed_steps(ctx, rows, k, sig, opts, args.steps, args.warmup, torch)
+        result["batched"] = (el, walk, build)
+        log(f"batched: {el / args.steps * 1e3:.3f} ms/step, walk kernel "
+            f"{np.mean(walk):.3f} ms, stream build {np.mean(build):.3f} ms")
+    if args.only in ("plain", "both"):
+        psteps = args.plain_steps or min(args.steps, 5)
+        opts = ctx.make_opts(mode="plain", profile=True)
+        log("plain: warmup + timed steps")
+        el, walk, _ = timed_steps(ctx, rows, k, sig_plain, opts, psteps, 1, torch)
+        result["plain"] = (el, walk, psteps)
+        log(f"plain: {el / psteps * 1e3:.3f} ms/step, walk kernels {np.mean(walk):.3f} ms")
+
+    main_key = "batched" if "batched" in result else "plain"
+    steps = args.steps if main_key == "batched" else result["plain"][2]
+    el, walk, _ = result[main_key][:3]
+    value = hashes * steps / el
+    out_sig = sig if main_key == "batched" else sig_plain
+    sig_np = wmh.sig_to_numpy(out_sig)
+    tests = int(sig_np.astype(np.int64).sum())  # exact membership tests of one step
+    walk_s = float(np.mean(walk)) / 1e3
+    achieved = OPS_PER_TEST * tests / walk_s / 1e12
+    line = {
+        "metric": "weighted minwise hashes/sec at k=500 (batched vs plain, bit-exact)",
+        "value": value,
+        "unit": "hashes/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "histogram-shaped: N=100000 rows, D=4096, cell density 0.3, "
+                               "LogNormal(0,1) weights in Q8.8, bounds = dataset max, k=500, "
+                               "seed 0",
+                   "N": ds.n_rows, "D": ds.D, "k": k, "nnz": ds.nnz, "M": M,
+                   "mode": main_key},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS,
+                     "unit": "TOP/s", "frac": achieved / PEAK_INT_TOPS, "traffic": None,
+                     "kernel": "batched_kernel" if main_key == "batched" else "plain_kernel",
+                     "kernel_ms": walk_s * 1e3, "membership_tests": tests,
+                     "ops_per_test": OPS_PER_TEST},
+        "mean_steps_per_hash": tests / hashes,
+    }
+    if "batched" in result and "plain" in result:
+        pel, pwalk, psteps = result["plain"]
+        plain_value = hashes * psteps / pel
+        same = bool(torch.equal(sig, sig_plain))
+        line["plain"] = {"value": plain_value, "ms_per_step": pel / psteps * 1e3,
+                         "walk_ms": float(np.mean(pwalk)), "steps": psteps}
+        line["batched_over_plain"] = value / plain_value
+        line["batched_equals_plain"] = same
+        bel, bwalk, bbuild = result["batched"]
+        line["batched_detail"] = {"walk_ms": float(np.mean(bwalk)),
+                                  "stream_build_ms": float(np.mean(bbuild))}
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on a sample")
+        cb, want = cpu_baseline(ds, k, args.cpu_seconds)
+        line["cpu_baseline"] = cb
+        line["sample_bit_exact"] = bool(np.array_equal(sig_np[: want.shape[0]], want))
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,200 @@
+/*
+ * wmh.h -- C-ABI of libwmh: red-green weighted minwise hashing on AMD Instinct MI355X (gfx950).
+ *
+ * Method: A. Shrivastava, "Exact Weighted Minwise Hashing in Constant Time" (arXiv 1602.08393).
+ * For a non-negative vector x with per-dimension integer bounds m_i, the interval [0, M),
+ * M = sum m_i, is cut into D pieces of size m_i; piece i is green on its first x_i units and red
+ * on the rest (Sec. 3.1, eq. redGreen).  Hash j of x is the 1-based index of the first position,
+ * in a random sequence shared by every vector, that lands in x's green region (Algorithm 3,
+ * Definition 1).  Two vectors collide on a hash with probability equal to their generalized
+ * Jaccard similarity (eq. 1, Theorem 1); the collision count over k hashes estimates it
+ * (eq. Estimator).
+ *
+ * Exact definition computed by this library (bit-exact, no floating point):
+ *   P[0] = 0, P[i+1] = P[i] + m[i] (uint64), M = P[D] >= 1.
+ *   Position of step t >= 1 of hash j: for attempt a = 0, 1, ...:
+ *     W = Philox4x32-10(key = (seed & 0xffffffff, seed >> 32), counter = ((t-1)/2, j, a, 0));
+ *     u = (W1 << 32 | W0) for odd t, (W3 << 32 | W2) for even t;
+ *     prod = u * M (128-bit); accept iff (prod mod 2^64) >= (2^64 mod M); p = prod >> 64.
+ *   c(p) = max{i : P[i] <= p}; p is green for x iff p - P[c(p)] < x[c(p)].
+ *   h_j(x) = first green t, capped at 65535 (the walk stops there); 0 for every j if sum x = 0.
+ *
+ * Conventions for every call:
+ *   - Every function returns a wmh_status and never throws or aborts across the ABI.
+ *   - "device" pointers are HIP device allocations on the context's device (e.g. the
+ *     data_ptr() of a torch tensor on that device); "host" pointers are ordinary host memory.
+ *   - The caller owns every buffer it passes; the library keeps no reference after the call
+ *     returns, except the bounds, which wmh_set_bounds copies into the context.
+ *   - `stream` is a hipStream_t of the context's device, or NULL for the context's own stream.
+ *   - A context is not thread-safe: use one context per host thread, or serialize calls.
+ *   - On any error the output buffers are left untouched (validation precedes every write),
+ *     and wmh_last_error() describes the failure (first offending row / column where known).
+ */
+#ifndef WMH_H
+#define WMH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WMH_CAP 65535u /* largest hash value; the walk stops at this step */
+
+typedef struct wmh_ctx wmh_ctx;
+
+typedef enum {
+    WMH_OK = 0,
+    WMH_E_ARG = -1,        /* invalid argument (null pointer, k = 0, sizes out of range) */
+    WMH_E_NO_BOUNDS = -2,  /* wmh_hash before wmh_set_bounds */
+    WMH_E_COL_RANGE = -3,  /* a column index >= D */
+    WMH_E_UNSORTED = -4,   /* columns of a row not strictly increasing */
+    WMH_E_BOUND = -5,      /* a value x_i above its bound m_i (never clamped) */
+    WMH_E_OVERFLOW = -6,   /* bounds sum to 0, or sizes overflow */
+    WMH_E_NOMEM = -7,      /* device or host allocation failed */
+    WMH_E_DEVICE = -8,     /* a HIP runtime error */
+    WMH_E_ROW_PTR = -9     /* row_ptr decreasing, or row_ptr[N] > nnz */
+} wmh_status;
+
+/* Scheduling of wmh_hash.  Every mode returns identical signatures. */
+typedef enum {
+    WMH_MODE_AUTO = 0,     /* the batched persistent path with the planner's choice of tiles */
+    WMH_MODE_PLAIN = 1,    /* one launch per batch of `batch_rows` rows, a workgroup per row
+                              group, each lane walking its own (row, hash) with its own draws */
+    WMH_MODE_BATCHED = 2   /* one persistent launch over (row block, hash block) tiles; each
+                              draw is shared by the rows of a block (see wmh_hash) */
+} wmh_mode;
+
+typedef struct {
+    int32_t mode;          /* wmh_mode; default WMH_MODE_AUTO */
+    uint32_t batch_rows;   /* plain mode: rows per launch; 0 = 8192 */
+    int32_t validate;      /* 1 (default): validate the CSR input before hashing */
+    int32_t use_graph;     /* batched mode: 1 (default) replay a captured hipGraph */
+    int32_t sync;          /* 1 (default): wait for completion before returning */
+    /* batched-mode tile plan overrides; 0 = planner / autotuner choice */
+    uint32_t rows_per_block;   /* R: rows whose dense rows share one walk (1, 2, 4, 8, 16) */
+    uint32_t hashes_per_tile;  /* J: hash ids per tile */
+    uint32_t stream_depth;     /* T0: steps of the shared position stream built per call;
+                                  steps beyond it are drawn in-lane.  UINT32_MAX disables it */
+    uint32_t waves_per_block;  /* wavefronts per workgroup (1..16) */
+    int32_t profile;           /* 1: time the walk kernels with HIP events on the launch stream
+                                  (read back with wmh_last_kernel_ms) */
+    uint32_t reserved[5];
+} wmh_opts;
+
+/* Fills *opts with the defaults listed above. */
+void wmh_opts_init(wmh_opts *opts);
+
+/* Creates a context on HIP device `device` (which becomes current for the calling thread). */
+wmh_status wmh_create(int device, wmh_ctx **out);
+
+/* Releases the context and every device buffer it owns.  NULL is ignored. */
+void wmh_destroy(wmh_ctx *ctx);
+
+/*
+ * wmh_set_bounds -- one-time preprocessing of the dataset bounds (Sec. 3.1; Algorithm 4).
+ *   m : host, D entries, the integer upper bound m_i of dimension i (0 allowed: an empty piece).
+ *   D : number of dimensions, 1 <= D <= 2^26.
+ * Builds on the device the prefix sums P[0..D] (uint64), the total M = P[D] (must be >= 1),
+ * the uniform bucket table T over [0, M) used for the O(1) position-to-component lookup
+ * (Algorithm 5), and the bounded-draw threshold 2^64 mod M.  Replaces earlier bounds.
+ * Synchronous.  Errors: WMH_E_ARG (null, D out of range), WMH_E_OVERFLOW (M = 0),
+ * WMH_E_NOMEM, WMH_E_DEVICE.
+ */
+wmh_status wmh_set_bounds(wmh_ctx *ctx, const uint32_t *m, uint32_t D);
+
+/*
+ * wmh_hash -- k weighted minwise hashes of each of N CSR rows (Algorithm 3, Definition 1).
+ *   row_ptr : device, N+1 entries (uint64); row r is entries [row_ptr[r], row_ptr[r+1]).
+ *   col     : device, nnz entries (uint32), strictly increasing within a row, < D.
+ *   val     : device, nnz entries (uint32 fixed point), val <= m[col]; 0 allowed (red).
+ *   n_rows  : N (0 allowed: nothing to do).   nnz : length of col and val.
+ *   k       : hashes per row, 1 <= k <= 2^24.   seed : the 64-bit key of the random sequence.
+ *   sig     : device, N*k uint16, row-major: sig[r*k + j] = h_j(row r); 0 for empty rows.
+ *   stream  : hipStream_t or NULL.   opts : NULL for defaults.
+ * The hash sequence depends only on (seed, j, t) and the bounds, never on the row, so rows can
+ * be hashed in any grouping and order with identical results, and the signature for k1 < k2
+ * is a prefix of the one for k2.
+ * With opts->validate (default) the rows are checked on the device first and the call waits
+ * for the verdict; on failure sig is untouched.  Errors: WMH_E_NO_BOUNDS, WMH_E_ARG,
+ * WMH_E_ROW_PTR, WMH_E_COL_RANGE, WMH_E_UNSORTED, WMH_E_BOUND, WMH_E_NOMEM, WMH_E_DEVICE.
+ * Without validation, invalid input gives unspecified signatures but never an out-of-bounds
+ * access as long as row_ptr is non-decreasing with row_ptr[N] <= nnz.
+ */
+wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
+                    const uint32_t *val, uint64_t n_rows, uint64_t nnz, uint32_t k,
+                    uint64_t seed, uint16_t *sig, void *stream, const wmh_opts *opts);
+
+/*
+ * wmh_draws -- the position sequence itself and its component lookup (Algorithm 3's draws,
+ * Algorithm 5's ISGREEN lookup), as the hash kernels compute them.  For hash ids
+ * j0 <= j < j0 + n_hashes and steps 1 <= t <= depth, with i = (j - j0) * depth + t - 1:
+ *   pos[i] = position of step t of hash j,  comp[i] = c(pos[i]),  off[i] = pos[i] - P[comp[i]].
+ *   pos, comp, off : device buffers of n_hashes*depth entries (uint64, uint32, uint64); any
+ *                    may be NULL.   Requires bounds.  Synchronous.
+ * Errors: WMH_E_NO_BOUNDS, WMH_E_ARG (depth = 0 or > 65536, n_hashes = 0, j0 + n_hashes >
+ * 2^32), WMH_E_DEVICE.
+ */
+wmh_status wmh_draws(wmh_ctx *ctx, uint64_t seed, uint32_t j0, uint32_t n_hashes, uint32_t depth,
+                     uint64_t *pos, uint32_t *comp, uint64_t *off, void *stream);
+
+/*
+ * wmh_estimate -- collision-count estimates for row-aligned pairs (eq. Estimator):
+ *   count[i] = #{j < k : A[i*k + j] == B[i*k + j]},  jhat[i] = count[i] / k (IEEE double).
+ *   A, B  : device, n_pairs*k uint16 signatures.   count : device, n_pairs uint32 (or NULL).
+ *   jhat  : device, n_pairs double (or NULL).       stream : hipStream_t or NULL.
+ * Two empty rows (all-zero signatures) give jhat = 1.  Synchronous.
+ * Errors: WMH_E_ARG, WMH_E_DEVICE.
+ */
+wmh_status wmh_estimate(wmh_ctx *ctx, const uint16_t *A, const uint16_t *B, uint64_t n_pairs,
+                        uint32_t k, uint32_t *count, double *jhat, void *stream);
+
+/*
+ * wmh_collisions -- all-pairs collision counts (eq. Estimator's numerator):
+ *   counts[a*NB + b] = #{j < k : A[a*k + j] == B[b*k + j]}  (exact uint32).
+ *   A : device, NA*k uint16.  B : device, NB*k uint16.  counts : device, NA*NB uint32.
+ * Synchronous.  Errors: WMH_E_ARG, WMH_E_DEVICE.
+ */
+wmh_status wmh_collisions(wmh_ctx *ctx, const uint16_t *A, uint64_t NA, const uint16_t *B,
+                          uint64_t NB, uint32_t k, uint32_t *counts, void *stream);
+
+/*
+ * wmh_bounds_tables -- host-only: the tables wmh_set_bounds uploads (Sec. 3.1; Algorithm 4).
+ *   m, D      : as for wmh_set_bounds (host).
+ *   prefix    : host, D+1 uint64 (or NULL): P[0] = 0, P[i+1] = P[i] + m[i].
+ *   bucket    : host, n_buckets+1 uint32 (or NULL): T[b] = max{i < D : P[i] <= b << shift}.
+ *   shift     : out, log2 of the bucket width; the smallest shift giving at most
+ *               2 * 2^ceil(log2 D) buckets (at least 4).
+ *   n_buckets : out, ceil(M / 2^shift).   threshold : out, 2^64 mod M.
+ * Call first with prefix = bucket = NULL to learn n_buckets.  No device is touched.
+ * Errors: WMH_E_ARG, WMH_E_OVERFLOW (M = 0).
+ */
+wmh_status wmh_bounds_tables(const uint32_t *m, uint32_t D, uint64_t *prefix, uint32_t *bucket,
+                             uint32_t *shift, uint64_t *n_buckets, uint64_t *threshold);
+
+/*
+ * wmh_last_kernel_ms -- device time of the last wmh_hash call made with opts->profile = 1,
+ * from HIP events recorded on the launch stream: *walk_ms spans the hash-walk kernels (the
+ * batched kernel, or every plain launch), *stream_ms the shared-stream build (0 if none).
+ * Requires that call to have completed (opts->sync, or a later synchronization).
+ * Errors: WMH_E_ARG (no profiled call yet), WMH_E_DEVICE.
+ */
+wmh_status wmh_last_kernel_ms(wmh_ctx *ctx, float *walk_ms, float *stream_ms);
+
+/* Bounds summary after wmh_set_bounds: D, M, bucket shift and bucket count (any may be NULL). */
+wmh_status wmh_bounds_info(const wmh_ctx *ctx, uint32_t *D, uint64_t *M, uint32_t *shift,
+                           uint64_t *n_buckets);
+
+/* Human-readable detail of the last failure on this context ("" if none).  Valid until the
+ * next call on the context. */
+const char *wmh_last_error(const wmh_ctx *ctx);
+
+/* Name of a status code. */
+const char *wmh_status_string(wmh_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WMH_H */

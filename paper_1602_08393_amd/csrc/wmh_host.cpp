@@ -1,0 +1,566 @@
+// Host side of libwmh: the C-ABI declared in include/wmh.h.
+//
+// wmh_set_bounds does the paper's one-time preprocessing (Sec. 3.1; Algorithm 4): prefix sums
+// of the bounds and a lookup structure from positions to components.  Algorithm 4 stores one
+// entry per integer of [0, M), which is infeasible here (M reaches 2^40), so the lookup is a
+// uniform bucket table: bucket b covers positions [b << shift, (b+1) << shift) and stores the
+// component owning its first position; with about two buckets per dimension the search inside
+// a bucket is O(1) expected.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/wmh.h"
+#include "wmh_internal.h"
+
+using namespace wmh;
+
+namespace {
+
+constexpr uint32_t kMaxDims = 1u << 26;
+constexpr uint32_t kMaxK = 1u << 24;
+constexpr uint64_t kStreamBudgetBytes = 1ull << 30;  // shared position stream, at most 1 GiB
+
+struct GraphKey {
+    const void *row_ptr = nullptr, *col = nullptr, *val = nullptr;
+    void *sig = nullptr;
+    uint64_t n_rows = 0, nnz = 0, seed = 0;
+    uint32_t k = 0, R = 0, J = 0, depth = 0, waves = 0, grid = 0;
+    bool narrow = false;
+    bool profile = false;
+    uint64_t bounds_epoch = 0;
+    bool operator==(const GraphKey &o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
+};
+
+}  // namespace
+
+struct wmh_ctx {
+    int device = 0;
+    hipStream_t own_stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+    int cu_count = 0;
+    // bounds
+    bool has_bounds = false;
+    uint64_t bounds_epoch = 0;
+    uint32_t dims = 0;
+    uint64_t total = 0;
+    uint64_t threshold = 0;
+    uint32_t shift = 0;
+    uint64_t n_buckets = 0;
+    uint32_t max_bound = 0;
+    uint64_t *d_prefix = nullptr;
+    uint32_t *d_bucket = nullptr;
+    uint32_t *d_bound = nullptr;
+    // per-call scratch
+    CheckWords *d_check = nullptr;
+    CheckWords *h_check = nullptr;  // pinned
+    uint32_t *d_tile_counter = nullptr;
+    StreamEntry *d_stream = nullptr;
+    size_t stream_bytes = 0;
+    // graph of the batched launch
+    hipGraphExec_t graph_exec = nullptr;
+    GraphKey graph_key;
+    // profiling events: [0] before the stream build, [1] before the walk, [2] after the walk
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    bool profiled = false;
+    bool profiled_stream = false;
+    std::string last_error;
+};
+
+namespace {
+
+wmh_status fail(wmh_ctx *ctx, wmh_status st, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        ctx->last_error = buf;
+    }
+    return st;
+}
+
+wmh_status device_fail(wmh_ctx *ctx, hipError_t e, const char *what)
+{
+    return fail(ctx, e == hipErrorOutOfMemory ? WMH_E_NOMEM : WMH_E_DEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+#define WMH_HIP(ctx, call)                                      \
+    do {                                                        \
+        hipError_t e_ = (call);                                 \
+        if (e_ != hipSuccess) return device_fail(ctx, e_, #call); \
+    } while (0)
+
+void release_bounds(wmh_ctx *ctx)
+{
+    if (ctx->d_prefix) hipFree(ctx->d_prefix);
+    if (ctx->d_bucket) hipFree(ctx->d_bucket);
+    if (ctx->d_bound) hipFree(ctx->d_bound);
+    ctx->d_prefix = nullptr;
+    ctx->d_bucket = nullptr;
+    ctx->d_bound = nullptr;
+    ctx->has_bounds = false;
+}
+
+void drop_graph(wmh_ctx *ctx)
+{
+    if (ctx->graph_exec) hipGraphExecDestroy(ctx->graph_exec);
+    ctx->graph_exec = nullptr;
+    ctx->graph_key = GraphKey{};
+}
+
+Bounds bounds_view(const wmh_ctx *ctx)
+{
+    Bounds b;
+    b.prefix = ctx->d_prefix;
+    b.bucket = ctx->d_bucket;
+    b.bound = ctx->d_bound;
+    b.total = ctx->total;
+    b.threshold = ctx->threshold;
+    b.shift = ctx->shift;
+    b.dims = ctx->dims;
+    return b;
+}
+
+hipStream_t pick_stream(wmh_ctx *ctx, void *stream)
+{
+    return stream ? reinterpret_cast<hipStream_t>(stream) : ctx->own_stream;
+}
+
+const char *check_name(uint32_t code)
+{
+    switch (code) {
+    case kCheckRowPtr: return "row_ptr decreasing or beyond nnz";
+    case kCheckColumn: return "column index >= D";
+    case kCheckUnsorted: return "columns not strictly increasing";
+    case kCheckBound: return "value above its bound m_i";
+    default: return "?";
+    }
+}
+
+wmh_status check_status(uint32_t code)
+{
+    switch (code) {
+    case kCheckRowPtr: return WMH_E_ROW_PTR;
+    case kCheckColumn: return WMH_E_COL_RANGE;
+    case kCheckUnsorted: return WMH_E_UNSORTED;
+    case kCheckBound: return WMH_E_BOUND;
+    default: return WMH_E_DEVICE;
+    }
+}
+
+wmh_status ensure_stream_capacity(wmh_ctx *ctx, size_t bytes)
+{
+    if (bytes <= ctx->stream_bytes) return WMH_OK;
+    if (ctx->d_stream) hipFree(ctx->d_stream);
+    ctx->d_stream = nullptr;
+    ctx->stream_bytes = 0;
+    drop_graph(ctx);
+    WMH_HIP(ctx, hipMalloc(&ctx->d_stream, bytes));
+    ctx->stream_bytes = bytes;
+    return WMH_OK;
+}
+
+// Tile plan of the batched walk.  Returns false when no dense plan fits in LDS.
+bool plan_batched(const wmh_ctx *ctx, uint32_t k, uint64_t min_green, const wmh_opts &o,
+                  BatchedPlan *plan)
+{
+    BatchedPlan p{};
+    p.narrow = ctx->max_bound <= 0xFFFFu;
+    p.waves_per_block = o.waves_per_block ? std::min<uint32_t>(o.waves_per_block, 16u) : 4u;
+    p.hashes_per_tile = o.hashes_per_tile ? std::min(o.hashes_per_tile, k) : std::min(k, 1024u);
+    const size_t elem = p.narrow ? 2 : 4;
+    const size_t lds_target = 48 * 1024;  // keep several workgroups resident per CU
+    uint32_t R = o.rows_per_block;
+    if (R == 0) {
+        R = 4;
+        while (R > 1 && (size_t)ctx->dims * R * elem > lds_target) R >>= 1;
+    }
+    if (R != 1 && R != 2 && R != 4 && R != 8 && R != 16) return false;
+    p.rows_per_block = R;
+    if (batched_lds_bytes(ctx->dims, p) > 160 * 1024 - 64) return false;
+    // shared stream depth: cover eight mean step counts of the sparsest row
+    uint32_t depth;
+    if (o.stream_depth == UINT32_MAX) {
+        depth = 0;
+    } else if (o.stream_depth) {
+        depth = std::min<uint32_t>(65536u, (o.stream_depth + 63u) & ~63u);
+    } else if (min_green != ~0ull && min_green != 0) {
+        const double mean_steps = (double)ctx->total / (double)min_green;
+        const double want = std::min(65536.0, 8.0 * mean_steps + 64.0);
+        depth = std::max<uint32_t>(64u, ((uint32_t)want + 63u) & ~63u);
+        depth = std::min<uint32_t>(depth, 65536u);
+    } else {
+        depth = 4096;
+    }
+    while (depth && (uint64_t)depth * k * sizeof(StreamEntry) > kStreamBudgetBytes) depth -= 64;
+    p.stream_depth = depth;
+    *plan = p;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+void wmh_opts_init(wmh_opts *opts)
+{
+    if (!opts) return;
+    std::memset(opts, 0, sizeof(*opts));
+    opts->mode = WMH_MODE_AUTO;
+    opts->batch_rows = 8192;
+    opts->validate = 1;
+    opts->use_graph = 1;
+    opts->sync = 1;
+}
+
+const char *wmh_status_string(wmh_status status)
+{
+    switch (status) {
+    case WMH_OK: return "WMH_OK";
+    case WMH_E_ARG: return "WMH_E_ARG";
+    case WMH_E_NO_BOUNDS: return "WMH_E_NO_BOUNDS";
+    case WMH_E_COL_RANGE: return "WMH_E_COL_RANGE";
+    case WMH_E_UNSORTED: return "WMH_E_UNSORTED";
+    case WMH_E_BOUND: return "WMH_E_BOUND";
+    case WMH_E_OVERFLOW: return "WMH_E_OVERFLOW";
+    case WMH_E_NOMEM: return "WMH_E_NOMEM";
+    case WMH_E_DEVICE: return "WMH_E_DEVICE";
+    case WMH_E_ROW_PTR: return "WMH_E_ROW_PTR";
+    }
+    return "WMH_E_UNKNOWN";
+}
+
+const char *wmh_last_error(const wmh_ctx *ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+wmh_status wmh_create(int device, wmh_ctx **out)
+{
+    if (!out) return WMH_E_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return WMH_E_ARG;
+    if (hipSetDevice(device) != hipSuccess) return WMH_E_DEVICE;
+    wmh_ctx *ctx = new (std::nothrow) wmh_ctx();
+    if (!ctx) return WMH_E_NOMEM;
+    ctx->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess ||
+        hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipMalloc(&ctx->d_check, sizeof(CheckWords)) != hipSuccess ||
+        hipHostMalloc(&ctx->h_check, sizeof(CheckWords), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(&ctx->d_tile_counter, sizeof(uint32_t)) != hipSuccess ||
+        hipEventCreate(&ctx->ev[0]) != hipSuccess || hipEventCreate(&ctx->ev[1]) != hipSuccess ||
+        hipEventCreate(&ctx->ev[2]) != hipSuccess) {
+        wmh_destroy(ctx);
+        return WMH_E_DEVICE;
+    }
+    ctx->cu_count = prop.multiProcessorCount;
+    *out = ctx;
+    return WMH_OK;
+}
+
+void wmh_destroy(wmh_ctx *ctx)
+{
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    drop_graph(ctx);
+    release_bounds(ctx);
+    if (ctx->d_stream) hipFree(ctx->d_stream);
+    if (ctx->d_check) hipFree(ctx->d_check);
+    if (ctx->h_check) hipHostFree(ctx->h_check);
+    if (ctx->d_tile_counter) hipFree(ctx->d_tile_counter);
+    for (hipEvent_t &e : ctx->ev)
+        if (e) hipEventDestroy(e);
+    if (ctx->own_stream) hipStreamDestroy(ctx->own_stream);
+    if (ctx->capture_stream) hipStreamDestroy(ctx->capture_stream);
+    delete ctx;
+}
+
+wmh_status wmh_bounds_tables(const uint32_t *m, uint32_t D, uint64_t *prefix, uint32_t *bucket,
+                             uint32_t *shift_out, uint64_t *n_buckets_out, uint64_t *threshold_out)
+{
+    if (!m || D == 0 || D > kMaxDims) return WMH_E_ARG;
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < D; ++i) total += m[i];
+    if (total == 0) return WMH_E_OVERFLOW;
+    // about two buckets per dimension: at most 2 * 2^ceil(log2 D), at least 4
+    uint64_t target = 2;
+    while (target < (uint64_t)D) target <<= 1;
+    target <<= 1;
+    uint32_t shift = 0;
+    while ((((total - 1) >> shift) + 1) > target) ++shift;
+    const uint64_t n_buckets = ((total - 1) >> shift) + 1;
+    if (shift_out) *shift_out = shift;
+    if (n_buckets_out) *n_buckets_out = n_buckets;
+    if (threshold_out) *threshold_out = (0ull - total) % total;  // 2^64 mod M
+    if (prefix) {
+        prefix[0] = 0;
+        for (uint32_t i = 0; i < D; ++i) prefix[i + 1] = prefix[i] + m[i];
+    }
+    if (bucket) {
+        // two pointers over the prefix sums, computed again here so `prefix` may be NULL
+        uint64_t start_next = m[0];  // P[c + 1]
+        uint32_t c = 0;
+        for (uint64_t bkt = 0; bkt <= n_buckets; ++bkt) {
+            const uint64_t q = bkt << shift;
+            while (c + 1 < D && start_next <= q) {
+                ++c;
+                start_next += m[c];
+            }
+            bucket[bkt] = c;
+        }
+    }
+    return WMH_OK;
+}
+
+wmh_status wmh_set_bounds(wmh_ctx *ctx, const uint32_t *m, uint32_t D)
+{
+    if (!ctx) return WMH_E_ARG;
+    if (!m || D == 0 || D > kMaxDims) return fail(ctx, WMH_E_ARG, "D must be in [1, 2^26]");
+    WMH_HIP(ctx, hipSetDevice(ctx->device));
+    uint32_t shift = 0;
+    uint64_t n_buckets = 0, threshold = 0;
+    wmh_status st = wmh_bounds_tables(m, D, nullptr, nullptr, &shift, &n_buckets, &threshold);
+    if (st == WMH_E_OVERFLOW) return fail(ctx, st, "the bounds sum to 0");
+    if (st != WMH_OK) return fail(ctx, st, "invalid bounds");
+    std::vector<uint64_t> prefix((size_t)D + 1);
+    std::vector<uint32_t> bucket(n_buckets + 1);
+    wmh_bounds_tables(m, D, prefix.data(), bucket.data(), nullptr, nullptr, nullptr);
+    const uint64_t total = prefix[D];
+    uint32_t max_bound = 0;
+    for (uint32_t i = 0; i < D; ++i) max_bound = std::max(max_bound, m[i]);
+
+    drop_graph(ctx);
+    release_bounds(ctx);
+    WMH_HIP(ctx, hipMalloc(&ctx->d_prefix, prefix.size() * sizeof(uint64_t)));
+    WMH_HIP(ctx, hipMalloc(&ctx->d_bucket, bucket.size() * sizeof(uint32_t)));
+    WMH_HIP(ctx, hipMalloc(&ctx->d_bound, (size_t)D * sizeof(uint32_t)));
+    WMH_HIP(ctx, hipMemcpy(ctx->d_prefix, prefix.data(), prefix.size() * sizeof(uint64_t),
+                           hipMemcpyHostToDevice));
+    WMH_HIP(ctx, hipMemcpy(ctx->d_bucket, bucket.data(), bucket.size() * sizeof(uint32_t),
+                           hipMemcpyHostToDevice));
+    WMH_HIP(ctx, hipMemcpy(ctx->d_bound, m, (size_t)D * sizeof(uint32_t), hipMemcpyHostToDevice));
+    ctx->dims = D;
+    ctx->total = total;
+    ctx->threshold = threshold;
+    ctx->shift = shift;
+    ctx->n_buckets = n_buckets;
+    ctx->max_bound = max_bound;
+    ctx->has_bounds = true;
+    ctx->bounds_epoch++;
+    ctx->last_error.clear();
+    return WMH_OK;
+}
+
+wmh_status wmh_bounds_info(const wmh_ctx *ctx, uint32_t *D, uint64_t *M, uint32_t *shift,
+                           uint64_t *n_buckets)
+{
+    if (!ctx) return WMH_E_ARG;
+    if (!ctx->has_bounds) return WMH_E_NO_BOUNDS;
+    if (D) *D = ctx->dims;
+    if (M) *M = ctx->total;
+    if (shift) *shift = ctx->shift;
+    if (n_buckets) *n_buckets = ctx->n_buckets;
+    return WMH_OK;
+}
+
+wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
+                    const uint32_t *val, uint64_t n_rows, uint64_t nnz, uint32_t k,
+                    uint64_t seed, uint16_t *sig, void *stream, const wmh_opts *opts)
+{
+    if (!ctx) return WMH_E_ARG;
+    ctx->last_error.clear();
+    if (!ctx->has_bounds) return fail(ctx, WMH_E_NO_BOUNDS, "wmh_set_bounds was not called");
+    if (k == 0 || k > kMaxK) return fail(ctx, WMH_E_ARG, "k must be in [1, 2^24]");
+    if (n_rows == 0) return WMH_OK;
+    if (!row_ptr || !sig || (nnz && (!col || !val)))
+        return fail(ctx, WMH_E_ARG, "null buffer");
+    if (n_rows > (1ull << 40) || nnz > (1ull << 40))
+        return fail(ctx, WMH_E_ARG, "sizes out of range");
+    wmh_opts o;
+    if (opts) o = *opts;
+    else wmh_opts_init(&o);
+    if (o.mode < WMH_MODE_AUTO || o.mode > WMH_MODE_BATCHED)
+        return fail(ctx, WMH_E_ARG, "unknown mode %d", o.mode);
+    WMH_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = pick_stream(ctx, stream);
+    const Rows rows{row_ptr, col, val, n_rows, nnz};
+    const Bounds b = bounds_view(ctx);
+
+    uint64_t min_green = ~0ull;
+    const bool profile = o.profile != 0;
+    ctx->profiled = false;
+    if (o.validate) {
+        // first_error and min_green start at ~0, n_empty at 0
+        uint32_t *words = reinterpret_cast<uint32_t *>(ctx->d_check);
+        WMH_HIP(ctx, launch_fill_u32(words, 0xFFFFFFFFu, 4, s));
+        WMH_HIP(ctx, launch_fill_u32(words + 4, 0u, 2, s));
+        WMH_HIP(ctx, launch_validate(rows, ctx->d_bound, ctx->dims, ctx->d_check, s));
+        WMH_HIP(ctx, hipMemcpyAsync(ctx->h_check, ctx->d_check, sizeof(CheckWords),
+                                    hipMemcpyDeviceToHost, s));
+        WMH_HIP(ctx, hipStreamSynchronize(s));
+        const CheckWords v = *ctx->h_check;
+        if (v.first_error != ~0ull) {
+            const uint64_t row = v.first_error >> 4;
+            const uint32_t code = (uint32_t)(v.first_error & 15u);
+            return fail(ctx, check_status(code), "row %llu: %s", (unsigned long long)row,
+                        check_name(code));
+        }
+        min_green = v.min_green;
+    }
+
+    BatchedPlan plan{};
+    bool batched = o.mode != WMH_MODE_PLAIN && plan_batched(ctx, k, min_green, o, &plan);
+    if (o.mode == WMH_MODE_BATCHED && !batched)
+        return fail(ctx, WMH_E_ARG, "no batched plan fits for D=%u with these options", ctx->dims);
+
+    if (!batched) {
+        const bool narrow = ctx->max_bound <= 0xFFFFu;
+        const bool dense = (size_t)4 * ctx->dims * (narrow ? 2 : 4) <= 64 * 1024;
+        const uint64_t step = o.batch_rows ? o.batch_rows : 8192;
+        if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[1], s));
+        for (uint64_t r0 = 0; r0 < n_rows; r0 += step) {
+            const uint64_t r1 = std::min(n_rows, r0 + step);
+            WMH_HIP(ctx, launch_plain(b, rows, r0, r1, k, seed, sig, narrow, dense, s));
+        }
+        if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[2], s));
+        ctx->profiled = profile;
+        ctx->profiled_stream = false;
+    } else {
+        if (plan.stream_depth) {
+            wmh_status st = ensure_stream_capacity(
+                ctx, (size_t)plan.stream_depth * k * sizeof(StreamEntry));
+            if (st != WMH_OK) return st;
+        }
+        const int per_cu = std::max(1, batched_blocks_per_cu(ctx->dims, plan));
+        const uint64_t n_blocks = (n_rows + plan.rows_per_block - 1) / plan.rows_per_block;
+        const uint64_t n_tiles =
+            n_blocks * ((k + plan.hashes_per_tile - 1) / plan.hashes_per_tile);
+        const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)ctx->cu_count * per_cu, n_tiles);
+
+        GraphKey key;
+        key.row_ptr = row_ptr; key.col = col; key.val = val; key.sig = sig;
+        key.n_rows = n_rows; key.nnz = nnz; key.seed = seed; key.k = k;
+        key.R = plan.rows_per_block; key.J = plan.hashes_per_tile; key.depth = plan.stream_depth;
+        key.waves = plan.waves_per_block; key.grid = grid; key.narrow = plan.narrow;
+        key.bounds_epoch = ctx->bounds_epoch;
+        key.profile = profile;
+
+        auto enqueue = [&](hipStream_t q) -> hipError_t {
+            hipError_t e = launch_fill_u32(ctx->d_tile_counter, 0u, 1, q);
+            if (e != hipSuccess) return e;
+            if (profile && (e = hipEventRecord(ctx->ev[0], q)) != hipSuccess) return e;
+            if (plan.stream_depth) {
+                e = launch_stream_build(b, seed, k, plan.stream_depth, ctx->d_stream, q);
+                if (e != hipSuccess) return e;
+            }
+            if (profile && (e = hipEventRecord(ctx->ev[1], q)) != hipSuccess) return e;
+            e = launch_batched(b, rows, k, seed, sig, plan, ctx->d_stream, ctx->d_tile_counter,
+                               grid, q);
+            if (e != hipSuccess) return e;
+            if (profile) e = hipEventRecord(ctx->ev[2], q);
+            return e;
+        };
+
+        if (o.use_graph) {
+            if (!(ctx->graph_exec && ctx->graph_key == key)) {
+                drop_graph(ctx);
+                hipGraph_t graph = nullptr;
+                WMH_HIP(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+                hipError_t e = enqueue(ctx->capture_stream);
+                hipError_t e2 = hipStreamEndCapture(ctx->capture_stream, &graph);
+                if (e != hipSuccess) {
+                    if (graph) hipGraphDestroy(graph);
+                    return device_fail(ctx, e, "batched launch (capture)");
+                }
+                if (e2 != hipSuccess) return device_fail(ctx, e2, "hipStreamEndCapture");
+                e = hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0);
+                hipGraphDestroy(graph);
+                if (e != hipSuccess) {
+                    ctx->graph_exec = nullptr;
+                    return device_fail(ctx, e, "hipGraphInstantiate");
+                }
+                ctx->graph_key = key;
+            }
+            WMH_HIP(ctx, hipGraphLaunch(ctx->graph_exec, s));
+        } else {
+            hipError_t e = enqueue(s);
+            if (e != hipSuccess) return device_fail(ctx, e, "batched launch");
+        }
+        ctx->profiled = profile;
+        ctx->profiled_stream = profile && plan.stream_depth != 0;
+    }
+    if (o.sync) WMH_HIP(ctx, hipStreamSynchronize(s));
+    return WMH_OK;
+}
+
+wmh_status wmh_last_kernel_ms(wmh_ctx *ctx, float *walk_ms, float *stream_ms)
+{
+    if (!ctx) return WMH_E_ARG;
+    if (!ctx->profiled) return fail(ctx, WMH_E_ARG, "no profiled wmh_hash call");
+    WMH_HIP(ctx, hipEventSynchronize(ctx->ev[2]));
+    float w = 0.f, st = 0.f;
+    WMH_HIP(ctx, hipEventElapsedTime(&w, ctx->ev[1], ctx->ev[2]));
+    if (ctx->profiled_stream) WMH_HIP(ctx, hipEventElapsedTime(&st, ctx->ev[0], ctx->ev[1]));
+    if (walk_ms) *walk_ms = w;
+    if (stream_ms) *stream_ms = st;
+    return WMH_OK;
+}
+
+wmh_status wmh_draws(wmh_ctx *ctx, uint64_t seed, uint32_t j0, uint32_t n_hashes, uint32_t depth,
+                     uint64_t *pos, uint32_t *comp, uint64_t *off, void *stream)
+{
+    if (!ctx) return WMH_E_ARG;
+    ctx->last_error.clear();
+    if (!ctx->has_bounds) return fail(ctx, WMH_E_NO_BOUNDS, "wmh_set_bounds was not called");
+    if (depth == 0 || depth > 65536u || n_hashes == 0 || (uint64_t)j0 + n_hashes > (1ull << 32))
+        return fail(ctx, WMH_E_ARG, "depth must be in [1, 65536], n_hashes >= 1");
+    if ((uint64_t)n_hashes * depth > (1ull << 34)) return fail(ctx, WMH_E_ARG, "too many draws");
+    WMH_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = pick_stream(ctx, stream);
+    WMH_HIP(ctx, launch_draws(bounds_view(ctx), seed, j0, n_hashes, depth, pos, comp, off, s));
+    WMH_HIP(ctx, hipStreamSynchronize(s));
+    return WMH_OK;
+}
+
+wmh_status wmh_estimate(wmh_ctx *ctx, const uint16_t *A, const uint16_t *B, uint64_t n_pairs,
+                        uint32_t k, uint32_t *count, double *jhat, void *stream)
+{
+    if (!ctx) return WMH_E_ARG;
+    ctx->last_error.clear();
+    if (k == 0) return fail(ctx, WMH_E_ARG, "k must be >= 1");
+    if (n_pairs == 0) return WMH_OK;
+    if (!A || !B || (!count && !jhat)) return fail(ctx, WMH_E_ARG, "null buffer");
+    WMH_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = pick_stream(ctx, stream);
+    WMH_HIP(ctx, launch_estimate(A, B, n_pairs, k, count, jhat, s));
+    WMH_HIP(ctx, hipStreamSynchronize(s));
+    return WMH_OK;
+}
+
+wmh_status wmh_collisions(wmh_ctx *ctx, const uint16_t *A, uint64_t NA, const uint16_t *B,
+                          uint64_t NB, uint32_t k, uint32_t *counts, void *stream)
+{
+    if (!ctx) return WMH_E_ARG;
+    ctx->last_error.clear();
+    if (k == 0) return fail(ctx, WMH_E_ARG, "k must be >= 1");
+    if (NA == 0 || NB == 0) return WMH_OK;
+    if (!A || !B || !counts) return fail(ctx, WMH_E_ARG, "null buffer");
+    if (NA > 65535ull * 64) return fail(ctx, WMH_E_ARG, "NA too large for one call (max 4194240)");
+    WMH_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = pick_stream(ctx, stream);
+    WMH_HIP(ctx, launch_collisions(A, NA, B, NB, k, counts, s));
+    WMH_HIP(ctx, hipStreamSynchronize(s));
+    return WMH_OK;
+}
+
+}  // extern "C"

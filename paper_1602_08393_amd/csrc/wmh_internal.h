@@ -1,0 +1,82 @@
+// Internal interface between the C-ABI host code (wmh_host.cpp) and the kernel launchers
+// (wmh_kernels.hip, wmh_collide.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wmh_device.h"
+
+namespace wmh {
+
+// Validation verdict codes, ordered by entry: the code of a row is that of its first bad entry.
+enum : uint32_t {
+    kCheckRowPtr = 1,   // row_ptr[r] > row_ptr[r+1] or row_ptr[r+1] > nnz
+    kCheckColumn = 2,   // col >= D
+    kCheckUnsorted = 3, // col[e-1] >= col[e] inside a row
+    kCheckBound = 4,    // val > m[col]
+};
+
+// Device words written by the validation kernel (one allocation, reset before each launch).
+struct CheckWords {
+    unsigned long long first_error;  // (row << 4) | code, minimum over rows; ~0 when valid
+    unsigned long long min_green;    // smallest sum(x) over non-empty rows; ~0 if none
+    unsigned long long n_empty;      // rows with sum(x) == 0
+};
+
+struct Rows {
+    const uint64_t *row_ptr;
+    const uint32_t *col;
+    const uint32_t *val;
+    uint64_t n_rows;
+    uint64_t nnz;
+};
+
+// One shared-stream entry: the component and the offset inside it of one step's position.
+struct StreamEntry {
+    uint32_t comp;
+    uint32_t offset;
+};
+
+struct BatchedPlan {
+    uint32_t rows_per_block;   // R
+    uint32_t hashes_per_tile;  // J
+    uint32_t stream_depth;     // T0 (multiple of 64, <= 65536), 0 = no shared stream
+    uint32_t waves_per_block;
+    bool narrow;               // dense rows stored as uint16 (every bound < 65536)
+};
+
+hipError_t launch_validate(const Rows &rows, const uint32_t *bound, uint32_t dims,
+                           CheckWords *words, hipStream_t stream);
+
+hipError_t launch_plain(const Bounds &b, const Rows &rows, uint64_t row_begin,
+                        uint64_t row_end, uint32_t k, uint64_t seed, uint16_t *sig, bool narrow,
+                        bool dense, hipStream_t stream);
+
+hipError_t launch_draws(const Bounds &b, uint64_t seed, uint32_t j0, uint32_t n_hashes,
+                        uint32_t depth, uint64_t *pos, uint32_t *comp, uint64_t *off,
+                        hipStream_t stream);
+
+hipError_t launch_stream_build(const Bounds &b, uint64_t seed, uint32_t k, uint32_t depth,
+                               StreamEntry *entries, hipStream_t stream);
+
+// Returns hipErrorInvalidValue when the plan does not fit (LDS).
+hipError_t launch_batched(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
+                          uint16_t *sig, const BatchedPlan &plan, const StreamEntry *entries,
+                          uint32_t *tile_counter, uint32_t grid, hipStream_t stream);
+
+// Dynamic LDS bytes a batched plan needs.
+size_t batched_lds_bytes(uint32_t dims, const BatchedPlan &plan);
+
+// Resident workgroups per CU for a batched plan (0 when it does not fit).
+int batched_blocks_per_cu(uint32_t dims, const BatchedPlan &plan);
+
+hipError_t launch_estimate(const uint16_t *A, const uint16_t *B, uint64_t n_pairs, uint32_t k,
+                           uint32_t *count, double *jhat, hipStream_t stream);
+
+hipError_t launch_collisions(const uint16_t *A, uint64_t na, const uint16_t *B, uint64_t nb,
+                             uint32_t k, uint32_t *counts, hipStream_t stream);
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t stream);
+
+}  // namespace wmh

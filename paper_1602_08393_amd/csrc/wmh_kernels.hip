@@ -1,0 +1,533 @@
+// HIP kernels of the hash walk for gfx950: input validation, the plain per-lane walk, the
+// shared position stream and the batched persistent walk.
+//
+// Work per (row, hash j): draw positions p_1, p_2, ... of hash j, map each to its component c
+// and offset (Algorithm 5 with a uniform bucket table in place of Algorithm 4's per-integer
+// map), and stop at the first t with offset < x_c (Algorithm 3, Definition 1).  Expected
+// steps are 1/s with s = sum(x)/M (Theorem 2), so the step counts are geometric and the
+// kernels are organised so that lanes do not idle on the long tails.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "wmh_internal.h"
+
+namespace wmh {
+
+namespace {
+
+__device__ __forceinline__ uint32_t lane() { return threadIdx.x & (kWave - 1u); }
+
+// Number of set bits of `mask` below this lane.
+__device__ __forceinline__ uint32_t count_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_min(uint64_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = __shfl_xor(v, off);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Validation: one wavefront per row, grid-stride over rows.
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void validate_kernel(Rows rows, const uint32_t *__restrict__ bound,
+                                                       uint32_t dims, CheckWords *words)
+{
+    const uint32_t waves = blockDim.x / kWave;
+    const uint64_t first = (uint64_t)blockIdx.x * waves + threadIdx.x / kWave;
+    const uint64_t stride = (uint64_t)gridDim.x * waves;
+    for (uint64_t r = first; r < rows.n_rows; r += stride) {
+        const uint64_t lo = rows.row_ptr[r];
+        const uint64_t hi = rows.row_ptr[r + 1];
+        if (lo > hi || hi > rows.nnz) {
+            if (lane() == 0) atomicMin(&words->first_error, (r << 4) | kCheckRowPtr);
+            continue;
+        }
+        uint64_t sum = 0;
+        uint64_t bad = ~0ull;  // (entry << 4) | code of this lane's first bad entry
+        for (uint64_t e = lo + lane(); e < hi; e += kWave) {
+            const uint32_t c = rows.col[e];
+            const uint32_t v = rows.val[e];
+            uint32_t code = 0;
+            if (c >= dims) code = kCheckColumn;
+            else if (e > lo && rows.col[e - 1] >= c) code = kCheckUnsorted;
+            else if (v > bound[c]) code = kCheckBound;
+            if (code && bad == ~0ull) bad = ((e - lo) << 4) | code;
+            sum += v;
+        }
+        bad = wave_min(bad);
+        sum = wave_sum(sum);
+        if (lane() == 0) {
+            if (bad != ~0ull) atomicMin(&words->first_error, (r << 4) | (bad & 15u));
+            else if (sum == 0) atomicAdd(&words->n_empty, 1ull);
+            else atomicMin(&words->min_green, (unsigned long long)sum);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Plain walk: one wavefront per row, `waves` rows per workgroup.  Each lane walks one
+// (row, hash) pair with its own draws; a lane that stops takes the next hash id of its row
+// (ballot refill), so lanes stay busy until the row's last k ids are in flight.
+// ---------------------------------------------------------------------------------------------
+template <typename XT, bool kDense>
+__global__ __launch_bounds__(256) void plain_kernel(Bounds b, Rows rows, uint64_t row_begin,
+                                                    uint64_t row_end, uint32_t k, uint64_t seed,
+                                                    uint16_t *__restrict__ sig)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t waves = blockDim.x / kWave;
+    const uint32_t wave = threadIdx.x / kWave;
+    const uint64_t row = row_begin + (uint64_t)blockIdx.x * waves + wave;
+    const bool live = row < row_end;
+    const uint32_t D = b.dims;
+    XT *x = reinterpret_cast<XT *>(smem) + (kDense ? (size_t)wave * D : 0);
+
+    uint64_t lo = 0, hi = 0;
+    if (live) {
+        lo = rows.row_ptr[row];
+        hi = rows.row_ptr[row + 1];
+    }
+    if (kDense) {
+        for (uint32_t i = lane(); i < D; i += kWave) x[i] = 0;
+        __syncthreads();
+        for (uint64_t e = lo + lane(); e < hi; e += kWave) {
+            const uint32_t c = rows.col[e];
+            if (c < D) x[c] = (XT)rows.val[e];
+        }
+        __syncthreads();
+    }
+    if (!live) return;
+    uint64_t green = 0;
+    for (uint64_t e = lo + lane(); e < hi; e += kWave) green += rows.val[e];
+    green = wave_sum(green);
+
+    uint16_t *out = sig + row * (uint64_t)k;
+    if (green == 0) {
+        for (uint32_t j = lane(); j < k; j += kWave) out[j] = 0;
+        return;
+    }
+
+    uint32_t j = lane();
+    uint32_t t = 0;
+    uint64_t next_even = 0;  // position of the even step of the current pair
+    uint32_t next_id = kWave;
+    bool active = j < k;
+    while (true) {
+        bool done = false;
+        if (active) {
+            ++t;
+            uint64_t p;
+            if (t & 1u) position_pair(seed, j, (t - 1u) >> 1, b.total, b.threshold, &p, &next_even);
+            else p = next_even;
+            uint64_t off;
+            const uint32_t c = component_of(p, b.prefix, b.bucket, b.shift, &off);
+            uint32_t xc;
+            if (kDense) {
+                xc = x[c];
+            } else {
+                // binary search of c among the row's sorted columns (global memory)
+                uint64_t a = lo, z = hi;
+                while (a < z) {
+                    const uint64_t mid = (a + z) >> 1;
+                    if (rows.col[mid] < c) a = mid + 1;
+                    else z = mid;
+                }
+                xc = (a < hi && rows.col[a] == c) ? rows.val[a] : 0u;
+            }
+            done = off < (uint64_t)xc || t == kCap;
+        }
+        const uint64_t finished = __ballot(done);
+        if (done) {
+            out[j] = (uint16_t)t;
+            j = next_id + count_below(finished);
+            t = 0;
+            active = j < k;
+        }
+        next_id += (uint32_t)__popcll(finished);
+        if (!__any(active)) break;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Shared position stream: entries[j * depth + t - 1] = (component, offset) of step t of hash
+// j, for t <= depth.  One thread per Philox block (two steps).
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void stream_kernel(Bounds b, uint64_t seed, uint32_t k,
+                                                     uint32_t depth, StreamEntry *__restrict__ entries)
+{
+    const uint64_t pairs = depth >> 1;
+    const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= pairs * k) return;
+    const uint32_t j = (uint32_t)(idx / pairs);
+    const uint32_t pair = (uint32_t)(idx - (uint64_t)j * pairs);
+    uint64_t p0, p1, off0, off1;
+    position_pair(seed, j, pair, b.total, b.threshold, &p0, &p1);
+    const uint32_t c0 = component_of(p0, b.prefix, b.bucket, b.shift, &off0);
+    const uint32_t c1 = component_of(p1, b.prefix, b.bucket, b.shift, &off1);
+    StreamEntry *e = entries + (uint64_t)j * depth + 2ull * pair;
+    e[0] = StreamEntry{c0, (uint32_t)off0};
+    e[1] = StreamEntry{c1, (uint32_t)off1};
+}
+
+// The sequence with its lookup, written out: same device functions as stream_kernel.
+__global__ __launch_bounds__(256) void draws_kernel(Bounds b, uint64_t seed, uint32_t j0,
+                                                    uint32_t n_hashes, uint32_t depth,
+                                                    uint64_t *pos, uint32_t *comp, uint64_t *off)
+{
+    const uint64_t pairs = (depth + 1u) >> 1;
+    const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= pairs * n_hashes) return;
+    const uint32_t jj = (uint32_t)(idx / pairs);
+    const uint32_t pair = (uint32_t)(idx - (uint64_t)jj * pairs);
+    uint64_t p[2], o[2];
+    uint32_t c[2];
+    position_pair(seed, j0 + jj, pair, b.total, b.threshold, &p[0], &p[1]);
+    c[0] = component_of(p[0], b.prefix, b.bucket, b.shift, &o[0]);
+    c[1] = component_of(p[1], b.prefix, b.bucket, b.shift, &o[1]);
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t t = 2u * pair + (uint32_t)h + 1u;
+        if (t > depth) break;
+        const uint64_t i = (uint64_t)jj * depth + t - 1u;
+        if (pos) pos[i] = p[h];
+        if (comp) comp[i] = c[h];
+        if (off) off[i] = o[h];
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Batched persistent walk.
+//
+// A tile is (row block of R rows) x (block of J hash ids).  Workgroups take tiles from an
+// atomic counter; the R rows of a tile's row block sit in LDS transposed (x[c * R + r]) so one
+// LDS read fetches component c of all R rows.  A wavefront walks one hash id for the whole
+// row block: lane l tests step base + l + 1 of the window [base + 1, base + 64] for every row,
+// a ballot per row gives the first green step of that row in the window, and the walk ends
+// when every row of the block has stopped.  Every row of the block sees the same draw, so one
+// draw serves R rows (the sequence depends only on (seed, j, t), never on the row), and the
+// window replaces the per-lane geometric tail of the plain walk by at most one partly used
+// window per (block, hash).  Draws come from the shared stream for t <= depth and are made
+// in-lane beyond it.
+// ---------------------------------------------------------------------------------------------
+template <typename XT, int R>
+__global__ __launch_bounds__(1024) void batched_kernel(Bounds b, Rows rows, uint32_t k,
+                                                       uint64_t seed, uint16_t *__restrict__ sig,
+                                                       uint32_t hashes_per_tile, uint32_t depth,
+                                                       const StreamEntry *__restrict__ entries,
+                                                       uint32_t *tile_counter)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t tile_slot;
+    __shared__ uint32_t unit_slot;
+    __shared__ uint32_t nonempty;
+    const uint32_t D = b.dims;
+    XT *x = reinterpret_cast<XT *>(smem);
+    uint16_t *hbuf = reinterpret_cast<uint16_t *>(smem + (((size_t)D * R * sizeof(XT) + 15) & ~(size_t)15));
+
+    const uint64_t n_blocks = (rows.n_rows + R - 1) / R;
+    const uint32_t n_hash_tiles = (k + hashes_per_tile - 1) / hashes_per_tile;
+    const uint64_t n_tiles = n_blocks * n_hash_tiles;
+    uint64_t staged = ~0ull;
+    const uint32_t wave = threadIdx.x / kWave;
+    (void)wave;
+
+    while (true) {
+        if (threadIdx.x == 0) {
+            tile_slot = atomicAdd(tile_counter, 1u);
+            unit_slot = 0;
+        }
+        __syncthreads();
+        const uint64_t tile = tile_slot;
+        if (tile >= n_tiles) break;
+        const uint64_t blk = tile / n_hash_tiles;
+        const uint32_t ht = (uint32_t)(tile - blk * n_hash_tiles);
+        const uint64_t row0 = blk * R;
+        const uint32_t n_here = (uint32_t)min((uint64_t)R, rows.n_rows - row0);
+
+        if (blk != staged) {
+            // zero the block, then scatter its rows
+            uint32_t *xz = reinterpret_cast<uint32_t *>(x);
+            const uint32_t words = (uint32_t)(((size_t)D * R * sizeof(XT) + 3) / 4);
+            for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) xz[i] = 0u;
+            if (threadIdx.x == 0) nonempty = 0;
+            __syncthreads();
+            uint32_t mine = 0;
+            for (uint32_t r = 0; r < n_here; ++r) {
+                const uint64_t lo = rows.row_ptr[row0 + r], hi = rows.row_ptr[row0 + r + 1];
+                for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+                    const uint32_t v = rows.val[e];
+                    const uint32_t c = rows.col[e];
+                    if (c < D) x[(size_t)c * R + r] = (XT)v;
+                    if (v) mine |= 1u << r;
+                }
+            }
+            if (mine) atomicOr(&nonempty, mine);
+            __syncthreads();
+            staged = blk;
+        }
+        const uint32_t live = nonempty;  // rows of the block with a green region
+        const uint32_t j0 = ht * hashes_per_tile;
+        const uint32_t j1 = min(k, j0 + hashes_per_tile);
+
+        while (true) {
+            uint32_t unit = 0;
+            if (lane() == 0) unit = atomicAdd(&unit_slot, 1u);
+            unit = __shfl(unit, 0);
+            const uint32_t j = j0 + unit;
+            if (j >= j1) break;
+
+            uint32_t pending = live;
+            uint32_t h[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) h[r] = 0;
+            const StreamEntry *col_entries = entries + (uint64_t)j * depth;
+            for (uint32_t base = 0; pending != 0 && base < kCap; base += kWave) {
+                const uint32_t t = base + lane() + 1u;
+                uint32_t c;
+                uint32_t off;
+                if (base < depth) {
+                    const StreamEntry e = col_entries[t - 1u];
+                    c = e.comp;
+                    off = e.offset;
+                } else {
+                    const uint64_t p = position(seed, j, t, b.total, b.threshold);
+                    uint64_t o64;
+                    c = component_of(p, b.prefix, b.bucket, b.shift, &o64);
+                    off = (uint32_t)o64;
+                }
+                const bool in_range = t <= kCap;
+                const XT *xc = x + (size_t)c * R;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const uint64_t m = __ballot(in_range && off < (uint32_t)xc[r]);
+                    if (((pending >> r) & 1u) && m != 0) {
+                        h[r] = base + (uint32_t)__ffsll((unsigned long long)m);
+                        pending &= ~(1u << r);
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if ((pending >> r) & 1u) h[r] = kCap;
+            uint32_t mine = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (lane() == (uint32_t)r) mine = h[r];
+            if (lane() < (uint32_t)R) hbuf[lane() * hashes_per_tile + (j - j0)] = (uint16_t)mine;
+        }
+        __syncthreads();
+        // write the tile's signatures row by row (coalesced along j)
+        const uint32_t width = j1 - j0;
+        for (uint32_t r = 0; r < n_here; ++r) {
+            uint16_t *out = sig + (row0 + r) * (uint64_t)k + j0;
+            for (uint32_t q = threadIdx.x; q < width; q += blockDim.x) out[q] = hbuf[r * hashes_per_tile + q];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint32_t value, uint64_t n)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = value;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Row-aligned pair estimates (eq. Estimator): one wavefront per pair.
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void estimate_kernel(const uint16_t *__restrict__ A,
+                                                       const uint16_t *__restrict__ B,
+                                                       uint64_t n_pairs, uint32_t k,
+                                                       uint32_t *count, double *jhat)
+{
+    const uint32_t waves = blockDim.x / kWave;
+    const uint64_t first = (uint64_t)blockIdx.x * waves + threadIdx.x / kWave;
+    const uint64_t stride = (uint64_t)gridDim.x * waves;
+    for (uint64_t i = first; i < n_pairs; i += stride) {
+        const uint16_t *a = A + i * k;
+        const uint16_t *bb = B + i * k;
+        uint64_t n = 0;
+        for (uint32_t j = lane(); j < k; j += kWave) n += (a[j] == bb[j]);
+        n = wave_sum(n);
+        if (lane() == 0) {
+            if (count) count[i] = (uint32_t)n;
+            if (jhat) jhat[i] = (double)n / (double)k;
+        }
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------------------------
+
+hipError_t launch_validate(const Rows &rows, const uint32_t *bound, uint32_t dims,
+                           CheckWords *words, hipStream_t stream)
+{
+    if (rows.n_rows == 0) return hipSuccess;
+    const uint64_t waves_needed = rows.n_rows;
+    const uint32_t grid = (uint32_t)std::min<uint64_t>((waves_needed + 3) / 4, 8192);
+    validate_kernel<<<grid, 256, 0, stream>>>(rows, bound, dims, words);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain(const Bounds &b, const Rows &rows, uint64_t row_begin, uint64_t row_end,
+                        uint32_t k, uint64_t seed, uint16_t *sig, bool narrow, bool dense,
+                        hipStream_t stream)
+{
+    if (row_end <= row_begin) return hipSuccess;
+    const uint32_t waves = 4;
+    const uint64_t n = row_end - row_begin;
+    const uint32_t grid = (uint32_t)((n + waves - 1) / waves);
+    if (dense) {
+        const size_t lds = (size_t)waves * b.dims * (narrow ? 2 : 4);
+        if (narrow)
+            plain_kernel<uint16_t, true><<<grid, waves * kWave, lds, stream>>>(b, rows, row_begin, row_end, k, seed, sig);
+        else
+            plain_kernel<uint32_t, true><<<grid, waves * kWave, lds, stream>>>(b, rows, row_begin, row_end, k, seed, sig);
+    } else {
+        plain_kernel<uint32_t, false><<<grid, waves * kWave, 0, stream>>>(b, rows, row_begin, row_end, k, seed, sig);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_draws(const Bounds &b, uint64_t seed, uint32_t j0, uint32_t n_hashes,
+                        uint32_t depth, uint64_t *pos, uint32_t *comp, uint64_t *off,
+                        hipStream_t stream)
+{
+    const uint64_t threads = (uint64_t)n_hashes * ((depth + 1u) / 2u);
+    if (threads == 0) return hipSuccess;
+    draws_kernel<<<(uint32_t)((threads + 255) / 256), 256, 0, stream>>>(b, seed, j0, n_hashes,
+                                                                      depth, pos, comp, off);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_build(const Bounds &b, uint64_t seed, uint32_t k, uint32_t depth,
+                               StreamEntry *entries, hipStream_t stream)
+{
+    if (depth == 0 || k == 0) return hipSuccess;
+    const uint64_t threads = (uint64_t)k * (depth / 2);
+    const uint32_t grid = (uint32_t)((threads + 255) / 256);
+    stream_kernel<<<grid, 256, 0, stream>>>(b, seed, k, depth, entries);
+    return hipGetLastError();
+}
+
+size_t batched_lds_bytes(uint32_t dims, const BatchedPlan &plan)
+{
+    const size_t xbytes = (size_t)dims * plan.rows_per_block * (plan.narrow ? 2 : 4);
+    const size_t aligned = (xbytes + 15) & ~(size_t)15;
+    return aligned + (size_t)plan.rows_per_block * plan.hashes_per_tile * 2;
+}
+
+template <typename XT, int R>
+static void configure_batched()
+{
+    static bool configured = false;
+    if (!configured) {
+        hipFuncSetAttribute((const void *)batched_kernel<XT, R>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64);
+        configured = true;
+    }
+}
+
+template <typename XT, int R>
+static int batched_occupancy_t(const BatchedPlan &plan, size_t lds)
+{
+    configure_batched<XT, R>();
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<XT, R>,
+                                                     plan.waves_per_block * kWave, lds) != hipSuccess)
+        return 1;
+    return blocks > 0 ? blocks : 1;
+}
+
+template <typename XT, int R>
+static hipError_t launch_batched_t(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
+                                   uint16_t *sig, const BatchedPlan &plan,
+                                   const StreamEntry *entries, uint32_t *tile_counter,
+                                   uint32_t grid, hipStream_t stream)
+{
+    const size_t lds = batched_lds_bytes(b.dims, plan);
+    configure_batched<XT, R>();
+    batched_kernel<XT, R><<<grid, plan.waves_per_block * kWave, lds, stream>>>(
+        b, rows, k, seed, sig, plan.hashes_per_tile, plan.stream_depth, entries, tile_counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_batched(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
+                          uint16_t *sig, const BatchedPlan &plan, const StreamEntry *entries,
+                          uint32_t *tile_counter, uint32_t grid, hipStream_t stream)
+{
+    if (batched_lds_bytes(b.dims, plan) > 160 * 1024 - 64) return hipErrorInvalidValue;
+#define WMH_BATCHED_CASE(RR)                                                                     \
+    case RR:                                                                                     \
+        return plan.narrow ? launch_batched_t<uint16_t, RR>(b, rows, k, seed, sig, plan, entries, \
+                                                            tile_counter, grid, stream)           \
+                           : launch_batched_t<uint32_t, RR>(b, rows, k, seed, sig, plan, entries, \
+                                                            tile_counter, grid, stream);
+    switch (plan.rows_per_block) {
+        WMH_BATCHED_CASE(1)
+        WMH_BATCHED_CASE(2)
+        WMH_BATCHED_CASE(4)
+        WMH_BATCHED_CASE(8)
+        WMH_BATCHED_CASE(16)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef WMH_BATCHED_CASE
+}
+
+int batched_blocks_per_cu(uint32_t dims, const BatchedPlan &plan)
+{
+    const size_t lds = batched_lds_bytes(dims, plan);
+    if (lds > 160 * 1024 - 64) return 0;
+#define WMH_OCC_CASE(RR)                                                                        \
+    case RR:                                                                                    \
+        return plan.narrow ? batched_occupancy_t<uint16_t, RR>(plan, lds)                       \
+                           : batched_occupancy_t<uint32_t, RR>(plan, lds);
+    switch (plan.rows_per_block) {
+        WMH_OCC_CASE(1)
+        WMH_OCC_CASE(2)
+        WMH_OCC_CASE(4)
+        WMH_OCC_CASE(8)
+        WMH_OCC_CASE(16)
+    default:
+        return 0;
+    }
+#undef WMH_OCC_CASE
+}
+
+hipError_t launch_estimate(const uint16_t *A, const uint16_t *B, uint64_t n_pairs, uint32_t k,
+                           uint32_t *count, double *jhat, hipStream_t stream)
+{
+    if (n_pairs == 0) return hipSuccess;
+    const uint32_t grid = (uint32_t)std::min<uint64_t>((n_pairs + 3) / 4, 8192);
+    estimate_kernel<<<grid, 256, 0, stream>>>(A, B, n_pairs, k, count, jhat);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    fill_u32_kernel<<<(uint32_t)((n + 255) / 256), 256, 0, stream>>>(p, value, n);
+    return hipGetLastError();
+}
+
+}  // namespace wmh

@@ -1,0 +1,273 @@
+"""Python binding of libwmh (include/wmh.h): argument marshalling only.
+
+Every computation runs in the library's HIP kernels; torch supplies device memory and streams.
+If ``libwmh.so`` has not been built this module raises on first use -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwmh.so")
+
+CAP = 65535
+
+STATUS = {0: "WMH_OK", -1: "WMH_E_ARG", -2: "WMH_E_NO_BOUNDS", -3: "WMH_E_COL_RANGE",
+          -4: "WMH_E_UNSORTED", -5: "WMH_E_BOUND", -6: "WMH_E_OVERFLOW", -7: "WMH_E_NOMEM",
+          -8: "WMH_E_DEVICE", -9: "WMH_E_ROW_PTR"}
+MODES = {"auto": 0, "plain": 1, "batched": 2}
+
+EXPORTED = ["wmh_opts_init", "wmh_create", "wmh_destroy", "wmh_set_bounds", "wmh_hash",
+            "wmh_estimate", "wmh_collisions", "wmh_bounds_info", "wmh_bounds_tables",
+            "wmh_draws", "wmh_last_kernel_ms", "wmh_last_error", "wmh_status_string"]
+
+
+class WmhOpts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("batch_rows", ctypes.c_uint32),
+                ("validate", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("sync", ctypes.c_int32), ("rows_per_block", ctypes.c_uint32),
+                ("hashes_per_tile", ctypes.c_uint32), ("stream_depth", ctypes.c_uint32),
+                ("waves_per_block", ctypes.c_uint32), ("profile", ctypes.c_int32),
+                ("reserved", ctypes.c_uint32 * 5)]
+
+
+class WMHError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        super().__init__(f"{self.name}: {detail}")
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads libwmh.so; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                           "python -m paper_1602_08393_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u64, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
+    L.wmh_opts_init.argtypes = [ctypes.POINTER(WmhOpts)]
+    L.wmh_opts_init.restype = None
+    L.wmh_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+    L.wmh_create.restype = ctypes.c_int
+    L.wmh_destroy.argtypes = [vp]
+    L.wmh_destroy.restype = None
+    L.wmh_set_bounds.argtypes = [vp, vp, u32]
+    L.wmh_set_bounds.restype = ctypes.c_int
+    L.wmh_hash.argtypes = [vp, vp, vp, vp, u64, u64, u32, u64, vp, vp, ctypes.POINTER(WmhOpts)]
+    L.wmh_hash.restype = ctypes.c_int
+    L.wmh_estimate.argtypes = [vp, vp, vp, u64, u32, vp, vp, vp]
+    L.wmh_estimate.restype = ctypes.c_int
+    L.wmh_collisions.argtypes = [vp, vp, u64, vp, u64, u32, vp, vp]
+    L.wmh_collisions.restype = ctypes.c_int
+    L.wmh_bounds_info.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u64),
+                                  ctypes.POINTER(u32), ctypes.POINTER(u64)]
+    L.wmh_bounds_info.restype = ctypes.c_int
+    L.wmh_bounds_tables.argtypes = [vp, u32, vp, vp, ctypes.POINTER(u32), ctypes.POINTER(u64),
+                                    ctypes.POINTER(u64)]
+    L.wmh_bounds_tables.restype = ctypes.c_int
+    L.wmh_last_kernel_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_float),
+                                     ctypes.POINTER(ctypes.c_float)]
+    L.wmh_last_kernel_ms.restype = ctypes.c_int
+    L.wmh_draws.argtypes = [vp, u64, u32, u32, u32, vp, vp, vp, vp]
+    L.wmh_draws.restype = ctypes.c_int
+    L.wmh_last_error.argtypes = [vp]
+    L.wmh_last_error.restype = ctypes.c_char_p
+    L.wmh_status_string.argtypes = [ctypes.c_int]
+    L.wmh_status_string.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def bounds_tables(m: np.ndarray) -> dict:
+    """Host-only: prefix sums, bucket table, shift and threshold (no device needed)."""
+    L = load()
+    m = np.ascontiguousarray(m, dtype=np.uint32)
+    shift, nb, thr = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64()
+    st = L.wmh_bounds_tables(m.ctypes.data, len(m), None, None, ctypes.byref(shift),
+                             ctypes.byref(nb), ctypes.byref(thr))
+    if st != 0:
+        raise WMHError(st, "wmh_bounds_tables")
+    prefix = np.zeros(len(m) + 1, dtype=np.uint64)
+    bucket = np.zeros(nb.value + 1, dtype=np.uint32)
+    st = L.wmh_bounds_tables(m.ctypes.data, len(m), prefix.ctypes.data, bucket.ctypes.data,
+                             None, None, None)
+    if st != 0:
+        raise WMHError(st, "wmh_bounds_tables")
+    return {"prefix": prefix, "bucket": bucket, "shift": shift.value, "n_buckets": nb.value,
+            "threshold": thr.value}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+@dataclass
+class DeviceRows:
+    """CSR rows resident on the device (torch tensors; unsigned data in signed containers)."""
+    row_ptr: object  # int64 [N+1]
+    col: object      # int32 [nnz]
+    val: object      # int32 [nnz]
+    n_rows: int
+    nnz: int
+
+
+def upload_rows(row_ptr: np.ndarray, col: np.ndarray, val: np.ndarray, device="cuda") \
+        -> DeviceRows:
+    torch = _torch()
+    rp = torch.from_numpy(np.ascontiguousarray(row_ptr, dtype=np.uint64).view(np.int64))
+    c = torch.from_numpy(np.ascontiguousarray(col, dtype=np.uint32).view(np.int32))
+    v = torch.from_numpy(np.ascontiguousarray(val, dtype=np.uint32).view(np.int32))
+    n = len(row_ptr) - 1
+    return DeviceRows(rp.to(device), c.to(device), v.to(device), n, len(col))
+
+
+def upload_dataset(ds, device="cuda") -> DeviceRows:
+    return upload_rows(ds.row_ptr, ds.col, ds.val, device)
+
+
+def sig_to_numpy(sig) -> np.ndarray:
+    return sig.cpu().numpy().view(np.uint16)
+
+
+class Context:
+    """One libwmh context on a HIP device."""
+
+    def __init__(self, device: int = 0):
+        self._lib = load()
+        self._ptr = ctypes.c_void_p()
+        self.device = device
+        self._check(self._lib.wmh_create(device, ctypes.byref(self._ptr)), "wmh_create")
+
+    def close(self):
+        if self._ptr:
+            self._lib.wmh_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, status: int, what: str):
+        if status != 0:
+            detail = ""
+            if self._ptr:
+                detail = self._lib.wmh_last_error(self._ptr).decode()
+            raise WMHError(status, f"{what}: {detail}")
+
+    def last_error(self) -> str:
+        return self._lib.wmh_last_error(self._ptr).decode()
+
+    def _stream(self, stream):
+        if stream is not None:
+            return ctypes.c_void_p(int(stream))
+        torch = _torch()
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    # -- calls --------------------------------------------------------------------------------
+    def set_bounds(self, m: np.ndarray):
+        m = np.ascontiguousarray(m, dtype=np.uint32)
+        self._check(self._lib.wmh_set_bounds(self._ptr, m.ctypes.data, len(m)), "wmh_set_bounds")
+
+    def bounds_info(self) -> dict:
+        D, M, shift, nb = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint64()
+        self._check(self._lib.wmh_bounds_info(self._ptr, ctypes.byref(D), ctypes.byref(M),
+                                              ctypes.byref(shift), ctypes.byref(nb)),
+                    "wmh_bounds_info")
+        return {"D": D.value, "M": M.value, "shift": shift.value, "n_buckets": nb.value}
+
+    @staticmethod
+    def make_opts(mode="auto", batch_rows=0, validate=True, use_graph=True, sync=True,
+                  rows_per_block=0, hashes_per_tile=0, stream_depth=0, waves_per_block=0,
+                  profile=False) -> WmhOpts:
+        o = WmhOpts()
+        load().wmh_opts_init(ctypes.byref(o))
+        o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+        if batch_rows:
+            o.batch_rows = batch_rows
+        o.validate = int(bool(validate))
+        o.use_graph = int(bool(use_graph))
+        o.sync = int(bool(sync))
+        o.rows_per_block = rows_per_block
+        o.hashes_per_tile = hashes_per_tile
+        o.stream_depth = 0xFFFFFFFF if stream_depth is None else stream_depth
+        o.waves_per_block = waves_per_block
+        o.profile = int(bool(profile))
+        return o
+
+    def last_kernel_ms(self) -> tuple[float, float]:
+        """(walk_ms, stream_ms) of the last profiled wmh_hash call."""
+        w, st = ctypes.c_float(), ctypes.c_float()
+        self._check(self._lib.wmh_last_kernel_ms(self._ptr, ctypes.byref(w), ctypes.byref(st)),
+                    "wmh_last_kernel_ms")
+        return w.value, st.value
+
+    def hash_into(self, rows: DeviceRows, k: int, seed: int, sig, stream=None, opts=None):
+        """Raw call: sig is a device int16 tensor of N*k elements."""
+        if opts is None:
+            opts = self.make_opts()
+        st = self._lib.wmh_hash(self._ptr, rows.row_ptr.data_ptr(), rows.col.data_ptr(),
+                                rows.val.data_ptr(), rows.n_rows, rows.nnz, k,
+                                ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), sig.data_ptr(),
+                                self._stream(stream), ctypes.byref(opts))
+        self._check(st, "wmh_hash")
+        return sig
+
+    def hash(self, rows: DeviceRows, k: int, seed: int = 0, stream=None, **opt_kwargs):
+        """Signatures [N, k] as a device int16 tensor (reinterpret as uint16)."""
+        torch = _torch()
+        sig = torch.empty((rows.n_rows, k), dtype=torch.int16,
+                          device=rows.row_ptr.device)
+        return self.hash_into(rows, k, seed, sig, stream, self.make_opts(**opt_kwargs))
+
+    def draws(self, seed: int, j0: int, n_hashes: int, depth: int, device="cuda", stream=None):
+        """(pos uint64, comp uint32, off uint64) as numpy arrays [n_hashes, depth]."""
+        torch = _torch()
+        pos = torch.empty((n_hashes, depth), dtype=torch.int64, device=device)
+        comp = torch.empty((n_hashes, depth), dtype=torch.int32, device=device)
+        off = torch.empty((n_hashes, depth), dtype=torch.int64, device=device)
+        self._check(self._lib.wmh_draws(self._ptr, ctypes.c_uint64(seed), j0, n_hashes, depth,
+                                        pos.data_ptr(), comp.data_ptr(), off.data_ptr(),
+                                        self._stream(stream)), "wmh_draws")
+        return (pos.cpu().numpy().view(np.uint64), comp.cpu().numpy().view(np.uint32),
+                off.cpu().numpy().view(np.uint64))
+
+    def estimate(self, A, B, stream=None):
+        """Row-aligned pairs: (count uint32 [n], jhat float64 [n]) as device tensors."""
+        torch = _torch()
+        n, k = A.shape
+        count = torch.empty(n, dtype=torch.int32, device=A.device)
+        jhat = torch.empty(n, dtype=torch.float64, device=A.device)
+        self._check(self._lib.wmh_estimate(self._ptr, A.data_ptr(), B.data_ptr(), n, k,
+                                           count.data_ptr(), jhat.data_ptr(),
+                                           self._stream(stream)), "wmh_estimate")
+        return count, jhat
+
+    def collisions(self, A, B, stream=None):
+        """All pairs: counts [NA, NB] (uint32 in an int32 tensor)."""
+        torch = _torch()
+        na, k = A.shape
+        nb = B.shape[0]
+        counts = torch.empty((na, nb), dtype=torch.int32, device=A.device)
+        self._check(self._lib.wmh_collisions(self._ptr, A.data_ptr(), na, B.data_ptr(), nb, k,
+                                             counts.data_ptr(), self._stream(stream)),
+                    "wmh_collisions")
+        return counts

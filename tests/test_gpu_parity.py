@@ -1,0 +1,306 @@
+"""GPU parity: the HIP library through its C-ABI against the CPU oracle, bit for bit.
+
+Signatures are integers, so the bar is exact equality.  Inputs come from the seeded generators
+in paper_1602_08393_amd.synth; the oracle never sees the GPU's outputs except to compare.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_1602_08393_amd import synth, wmh  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = wmh.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_sig(ctx, ds, k, seed=0, **opts):
+    ctx.set_bounds(ds.m)
+    rows = wmh.upload_dataset(ds, DEV)
+    return wmh.sig_to_numpy(ctx.hash(rows, k, seed=seed, **opts))
+
+
+def assert_same(got, want, what):
+    if not np.array_equal(got, want):
+        bad = np.argwhere(got != want)
+        r, j = bad[0]
+        raise AssertionError(f"{what}: {len(bad)} of {want.size} differ; first at row {r} hash "
+                             f"{j}: gpu {got[r, j]} oracle {want[r, j]}")
+
+
+# ---------------------------------------------------------------------------------------------
+# A3/A4: the position sequence and the component lookup
+# ---------------------------------------------------------------------------------------------
+
+def test_draws_match_oracle_config1(ctx):
+    ds = synth.config1()
+    ctx.set_bounds(ds.m)
+    M = int(ds.m.astype(np.uint64).sum())
+    P = np.concatenate([[0], np.cumsum(ds.m.astype(np.uint64))]).astype(np.uint64)
+    for seed in (0, 0x0123456789ABCDEF):
+        pos, comp, off = ctx.draws(seed, 5, 6, 301)
+        for jj in range(6):
+            for t in range(1, 302):
+                p, _ = oracle.position(seed, 5 + jj, t, M)
+                assert int(pos[jj, t - 1]) == p
+        c = np.searchsorted(P[:-1], pos, side="right") - 1
+        assert np.array_equal(comp, c.astype(np.uint32))
+        assert np.array_equal(off, pos - P[c])
+
+
+def test_draws_redraw_path_at_huge_total(ctx):
+    """M close to 2^52: about one word in 2^12 is rejected and redrawn."""
+    D = 1 << 20
+    m = np.full(D, 0xFFFFFFFF, dtype=np.uint32)
+    m[::7] = 0xFFFF0000
+    ctx.set_bounds(m)
+    M = int(m.astype(np.uint64).sum())
+    depth, nh = 2048, 32
+    pos, comp, off = ctx.draws(99, 1000, nh, depth)
+    redraws = 0
+    for jj in range(nh):
+        for t in range(1, depth + 1):
+            p, used = oracle.position(99, 1000 + jj, t, M)
+            redraws += used > 1
+            assert int(pos[jj, t - 1]) == p, (jj, t)
+    assert redraws >= 3
+    P = np.concatenate([[0], np.cumsum(m.astype(np.uint64))]).astype(np.uint64)
+    c = np.searchsorted(P[:-1], pos, side="right") - 1
+    assert np.array_equal(comp, c.astype(np.uint32))
+    assert np.array_equal(off, pos - P[c])
+
+
+def test_draws_with_zero_bounds_and_clusters(ctx):
+    rng = np.random.Generator(np.random.PCG64(3))
+    D = 5000
+    m = np.where(rng.random(D) < 0.8, rng.integers(0, 2, D), rng.integers(1, 2 ** 32, D))
+    m = m.astype(np.uint32)
+    ctx.set_bounds(m)
+    P = np.concatenate([[0], np.cumsum(m.astype(np.uint64))]).astype(np.uint64)
+    pos, comp, off = ctx.draws(7, 0, 16, 1000)
+    c = np.searchsorted(P[:-1], pos, side="right") - 1
+    assert np.array_equal(comp, c.astype(np.uint32))
+    assert np.all(m[comp] > 0)
+    assert np.array_equal(off, pos - P[c])
+    assert np.all(off < m[comp].astype(np.uint64))
+
+
+# ---------------------------------------------------------------------------------------------
+# Whole signatures
+# ---------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("opts", [
+    dict(mode="plain"),
+    dict(mode="plain", batch_rows=100),
+    dict(mode="batched"),
+    dict(mode="batched", use_graph=False),
+    dict(mode="auto"),
+])
+def test_config1_full(ctx, opts):
+    ds = synth.config1()
+    want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, ds.k, seed=0)
+    assert_same(gpu_sig(ctx, ds, ds.k, 0, **opts), want, f"config1 {opts}")
+
+
+BATCHED_PLANS = [
+    dict(rows_per_block=1), dict(rows_per_block=2), dict(rows_per_block=4),
+    dict(rows_per_block=8), dict(rows_per_block=16),
+    dict(rows_per_block=4, hashes_per_tile=7),
+    dict(rows_per_block=8, waves_per_block=1), dict(rows_per_block=2, waves_per_block=16),
+    dict(rows_per_block=4, stream_depth=None),   # every draw made in-lane
+    dict(rows_per_block=4, stream_depth=64),     # stream for the first window only
+]
+
+CASES = {
+    # name: (generator kwargs, k, seed)
+    "ragged-empty-zero-dims": (dict(seed=1, n_rows=37, D=300, density=0.2, max_val=60000,
+                                    bound_slack=5000, empty_rows=5, zero_bound_dims=20), 70, 11),
+    "wide-values": (dict(seed=2, n_rows=29, D=257, density=0.1, max_val=2 ** 32 - 1,
+                         bound_slack=0, empty_rows=1), 33, 12),
+    "dense-small-D": (dict(seed=3, n_rows=50, D=1, density=1.0, max_val=100, bound_slack=300), 65,
+                      13),
+    "sparse-slow": (dict(seed=4, n_rows=19, D=2000, density=0.005, max_val=500,
+                         bound_slack=60000), 40, 14),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_random_cases_all_plans(ctx, name):
+    kw, k, seed = CASES[name]
+    ds = synth.random_case(k=k, **kw)
+    want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, k, seed=seed)
+    assert_same(gpu_sig(ctx, ds, k, seed, mode="plain"), want, f"{name} plain")
+    for plan in BATCHED_PLANS:
+        got = gpu_sig(ctx, ds, k, seed, mode="batched", **plan)
+        assert_same(got, want, f"{name} batched {plan}")
+
+
+def test_full_rows_hash_to_one_and_saturation(ctx):
+    """x = m gives h = 1 everywhere; s = 1/2^40 saturates every hash at 65535."""
+    m = np.full(256, 0xFFFFFFFF, dtype=np.uint32)
+    X = np.zeros((6, 256), dtype=np.uint32)
+    X[0] = m
+    X[1, 3] = 1
+    X[2, 200] = 1
+    X[3, :] = m
+    X[3, 7] = 0
+    ds = synth.csr_from_dense(X, m=m)
+    k = 20
+    want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, k, seed=5)
+    assert np.all(want[0] == 1) and np.all(want[1] == 65535)
+    for opts in (dict(mode="plain"), dict(mode="batched", rows_per_block=4),
+                 dict(mode="batched", rows_per_block=2, stream_depth=128)):
+        assert_same(gpu_sig(ctx, ds, k, 5, **opts), want, f"saturation {opts}")
+
+
+def test_large_dimension_sparse_rows(ctx):
+    """D = 2^20 (dense rows do not fit in LDS): the sparse plain path; includes the redraw
+    path of the bounded draw (M near 2^52)."""
+    D = 1 << 20
+    rng = np.random.Generator(np.random.PCG64(8))
+    m = np.full(D, 0xFFFFFFFF, dtype=np.uint32)
+    cols, vals = [], []
+    for r in range(12):
+        c = np.sort(rng.choice(D, size=int(rng.integers(1, 3000)), replace=False))
+        cols.append(c)
+        vals.append(m[c] - rng.integers(0, 2 ** 20, size=len(c)).astype(np.uint32))
+    ds = synth.csr_from_lists(cols, vals, D, m=m)
+    k = 24
+    want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, k, seed=3)
+    assert_same(gpu_sig(ctx, ds, k, 3), want, "D=2^20 auto")
+    assert_same(gpu_sig(ctx, ds, k, 3, mode="plain"), want, "D=2^20 plain")
+
+
+def test_config2_head(ctx):
+    ds = synth.config2(n_rows=512)
+    want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, 500, seed=0)
+    assert_same(gpu_sig(ctx, ds, 500, 0, mode="plain"), want, "config2 head plain")
+    assert_same(gpu_sig(ctx, ds, 500, 0, mode="batched"), want, "config2 head batched")
+
+
+@pytest.fixture(scope="module")
+def config4():
+    return synth.config4()
+
+
+def test_config4_head_full_bounds(ctx, config4):
+    ds = config4.head(300)
+    want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, 500, seed=0)
+    assert_same(gpu_sig(ctx, ds, 500, 0, mode="batched"), want, "config4 head batched")
+    assert_same(gpu_sig(ctx, ds, 500, 0, mode="plain"), want, "config4 head plain")
+
+
+def test_prefix_property_and_determinism(ctx):
+    ds = synth.config1().head(200)
+    a = gpu_sig(ctx, ds, 64, 9, mode="batched")
+    b = gpu_sig(ctx, ds, 500, 9, mode="batched")
+    c = gpu_sig(ctx, ds, 500, 9, mode="batched", rows_per_block=16, hashes_per_tile=33)
+    d = gpu_sig(ctx, ds, 500, 9, mode="plain", batch_rows=17)
+    assert np.array_equal(a, b[:, :64])
+    assert np.array_equal(b, c) and np.array_equal(b, d)
+    for _ in range(3):
+        assert np.array_equal(gpu_sig(ctx, ds, 500, 9, mode="batched"), b)
+
+
+# ---------------------------------------------------------------------------------------------
+# Validation, errors, empty input
+# ---------------------------------------------------------------------------------------------
+
+def _rows(rp, col, val):
+    return wmh.upload_rows(np.array(rp, np.uint64), np.array(col, np.uint32),
+                           np.array(val, np.uint32), DEV)
+
+
+@pytest.mark.parametrize("rp,col,val,status", [
+    ([0, 2, 3], [0, 5, 1], [1, 1, 1], "WMH_E_COL_RANGE"),
+    ([0, 2, 3], [1, 1, 1], [1, 1, 1], "WMH_E_UNSORTED"),
+    ([0, 2, 3], [2, 1, 1], [1, 1, 1], "WMH_E_UNSORTED"),
+    ([0, 2, 3], [0, 1, 2], [1, 9, 1], "WMH_E_BOUND"),
+    ([0, 2, 1], [0, 1, 2], [1, 1, 1], "WMH_E_ROW_PTR"),
+    ([0, 2, 4], [0, 1, 2], [1, 1, 1], "WMH_E_ROW_PTR"),
+])
+def test_validation_errors_leave_output_untouched(ctx, rp, col, val, status):
+    m = np.array([5, 5, 5, 5], dtype=np.uint32)
+    ctx.set_bounds(m)
+    rows = _rows(rp, col, val)
+    rows.nnz = 3
+    for mode in ("plain", "batched"):
+        sig = torch.full((2, 8), 0x5A5A, dtype=torch.int16, device=DEV)
+        with pytest.raises(wmh.WMHError) as e:
+            ctx.hash_into(rows, 8, 0, sig, opts=ctx.make_opts(mode=mode))
+        assert e.value.name == status, ctx.last_error()
+        assert torch.all(sig == 0x5A5A)
+        assert "row" in ctx.last_error()
+
+
+def test_empty_rows_and_empty_batch(ctx):
+    m = np.array([3, 4], dtype=np.uint32)
+    ds = synth.csr_from_dense(np.zeros((5, 2), dtype=np.uint32), m=m)
+    for mode in ("plain", "batched"):
+        assert np.all(gpu_sig(ctx, ds, 10, 0, mode=mode) == 0)
+    rows = wmh.upload_rows(np.zeros(1, np.uint64), np.zeros(0, np.uint32),
+                           np.zeros(0, np.uint32), DEV)
+    ctx.hash_into(rows, 10, 0, torch.empty(0, dtype=torch.int16, device=DEV))
+
+
+def test_bad_arguments(ctx):
+    fresh = wmh.Context(0)
+    rows = _rows([0, 1], [0], [1])
+    with pytest.raises(wmh.WMHError) as e:
+        fresh.hash(rows, 4)
+    assert e.value.name == "WMH_E_NO_BOUNDS"
+    with pytest.raises(wmh.WMHError) as e:
+        fresh.set_bounds(np.zeros(3, dtype=np.uint32))
+    assert e.value.name == "WMH_E_OVERFLOW"
+    fresh.set_bounds(np.array([2], dtype=np.uint32))
+    with pytest.raises(wmh.WMHError) as e:
+        fresh.hash(rows, 0)
+    assert e.value.name == "WMH_E_ARG"
+    fresh.close()
+
+
+# ---------------------------------------------------------------------------------------------
+# A8: estimator and all-pairs collision counts
+# ---------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("na,nb,k", [(1, 1, 1), (3, 5, 7), (64, 64, 64), (70, 129, 33),
+                                     (200, 150, 500)])
+def test_collisions_random_signatures(ctx, na, nb, k):
+    rng = np.random.Generator(np.random.PCG64(na * 1000 + nb))
+    A = rng.integers(0, 4, size=(na, k)).astype(np.uint16)
+    B = rng.integers(0, 4, size=(nb, k)).astype(np.uint16)
+    A[:, ::5] = 65535
+    B[:, ::7] = 65535
+    want = oracle.collisions_all_pairs(A, B)
+    tA = torch.from_numpy(A.view(np.int16)).to(DEV)
+    tB = torch.from_numpy(B.view(np.int16)).to(DEV)
+    got = ctx.collisions(tA, tB).cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, want)
+    n = min(na, nb)
+    count, jhat = ctx.estimate(tA[:n].contiguous(), tB[:n].contiguous())
+    count = count.cpu().numpy().view(np.uint32)
+    jhat = jhat.cpu().numpy()
+    for i in range(n):
+        assert count[i] == oracle.collisions(A[i], B[i])
+        assert jhat[i] == oracle.estimate(A[i], B[i])
+
+
+def test_collisions_on_real_signatures(ctx, config4):
+    ds = config4.head(96)
+    sig = gpu_sig(ctx, ds, 500, 0)
+    A, B = sig[:40], sig[40:]
+    want = oracle.collisions_all_pairs(A, B)
+    got = ctx.collisions(torch.from_numpy(A.view(np.int16)).to(DEV),
+                         torch.from_numpy(B.view(np.int16)).to(DEV)).cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, want)
