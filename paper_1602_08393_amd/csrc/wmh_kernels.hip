@@ -19,6 +19,12 @@ namespace {
 
 __device__ __forceinline__ uint32_t lane() { return threadIdx.x & (kWave - 1u); }
 
+// Index of this wavefront in its workgroup, in a scalar register.
+__device__ __forceinline__ uint32_t wave_index()
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+}
+
 // Number of set bits of `mask` below this lane.
 __device__ __forceinline__ uint32_t count_below(uint64_t mask)
 {
@@ -50,7 +56,7 @@ __global__ __launch_bounds__(256) void validate_kernel(Rows rows, const uint32_t
                                                        uint32_t dims, CheckWords *words)
 {
     const uint32_t waves = blockDim.x / kWave;
-    const uint64_t first = (uint64_t)blockIdx.x * waves + threadIdx.x / kWave;
+    const uint64_t first = (uint64_t)blockIdx.x * waves + wave_index();
     const uint64_t stride = (uint64_t)gridDim.x * waves;
     for (uint64_t r = first; r < rows.n_rows; r += stride) {
         const uint64_t lo = rows.row_ptr[r];
@@ -93,7 +99,7 @@ __global__ __launch_bounds__(256) void plain_kernel(Bounds b, Rows rows, uint64_
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t waves = blockDim.x / kWave;
-    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t wave = wave_index();
     const uint64_t row = row_begin + (uint64_t)blockIdx.x * waves + wave;
     const bool live = row < row_end;
     const uint32_t D = b.dims;
@@ -244,8 +250,6 @@ __global__ __launch_bounds__(1024) void batched_kernel(Bounds b, Rows rows, uint
     const uint32_t n_hash_tiles = (k + hashes_per_tile - 1) / hashes_per_tile;
     const uint64_t n_tiles = n_blocks * n_hash_tiles;
     uint64_t staged = ~0ull;
-    const uint32_t wave = threadIdx.x / kWave;
-    (void)wave;
 
     while (true) {
         if (threadIdx.x == 0) {
@@ -281,21 +285,23 @@ __global__ __launch_bounds__(1024) void batched_kernel(Bounds b, Rows rows, uint
             __syncthreads();
             staged = blk;
         }
-        const uint32_t live = nonempty;  // rows of the block with a green region
+        // Wave-uniform values are read into scalar registers so every branch on them is a
+        // scalar branch: no lane-divergent region sits on the unit loop's path.
+        const uint32_t live = __builtin_amdgcn_readfirstlane(nonempty);
         const uint32_t j0 = ht * hashes_per_tile;
         const uint32_t j1 = min(k, j0 + hashes_per_tile);
 
         while (true) {
-            uint32_t unit = 0;
-            if (lane() == 0) unit = atomicAdd(&unit_slot, 1u);
-            unit = __shfl(unit, 0);
-            const uint32_t j = j0 + unit;
+            // claim the next hash id of the tile.  All 64 lanes add 1 (no lane-divergent
+            // region here), so the counter only moves in steps of 64 and every value one
+            // wave instruction returns lies in [64u, 64u + 64): shifting any lane's value by 6
+            // gives the wave's claim u, whatever order the lanes are serviced in.
+            const uint32_t claimed = atomicAdd(&unit_slot, 1u);
+            const uint32_t j = j0 + ((uint32_t)__builtin_amdgcn_readfirstlane(claimed) >> 6);
             if (j >= j1) break;
 
             uint32_t pending = live;
-            uint32_t h[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) h[r] = 0;
+            uint32_t hv = 0;  // lane r < R holds the hash value of row r
             const StreamEntry *col_entries = entries + (uint64_t)j * depth;
             for (uint32_t base = 0; pending != 0 && base < kCap; base += kWave) {
                 const uint32_t t = base + lane() + 1u;
@@ -317,19 +323,18 @@ __global__ __launch_bounds__(1024) void batched_kernel(Bounds b, Rows rows, uint
                 for (int r = 0; r < R; ++r) {
                     const uint64_t m = __ballot(in_range && off < (uint32_t)xc[r]);
                     if (((pending >> r) & 1u) && m != 0) {
-                        h[r] = base + (uint32_t)__ffsll((unsigned long long)m);
+                        const uint32_t h = base + (uint32_t)__ffsll((unsigned long long)m);
+                        hv = lane() == (uint32_t)r ? h : hv;
                         pending &= ~(1u << r);
                     }
                 }
             }
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                if ((pending >> r) & 1u) h[r] = kCap;
-            uint32_t mine = 0;
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (lane() == (uint32_t)r) mine = h[r];
-            if (lane() < (uint32_t)R) hbuf[lane() * hashes_per_tile + (j - j0)] = (uint16_t)mine;
+            // rows still pending after the last window saturate at the cap
+            hv = (lane() < (uint32_t)R && ((pending >> lane()) & 1u)) ? kCap : hv;
+            // every lane stores; lanes >= R write to their own slot past the tile's values
+            const uint32_t slot = lane() < (uint32_t)R ? lane() * hashes_per_tile + (j - j0)
+                                                      : R * hashes_per_tile + lane();
+            hbuf[slot] = (uint16_t)hv;
         }
         __syncthreads();
         // write the tile's signatures row by row (coalesced along j)
@@ -357,7 +362,7 @@ __global__ __launch_bounds__(256) void estimate_kernel(const uint16_t *__restric
                                                        uint32_t *count, double *jhat)
 {
     const uint32_t waves = blockDim.x / kWave;
-    const uint64_t first = (uint64_t)blockIdx.x * waves + threadIdx.x / kWave;
+    const uint64_t first = (uint64_t)blockIdx.x * waves + wave_index();
     const uint64_t stride = (uint64_t)gridDim.x * waves;
     for (uint64_t i = first; i < n_pairs; i += stride) {
         const uint16_t *a = A + i * k;
@@ -433,7 +438,8 @@ size_t batched_lds_bytes(uint32_t dims, const BatchedPlan &plan)
 {
     const size_t xbytes = (size_t)dims * plan.rows_per_block * (plan.narrow ? 2 : 4);
     const size_t aligned = (xbytes + 15) & ~(size_t)15;
-    return aligned + (size_t)plan.rows_per_block * plan.hashes_per_tile * 2;
+    // per-row hash values of a tile, then one spare slot per lane
+    return aligned + ((size_t)plan.rows_per_block * plan.hashes_per_tile + kWave) * 2;
 }
 
 template <typename XT, int R>

@@ -26,6 +26,7 @@ def ctx():
 
 
 def gpu_sig(ctx, ds, k, seed=0, **opts):
+    print(f"  gpu: {ds.name} N={ds.n_rows} D={ds.D} k={k} seed={seed} {opts}", flush=True)
     ctx.set_bounds(ds.m)
     rows = wmh.upload_dataset(ds, DEV)
     return wmh.sig_to_numpy(ctx.hash(rows, k, seed=seed, **opts))
@@ -60,12 +61,16 @@ def test_draws_match_oracle_config1(ctx):
 
 
 def test_draws_redraw_path_at_huge_total(ctx):
-    """M close to 2^52: about one word in 2^12 is rejected and redrawn."""
+    """M = ceil(2^64 / 4097), so 2^64 mod M is close to M and about one word in 4097 is
+    rejected and redrawn."""
     D = 1 << 20
-    m = np.full(D, 0xFFFFFFFF, dtype=np.uint32)
-    m[::7] = 0xFFFF0000
+    target = -(-(1 << 64) // 4097)
+    m = np.full(D, target // D, dtype=np.uint64)
+    m[: target - int(m.sum())] += 1
+    m = m.astype(np.uint32)
     ctx.set_bounds(m)
     M = int(m.astype(np.uint64).sum())
+    assert M == target and ((1 << 64) % M) > 0.99 * M
     depth, nh = 2048, 32
     pos, comp, off = ctx.draws(99, 1000, nh, depth)
     redraws = 0
@@ -74,7 +79,7 @@ def test_draws_redraw_path_at_huge_total(ctx):
             p, used = oracle.position(99, 1000 + jj, t, M)
             redraws += used > 1
             assert int(pos[jj, t - 1]) == p, (jj, t)
-    assert redraws >= 3
+    assert redraws >= 5
     P = np.concatenate([[0], np.cumsum(m.astype(np.uint64))]).astype(np.uint64)
     c = np.searchsorted(P[:-1], pos, side="right") - 1
     assert np.array_equal(comp, c.astype(np.uint32))
