@@ -44,7 +44,21 @@ def parse():
     ap.add_argument("--stream-depth", type=int, default=0)
     ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--only", choices=["batched", "plain", "both"], default="both")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run device-to-device copies of BYTES (scales HBM counters)")
     return ap.parse_args()
+
+
+def copy_calibration(nbytes: int):
+    """Three device-to-device copies of a known size, for scaling FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "copies": 3}), flush=True)
 
 
 def timed_steps(ctx, rows, k, sig, opts, steps, warmup, torch):
@@ -92,6 +106,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the hash walk "
               "shards by rows with no exchange step, see DESIGN.md", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     import torch
     from paper_1602_08393_amd import synth, wmh
 
@@ -118,11 +135,16 @@ def main():
     result = {}
     if args.only in ("batched", "both"):
         opts = ctx.make_opts(mode="batched", profile=True, **plan)
-        log("batched: warmup + timed steps")
-        el, walk, build = timed_steps(ctx, rows, k, sig, opts, args.steps, args.warmup, torch)
-        result["batched"] = (el, walk, build)
-        log(f"batched: {el / args.steps * 1e3:.3f} ms/step, walk kernel "
-            f"{np.mean(walk):.3f} ms, stream build {np.mean(build):.3f} ms")
+        log("batched: warmup + timed steps (hipGraph replay)")
+        el, graph_ms, _ = timed_steps(ctx, rows, k, sig, opts, args.steps, args.warmup, torch)
+        # the same kernels launched directly, with events between them on the launch stream,
+        # to time the walk kernel alone
+        dopts = ctx.make_opts(mode="batched", profile=True, use_graph=False, **plan)
+        _, walk, build = timed_steps(ctx, rows, k, sig, dopts, max(3, min(args.steps, 5)), 1,
+                                     torch)
+        result["batched"] = (el, walk, build, graph_ms)
+        log(f"batched: {el / args.steps * 1e3:.3f} ms/step, graph {np.mean(graph_ms):.3f} ms, "
+            f"walk kernel {np.mean(walk):.3f} ms, stream build {np.mean(build):.3f} ms")
     if args.only in ("plain", "both"):
         psteps = args.plain_steps or min(args.steps, 5)
         opts = ctx.make_opts(mode="plain", profile=True)
@@ -173,8 +195,9 @@ def main():
                          "walk_ms": float(np.mean(pwalk)), "steps": psteps}
         line["batched_over_plain"] = value / plain_value
         line["batched_equals_plain"] = same
-        bel, bwalk, bbuild = result["batched"]
-        line["batched_detail"] = {"walk_ms": float(np.mean(bwalk)),
+        bel, bwalk, bbuild, bgraph = result["batched"]
+        line["batched_detail"] = {"graph_ms": float(np.mean(bgraph)),
+                                  "walk_ms": float(np.mean(bwalk)),
                                   "stream_build_ms": float(np.mean(bbuild))}
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a sample")

@@ -75,8 +75,9 @@ typedef struct {
     /* batched-mode tile plan overrides; 0 = planner / autotuner choice */
     uint32_t rows_per_block;   /* R: rows whose dense rows share one walk (1, 2, 4, 8, 16) */
     uint32_t hashes_per_tile;  /* J: hash ids per tile */
-    uint32_t stream_depth;     /* T0: steps of the shared position stream built per call;
-                                  steps beyond it are drawn in-lane.  UINT32_MAX disables it */
+    uint32_t stream_depth;     /* T0: steps of the shared position stream built per call
+                                  (rounded up to a multiple of 64, at most 65536); steps beyond
+                                  it are drawn in-lane.  UINT32_MAX: the shortest stream (64) */
     uint32_t waves_per_block;  /* wavefronts per workgroup (1..16) */
     int32_t profile;           /* 1: time the walk kernels with HIP events on the launch stream
                                   (read back with wmh_last_kernel_ms) */
@@ -175,8 +176,10 @@ wmh_status wmh_bounds_tables(const uint32_t *m, uint32_t D, uint64_t *prefix, ui
 
 /*
  * wmh_last_kernel_ms -- device time of the last wmh_hash call made with opts->profile = 1,
- * from HIP events recorded on the launch stream: *walk_ms spans the hash-walk kernels (the
- * batched kernel, or every plain launch), *stream_ms the shared-stream build (0 if none).
+ * from HIP events recorded on the launch stream.  Direct launches: *walk_ms spans the
+ * hash-walk kernels (the batched kernel, or every plain launch), *stream_ms the shared-stream
+ * build (0 if none).  hipGraph replays (batched with use_graph): *walk_ms spans the whole
+ * graph (counter reset, stream build and walk) and *stream_ms is 0.
  * Requires that call to have completed (opts->sync, or a later synchronization).
  * Errors: WMH_E_ARG (no profiled call yet), WMH_E_DEVICE.
  */

@@ -31,10 +31,15 @@ struct GraphKey {
     void *sig = nullptr;
     uint64_t n_rows = 0, nnz = 0, seed = 0;
     uint32_t k = 0, R = 0, J = 0, depth = 0, waves = 0, grid = 0;
-    bool narrow = false;
-    bool profile = false;
+    bool narrow = false, packed = false;
     uint64_t bounds_epoch = 0;
-    bool operator==(const GraphKey &o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
+    bool operator==(const GraphKey &o) const
+    {
+        return row_ptr == o.row_ptr && col == o.col && val == o.val && sig == o.sig &&
+               n_rows == o.n_rows && nnz == o.nnz && seed == o.seed && k == o.k && R == o.R &&
+               J == o.J && depth == o.depth && waves == o.waves && grid == o.grid &&
+               narrow == o.narrow && packed == o.packed && bounds_epoch == o.bounds_epoch;
+    }
 };
 
 }  // namespace
@@ -60,7 +65,7 @@ struct wmh_ctx {
     CheckWords *d_check = nullptr;
     CheckWords *h_check = nullptr;  // pinned
     uint32_t *d_tile_counter = nullptr;
-    StreamEntry *d_stream = nullptr;
+    void *d_stream = nullptr;
     size_t stream_bytes = 0;
     // graph of the batched launch
     hipGraphExec_t graph_exec = nullptr;
@@ -175,7 +180,8 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, uint64_t min_green, const wmh_
 {
     BatchedPlan p{};
     p.narrow = ctx->max_bound <= 0xFFFFu;
-    p.waves_per_block = o.waves_per_block ? std::min<uint32_t>(o.waves_per_block, 16u) : 4u;
+    p.packed = p.narrow && ctx->dims <= 65536u;
+    p.waves_per_block = o.waves_per_block ? std::min<uint32_t>(o.waves_per_block, 16u) : 8u;
     p.hashes_per_tile = o.hashes_per_tile ? std::min(o.hashes_per_tile, k) : std::min(k, 1024u);
     const size_t elem = p.narrow ? 2 : 4;
     const size_t lds_target = 48 * 1024;  // keep several workgroups resident per CU
@@ -188,9 +194,10 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, uint64_t min_green, const wmh_
     p.rows_per_block = R;
     if (batched_lds_bytes(ctx->dims, p) > 160 * 1024 - 64) return false;
     // shared stream depth: cover eight mean step counts of the sparsest row
+    // (the batched kernel always reads at least one window of the stream: depth >= 64)
     uint32_t depth;
     if (o.stream_depth == UINT32_MAX) {
-        depth = 0;
+        depth = 64;
     } else if (o.stream_depth) {
         depth = std::min<uint32_t>(65536u, (o.stream_depth + 63u) & ~63u);
     } else if (min_green != ~0ull && min_green != 0) {
@@ -201,7 +208,8 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, uint64_t min_green, const wmh_
     } else {
         depth = 4096;
     }
-    while (depth && (uint64_t)depth * k * sizeof(StreamEntry) > kStreamBudgetBytes) depth -= 64;
+    while (depth > 64 && (uint64_t)depth * k * stream_entry_bytes(p.packed) > kStreamBudgetBytes)
+        depth -= 64;
     p.stream_depth = depth;
     *plan = p;
     return true;
@@ -436,9 +444,9 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         ctx->profiled = profile;
         ctx->profiled_stream = false;
     } else {
-        if (plan.stream_depth) {
+        {
             wmh_status st = ensure_stream_capacity(
-                ctx, (size_t)plan.stream_depth * k * sizeof(StreamEntry));
+                ctx, (size_t)plan.stream_depth * k * stream_entry_bytes(plan.packed));
             if (st != WMH_OK) return st;
         }
         const int per_cu = std::max(1, batched_blocks_per_cu(ctx->dims, plan));
@@ -452,22 +460,24 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         key.n_rows = n_rows; key.nnz = nnz; key.seed = seed; key.k = k;
         key.R = plan.rows_per_block; key.J = plan.hashes_per_tile; key.depth = plan.stream_depth;
         key.waves = plan.waves_per_block; key.grid = grid; key.narrow = plan.narrow;
+        key.packed = plan.packed;
         key.bounds_epoch = ctx->bounds_epoch;
-        key.profile = profile;
 
-        auto enqueue = [&](hipStream_t q) -> hipError_t {
+        // events between kernels only on direct launches; a graph is timed as a whole
+        auto enqueue = [&](hipStream_t q, bool events) -> hipError_t {
             hipError_t e = launch_fill_u32(ctx->d_tile_counter, 0u, 1, q);
             if (e != hipSuccess) return e;
-            if (profile && (e = hipEventRecord(ctx->ev[0], q)) != hipSuccess) return e;
+            if (events && (e = hipEventRecord(ctx->ev[0], q)) != hipSuccess) return e;
             if (plan.stream_depth) {
-                e = launch_stream_build(b, seed, k, plan.stream_depth, ctx->d_stream, q);
+                e = launch_stream_build(b, seed, k, plan.stream_depth, plan.packed,
+                                        ctx->d_stream, q);
                 if (e != hipSuccess) return e;
             }
-            if (profile && (e = hipEventRecord(ctx->ev[1], q)) != hipSuccess) return e;
+            if (events && (e = hipEventRecord(ctx->ev[1], q)) != hipSuccess) return e;
             e = launch_batched(b, rows, k, seed, sig, plan, ctx->d_stream, ctx->d_tile_counter,
                                grid, q);
             if (e != hipSuccess) return e;
-            if (profile) e = hipEventRecord(ctx->ev[2], q);
+            if (events) e = hipEventRecord(ctx->ev[2], q);
             return e;
         };
 
@@ -476,7 +486,7 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
                 drop_graph(ctx);
                 hipGraph_t graph = nullptr;
                 WMH_HIP(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
-                hipError_t e = enqueue(ctx->capture_stream);
+                hipError_t e = enqueue(ctx->capture_stream, false);
                 hipError_t e2 = hipStreamEndCapture(ctx->capture_stream, &graph);
                 if (e != hipSuccess) {
                     if (graph) hipGraphDestroy(graph);
@@ -491,13 +501,16 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
                 }
                 ctx->graph_key = key;
             }
+            if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[1], s));
             WMH_HIP(ctx, hipGraphLaunch(ctx->graph_exec, s));
+            if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[2], s));
+            ctx->profiled_stream = false;
         } else {
-            hipError_t e = enqueue(s);
+            hipError_t e = enqueue(s, profile);
             if (e != hipSuccess) return device_fail(ctx, e, "batched launch");
+            ctx->profiled_stream = profile && plan.stream_depth != 0;
         }
         ctx->profiled = profile;
-        ctx->profiled_stream = profile && plan.stream_depth != 0;
     }
     if (o.sync) WMH_HIP(ctx, hipStreamSynchronize(s));
     return WMH_OK;

@@ -32,7 +32,9 @@ struct Rows {
     uint64_t nnz;
 };
 
-// One shared-stream entry: the component and the offset inside it of one step's position.
+// One shared-stream entry: the component c and the offset inside it of one step's position.
+// Wide entries are (c, offset) as two uint32; packed entries are (c << 16) | offset, used when
+// D <= 65536 and every bound is below 65536.
 struct StreamEntry {
     uint32_t comp;
     uint32_t offset;
@@ -44,7 +46,10 @@ struct BatchedPlan {
     uint32_t stream_depth;     // T0 (multiple of 64, <= 65536), 0 = no shared stream
     uint32_t waves_per_block;
     bool narrow;               // dense rows stored as uint16 (every bound < 65536)
+    bool packed;               // 4-byte stream entries
 };
+
+inline size_t stream_entry_bytes(bool packed) { return packed ? 4 : 8; }
 
 hipError_t launch_validate(const Rows &rows, const uint32_t *bound, uint32_t dims,
                            CheckWords *words, hipStream_t stream);
@@ -58,11 +63,11 @@ hipError_t launch_draws(const Bounds &b, uint64_t seed, uint32_t j0, uint32_t n_
                         hipStream_t stream);
 
 hipError_t launch_stream_build(const Bounds &b, uint64_t seed, uint32_t k, uint32_t depth,
-                               StreamEntry *entries, hipStream_t stream);
+                               bool packed, void *entries, hipStream_t stream);
 
 // Returns hipErrorInvalidValue when the plan does not fit (LDS).
 hipError_t launch_batched(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
-                          uint16_t *sig, const BatchedPlan &plan, const StreamEntry *entries,
+                          uint16_t *sig, const BatchedPlan &plan, const void *entries,
                           uint32_t *tile_counter, uint32_t grid, hipStream_t stream);
 
 // Dynamic LDS bytes a batched plan needs.

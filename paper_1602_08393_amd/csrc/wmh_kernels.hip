@@ -55,35 +55,71 @@ __device__ __forceinline__ uint64_t wave_min(uint64_t v)
 __global__ __launch_bounds__(256) void validate_kernel(Rows rows, const uint32_t *__restrict__ bound,
                                                        uint32_t dims, CheckWords *words)
 {
+    // per-workgroup partials, so each word gets at most one global atomic per workgroup
+    __shared__ unsigned long long part_err[256 / kWave], part_green[256 / kWave],
+        part_empty[256 / kWave];
     const uint32_t waves = blockDim.x / kWave;
     const uint64_t first = (uint64_t)blockIdx.x * waves + wave_index();
     const uint64_t stride = (uint64_t)gridDim.x * waves;
+    uint64_t w_err = ~0ull, w_green = ~0ull, w_empty = 0;  // this wave's partials (uniform)
     for (uint64_t r = first; r < rows.n_rows; r += stride) {
         const uint64_t lo = rows.row_ptr[r];
         const uint64_t hi = rows.row_ptr[r + 1];
         if (lo > hi || hi > rows.nnz) {
-            if (lane() == 0) atomicMin(&words->first_error, (r << 4) | kCheckRowPtr);
+            w_err = min(w_err, (unsigned long long)((r << 4) | kCheckRowPtr));
             continue;
         }
         uint64_t sum = 0;
         uint64_t bad = ~0ull;  // (entry << 4) | code of this lane's first bad entry
-        for (uint64_t e = lo + lane(); e < hi; e += kWave) {
-            const uint32_t c = rows.col[e];
-            const uint32_t v = rows.val[e];
-            uint32_t code = 0;
-            if (c >= dims) code = kCheckColumn;
-            else if (e > lo && rows.col[e - 1] >= c) code = kCheckUnsorted;
-            else if (v > bound[c]) code = kCheckBound;
-            if (code && bad == ~0ull) bad = ((e - lo) << 4) | code;
-            sum += v;
+        // each lane checks 4 consecutive entries per pass, so a wave has many loads in flight
+        constexpr uint32_t kPer = 4;
+        for (uint64_t e0 = lo + (uint64_t)lane() * kPer; e0 < hi; e0 += (uint64_t)kWave * kPer) {
+            uint32_t c[kPer], v[kPer], m[kPer];
+            const uint32_t prev = e0 > lo ? rows.col[e0 - 1] : 0u;
+#pragma unroll
+            for (uint32_t i = 0; i < kPer; ++i) {
+                const bool in = e0 + i < hi;
+                c[i] = in ? rows.col[e0 + i] : 0u;
+                v[i] = in ? rows.val[e0 + i] : 0u;
+            }
+#pragma unroll
+            for (uint32_t i = 0; i < kPer; ++i) m[i] = c[i] < dims ? bound[c[i]] : 0u;
+#pragma unroll
+            for (uint32_t i = 0; i < kPer; ++i) {
+                const uint64_t e = e0 + i;
+                if (e >= hi) break;
+                const uint32_t before = i ? c[i - 1] : prev;
+                uint32_t code = 0;
+                if (c[i] >= dims) code = kCheckColumn;
+                else if (e > lo && before >= c[i]) code = kCheckUnsorted;
+                else if (v[i] > m[i]) code = kCheckBound;
+                if (code && bad == ~0ull) bad = ((e - lo) << 4) | code;
+                sum += v[i];
+            }
         }
         bad = wave_min(bad);
         sum = wave_sum(sum);
-        if (lane() == 0) {
-            if (bad != ~0ull) atomicMin(&words->first_error, (r << 4) | (bad & 15u));
-            else if (sum == 0) atomicAdd(&words->n_empty, 1ull);
-            else atomicMin(&words->min_green, (unsigned long long)sum);
+        if (bad != ~0ull) w_err = min(w_err, (unsigned long long)((r << 4) | (bad & 15u)));
+        else if (sum == 0) ++w_empty;
+        else w_green = min(w_green, (unsigned long long)sum);
+    }
+    const uint32_t wave = wave_index();
+    if (lane() == 0) {
+        part_err[wave] = w_err;
+        part_green[wave] = w_green;
+        part_empty[wave] = w_empty;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long e = ~0ull, g = ~0ull, n = 0;
+        for (uint32_t w = 0; w < waves; ++w) {
+            e = min(e, part_err[w]);
+            g = min(g, part_green[w]);
+            n += part_empty[w];
         }
+        if (e != ~0ull) atomicMin(&words->first_error, e);
+        if (g != ~0ull) atomicMin(&words->min_green, g);
+        if (n) atomicAdd(&words->n_empty, n);
     }
 }
 
@@ -175,8 +211,9 @@ __global__ __launch_bounds__(256) void plain_kernel(Bounds b, Rows rows, uint64_
 // Shared position stream: entries[j * depth + t - 1] = (component, offset) of step t of hash
 // j, for t <= depth.  One thread per Philox block (two steps).
 // ---------------------------------------------------------------------------------------------
+template <bool kPacked>
 __global__ __launch_bounds__(256) void stream_kernel(Bounds b, uint64_t seed, uint32_t k,
-                                                     uint32_t depth, StreamEntry *__restrict__ entries)
+                                                     uint32_t depth, void *__restrict__ entries)
 {
     const uint64_t pairs = depth >> 1;
     const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -187,9 +224,16 @@ __global__ __launch_bounds__(256) void stream_kernel(Bounds b, uint64_t seed, ui
     position_pair(seed, j, pair, b.total, b.threshold, &p0, &p1);
     const uint32_t c0 = component_of(p0, b.prefix, b.bucket, b.shift, &off0);
     const uint32_t c1 = component_of(p1, b.prefix, b.bucket, b.shift, &off1);
-    StreamEntry *e = entries + (uint64_t)j * depth + 2ull * pair;
-    e[0] = StreamEntry{c0, (uint32_t)off0};
-    e[1] = StreamEntry{c1, (uint32_t)off1};
+    const uint64_t at = (uint64_t)j * depth + 2ull * pair;
+    if (kPacked) {
+        uint32_t *e = reinterpret_cast<uint32_t *>(entries) + at;
+        *reinterpret_cast<uint2 *>(e) = make_uint2((c0 << 16) | (uint32_t)off0,
+                                                   (c1 << 16) | (uint32_t)off1);
+    } else {
+        StreamEntry *e = reinterpret_cast<StreamEntry *>(entries) + at;
+        e[0] = StreamEntry{c0, (uint32_t)off0};
+        e[1] = StreamEntry{c1, (uint32_t)off1};
+    }
 }
 
 // The sequence with its lookup, written out: same device functions as stream_kernel.
@@ -231,13 +275,66 @@ __global__ __launch_bounds__(256) void draws_kernel(Bounds b, uint64_t seed, uin
 // window per (block, hash).  Draws come from the shared stream for t <= depth and are made
 // in-lane beyond it.
 // ---------------------------------------------------------------------------------------------
-template <typename XT, int R>
+// K consecutive shared-stream entries of one lane (4-byte packed or 8-byte wide), read with the
+// widest aligned loads: the first entry index is a multiple of K.
+template <int K, bool kPacked>
+struct EntryRun {
+    static constexpr int kWords = K * (kPacked ? 1 : 2);
+    uint32_t w[kWords];
+
+    __device__ __forceinline__ void load(const void *entries, uint64_t index)
+    {
+        const uint32_t *p = reinterpret_cast<const uint32_t *>(entries) + index * (kPacked ? 1 : 2);
+        if constexpr (kWords == 1) {
+            w[0] = p[0];
+        } else if constexpr (kWords == 2) {
+            const uint2 q = *reinterpret_cast<const uint2 *>(p);
+            w[0] = q.x;
+            w[1] = q.y;
+        } else {
+#pragma unroll
+            for (int i = 0; i < kWords / 4; ++i) {
+                const uint4 q = reinterpret_cast<const uint4 *>(p)[i];
+                w[4 * i] = q.x;
+                w[4 * i + 1] = q.y;
+                w[4 * i + 2] = q.z;
+                w[4 * i + 3] = q.w;
+            }
+        }
+    }
+    __device__ __forceinline__ void get(int k, uint32_t *c, uint32_t *off) const
+    {
+        if (kPacked) {
+            *c = w[k] >> 16;
+            *off = w[k] & 0xFFFFu;
+        } else {
+            *c = w[2 * k];
+            *off = w[2 * k + 1];
+        }
+    }
+};
+
+// Lanes [r * L, (r + 1) * L) of a wavefront, L = 64 / R.
+template <int R>
+__device__ __forceinline__ uint64_t row_lanes(uint32_t r)
+{
+    constexpr uint32_t L = kWave / R;
+    if constexpr (L == kWave) return ~0ull;
+    else return ((1ull << L) - 1ull) << (r * L);
+}
+
+template <typename XT, int R, bool kPacked>
 __global__ __launch_bounds__(1024) void batched_kernel(Bounds b, Rows rows, uint32_t k,
                                                        uint64_t seed, uint16_t *__restrict__ sig,
                                                        uint32_t hashes_per_tile, uint32_t depth,
-                                                       const StreamEntry *__restrict__ entries,
+                                                       const void *__restrict__ entries,
                                                        uint32_t *tile_counter)
 {
+    // Lane layout of one window: lane l serves row r = l / L (L = 64 / R lanes per row) and
+    // the K = R consecutive steps base + g*K + 1 .. base + g*K + K, g = l mod L; the 64 lanes
+    // cover steps base + 1 .. base + 64 of all R rows.
+    constexpr uint32_t L = kWave / R;
+    constexpr uint32_t K = R;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t tile_slot;
     __shared__ uint32_t unit_slot;
@@ -245,6 +342,8 @@ __global__ __launch_bounds__(1024) void batched_kernel(Bounds b, Rows rows, uint
     const uint32_t D = b.dims;
     XT *x = reinterpret_cast<XT *>(smem);
     uint16_t *hbuf = reinterpret_cast<uint16_t *>(smem + (((size_t)D * R * sizeof(XT) + 15) & ~(size_t)15));
+    const uint32_t my_row = lane() / L;
+    const uint32_t my_grp = lane() % L;
 
     const uint64_t n_blocks = (rows.n_rows + R - 1) / R;
     const uint32_t n_hash_tiles = (k + hashes_per_tile - 1) / hashes_per_tile;
@@ -288,6 +387,10 @@ __global__ __launch_bounds__(1024) void batched_kernel(Bounds b, Rows rows, uint
         // Wave-uniform values are read into scalar registers so every branch on them is a
         // scalar branch: no lane-divergent region sits on the unit loop's path.
         const uint32_t live = __builtin_amdgcn_readfirstlane(nonempty);
+        uint64_t live_lanes = 0;  // lanes of the rows that have a green region
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if ((live >> r) & 1u) live_lanes |= row_lanes<R>(r);
         const uint32_t j0 = ht * hashes_per_tile;
         const uint32_t j1 = min(k, j0 + hashes_per_tile);
 
@@ -300,37 +403,70 @@ __global__ __launch_bounds__(1024) void batched_kernel(Bounds b, Rows rows, uint
             const uint32_t j = j0 + ((uint32_t)__builtin_amdgcn_readfirstlane(claimed) >> 6);
             if (j >= j1) break;
 
-            uint32_t pending = live;
-            uint32_t hv = 0;  // lane r < R holds the hash value of row r
-            const StreamEntry *col_entries = entries + (uint64_t)j * depth;
-            for (uint32_t base = 0; pending != 0 && base < kCap; base += kWave) {
-                const uint32_t t = base + lane() + 1u;
-                uint32_t c;
-                uint32_t off;
+            uint64_t pend = live_lanes;  // lanes of rows still walking
+            uint32_t hv = 0;             // lane r < R holds the hash value of row r
+            // The stream holds depth >= 64 steps per hash id.  Entries are prefetched three
+            // windows ahead into a ring of three register sets, each reloaded in place right
+            // after its window is tested; the loads use clamped, in-bounds indices (windows
+            // past the stream re-read its last window and ignore it) so they stay straight-line
+            // code and no register with a load in flight is ever copied.
+            const uint64_t lane_first = (uint64_t)j * depth + my_grp * K;
+            const uint32_t last_base = depth - kWave;
+            auto fetch = [&](uint32_t base) {
+                EntryRun<K, kPacked> run;
+                run.load(entries, lane_first + min(base, last_base));
+                return run;
+            };
+            // tests window [base + 1, base + 64]; false once the walk is over
+            auto window = [&](const EntryRun<K, kPacked> &run, uint32_t base) -> bool {
+                if (pend == 0 || base >= kCap) return false;
+                uint32_t first = K;  // first green step of this lane's K, K if none
                 if (base < depth) {
-                    const StreamEntry e = col_entries[t - 1u];
-                    c = e.comp;
-                    off = e.offset;
-                } else {
-                    const uint64_t p = position(seed, j, t, b.total, b.threshold);
-                    uint64_t o64;
-                    c = component_of(p, b.prefix, b.bucket, b.shift, &o64);
-                    off = (uint32_t)o64;
-                }
-                const bool in_range = t <= kCap;
-                const XT *xc = x + (size_t)c * R;
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const uint64_t m = __ballot(in_range && off < (uint32_t)xc[r]);
-                    if (((pending >> r) & 1u) && m != 0) {
-                        const uint32_t h = base + (uint32_t)__ffsll((unsigned long long)m);
-                        hv = lane() == (uint32_t)r ? h : hv;
-                        pending &= ~(1u << r);
+                    for (int q = K - 1; q >= 0; --q) {
+                        uint32_t c, off;
+                        run.get(q, &c, &off);
+                        first = off < (uint32_t)x[(size_t)c * R + my_row] ? (uint32_t)q : first;
+                    }
+                } else {
+#pragma unroll
+                    for (int q = K - 1; q >= 0; --q) {
+                        const uint32_t t = base + my_grp * K + q + 1u;
+                        const uint64_t p = position(seed, j, t, b.total, b.threshold);
+                        uint64_t o64;
+                        const uint32_t c = component_of(p, b.prefix, b.bucket, b.shift, &o64);
+                        first = o64 < (uint64_t)x[(size_t)c * R + my_row] ? (uint32_t)q : first;
                     }
                 }
+                // in the last window the lane holding step 65536 may not count it
+                if (base + kWave > kCap)
+                    first = (my_grp == L - 1 && first == K - 1) ? K : first;
+                uint64_t hit = __builtin_amdgcn_ballot_w64(first < K) & pend;
+                // the lowest hit lane is the first green lane of its row (lower lanes of that
+                // row had no green step); handle each row once, lowest first
+                while (hit != 0) {
+                    const uint32_t l = (uint32_t)__builtin_ctzll(hit);
+                    const uint32_t r = l / L;
+                    const uint32_t q = (uint32_t)__builtin_amdgcn_readlane(first, l);
+                    const uint32_t h = base + (l % L) * K + q + 1u;
+                    hv = lane() == r ? h : hv;
+                    const uint64_t done = row_lanes<R>(r);
+                    hit &= ~done;
+                    pend &= ~done;
+                }
+                return true;
+            };
+            EntryRun<K, kPacked> e0 = fetch(0), e1 = fetch(kWave), e2 = fetch(2 * kWave);
+            for (uint32_t base = 0;; base += 3 * kWave) {
+                if (!window(e0, base)) break;
+                e0 = fetch(base + 3 * kWave);
+                if (!window(e1, base + kWave)) break;
+                e1 = fetch(base + 4 * kWave);
+                if (!window(e2, base + 2 * kWave)) break;
+                e2 = fetch(base + 5 * kWave);
             }
-            // rows still pending after the last window saturate at the cap
-            hv = (lane() < (uint32_t)R && ((pending >> lane()) & 1u)) ? kCap : hv;
+            // rows still walking after the last window saturate at the cap
+            hv = (lane() < (uint32_t)R && ((pend >> (lane() * L)) & 1ull)) ? kCap : hv;
             // every lane stores; lanes >= R write to their own slot past the tile's values
             const uint32_t slot = lane() < (uint32_t)R ? lane() * hashes_per_tile + (j - j0)
                                                       : R * hashes_per_tile + lane();
@@ -388,7 +524,7 @@ hipError_t launch_validate(const Rows &rows, const uint32_t *bound, uint32_t dim
 {
     if (rows.n_rows == 0) return hipSuccess;
     const uint64_t waves_needed = rows.n_rows;
-    const uint32_t grid = (uint32_t)std::min<uint64_t>((waves_needed + 3) / 4, 8192);
+    const uint32_t grid = (uint32_t)std::min<uint64_t>((waves_needed + 3) / 4, 2048);
     validate_kernel<<<grid, 256, 0, stream>>>(rows, bound, dims, words);
     return hipGetLastError();
 }
@@ -425,12 +561,13 @@ hipError_t launch_draws(const Bounds &b, uint64_t seed, uint32_t j0, uint32_t n_
 }
 
 hipError_t launch_stream_build(const Bounds &b, uint64_t seed, uint32_t k, uint32_t depth,
-                               StreamEntry *entries, hipStream_t stream)
+                               bool packed, void *entries, hipStream_t stream)
 {
     if (depth == 0 || k == 0) return hipSuccess;
     const uint64_t threads = (uint64_t)k * (depth / 2);
     const uint32_t grid = (uint32_t)((threads + 255) / 256);
-    stream_kernel<<<grid, 256, 0, stream>>>(b, seed, k, depth, entries);
+    if (packed) stream_kernel<true><<<grid, 256, 0, stream>>>(b, seed, k, depth, entries);
+    else stream_kernel<false><<<grid, 256, 0, stream>>>(b, seed, k, depth, entries);
     return hipGetLastError();
 }
 
@@ -442,82 +579,100 @@ size_t batched_lds_bytes(uint32_t dims, const BatchedPlan &plan)
     return aligned + ((size_t)plan.rows_per_block * plan.hashes_per_tile + kWave) * 2;
 }
 
-template <typename XT, int R>
+template <typename XT, int R, bool kPacked>
 static void configure_batched()
 {
     static bool configured = false;
     if (!configured) {
-        hipFuncSetAttribute((const void *)batched_kernel<XT, R>,
+        hipFuncSetAttribute((const void *)batched_kernel<XT, R, kPacked>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64);
         configured = true;
     }
 }
 
-template <typename XT, int R>
+template <typename XT, int R, bool kPacked>
 static int batched_occupancy_t(const BatchedPlan &plan, size_t lds)
 {
-    configure_batched<XT, R>();
+    configure_batched<XT, R, kPacked>();
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<XT, R>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<XT, R, kPacked>,
                                                      plan.waves_per_block * kWave, lds) != hipSuccess)
         return 1;
     return blocks > 0 ? blocks : 1;
 }
 
-template <typename XT, int R>
+template <typename XT, int R, bool kPacked>
 static hipError_t launch_batched_t(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
-                                   uint16_t *sig, const BatchedPlan &plan,
-                                   const StreamEntry *entries, uint32_t *tile_counter,
-                                   uint32_t grid, hipStream_t stream)
+                                   uint16_t *sig, const BatchedPlan &plan, const void *entries,
+                                   uint32_t *tile_counter, uint32_t grid, hipStream_t stream)
 {
     const size_t lds = batched_lds_bytes(b.dims, plan);
-    configure_batched<XT, R>();
-    batched_kernel<XT, R><<<grid, plan.waves_per_block * kWave, lds, stream>>>(
+    configure_batched<XT, R, kPacked>();
+    batched_kernel<XT, R, kPacked><<<grid, plan.waves_per_block * kWave, lds, stream>>>(
         b, rows, k, seed, sig, plan.hashes_per_tile, plan.stream_depth, entries, tile_counter);
     return hipGetLastError();
 }
 
+// Calls F<XT, R, packed>() for the plan's template parameters.
+template <template <typename, int, bool> class F, typename... Args>
+static auto dispatch_batched(const BatchedPlan &plan, Args &&...args)
+    -> decltype(F<uint16_t, 1, true>::run(args...))
+{
+#define WMH_R_CASE(RR)                                                                           \
+    case RR:                                                                                     \
+        if (plan.narrow)                                                                         \
+            return plan.packed ? F<uint16_t, RR, true>::run(args...)                             \
+                               : F<uint16_t, RR, false>::run(args...);                           \
+        return plan.packed ? F<uint32_t, RR, true>::run(args...)                                 \
+                           : F<uint32_t, RR, false>::run(args...);
+    switch (plan.rows_per_block) {
+        WMH_R_CASE(1)
+        WMH_R_CASE(2)
+        WMH_R_CASE(4)
+        WMH_R_CASE(8)
+        WMH_R_CASE(16)
+    default:
+        return F<uint16_t, 1, true>::fail();
+    }
+#undef WMH_R_CASE
+}
+
+template <typename XT, int R, bool kPacked>
+struct LaunchBatched {
+    static hipError_t run(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
+                          uint16_t *sig, const BatchedPlan &plan, const void *entries,
+                          uint32_t *tile_counter, uint32_t grid, hipStream_t stream)
+    {
+        return launch_batched_t<XT, R, kPacked>(b, rows, k, seed, sig, plan, entries,
+                                                tile_counter, grid, stream);
+    }
+    static hipError_t fail() { return hipErrorInvalidValue; }
+};
+
+template <typename XT, int R, bool kPacked>
+struct OccupancyBatched {
+    static int run(const BatchedPlan &plan, size_t lds)
+    {
+        return batched_occupancy_t<XT, R, kPacked>(plan, lds);
+    }
+    static int fail() { return 0; }
+};
+
 hipError_t launch_batched(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
-                          uint16_t *sig, const BatchedPlan &plan, const StreamEntry *entries,
+                          uint16_t *sig, const BatchedPlan &plan, const void *entries,
                           uint32_t *tile_counter, uint32_t grid, hipStream_t stream)
 {
     if (batched_lds_bytes(b.dims, plan) > 160 * 1024 - 64) return hipErrorInvalidValue;
-#define WMH_BATCHED_CASE(RR)                                                                     \
-    case RR:                                                                                     \
-        return plan.narrow ? launch_batched_t<uint16_t, RR>(b, rows, k, seed, sig, plan, entries, \
-                                                            tile_counter, grid, stream)           \
-                           : launch_batched_t<uint32_t, RR>(b, rows, k, seed, sig, plan, entries, \
-                                                            tile_counter, grid, stream);
-    switch (plan.rows_per_block) {
-        WMH_BATCHED_CASE(1)
-        WMH_BATCHED_CASE(2)
-        WMH_BATCHED_CASE(4)
-        WMH_BATCHED_CASE(8)
-        WMH_BATCHED_CASE(16)
-    default:
-        return hipErrorInvalidValue;
-    }
-#undef WMH_BATCHED_CASE
+    if (plan.packed && !plan.narrow) return hipErrorInvalidValue;
+    return dispatch_batched<LaunchBatched>(plan, b, rows, k, seed, sig, plan, entries,
+                                           tile_counter, grid, stream);
 }
 
 int batched_blocks_per_cu(uint32_t dims, const BatchedPlan &plan)
 {
     const size_t lds = batched_lds_bytes(dims, plan);
     if (lds > 160 * 1024 - 64) return 0;
-#define WMH_OCC_CASE(RR)                                                                        \
-    case RR:                                                                                    \
-        return plan.narrow ? batched_occupancy_t<uint16_t, RR>(plan, lds)                       \
-                           : batched_occupancy_t<uint32_t, RR>(plan, lds);
-    switch (plan.rows_per_block) {
-        WMH_OCC_CASE(1)
-        WMH_OCC_CASE(2)
-        WMH_OCC_CASE(4)
-        WMH_OCC_CASE(8)
-        WMH_OCC_CASE(16)
-    default:
-        return 0;
-    }
-#undef WMH_OCC_CASE
+    return dispatch_batched<OccupancyBatched>(plan, plan, lds);
 }
 
 hipError_t launch_estimate(const uint16_t *A, const uint16_t *B, uint64_t n_pairs, uint32_t k,
