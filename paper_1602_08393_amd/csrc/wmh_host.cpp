@@ -180,7 +180,6 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, uint64_t min_green, const wmh_
 {
     BatchedPlan p{};
     p.narrow = ctx->max_bound <= 0xFFFFu;
-    p.packed = p.narrow && ctx->dims <= 65536u;
     p.waves_per_block = o.waves_per_block ? std::min<uint32_t>(o.waves_per_block, 16u) : 8u;
     p.hashes_per_tile = o.hashes_per_tile ? std::min(o.hashes_per_tile, k) : std::min(k, 1024u);
     const size_t elem = p.narrow ? 2 : 4;
@@ -193,6 +192,7 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, uint64_t min_green, const wmh_
     if (R != 1 && R != 2 && R != 4 && R != 8 && R != 16) return false;
     p.rows_per_block = R;
     if (batched_lds_bytes(ctx->dims, p) > 160 * 1024 - 64) return false;
+    p.packed = p.narrow && (uint64_t)ctx->dims * p.scale() <= 65536u;
     // shared stream depth: cover eight mean step counts of the sparsest row
     // (the batched kernel always reads at least one window of the stream: depth >= 64)
     uint32_t depth;
@@ -470,7 +470,7 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
             if (events && (e = hipEventRecord(ctx->ev[0], q)) != hipSuccess) return e;
             if (plan.stream_depth) {
                 e = launch_stream_build(b, seed, k, plan.stream_depth, plan.packed,
-                                        ctx->d_stream, q);
+                                        plan.scale(), ctx->d_stream, q);
                 if (e != hipSuccess) return e;
             }
             if (events && (e = hipEventRecord(ctx->ev[1], q)) != hipSuccess) return e;

@@ -33,8 +33,9 @@ struct Rows {
 };
 
 // One shared-stream entry: the component c and the offset inside it of one step's position.
-// Wide entries are (c, offset) as two uint32; packed entries are (c << 16) | offset, used when
-// D <= 65536 and every bound is below 65536.
+// Wide entries are (c, offset) as two uint32; packed entries are (offset << 16) | (c * scale)
+// with scale = R * sizeof(dense value), the LDS byte offset of component c's group of R dense
+// values; used when every bound is below 65536 and D * scale <= 65536.
 struct StreamEntry {
     uint32_t comp;
     uint32_t offset;
@@ -47,6 +48,7 @@ struct BatchedPlan {
     uint32_t waves_per_block;
     bool narrow;               // dense rows stored as uint16 (every bound < 65536)
     bool packed;               // 4-byte stream entries
+    uint32_t scale() const { return rows_per_block * (narrow ? 2u : 4u); }
 };
 
 inline size_t stream_entry_bytes(bool packed) { return packed ? 4 : 8; }
@@ -63,7 +65,7 @@ hipError_t launch_draws(const Bounds &b, uint64_t seed, uint32_t j0, uint32_t n_
                         hipStream_t stream);
 
 hipError_t launch_stream_build(const Bounds &b, uint64_t seed, uint32_t k, uint32_t depth,
-                               bool packed, void *entries, hipStream_t stream);
+                               bool packed, uint32_t scale, void *entries, hipStream_t stream);
 
 // Returns hipErrorInvalidValue when the plan does not fit (LDS).
 hipError_t launch_batched(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,

@@ -208,12 +208,15 @@ __global__ __launch_bounds__(256) void plain_kernel(Bounds b, Rows rows, uint64_
 }
 
 // ---------------------------------------------------------------------------------------------
-// Shared position stream: entries[j * depth + t - 1] = (component, offset) of step t of hash
-// j, for t <= depth.  One thread per Philox block (two steps).
+// Shared position stream: entry j * depth + t - 1 holds step t of hash j, for t <= depth:
+// wide entries (component c, offset); packed entries (offset << 16) | (c * scale), where
+// c * scale is the LDS byte offset of component c's group of dense-row values.  One thread per
+// Philox block (two steps).
 // ---------------------------------------------------------------------------------------------
 template <bool kPacked>
 __global__ __launch_bounds__(256) void stream_kernel(Bounds b, uint64_t seed, uint32_t k,
-                                                     uint32_t depth, void *__restrict__ entries)
+                                                     uint32_t depth, uint32_t scale,
+                                                     void *__restrict__ entries)
 {
     const uint64_t pairs = depth >> 1;
     const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -227,8 +230,8 @@ __global__ __launch_bounds__(256) void stream_kernel(Bounds b, uint64_t seed, ui
     const uint64_t at = (uint64_t)j * depth + 2ull * pair;
     if (kPacked) {
         uint32_t *e = reinterpret_cast<uint32_t *>(entries) + at;
-        *reinterpret_cast<uint2 *>(e) = make_uint2((c0 << 16) | (uint32_t)off0,
-                                                   (c1 << 16) | (uint32_t)off1);
+        *reinterpret_cast<uint2 *>(e) = make_uint2(((uint32_t)off0 << 16) | (c0 * scale),
+                                                   ((uint32_t)off1 << 16) | (c1 * scale));
     } else {
         StreamEntry *e = reinterpret_cast<StreamEntry *>(entries) + at;
         e[0] = StreamEntry{c0, (uint32_t)off0};
@@ -302,13 +305,14 @@ struct EntryRun {
             }
         }
     }
-    __device__ __forceinline__ void get(int k, uint32_t *c, uint32_t *off) const
+    // LDS byte offset of the step's component group (c * scale) and the offset in the piece
+    __device__ __forceinline__ void get(int k, uint32_t scale, uint32_t *lds, uint32_t *off) const
     {
         if (kPacked) {
-            *c = w[k] >> 16;
-            *off = w[k] & 0xFFFFu;
+            *lds = w[k] & 0xFFFFu;
+            *off = w[k] >> 16;
         } else {
-            *c = w[2 * k];
+            *lds = w[2 * k] * scale;
             *off = w[2 * k + 1];
         }
     }
@@ -323,8 +327,13 @@ __device__ __forceinline__ uint64_t row_lanes(uint32_t r)
     else return ((1ull << L) - 1ull) << (r * L);
 }
 
+// Up to four rows per block the walk fits eight wavefronts per SIMD (at most 64 VGPRs and a
+// few scalar registers spilled to vector lanes); wider blocks keep their registers.
+template <int R>
+constexpr int walk_waves_per_eu() { return R <= 4 ? 8 : 1; }
+
 template <typename XT, int R, bool kPacked>
-__global__ __launch_bounds__(1024) void batched_kernel(Bounds b, Rows rows, uint32_t k,
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves_per_eu<R>()))) void batched_kernel(Bounds b, Rows rows, uint32_t k,
                                                        uint64_t seed, uint16_t *__restrict__ sig,
                                                        uint32_t hashes_per_tile, uint32_t depth,
                                                        const void *__restrict__ entries,
@@ -344,6 +353,8 @@ __global__ __launch_bounds__(1024) void batched_kernel(Bounds b, Rows rows, uint
     uint16_t *hbuf = reinterpret_cast<uint16_t *>(smem + (((size_t)D * R * sizeof(XT) + 15) & ~(size_t)15));
     const uint32_t my_row = lane() / L;
     const uint32_t my_grp = lane() % L;
+    constexpr uint32_t kScale = R * sizeof(XT);  // LDS bytes per component group
+    const uint32_t row_byte = my_row * sizeof(XT);
 
     const uint64_t n_blocks = (rows.n_rows + R - 1) / R;
     const uint32_t n_hash_tiles = (k + hashes_per_tile - 1) / hashes_per_tile;
@@ -387,10 +398,12 @@ __global__ __launch_bounds__(1024) void batched_kernel(Bounds b, Rows rows, uint
         // Wave-uniform values are read into scalar registers so every branch on them is a
         // scalar branch: no lane-divergent region sits on the unit loop's path.
         const uint32_t live = __builtin_amdgcn_readfirstlane(nonempty);
-        uint64_t live_lanes = 0;  // lanes of the rows that have a green region
+        const bool my_row_live = ((live >> my_row) & 1u) != 0;
+        // bit r * L set for every live row r: the walk ends when each of them has a green lane
+        uint64_t need = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            if ((live >> r) & 1u) live_lanes |= row_lanes<R>(r);
+            if ((live >> r) & 1u) need |= 1ull << (r * L);
         const uint32_t j0 = ht * hashes_per_tile;
         const uint32_t j1 = min(k, j0 + hashes_per_tile);
 
@@ -403,8 +416,10 @@ __global__ __launch_bounds__(1024) void batched_kernel(Bounds b, Rows rows, uint
             const uint32_t j = j0 + ((uint32_t)__builtin_amdgcn_readfirstlane(claimed) >> 6);
             if (j >= j1) break;
 
-            uint64_t pend = live_lanes;  // lanes of rows still walking
-            uint32_t hv = 0;             // lane r < R holds the hash value of row r
+            // Each lane keeps the first green step among its own steps (0: none yet); a row's
+            // hash is the smallest of its lanes' values, since together they cover every step.
+            uint32_t lane_h = 0;
+            bool walking = live != 0;
             // The stream holds depth >= 64 steps per hash id.  Entries are prefetched three
             // windows ahead into a ring of three register sets, each reloaded in place right
             // after its window is tested; the loads use clamped, in-bounds indices (windows
@@ -419,17 +434,22 @@ __global__ __launch_bounds__(1024) void batched_kernel(Bounds b, Rows rows, uint
             };
             // tests window [base + 1, base + 64]; false once the walk is over
             auto window = [&](const EntryRun<K, kPacked> &run, uint32_t base) -> bool {
-                if (pend == 0 || base >= kCap) return false;
+                if (!walking || base >= kCap) return false;
                 uint32_t first = K;  // first green step of this lane's K, K if none
                 if (base < depth) {
+                    // all K reads in flight before the first compare
+                    uint32_t xv[K], off[K];
 #pragma unroll
-                    for (int q = K - 1; q >= 0; --q) {
-                        uint32_t c, off;
-                        run.get(q, &c, &off);
-                        first = off < (uint32_t)x[(size_t)c * R + my_row] ? (uint32_t)q : first;
+                    for (int q = 0; q < (int)K; ++q) {
+                        uint32_t lds;
+                        run.get(q, kScale, &lds, &off[q]);
+                        xv[q] = *reinterpret_cast<const XT *>(smem + lds + row_byte);
                     }
-                } else {
 #pragma unroll
+                    for (int q = K - 1; q >= 0; --q) first = off[q] < xv[q] ? (uint32_t)q : first;
+                } else {
+                    // beyond the stream (rare): draw in-lane, one step at a time
+#pragma unroll 1
                     for (int q = K - 1; q >= 0; --q) {
                         const uint32_t t = base + my_grp * K + q + 1u;
                         const uint64_t p = position(seed, j, t, b.total, b.threshold);
@@ -441,19 +461,14 @@ __global__ __launch_bounds__(1024) void batched_kernel(Bounds b, Rows rows, uint
                 // in the last window the lane holding step 65536 may not count it
                 if (base + kWave > kCap)
                     first = (my_grp == L - 1 && first == K - 1) ? K : first;
-                uint64_t hit = __builtin_amdgcn_ballot_w64(first < K) & pend;
-                // the lowest hit lane is the first green lane of its row (lower lanes of that
-                // row had no green step); handle each row once, lowest first
-                while (hit != 0) {
-                    const uint32_t l = (uint32_t)__builtin_ctzll(hit);
-                    const uint32_t r = l / L;
-                    const uint32_t q = (uint32_t)__builtin_amdgcn_readlane(first, l);
-                    const uint32_t h = base + (l % L) * K + q + 1u;
-                    hv = lane() == r ? h : hv;
-                    const uint64_t done = row_lanes<R>(r);
-                    hit &= ~done;
-                    pend &= ~done;
-                }
+                const uint32_t step = base + my_grp * K + first + 1u;
+                lane_h = (lane_h == 0 && first < K) ? step : lane_h;
+                // done when every live row has a lane with a green step: fold each row's L
+                // lanes of the ballot onto its lowest bit (scalar work)
+                uint64_t seen = __builtin_amdgcn_ballot_w64(lane_h != 0);
+#pragma unroll
+                for (uint32_t d = 1; d < L; d <<= 1) seen |= seen >> d;
+                walking = (seen & need) != need;
                 return true;
             };
             EntryRun<K, kPacked> e0 = fetch(0), e1 = fetch(kWave), e2 = fetch(2 * kWave);
@@ -465,12 +480,16 @@ __global__ __launch_bounds__(1024) void batched_kernel(Bounds b, Rows rows, uint
                 if (!window(e2, base + 2 * kWave)) break;
                 e2 = fetch(base + 5 * kWave);
             }
-            // rows still walking after the last window saturate at the cap
-            hv = (lane() < (uint32_t)R && ((pend >> (lane() * L)) & 1ull)) ? kCap : hv;
-            // every lane stores; lanes >= R write to their own slot past the tile's values
-            const uint32_t slot = lane() < (uint32_t)R ? lane() * hashes_per_tile + (j - j0)
-                                                      : R * hashes_per_tile + lane();
-            hbuf[slot] = (uint16_t)hv;
+            // smallest nonzero lane value of each row (0 counts as "none": h - 1 wraps)
+            uint32_t best = lane_h - 1u;
+#pragma unroll
+            for (uint32_t d = 1; d < L; d <<= 1) best = min(best, (uint32_t)__shfl_xor((int)best, (int)d));
+            // rows without a green step up to the cap saturate; empty rows hash to 0
+            const uint32_t h = !my_row_live ? 0u : (best == ~0u ? kCap : best + 1u);
+            // every lane stores; only each row's first lane writes a tile value
+            const uint32_t slot = my_grp == 0 ? my_row * hashes_per_tile + (j - j0)
+                                              : R * hashes_per_tile + lane();
+            hbuf[slot] = (uint16_t)h;
         }
         __syncthreads();
         // write the tile's signatures row by row (coalesced along j)
@@ -561,13 +580,13 @@ hipError_t launch_draws(const Bounds &b, uint64_t seed, uint32_t j0, uint32_t n_
 }
 
 hipError_t launch_stream_build(const Bounds &b, uint64_t seed, uint32_t k, uint32_t depth,
-                               bool packed, void *entries, hipStream_t stream)
+                               bool packed, uint32_t scale, void *entries, hipStream_t stream)
 {
     if (depth == 0 || k == 0) return hipSuccess;
     const uint64_t threads = (uint64_t)k * (depth / 2);
     const uint32_t grid = (uint32_t)((threads + 255) / 256);
-    if (packed) stream_kernel<true><<<grid, 256, 0, stream>>>(b, seed, k, depth, entries);
-    else stream_kernel<false><<<grid, 256, 0, stream>>>(b, seed, k, depth, entries);
+    if (packed) stream_kernel<true><<<grid, 256, 0, stream>>>(b, seed, k, depth, scale, entries);
+    else stream_kernel<false><<<grid, 256, 0, stream>>>(b, seed, k, depth, scale, entries);
     return hipGetLastError();
 }
 
