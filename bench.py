@@ -46,7 +46,68 @@ def parse():
     ap.add_argument("--only", choices=["batched", "plain", "both"], default="both")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run device-to-device copies of BYTES (scales HBM counters)")
+    ap.add_argument("--serve", action="store_true",
+                    help="only run the serving workload (corpus of config 5, k=256)")
+    ap.add_argument("--serve-requests", type=int, default=64,
+                    help="open-loop requests per load level")
+    ap.add_argument("--serve-corpus-rows", type=int, default=100_000)
+    ap.add_argument("--serve-max-rows", type=int, default=4096)
+    ap.add_argument("--serve-slots", type=int, default=4)
     return ap.parse_args()
+
+
+def serve_bench(args) -> dict:
+    """Serving loop on the D = 2^20 corpus: saturated throughput from a closed burst, then
+    open-loop Poisson arrivals at 0.5x and 0.8x of it; p50/p99 latency from scheduled arrival
+    to completion."""
+    import torch
+    from paper_1602_08393_amd import serve, synth, wmh
+    torch.cuda.set_device(0)
+    t = time.perf_counter()
+    corpus = synth.config5_corpus(n_rows=args.serve_corpus_rows)
+    log(f"serve: corpus N={corpus.n_rows} D={corpus.D} nnz={corpus.nnz} "
+        f"({time.perf_counter() - t:.1f}s)")
+    k = corpus.k
+    ctx = wmh.Context(0)
+    ctx.set_bounds(corpus.m)
+    out = {"workload": f"requests of 1..{args.serve_max_rows} rows (log-uniform) drawn from a "
+                       f"{corpus.n_rows}-row corpus, D=2^20, tf weights Q16.16, k={k}",
+           "slots": args.serve_slots}
+    with serve.Server(ctx, k, seed=0, slots=args.serve_slots) as srv:
+        # saturated throughput: a closed burst submitted at once
+        burst = max(8, args.serve_requests // 4)
+        _, sizes, rows = synth.serving_requests(burst, corpus.n_rows, qps=1.0, seed=3005,
+                                                max_rows=args.serve_max_rows)
+        reqs = serve.requests_from_corpus(corpus, rows, srv)
+        t0 = time.perf_counter()
+        for r in reqs:
+            srv.submit(r)
+        srv.drain()
+        for r in reqs:
+            srv.wait(r.ticket)
+        burst_s = time.perf_counter() - t0
+        sat_qps = burst / burst_s
+        out["saturated_qps"] = sat_qps
+        out["saturated_hashes_per_s"] = float(sum(sizes)) * k / burst_s
+        log(f"serve: burst of {burst} requests in {burst_s:.2f}s -> {sat_qps:.2f} req/s")
+    levels = []
+    for frac in (0.5, 0.8):
+        qps = frac * sat_qps
+        arrivals, sizes, rows = synth.serving_requests(args.serve_requests, corpus.n_rows,
+                                                       qps=qps, seed=int(4005 + 100 * frac),
+                                                       max_rows=args.serve_max_rows)
+        with serve.Server(ctx, k, seed=0, slots=args.serve_slots) as srv:
+            reqs = serve.requests_from_corpus(corpus, rows, srv)
+            st = serve.run_open_loop(srv, reqs, arrivals)
+        levels.append({"load": frac, "qps": qps, "requests": st["completed"],
+                       "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "max_ms": st["max_ms"],
+                       "mean_ms": st["mean_ms"], "hashes_per_s": st["hashes_per_s"],
+                       "max_queued": st["max_queued"], "peak_bytes": st["peak_bytes"]})
+        log(f"serve: load {frac}: p50 {st['p50_ms']:.1f} ms p99 {st['p99_ms']:.1f} ms "
+            f"{st['hashes_per_s']:.3g} hashes/s")
+    out["levels"] = levels
+    ctx.close()
+    return out
 
 
 def copy_calibration(nbytes: int):
@@ -108,6 +169,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.serve:
+        print(json.dumps({"serving": serve_bench(args)}), flush=True)
         return
     import torch
     from paper_1602_08393_amd import synth, wmh

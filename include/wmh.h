@@ -90,7 +90,8 @@ void wmh_opts_init(wmh_opts *opts);
 /* Creates a context on HIP device `device` (which becomes current for the calling thread). */
 wmh_status wmh_create(int device, wmh_ctx **out);
 
-/* Releases the context and every device buffer it owns.  NULL is ignored. */
+/* Releases the context and every device buffer it owns.  NULL is ignored.  Destroy the
+ * context's serving loops first. */
 void wmh_destroy(wmh_ctx *ctx);
 
 /*
@@ -100,8 +101,8 @@ void wmh_destroy(wmh_ctx *ctx);
  * Builds on the device the prefix sums P[0..D] (uint64), the total M = P[D] (must be >= 1),
  * the uniform bucket table T over [0, M) used for the O(1) position-to-component lookup
  * (Algorithm 5), and the bounded-draw threshold 2^64 mod M.  Replaces earlier bounds.
- * Synchronous.  Errors: WMH_E_ARG (null, D out of range), WMH_E_OVERFLOW (M = 0),
- * WMH_E_NOMEM, WMH_E_DEVICE.
+ * Synchronous.  Errors: WMH_E_ARG (null, D out of range, a serving loop of this context is
+ * alive), WMH_E_OVERFLOW (M = 0), WMH_E_NOMEM, WMH_E_DEVICE.
  */
 wmh_status wmh_set_bounds(wmh_ctx *ctx, const uint32_t *m, uint32_t D);
 
@@ -184,6 +185,77 @@ wmh_status wmh_bounds_tables(const uint32_t *m, uint32_t D, uint64_t *prefix, ui
  * Errors: WMH_E_ARG (no profiled call yet), WMH_E_DEVICE.
  */
 wmh_status wmh_last_kernel_ms(wmh_ctx *ctx, float *walk_ms, float *stream_ms);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Serving loop: continuous batching of hash requests on one device.                           */
+/* ------------------------------------------------------------------------------------------ */
+
+typedef struct wmh_server wmh_server;
+
+typedef struct {
+    uint32_t k;            /* hashes per row, 1 <= k <= 2^24 */
+    uint32_t slots;        /* requests on the device at once, each on its own HIP stream;
+                              1..64, 0 = 4 */
+    uint64_t seed;         /* key of the random sequence */
+    uint64_t mem_budget;   /* device bytes for the admitted requests' rows and signatures
+                              ((N+1)*8 + nnz*8 + N*k*2 each); 0 = 4 GiB */
+    int32_t mode;          /* wmh_mode of every request's walk; 0 = auto */
+    uint32_t stream_depth; /* steps of the shared position stream built once at creation;
+                              0 = 8192 (steps beyond are drawn in-lane) */
+    uint32_t reserved[4];
+} wmh_server_config;
+
+typedef struct {
+    uint64_t submitted, completed, failed;
+    uint64_t queued;       /* requests waiting for admission at the time of the call */
+    uint64_t max_queued;   /* largest such backlog seen */
+    uint64_t peak_bytes;   /* largest device bytes admitted at once */
+    uint64_t hashes;       /* rows * k over completed requests */
+    double p50_ms, p99_ms, p999_ms, max_ms, mean_ms; /* arrival -> completion */
+    double busy_s;         /* first admission -> last completion */
+    double hashes_per_s;   /* hashes / busy_s */
+} wmh_serving_stats;
+
+/*
+ * wmh_server_create -- starts a serving loop on ctx's device using ctx's bounds (which must
+ * not change while the loop exists).  A worker thread admits queued requests in arrival order
+ * whenever a slot is free and the admitted bytes stay within mem_budget, runs each request's
+ * walk on its slot's stream (so requests overlap on the device), and completes them as their
+ * results arrive.  Bounds, bucket table and the shared position stream stay device-resident.
+ * Errors: WMH_E_ARG, WMH_E_NO_BOUNDS, WMH_E_NOMEM, WMH_E_DEVICE.
+ */
+wmh_status wmh_server_create(wmh_ctx *ctx, const wmh_server_config *cfg, wmh_server **out);
+
+/*
+ * wmh_server_submit -- queues one request of N CSR rows (host buffers: row_ptr N+1, col/val
+ * nnz) whose signatures go to sig (host, N*k uint16).  The caller keeps all four buffers valid
+ * and unchanged until the request completes.  The rows are checked on the host first (same
+ * rules and errors as wmh_hash); a request larger than mem_budget is WMH_E_NOMEM.
+ * arrival_ns is the request's arrival on wmh_server_now_ns()'s clock (0 = now); latency is
+ * measured from it, so an open-loop driver that submits late does not hide queueing delay.
+ * Each request's signatures are identical to a wmh_hash call on the same rows.
+ */
+wmh_status wmh_server_submit(wmh_server *srv, const uint64_t *row_ptr, const uint32_t *col,
+                             const uint32_t *val, uint64_t n_rows, uint64_t nnz, uint16_t *sig,
+                             uint64_t arrival_ns, uint64_t *ticket);
+
+/* Non-blocking completion test; *latency_ms (may be NULL) is set once done. */
+wmh_status wmh_server_poll(wmh_server *srv, uint64_t ticket, int *done, double *latency_ms);
+
+/* Blocks until the request completes. */
+wmh_status wmh_server_wait(wmh_server *srv, uint64_t ticket, double *latency_ms);
+
+/* Blocks until every submitted request has completed. */
+wmh_status wmh_server_drain(wmh_server *srv);
+
+/* Counters and latency percentiles over the completed requests. */
+wmh_status wmh_server_stats(wmh_server *srv, wmh_serving_stats *out);
+
+/* The steady clock used for arrival times, in nanoseconds. */
+uint64_t wmh_server_now_ns(void);
+
+/* Drains, stops the worker and releases every buffer.  NULL is ignored. */
+void wmh_server_destroy(wmh_server *srv);
 
 /* Bounds summary after wmh_set_bounds: D, M, bucket shift and bucket count (any may be NULL). */
 wmh_status wmh_bounds_info(const wmh_ctx *ctx, uint32_t *D, uint64_t *M, uint32_t *shift,

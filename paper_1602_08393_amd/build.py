@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwmh.so")
-SOURCES = ["wmh_host.cpp", "wmh_kernels.hip", "wmh_collide.hip"]
+SOURCES = ["wmh_host.cpp", "wmh_server.cpp", "wmh_kernels.hip", "wmh_collide.hip"]
 ARCH = "gfx950"
 
 
@@ -43,7 +43,7 @@ def build(verbose: bool = False) -> str:
         subprocess.run(cmd, check=True)
         objects.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objects, "-o", tmp]
+    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", *objects, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

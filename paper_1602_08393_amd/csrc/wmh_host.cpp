@@ -16,68 +16,12 @@
 #include <vector>
 
 #include "../../include/wmh.h"
+#include "wmh_context.h"
 #include "wmh_internal.h"
 
 using namespace wmh;
 
-namespace {
-
-constexpr uint32_t kMaxDims = 1u << 26;
-constexpr uint32_t kMaxK = 1u << 24;
-constexpr uint64_t kStreamBudgetBytes = 1ull << 30;  // shared position stream, at most 1 GiB
-
-struct GraphKey {
-    const void *row_ptr = nullptr, *col = nullptr, *val = nullptr;
-    void *sig = nullptr;
-    uint64_t n_rows = 0, nnz = 0, seed = 0;
-    uint32_t k = 0, R = 0, J = 0, depth = 0, waves = 0, grid = 0;
-    bool narrow = false, packed = false;
-    uint64_t bounds_epoch = 0;
-    bool operator==(const GraphKey &o) const
-    {
-        return row_ptr == o.row_ptr && col == o.col && val == o.val && sig == o.sig &&
-               n_rows == o.n_rows && nnz == o.nnz && seed == o.seed && k == o.k && R == o.R &&
-               J == o.J && depth == o.depth && waves == o.waves && grid == o.grid &&
-               narrow == o.narrow && packed == o.packed && bounds_epoch == o.bounds_epoch;
-    }
-};
-
-}  // namespace
-
-struct wmh_ctx {
-    int device = 0;
-    hipStream_t own_stream = nullptr;
-    hipStream_t capture_stream = nullptr;
-    int cu_count = 0;
-    // bounds
-    bool has_bounds = false;
-    uint64_t bounds_epoch = 0;
-    uint32_t dims = 0;
-    uint64_t total = 0;
-    uint64_t threshold = 0;
-    uint32_t shift = 0;
-    uint64_t n_buckets = 0;
-    uint32_t max_bound = 0;
-    uint64_t *d_prefix = nullptr;
-    uint32_t *d_bucket = nullptr;
-    uint32_t *d_bound = nullptr;
-    // per-call scratch
-    CheckWords *d_check = nullptr;
-    CheckWords *h_check = nullptr;  // pinned
-    uint32_t *d_tile_counter = nullptr;
-    void *d_stream = nullptr;
-    size_t stream_bytes = 0;
-    // graph of the batched launch
-    hipGraphExec_t graph_exec = nullptr;
-    GraphKey graph_key;
-    // profiling events: [0] before the stream build, [1] before the walk, [2] after the walk
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-    bool profiled = false;
-    bool profiled_stream = false;
-    std::string last_error;
-};
-
-namespace {
+namespace wmh {
 
 wmh_status fail(wmh_ctx *ctx, wmh_status st, const char *fmt, ...)
 {
@@ -98,30 +42,6 @@ wmh_status device_fail(wmh_ctx *ctx, hipError_t e, const char *what)
                 hipGetErrorString(e));
 }
 
-#define WMH_HIP(ctx, call)                                      \
-    do {                                                        \
-        hipError_t e_ = (call);                                 \
-        if (e_ != hipSuccess) return device_fail(ctx, e_, #call); \
-    } while (0)
-
-void release_bounds(wmh_ctx *ctx)
-{
-    if (ctx->d_prefix) hipFree(ctx->d_prefix);
-    if (ctx->d_bucket) hipFree(ctx->d_bucket);
-    if (ctx->d_bound) hipFree(ctx->d_bound);
-    ctx->d_prefix = nullptr;
-    ctx->d_bucket = nullptr;
-    ctx->d_bound = nullptr;
-    ctx->has_bounds = false;
-}
-
-void drop_graph(wmh_ctx *ctx)
-{
-    if (ctx->graph_exec) hipGraphExecDestroy(ctx->graph_exec);
-    ctx->graph_exec = nullptr;
-    ctx->graph_key = GraphKey{};
-}
-
 Bounds bounds_view(const wmh_ctx *ctx)
 {
     Bounds b;
@@ -133,45 +53,6 @@ Bounds bounds_view(const wmh_ctx *ctx)
     b.shift = ctx->shift;
     b.dims = ctx->dims;
     return b;
-}
-
-hipStream_t pick_stream(wmh_ctx *ctx, void *stream)
-{
-    return stream ? reinterpret_cast<hipStream_t>(stream) : ctx->own_stream;
-}
-
-const char *check_name(uint32_t code)
-{
-    switch (code) {
-    case kCheckRowPtr: return "row_ptr decreasing or beyond nnz";
-    case kCheckColumn: return "column index >= D";
-    case kCheckUnsorted: return "columns not strictly increasing";
-    case kCheckBound: return "value above its bound m_i";
-    default: return "?";
-    }
-}
-
-wmh_status check_status(uint32_t code)
-{
-    switch (code) {
-    case kCheckRowPtr: return WMH_E_ROW_PTR;
-    case kCheckColumn: return WMH_E_COL_RANGE;
-    case kCheckUnsorted: return WMH_E_UNSORTED;
-    case kCheckBound: return WMH_E_BOUND;
-    default: return WMH_E_DEVICE;
-    }
-}
-
-wmh_status ensure_stream_capacity(wmh_ctx *ctx, size_t bytes)
-{
-    if (bytes <= ctx->stream_bytes) return WMH_OK;
-    if (ctx->d_stream) hipFree(ctx->d_stream);
-    ctx->d_stream = nullptr;
-    ctx->stream_bytes = 0;
-    drop_graph(ctx);
-    WMH_HIP(ctx, hipMalloc(&ctx->d_stream, bytes));
-    ctx->stream_bytes = bytes;
-    return WMH_OK;
 }
 
 // Tile plan of the batched walk.  Returns false when no dense plan fits in LDS.
@@ -213,6 +94,103 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, uint64_t min_green, const wmh_
     p.stream_depth = depth;
     *plan = p;
     return true;
+}
+
+wmh_status check_rows_host(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
+                           const uint32_t *val, uint64_t n_rows, uint64_t nnz,
+                           uint64_t *min_green_out)
+{
+    uint64_t min_green = ~0ull;
+    for (uint64_t r = 0; r < n_rows; ++r) {
+        const uint64_t lo = row_ptr[r], hi = row_ptr[r + 1];
+        if (lo > hi || hi > nnz)
+            return fail(ctx, WMH_E_ROW_PTR, "row %llu: row_ptr decreasing or beyond nnz",
+                        (unsigned long long)r);
+        uint64_t green = 0;
+        for (uint64_t e = lo; e < hi; ++e) {
+            const uint32_t c = col[e];
+            if (c >= ctx->dims)
+                return fail(ctx, WMH_E_COL_RANGE, "row %llu: column index >= D",
+                            (unsigned long long)r);
+            if (e > lo && col[e - 1] >= c)
+                return fail(ctx, WMH_E_UNSORTED, "row %llu: columns not strictly increasing",
+                            (unsigned long long)r);
+            if (val[e] > ctx->h_bound[c])
+                return fail(ctx, WMH_E_BOUND, "row %llu: value above its bound m_i",
+                            (unsigned long long)r);
+            green += val[e];
+        }
+        if (green) min_green = std::min(min_green, green);
+    }
+    if (min_green_out) *min_green_out = min_green;
+    return WMH_OK;
+}
+
+}  // namespace wmh
+
+namespace {
+
+#define WMH_HIP(ctx, call)                                      \
+    do {                                                        \
+        hipError_t e_ = (call);                                 \
+        if (e_ != hipSuccess) return device_fail(ctx, e_, #call); \
+    } while (0)
+
+void release_bounds(wmh_ctx *ctx)
+{
+    if (ctx->d_prefix) hipFree(ctx->d_prefix);
+    if (ctx->d_bucket) hipFree(ctx->d_bucket);
+    if (ctx->d_bound) hipFree(ctx->d_bound);
+    ctx->d_prefix = nullptr;
+    ctx->d_bucket = nullptr;
+    ctx->d_bound = nullptr;
+    ctx->has_bounds = false;
+}
+
+void drop_graph(wmh_ctx *ctx)
+{
+    if (ctx->graph_exec) hipGraphExecDestroy(ctx->graph_exec);
+    ctx->graph_exec = nullptr;
+    ctx->graph_key = GraphKey{};
+}
+
+hipStream_t pick_stream(wmh_ctx *ctx, void *stream)
+{
+    return stream ? reinterpret_cast<hipStream_t>(stream) : ctx->own_stream;
+}
+
+const char *check_name(uint32_t code)
+{
+    switch (code) {
+    case kCheckRowPtr: return "row_ptr decreasing or beyond nnz";
+    case kCheckColumn: return "column index >= D";
+    case kCheckUnsorted: return "columns not strictly increasing";
+    case kCheckBound: return "value above its bound m_i";
+    default: return "?";
+    }
+}
+
+wmh_status check_status(uint32_t code)
+{
+    switch (code) {
+    case kCheckRowPtr: return WMH_E_ROW_PTR;
+    case kCheckColumn: return WMH_E_COL_RANGE;
+    case kCheckUnsorted: return WMH_E_UNSORTED;
+    case kCheckBound: return WMH_E_BOUND;
+    default: return WMH_E_DEVICE;
+    }
+}
+
+wmh_status ensure_stream_capacity(wmh_ctx *ctx, size_t bytes)
+{
+    if (bytes <= ctx->stream_bytes) return WMH_OK;
+    if (ctx->d_stream) hipFree(ctx->d_stream);
+    ctx->d_stream = nullptr;
+    ctx->stream_bytes = 0;
+    drop_graph(ctx);
+    WMH_HIP(ctx, hipMalloc(&ctx->d_stream, bytes));
+    ctx->stream_bytes = bytes;
+    return WMH_OK;
 }
 
 }  // namespace
@@ -334,6 +312,8 @@ wmh_status wmh_set_bounds(wmh_ctx *ctx, const uint32_t *m, uint32_t D)
 {
     if (!ctx) return WMH_E_ARG;
     if (!m || D == 0 || D > kMaxDims) return fail(ctx, WMH_E_ARG, "D must be in [1, 2^26]");
+    if (ctx->servers > 0)
+        return fail(ctx, WMH_E_ARG, "a serving loop is using this context's bounds");
     WMH_HIP(ctx, hipSetDevice(ctx->device));
     uint32_t shift = 0;
     uint64_t n_buckets = 0, threshold = 0;
@@ -363,6 +343,7 @@ wmh_status wmh_set_bounds(wmh_ctx *ctx, const uint32_t *m, uint32_t D)
     ctx->shift = shift;
     ctx->n_buckets = n_buckets;
     ctx->max_bound = max_bound;
+    ctx->h_bound.assign(m, m + D);
     ctx->has_bounds = true;
     ctx->bounds_epoch++;
     ctx->last_error.clear();

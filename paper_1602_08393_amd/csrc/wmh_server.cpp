@@ -1,0 +1,427 @@
+// Serving loop of libwmh: continuous batching of hash requests on one device.
+//
+// Requests are queued by any host thread and admitted, in arrival order, by one worker thread
+// whenever a slot (a HIP stream with its own buffers) is free and the admitted device bytes
+// stay within the budget.  Each admitted request is copied in, walked and copied out on its
+// slot's stream, so requests overlap on the device; the worker completes a request when its
+// slot's event has fired.  The bounds tables and the shared position stream are built once and
+// stay device-resident.  Every request computes the same function as wmh_hash on its rows.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/wmh.h"
+#include "wmh_context.h"
+#include "wmh_internal.h"
+
+using namespace wmh;
+
+namespace {
+
+uint64_t steady_ns()
+{
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+struct Request {
+    uint64_t id = 0;
+    const uint64_t *row_ptr = nullptr;
+    const uint32_t *col = nullptr;
+    const uint32_t *val = nullptr;
+    uint64_t n_rows = 0, nnz = 0;
+    uint16_t *sig = nullptr;
+    uint64_t arrival_ns = 0, admit_ns = 0, done_ns = 0;
+    uint64_t bytes = 0;
+    bool done = false;
+    wmh_status status = WMH_OK;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t finished = nullptr;
+    uint64_t *d_row_ptr = nullptr;
+    uint32_t *d_col = nullptr, *d_val = nullptr;
+    uint16_t *d_sig = nullptr;
+    uint16_t *h_sig = nullptr;  // pinned staging of the signatures
+    uint64_t cap_rows = 0, cap_col = 0, cap_val = 0, cap_sig = 0, cap_h_sig = 0;
+    uint32_t *d_tile_counter = nullptr;
+    Request *req = nullptr;
+};
+
+template <typename T>
+hipError_t grow_device(T **p, uint64_t *cap, uint64_t want)
+{
+    if (want <= *cap && *p) return hipSuccess;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    const uint64_t n = std::max<uint64_t>(want, 1);
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), n * sizeof(T));
+    if (e == hipSuccess) *cap = n;
+    return e;
+}
+
+}  // namespace
+
+struct wmh_server {
+    wmh_ctx *ctx = nullptr;
+    wmh_server_config cfg{};
+    std::vector<Slot> slots;
+    // walk plan shared by every request
+    bool batched = false;
+    BatchedPlan plan{};
+    uint32_t grid = 0;
+    void *d_stream = nullptr;
+    // queue and bookkeeping (guarded by mu)
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request *> queue;
+    std::unordered_map<uint64_t, Request *> requests;
+    uint64_t next_id = 1;
+    uint64_t inflight_bytes = 0;
+    uint32_t inflight = 0;
+    bool stopping = false;
+    std::thread worker;
+    // statistics
+    uint64_t submitted = 0, completed = 0, failed = 0, max_queued = 0, peak_bytes = 0;
+    uint64_t hashes = 0;
+    std::vector<double> latencies_ms;
+    uint64_t first_admit_ns = 0, last_done_ns = 0;
+
+    wmh_status launch(Slot &slot, Request &r);
+    void complete(Slot &slot, wmh_status st);
+    void run();
+};
+
+wmh_status wmh_server::launch(Slot &slot, Request &r)
+{
+    const uint32_t k = cfg.k;
+    const uint64_t sig_elems = r.n_rows * (uint64_t)k;
+    hipError_t e = grow_device(&slot.d_row_ptr, &slot.cap_rows, r.n_rows + 1);
+    if (e == hipSuccess) e = grow_device(&slot.d_col, &slot.cap_col, r.nnz);
+    if (e == hipSuccess) e = grow_device(&slot.d_val, &slot.cap_val, r.nnz);
+    if (e == hipSuccess) e = grow_device(&slot.d_sig, &slot.cap_sig, sig_elems);
+    if (e == hipSuccess && (slot.cap_h_sig < sig_elems || !slot.h_sig)) {
+        if (slot.h_sig) (void)hipHostFree(slot.h_sig);
+        slot.h_sig = nullptr;
+        slot.cap_h_sig = 0;
+        e = hipHostMalloc(reinterpret_cast<void **>(&slot.h_sig),
+                          std::max<uint64_t>(sig_elems, 1) * sizeof(uint16_t), hipHostMallocDefault);
+        if (e == hipSuccess) slot.cap_h_sig = std::max<uint64_t>(sig_elems, 1);
+    }
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? WMH_E_NOMEM : WMH_E_DEVICE;
+
+    hipStream_t s = slot.stream;
+    e = hipMemcpyAsync(slot.d_row_ptr, r.row_ptr, (r.n_rows + 1) * sizeof(uint64_t),
+                       hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && r.nnz)
+        e = hipMemcpyAsync(slot.d_col, r.col, r.nnz * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && r.nnz)
+        e = hipMemcpyAsync(slot.d_val, r.val, r.nnz * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    const Rows rows{slot.d_row_ptr, slot.d_col, slot.d_val, r.n_rows, r.nnz};
+    const Bounds b = bounds_view(ctx);
+    if (e == hipSuccess) {
+        if (batched) {
+            e = launch_fill_u32(slot.d_tile_counter, 0u, 1, s);
+            if (e == hipSuccess)
+                e = launch_batched(b, rows, k, cfg.seed, slot.d_sig, plan, d_stream,
+                                   slot.d_tile_counter, grid, s);
+        } else {
+            const bool narrow = ctx->max_bound <= 0xFFFFu;
+            const bool dense = (size_t)4 * ctx->dims * (narrow ? 2 : 4) <= 64 * 1024;
+            for (uint64_t r0 = 0; r0 < r.n_rows && e == hipSuccess; r0 += 8192)
+                e = launch_plain(b, rows, r0, std::min(r.n_rows, r0 + 8192), k, cfg.seed,
+                                 slot.d_sig, narrow, dense, s);
+        }
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(slot.h_sig, slot.d_sig, sig_elems * sizeof(uint16_t),
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(slot.finished, s);
+    return e == hipSuccess ? WMH_OK : WMH_E_DEVICE;
+}
+
+// Called with mu held.
+void wmh_server::complete(Slot &slot, wmh_status st)
+{
+    Request &r = *slot.req;
+    if (st == WMH_OK)
+        std::memcpy(r.sig, slot.h_sig, r.n_rows * (uint64_t)cfg.k * sizeof(uint16_t));
+    r.done_ns = steady_ns();
+    r.status = st;
+    r.done = true;
+    inflight_bytes -= r.bytes;
+    --inflight;
+    if (st == WMH_OK) {
+        ++completed;
+        hashes += r.n_rows * (uint64_t)cfg.k;
+        latencies_ms.push_back((double)(r.done_ns - r.arrival_ns) * 1e-6);
+        last_done_ns = std::max(last_done_ns, r.done_ns);
+    } else {
+        ++failed;
+    }
+    slot.req = nullptr;
+    cv_done.notify_all();
+}
+
+void wmh_server::run()
+{
+    (void)hipSetDevice(ctx->device);
+    std::unique_lock<std::mutex> lk(mu);
+    while (true) {
+        // completions
+        for (Slot &slot : slots) {
+            if (!slot.req) continue;
+            const hipError_t q = hipEventQuery(slot.finished);
+            if (q == hipSuccess) complete(slot, WMH_OK);
+            else if (q != hipErrorNotReady) complete(slot, WMH_E_DEVICE);
+        }
+        // admissions, in arrival order
+        while (!queue.empty()) {
+            Request *r = queue.front();
+            Slot *free_slot = nullptr;
+            for (Slot &slot : slots)
+                if (!slot.req) {
+                    free_slot = &slot;
+                    break;
+                }
+            if (!free_slot) break;
+            if (inflight > 0 && inflight_bytes + r->bytes > cfg.mem_budget) break;
+            queue.pop_front();
+            free_slot->req = r;
+            inflight_bytes += r->bytes;
+            ++inflight;
+            peak_bytes = std::max(peak_bytes, inflight_bytes);
+            r->admit_ns = steady_ns();
+            if (!first_admit_ns) first_admit_ns = r->admit_ns;
+            lk.unlock();
+            const wmh_status st = launch(*free_slot, *r);
+            lk.lock();
+            if (st != WMH_OK) complete(*free_slot, st);
+        }
+        if (stopping && queue.empty() && inflight == 0) break;
+        if (inflight > 0) {
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            lk.lock();
+        } else {
+            cv_work.wait(lk, [&] { return stopping || !queue.empty(); });
+        }
+    }
+}
+
+extern "C" {
+
+uint64_t wmh_server_now_ns(void) { return steady_ns(); }
+
+wmh_status wmh_server_create(wmh_ctx *ctx, const wmh_server_config *cfg_in, wmh_server **out)
+{
+    if (!ctx || !cfg_in || !out) return WMH_E_ARG;
+    *out = nullptr;
+    if (!ctx->has_bounds) return fail(ctx, WMH_E_NO_BOUNDS, "wmh_set_bounds was not called");
+    wmh_server_config cfg = *cfg_in;
+    if (cfg.k == 0 || cfg.k > kMaxK) return fail(ctx, WMH_E_ARG, "k must be in [1, 2^24]");
+    if (cfg.slots == 0) cfg.slots = 4;
+    if (cfg.slots > 64) return fail(ctx, WMH_E_ARG, "slots must be in [1, 64]");
+    if (cfg.mem_budget == 0) cfg.mem_budget = 4ull << 30;
+    if (cfg.mode < WMH_MODE_AUTO || cfg.mode > WMH_MODE_BATCHED)
+        return fail(ctx, WMH_E_ARG, "unknown mode %d", cfg.mode);
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, WMH_E_DEVICE, "hipSetDevice");
+
+    wmh_server *srv = new (std::nothrow) wmh_server();
+    if (!srv) return WMH_E_NOMEM;
+    srv->ctx = ctx;
+    srv->cfg = cfg;
+    wmh_opts o;
+    wmh_opts_init(&o);
+    o.stream_depth = cfg.stream_depth ? cfg.stream_depth : 8192;
+    srv->batched = cfg.mode != WMH_MODE_PLAIN && plan_batched(ctx, cfg.k, ~0ull, o, &srv->plan);
+    if (cfg.mode == WMH_MODE_BATCHED && !srv->batched) {
+        delete srv;
+        return fail(ctx, WMH_E_ARG, "no batched plan fits for D=%u", ctx->dims);
+    }
+    hipError_t e = hipSuccess;
+    if (srv->batched) {
+        srv->grid = (uint32_t)(ctx->cu_count * std::max(1, batched_blocks_per_cu(ctx->dims, srv->plan)));
+        const size_t bytes = (size_t)srv->plan.stream_depth * cfg.k * stream_entry_bytes(srv->plan.packed);
+        e = hipMalloc(&srv->d_stream, bytes);
+        if (e == hipSuccess)
+            e = launch_stream_build(bounds_view(ctx), cfg.seed, cfg.k, srv->plan.stream_depth,
+                                    srv->plan.packed, srv->plan.scale(), srv->d_stream,
+                                    ctx->own_stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->own_stream);
+    }
+    srv->slots.resize(cfg.slots);
+    for (Slot &slot : srv->slots) {
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&slot.finished, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipMalloc(&slot.d_tile_counter, sizeof(uint32_t));
+    }
+    if (e != hipSuccess) {
+        wmh_status st = device_fail(ctx, e, "server setup");
+        wmh_server_destroy(srv);
+        return st;
+    }
+    ctx->servers++;
+    srv->worker = std::thread([srv] { srv->run(); });
+    *out = srv;
+    return WMH_OK;
+}
+
+wmh_status wmh_server_submit(wmh_server *srv, const uint64_t *row_ptr, const uint32_t *col,
+                             const uint32_t *val, uint64_t n_rows, uint64_t nnz, uint16_t *sig,
+                             uint64_t arrival_ns, uint64_t *ticket)
+{
+    if (!srv || !ticket) return WMH_E_ARG;
+    wmh_ctx *ctx = srv->ctx;
+    if (!row_ptr || (n_rows && !sig) || (nnz && (!col || !val)))
+        return fail(ctx, WMH_E_ARG, "null buffer");
+    const wmh_status st = check_rows_host(ctx, row_ptr, col, val, n_rows, nnz, nullptr);
+    if (st != WMH_OK) return st;
+    const uint64_t bytes = (n_rows + 1) * 8 + nnz * 8 + n_rows * (uint64_t)srv->cfg.k * 2;
+    if (bytes > srv->cfg.mem_budget)
+        return fail(ctx, WMH_E_NOMEM, "request needs %llu bytes, budget %llu",
+                    (unsigned long long)bytes, (unsigned long long)srv->cfg.mem_budget);
+    Request *r = new (std::nothrow) Request();
+    if (!r) return WMH_E_NOMEM;
+    r->row_ptr = row_ptr;
+    r->col = col;
+    r->val = val;
+    r->n_rows = n_rows;
+    r->nnz = nnz;
+    r->sig = sig;
+    r->arrival_ns = arrival_ns ? arrival_ns : steady_ns();
+    r->bytes = bytes;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        r->id = srv->next_id++;
+        srv->requests[r->id] = r;
+        ++srv->submitted;
+        if (n_rows == 0) {
+            r->done = true;
+            r->done_ns = steady_ns();
+        } else {
+            srv->queue.push_back(r);
+            srv->max_queued = std::max<uint64_t>(srv->max_queued, srv->queue.size());
+        }
+        *ticket = r->id;
+    }
+    srv->cv_work.notify_one();
+    return WMH_OK;
+}
+
+wmh_status wmh_server_poll(wmh_server *srv, uint64_t ticket, int *done, double *latency_ms)
+{
+    if (!srv || !done) return WMH_E_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->requests.find(ticket);
+    if (it == srv->requests.end()) return WMH_E_ARG;
+    Request *r = it->second;
+    *done = r->done ? 1 : 0;
+    if (!r->done) return WMH_OK;
+    if (latency_ms) *latency_ms = (double)(r->done_ns - r->arrival_ns) * 1e-6;
+    const wmh_status st = r->status;
+    srv->requests.erase(it);
+    delete r;
+    return st;
+}
+
+wmh_status wmh_server_wait(wmh_server *srv, uint64_t ticket, double *latency_ms)
+{
+    if (!srv) return WMH_E_ARG;
+    std::unique_lock<std::mutex> lk(srv->mu);
+    auto it = srv->requests.find(ticket);
+    if (it == srv->requests.end()) return WMH_E_ARG;
+    Request *r = it->second;
+    srv->cv_done.wait(lk, [&] { return r->done; });
+    if (latency_ms) *latency_ms = (double)(r->done_ns - r->arrival_ns) * 1e-6;
+    const wmh_status st = r->status;
+    srv->requests.erase(ticket);
+    delete r;
+    return st;
+}
+
+wmh_status wmh_server_drain(wmh_server *srv)
+{
+    if (!srv) return WMH_E_ARG;
+    std::unique_lock<std::mutex> lk(srv->mu);
+    srv->cv_done.wait(lk, [&] { return srv->queue.empty() && srv->inflight == 0; });
+    return srv->failed ? WMH_E_DEVICE : WMH_OK;
+}
+
+wmh_status wmh_server_stats(wmh_server *srv, wmh_serving_stats *out)
+{
+    if (!srv || !out) return WMH_E_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    std::memset(out, 0, sizeof(*out));
+    out->submitted = srv->submitted;
+    out->completed = srv->completed;
+    out->failed = srv->failed;
+    out->queued = srv->queue.size();
+    out->max_queued = srv->max_queued;
+    out->peak_bytes = srv->peak_bytes;
+    out->hashes = srv->hashes;
+    std::vector<double> v = srv->latencies_ms;
+    if (!v.empty()) {
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double q) {
+            const size_t i = (size_t)std::min<double>(v.size() - 1, std::ceil(q * v.size()) - 1);
+            return v[i];
+        };
+        out->p50_ms = pct(0.50);
+        out->p99_ms = pct(0.99);
+        out->p999_ms = pct(0.999);
+        out->max_ms = v.back();
+        double sum = 0;
+        for (double x : v) sum += x;
+        out->mean_ms = sum / v.size();
+    }
+    if (srv->last_done_ns > srv->first_admit_ns && srv->first_admit_ns) {
+        out->busy_s = (double)(srv->last_done_ns - srv->first_admit_ns) * 1e-9;
+        out->hashes_per_s = (double)srv->hashes / out->busy_s;
+    }
+    return WMH_OK;
+}
+
+void wmh_server_destroy(wmh_server *srv)
+{
+    if (!srv) return;
+    if (srv->worker.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            srv->stopping = true;
+        }
+        srv->cv_work.notify_all();
+        srv->worker.join();
+        srv->ctx->servers--;
+    }
+    (void)hipSetDevice(srv->ctx->device);
+    for (Slot &slot : srv->slots) {
+        if (slot.stream) (void)hipStreamSynchronize(slot.stream);
+        if (slot.d_row_ptr) (void)hipFree(slot.d_row_ptr);
+        if (slot.d_col) (void)hipFree(slot.d_col);
+        if (slot.d_val) (void)hipFree(slot.d_val);
+        if (slot.d_sig) (void)hipFree(slot.d_sig);
+        if (slot.h_sig) (void)hipHostFree(slot.h_sig);
+        if (slot.d_tile_counter) (void)hipFree(slot.d_tile_counter);
+        if (slot.finished) (void)hipEventDestroy(slot.finished);
+        if (slot.stream) (void)hipStreamDestroy(slot.stream);
+    }
+    if (srv->d_stream) (void)hipFree(srv->d_stream);
+    for (auto &kv : srv->requests) delete kv.second;
+    delete srv;
+}
+
+}  // extern "C"

@@ -1,0 +1,151 @@
+"""Serving loop binding (wmh_server_* in include/wmh.h) and an open-loop request driver.
+
+The loop itself runs in libwmh: a worker thread admits queued requests as slots and device
+memory free up and overlaps their walks on the device.  This module only marshals arguments
+and, for benchmarking, submits requests at their scheduled (Poisson) arrival times.
+"""
+from __future__ import annotations
+
+import ctypes
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import wmh
+
+
+def now_ns() -> int:
+    return int(wmh.load().wmh_server_now_ns())
+
+
+@dataclass
+class Request:
+    row_ptr: np.ndarray  # u64 [N+1]
+    col: np.ndarray      # u32 [nnz]
+    val: np.ndarray      # u32 [nnz]
+    sig: np.ndarray      # u16 [N, k], written on completion
+    ticket: int = 0
+
+    @property
+    def n_rows(self) -> int:
+        return len(self.row_ptr) - 1
+
+
+class Server:
+    """A serving loop on a context's device and bounds."""
+
+    def __init__(self, ctx: "wmh.Context", k: int, seed: int = 0, slots: int = 4,
+                 mem_budget: int = 0, mode: str = "auto", stream_depth: int = 0):
+        self._lib = wmh.load()
+        self.ctx = ctx
+        self.k = k
+        cfg = wmh.ServerConfig()
+        cfg.k = k
+        cfg.slots = slots
+        cfg.seed = seed & 0xFFFFFFFFFFFFFFFF
+        cfg.mem_budget = mem_budget
+        cfg.mode = wmh.MODES[mode]
+        cfg.stream_depth = stream_depth
+        self._ptr = ctypes.c_void_p()
+        ctx._check(self._lib.wmh_server_create(ctx._ptr, ctypes.byref(cfg),
+                                               ctypes.byref(self._ptr)), "wmh_server_create")
+        self._live: dict[int, Request] = {}
+
+    def close(self):
+        if self._ptr:
+            self._lib.wmh_server_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def make_request(self, row_ptr, col, val) -> Request:
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.uint64)
+        col = np.ascontiguousarray(col, dtype=np.uint32)
+        val = np.ascontiguousarray(val, dtype=np.uint32)
+        sig = np.zeros((len(row_ptr) - 1, self.k), dtype=np.uint16)
+        return Request(row_ptr, col, val, sig)
+
+    def submit(self, req: Request, arrival_ns: int = 0) -> int:
+        t = ctypes.c_uint64()
+        st = self._lib.wmh_server_submit(self._ptr, req.row_ptr.ctypes.data,
+                                         req.col.ctypes.data if len(req.col) else None,
+                                         req.val.ctypes.data if len(req.val) else None,
+                                         req.n_rows, len(req.col),
+                                         req.sig.ctypes.data if req.sig.size else None,
+                                         ctypes.c_uint64(arrival_ns), ctypes.byref(t))
+        self.ctx._check(st, "wmh_server_submit")
+        req.ticket = t.value
+        self._live[t.value] = req  # keeps the buffers alive until completion
+        return t.value
+
+    def wait(self, ticket: int) -> float:
+        lat = ctypes.c_double()
+        st = self._lib.wmh_server_wait(self._ptr, ticket, ctypes.byref(lat))
+        self._live.pop(ticket, None)
+        self.ctx._check(st, "wmh_server_wait")
+        return lat.value
+
+    def poll(self, ticket: int):
+        done, lat = ctypes.c_int(), ctypes.c_double()
+        st = self._lib.wmh_server_poll(self._ptr, ticket, ctypes.byref(done), ctypes.byref(lat))
+        if done.value:
+            self._live.pop(ticket, None)
+        self.ctx._check(st, "wmh_server_poll")
+        return (lat.value if done.value else None)
+
+    def drain(self):
+        self.ctx._check(self._lib.wmh_server_drain(self._ptr), "wmh_server_drain")
+
+    def stats(self) -> dict:
+        s = wmh.ServingStats()
+        self.ctx._check(self._lib.wmh_server_stats(self._ptr, ctypes.byref(s)),
+                        "wmh_server_stats")
+        return {name: getattr(s, name) for name, _ in wmh.ServingStats._fields_}
+
+
+def requests_from_corpus(ds, row_lists, server: Server) -> list[Request]:
+    """One Request per list of corpus row indices (rows copied out of the corpus)."""
+    out = []
+    rp = ds.row_ptr.astype(np.int64)
+    for rows in row_lists:
+        rows = np.asarray(rows, dtype=np.int64)
+        lengths = rp[rows + 1] - rp[rows]
+        row_ptr = np.zeros(len(rows) + 1, dtype=np.uint64)
+        row_ptr[1:] = np.cumsum(lengths)
+        if lengths.sum():
+            idx = np.concatenate([np.arange(a, b) for a, b in zip(rp[rows], rp[rows + 1])])
+        else:
+            idx = np.zeros(0, dtype=np.int64)
+        out.append(server.make_request(row_ptr, ds.col[idx], ds.val[idx]))
+    return out
+
+
+def run_open_loop(server: Server, requests: list[Request], arrivals_s: np.ndarray) -> dict:
+    """Submits request i at t0 + arrivals_s[i] (open loop: the schedule never waits for
+    completions) with that scheduled time as its arrival, then drains and returns stats."""
+    t0 = now_ns() + 2_000_000
+    for req, a in zip(requests, arrivals_s):
+        due = t0 + int(a * 1e9)
+        while True:
+            left = due - now_ns()
+            if left <= 0:
+                break
+            time.sleep(min(left, 2_000_000) / 1e9 if left > 200_000 else 0)
+        server.submit(req, arrival_ns=due)
+    server.drain()
+    for req in requests:
+        if req.ticket in server._live:
+            server.wait(req.ticket)
+    return server.stats()

@@ -23,7 +23,9 @@ MODES = {"auto": 0, "plain": 1, "batched": 2}
 
 EXPORTED = ["wmh_opts_init", "wmh_create", "wmh_destroy", "wmh_set_bounds", "wmh_hash",
             "wmh_estimate", "wmh_collisions", "wmh_bounds_info", "wmh_bounds_tables",
-            "wmh_draws", "wmh_last_kernel_ms", "wmh_last_error", "wmh_status_string"]
+            "wmh_draws", "wmh_last_kernel_ms", "wmh_last_error", "wmh_status_string",
+            "wmh_server_create", "wmh_server_submit", "wmh_server_poll", "wmh_server_wait",
+            "wmh_server_drain", "wmh_server_stats", "wmh_server_now_ns", "wmh_server_destroy"]
 
 
 class WmhOpts(ctypes.Structure):
@@ -33,6 +35,22 @@ class WmhOpts(ctypes.Structure):
                 ("hashes_per_tile", ctypes.c_uint32), ("stream_depth", ctypes.c_uint32),
                 ("waves_per_block", ctypes.c_uint32), ("profile", ctypes.c_int32),
                 ("reserved", ctypes.c_uint32 * 5)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("slots", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+                ("mem_budget", ctypes.c_uint64), ("mode", ctypes.c_int32),
+                ("stream_depth", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 4)]
+
+
+class ServingStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("queued", ctypes.c_uint64),
+                ("max_queued", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
+                ("hashes", ctypes.c_uint64), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("p999_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("busy_s", ctypes.c_double), ("hashes_per_s", ctypes.c_double)]
 
 
 class WMHError(RuntimeError):
@@ -80,6 +98,23 @@ def load() -> ctypes.CDLL:
     L.wmh_last_kernel_ms.restype = ctypes.c_int
     L.wmh_draws.argtypes = [vp, u64, u32, u32, u32, vp, vp, vp, vp]
     L.wmh_draws.restype = ctypes.c_int
+    L.wmh_server_create.argtypes = [vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+    L.wmh_server_create.restype = ctypes.c_int
+    L.wmh_server_submit.argtypes = [vp, vp, vp, vp, u64, u64, vp, u64, ctypes.POINTER(u64)]
+    L.wmh_server_submit.restype = ctypes.c_int
+    L.wmh_server_poll.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_int),
+                                  ctypes.POINTER(ctypes.c_double)]
+    L.wmh_server_poll.restype = ctypes.c_int
+    L.wmh_server_wait.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_double)]
+    L.wmh_server_wait.restype = ctypes.c_int
+    L.wmh_server_drain.argtypes = [vp]
+    L.wmh_server_drain.restype = ctypes.c_int
+    L.wmh_server_stats.argtypes = [vp, ctypes.POINTER(ServingStats)]
+    L.wmh_server_stats.restype = ctypes.c_int
+    L.wmh_server_now_ns.argtypes = []
+    L.wmh_server_now_ns.restype = ctypes.c_uint64
+    L.wmh_server_destroy.argtypes = [vp]
+    L.wmh_server_destroy.restype = None
     L.wmh_last_error.argtypes = [vp]
     L.wmh_last_error.restype = ctypes.c_char_p
     L.wmh_status_string.argtypes = [ctypes.c_int]

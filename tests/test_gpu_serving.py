@@ -1,0 +1,157 @@
+"""GPU tests of the serving loop (wmh_server_*): every request's signatures equal the oracle's
+and wmh_hash's on the same rows, a request gives the same bytes alone and in a concurrent mix,
+admission respects the memory budget, and bad requests are refused at submission."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_1602_08393_amd import serve, synth, wmh  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = wmh.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def corpus():
+    return synth.config1()
+
+
+def _rows(rng, n_corpus, sizes):
+    return [rng.integers(0, n_corpus, size=s) for s in sizes]
+
+
+def _oracle_sig(ds, rows, k, seed):
+    sub = ds.rows(rows)
+    return oracle.hash_csr(sub.m, sub.row_ptr, sub.col, sub.val, k, seed=seed)
+
+
+@pytest.mark.parametrize("mode,slots", [("auto", 4), ("plain", 2), ("batched", 1)])
+def test_requests_match_oracle(ctx, corpus, mode, slots):
+    k, seed = 48, 21
+    print(f"  serving {mode} slots={slots}", flush=True)
+    ctx.set_bounds(corpus.m)
+    rng = np.random.Generator(np.random.PCG64(5))
+    row_lists = _rows(rng, corpus.n_rows, [1, 7, 64, 130, 3, 257])
+    with serve.Server(ctx, k, seed=seed, slots=slots, mode=mode) as srv:
+        reqs = serve.requests_from_corpus(corpus, row_lists, srv)
+        for r in reqs:
+            srv.submit(r)
+        for r in reqs:
+            assert srv.wait(r.ticket) >= 0
+        st = srv.stats()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["hashes"] == sum(len(x) for x in row_lists) * k
+    assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+    for rows, r in zip(row_lists, reqs):
+        assert np.array_equal(r.sig, _oracle_sig(corpus, rows, k, seed))
+
+
+def test_alone_and_in_the_mix_are_identical(ctx, corpus):
+    k, seed = 64, 0
+    ctx.set_bounds(corpus.m)
+    rng = np.random.Generator(np.random.PCG64(6))
+    probe_rows = rng.integers(0, corpus.n_rows, size=300)
+    others = _rows(rng, corpus.n_rows, [500, 1, 40, 999, 77, 300, 2, 600])
+    with serve.Server(ctx, k, seed=seed, slots=4) as srv:
+        alone = serve.requests_from_corpus(corpus, [probe_rows], srv)[0]
+        srv.submit(alone)
+        srv.wait(alone.ticket)
+        mix = serve.requests_from_corpus(corpus, others[:4] + [probe_rows] + others[4:], srv)
+        for r in mix:
+            srv.submit(r)
+        srv.drain()
+        for r in mix:
+            srv.wait(r.ticket)
+    assert np.array_equal(alone.sig, mix[4].sig)
+    # and equal to a direct wmh_hash of the same rows
+    sub = corpus.rows(probe_rows)
+    direct = wmh.sig_to_numpy(ctx.hash(wmh.upload_dataset(sub, DEV), k, seed=seed))
+    assert np.array_equal(alone.sig, direct)
+
+
+def test_memory_budget_queues_requests(ctx, corpus):
+    k = 32
+    ctx.set_bounds(corpus.m)
+    rng = np.random.Generator(np.random.PCG64(7))
+    row_lists = _rows(rng, corpus.n_rows, [200] * 6)
+    with serve.Server(ctx, k, slots=4, mem_budget=1) as probe:
+        big = serve.requests_from_corpus(corpus, row_lists[:1], probe)[0]
+        with pytest.raises(wmh.WMHError) as e:
+            probe.submit(big)
+        assert e.value.name == "WMH_E_NOMEM"
+    # a budget that holds only one of these requests at a time: the rest wait in the queue
+    with serve.Server(ctx, k, slots=4) as sizer:
+        reqs = serve.requests_from_corpus(corpus, row_lists, sizer)
+    sizes = [(r.n_rows + 1) * 8 + len(r.col) * 8 + r.n_rows * k * 2 for r in reqs]
+    budget = int(max(sizes) * 1.3)
+    with serve.Server(ctx, k, slots=4, mem_budget=budget) as srv:
+        for r in reqs:
+            srv.submit(r)
+        srv.drain()
+        st = srv.stats()
+        for r in reqs:
+            srv.wait(r.ticket)
+    assert st["completed"] == len(reqs)
+    assert st["peak_bytes"] <= budget
+    assert st["max_queued"] >= 1
+    for rows, r in zip(row_lists, reqs):
+        assert np.array_equal(r.sig, _oracle_sig(corpus, rows, k, 0))
+
+
+def test_bad_requests_are_refused(ctx, corpus):
+    ctx.set_bounds(corpus.m)
+    with serve.Server(ctx, 8, slots=2) as srv:
+        bad = srv.make_request(np.array([0, 2], np.uint64), np.array([5, 3], np.uint32),
+                               np.array([1, 1], np.uint32))
+        with pytest.raises(wmh.WMHError) as e:
+            srv.submit(bad)
+        assert e.value.name == "WMH_E_UNSORTED"
+        over = srv.make_request(np.array([0, 1], np.uint64), np.array([0], np.uint32),
+                                np.array([int(corpus.m[0]) + 1], np.uint32))
+        with pytest.raises(wmh.WMHError) as e:
+            srv.submit(over)
+        assert e.value.name == "WMH_E_BOUND"
+        # bounds cannot change under a live serving loop
+        with pytest.raises(wmh.WMHError) as e:
+            ctx.set_bounds(corpus.m)
+        assert e.value.name == "WMH_E_ARG"
+        empty = srv.make_request(np.zeros(1, np.uint64), np.zeros(0, np.uint32),
+                                 np.zeros(0, np.uint32))
+        srv.wait(srv.submit(empty))
+    ctx.set_bounds(corpus.m)
+
+
+def test_large_dimension_requests(ctx):
+    """D = 2^20 (dense rows do not fit in LDS): the loop runs the plain walk."""
+    D = 1 << 20
+    rng = np.random.Generator(np.random.PCG64(9))
+    cols, vals = [], []
+    for _ in range(40):
+        c = np.sort(rng.choice(D, size=int(rng.integers(1, 400)), replace=False))
+        cols.append(c)
+        vals.append(rng.integers(1, 1000, size=len(c)))
+    ds = synth.csr_from_lists(cols, vals, D)
+    ds.m[:] = np.maximum(ds.m, 50)
+    k = 16
+    ctx.set_bounds(ds.m)
+    with serve.Server(ctx, k, seed=4, slots=3) as srv:
+        row_lists = [np.arange(0, 10), np.arange(10, 40), np.array([3, 3, 7])]
+        reqs = serve.requests_from_corpus(ds, row_lists, srv)
+        for r in reqs:
+            srv.submit(r)
+        for r in reqs:
+            srv.wait(r.ticket)
+    for rows, r in zip(row_lists, reqs):
+        assert np.array_equal(r.sig, _oracle_sig(ds, rows, k, 4))
