@@ -59,11 +59,23 @@ typedef enum {
 
 /* Scheduling of wmh_hash.  Every mode returns identical signatures. */
 typedef enum {
-    WMH_MODE_AUTO = 0,     /* the batched persistent path with the planner's choice of tiles */
+    WMH_MODE_AUTO = 0,     /* the cheapest of the three below by a cost estimate from the
+                              rows' statistics: expected walk steps min(M / sum x, 65535) per
+                              hash (Theorem 2) against the index's nnz + 65534 * k * sum x / M
+                              reads (the statistics come from the validation pass, which AUTO
+                              runs, and waits for, even when validate = 0) */
     WMH_MODE_PLAIN = 1,    /* one launch per batch of `batch_rows` rows, a workgroup per row
                               group, each lane walking its own (row, hash) with its own draws */
-    WMH_MODE_BATCHED = 2   /* one persistent launch over (row block, hash block) tiles; each
+    WMH_MODE_BATCHED = 2,  /* one persistent launch over (row block, hash block) tiles; each
                               draw is shared by the rows of a block (see wmh_hash) */
+    WMH_MODE_INDEXED = 3   /* the capped sequence filed by component: every draw (j, t) with
+                              t <= 65534 is listed under its component with its offset, once
+                              per (bounds, seed, k) and kept in the context; a row's hash j is
+                              the smallest t among the keys of its nonzero components whose
+                              offset is below x_c, else 65535.  The same values as the walk, in
+                              O(nnz + k * 65534 * sum x / M) per row: the choice for small
+                              green fractions.  Needs k <= 8192 and k * 65534 * 8 bytes of
+                              device memory */
 } wmh_mode;
 
 typedef struct {
@@ -100,7 +112,8 @@ void wmh_destroy(wmh_ctx *ctx);
  *   D : number of dimensions, 1 <= D <= 2^26.
  * Builds on the device the prefix sums P[0..D] (uint64), the total M = P[D] (must be >= 1),
  * the uniform bucket table T over [0, M) used for the O(1) position-to-component lookup
- * (Algorithm 5), and the bounded-draw threshold 2^64 mod M.  Replaces earlier bounds.
+ * (Algorithm 5), and the bounded-draw threshold 2^64 mod M.  Replaces earlier bounds; bounds
+ * identical to the current ones change nothing (cached graphs and indexes stay valid).
  * Synchronous.  Errors: WMH_E_ARG (null, D out of range, a serving loop of this context is
  * alive), WMH_E_OVERFLOW (M = 0), WMH_E_NOMEM, WMH_E_DEVICE.
  */
@@ -180,11 +193,19 @@ wmh_status wmh_bounds_tables(const uint32_t *m, uint32_t D, uint64_t *prefix, ui
  * from HIP events recorded on the launch stream.  Direct launches: *walk_ms spans the
  * hash-walk kernels (the batched kernel, or every plain launch), *stream_ms the shared-stream
  * build (0 if none).  hipGraph replays (batched with use_graph): *walk_ms spans the whole
- * graph (counter reset, stream build and walk) and *stream_ms is 0.
+ * graph (counter reset, stream build and walk) and *stream_ms is 0.  Indexed path: *walk_ms
+ * spans the row kernel, *stream_ms the index build when that call built it (else 0).
  * Requires that call to have completed (opts->sync, or a later synchronization).
  * Errors: WMH_E_ARG (no profiled call yet), WMH_E_DEVICE.
  */
 wmh_status wmh_last_kernel_ms(wmh_ctx *ctx, float *walk_ms, float *stream_ms);
+
+/*
+ * wmh_last_mode -- the path the last successful wmh_hash on this context took:
+ * WMH_MODE_PLAIN, WMH_MODE_BATCHED or WMH_MODE_INDEXED (WMH_MODE_AUTO before any call).
+ * Errors: WMH_E_ARG (null).
+ */
+wmh_status wmh_last_mode(const wmh_ctx *ctx, int32_t *mode);
 
 /* ------------------------------------------------------------------------------------------ */
 /* Serving loop: continuous batching of hash requests on one device.                           */

@@ -32,6 +32,29 @@ struct GraphKey {
     }
 };
 
+// Row statistics gathered by the validation pass (device) or the host check, for the planner.
+struct RowStats {
+    bool known = false;
+    uint64_t min_green = ~0ull;  // smallest sum(x) over non-empty rows
+    uint64_t walk_steps = 0;     // sum over non-empty rows of min(M / sum(x), 65535)
+    uint64_t index_keys = 0;     // sum over non-empty rows of ceil(65534 * sum(x) / M)
+};
+
+// A component index owned by a context or a serving loop, rebuilt when its key changes.
+struct OwnedIndex {
+    IndexBuffers buf;
+    uint64_t cap_entries = 0;
+    uint32_t cap_dims = 0;
+    bool valid = false;
+    uint64_t seed = 0, epoch = 0;
+    uint32_t k = 0;
+    hipEvent_t used = nullptr;  // recorded after each read, awaited before a rebuild
+};
+
+constexpr uint64_t kIndexBudgetBytes = 4ull << 30;  // index entries, at most 4 GiB
+
+enum class Path { kPlain, kBatched, kIndexed };
+
 }  // namespace wmh
 
 struct wmh_ctx {
@@ -65,6 +88,8 @@ struct wmh_ctx {
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     bool profiled = false;
     bool profiled_stream = false;
+    wmh::OwnedIndex index;  // component index of the last indexed call
+    int32_t last_mode = 0;  // path of the last successful wmh_hash (wmh_mode)
     int servers = 0;  // live serving loops using this context's bounds
     std::string last_error;
 };
@@ -77,9 +102,20 @@ Bounds bounds_view(const wmh_ctx *ctx);
 // Tile plan of the batched walk; false when no dense plan fits in LDS.
 bool plan_batched(const wmh_ctx *ctx, uint32_t k, uint64_t min_green, const wmh_opts &o,
                   BatchedPlan *plan);
-// Host-side check of CSR rows against the context's bounds (same rules as the device check).
+// Host-side check of CSR rows against the context's bounds (same rules as the device check);
+// fills *stats (may be NULL) like the device pass.
 wmh_status check_rows_host(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
-                           const uint32_t *val, uint64_t n_rows, uint64_t nnz,
-                           uint64_t *min_green);
+                           const uint32_t *val, uint64_t n_rows, uint64_t nnz, RowStats *stats);
+// Whether an index for k hashes is allowed (k and memory limits).
+bool index_fits(uint32_t k);
+// Makes `ix` the index of (ctx's bounds, seed, k), building it on `stream` when stale.
+// With record_error false the context's error text is left alone (calls from the serving
+// loop's worker thread).
+wmh_status ensure_index(wmh_ctx *ctx, OwnedIndex *ix, uint64_t seed, uint32_t k,
+                        hipStream_t stream, bool record_error = true);
+void free_index(OwnedIndex *ix);
+// The planner's choice for `mode` (AUTO compares estimated costs; see wmh_mode).
+Path choose_path(const wmh_ctx *ctx, int mode, bool batched_ok, bool index_ready, uint32_t k,
+                 uint64_t n_rows, uint64_t nnz, const RowStats &stats);
 
 }  // namespace wmh

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -97,10 +98,10 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, uint64_t min_green, const wmh_
 }
 
 wmh_status check_rows_host(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
-                           const uint32_t *val, uint64_t n_rows, uint64_t nnz,
-                           uint64_t *min_green_out)
+                           const uint32_t *val, uint64_t n_rows, uint64_t nnz, RowStats *stats)
 {
-    uint64_t min_green = ~0ull;
+    RowStats st;
+    st.known = true;
     for (uint64_t r = 0; r < n_rows; ++r) {
         const uint64_t lo = row_ptr[r], hi = row_ptr[r + 1];
         if (lo > hi || hi > nnz)
@@ -120,10 +121,104 @@ wmh_status check_rows_host(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t
                             (unsigned long long)r);
             green += val[e];
         }
-        if (green) min_green = std::min(min_green, green);
+        if (green) {
+            st.min_green = std::min(st.min_green, green);
+            st.walk_steps += std::min<uint64_t>(ctx->total / green, kCap);
+            st.index_keys += (uint64_t)std::ceil(65534.0 * ((double)green / (double)ctx->total));
+        }
     }
-    if (min_green_out) *min_green_out = min_green;
+    if (stats) *stats = st;
     return WMH_OK;
+}
+
+bool index_fits(uint32_t k)
+{
+    return k >= 1 && k <= kIndexMaxK && index_entry_count(k) * sizeof(uint64_t) <= kIndexBudgetBytes;
+}
+
+void free_index(OwnedIndex *ix)
+{
+    if (ix->buf.entries) (void)hipFree(ix->buf.entries);
+    if (ix->buf.offsets) (void)hipFree(ix->buf.offsets);
+    if (ix->buf.cursor) (void)hipFree(ix->buf.cursor);
+    if (ix->buf.block_sums) (void)hipFree(ix->buf.block_sums);
+    if (ix->used) (void)hipEventDestroy(ix->used);
+    *ix = OwnedIndex{};
+}
+
+wmh_status ensure_index(wmh_ctx *ctx, OwnedIndex *ix, uint64_t seed, uint32_t k,
+                        hipStream_t stream, bool record_error)
+{
+    if (ix->valid && ix->seed == seed && ix->k == k && ix->epoch == ctx->bounds_epoch)
+        return WMH_OK;
+    wmh_ctx *err = record_error ? ctx : nullptr;
+    if (!index_fits(k))
+        return fail(err, WMH_E_ARG, "the component index needs k <= %u", kIndexMaxK);
+    ix->valid = false;
+    hipError_t e = hipSuccess;
+    if (!ix->used) e = hipEventCreateWithFlags(&ix->used, hipEventDisableTiming);
+    else e = hipStreamWaitEvent(stream, ix->used, 0);  // earlier readers, on any stream
+    if (e != hipSuccess) return device_fail(err, e, "index event");
+    const uint64_t n = index_entry_count(k);
+    if (n > ix->cap_entries) {
+        if (ix->buf.entries) (void)hipFree(ix->buf.entries);
+        ix->buf.entries = nullptr;
+        ix->cap_entries = 0;
+        e = hipMalloc(&ix->buf.entries, n * sizeof(uint64_t));
+        if (e != hipSuccess) return device_fail(err, e, "index entries");
+        ix->cap_entries = n;
+    }
+    if (ctx->dims > ix->cap_dims || !ix->buf.offsets) {
+        for (uint32_t **p : {&ix->buf.offsets, &ix->buf.cursor, &ix->buf.block_sums}) {
+            if (*p) (void)hipFree(*p);
+            *p = nullptr;
+        }
+        ix->cap_dims = 0;
+        const size_t words = (size_t)ctx->dims + 1;
+        e = hipMalloc(&ix->buf.offsets, words * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(&ix->buf.cursor, words * sizeof(uint32_t));
+        if (e == hipSuccess)
+            e = hipMalloc(&ix->buf.block_sums, index_scan_blocks(ctx->dims) * sizeof(uint32_t));
+        if (e != hipSuccess) return device_fail(err, e, "index offsets");
+        ix->cap_dims = ctx->dims;
+    }
+    e = launch_index_build(bounds_view(ctx), seed, k, ix->buf, stream);
+    if (e != hipSuccess) return device_fail(err, e, "index build");
+    ix->valid = true;
+    ix->seed = seed;
+    ix->k = k;
+    ix->epoch = ctx->bounds_epoch;
+    return WMH_OK;
+}
+
+// Relative costs in units of one membership test of the batched walk (measured on MI355X:
+// the walk runs about 1.7e12 tests/s; the other figures are per item of the named kind).
+namespace {
+constexpr double kCostPlainDenseStep = 12.0;   // a step of the plain walk, dense row in LDS
+constexpr double kCostPlainSparseStep = 24.0;  // a step of the plain walk, binary search in HBM
+constexpr double kCostPerRowHash = 2.0;        // writing one signature value (either order)
+constexpr double kCostIndexEntry = 64.0;       // building one index key (two draws, sort)
+constexpr double kCostIndexNnz = 64.0;         // a nonzero's list lookup (dependent loads)
+constexpr double kCostIndexKey = 16.0;         // one green key read and its LDS minimum
+}  // namespace
+
+Path choose_path(const wmh_ctx *ctx, int mode, bool batched_ok, bool index_ready, uint32_t k,
+                 uint64_t n_rows, uint64_t nnz, const RowStats &stats)
+{
+    if (mode == WMH_MODE_PLAIN) return Path::kPlain;
+    if (mode == WMH_MODE_BATCHED) return Path::kBatched;
+    if (mode == WMH_MODE_INDEXED) return Path::kIndexed;
+    const Path walk_path = batched_ok ? Path::kBatched : Path::kPlain;
+    if (!stats.known || !index_fits(k)) return walk_path;
+    const bool narrow = ctx->max_bound <= 0xFFFFu;
+    const bool dense = (size_t)4 * ctx->dims * (narrow ? 2 : 4) <= 64 * 1024;
+    const double step = batched_ok ? 1.0 : (dense ? kCostPlainDenseStep : kCostPlainSparseStep);
+    const double walk = (double)k * ((double)stats.walk_steps * step + kCostPerRowHash * n_rows);
+    const double index = (index_ready ? 0.0 : (double)index_entry_count(k) * kCostIndexEntry) +
+                         (double)nnz * kCostIndexNnz +
+                         (double)k * ((double)stats.index_keys * kCostIndexKey +
+                                      kCostPerRowHash * n_rows);
+    return index < walk ? Path::kIndexed : walk_path;
 }
 
 }  // namespace wmh
@@ -260,6 +355,7 @@ void wmh_destroy(wmh_ctx *ctx)
     hipSetDevice(ctx->device);
     drop_graph(ctx);
     release_bounds(ctx);
+    free_index(&ctx->index);
     if (ctx->d_stream) hipFree(ctx->d_stream);
     if (ctx->d_check) hipFree(ctx->d_check);
     if (ctx->h_check) hipHostFree(ctx->h_check);
@@ -314,6 +410,11 @@ wmh_status wmh_set_bounds(wmh_ctx *ctx, const uint32_t *m, uint32_t D)
     if (!m || D == 0 || D > kMaxDims) return fail(ctx, WMH_E_ARG, "D must be in [1, 2^26]");
     if (ctx->servers > 0)
         return fail(ctx, WMH_E_ARG, "a serving loop is using this context's bounds");
+    if (ctx->has_bounds && ctx->dims == D &&
+        std::memcmp(ctx->h_bound.data(), m, (size_t)D * sizeof(uint32_t)) == 0) {
+        ctx->last_error.clear();  // the same bounds: tables, graph and index stay valid
+        return WMH_OK;
+    }
     WMH_HIP(ctx, hipSetDevice(ctx->device));
     uint32_t shift = 0;
     uint64_t n_buckets = 0, threshold = 0;
@@ -378,39 +479,65 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
     wmh_opts o;
     if (opts) o = *opts;
     else wmh_opts_init(&o);
-    if (o.mode < WMH_MODE_AUTO || o.mode > WMH_MODE_BATCHED)
+    if (o.mode < WMH_MODE_AUTO || o.mode > WMH_MODE_INDEXED)
         return fail(ctx, WMH_E_ARG, "unknown mode %d", o.mode);
+    if (o.mode == WMH_MODE_INDEXED && !index_fits(k))
+        return fail(ctx, WMH_E_ARG, "the component index needs k <= %u", kIndexMaxK);
     WMH_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t s = pick_stream(ctx, stream);
     const Rows rows{row_ptr, col, val, n_rows, nnz};
     const Bounds b = bounds_view(ctx);
 
-    uint64_t min_green = ~0ull;
+    RowStats stats;
     const bool profile = o.profile != 0;
     ctx->profiled = false;
-    if (o.validate) {
-        // first_error and min_green start at ~0, n_empty at 0
+    if (o.validate || o.mode == WMH_MODE_AUTO) {
+        // first_error and min_green start at ~0, the counters at 0
         uint32_t *words = reinterpret_cast<uint32_t *>(ctx->d_check);
         WMH_HIP(ctx, launch_fill_u32(words, 0xFFFFFFFFu, 4, s));
-        WMH_HIP(ctx, launch_fill_u32(words + 4, 0u, 2, s));
-        WMH_HIP(ctx, launch_validate(rows, ctx->d_bound, ctx->dims, ctx->d_check, s));
+        WMH_HIP(ctx, launch_fill_u32(words + 4, 0u, 6, s));
+        WMH_HIP(ctx, launch_validate(rows, ctx->d_bound, ctx->dims, ctx->total, ctx->d_check, s));
         WMH_HIP(ctx, hipMemcpyAsync(ctx->h_check, ctx->d_check, sizeof(CheckWords),
                                     hipMemcpyDeviceToHost, s));
         WMH_HIP(ctx, hipStreamSynchronize(s));
         const CheckWords v = *ctx->h_check;
-        if (v.first_error != ~0ull) {
+        if (o.validate && v.first_error != ~0ull) {
             const uint64_t row = v.first_error >> 4;
             const uint32_t code = (uint32_t)(v.first_error & 15u);
             return fail(ctx, check_status(code), "row %llu: %s", (unsigned long long)row,
                         check_name(code));
         }
-        min_green = v.min_green;
+        stats.known = true;
+        stats.min_green = v.min_green;
+        stats.walk_steps = v.walk_steps;
+        stats.index_keys = v.index_keys;
     }
 
     BatchedPlan plan{};
-    bool batched = o.mode != WMH_MODE_PLAIN && plan_batched(ctx, k, min_green, o, &plan);
-    if (o.mode == WMH_MODE_BATCHED && !batched)
+    const bool batched_ok = (o.mode == WMH_MODE_AUTO || o.mode == WMH_MODE_BATCHED) &&
+                            plan_batched(ctx, k, stats.min_green, o, &plan);
+    if (o.mode == WMH_MODE_BATCHED && !batched_ok)
         return fail(ctx, WMH_E_ARG, "no batched plan fits for D=%u with these options", ctx->dims);
+    const bool index_ready = ctx->index.valid && ctx->index.seed == seed && ctx->index.k == k &&
+                             ctx->index.epoch == ctx->bounds_epoch;
+    const Path path = choose_path(ctx, o.mode, batched_ok, index_ready, k, n_rows, nnz, stats);
+    const bool batched = path == Path::kBatched;
+
+    if (path == Path::kIndexed) {
+        if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[0], s));
+        const wmh_status st = ensure_index(ctx, &ctx->index, seed, k, s);
+        if (st != WMH_OK) return st;
+        if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[1], s));
+        const uint32_t grid = (uint32_t)ctx->cu_count * (uint32_t)index_rows_blocks_per_cu(k);
+        WMH_HIP(ctx, launch_index_rows(rows, ctx->index.buf, ctx->dims, k, sig, grid, s));
+        if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[2], s));
+        WMH_HIP(ctx, hipEventRecord(ctx->index.used, s));
+        ctx->profiled = profile;
+        ctx->profiled_stream = profile && !index_ready;
+        ctx->last_mode = WMH_MODE_INDEXED;
+        if (o.sync) WMH_HIP(ctx, hipStreamSynchronize(s));
+        return WMH_OK;
+    }
 
     if (!batched) {
         const bool narrow = ctx->max_bound <= 0xFFFFu;
@@ -493,7 +620,15 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         }
         ctx->profiled = profile;
     }
+    ctx->last_mode = batched ? WMH_MODE_BATCHED : WMH_MODE_PLAIN;
     if (o.sync) WMH_HIP(ctx, hipStreamSynchronize(s));
+    return WMH_OK;
+}
+
+wmh_status wmh_last_mode(const wmh_ctx *ctx, int32_t *mode)
+{
+    if (!ctx || !mode) return WMH_E_ARG;
+    *mode = ctx->last_mode;
     return WMH_OK;
 }
 

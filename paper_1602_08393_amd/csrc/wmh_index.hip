@@ -1,0 +1,304 @@
+// The component index: the capped position sequence filed by component, an exact second
+// evaluation order of the hash for sparse green regions.
+//
+// Hash j of x is the first step t <= 65534 whose position is green for x, else 65535
+// (Algorithm 3, Definition 1, with the walk capped).  A position is green exactly when it falls
+// in a piece c with x_c > 0 and its offset inside the piece is below x_c (Sec. 3.1).  Filing
+// every draw (j, t <= 65534) under its component c as the key (offset << 32) | (t << 16) | j,
+// hash j of x is the smallest t over the keys of x's nonzero components whose offset is below
+// x_c, and 65535 when there is none.  The keys of a component are sorted in chunks of
+// kChunk, so a row reads only the green keys of its pieces plus one key per chunk: the work
+// per row is about nnz + k * 65534 * s (s = sum(x) / M) instead of the walk's
+// k * min(1/s, 65535), which wins by orders of magnitude when s is small (Theorem 2 gives the
+// walk's 1/s; Sec. 4 discusses the small-s regime).  Both orders compute the same values.
+//
+// Build, once per (bounds, seed, k): count draws per component, exclusive scan, draw again and
+// scatter the keys, sort each chunk (a wavefront per list of at most 64 keys, a workgroup in
+// LDS for longer chunks).  The order in which draws land in a list varies between builds, so
+// which keys share a chunk of a list longer than kChunk may vary too: that changes the cost of
+// reading the list, never a hash value.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "wmh_internal.h"
+
+namespace wmh {
+
+namespace {
+
+constexpr uint32_t kIndexPairs = (kCap - 1u) / 2u;  // pairs of steps (1,2) ... (65533,65534)
+constexpr uint32_t kChunk = 4096;                   // keys sorted together (32 KB of LDS)
+constexpr uint32_t kScanBlock = 1024;
+
+__device__ __forceinline__ uint32_t lane() { return threadIdx.x & (kWave - 1u); }
+
+__device__ __forceinline__ uint32_t wave_index()
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+}
+
+// Every lane's LDS operations before this point are visible to the wave's later ones (LDS
+// executes one wavefront's instructions in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Pass 1 and pass 2 of the build: one thread per (j, pair of steps).  Pass 1 counts the draws
+// of each component; pass 2 claims a slot in the component's list and writes the key.
+template <bool kScatter>
+__global__ __launch_bounds__(256) void index_draw_kernel(Bounds b, uint64_t seed, uint32_t k,
+                                                         uint32_t *__restrict__ counter,
+                                                         uint64_t *__restrict__ entries)
+{
+    const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (uint64_t)kIndexPairs * k) return;
+    const uint32_t j = (uint32_t)(idx / kIndexPairs);
+    const uint32_t pair = (uint32_t)(idx - (uint64_t)j * kIndexPairs);
+    uint64_t p[2];
+    position_pair(seed, j, pair, b.total, b.threshold, &p[0], &p[1]);
+#pragma unroll
+    for (uint32_t h = 0; h < 2; ++h) {
+        uint64_t off;
+        const uint32_t c = component_of(p[h], b.prefix, b.bucket, b.shift, &off);
+        const uint32_t at = atomicAdd(&counter[c], 1u);
+        if (kScatter) {
+            const uint32_t t = 2u * pair + h + 1u;
+            entries[at] = (off << 32) | ((uint64_t)t << 16) | j;
+        }
+    }
+}
+
+// Exclusive scan of n counts: per-block scans, then the block sums, then the carry added.
+__global__ __launch_bounds__(kScanBlock) void scan_blocks_kernel(const uint32_t *__restrict__ in,
+                                                                 uint32_t *__restrict__ out,
+                                                                 uint32_t *__restrict__ block_sums,
+                                                                 uint64_t n)
+{
+    __shared__ uint32_t s[kScanBlock];
+    const uint64_t i = (uint64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    const uint32_t v = i < n ? in[i] : 0u;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (uint32_t d = 1; d < kScanBlock; d <<= 1) {
+        const uint32_t add = threadIdx.x >= d ? s[threadIdx.x - d] : 0u;
+        __syncthreads();
+        s[threadIdx.x] += add;
+        __syncthreads();
+    }
+    if (i < n) out[i] = s[threadIdx.x] - v;
+    if (threadIdx.x == kScanBlock - 1) block_sums[blockIdx.x] = s[threadIdx.x];
+}
+
+// One workgroup: exclusive scan of the block sums in place, chunk by chunk.
+__global__ __launch_bounds__(kScanBlock) void scan_sums_kernel(uint32_t *__restrict__ sums,
+                                                               uint32_t n_blocks)
+{
+    __shared__ uint32_t s[kScanBlock];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < n_blocks; base += kScanBlock) {
+        const uint32_t i = base + threadIdx.x;
+        const uint32_t v = i < n_blocks ? sums[i] : 0u;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (uint32_t d = 1; d < kScanBlock; d <<= 1) {
+            const uint32_t add = threadIdx.x >= d ? s[threadIdx.x - d] : 0u;
+            __syncthreads();
+            s[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (i < n_blocks) sums[i] = carry + s[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == kScanBlock - 1) carry += s[threadIdx.x];
+        __syncthreads();
+    }
+}
+
+// offsets[i] += block carry; cursor[i] = offsets[i] (the scatter pass's claim counters).
+__global__ __launch_bounds__(256) void scan_add_kernel(uint32_t *__restrict__ offsets,
+                                                       uint32_t *__restrict__ cursor,
+                                                       const uint32_t *__restrict__ block_sums,
+                                                       uint64_t n)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t v = offsets[i] + block_sums[i / kScanBlock];
+    offsets[i] = v;
+    cursor[i] = v;
+}
+
+__device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
+__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a < b ? b : a; }
+
+// Lists of 2..64 keys: one wavefront per list, bitonic sort across lanes (pads are ~0).
+__global__ __launch_bounds__(256) void sort_small_kernel(const uint32_t *__restrict__ offsets,
+                                                         uint32_t dims,
+                                                         uint64_t *__restrict__ entries)
+{
+    const uint32_t waves = blockDim.x / kWave;
+    const uint32_t ln = lane();
+    for (uint32_t c = blockIdx.x * waves + wave_index(); c < dims; c += gridDim.x * waves) {
+        const uint32_t a = offsets[c];
+        const uint32_t n = offsets[c + 1] - a;
+        if (n < 2 || n > kWave) continue;  // uniform across the wavefront
+        uint64_t v = ln < n ? entries[a + ln] : ~0ull;
+#pragma unroll
+        for (uint32_t size = 2; size <= kWave; size <<= 1) {
+#pragma unroll
+            for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+                const uint64_t o = __shfl_xor(v, (int)stride);
+                const bool ascending = (ln & size) == 0;
+                const bool lower = (ln & stride) == 0;
+                v = lower == ascending ? umin64(v, o) : umax64(v, o);
+            }
+        }
+        if (ln < n) entries[a + ln] = v;
+    }
+}
+
+// Lists of more than 64 keys: one workgroup per list, each chunk of kChunk keys sorted in LDS.
+__global__ __launch_bounds__(256) void sort_chunks_kernel(const uint32_t *__restrict__ offsets,
+                                                          uint32_t dims,
+                                                          uint64_t *__restrict__ entries)
+{
+    __shared__ uint64_t s[kChunk];
+    for (uint32_t c = blockIdx.x; c < dims; c += gridDim.x) {
+        const uint32_t a = offsets[c], z = offsets[c + 1];
+        if (z - a <= kWave) continue;  // uniform across the workgroup
+        for (uint32_t base = a; base < z; base += kChunk) {
+            const uint32_t n = std::min(z - base, kChunk);
+            uint32_t size = 2;
+            while (size < n) size <<= 1;
+            for (uint32_t i = threadIdx.x; i < size; i += blockDim.x)
+                s[i] = i < n ? entries[base + i] : ~0ull;
+            __syncthreads();
+            for (uint32_t span = 2; span <= size; span <<= 1) {
+                for (uint32_t stride = span >> 1; stride > 0; stride >>= 1) {
+                    for (uint32_t i = threadIdx.x; i < size; i += blockDim.x) {
+                        const uint32_t partner = i ^ stride;
+                        if (partner > i) {
+                            const bool ascending = (i & span) == 0;
+                            const uint64_t x = s[i], y = s[partner];
+                            if ((x > y) == ascending) {
+                                s[i] = y;
+                                s[partner] = x;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) entries[base + i] = s[i];
+            __syncthreads();
+        }
+    }
+}
+
+// Hashes of rows from the index: one wavefront per row, the running minimum of each hash id in
+// LDS.  A lane takes one nonzero (c, x_c) at a time and reads c's keys chunk by chunk up to the
+// first offset >= x_c.
+__global__ __launch_bounds__(256) void index_rows_kernel(Rows rows,
+                                                         const uint32_t *__restrict__ offsets,
+                                                         const uint64_t *__restrict__ entries,
+                                                         uint32_t dims, uint32_t k,
+                                                         uint16_t *__restrict__ sig)
+{
+    extern __shared__ uint32_t lds[];
+    const uint32_t waves = blockDim.x / kWave;
+    const uint32_t wave = wave_index();
+    const uint32_t ln = lane();
+    uint32_t *hmin = lds + (size_t)wave * k;
+    for (uint64_t row = (uint64_t)blockIdx.x * waves + wave; row < rows.n_rows;
+         row += (uint64_t)gridDim.x * waves) {
+        for (uint32_t j = ln; j < k; j += kWave) hmin[j] = kCap;
+        wave_lds_fence();
+        const uint64_t lo = rows.row_ptr[row], hi = rows.row_ptr[row + 1];
+        bool green = false;
+        for (uint64_t e = lo + ln; e < hi; e += kWave) {
+            const uint32_t c = rows.col[e];
+            const uint32_t x = rows.val[e];
+            if (x == 0 || c >= dims) continue;
+            green = true;
+            const uint32_t a = offsets[c], z = offsets[c + 1];
+            for (uint32_t base = a; base < z; base += kChunk) {
+                const uint32_t end = std::min(z, base + kChunk);
+                for (uint32_t i = base; i < end; ++i) {
+                    const uint64_t key = entries[i];
+                    if ((uint32_t)(key >> 32) >= x) break;
+                    atomicMin(&hmin[(uint32_t)key & 0xFFFFu], ((uint32_t)key) >> 16);
+                }
+            }
+        }
+        const bool live = __ballot(green) != 0;
+        wave_lds_fence();
+        uint16_t *out = sig + row * (uint64_t)k;
+        for (uint32_t j = ln; j < k; j += kWave) out[j] = live ? (uint16_t)hmin[j] : (uint16_t)0;
+        wave_lds_fence();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_index_build(const Bounds &b, uint64_t seed, uint32_t k, const IndexBuffers &ix,
+                              hipStream_t stream)
+{
+    const uint64_t D = b.dims;
+    const uint64_t n_scan = D + 1;  // offsets[D] is the total
+    const uint32_t n_blocks = (uint32_t)((n_scan + kScanBlock - 1) / kScanBlock);
+    hipError_t e = launch_fill_u32(ix.cursor, 0u, n_scan, stream);
+    if (e != hipSuccess) return e;
+    const uint64_t threads = (uint64_t)kIndexPairs * k;
+    const uint32_t grid = (uint32_t)((threads + 255) / 256);
+    index_draw_kernel<false><<<grid, 256, 0, stream>>>(b, seed, k, ix.cursor, nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    scan_blocks_kernel<<<n_blocks, kScanBlock, 0, stream>>>(ix.cursor, ix.offsets, ix.block_sums,
+                                                          n_scan);
+    scan_sums_kernel<<<1, kScanBlock, 0, stream>>>(ix.block_sums, n_blocks);
+    scan_add_kernel<<<(uint32_t)((n_scan + 255) / 256), 256, 0, stream>>>(ix.offsets, ix.cursor,
+                                                                         ix.block_sums, n_scan);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    index_draw_kernel<true><<<grid, 256, 0, stream>>>(b, seed, k, ix.cursor, ix.entries);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const uint32_t sort_grid = (uint32_t)std::min<uint64_t>((D + 3) / 4, 16384);
+    sort_small_kernel<<<sort_grid, 256, 0, stream>>>(ix.offsets, (uint32_t)D, ix.entries);
+    sort_chunks_kernel<<<(uint32_t)std::min<uint64_t>(D, 4096), 256, 0, stream>>>(
+        ix.offsets, (uint32_t)D, ix.entries);
+    return hipGetLastError();
+}
+
+namespace {
+
+uint32_t index_rows_waves(uint32_t k) { return k <= 2048 ? 4u : 1u; }
+
+size_t index_rows_lds_bytes(uint32_t k) { return (size_t)index_rows_waves(k) * k * sizeof(uint32_t); }
+
+}  // namespace
+
+int index_rows_blocks_per_cu(uint32_t k)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, index_rows_kernel, index_rows_waves(k) * kWave,
+                                                     index_rows_lds_bytes(k)) != hipSuccess)
+        return 1;
+    return std::max(1, n);
+}
+
+hipError_t launch_index_rows(const Rows &rows, const IndexBuffers &ix, uint32_t dims, uint32_t k,
+                             uint16_t *sig, uint32_t grid, hipStream_t stream)
+{
+    if (rows.n_rows == 0) return hipSuccess;
+    const uint32_t waves = index_rows_waves(k);
+    const uint64_t need = (rows.n_rows + waves - 1) / waves;
+    const uint32_t g = (uint32_t)std::min<uint64_t>(need, grid);
+    index_rows_kernel<<<g, waves * kWave, index_rows_lds_bytes(k), stream>>>(rows, ix.offsets,
+                                                                            ix.entries, dims, k, sig);
+    return hipGetLastError();
+}
+
+}  // namespace wmh

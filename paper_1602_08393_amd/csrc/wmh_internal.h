@@ -22,6 +22,8 @@ struct CheckWords {
     unsigned long long first_error;  // (row << 4) | code, minimum over rows; ~0 when valid
     unsigned long long min_green;    // smallest sum(x) over non-empty rows; ~0 if none
     unsigned long long n_empty;      // rows with sum(x) == 0
+    unsigned long long walk_steps;   // sum over non-empty rows of min(M / sum(x), 65535)
+    unsigned long long index_keys;   // sum over non-empty rows of ceil(65534 * sum(x) / M)
 };
 
 struct Rows {
@@ -53,7 +55,8 @@ struct BatchedPlan {
 
 inline size_t stream_entry_bytes(bool packed) { return packed ? 4 : 8; }
 
-hipError_t launch_validate(const Rows &rows, const uint32_t *bound, uint32_t dims,
+// Checks the rows and gathers the statistics of CheckWords (M = total, for the cost estimates).
+hipError_t launch_validate(const Rows &rows, const uint32_t *bound, uint32_t dims, uint64_t total,
                            CheckWords *words, hipStream_t stream);
 
 hipError_t launch_plain(const Bounds &b, const Rows &rows, uint64_t row_begin,
@@ -85,5 +88,30 @@ hipError_t launch_collisions(const uint16_t *A, uint64_t na, const uint16_t *B, 
                              uint32_t k, uint32_t *counts, hipStream_t stream);
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t stream);
+
+// Component index of the capped sequence (wmh_index.hip).  entries: k * 65534 keys
+// (offset << 32) | (t << 16) | j grouped by component; offsets: D + 1 list starts; cursor:
+// D + 1 counters; block_sums: ceil((D + 1) / 1024) scan carries.
+struct IndexBuffers {
+    uint64_t *entries = nullptr;
+    uint32_t *offsets = nullptr;
+    uint32_t *cursor = nullptr;
+    uint32_t *block_sums = nullptr;
+};
+
+constexpr uint32_t kIndexSteps = 65534u;  // steps 1 .. cap - 1 decide every capped hash value
+constexpr uint32_t kIndexMaxK = 8192u;    // j fits the key's 16 bits; LDS of the row kernel
+
+inline uint64_t index_entry_count(uint32_t k) { return (uint64_t)k * kIndexSteps; }
+inline uint64_t index_scan_blocks(uint32_t dims) { return ((uint64_t)dims + 1 + 1023) / 1024; }
+
+hipError_t launch_index_build(const Bounds &b, uint64_t seed, uint32_t k, const IndexBuffers &ix,
+                              hipStream_t stream);
+
+hipError_t launch_index_rows(const Rows &rows, const IndexBuffers &ix, uint32_t dims, uint32_t k,
+                             uint16_t *sig, uint32_t grid, hipStream_t stream);
+
+// Resident workgroups per CU of the index row kernel.
+int index_rows_blocks_per_cu(uint32_t k);
 
 }  // namespace wmh

@@ -53,15 +53,17 @@ __device__ __forceinline__ uint64_t wave_min(uint64_t v)
 // Validation: one wavefront per row, grid-stride over rows.
 // ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void validate_kernel(Rows rows, const uint32_t *__restrict__ bound,
-                                                       uint32_t dims, CheckWords *words)
+                                                       uint32_t dims, uint64_t total,
+                                                       CheckWords *words)
 {
     // per-workgroup partials, so each word gets at most one global atomic per workgroup
     __shared__ unsigned long long part_err[256 / kWave], part_green[256 / kWave],
-        part_empty[256 / kWave];
+        part_empty[256 / kWave], part_walk[256 / kWave], part_keys[256 / kWave];
     const uint32_t waves = blockDim.x / kWave;
     const uint64_t first = (uint64_t)blockIdx.x * waves + wave_index();
     const uint64_t stride = (uint64_t)gridDim.x * waves;
     uint64_t w_err = ~0ull, w_green = ~0ull, w_empty = 0;  // this wave's partials (uniform)
+    uint64_t w_walk = 0, w_keys = 0;  // cost statistics: expected walk steps, green index keys
     for (uint64_t r = first; r < rows.n_rows; r += stride) {
         const uint64_t lo = rows.row_ptr[r];
         const uint64_t hi = rows.row_ptr[r + 1];
@@ -101,25 +103,36 @@ __global__ __launch_bounds__(256) void validate_kernel(Rows rows, const uint32_t
         sum = wave_sum(sum);
         if (bad != ~0ull) w_err = min(w_err, (unsigned long long)((r << 4) | (bad & 15u)));
         else if (sum == 0) ++w_empty;
-        else w_green = min(w_green, (unsigned long long)sum);
+        else {
+            w_green = min(w_green, (unsigned long long)sum);
+            // mean capped step count ~ min(1/s, cap) (Theorem 2); green keys ~ 65534 * s
+            w_walk += min(total / sum, (uint64_t)kCap);
+            w_keys += (uint64_t)ceil(65534.0 * ((double)sum / (double)total));
+        }
     }
     const uint32_t wave = wave_index();
     if (lane() == 0) {
         part_err[wave] = w_err;
         part_green[wave] = w_green;
         part_empty[wave] = w_empty;
+        part_walk[wave] = w_walk;
+        part_keys[wave] = w_keys;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long e = ~0ull, g = ~0ull, n = 0;
+        unsigned long long e = ~0ull, g = ~0ull, n = 0, wk = 0, ky = 0;
         for (uint32_t w = 0; w < waves; ++w) {
             e = min(e, part_err[w]);
             g = min(g, part_green[w]);
             n += part_empty[w];
+            wk += part_walk[w];
+            ky += part_keys[w];
         }
         if (e != ~0ull) atomicMin(&words->first_error, e);
         if (g != ~0ull) atomicMin(&words->min_green, g);
         if (n) atomicAdd(&words->n_empty, n);
+        if (wk) atomicAdd(&words->walk_steps, wk);
+        if (ky) atomicAdd(&words->index_keys, ky);
     }
 }
 
@@ -538,13 +551,13 @@ __global__ __launch_bounds__(256) void estimate_kernel(const uint16_t *__restric
 // Launchers
 // ---------------------------------------------------------------------------------------------
 
-hipError_t launch_validate(const Rows &rows, const uint32_t *bound, uint32_t dims,
+hipError_t launch_validate(const Rows &rows, const uint32_t *bound, uint32_t dims, uint64_t total,
                            CheckWords *words, hipStream_t stream)
 {
     if (rows.n_rows == 0) return hipSuccess;
     const uint64_t waves_needed = rows.n_rows;
     const uint32_t grid = (uint32_t)std::min<uint64_t>((waves_needed + 3) / 4, 2048);
-    validate_kernel<<<grid, 256, 0, stream>>>(rows, bound, dims, words);
+    validate_kernel<<<grid, 256, 0, stream>>>(rows, bound, dims, total, words);
     return hipGetLastError();
 }
 

@@ -44,6 +44,7 @@ struct Request {
     uint16_t *sig = nullptr;
     uint64_t arrival_ns = 0, admit_ns = 0, done_ns = 0;
     uint64_t bytes = 0;
+    RowStats stats;  // from the host check, for the planner
     bool done = false;
     wmh_status status = WMH_OK;
 };
@@ -84,6 +85,9 @@ struct wmh_server {
     BatchedPlan plan{};
     uint32_t grid = 0;
     void *d_stream = nullptr;
+    // component index for requests whose green fraction is small (built on first use)
+    OwnedIndex index;
+    uint32_t index_grid = 0;
     // queue and bookkeeping (guarded by mu)
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -132,7 +136,20 @@ wmh_status wmh_server::launch(Slot &slot, Request &r)
         e = hipMemcpyAsync(slot.d_val, r.val, r.nnz * sizeof(uint32_t), hipMemcpyHostToDevice, s);
     const Rows rows{slot.d_row_ptr, slot.d_col, slot.d_val, r.n_rows, r.nnz};
     const Bounds b = bounds_view(ctx);
-    if (e == hipSuccess) {
+    // the index is built once per loop, so its cost is left out of the comparison
+    const Path path = choose_path(ctx, cfg.mode, batched, true, k, r.n_rows, r.nnz, r.stats);
+    if (e == hipSuccess && path == Path::kIndexed) {
+        if (!index.valid) {
+            // the worker is the only builder; the first indexed request waits for the build so
+            // that requests on the other slots' streams find it complete
+            const wmh_status st = ensure_index(ctx, &index, cfg.seed, k, s, false);
+            if (st != WMH_OK) return st;
+            e = hipStreamSynchronize(s);
+        }
+        if (e == hipSuccess)
+            e = launch_index_rows(rows, index.buf, ctx->dims, k, slot.d_sig, index_grid, s);
+        if (e == hipSuccess) e = hipEventRecord(index.used, s);
+    } else if (e == hipSuccess) {
         if (batched) {
             e = launch_fill_u32(slot.d_tile_counter, 0u, 1, s);
             if (e == hipSuccess)
@@ -236,8 +253,10 @@ wmh_status wmh_server_create(wmh_ctx *ctx, const wmh_server_config *cfg_in, wmh_
     if (cfg.slots == 0) cfg.slots = 4;
     if (cfg.slots > 64) return fail(ctx, WMH_E_ARG, "slots must be in [1, 64]");
     if (cfg.mem_budget == 0) cfg.mem_budget = 4ull << 30;
-    if (cfg.mode < WMH_MODE_AUTO || cfg.mode > WMH_MODE_BATCHED)
+    if (cfg.mode < WMH_MODE_AUTO || cfg.mode > WMH_MODE_INDEXED)
         return fail(ctx, WMH_E_ARG, "unknown mode %d", cfg.mode);
+    if (cfg.mode == WMH_MODE_INDEXED && !index_fits(cfg.k))
+        return fail(ctx, WMH_E_ARG, "the component index needs k <= %u", kIndexMaxK);
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, WMH_E_DEVICE, "hipSetDevice");
 
     wmh_server *srv = new (std::nothrow) wmh_server();
@@ -247,7 +266,9 @@ wmh_status wmh_server_create(wmh_ctx *ctx, const wmh_server_config *cfg_in, wmh_
     wmh_opts o;
     wmh_opts_init(&o);
     o.stream_depth = cfg.stream_depth ? cfg.stream_depth : 8192;
-    srv->batched = cfg.mode != WMH_MODE_PLAIN && plan_batched(ctx, cfg.k, ~0ull, o, &srv->plan);
+    srv->batched = (cfg.mode == WMH_MODE_AUTO || cfg.mode == WMH_MODE_BATCHED) &&
+                   plan_batched(ctx, cfg.k, ~0ull, o, &srv->plan);
+    srv->index_grid = (uint32_t)ctx->cu_count * (uint32_t)index_rows_blocks_per_cu(cfg.k);
     if (cfg.mode == WMH_MODE_BATCHED && !srv->batched) {
         delete srv;
         return fail(ctx, WMH_E_ARG, "no batched plan fits for D=%u", ctx->dims);
@@ -288,7 +309,8 @@ wmh_status wmh_server_submit(wmh_server *srv, const uint64_t *row_ptr, const uin
     wmh_ctx *ctx = srv->ctx;
     if (!row_ptr || (n_rows && !sig) || (nnz && (!col || !val)))
         return fail(ctx, WMH_E_ARG, "null buffer");
-    const wmh_status st = check_rows_host(ctx, row_ptr, col, val, n_rows, nnz, nullptr);
+    RowStats stats;
+    const wmh_status st = check_rows_host(ctx, row_ptr, col, val, n_rows, nnz, &stats);
     if (st != WMH_OK) return st;
     const uint64_t bytes = (n_rows + 1) * 8 + nnz * 8 + n_rows * (uint64_t)srv->cfg.k * 2;
     if (bytes > srv->cfg.mem_budget)
@@ -304,6 +326,7 @@ wmh_status wmh_server_submit(wmh_server *srv, const uint64_t *row_ptr, const uin
     r->sig = sig;
     r->arrival_ns = arrival_ns ? arrival_ns : steady_ns();
     r->bytes = bytes;
+    r->stats = stats;
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         r->id = srv->next_id++;
@@ -420,6 +443,7 @@ void wmh_server_destroy(wmh_server *srv)
         if (slot.stream) (void)hipStreamDestroy(slot.stream);
     }
     if (srv->d_stream) (void)hipFree(srv->d_stream);
+    free_index(&srv->index);
     for (auto &kv : srv->requests) delete kv.second;
     delete srv;
 }

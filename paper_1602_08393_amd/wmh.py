@@ -19,11 +19,12 @@ CAP = 65535
 STATUS = {0: "WMH_OK", -1: "WMH_E_ARG", -2: "WMH_E_NO_BOUNDS", -3: "WMH_E_COL_RANGE",
           -4: "WMH_E_UNSORTED", -5: "WMH_E_BOUND", -6: "WMH_E_OVERFLOW", -7: "WMH_E_NOMEM",
           -8: "WMH_E_DEVICE", -9: "WMH_E_ROW_PTR"}
-MODES = {"auto": 0, "plain": 1, "batched": 2}
+MODES = {"auto": 0, "plain": 1, "batched": 2, "indexed": 3}
 
 EXPORTED = ["wmh_opts_init", "wmh_create", "wmh_destroy", "wmh_set_bounds", "wmh_hash",
             "wmh_estimate", "wmh_collisions", "wmh_bounds_info", "wmh_bounds_tables",
-            "wmh_draws", "wmh_last_kernel_ms", "wmh_last_error", "wmh_status_string",
+            "wmh_draws", "wmh_last_kernel_ms", "wmh_last_mode", "wmh_last_error",
+            "wmh_status_string",
             "wmh_server_create", "wmh_server_submit", "wmh_server_poll", "wmh_server_wait",
             "wmh_server_drain", "wmh_server_stats", "wmh_server_now_ns", "wmh_server_destroy"]
 
@@ -96,6 +97,8 @@ def load() -> ctypes.CDLL:
     L.wmh_last_kernel_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_float),
                                      ctypes.POINTER(ctypes.c_float)]
     L.wmh_last_kernel_ms.restype = ctypes.c_int
+    L.wmh_last_mode.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.wmh_last_mode.restype = ctypes.c_int
     L.wmh_draws.argtypes = [vp, u64, u32, u32, u32, vp, vp, vp, vp]
     L.wmh_draws.restype = ctypes.c_int
     L.wmh_server_create.argtypes = [vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
@@ -254,6 +257,12 @@ class Context:
         self._check(self._lib.wmh_last_kernel_ms(self._ptr, ctypes.byref(w), ctypes.byref(st)),
                     "wmh_last_kernel_ms")
         return w.value, st.value
+
+    def last_mode(self) -> str:
+        """Name of the path ("plain", "batched", "indexed") the last wmh_hash call took."""
+        m = ctypes.c_int32()
+        self._check(self._lib.wmh_last_mode(self._ptr, ctypes.byref(m)), "wmh_last_mode")
+        return {v: k for k, v in MODES.items()}[m.value]
 
     def hash_into(self, rows: DeviceRows, k: int, seed: int, sig, stream=None, opts=None):
         """Raw call: sig is a device int16 tensor of N*k elements."""

@@ -37,7 +37,8 @@ def _oracle_sig(ds, rows, k, seed):
     return oracle.hash_csr(sub.m, sub.row_ptr, sub.col, sub.val, k, seed=seed)
 
 
-@pytest.mark.parametrize("mode,slots", [("auto", 4), ("plain", 2), ("batched", 1)])
+@pytest.mark.parametrize("mode,slots", [("auto", 4), ("plain", 2), ("batched", 1),
+                                        ("indexed", 3)])
 def test_requests_match_oracle(ctx, corpus, mode, slots):
     k, seed = 48, 21
     print(f"  serving {mode} slots={slots}", flush=True)
@@ -134,7 +135,8 @@ def test_bad_requests_are_refused(ctx, corpus):
 
 
 def test_large_dimension_requests(ctx):
-    """D = 2^20 (dense rows do not fit in LDS): the loop runs the plain walk."""
+    """D = 2^20 (dense rows do not fit in LDS): the loop picks the plain walk or the component
+    index per request; both ways the bytes equal the oracle's."""
     D = 1 << 20
     rng = np.random.Generator(np.random.PCG64(9))
     cols, vals = [], []
