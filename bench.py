@@ -1,9 +1,13 @@
 """Benchmark: weighted minwise hashes/s at k=500 on the histogram-shaped workload
 (N=100000 rows, D=4096, each cell nonzero with probability 0.3, LogNormal(0,1) weights in Q8.8),
-batched persistent launch vs plain one-launch-per-8192-rows, on one GPU.
+batched persistent launch (autotuned plan, hipGraph replay) vs plain one-launch-per-8192-rows,
+on one GPU.
 
 A step is one wmh_hash call over the whole batch (validation, shared position stream, walk),
-with the rows already resident in HBM.  Prints one JSON line.
+with the rows already resident in HBM.  Prints one JSON line.  Beside the headline the line
+carries the heavy-tail workload (batched vs plain, and the 10^4 x 10^4 all-pairs collision
+counts), a row subset of the text-like workload on the component index, and the serving loop's
+p50/p99 latency on the D = 2^20 corpus (skip them with --no-extras).
 """
 from __future__ import annotations
 
@@ -48,9 +52,15 @@ def parse():
                     help="only run device-to-device copies of BYTES (scales HBM counters)")
     ap.add_argument("--serve", action="store_true",
                     help="only run the serving workload (corpus of config 5, k=256)")
-    ap.add_argument("--serve-requests", type=int, default=64,
+    ap.add_argument("--serve-requests", type=int, default=48,
                     help="open-loop requests per load level")
-    ap.add_argument("--serve-corpus-rows", type=int, default=100_000)
+    ap.add_argument("--serve-corpus-rows", type=int, default=20_000)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline workload")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (planner default plan)")
+    ap.add_argument("--text-rows", type=int, default=100_000,
+                    help="rows of the text-like workload generated for its line")
     ap.add_argument("--serve-max-rows", type=int, default=4096)
     ap.add_argument("--serve-slots", type=int, default=4)
     return ap.parse_args()
@@ -141,6 +151,118 @@ def timed_steps(ctx, rows, k, sig, opts, steps, warmup, torch):
     return elapsed, walk, build
 
 
+def heavy_tail_bench(args, torch, synth, wmh) -> dict:
+    """Heavy-tail workload (N=200000, D=16384, 1% of bounds inflated 100x, k=500): batched
+    (autotuned) vs plain, then exact all-pairs collision counts of rows [0, 10^4) against
+    [10^4, 2*10^4)."""
+    t = time.perf_counter()
+    ds = synth.config4()
+    gen_s = time.perf_counter() - t
+    log(f"heavy-tail: N={ds.n_rows} D={ds.D} nnz={ds.nnz} ({gen_s:.1f}s)")
+    k = ds.k
+    ctx = wmh.Context(0)
+    ctx.set_bounds(ds.m)
+    rows = wmh.upload_dataset(ds, "cuda:0")
+    out = {"workload": "heavy-tail: N=200000, D=16384, nnz ~ U{20..2000}, weights U{1..2^24}, "
+                       "1% of dims with one outlier row at 100*2^24, bounds = dataset max, "
+                       "k=500, seed 0",
+           "N": ds.n_rows, "D": ds.D, "k": k, "nnz": ds.nnz}
+    if not args.no_tune:
+        out["autotune"] = ctx.tune(rows, k, 0, reps=1)
+    sig_b = torch.empty((ds.n_rows, k), dtype=torch.int16, device="cuda:0")
+    sig_p = torch.empty_like(sig_b)
+    el_b, walk_b, _ = timed_steps(ctx, rows, k, sig_b, ctx.make_opts(mode="batched", profile=True),
+                                  3, 1, torch)
+    out["batched_plan"] = ctx.last_plan()
+    el_p, walk_p, _ = timed_steps(ctx, rows, k, sig_p, ctx.make_opts(mode="plain", profile=True),
+                                  2, 1, torch)
+    hashes = ds.n_rows * k
+    tests = int(wmh.sig_to_numpy(sig_b).astype(np.int64).sum())
+    out.update({"batched_hashes_per_s": hashes * 3 / el_b,
+                "batched_ms_per_step": el_b / 3 * 1e3,
+                "batched_walk_ms": float(np.mean(walk_b)),
+                "plain_hashes_per_s": hashes * 2 / el_p,
+                "plain_ms_per_step": el_p / 2 * 1e3,
+                "batched_over_plain": (hashes * 3 / el_b) / (hashes * 2 / el_p),
+                "batched_equals_plain": bool(torch.equal(sig_b, sig_p)),
+                "mean_steps_per_hash": tests / hashes,
+                "walk_frac_of_alu_peak": OPS_PER_TEST * tests / (np.mean(walk_b) / 1e3) / 1e12
+                / PEAK_INT_TOPS})
+    log(f"heavy-tail: batched {out['batched_ms_per_step']:.2f} ms/step, plain "
+        f"{out['plain_ms_per_step']:.2f} ms/step, equal {out['batched_equals_plain']}")
+    del sig_p
+    # all-pairs collision counts
+    A = sig_b[0:10000].contiguous()
+    B = sig_b[10000:20000].contiguous()
+    stream = torch.cuda.current_stream()
+    counts = ctx.collisions(A, B, stream=stream.cuda_stream)
+    times = []
+    for _ in range(3):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        counts = ctx.collisions(A, B, stream=stream.cuda_stream)
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    rng = np.random.Generator(np.random.PCG64(77))
+    a_idx = rng.integers(0, 10000, 2000)
+    b_idx = rng.integers(0, 10000, 2000)
+    An = wmh.sig_to_numpy(A)
+    Bn = wmh.sig_to_numpy(B)
+    Cn = counts.cpu().numpy().view(np.uint32)
+    exact = bool(np.all((An[a_idx] == Bn[b_idx]).sum(axis=1) == Cn[a_idx, b_idx]))
+    ms = float(np.median(times))
+    out["collisions"] = {"pairs": 10000 * 10000, "k": k, "ms": ms,
+                         "pairs_per_s": 1e8 / (ms / 1e3),
+                         "compares_per_s": 1e8 * k / (ms / 1e3),
+                         "sampled_pairs_exact": exact, "sampled_pairs": len(a_idx)}
+    log(f"heavy-tail: all-pairs collisions {ms:.2f} ms, sample exact {exact}")
+    ctx.close()
+    return out
+
+
+def text_like_bench(args, torch, synth, wmh) -> dict:
+    """Rows of the text-like workload (D=65536, tf weights, k=1000), where s is so small that
+    the planner takes the component index; the first rows are checked against the plain walk
+    on the GPU."""
+    t = time.perf_counter()
+    ds = synth.config3(n_rows=args.text_rows, block=20_000)
+    gen_s = time.perf_counter() - t
+    log(f"text-like: N={ds.n_rows} D={ds.D} nnz={ds.nnz} ({gen_s:.1f}s)")
+    k = ds.k
+    ctx = wmh.Context(0)
+    ctx.set_bounds(ds.m)
+    rows = wmh.upload_dataset(ds, "cuda:0")
+    sig = torch.empty((ds.n_rows, k), dtype=torch.int16, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    opts = ctx.make_opts(mode="auto", profile=True)
+    ctx.hash_into(rows, k, 0, sig, stream=stream.cuda_stream, opts=opts)
+    first_rows_ms, build_ms = ctx.last_kernel_ms()
+    mode = ctx.last_mode()
+    el, walk, _ = timed_steps(ctx, rows, k, sig, opts, 3, 0, torch)
+    sig_np = wmh.sig_to_numpy(sig)
+    head = ds.head(48)
+    walk_sig = wmh.sig_to_numpy(ctx.hash(wmh.upload_dataset(head, "cuda:0"), k, seed=0,
+                                         mode="plain"))
+    hashes = ds.n_rows * k
+    capped = float((sig_np == 65535).mean())
+    out = {"workload": f"text-like: first {ds.n_rows} rows of the N=1e6 generator (bounds = "
+                       "max over these rows), D=65536, nnz = clamp(Zipf(1.2), 10, 5000) draws, "
+                       "tf weights 1+ln(Zipf(1.5)) Q16.16, k=1000, seed 0",
+           "N": ds.n_rows, "D": ds.D, "k": k, "nnz": ds.nnz, "mode": mode,
+           "hashes_per_s": hashes * 3 / el, "ms_per_step": el / 3 * 1e3,
+           "rows_kernel_ms": float(np.mean(walk)), "index_build_ms": build_ms,
+           "first_call_rows_kernel_ms": first_rows_ms,
+           "walk_steps_equivalent": int(sig_np.astype(np.int64).sum()),
+           "capped_fraction": capped,
+           "head_equals_plain_walk": bool(np.array_equal(sig_np[:48], walk_sig))}
+    log(f"text-like: {mode} {out['ms_per_step']:.2f} ms/step, index build {build_ms:.2f} ms, "
+        f"head equals walk {out['head_equals_plain_walk']}")
+    ctx.close()
+    return out
+
+
 def cpu_baseline(ds, k, target_s):
     import oracle
     threads = min(16, os.cpu_count() or 1)
@@ -197,10 +319,18 @@ def main():
     plan = dict(rows_per_block=args.rows_per_block, hashes_per_tile=args.hashes_per_tile,
                 stream_depth=args.stream_depth, waves_per_block=args.waves_per_block)
     result = {}
+    tune = None
+    if args.only in ("batched", "both") and not args.no_tune and not any(plan.values()):
+        log("batched: autotuning the tile plan")
+        tune = ctx.tune(rows, k, 0, reps=2)
+        log(f"batched: tuned R={tune['rows_per_block']} J={tune['hashes_per_tile']} "
+            f"W={tune['waves_per_block']}: {tune['best_ms']:.3f} ms vs default "
+            f"{tune['default_ms']:.3f} ms over {tune['candidates']} plans")
     if args.only in ("batched", "both"):
         opts = ctx.make_opts(mode="batched", profile=True, **plan)
         log("batched: warmup + timed steps (hipGraph replay)")
         el, graph_ms, _ = timed_steps(ctx, rows, k, sig, opts, args.steps, args.warmup, torch)
+        batched_plan = ctx.last_plan()
         # the same kernels launched directly, with events between them on the launch stream,
         # to time the walk kernel alone
         dopts = ctx.make_opts(mode="batched", profile=True, use_graph=False, **plan)
@@ -262,14 +392,25 @@ def main():
         bel, bwalk, bbuild, bgraph = result["batched"]
         line["batched_detail"] = {"graph_ms": float(np.mean(bgraph)),
                                   "walk_ms": float(np.mean(bwalk)),
-                                  "stream_build_ms": float(np.mean(bbuild))}
+                                  "stream_build_ms": float(np.mean(bbuild)),
+                                  "plan": batched_plan}
+    if tune is not None:
+        line["autotune"] = tune
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a sample")
         cb, want = cpu_baseline(ds, k, args.cpu_seconds)
         line["cpu_baseline"] = cb
         line["sample_bit_exact"] = bool(np.array_equal(sig_np[: want.shape[0]], want))
-    print(json.dumps(line), flush=True)
     ctx.close()
+    if not args.no_extras and args.only == "both":
+        del rows, sig, sig_plain
+        torch.cuda.empty_cache()
+        line["heavy_tail"] = heavy_tail_bench(args, torch, synth, wmh)
+        torch.cuda.empty_cache()
+        line["text_like"] = text_like_bench(args, torch, synth, wmh)
+        torch.cuda.empty_cache()
+        line["serving"] = serve_bench(args)
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -207,6 +207,50 @@ wmh_status wmh_last_kernel_ms(wmh_ctx *ctx, float *walk_ms, float *stream_ms);
  */
 wmh_status wmh_last_mode(const wmh_ctx *ctx, int32_t *mode);
 
+/*
+ * wmh_last_plan -- the schedule of the last successful wmh_hash: plan->mode as wmh_last_mode,
+ * and for the batched path the tile plan it ran (rows_per_block, hashes_per_tile,
+ * stream_depth, waves_per_block; 0 for the other paths).  Other fields are the defaults.
+ * Errors: WMH_E_ARG (null).
+ */
+wmh_status wmh_last_plan(const wmh_ctx *ctx, wmh_opts *plan);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Autotuner of the batched tile plan (scheduling only: every plan gives the same bytes).      */
+/* ------------------------------------------------------------------------------------------ */
+
+typedef struct {
+    uint32_t rows_per_block;   /* R of the fastest plan */
+    uint32_t hashes_per_tile;  /* J */
+    uint32_t waves_per_block;  /* W */
+    uint32_t stream_depth;     /* the planner's shared-stream depth used for every candidate */
+    float best_ms;             /* device time of one wmh_hash call with that plan */
+    float default_ms;          /* the same with the planner's default plan */
+    uint32_t candidates;       /* plans timed */
+    int32_t steps_class;       /* floor(log2(mean capped steps per hash)) of the rows */
+    uint32_t reserved[4];
+} wmh_tune_result;
+
+/*
+ * wmh_tune -- times the batched walk on the given rows (device CSR as for wmh_hash) under
+ * candidate plans R in {1,2,4,8,16} x W in {4,8,16} x J in {min(k,1024), min(k,512),
+ * min(k,256)}, each the best of `reps` (0 = 3) calls after one untimed call, and keeps the
+ * fastest in the context under (D, value width, k, step class).  Later wmh_hash calls in the
+ * batched or auto mode whose rows fall in the same key and whose plan options are 0 run that
+ * plan.  sig (device, N*k uint16) receives the signatures.  Synchronous.
+ * Errors: as wmh_hash, plus WMH_E_ARG when no batched plan fits.
+ */
+wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
+                    const uint32_t *val, uint64_t n_rows, uint64_t nnz, uint32_t k, uint64_t seed,
+                    uint16_t *sig, void *stream, uint32_t reps, wmh_tune_result *out);
+
+/* Writes the context's tuned plans to a text file (one line per key).  Errors: WMH_E_ARG. */
+wmh_status wmh_tune_save(wmh_ctx *ctx, const char *path);
+
+/* Adds the plans of a file written by wmh_tune_save (replacing equal keys); nothing is added
+ * if any line is malformed.  Errors: WMH_E_ARG (missing or malformed file). */
+wmh_status wmh_tune_load(wmh_ctx *ctx, const char *path);
+
 /* ------------------------------------------------------------------------------------------ */
 /* Serving loop: continuous batching of hash requests on one device.                           */
 /* ------------------------------------------------------------------------------------------ */

@@ -35,6 +35,7 @@ struct GraphKey {
 // Row statistics gathered by the validation pass (device) or the host check, for the planner.
 struct RowStats {
     bool known = false;
+    uint64_t nonempty = 0;       // rows with sum(x) > 0
     uint64_t min_green = ~0ull;  // smallest sum(x) over non-empty rows
     uint64_t walk_steps = 0;     // sum over non-empty rows of min(M / sum(x), 65535)
     uint64_t index_keys = 0;     // sum over non-empty rows of ceil(65534 * sum(x) / M)
@@ -54,6 +55,25 @@ struct OwnedIndex {
 constexpr uint64_t kIndexBudgetBytes = 4ull << 30;  // index entries, at most 4 GiB
 
 enum class Path { kPlain, kBatched, kIndexed };
+
+// Autotuned batched plans, per (D, value width, k, step class); step class = floor(log2) of
+// the mean capped step count of the tuned rows.
+struct TuneKey {
+    uint32_t dims = 0;
+    bool narrow = false;
+    uint32_t k = 0;
+    int32_t steps_class = -1;
+    bool operator==(const TuneKey &o) const
+    {
+        return dims == o.dims && narrow == o.narrow && k == o.k && steps_class == o.steps_class;
+    }
+};
+
+struct TuneEntry {
+    TuneKey key;
+    uint32_t R = 0, J = 0, W = 0;
+    float ms = 0.f;
+};
 
 }  // namespace wmh
 
@@ -90,6 +110,8 @@ struct wmh_ctx {
     bool profiled_stream = false;
     wmh::OwnedIndex index;  // component index of the last indexed call
     int32_t last_mode = 0;  // path of the last successful wmh_hash (wmh_mode)
+    wmh::BatchedPlan last_plan{};  // its batched plan (when batched)
+    std::vector<wmh::TuneEntry> tuned;  // autotuner results
     int servers = 0;  // live serving loops using this context's bounds
     std::string last_error;
 };
@@ -99,9 +121,14 @@ namespace wmh {
 wmh_status fail(wmh_ctx *ctx, wmh_status st, const char *fmt, ...);
 wmh_status device_fail(wmh_ctx *ctx, hipError_t e, const char *what);
 Bounds bounds_view(const wmh_ctx *ctx);
-// Tile plan of the batched walk; false when no dense plan fits in LDS.
-bool plan_batched(const wmh_ctx *ctx, uint32_t k, uint64_t min_green, const wmh_opts &o,
-                  BatchedPlan *plan);
+// Tile plan of the batched walk; false when no dense plan fits in LDS.  Options left at 0
+// take the autotuned plan for (ctx, k, stats) when there is one and use_tuned is set.
+bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const wmh_opts &o,
+                  BatchedPlan *plan, bool use_tuned = true);
+TuneKey tune_key(const wmh_ctx *ctx, uint32_t k, const RowStats &stats);
+// Validation pass on the device: checks the rows (when check) and fills *stats; waits.
+wmh_status gather_stats(wmh_ctx *ctx, const Rows &rows, hipStream_t s, bool check,
+                        RowStats *stats);
 // Host-side check of CSR rows against the context's bounds (same rules as the device check);
 // fills *stats (may be NULL) like the device pass.
 wmh_status check_rows_host(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,

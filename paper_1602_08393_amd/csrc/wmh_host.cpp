@@ -43,6 +43,28 @@ wmh_status device_fail(wmh_ctx *ctx, hipError_t e, const char *what)
                 hipGetErrorString(e));
 }
 
+const char *check_name(uint32_t code)
+{
+    switch (code) {
+    case kCheckRowPtr: return "row_ptr decreasing or beyond nnz";
+    case kCheckColumn: return "column index >= D";
+    case kCheckUnsorted: return "columns not strictly increasing";
+    case kCheckBound: return "value above its bound m_i";
+    default: return "?";
+    }
+}
+
+wmh_status check_status(uint32_t code)
+{
+    switch (code) {
+    case kCheckRowPtr: return WMH_E_ROW_PTR;
+    case kCheckColumn: return WMH_E_COL_RANGE;
+    case kCheckUnsorted: return WMH_E_UNSORTED;
+    case kCheckBound: return WMH_E_BOUND;
+    default: return WMH_E_DEVICE;
+    }
+}
+
 Bounds bounds_view(const wmh_ctx *ctx)
 {
     Bounds b;
@@ -57,9 +79,35 @@ Bounds bounds_view(const wmh_ctx *ctx)
 }
 
 // Tile plan of the batched walk.  Returns false when no dense plan fits in LDS.
-bool plan_batched(const wmh_ctx *ctx, uint32_t k, uint64_t min_green, const wmh_opts &o,
-                  BatchedPlan *plan)
+TuneKey tune_key(const wmh_ctx *ctx, uint32_t k, const RowStats &stats)
 {
+    TuneKey key;
+    key.dims = ctx->dims;
+    key.narrow = ctx->max_bound <= 0xFFFFu;
+    key.k = k;
+    if (stats.known && stats.nonempty) {
+        const double mean = (double)stats.walk_steps / (double)stats.nonempty;
+        key.steps_class = mean >= 1.0 ? (int32_t)std::floor(std::log2(mean)) : 0;
+    }
+    return key;
+}
+
+bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const wmh_opts &o_in,
+                  BatchedPlan *plan, bool use_tuned)
+{
+    wmh_opts o = o_in;
+    if (use_tuned && stats.known && !o.rows_per_block && !o.hashes_per_tile &&
+        !o.waves_per_block) {
+        const TuneKey key = tune_key(ctx, k, stats);
+        for (const TuneEntry &e : ctx->tuned)
+            if (e.key == key) {
+                o.rows_per_block = e.R;
+                o.hashes_per_tile = e.J;
+                o.waves_per_block = e.W;
+                break;
+            }
+    }
+    const uint64_t min_green = stats.known ? stats.min_green : ~0ull;
     BatchedPlan p{};
     p.narrow = ctx->max_bound <= 0xFFFFu;
     p.waves_per_block = o.waves_per_block ? std::min<uint32_t>(o.waves_per_block, 16u) : 8u;
@@ -122,12 +170,40 @@ wmh_status check_rows_host(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t
             green += val[e];
         }
         if (green) {
+            ++st.nonempty;
             st.min_green = std::min(st.min_green, green);
             st.walk_steps += std::min<uint64_t>(ctx->total / green, kCap);
             st.index_keys += (uint64_t)std::ceil(65534.0 * ((double)green / (double)ctx->total));
         }
     }
     if (stats) *stats = st;
+    return WMH_OK;
+}
+
+wmh_status gather_stats(wmh_ctx *ctx, const Rows &rows, hipStream_t s, bool check,
+                        RowStats *stats)
+{
+    // first_error and min_green start at ~0, the counters at 0
+    uint32_t *words = reinterpret_cast<uint32_t *>(ctx->d_check);
+    hipError_t e = launch_fill_u32(words, 0xFFFFFFFFu, 4, s);
+    if (e == hipSuccess) e = launch_fill_u32(words + 4, 0u, 6, s);
+    if (e == hipSuccess) e = launch_validate(rows, ctx->d_bound, ctx->dims, ctx->total, ctx->d_check, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->h_check, ctx->d_check, sizeof(CheckWords), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_fail(ctx, e, "validation pass");
+    const CheckWords v = *ctx->h_check;
+    if (check && v.first_error != ~0ull) {
+        const uint64_t row = v.first_error >> 4;
+        const uint32_t code = (uint32_t)(v.first_error & 15u);
+        return fail(ctx, check_status(code), "row %llu: %s", (unsigned long long)row,
+                    check_name(code));
+    }
+    stats->known = true;
+    stats->nonempty = rows.n_rows - std::min<uint64_t>(rows.n_rows, v.n_empty);
+    stats->min_green = v.min_green;
+    stats->walk_steps = v.walk_steps;
+    stats->index_keys = v.index_keys;
     return WMH_OK;
 }
 
@@ -252,28 +328,6 @@ void drop_graph(wmh_ctx *ctx)
 hipStream_t pick_stream(wmh_ctx *ctx, void *stream)
 {
     return stream ? reinterpret_cast<hipStream_t>(stream) : ctx->own_stream;
-}
-
-const char *check_name(uint32_t code)
-{
-    switch (code) {
-    case kCheckRowPtr: return "row_ptr decreasing or beyond nnz";
-    case kCheckColumn: return "column index >= D";
-    case kCheckUnsorted: return "columns not strictly increasing";
-    case kCheckBound: return "value above its bound m_i";
-    default: return "?";
-    }
-}
-
-wmh_status check_status(uint32_t code)
-{
-    switch (code) {
-    case kCheckRowPtr: return WMH_E_ROW_PTR;
-    case kCheckColumn: return WMH_E_COL_RANGE;
-    case kCheckUnsorted: return WMH_E_UNSORTED;
-    case kCheckBound: return WMH_E_BOUND;
-    default: return WMH_E_DEVICE;
-    }
 }
 
 wmh_status ensure_stream_capacity(wmh_ctx *ctx, size_t bytes)
@@ -492,30 +546,13 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
     const bool profile = o.profile != 0;
     ctx->profiled = false;
     if (o.validate || o.mode == WMH_MODE_AUTO) {
-        // first_error and min_green start at ~0, the counters at 0
-        uint32_t *words = reinterpret_cast<uint32_t *>(ctx->d_check);
-        WMH_HIP(ctx, launch_fill_u32(words, 0xFFFFFFFFu, 4, s));
-        WMH_HIP(ctx, launch_fill_u32(words + 4, 0u, 6, s));
-        WMH_HIP(ctx, launch_validate(rows, ctx->d_bound, ctx->dims, ctx->total, ctx->d_check, s));
-        WMH_HIP(ctx, hipMemcpyAsync(ctx->h_check, ctx->d_check, sizeof(CheckWords),
-                                    hipMemcpyDeviceToHost, s));
-        WMH_HIP(ctx, hipStreamSynchronize(s));
-        const CheckWords v = *ctx->h_check;
-        if (o.validate && v.first_error != ~0ull) {
-            const uint64_t row = v.first_error >> 4;
-            const uint32_t code = (uint32_t)(v.first_error & 15u);
-            return fail(ctx, check_status(code), "row %llu: %s", (unsigned long long)row,
-                        check_name(code));
-        }
-        stats.known = true;
-        stats.min_green = v.min_green;
-        stats.walk_steps = v.walk_steps;
-        stats.index_keys = v.index_keys;
+        const wmh_status st = gather_stats(ctx, rows, s, o.validate != 0, &stats);
+        if (st != WMH_OK) return st;
     }
 
     BatchedPlan plan{};
     const bool batched_ok = (o.mode == WMH_MODE_AUTO || o.mode == WMH_MODE_BATCHED) &&
-                            plan_batched(ctx, k, stats.min_green, o, &plan);
+                            plan_batched(ctx, k, stats, o, &plan);
     if (o.mode == WMH_MODE_BATCHED && !batched_ok)
         return fail(ctx, WMH_E_ARG, "no batched plan fits for D=%u with these options", ctx->dims);
     const bool index_ready = ctx->index.valid && ctx->index.seed == seed && ctx->index.k == k &&
@@ -621,6 +658,7 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         ctx->profiled = profile;
     }
     ctx->last_mode = batched ? WMH_MODE_BATCHED : WMH_MODE_PLAIN;
+    ctx->last_plan = batched ? plan : BatchedPlan{};
     if (o.sync) WMH_HIP(ctx, hipStreamSynchronize(s));
     return WMH_OK;
 }
@@ -629,6 +667,18 @@ wmh_status wmh_last_mode(const wmh_ctx *ctx, int32_t *mode)
 {
     if (!ctx || !mode) return WMH_E_ARG;
     *mode = ctx->last_mode;
+    return WMH_OK;
+}
+
+wmh_status wmh_last_plan(const wmh_ctx *ctx, wmh_opts *plan)
+{
+    if (!ctx || !plan) return WMH_E_ARG;
+    wmh_opts_init(plan);
+    plan->mode = ctx->last_mode;
+    plan->rows_per_block = ctx->last_plan.rows_per_block;
+    plan->hashes_per_tile = ctx->last_plan.hashes_per_tile;
+    plan->stream_depth = ctx->last_plan.stream_depth;
+    plan->waves_per_block = ctx->last_plan.waves_per_block;
     return WMH_OK;
 }
 

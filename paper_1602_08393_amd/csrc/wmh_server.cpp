@@ -267,7 +267,7 @@ wmh_status wmh_server_create(wmh_ctx *ctx, const wmh_server_config *cfg_in, wmh_
     wmh_opts_init(&o);
     o.stream_depth = cfg.stream_depth ? cfg.stream_depth : 8192;
     srv->batched = (cfg.mode == WMH_MODE_AUTO || cfg.mode == WMH_MODE_BATCHED) &&
-                   plan_batched(ctx, cfg.k, ~0ull, o, &srv->plan);
+                   plan_batched(ctx, cfg.k, RowStats{}, o, &srv->plan);
     srv->index_grid = (uint32_t)ctx->cu_count * (uint32_t)index_rows_blocks_per_cu(cfg.k);
     if (cfg.mode == WMH_MODE_BATCHED && !srv->batched) {
         delete srv;

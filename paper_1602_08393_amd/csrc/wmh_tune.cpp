@@ -1,0 +1,192 @@
+// Autotuner of the batched walk's tile plan: rows per block R, hash ids per tile J and
+// wavefronts per workgroup W (the scheduling choices of the persistent launch; they change
+// only the time, never a hash value).  Each candidate plan hashes the caller's rows on the
+// device, timed with HIP events; the fastest is kept in the context under (D, value width, k,
+// step class) and taken by later wmh_hash calls whose key matches and which leave the plan
+// options at 0.  Results can be saved to and loaded from a text file.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/wmh.h"
+#include "wmh_context.h"
+#include "wmh_internal.h"
+
+using namespace wmh;
+
+namespace {
+
+constexpr char kTuneHeader[] = "wmh-tune 1";
+
+void put_entry(wmh_ctx *ctx, const TuneEntry &e)
+{
+    for (TuneEntry &x : ctx->tuned)
+        if (x.key == e.key) {
+            x = e;
+            return;
+        }
+    ctx->tuned.push_back(e);
+}
+
+bool valid_plan(uint32_t R, uint32_t J, uint32_t W)
+{
+    return (R == 1 || R == 2 || R == 4 || R == 8 || R == 16) && J >= 1 && W >= 1 && W <= 16;
+}
+
+}  // namespace
+
+extern "C" {
+
+wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
+                    const uint32_t *val, uint64_t n_rows, uint64_t nnz, uint32_t k, uint64_t seed,
+                    uint16_t *sig, void *stream, uint32_t reps, wmh_tune_result *out)
+{
+    if (!ctx) return WMH_E_ARG;
+    ctx->last_error.clear();
+    if (!ctx->has_bounds) return fail(ctx, WMH_E_NO_BOUNDS, "wmh_set_bounds was not called");
+    if (k == 0 || k > kMaxK) return fail(ctx, WMH_E_ARG, "k must be in [1, 2^24]");
+    if (n_rows == 0 || !row_ptr || !sig || !out || (nnz && (!col || !val)))
+        return fail(ctx, WMH_E_ARG, "null buffer or no rows");
+    if (reps == 0) reps = 3;
+    if (reps > 100) return fail(ctx, WMH_E_ARG, "reps must be in [1, 100]");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, WMH_E_DEVICE, "hipSetDevice");
+    hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : ctx->own_stream;
+    const Rows rows{row_ptr, col, val, n_rows, nnz};
+    RowStats stats;
+    wmh_status st = gather_stats(ctx, rows, s, true, &stats);
+    if (st != WMH_OK) return st;
+
+    wmh_opts base;
+    wmh_opts_init(&base);
+    BatchedPlan def{};
+    if (!plan_batched(ctx, k, stats, base, &def, false))
+        return fail(ctx, WMH_E_ARG, "no batched plan fits for D=%u", ctx->dims);
+
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {
+        if (t0) (void)hipEventDestroy(t0);
+        return fail(ctx, WMH_E_DEVICE, "hipEventCreate");
+    }
+    // best of `reps` timed calls after one untimed call; <0 when the plan does not fit
+    auto time_plan = [&](uint32_t R, uint32_t J, uint32_t W, float *ms) -> wmh_status {
+        wmh_opts o = base;
+        o.mode = WMH_MODE_BATCHED;
+        o.validate = 0;
+        o.use_graph = 0;
+        o.rows_per_block = R;
+        o.hashes_per_tile = J;
+        o.waves_per_block = W;
+        o.stream_depth = def.stream_depth;
+        BatchedPlan p{};
+        *ms = -1.f;
+        if (!plan_batched(ctx, k, stats, o, &p, false)) return WMH_OK;
+        float best = 1e30f;
+        for (uint32_t r = 0; r <= reps; ++r) {
+            if (hipEventRecord(t0, s) != hipSuccess) return WMH_E_DEVICE;
+            wmh_status h = wmh_hash(ctx, row_ptr, col, val, n_rows, nnz, k, seed, sig, s, &o);
+            if (h != WMH_OK) return h;
+            if (hipEventRecord(t1, s) != hipSuccess || hipEventSynchronize(t1) != hipSuccess)
+                return WMH_E_DEVICE;
+            float e = 0.f;
+            if (hipEventElapsedTime(&e, t0, t1) != hipSuccess) return WMH_E_DEVICE;
+            if (r > 0) best = std::min(best, e);
+        }
+        *ms = best;
+        return WMH_OK;
+    };
+
+    wmh_tune_result res{};
+    float default_ms = 0.f;
+    st = time_plan(def.rows_per_block, def.hashes_per_tile, def.waves_per_block, &default_ms);
+    TuneEntry best;
+    best.key = tune_key(ctx, k, stats);
+    best.R = def.rows_per_block;
+    best.J = def.hashes_per_tile;
+    best.W = def.waves_per_block;
+    best.ms = default_ms;
+    uint32_t tried = 1;
+    std::vector<uint32_t> Js{std::min(k, 1024u), std::min(k, 512u), std::min(k, 256u)};
+    Js.erase(std::unique(Js.begin(), Js.end()), Js.end());
+    for (uint32_t R : {1u, 2u, 4u, 8u, 16u}) {
+        for (uint32_t W : {4u, 8u, 16u}) {
+            for (uint32_t J : Js) {
+                if (st != WMH_OK) break;
+                if (R == def.rows_per_block && J == def.hashes_per_tile && W == def.waves_per_block)
+                    continue;
+                float ms = -1.f;
+                st = time_plan(R, J, W, &ms);
+                if (st == WMH_OK && ms >= 0.f) {
+                    ++tried;
+                    if (ms < best.ms) {
+                        best.R = R;
+                        best.J = J;
+                        best.W = W;
+                        best.ms = ms;
+                    }
+                }
+            }
+        }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (st != WMH_OK) return st;
+    put_entry(ctx, best);
+    res.rows_per_block = best.R;
+    res.hashes_per_tile = best.J;
+    res.waves_per_block = best.W;
+    res.stream_depth = def.stream_depth;
+    res.best_ms = best.ms;
+    res.default_ms = default_ms;
+    res.candidates = tried;
+    res.steps_class = best.key.steps_class;
+    *out = res;
+    return WMH_OK;
+}
+
+wmh_status wmh_tune_save(wmh_ctx *ctx, const char *path)
+{
+    if (!ctx || !path) return WMH_E_ARG;
+    FILE *f = std::fopen(path, "w");
+    if (!f) return fail(ctx, WMH_E_ARG, "cannot write %s", path);
+    std::fprintf(f, "%s\n", kTuneHeader);
+    for (const TuneEntry &e : ctx->tuned)
+        std::fprintf(f, "%u %d %u %d %u %u %u %.6f\n", e.key.dims, e.key.narrow ? 1 : 0, e.key.k,
+                     e.key.steps_class, e.R, e.J, e.W, (double)e.ms);
+    const bool ok = std::fclose(f) == 0;
+    return ok ? WMH_OK : fail(ctx, WMH_E_ARG, "cannot write %s", path);
+}
+
+wmh_status wmh_tune_load(wmh_ctx *ctx, const char *path)
+{
+    if (!ctx || !path) return WMH_E_ARG;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return fail(ctx, WMH_E_ARG, "cannot read %s", path);
+    char line[256];
+    std::vector<TuneEntry> got;
+    bool ok = std::fgets(line, sizeof(line), f) &&
+              std::strncmp(line, kTuneHeader, sizeof(kTuneHeader) - 1) == 0;
+    while (ok && std::fgets(line, sizeof(line), f)) {
+        TuneEntry e;
+        int narrow = 0;
+        double ms = 0;
+        if (std::sscanf(line, "%u %d %u %d %u %u %u %lf", &e.key.dims, &narrow, &e.key.k,
+                        &e.key.steps_class, &e.R, &e.J, &e.W, &ms) != 8 ||
+            (narrow != 0 && narrow != 1) || !valid_plan(e.R, e.J, e.W) || e.key.k == 0) {
+            ok = false;
+            break;
+        }
+        e.key.narrow = narrow != 0;
+        e.ms = (float)ms;
+        got.push_back(e);
+    }
+    std::fclose(f);
+    if (!ok) return fail(ctx, WMH_E_ARG, "%s is not a tuning file", path);
+    for (const TuneEntry &e : got) put_entry(ctx, e);
+    return WMH_OK;
+}
+
+}  // extern "C"

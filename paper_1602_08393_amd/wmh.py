@@ -23,8 +23,8 @@ MODES = {"auto": 0, "plain": 1, "batched": 2, "indexed": 3}
 
 EXPORTED = ["wmh_opts_init", "wmh_create", "wmh_destroy", "wmh_set_bounds", "wmh_hash",
             "wmh_estimate", "wmh_collisions", "wmh_bounds_info", "wmh_bounds_tables",
-            "wmh_draws", "wmh_last_kernel_ms", "wmh_last_mode", "wmh_last_error",
-            "wmh_status_string",
+            "wmh_draws", "wmh_last_kernel_ms", "wmh_last_mode", "wmh_last_plan",
+            "wmh_tune", "wmh_tune_save", "wmh_tune_load", "wmh_last_error", "wmh_status_string",
             "wmh_server_create", "wmh_server_submit", "wmh_server_poll", "wmh_server_wait",
             "wmh_server_drain", "wmh_server_stats", "wmh_server_now_ns", "wmh_server_destroy"]
 
@@ -52,6 +52,14 @@ class ServingStats(ctypes.Structure):
                 ("p99_ms", ctypes.c_double), ("p999_ms", ctypes.c_double),
                 ("max_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
                 ("busy_s", ctypes.c_double), ("hashes_per_s", ctypes.c_double)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("rows_per_block", ctypes.c_uint32), ("hashes_per_tile", ctypes.c_uint32),
+                ("waves_per_block", ctypes.c_uint32), ("stream_depth", ctypes.c_uint32),
+                ("best_ms", ctypes.c_float), ("default_ms", ctypes.c_float),
+                ("candidates", ctypes.c_uint32), ("steps_class", ctypes.c_int32),
+                ("reserved", ctypes.c_uint32 * 4)]
 
 
 class WMHError(RuntimeError):
@@ -99,6 +107,15 @@ def load() -> ctypes.CDLL:
     L.wmh_last_kernel_ms.restype = ctypes.c_int
     L.wmh_last_mode.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.wmh_last_mode.restype = ctypes.c_int
+    L.wmh_last_plan.argtypes = [vp, ctypes.POINTER(WmhOpts)]
+    L.wmh_last_plan.restype = ctypes.c_int
+    L.wmh_tune.argtypes = [vp, vp, vp, vp, u64, u64, u32, u64, vp, vp, u32,
+                           ctypes.POINTER(TuneResult)]
+    L.wmh_tune.restype = ctypes.c_int
+    L.wmh_tune_save.argtypes = [vp, ctypes.c_char_p]
+    L.wmh_tune_save.restype = ctypes.c_int
+    L.wmh_tune_load.argtypes = [vp, ctypes.c_char_p]
+    L.wmh_tune_load.restype = ctypes.c_int
     L.wmh_draws.argtypes = [vp, u64, u32, u32, u32, vp, vp, vp, vp]
     L.wmh_draws.restype = ctypes.c_int
     L.wmh_server_create.argtypes = [vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
@@ -263,6 +280,35 @@ class Context:
         m = ctypes.c_int32()
         self._check(self._lib.wmh_last_mode(self._ptr, ctypes.byref(m)), "wmh_last_mode")
         return {v: k for k, v in MODES.items()}[m.value]
+
+    def last_plan(self) -> dict:
+        """Mode and batched tile plan of the last wmh_hash call."""
+        o = WmhOpts()
+        self._check(self._lib.wmh_last_plan(self._ptr, ctypes.byref(o)), "wmh_last_plan")
+        return {"mode": {v: k for k, v in MODES.items()}[o.mode],
+                "rows_per_block": o.rows_per_block, "hashes_per_tile": o.hashes_per_tile,
+                "stream_depth": o.stream_depth, "waves_per_block": o.waves_per_block}
+
+    def tune(self, rows: DeviceRows, k: int, seed: int = 0, reps: int = 3, stream=None) -> dict:
+        """Autotunes the batched tile plan on these rows (see wmh_tune); returns the result and
+        leaves the signatures of the last candidate in a scratch tensor."""
+        torch = _torch()
+        sig = torch.empty((rows.n_rows, k), dtype=torch.int16, device=rows.row_ptr.device)
+        r = TuneResult()
+        st = self._lib.wmh_tune(self._ptr, rows.row_ptr.data_ptr(), rows.col.data_ptr(),
+                                rows.val.data_ptr(), rows.n_rows, rows.nnz, k, seed,
+                                sig.data_ptr(), self._stream(stream), reps, ctypes.byref(r))
+        self._check(st, "wmh_tune")
+        return {"rows_per_block": r.rows_per_block, "hashes_per_tile": r.hashes_per_tile,
+                "waves_per_block": r.waves_per_block, "stream_depth": r.stream_depth,
+                "best_ms": r.best_ms, "default_ms": r.default_ms, "candidates": r.candidates,
+                "steps_class": r.steps_class}
+
+    def tune_save(self, path: str):
+        self._check(self._lib.wmh_tune_save(self._ptr, os.fsencode(path)), "wmh_tune_save")
+
+    def tune_load(self, path: str):
+        self._check(self._lib.wmh_tune_load(self._ptr, os.fsencode(path)), "wmh_tune_load")
 
     def hash_into(self, rows: DeviceRows, k: int, seed: int, sig, stream=None, opts=None):
         """Raw call: sig is a device int16 tensor of N*k elements."""
