@@ -26,6 +26,11 @@ if ROOT not in sys.path:
 PEAK_INT_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3
 HBM_PEAK_GBS = 8000.0
 OPS_PER_TEST = 2  # one lookup of x at the draw's component and one compare
+# HBM bytes per launch of batched_kernel<unsigned short, 4, true> on the full histogram-shaped
+# workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy (read x2.000,
+# write x1.000); profiles/batched_kernel_histogram_k500.txt.  Valid while that kernel and plan
+# (R = 4, narrow packed entries) are the ones timed.
+TRAFFIC_R4_HISTOGRAM = 1.2136e9 + 0.1009e9
 
 
 def log(msg: str):
@@ -348,6 +353,8 @@ def main():
         log(f"plain: {el / psteps * 1e3:.3f} ms/step, walk kernels {np.mean(walk):.3f} ms")
 
     main_key = "batched" if "batched" in result else "plain"
+    profiled_plan = (main_key == "batched" and batched_plan["rows_per_block"] == 4
+                     and ds.n_rows == 100_000)
     steps = args.steps if main_key == "batched" else result["plain"][2]
     el, walk, _ = result[main_key][:3]
     value = hashes * steps / el
@@ -375,7 +382,8 @@ def main():
                    "N": ds.n_rows, "D": ds.D, "k": k, "nnz": ds.nnz, "M": M,
                    "mode": main_key},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS,
-                     "unit": "TOP/s", "frac": achieved / PEAK_INT_TOPS, "traffic": None,
+                     "unit": "TOP/s", "frac": achieved / PEAK_INT_TOPS,
+                     "traffic": TRAFFIC_R4_HISTOGRAM if profiled_plan else None,
                      "kernel": "batched_kernel" if main_key == "batched" else "plain_kernel",
                      "kernel_ms": walk_s * 1e3, "membership_tests": tests,
                      "ops_per_test": OPS_PER_TEST},
