@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--hashes-per-tile", type=int, default=0)
     ap.add_argument("--stream-depth", type=int, default=0)
     ap.add_argument("--waves-per-block", type=int, default=0)
+    ap.add_argument("--walk", type=int, default=0, choices=[0, 1, 2],
+                    help="batched walk: 0 planner/autotuner, 1 shared windows, 2 independent rows")
     ap.add_argument("--only", choices=["batched", "plain", "both"], default="both")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run device-to-device copies of BYTES (scales HBM counters)")
@@ -268,6 +270,19 @@ def text_like_bench(args, torch, synth, wmh) -> dict:
     return out
 
 
+def cpu_model() -> str:
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {os.cpu_count()} logical CPUs visible"
+
+
 def cpu_baseline(ds, k, target_s):
     import oracle
     threads = min(16, os.cpu_count() or 1)
@@ -283,9 +298,18 @@ def cpu_baseline(ds, k, target_s):
     sig, steps = oracle.hash_csr(sample.m, sample.row_ptr, sample.col, sample.val, k, seed=0,
                                  threads=threads, return_steps=True)
     dt = time.perf_counter() - t0
+    # one thread on a tenth of the sample
+    n1 = max(1, n // (10 * threads) * 1)
+    one = ds.head(n1)
+    t1 = time.perf_counter()
+    oracle.hash_csr(one.m, one.row_ptr, one.col, one.val, k, seed=0, threads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": n * k / dt, "unit": "hashes/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n} rows of the workload, k={k} ({steps} membership tests, "
-                      f"{dt:.1f} s, {steps / dt:.3g} tests/s)"}, sig
+                      f"{dt:.1f} s, {steps / dt:.3g} tests/s)",
+            "single_thread_value": n1 * k / dt1,
+            "single_thread_sample": f"first {n1} rows, 1 thread, {dt1:.1f} s",
+            "host": cpu_model()}, sig
 
 
 def main():
@@ -322,7 +346,8 @@ def main():
     hashes = ds.n_rows * k
 
     plan = dict(rows_per_block=args.rows_per_block, hashes_per_tile=args.hashes_per_tile,
-                stream_depth=args.stream_depth, waves_per_block=args.waves_per_block)
+                stream_depth=args.stream_depth, waves_per_block=args.waves_per_block,
+                walk=args.walk)
     result = {}
     tune = None
     if args.only in ("batched", "both") and not args.no_tune and not any(plan.values()):

@@ -21,14 +21,15 @@ struct GraphKey {
     void *sig = nullptr;
     uint64_t n_rows = 0, nnz = 0, seed = 0;
     uint32_t k = 0, R = 0, J = 0, depth = 0, waves = 0, grid = 0;
-    bool narrow = false, packed = false;
+    bool narrow = false, packed = false, independent_rows = false;
     uint64_t bounds_epoch = 0;
     bool operator==(const GraphKey &o) const
     {
         return row_ptr == o.row_ptr && col == o.col && val == o.val && sig == o.sig &&
                n_rows == o.n_rows && nnz == o.nnz && seed == o.seed && k == o.k && R == o.R &&
                J == o.J && depth == o.depth && waves == o.waves && grid == o.grid &&
-               narrow == o.narrow && packed == o.packed && bounds_epoch == o.bounds_epoch;
+               narrow == o.narrow && packed == o.packed &&
+               independent_rows == o.independent_rows && bounds_epoch == o.bounds_epoch;
     }
 };
 
@@ -72,6 +73,7 @@ struct TuneKey {
 struct TuneEntry {
     TuneKey key;
     uint32_t R = 0, J = 0, W = 0;
+    int32_t walk = 1;  // wmh_opts.walk: 1 shared windows, 2 independent rows
     float ms = 0.f;
 };
 

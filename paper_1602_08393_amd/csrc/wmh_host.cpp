@@ -97,13 +97,14 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const w
 {
     wmh_opts o = o_in;
     if (use_tuned && stats.known && !o.rows_per_block && !o.hashes_per_tile &&
-        !o.waves_per_block) {
+        !o.waves_per_block && !o.walk) {
         const TuneKey key = tune_key(ctx, k, stats);
         for (const TuneEntry &e : ctx->tuned)
             if (e.key == key) {
                 o.rows_per_block = e.R;
                 o.hashes_per_tile = e.J;
                 o.waves_per_block = e.W;
+                o.walk = e.walk;
                 break;
             }
     }
@@ -114,13 +115,17 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const w
     p.hashes_per_tile = o.hashes_per_tile ? std::min(o.hashes_per_tile, k) : std::min(k, 1024u);
     const size_t elem = p.narrow ? 2 : 4;
     const size_t lds_target = 48 * 1024;  // keep several workgroups resident per CU
+    if (o.walk < 0 || o.walk > 2) return false;
     uint32_t R = o.rows_per_block;
     if (R == 0) {
         R = 4;
         while (R > 1 && (size_t)ctx->dims * R * elem > lds_target) R >>= 1;
+        if (o.walk == 2) R = 4;
     }
     if (R != 1 && R != 2 && R != 4 && R != 8 && R != 16) return false;
+    if (o.walk == 2 && R != 4) return false;
     p.rows_per_block = R;
+    p.independent_rows = o.walk == 2;
     if (batched_lds_bytes(ctx->dims, p) > 160 * 1024 - 64) return false;
     p.packed = p.narrow && (uint64_t)ctx->dims * p.scale() <= 65536u;
     // shared stream depth: cover eight mean step counts of the sparsest row
@@ -606,6 +611,7 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         key.R = plan.rows_per_block; key.J = plan.hashes_per_tile; key.depth = plan.stream_depth;
         key.waves = plan.waves_per_block; key.grid = grid; key.narrow = plan.narrow;
         key.packed = plan.packed;
+        key.independent_rows = plan.independent_rows;
         key.bounds_epoch = ctx->bounds_epoch;
 
         // events between kernels only on direct launches; a graph is timed as a whole
@@ -679,6 +685,7 @@ wmh_status wmh_last_plan(const wmh_ctx *ctx, wmh_opts *plan)
     plan->hashes_per_tile = ctx->last_plan.hashes_per_tile;
     plan->stream_depth = ctx->last_plan.stream_depth;
     plan->waves_per_block = ctx->last_plan.waves_per_block;
+    plan->walk = ctx->last_mode == WMH_MODE_BATCHED ? (ctx->last_plan.independent_rows ? 2 : 1) : 0;
     return WMH_OK;
 }
 

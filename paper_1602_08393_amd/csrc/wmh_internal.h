@@ -50,6 +50,7 @@ struct BatchedPlan {
     uint32_t waves_per_block;
     bool narrow;               // dense rows stored as uint16 (every bound < 65536)
     bool packed;               // 4-byte stream entries
+    bool independent_rows;     // each row of a block walks its own hash ids (R = 4 only)
     uint32_t scale() const { return rows_per_block * (narrow ? 2u : 4u); }
 };
 

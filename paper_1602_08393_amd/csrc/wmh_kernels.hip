@@ -515,6 +515,185 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Independent rows (R = 4): the tiles, LDS rows and shared stream of batched_kernel, but each
+// row of a block walks its own hash ids.  batched_kernel tests every window for all R rows until
+// the block's last row is green, so it tests about E[max of R step counts] per row instead of
+// E[one] (x2.5 at R = 4); here a row group of 16 lanes (one DPP row) stops at its own first
+// green window and moves on to its next hash id.  Lane l serves row r = l / 16 and steps
+// base_r + (l mod 16) * 4 + 1 .. + 4 of the row's current hash id j_r; wave w of the workgroup
+// takes the hash ids j0 + w, j0 + w + W, ... of every row of the tile.
+// ---------------------------------------------------------------------------------------------
+
+// Minimum of c over lanes i-15 .. i of the lane's 16-lane row (a prefix scan); lanes whose
+// source lies outside the row keep their value.  Lane 15 of each row ends with the row minimum.
+template <int S>
+__device__ __forceinline__ uint32_t row16_scan_min(uint32_t c)
+{
+    const uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFFu, (int)c, 0x110 + S,
+                                                             0xF, 0xF, false);
+    return min(c, t);
+}
+
+// Every 16-bit segment of g that is nonzero, as a full segment of ones.
+__device__ __forceinline__ uint64_t nonzero_segments16(uint64_t g)
+{
+    constexpr uint64_t kHigh = 0x8000800080008000ull, kLow = ~kHigh;
+    const uint64_t h = (((g & kLow) + kLow) | g) & kHigh;  // no carry leaves a segment
+    return h | (h - (h >> 15));
+}
+
+__device__ __forceinline__ bool lane_bit(uint64_t mask) { return ((mask >> lane()) & 1ull) != 0; }
+
+template <typename XT, bool kPacked>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void rows_kernel(
+    Bounds b, Rows rows, uint32_t k, uint64_t seed, uint16_t *__restrict__ sig,
+    uint32_t hashes_per_tile, uint32_t depth, const void *__restrict__ entries,
+    uint32_t *tile_counter)
+{
+    constexpr uint32_t R = 4, L = 16, K = 4;
+    constexpr uint32_t kLastBase = kCap + 1u - kWave;  // window of steps 65473 .. 65536
+    constexpr uint32_t kNone = 0xFFFFu;                // no green step in the lane's steps
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t tile_slot;
+    __shared__ uint32_t nonempty;
+    const uint32_t D = b.dims;
+    XT *x = reinterpret_cast<XT *>(smem);
+    uint16_t *hbuf = reinterpret_cast<uint16_t *>(smem + (((size_t)D * R * sizeof(XT) + 15) & ~(size_t)15));
+    const uint32_t my_row = lane() / L;
+    const uint32_t gk = (lane() % L) * K;  // first of the lane's K steps inside a window
+    constexpr uint32_t kScale = R * sizeof(XT);
+    const uint32_t row_byte = my_row * sizeof(XT);
+    const uint32_t waves = blockDim.x / kWave;
+    const uint32_t wave = wave_index();
+    const uint32_t last_base = depth - kWave;
+
+    const uint64_t n_blocks = (rows.n_rows + R - 1) / R;
+    const uint32_t n_hash_tiles = (k + hashes_per_tile - 1) / hashes_per_tile;
+    const uint64_t n_tiles = n_blocks * n_hash_tiles;
+    uint64_t staged = ~0ull;
+
+    while (true) {
+        if (threadIdx.x == 0) tile_slot = atomicAdd(tile_counter, 1u);
+        __syncthreads();
+        const uint64_t tile = tile_slot;
+        if (tile >= n_tiles) break;
+        const uint64_t blk = tile / n_hash_tiles;
+        const uint32_t ht = (uint32_t)(tile - blk * n_hash_tiles);
+        const uint64_t row0 = blk * R;
+        const uint32_t n_here = (uint32_t)min((uint64_t)R, rows.n_rows - row0);
+
+        if (blk != staged) {
+            uint32_t *xz = reinterpret_cast<uint32_t *>(x);
+            const uint32_t words = (uint32_t)(((size_t)D * R * sizeof(XT) + 3) / 4);
+            for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) xz[i] = 0u;
+            if (threadIdx.x == 0) nonempty = 0;
+            __syncthreads();
+            uint32_t mine = 0;
+            for (uint32_t r = 0; r < n_here; ++r) {
+                const uint64_t lo = rows.row_ptr[row0 + r], hi = rows.row_ptr[row0 + r + 1];
+                for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+                    const uint32_t v = rows.val[e];
+                    const uint32_t c = rows.col[e];
+                    if (c < D) x[(size_t)c * R + r] = (XT)v;
+                    if (v) mine |= 1u << r;
+                }
+            }
+            if (mine) atomicOr(&nonempty, mine);
+            __syncthreads();
+            staged = blk;
+        }
+        const uint32_t live = __builtin_amdgcn_readfirstlane(nonempty);
+        const uint32_t j0 = ht * hashes_per_tile;
+        const uint32_t j1 = min(k, j0 + hashes_per_tile);
+
+        // the row's current hash id (rows without a green unit start past the end) and window
+        uint32_t jr = ((live >> my_row) & 1u) ? j0 + wave : j1;
+        uint32_t base = 0;
+        // entry index of window 0 of id jr (jr * depth, kept by addition: the whole stream has
+        // fewer than 2^32 entries); loads clamp it to the last id, so finished rows read
+        // in-bounds entries and ignore them
+        const uint32_t id_step = waves * depth;
+        const uint32_t last_id = (k - 1u) * depth;
+        uint32_t jbase = min(jr, k - 1u) * depth;
+        auto fetch = [&](uint32_t first, uint32_t at) {
+            EntryRun<K, kPacked> run;
+            run.load(entries, (uint64_t)(min(first, last_id) + min(at, last_base) + gk));
+            return run;
+        };
+        // cur: the window to test; nxt: the next window of the same id; nid: the first window
+        // of the row's next id (jr + waves)
+        EntryRun<K, kPacked> cur = fetch(jbase, 0), nxt = fetch(jbase, kWave),
+                             nid = fetch(jbase + id_step, 0);
+        uint64_t active = __ballot(jr < j1);
+        while (active != 0) {
+            uint32_t c = kNone;  // position in the window of this lane's first green step
+            {
+                uint32_t xv[K], off[K];
+#pragma unroll
+                for (int q = 0; q < (int)K; ++q) {
+                    uint32_t lds;
+                    cur.get(q, kScale, &lds, &off[q]);
+                    xv[q] = *reinterpret_cast<const XT *>(smem + lds + row_byte);
+                }
+#pragma unroll
+                for (int q = K - 1; q >= 0; --q) c = off[q] < xv[q] ? gk + (uint32_t)q : c;
+            }
+            if (base >= depth) {
+                // beyond the stream (rare): draw in-lane, one step at a time
+                c = kNone;
+#pragma unroll 1
+                for (int q = K - 1; q >= 0; --q) {
+                    const uint32_t t = base + gk + (uint32_t)q + 1u;
+                    const uint64_t p = position(seed, jr, t, b.total, b.threshold);
+                    uint64_t o64;
+                    const uint32_t comp = component_of(p, b.prefix, b.bucket, b.shift, &o64);
+                    c = o64 < (uint64_t)x[(size_t)comp * R + my_row] ? gk + (uint32_t)q : c;
+                }
+            }
+            const uint64_t at_last = __ballot(base == kLastBase);
+            if (at_last) {
+                // step 65536 (the last step of the row's last lane) does not count
+                if (base == kLastBase && c == kWave - 1u) c = kNone;
+            }
+            const uint64_t green = __ballot(c != kNone);
+            const uint64_t done = (nonzero_segments16(green) | at_last) & active;
+            uint32_t m = c;
+            m = row16_scan_min<1>(m);
+            m = row16_scan_min<2>(m);
+            m = row16_scan_min<4>(m);
+            m = row16_scan_min<8>(m);
+            const bool is_done = lane_bit(done);
+            if (is_done && gk == kWave - K) {
+                // lane 15 of a finished row holds the row's first green position
+                hbuf[my_row * hashes_per_tile + (jr - j0)] =
+                    (uint16_t)(m == kNone ? kCap : base + m + 1u);
+            }
+#pragma unroll
+            for (int i = 0; i < EntryRun<K, kPacked>::kWords; ++i)
+                cur.w[i] = is_done ? nid.w[i] : nxt.w[i];
+            jr = is_done ? jr + waves : jr;
+            jbase = is_done ? jbase + id_step : jbase;
+            base = is_done ? 0u : base + kWave;
+            // the loads below reuse the registers the select has just read: keep them after it,
+            // so they stay in flight for a whole iteration and nothing copies them
+            __builtin_amdgcn_sched_barrier(0);
+            nxt = fetch(jbase, base + kWave);
+            nid = fetch(jbase + id_step, 0);
+            active = __ballot(jr < j1);
+        }
+        __syncthreads();
+        const uint32_t width = j1 - j0;
+        for (uint32_t r = 0; r < n_here; ++r) {
+            uint16_t *out = sig + (row0 + r) * (uint64_t)k + j0;
+            const bool row_live = ((live >> r) & 1u) != 0;
+            for (uint32_t q = threadIdx.x; q < width; q += blockDim.x)
+                out[q] = row_live ? hbuf[r * hashes_per_tile + q] : (uint16_t)0;
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void fill_u32_kernel(uint32_t *p, uint32_t value, uint64_t n)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -690,12 +869,53 @@ struct OccupancyBatched {
     static int fail() { return 0; }
 };
 
+template <typename XT, bool kPacked>
+static void configure_rows()
+{
+    static bool configured = false;
+    if (!configured) {
+        hipFuncSetAttribute((const void *)rows_kernel<XT, kPacked>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64);
+        configured = true;
+    }
+}
+
+template <typename XT, bool kPacked>
+static int rows_occupancy_t(const BatchedPlan &plan, size_t lds)
+{
+    configure_rows<XT, kPacked>();
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, rows_kernel<XT, kPacked>,
+                                                     plan.waves_per_block * kWave, lds) != hipSuccess)
+        return 1;
+    return blocks > 0 ? blocks : 1;
+}
+
+template <typename XT, bool kPacked>
+static hipError_t launch_rows_t(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
+                                uint16_t *sig, const BatchedPlan &plan, const void *entries,
+                                uint32_t *tile_counter, uint32_t grid, hipStream_t stream)
+{
+    const size_t lds = batched_lds_bytes(b.dims, plan);
+    configure_rows<XT, kPacked>();
+    rows_kernel<XT, kPacked><<<grid, plan.waves_per_block * kWave, lds, stream>>>(
+        b, rows, k, seed, sig, plan.hashes_per_tile, plan.stream_depth, entries, tile_counter);
+    return hipGetLastError();
+}
+
 hipError_t launch_batched(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
                           uint16_t *sig, const BatchedPlan &plan, const void *entries,
                           uint32_t *tile_counter, uint32_t grid, hipStream_t stream)
 {
     if (batched_lds_bytes(b.dims, plan) > 160 * 1024 - 64) return hipErrorInvalidValue;
     if (plan.packed && !plan.narrow) return hipErrorInvalidValue;
+    if (plan.independent_rows) {
+        if (plan.rows_per_block != 4 || plan.stream_depth < kWave) return hipErrorInvalidValue;
+        if (plan.narrow)
+            return plan.packed ? launch_rows_t<uint16_t, true>(b, rows, k, seed, sig, plan, entries, tile_counter, grid, stream)
+                               : launch_rows_t<uint16_t, false>(b, rows, k, seed, sig, plan, entries, tile_counter, grid, stream);
+        return launch_rows_t<uint32_t, false>(b, rows, k, seed, sig, plan, entries, tile_counter, grid, stream);
+    }
     return dispatch_batched<LaunchBatched>(plan, b, rows, k, seed, sig, plan, entries,
                                            tile_counter, grid, stream);
 }
@@ -704,6 +924,12 @@ int batched_blocks_per_cu(uint32_t dims, const BatchedPlan &plan)
 {
     const size_t lds = batched_lds_bytes(dims, plan);
     if (lds > 160 * 1024 - 64) return 0;
+    if (plan.independent_rows) {
+        if (plan.rows_per_block != 4) return 0;
+        if (plan.narrow) return plan.packed ? rows_occupancy_t<uint16_t, true>(plan, lds)
+                                            : rows_occupancy_t<uint16_t, false>(plan, lds);
+        return rows_occupancy_t<uint32_t, false>(plan, lds);
+    }
     return dispatch_batched<OccupancyBatched>(plan, plan, lds);
 }
 

@@ -20,7 +20,7 @@ using namespace wmh;
 
 namespace {
 
-constexpr char kTuneHeader[] = "wmh-tune 1";
+constexpr char kTuneHeader[] = "wmh-tune 2";
 
 void put_entry(wmh_ctx *ctx, const TuneEntry &e)
 {
@@ -32,9 +32,10 @@ void put_entry(wmh_ctx *ctx, const TuneEntry &e)
     ctx->tuned.push_back(e);
 }
 
-bool valid_plan(uint32_t R, uint32_t J, uint32_t W)
+bool valid_plan(uint32_t R, uint32_t J, uint32_t W, int32_t walk)
 {
-    return (R == 1 || R == 2 || R == 4 || R == 8 || R == 16) && J >= 1 && W >= 1 && W <= 16;
+    return (R == 1 || R == 2 || R == 4 || R == 8 || R == 16) && J >= 1 && W >= 1 && W <= 16 &&
+           (walk == 1 || (walk == 2 && R == 4));
 }
 
 }  // namespace
@@ -72,8 +73,9 @@ wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         return fail(ctx, WMH_E_DEVICE, "hipEventCreate");
     }
     // best of `reps` timed calls after one untimed call; <0 when the plan does not fit
-    auto time_plan = [&](uint32_t R, uint32_t J, uint32_t W, float *ms) -> wmh_status {
+    auto time_plan = [&](uint32_t R, uint32_t J, uint32_t W, int32_t walk, float *ms) -> wmh_status {
         wmh_opts o = base;
+        o.walk = walk;
         o.mode = WMH_MODE_BATCHED;
         o.validate = 0;
         o.use_graph = 0;
@@ -101,31 +103,38 @@ wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
 
     wmh_tune_result res{};
     float default_ms = 0.f;
-    st = time_plan(def.rows_per_block, def.hashes_per_tile, def.waves_per_block, &default_ms);
+    st = time_plan(def.rows_per_block, def.hashes_per_tile, def.waves_per_block, 1, &default_ms);
     TuneEntry best;
     best.key = tune_key(ctx, k, stats);
     best.R = def.rows_per_block;
     best.J = def.hashes_per_tile;
     best.W = def.waves_per_block;
+    best.walk = 1;
     best.ms = default_ms;
     uint32_t tried = 1;
     std::vector<uint32_t> Js{std::min(k, 1024u), std::min(k, 512u), std::min(k, 256u)};
     Js.erase(std::unique(Js.begin(), Js.end()), Js.end());
-    for (uint32_t R : {1u, 2u, 4u, 8u, 16u}) {
-        for (uint32_t W : {4u, 8u, 16u}) {
-            for (uint32_t J : Js) {
-                if (st != WMH_OK) break;
-                if (R == def.rows_per_block && J == def.hashes_per_tile && W == def.waves_per_block)
-                    continue;
-                float ms = -1.f;
-                st = time_plan(R, J, W, &ms);
-                if (st == WMH_OK && ms >= 0.f) {
-                    ++tried;
-                    if (ms < best.ms) {
-                        best.R = R;
-                        best.J = J;
-                        best.W = W;
-                        best.ms = ms;
+    // shared windows for every R; independent rows at R = 4 (walk 2)
+    for (int32_t walk : {1, 2}) {
+        for (uint32_t R : {1u, 2u, 4u, 8u, 16u}) {
+            if (walk == 2 && R != 4) continue;
+            for (uint32_t W : {4u, 8u, 16u}) {
+                for (uint32_t J : Js) {
+                    if (st != WMH_OK) break;
+                    if (walk == 1 && R == def.rows_per_block && J == def.hashes_per_tile &&
+                        W == def.waves_per_block)
+                        continue;
+                    float ms = -1.f;
+                    st = time_plan(R, J, W, walk, &ms);
+                    if (st == WMH_OK && ms >= 0.f) {
+                        ++tried;
+                        if (ms < best.ms) {
+                            best.R = R;
+                            best.J = J;
+                            best.W = W;
+                            best.walk = walk;
+                            best.ms = ms;
+                        }
                     }
                 }
             }
@@ -143,6 +152,7 @@ wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
     res.default_ms = default_ms;
     res.candidates = tried;
     res.steps_class = best.key.steps_class;
+    res.walk = best.walk;
     *out = res;
     return WMH_OK;
 }
@@ -154,8 +164,8 @@ wmh_status wmh_tune_save(wmh_ctx *ctx, const char *path)
     if (!f) return fail(ctx, WMH_E_ARG, "cannot write %s", path);
     std::fprintf(f, "%s\n", kTuneHeader);
     for (const TuneEntry &e : ctx->tuned)
-        std::fprintf(f, "%u %d %u %d %u %u %u %.6f\n", e.key.dims, e.key.narrow ? 1 : 0, e.key.k,
-                     e.key.steps_class, e.R, e.J, e.W, (double)e.ms);
+        std::fprintf(f, "%u %d %u %d %u %u %u %d %.6f\n", e.key.dims, e.key.narrow ? 1 : 0,
+                     e.key.k, e.key.steps_class, e.R, e.J, e.W, e.walk, (double)e.ms);
     const bool ok = std::fclose(f) == 0;
     return ok ? WMH_OK : fail(ctx, WMH_E_ARG, "cannot write %s", path);
 }
@@ -173,9 +183,9 @@ wmh_status wmh_tune_load(wmh_ctx *ctx, const char *path)
         TuneEntry e;
         int narrow = 0;
         double ms = 0;
-        if (std::sscanf(line, "%u %d %u %d %u %u %u %lf", &e.key.dims, &narrow, &e.key.k,
-                        &e.key.steps_class, &e.R, &e.J, &e.W, &ms) != 8 ||
-            (narrow != 0 && narrow != 1) || !valid_plan(e.R, e.J, e.W) || e.key.k == 0) {
+        if (std::sscanf(line, "%u %d %u %d %u %u %u %d %lf", &e.key.dims, &narrow, &e.key.k,
+                        &e.key.steps_class, &e.R, &e.J, &e.W, &e.walk, &ms) != 9 ||
+            (narrow != 0 && narrow != 1) || !valid_plan(e.R, e.J, e.W, e.walk) || e.key.k == 0) {
             ok = false;
             break;
         }

@@ -20,6 +20,7 @@ STATUS = {0: "WMH_OK", -1: "WMH_E_ARG", -2: "WMH_E_NO_BOUNDS", -3: "WMH_E_COL_RA
           -4: "WMH_E_UNSORTED", -5: "WMH_E_BOUND", -6: "WMH_E_OVERFLOW", -7: "WMH_E_NOMEM",
           -8: "WMH_E_DEVICE", -9: "WMH_E_ROW_PTR"}
 MODES = {"auto": 0, "plain": 1, "batched": 2, "indexed": 3}
+WALKS = {"auto": 0, "shared": 1, "rows": 2}
 
 EXPORTED = ["wmh_opts_init", "wmh_create", "wmh_destroy", "wmh_set_bounds", "wmh_hash",
             "wmh_estimate", "wmh_collisions", "wmh_bounds_info", "wmh_bounds_tables",
@@ -35,7 +36,7 @@ class WmhOpts(ctypes.Structure):
                 ("sync", ctypes.c_int32), ("rows_per_block", ctypes.c_uint32),
                 ("hashes_per_tile", ctypes.c_uint32), ("stream_depth", ctypes.c_uint32),
                 ("waves_per_block", ctypes.c_uint32), ("profile", ctypes.c_int32),
-                ("reserved", ctypes.c_uint32 * 5)]
+                ("walk", ctypes.c_int32), ("reserved", ctypes.c_uint32 * 4)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -59,7 +60,7 @@ class TuneResult(ctypes.Structure):
                 ("waves_per_block", ctypes.c_uint32), ("stream_depth", ctypes.c_uint32),
                 ("best_ms", ctypes.c_float), ("default_ms", ctypes.c_float),
                 ("candidates", ctypes.c_uint32), ("steps_class", ctypes.c_int32),
-                ("reserved", ctypes.c_uint32 * 4)]
+                ("walk", ctypes.c_int32), ("reserved", ctypes.c_uint32 * 3)]
 
 
 class WMHError(RuntimeError):
@@ -252,7 +253,7 @@ class Context:
     @staticmethod
     def make_opts(mode="auto", batch_rows=0, validate=True, use_graph=True, sync=True,
                   rows_per_block=0, hashes_per_tile=0, stream_depth=0, waves_per_block=0,
-                  profile=False) -> WmhOpts:
+                  profile=False, walk=0) -> WmhOpts:
         o = WmhOpts()
         load().wmh_opts_init(ctypes.byref(o))
         o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
@@ -266,6 +267,7 @@ class Context:
         o.stream_depth = 0xFFFFFFFF if stream_depth is None else stream_depth
         o.waves_per_block = waves_per_block
         o.profile = int(bool(profile))
+        o.walk = WALKS[walk] if isinstance(walk, str) else int(walk)
         return o
 
     def last_kernel_ms(self) -> tuple[float, float]:
@@ -287,7 +289,8 @@ class Context:
         self._check(self._lib.wmh_last_plan(self._ptr, ctypes.byref(o)), "wmh_last_plan")
         return {"mode": {v: k for k, v in MODES.items()}[o.mode],
                 "rows_per_block": o.rows_per_block, "hashes_per_tile": o.hashes_per_tile,
-                "stream_depth": o.stream_depth, "waves_per_block": o.waves_per_block}
+                "stream_depth": o.stream_depth, "waves_per_block": o.waves_per_block,
+                "walk": {v: k for k, v in WALKS.items()}.get(o.walk, o.walk)}
 
     def tune(self, rows: DeviceRows, k: int, seed: int = 0, reps: int = 3, stream=None) -> dict:
         """Autotunes the batched tile plan on these rows (see wmh_tune); returns the result and
@@ -302,7 +305,8 @@ class Context:
         return {"rows_per_block": r.rows_per_block, "hashes_per_tile": r.hashes_per_tile,
                 "waves_per_block": r.waves_per_block, "stream_depth": r.stream_depth,
                 "best_ms": r.best_ms, "default_ms": r.default_ms, "candidates": r.candidates,
-                "steps_class": r.steps_class}
+                "steps_class": r.steps_class,
+                "walk": {v: k for k, v in WALKS.items()}.get(r.walk, r.walk)}
 
     def tune_save(self, path: str):
         self._check(self._lib.wmh_tune_save(self._ptr, os.fsencode(path)), "wmh_tune_save")

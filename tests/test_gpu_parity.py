@@ -110,6 +110,8 @@ def test_draws_with_zero_bounds_and_clusters(ctx):
     dict(mode="plain", batch_rows=100),
     dict(mode="batched"),
     dict(mode="batched", use_graph=False),
+    dict(mode="batched", walk="rows"),
+    dict(mode="batched", walk="rows", use_graph=False, hashes_per_tile=17),
     dict(mode="auto"),
 ])
 def test_config1_full(ctx, opts):
@@ -125,6 +127,10 @@ BATCHED_PLANS = [
     dict(rows_per_block=8, waves_per_block=1), dict(rows_per_block=2, waves_per_block=16),
     dict(rows_per_block=4, stream_depth=None),   # every draw made in-lane
     dict(rows_per_block=4, stream_depth=64),     # stream for the first window only
+    # independent rows: each row of a block walks its own hash ids
+    dict(walk="rows"), dict(walk="rows", hashes_per_tile=7),
+    dict(walk="rows", waves_per_block=1), dict(walk="rows", waves_per_block=16),
+    dict(walk="rows", stream_depth=None), dict(walk="rows", stream_depth=128),
 ]
 
 CASES = {
@@ -165,7 +171,9 @@ def test_full_rows_hash_to_one_and_saturation(ctx):
     want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, k, seed=5)
     assert np.all(want[0] == 1) and np.all(want[1] == 65535)
     for opts in (dict(mode="plain"), dict(mode="batched", rows_per_block=4),
-                 dict(mode="batched", rows_per_block=2, stream_depth=128)):
+                 dict(mode="batched", rows_per_block=2, stream_depth=128),
+                 dict(mode="batched", walk="rows"),
+                 dict(mode="batched", walk="rows", stream_depth=None)):
         assert_same(gpu_sig(ctx, ds, k, 5, **opts), want, f"saturation {opts}")
 
 
@@ -192,6 +200,8 @@ def test_config2_head(ctx):
     want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, 500, seed=0)
     assert_same(gpu_sig(ctx, ds, 500, 0, mode="plain"), want, "config2 head plain")
     assert_same(gpu_sig(ctx, ds, 500, 0, mode="batched"), want, "config2 head batched")
+    assert_same(gpu_sig(ctx, ds, 500, 0, mode="batched", walk="rows"), want,
+                "config2 head independent rows")
 
 
 @pytest.fixture(scope="module")

@@ -28,7 +28,7 @@ def ds():
 
 
 def _plan_of(res):
-    return (res["rows_per_block"], res["hashes_per_tile"], res["waves_per_block"])
+    return (res["rows_per_block"], res["hashes_per_tile"], res["waves_per_block"], res["walk"])
 
 
 def test_tune_then_hash_uses_the_plan(ctx, ds):
@@ -45,8 +45,7 @@ def test_tune_then_hash_uses_the_plan(ctx, ds):
         assert np.array_equal(got, want)
         plan = ctx.last_plan()
         assert plan["mode"] == "batched"
-        assert (plan["rows_per_block"], plan["hashes_per_tile"], plan["waves_per_block"]) \
-            == _plan_of(res)
+        assert _plan_of(plan) == _plan_of(res)
     # an explicit override wins over the tuned plan
     ctx.hash(rows, ds.k, seed=0, mode="batched", rows_per_block=16, waves_per_block=4)
     assert ctx.last_plan()["rows_per_block"] == 16
@@ -74,16 +73,16 @@ def test_save_and_load(ctx, ds, tmp_path):
     res = ctx.tune(rows, ds.k, seed=0, reps=1)
     path = tmp_path / "plans.txt"
     ctx.tune_save(str(path))
-    assert path.read_text().startswith("wmh-tune 1\n")
+    assert path.read_text().startswith("wmh-tune 2\n")
     fresh = wmh.Context(0)
     try:
         fresh.set_bounds(ds.m)
         fresh.tune_load(str(path))
         fresh.hash(rows, ds.k, seed=0, mode="batched")
         p = fresh.last_plan()
-        assert (p["rows_per_block"], p["hashes_per_tile"], p["waves_per_block"]) == _plan_of(res)
+        assert _plan_of(p) == _plan_of(res)
         bad = tmp_path / "bad.txt"
-        bad.write_text("wmh-tune 1\n1024 0 64 4 3 64 8 0.5\n")  # R = 3 is not a plan
+        bad.write_text("wmh-tune 2\n1024 0 64 4 3 64 8 1 0.5\n")  # R = 3 is not a plan
         with pytest.raises(wmh.WMHError) as e:
             fresh.tune_load(str(bad))
         assert e.value.name == "WMH_E_ARG"
