@@ -225,6 +225,28 @@ def heavy_tail_bench(args, torch, synth, wmh) -> dict:
                          "compares_per_s": 1e8 * k / (ms / 1e3),
                          "sampled_pairs_exact": exact, "sampled_pairs": len(a_idx)}
     log(f"heavy-tail: all-pairs collisions {ms:.2f} ms, sample exact {exact}")
+    # the same counts on b-bit packed signatures (lossless width)
+    bits, top = ctx.sig_bits(sig_b, stream=stream.cuda_stream)
+    packed, sat = ctx.pack(sig_b, bits, stream=stream.cuda_stream)
+    PA, PB = packed[0:10000].contiguous(), packed[10000:20000].contiguous()
+    pcounts = ctx.packed_collisions(PA, PB, k, bits, stream=stream.cuda_stream)
+    ptimes = []
+    for _ in range(3):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        pcounts = ctx.packed_collisions(PA, PB, k, bits, stream=stream.cuda_stream)
+        e1.record(stream)
+        e1.synchronize()
+        ptimes.append(e0.elapsed_time(e1))
+    pms = float(np.median(ptimes))
+    out["packed"] = {"bits": bits, "max_value": top, "saturated": sat,
+                     "words_per_row": int(packed.shape[1]),
+                     "bytes_per_row": int(packed.shape[1]) * 4, "u16_bytes_per_row": 2 * k,
+                     "collisions_ms": pms, "speedup_over_u16": ms / pms,
+                     "counts_equal_u16": bool(torch.equal(pcounts, counts))}
+    log(f"heavy-tail: packed at {bits} bits: {packed.shape[1] * 4} B/row vs {2 * k}, "
+        f"collisions {pms:.2f} ms, equal {out['packed']['counts_equal_u16']}")
     ctx.close()
     return out
 

@@ -221,6 +221,56 @@ wmh_status wmh_last_mode(const wmh_ctx *ctx, int32_t *mode);
 wmh_status wmh_last_plan(const wmh_ctx *ctx, wmh_opts *plan);
 
 /* ------------------------------------------------------------------------------------------ */
+/* b-bit signatures.  Hash values are geometric with mean 1/s (Theorem 2) and so small with    */
+/* high probability (Corollary 1; Table 3 reports 5-9 bits on the paper's data).  Layout of a  */
+/* packed row: f = floor(32 / bits) fields per uint32 word, W = ceil(k / f) words; value j is  */
+/* in word j / f at bit (j mod f) * bits; unused bits and fields are 0; a value above          */
+/* 2^bits - 1 is stored as 2^bits - 1 (saturated: lossless iff bits >= wmh_sig_bits).          */
+/* ------------------------------------------------------------------------------------------ */
+
+/* Words per packed row, ceil(k / floor(32 / bits)); 0 if bits is not in [1, 16] or k = 0.
+ * Host only. */
+uint32_t wmh_pack_words(uint32_t k, uint32_t bits);
+
+/*
+ * wmh_sig_bits -- the smallest width that packs these signatures losslessly: the least
+ * bits >= 1 with max < 2^bits.  sig: device, N*k uint16.  *bits (host) receives it, *max_value
+ * (host, may be NULL) the largest value.  Synchronous.  Errors: WMH_E_ARG, WMH_E_DEVICE.
+ */
+wmh_status wmh_sig_bits(wmh_ctx *ctx, const uint16_t *sig, uint64_t n_rows, uint32_t k,
+                        uint32_t *bits, uint32_t *max_value, void *stream);
+
+/*
+ * wmh_pack -- packs N signatures of k values into bits-wide fields (layout above).
+ *   sig : device, N*k uint16.   packed : device, N*W uint32.   bits : 1..16.
+ *   *n_saturated (host, may be NULL): how many values exceeded 2^bits - 1.  Synchronous.
+ * Errors: WMH_E_ARG, WMH_E_DEVICE.
+ */
+wmh_status wmh_pack(wmh_ctx *ctx, const uint16_t *sig, uint64_t n_rows, uint32_t k,
+                    uint32_t bits, uint32_t *packed, uint64_t *n_saturated, void *stream);
+
+/* wmh_unpack -- the inverse: sig (device, N*k uint16) from packed (device, N*W uint32);
+ * saturated values come back as 2^bits - 1.  Synchronous.  Errors: WMH_E_ARG, WMH_E_DEVICE. */
+wmh_status wmh_unpack(wmh_ctx *ctx, const uint32_t *packed, uint64_t n_rows, uint32_t k,
+                      uint32_t bits, uint16_t *sig, void *stream);
+
+/*
+ * wmh_packed_collisions -- wmh_collisions on packed rows: counts[a*NB + b] = number of equal
+ * fields of A row a and B row b (exact uint32); equals wmh_collisions on the unpacked values.
+ * A : device, NA*W uint32.  B : device, NB*W uint32.  counts : device, NA*NB uint32.
+ * Synchronous.  Errors: WMH_E_ARG, WMH_E_DEVICE.
+ */
+wmh_status wmh_packed_collisions(wmh_ctx *ctx, const uint32_t *A, uint64_t NA, const uint32_t *B,
+                                 uint64_t NB, uint32_t k, uint32_t bits, uint32_t *counts,
+                                 void *stream);
+
+/* wmh_packed_estimate -- wmh_estimate on packed, row-aligned pairs (count and/or jhat, device).
+ * Synchronous.  Errors: WMH_E_ARG, WMH_E_DEVICE. */
+wmh_status wmh_packed_estimate(wmh_ctx *ctx, const uint32_t *A, const uint32_t *B,
+                               uint64_t n_pairs, uint32_t k, uint32_t bits, uint32_t *count,
+                               double *jhat, void *stream);
+
+/* ------------------------------------------------------------------------------------------ */
 /* Autotuner of the batched tile plan (scheduling only: every plan gives the same bytes).      */
 /* ------------------------------------------------------------------------------------------ */
 

@@ -101,6 +101,8 @@ struct wmh_ctx {
     wmh::CheckWords *d_check = nullptr;
     wmh::CheckWords *h_check = nullptr;  // pinned
     uint32_t *d_tile_counter = nullptr;
+    unsigned long long *d_codec = nullptr;  // codec counters: saturated values, maximum
+    unsigned long long *h_codec = nullptr;  // pinned copy
     void *d_stream = nullptr;
     size_t stream_bytes = 0;
     // graph of the batched launch

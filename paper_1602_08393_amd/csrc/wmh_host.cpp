@@ -398,6 +398,8 @@ wmh_status wmh_create(int device, wmh_ctx **out)
         hipMalloc(&ctx->d_check, sizeof(CheckWords)) != hipSuccess ||
         hipHostMalloc(&ctx->h_check, sizeof(CheckWords), hipHostMallocDefault) != hipSuccess ||
         hipMalloc(&ctx->d_tile_counter, sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&ctx->d_codec, 2 * sizeof(unsigned long long)) != hipSuccess ||
+        hipHostMalloc(&ctx->h_codec, 2 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
         hipEventCreate(&ctx->ev[0]) != hipSuccess || hipEventCreate(&ctx->ev[1]) != hipSuccess ||
         hipEventCreate(&ctx->ev[2]) != hipSuccess) {
         wmh_destroy(ctx);
@@ -419,6 +421,8 @@ void wmh_destroy(wmh_ctx *ctx)
     if (ctx->d_check) hipFree(ctx->d_check);
     if (ctx->h_check) hipHostFree(ctx->h_check);
     if (ctx->d_tile_counter) hipFree(ctx->d_tile_counter);
+    if (ctx->d_codec) hipFree(ctx->d_codec);
+    if (ctx->h_codec) hipHostFree(ctx->h_codec);
     for (hipEvent_t &e : ctx->ev)
         if (e) hipEventDestroy(e);
     if (ctx->own_stream) hipStreamDestroy(ctx->own_stream);

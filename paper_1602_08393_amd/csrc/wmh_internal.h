@@ -115,4 +115,17 @@ hipError_t launch_index_rows(const Rows &rows, const IndexBuffers &ix, uint32_t 
 // Resident workgroups per CU of the index row kernel.
 int index_rows_blocks_per_cu(uint32_t k);
 
+// b-bit signatures (wmh_codec.hip): f = 32 / bits fields per word, W = ceil(k / f) words a row.
+uint32_t pack_words(uint32_t k, uint32_t bits);  // 0 when bits is not in [1, 16] or k = 0
+hipError_t launch_pack(const uint16_t *sig, uint64_t n_rows, uint32_t k, uint32_t bits,
+                       uint32_t *packed, unsigned long long *saturated, hipStream_t stream);
+hipError_t launch_unpack(const uint32_t *packed, uint64_t n_rows, uint32_t k, uint32_t bits,
+                         uint16_t *sig, hipStream_t stream);
+hipError_t launch_sig_max(const uint16_t *sig, uint64_t n, uint32_t *max_value, hipStream_t stream);
+hipError_t launch_packed_collisions(const uint32_t *A, uint64_t na, const uint32_t *B, uint64_t nb,
+                                    uint32_t k, uint32_t bits, uint32_t *counts, hipStream_t stream);
+hipError_t launch_packed_estimate(const uint32_t *A, const uint32_t *B, uint64_t n_pairs,
+                                  uint32_t k, uint32_t bits, uint32_t *count, double *jhat,
+                                  hipStream_t stream);
+
 }  // namespace wmh

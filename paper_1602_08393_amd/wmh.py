@@ -25,7 +25,9 @@ WALKS = {"auto": 0, "shared": 1, "rows": 2}
 EXPORTED = ["wmh_opts_init", "wmh_create", "wmh_destroy", "wmh_set_bounds", "wmh_hash",
             "wmh_estimate", "wmh_collisions", "wmh_bounds_info", "wmh_bounds_tables",
             "wmh_draws", "wmh_last_kernel_ms", "wmh_last_mode", "wmh_last_plan",
-            "wmh_tune", "wmh_tune_save", "wmh_tune_load", "wmh_last_error", "wmh_status_string",
+            "wmh_tune", "wmh_tune_save", "wmh_tune_load", "wmh_pack_words", "wmh_sig_bits",
+            "wmh_pack", "wmh_unpack", "wmh_packed_collisions", "wmh_packed_estimate",
+            "wmh_last_error", "wmh_status_string",
             "wmh_server_create", "wmh_server_submit", "wmh_server_poll", "wmh_server_wait",
             "wmh_server_drain", "wmh_server_stats", "wmh_server_now_ns", "wmh_server_destroy"]
 
@@ -117,6 +119,18 @@ def load() -> ctypes.CDLL:
     L.wmh_tune_save.restype = ctypes.c_int
     L.wmh_tune_load.argtypes = [vp, ctypes.c_char_p]
     L.wmh_tune_load.restype = ctypes.c_int
+    L.wmh_pack_words.argtypes = [u32, u32]
+    L.wmh_pack_words.restype = ctypes.c_uint32
+    L.wmh_sig_bits.argtypes = [vp, vp, u64, u32, ctypes.POINTER(u32), ctypes.POINTER(u32), vp]
+    L.wmh_sig_bits.restype = ctypes.c_int
+    L.wmh_pack.argtypes = [vp, vp, u64, u32, u32, vp, ctypes.POINTER(u64), vp]
+    L.wmh_pack.restype = ctypes.c_int
+    L.wmh_unpack.argtypes = [vp, vp, u64, u32, u32, vp, vp]
+    L.wmh_unpack.restype = ctypes.c_int
+    L.wmh_packed_collisions.argtypes = [vp, vp, u64, vp, u64, u32, u32, vp, vp]
+    L.wmh_packed_collisions.restype = ctypes.c_int
+    L.wmh_packed_estimate.argtypes = [vp, vp, vp, u64, u32, u32, vp, vp, vp]
+    L.wmh_packed_estimate.restype = ctypes.c_int
     L.wmh_draws.argtypes = [vp, u64, u32, u32, u32, vp, vp, vp, vp]
     L.wmh_draws.restype = ctypes.c_int
     L.wmh_server_create.argtypes = [vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
@@ -353,6 +367,54 @@ class Context:
         self._check(self._lib.wmh_estimate(self._ptr, A.data_ptr(), B.data_ptr(), n, k,
                                            count.data_ptr(), jhat.data_ptr(),
                                            self._stream(stream)), "wmh_estimate")
+        return count, jhat
+
+    # -- b-bit signatures ------------------------------------------------------------------
+
+    def sig_bits(self, sig, stream=None) -> tuple[int, int]:
+        """(smallest lossless width, largest value) of device signatures [N, k]."""
+        n, k = sig.shape
+        b, m = ctypes.c_uint32(), ctypes.c_uint32()
+        self._check(self._lib.wmh_sig_bits(self._ptr, sig.data_ptr(), n, k, ctypes.byref(b),
+                                           ctypes.byref(m), self._stream(stream)), "wmh_sig_bits")
+        return b.value, m.value
+
+    def pack(self, sig, bits: int, stream=None):
+        """(packed int32 tensor [N, W], number of saturated values)."""
+        torch = _torch()
+        n, k = sig.shape
+        words = self._lib.wmh_pack_words(k, bits)
+        packed = torch.empty((n, max(words, 1)), dtype=torch.int32, device=sig.device)
+        sat = ctypes.c_uint64()
+        self._check(self._lib.wmh_pack(self._ptr, sig.data_ptr(), n, k, bits, packed.data_ptr(),
+                                       ctypes.byref(sat), self._stream(stream)), "wmh_pack")
+        return packed, sat.value
+
+    def unpack(self, packed, k: int, bits: int, stream=None):
+        torch = _torch()
+        n = packed.shape[0]
+        sig = torch.empty((n, k), dtype=torch.int16, device=packed.device)
+        self._check(self._lib.wmh_unpack(self._ptr, packed.data_ptr(), n, k, bits, sig.data_ptr(),
+                                         self._stream(stream)), "wmh_unpack")
+        return sig
+
+    def packed_collisions(self, A, B, k: int, bits: int, stream=None):
+        torch = _torch()
+        na, nb = A.shape[0], B.shape[0]
+        counts = torch.empty((na, nb), dtype=torch.int32, device=A.device)
+        self._check(self._lib.wmh_packed_collisions(self._ptr, A.data_ptr(), na, B.data_ptr(), nb,
+                                                    k, bits, counts.data_ptr(),
+                                                    self._stream(stream)), "wmh_packed_collisions")
+        return counts
+
+    def packed_estimate(self, A, B, k: int, bits: int, stream=None):
+        torch = _torch()
+        n = A.shape[0]
+        count = torch.empty(n, dtype=torch.int32, device=A.device)
+        jhat = torch.empty(n, dtype=torch.float64, device=A.device)
+        self._check(self._lib.wmh_packed_estimate(self._ptr, A.data_ptr(), B.data_ptr(), n, k,
+                                                  bits, count.data_ptr(), jhat.data_ptr(),
+                                                  self._stream(stream)), "wmh_packed_estimate")
         return count, jhat
 
     def collisions(self, A, B, stream=None):
