@@ -271,6 +271,42 @@ wmh_status wmh_packed_estimate(wmh_ctx *ctx, const uint32_t *A, const uint32_t *
                                double *jhat, void *stream);
 
 /* ------------------------------------------------------------------------------------------ */
+/* Fixed-point scaling of real-valued data (Sec. 4, Practical Issues).  The expected step count */
+/* is M / sum(x) (Theorem 2); scaling by alpha and rounding up the bounds gives                 */
+/* alpha * sum(x) / sum(ceil(alpha * m_i)), which the paper asks to maximize.  sum(x) is a      */
+/* common factor, so the best alpha depends on the bounds only.                                 */
+/* ------------------------------------------------------------------------------------------ */
+
+/*
+ * wmh_choose_scale -- host only.  m: host, D real bounds (finite, >= 0, not all 0).  limit: the
+ * largest integer bound allowed (65535 lets the batched walk keep 16-bit rows and 4-byte stream
+ * entries; 0 = 2^32 - 1).  Searches alpha <= limit / max(m): the largest such scale and the
+ * points n / m_i just below it (where alpha * m_i is an integer) for the `components` largest
+ * bounds (0 = 8), `steps` points each (0 = 8), keeping the one with the largest
+ * alpha / sum(ceil(alpha * m_i)).
+ *   *alpha_out: the scale.   *efficiency (may be NULL): alpha * sum(m) / sum(ceil(alpha * m)),
+ *   in (0, 1]: the expected step count grows by 1 / efficiency against unrounded bounds.
+ *   m_q (host, D, may be NULL): ceil(alpha * m_i), the integer bounds to pass to wmh_set_bounds.
+ * Errors: WMH_E_ARG (null, D = 0, a bound negative or not finite), WMH_E_OVERFLOW (all 0).
+ */
+wmh_status wmh_choose_scale(const double *m, uint32_t D, uint32_t limit, uint32_t components,
+                            uint32_t steps, double *alpha_out, double *efficiency,
+                            uint32_t *m_q);
+
+/*
+ * wmh_quantize -- real CSR values to the library's fixed point:
+ *   out[e] = min(floor(alpha * x[e] + 1/2), m_q[col[e]]) with m_q the context's bounds (set
+ *   from wmh_choose_scale's m_q); alpha * x and + 1/2 are IEEE double operations rounded one
+ *   at a time, so a host computing the same expression gets the same integers.
+ *   x : device, nnz float32 (>= 0; negative values give 0).   col : device, nnz uint32.
+ *   out : device, nnz uint32.   *n_clipped (host, may be NULL): values above their bound
+ *   (only possible when x exceeded the real bound).  Synchronous.
+ * Errors: WMH_E_ARG, WMH_E_NO_BOUNDS, WMH_E_DEVICE.
+ */
+wmh_status wmh_quantize(wmh_ctx *ctx, const float *x, const uint32_t *col, uint64_t nnz,
+                        double alpha, uint32_t *out, uint64_t *n_clipped, void *stream);
+
+/* ------------------------------------------------------------------------------------------ */
 /* Autotuner of the batched tile plan (scheduling only: every plan gives the same bytes).      */
 /* ------------------------------------------------------------------------------------------ */
 

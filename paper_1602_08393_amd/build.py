@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwmh.so")
 SOURCES = ["wmh_host.cpp", "wmh_server.cpp", "wmh_kernels.hip", "wmh_collide.hip", "wmh_index.hip",
-           "wmh_tune.cpp", "wmh_codec.hip", "wmh_codec_host.cpp"]
+           "wmh_tune.cpp", "wmh_codec.hip", "wmh_codec_host.cpp",
+           "wmh_quantize.hip", "wmh_scale.cpp"]
 ARCH = "gfx950"
 
 

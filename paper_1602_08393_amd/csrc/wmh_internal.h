@@ -124,6 +124,9 @@ hipError_t launch_unpack(const uint32_t *packed, uint64_t n_rows, uint32_t k, ui
 hipError_t launch_sig_max(const uint16_t *sig, uint64_t n, uint32_t *max_value, hipStream_t stream);
 hipError_t launch_packed_collisions(const uint32_t *A, uint64_t na, const uint32_t *B, uint64_t nb,
                                     uint32_t k, uint32_t bits, uint32_t *counts, hipStream_t stream);
+hipError_t launch_quantize(const float *x, uint64_t n, const uint32_t *col, const uint32_t *bound_q,
+                           uint32_t dims, double alpha, uint32_t *out, unsigned long long *clipped,
+                           hipStream_t stream);
 hipError_t launch_packed_estimate(const uint32_t *A, const uint32_t *B, uint64_t n_pairs,
                                   uint32_t k, uint32_t bits, uint32_t *count, double *jhat,
                                   hipStream_t stream);

@@ -27,6 +27,7 @@ EXPORTED = ["wmh_opts_init", "wmh_create", "wmh_destroy", "wmh_set_bounds", "wmh
             "wmh_draws", "wmh_last_kernel_ms", "wmh_last_mode", "wmh_last_plan",
             "wmh_tune", "wmh_tune_save", "wmh_tune_load", "wmh_pack_words", "wmh_sig_bits",
             "wmh_pack", "wmh_unpack", "wmh_packed_collisions", "wmh_packed_estimate",
+            "wmh_choose_scale", "wmh_quantize",
             "wmh_last_error", "wmh_status_string",
             "wmh_server_create", "wmh_server_submit", "wmh_server_poll", "wmh_server_wait",
             "wmh_server_drain", "wmh_server_stats", "wmh_server_now_ns", "wmh_server_destroy"]
@@ -131,6 +132,11 @@ def load() -> ctypes.CDLL:
     L.wmh_packed_collisions.restype = ctypes.c_int
     L.wmh_packed_estimate.argtypes = [vp, vp, vp, u64, u32, u32, vp, vp, vp]
     L.wmh_packed_estimate.restype = ctypes.c_int
+    L.wmh_choose_scale.argtypes = [vp, u32, u32, u32, u32, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double), vp]
+    L.wmh_choose_scale.restype = ctypes.c_int
+    L.wmh_quantize.argtypes = [vp, vp, vp, u64, ctypes.c_double, vp, ctypes.POINTER(u64), vp]
+    L.wmh_quantize.restype = ctypes.c_int
     L.wmh_draws.argtypes = [vp, u64, u32, u32, u32, vp, vp, vp, vp]
     L.wmh_draws.restype = ctypes.c_int
     L.wmh_server_create.argtypes = [vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
@@ -156,6 +162,18 @@ def load() -> ctypes.CDLL:
     L.wmh_status_string.restype = ctypes.c_char_p
     _lib = L
     return L
+
+
+def choose_scale(m, limit: int = 0, components: int = 0, steps: int = 0):
+    """Host-only scale choice (see wmh_choose_scale): (alpha, efficiency, integer bounds)."""
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    mq = np.zeros(len(m), dtype=np.uint32)
+    a, eff = ctypes.c_double(), ctypes.c_double()
+    st = load().wmh_choose_scale(m.ctypes.data, len(m), limit, components, steps,
+                                 ctypes.byref(a), ctypes.byref(eff), mq.ctypes.data)
+    if st != 0:
+        raise WMHError(st, "wmh_choose_scale")
+    return a.value, eff.value, mq
 
 
 def bounds_tables(m: np.ndarray) -> dict:
@@ -368,6 +386,16 @@ class Context:
                                            count.data_ptr(), jhat.data_ptr(),
                                            self._stream(stream)), "wmh_estimate")
         return count, jhat
+
+    def quantize(self, x, col, alpha: float, stream=None):
+        """(uint32 values as an int32 tensor, number clipped) from device float32 x."""
+        torch = _torch()
+        out = torch.empty(x.shape[0], dtype=torch.int32, device=x.device)
+        clipped = ctypes.c_uint64()
+        self._check(self._lib.wmh_quantize(self._ptr, x.data_ptr(), col.data_ptr(), x.shape[0],
+                                           alpha, out.data_ptr(), ctypes.byref(clipped),
+                                           self._stream(stream)), "wmh_quantize")
+        return out, clipped.value
 
     # -- b-bit signatures ------------------------------------------------------------------
 
