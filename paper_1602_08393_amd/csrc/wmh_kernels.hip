@@ -295,8 +295,15 @@ __global__ __launch_bounds__(256) void draws_kernel(Bounds b, uint64_t seed, uin
 // widest aligned loads: the first entry index is a multiple of K.
 template <int K, bool kPacked>
 struct EntryRun {
-    static constexpr int kWords = K * (kPacked ? 1 : 2);
+    static constexpr int kWordsPerEntry = kPacked ? 1 : 2;
+    static constexpr int kWords = K * kWordsPerEntry;
     uint32_t w[kWords];
+
+    // the run starting `lane_word` words after a (wave-uniform) window start
+    __device__ __forceinline__ void load_at(const uint32_t *window, uint32_t lane_word)
+    {
+        load(window + lane_word, 0);
+    }
 
     __device__ __forceinline__ void load(const void *entries, uint64_t index)
     {
@@ -340,6 +347,31 @@ __device__ __forceinline__ uint64_t row_lanes(uint32_t r)
     else return ((1ull << L) - 1ull) << (r * L);
 }
 
+// min(v, v of the lane the DPP control selects); lanes outside the written rows, or whose
+// source lies outside their row, keep v.
+template <int kCtrl, int kRows>
+__device__ __forceinline__ uint32_t dpp_min(uint32_t v)
+{
+    const uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFFu, (int)v, kCtrl,
+                                                             kRows, 0xF, false);
+    return min(v, t);
+}
+
+// Minimum of v over each group of L consecutive lanes (L a power of two <= 64), left in the
+// group's last lane: prefix minima by row shifts inside 16-lane DPP rows, then row broadcasts
+// (lane 15 into the next row, lane 31 into rows 2 and 3) for groups of 32 and 64 lanes.
+template <uint32_t L>
+__device__ __forceinline__ uint32_t group_min_at_last_lane(uint32_t v)
+{
+    if constexpr (L >= 2) v = dpp_min<0x111, 0xF>(v);   // row_shr:1
+    if constexpr (L >= 4) v = dpp_min<0x112, 0xF>(v);   // row_shr:2
+    if constexpr (L >= 8) v = dpp_min<0x114, 0xF>(v);   // row_shr:4
+    if constexpr (L >= 16) v = dpp_min<0x118, 0xF>(v);  // row_shr:8
+    if constexpr (L >= 32) v = dpp_min<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    if constexpr (L >= 64) v = dpp_min<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 // Up to four rows per block the walk fits eight wavefronts per SIMD (at most 64 VGPRs and a
 // few scalar registers spilled to vector lanes); wider blocks keep their registers.
 template <int R>
@@ -368,6 +400,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
     const uint32_t my_grp = lane() % L;
     constexpr uint32_t kScale = R * sizeof(XT);  // LDS bytes per component group
     const uint32_t row_byte = my_row * sizeof(XT);
+    // 1 + position in a window of each of the lane's K steps; offset of its run in words
+    uint32_t step_in_window[K];
+#pragma unroll
+    for (int q = 0; q < (int)K; ++q) step_in_window[q] = my_grp * K + q + 1u;
+    const uint32_t lane_words = my_grp * K * EntryRun<K, kPacked>::kWordsPerEntry;
 
     const uint64_t n_blocks = (rows.n_rows + R - 1) / R;
     const uint32_t n_hash_tiles = (k + hashes_per_tile - 1) / hashes_per_tile;
@@ -429,26 +466,31 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
             const uint32_t j = j0 + ((uint32_t)__builtin_amdgcn_readfirstlane(claimed) >> 6);
             if (j >= j1) break;
 
-            // Each lane keeps the first green step among its own steps (0: none yet); a row's
-            // hash is the smallest of its lanes' values, since together they cover every step.
-            uint32_t lane_h = 0;
+            // Each lane keeps the first green step among its own steps (kNoStep: none yet); a
+            // row's hash is the smallest of its lanes' values, since together they cover every
+            // step, and a row whose smallest value is above the cap saturates at 65535.
+            constexpr uint32_t kNoStep = 0xFFFFFFFFu;
+            constexpr uint32_t kNotGreen = 0x10000u;  // base + kNotGreen is past the cap
+            uint32_t lane_h = kNoStep;
             bool walking = live != 0;
             // The stream holds depth >= 64 steps per hash id.  Entries are prefetched three
             // windows ahead into a ring of three register sets, each reloaded in place right
             // after its window is tested; the loads use clamped, in-bounds indices (windows
             // past the stream re-read its last window and ignore it) so they stay straight-line
-            // code and no register with a load in flight is ever copied.
-            const uint64_t lane_first = (uint64_t)j * depth + my_grp * K;
+            // code and no register with a load in flight is ever copied.  The window's address
+            // is scalar; each lane adds its own 32-bit offset.
+            const uint32_t *id_entries = reinterpret_cast<const uint32_t *>(entries) +
+                                         (uint64_t)j * depth * EntryRun<K, kPacked>::kWordsPerEntry;
             const uint32_t last_base = depth - kWave;
             auto fetch = [&](uint32_t base) {
                 EntryRun<K, kPacked> run;
-                run.load(entries, lane_first + min(base, last_base));
+                run.load_at(id_entries + (size_t)min(base, last_base) * EntryRun<K, kPacked>::kWordsPerEntry,
+                            lane_words);
                 return run;
             };
-            // tests window [base + 1, base + 64]; false once the walk is over
-            auto window = [&](const EntryRun<K, kPacked> &run, uint32_t base) -> bool {
-                if (!walking || base >= kCap) return false;
-                uint32_t first = K;  // first green step of this lane's K, K if none
+            // tests window [base + 1, base + 64] (the caller checks that the walk goes on)
+            auto window = [&](const EntryRun<K, kPacked> &run, uint32_t base) {
+                uint32_t c = kNotGreen;  // 1 + position in the window of the lane's first green step
                 if (base < depth) {
                     // all K reads in flight before the first compare
                     uint32_t xv[K], off[K];
@@ -459,7 +501,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
                         xv[q] = *reinterpret_cast<const XT *>(smem + lds + row_byte);
                     }
 #pragma unroll
-                    for (int q = K - 1; q >= 0; --q) first = off[q] < xv[q] ? (uint32_t)q : first;
+                    for (int q = K - 1; q >= 0; --q) c = off[q] < xv[q] ? step_in_window[q] : c;
                 } else {
                     // beyond the stream (rare): draw in-lane, one step at a time
 #pragma unroll 1
@@ -467,41 +509,39 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
                         const uint32_t t = base + my_grp * K + q + 1u;
                         const uint64_t p = position(seed, j, t, b.total, b.threshold);
                         uint64_t o64;
-                        const uint32_t c = component_of(p, b.prefix, b.bucket, b.shift, &o64);
-                        first = o64 < (uint64_t)x[(size_t)c * R + my_row] ? (uint32_t)q : first;
+                        const uint32_t comp = component_of(p, b.prefix, b.bucket, b.shift, &o64);
+                        c = o64 < (uint64_t)x[(size_t)comp * R + my_row] ? my_grp * K + q + 1u : c;
                     }
                 }
-                // in the last window the lane holding step 65536 may not count it
-                if (base + kWave > kCap)
-                    first = (my_grp == L - 1 && first == K - 1) ? K : first;
-                const uint32_t step = base + my_grp * K + first + 1u;
-                lane_h = (lane_h == 0 && first < K) ? step : lane_h;
+                // step 65536 of the last window may show up here: it is above the cap like
+                // "no green step", and the walk ends with that window
+                lane_h = min(lane_h, base + c);
                 // done when every live row has a lane with a green step: fold each row's L
                 // lanes of the ballot onto its lowest bit (scalar work)
-                uint64_t seen = __builtin_amdgcn_ballot_w64(lane_h != 0);
+                uint64_t seen = __builtin_amdgcn_ballot_w64(lane_h <= kCap);
 #pragma unroll
                 for (uint32_t d = 1; d < L; d <<= 1) seen |= seen >> d;
                 walking = (seen & need) != need;
-                return true;
             };
             EntryRun<K, kPacked> e0 = fetch(0), e1 = fetch(kWave), e2 = fetch(2 * kWave);
-            for (uint32_t base = 0;; base += 3 * kWave) {
-                if (!window(e0, base)) break;
+            for (uint32_t base = 0; walking && base < kCap; base += 3 * kWave) {
+                window(e0, base);
                 e0 = fetch(base + 3 * kWave);
-                if (!window(e1, base + kWave)) break;
+                if (!walking || base + kWave >= kCap) break;
+                window(e1, base + kWave);
                 e1 = fetch(base + 4 * kWave);
-                if (!window(e2, base + 2 * kWave)) break;
+                if (!walking || base + 2 * kWave >= kCap) break;
+                window(e2, base + 2 * kWave);
                 e2 = fetch(base + 5 * kWave);
             }
-            // smallest nonzero lane value of each row (0 counts as "none": h - 1 wraps)
-            uint32_t best = lane_h - 1u;
-#pragma unroll
-            for (uint32_t d = 1; d < L; d <<= 1) best = min(best, (uint32_t)__shfl_xor((int)best, (int)d));
-            // rows without a green step up to the cap saturate; empty rows hash to 0
-            const uint32_t h = !my_row_live ? 0u : (best == ~0u ? kCap : best + 1u);
-            // every lane stores; only each row's first lane writes a tile value
-            const uint32_t slot = my_grp == 0 ? my_row * hashes_per_tile + (j - j0)
-                                              : R * hashes_per_tile + lane();
+            // smallest lane value of each row, in the row's last lane; above the cap: no green
+            // step, the hash saturates
+            const uint32_t best = group_min_at_last_lane<L>(lane_h);
+            // empty rows hash to 0
+            const uint32_t h = !my_row_live ? 0u : min(best, kCap);
+            // every lane stores; only each row's last lane writes a tile value
+            const uint32_t slot = my_grp == L - 1 ? my_row * hashes_per_tile + (j - j0)
+                                                  : R * hashes_per_tile + lane();
             hbuf[slot] = (uint16_t)h;
         }
         __syncthreads();
