@@ -30,6 +30,7 @@ namespace {
 
 constexpr uint32_t kIndexPairs = (kCap - 1u) / 2u;  // pairs of steps (1,2) ... (65533,65534)
 constexpr uint32_t kChunk = 4096;                   // keys sorted together (32 KB of LDS)
+constexpr uint32_t kBatch = 8;                      // keys a lane loads per round trip
 constexpr uint32_t kScanBlock = 1024;
 
 __device__ __forceinline__ uint32_t lane() { return threadIdx.x & (kWave - 1u); }
@@ -228,10 +229,20 @@ __global__ __launch_bounds__(256) void index_rows_kernel(Rows rows,
             const uint32_t a = offsets[c], z = offsets[c + 1];
             for (uint32_t base = a; base < z; base += kChunk) {
                 const uint32_t end = std::min(z, base + kChunk);
-                for (uint32_t i = base; i < end; ++i) {
-                    const uint64_t key = entries[i];
-                    if ((uint32_t)(key >> 32) >= x) break;
-                    atomicMin(&hmin[(uint32_t)key & 0xFFFFu], ((uint32_t)key) >> 16);
+                // kBatch independent loads per round trip (indices clamped into the chunk; keys
+                // past its end count as red); the chunk is sorted, so the first red key ends it
+                for (uint32_t i = base; i < end; i += kBatch) {
+                    uint64_t key[kBatch];
+#pragma unroll
+                    for (uint32_t u = 0; u < kBatch; ++u) key[u] = entries[std::min(i + u, end - 1u)];
+                    bool all_green = true;
+#pragma unroll
+                    for (uint32_t u = 0; u < kBatch; ++u) {
+                        const bool green = i + u < end && (uint32_t)(key[u] >> 32) < x;
+                        if (green) atomicMin(&hmin[(uint32_t)key[u] & 0xFFFFu], ((uint32_t)key[u]) >> 16);
+                        all_green = all_green && green;
+                    }
+                    if (!all_green) break;
                 }
             }
         }
