@@ -271,6 +271,38 @@ wmh_status wmh_packed_estimate(wmh_ctx *ctx, const uint32_t *A, const uint32_t *
                                double *jhat, void *stream);
 
 /* ------------------------------------------------------------------------------------------ */
+/* (K, L) banding index: the LSH consumer of the signatures (the paper's introduction: the k   */
+/* hashes serve indexing for sublinear search).  Band b of a signature is its values at hash    */
+/* ids [b*K, (b+1)*K); a database row is a candidate for a query when at least one band is     */
+/* equal value for value.  Pairs whose hashes collide independently with probability J are     */
+/* candidates with probability 1 - (1 - J^K)^L.                                                */
+/* ------------------------------------------------------------------------------------------ */
+
+typedef struct wmh_lsh wmh_lsh;
+
+/*
+ * wmh_lsh_build -- indexes N database signatures (device, N*k uint16) under K hashes per band
+ * and L bands (K, L >= 1, K*L <= k, L <= 4096, N < 2^32 - 1).  The index copies the bands it
+ * uses; sig may be freed afterwards.  Device memory: about N*L*(2K + 4) + 24*L*2^ceil(log2 2N)
+ * bytes.  Synchronous.  Errors: WMH_E_ARG, WMH_E_NOMEM, WMH_E_DEVICE.
+ */
+wmh_status wmh_lsh_build(wmh_ctx *ctx, const uint16_t *sig, uint64_t n_rows, uint32_t k,
+                         uint32_t K, uint32_t L, void *stream, wmh_lsh **out);
+
+/*
+ * wmh_lsh_query -- candidates of Q query signatures (device, Q*k uint16, the index's k):
+ *   out_count[q] (device uint32) = number of distinct database rows sharing a band with query
+ *   q, or 0xFFFFFFFF when its band matches (one per band and row) exceed 2048;
+ *   out[q*max_out + i] (device uint32), i < min(out_count[q], max_out): those rows in
+ *   increasing order.  Synchronous.  Errors: WMH_E_ARG (null, k differs), WMH_E_DEVICE.
+ */
+wmh_status wmh_lsh_query(wmh_lsh *ix, const uint16_t *query, uint64_t n_queries, uint32_t k,
+                         uint32_t max_out, uint32_t *out, uint32_t *out_count, void *stream);
+
+/* Releases the index.  NULL is ignored.  Destroy indexes before their context. */
+void wmh_lsh_destroy(wmh_lsh *ix);
+
+/* ------------------------------------------------------------------------------------------ */
 /* Fixed-point scaling of real-valued data (Sec. 4, Practical Issues).  The expected step count */
 /* is M / sum(x) (Theorem 2); scaling by alpha and rounding up the bounds gives                 */
 /* alpha * sum(x) / sum(ceil(alpha * m_i)), which the paper asks to maximize.  sum(x) is a      */

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwmh.so")
 SOURCES = ["wmh_host.cpp", "wmh_server.cpp", "wmh_kernels.hip", "wmh_collide.hip", "wmh_index.hip",
            "wmh_tune.cpp", "wmh_codec.hip", "wmh_codec_host.cpp",
-           "wmh_quantize.hip", "wmh_scale.cpp"]
+           "wmh_quantize.hip", "wmh_scale.cpp", "wmh_lsh.hip", "wmh_lsh_host.cpp"]
 ARCH = "gfx950"
 
 

@@ -124,6 +124,17 @@ hipError_t launch_unpack(const uint32_t *packed, uint64_t n_rows, uint32_t k, ui
 hipError_t launch_sig_max(const uint16_t *sig, uint64_t n, uint32_t *max_value, hipStream_t stream);
 hipError_t launch_packed_collisions(const uint32_t *A, uint64_t na, const uint32_t *B, uint64_t nb,
                                     uint32_t k, uint32_t bits, uint32_t *counts, hipStream_t stream);
+// (K, L) banding index over signatures (wmh_lsh.hip).
+constexpr uint32_t kLshQueryBuffer = 2048;  // candidate matches a query may collect (a power of 2)
+hipError_t launch_lsh_build(const uint16_t *sig, uint64_t n, uint32_t k, uint32_t K, uint32_t L,
+                            uint32_t cap_log2, uint16_t *bands, unsigned long long *table_key,
+                            uint32_t *table_head, uint32_t *next, hipStream_t stream);
+hipError_t launch_lsh_query(const uint16_t *query, uint64_t nq, uint32_t k, uint32_t K, uint32_t L,
+                            uint64_t n, uint32_t cap_log2, const uint16_t *bands,
+                            const unsigned long long *table_key, const uint32_t *table_head,
+                            const uint32_t *next, uint32_t max_out, uint32_t *out,
+                            uint32_t *out_count, hipStream_t stream);
+
 hipError_t launch_quantize(const float *x, uint64_t n, const uint32_t *col, const uint32_t *bound_q,
                            uint32_t dims, double alpha, uint32_t *out, unsigned long long *clipped,
                            hipStream_t stream);

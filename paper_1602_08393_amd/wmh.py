@@ -27,7 +27,8 @@ EXPORTED = ["wmh_opts_init", "wmh_create", "wmh_destroy", "wmh_set_bounds", "wmh
             "wmh_draws", "wmh_last_kernel_ms", "wmh_last_mode", "wmh_last_plan",
             "wmh_tune", "wmh_tune_save", "wmh_tune_load", "wmh_pack_words", "wmh_sig_bits",
             "wmh_pack", "wmh_unpack", "wmh_packed_collisions", "wmh_packed_estimate",
-            "wmh_choose_scale", "wmh_quantize",
+            "wmh_choose_scale", "wmh_quantize", "wmh_lsh_build", "wmh_lsh_query",
+            "wmh_lsh_destroy",
             "wmh_last_error", "wmh_status_string",
             "wmh_server_create", "wmh_server_submit", "wmh_server_poll", "wmh_server_wait",
             "wmh_server_drain", "wmh_server_stats", "wmh_server_now_ns", "wmh_server_destroy"]
@@ -137,6 +138,12 @@ def load() -> ctypes.CDLL:
     L.wmh_choose_scale.restype = ctypes.c_int
     L.wmh_quantize.argtypes = [vp, vp, vp, u64, ctypes.c_double, vp, ctypes.POINTER(u64), vp]
     L.wmh_quantize.restype = ctypes.c_int
+    L.wmh_lsh_build.argtypes = [vp, vp, u64, u32, u32, u32, vp, ctypes.POINTER(vp)]
+    L.wmh_lsh_build.restype = ctypes.c_int
+    L.wmh_lsh_query.argtypes = [vp, vp, u64, u32, u32, vp, vp, vp]
+    L.wmh_lsh_query.restype = ctypes.c_int
+    L.wmh_lsh_destroy.argtypes = [vp]
+    L.wmh_lsh_destroy.restype = None
     L.wmh_draws.argtypes = [vp, u64, u32, u32, u32, vp, vp, vp, vp]
     L.wmh_draws.restype = ctypes.c_int
     L.wmh_server_create.argtypes = [vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
@@ -226,6 +233,36 @@ def upload_dataset(ds, device="cuda") -> DeviceRows:
 
 def sig_to_numpy(sig) -> np.ndarray:
     return sig.cpu().numpy().view(np.uint16)
+
+
+class LshIndex:
+    """A (K, L) banding index owned by a Context (see wmh_lsh_build / wmh_lsh_query)."""
+
+    def __init__(self, ctx: "Context", ptr, k: int):
+        self._ctx, self._ptr, self.k = ctx, ptr, k
+
+    def query(self, q, max_out: int, stream=None):
+        """(candidates int32 [Q, max_out], counts int32 [Q]) as device tensors; rows in
+        increasing order, count 0xFFFFFFFF (-1 as int32) when a query overflows."""
+        torch = _torch()
+        nq = q.shape[0]
+        out = torch.full((nq, max(max_out, 1)), -1, dtype=torch.int32, device=q.device)
+        cnt = torch.empty(nq, dtype=torch.int32, device=q.device)
+        self._ctx._check(self._ctx._lib.wmh_lsh_query(self._ptr, q.data_ptr(), nq, self.k,
+                                                      max_out, out.data_ptr(), cnt.data_ptr(),
+                                                      self._ctx._stream(stream)), "wmh_lsh_query")
+        return out, cnt
+
+    def close(self):
+        if self._ptr:
+            self._ctx._lib.wmh_lsh_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Context:
@@ -396,6 +433,15 @@ class Context:
                                            alpha, out.data_ptr(), ctypes.byref(clipped),
                                            self._stream(stream)), "wmh_quantize")
         return out, clipped.value
+
+    def lsh_index(self, sig, K: int, L: int, stream=None) -> "LshIndex":
+        """(K, L) banding index over device signatures [N, k] (see wmh_lsh_build)."""
+        n, k = sig.shape
+        ptr = ctypes.c_void_p()
+        self._check(self._lib.wmh_lsh_build(self._ptr, sig.data_ptr(), n, k, K, L,
+                                            self._stream(stream), ctypes.byref(ptr)),
+                    "wmh_lsh_build")
+        return LshIndex(self, ptr, k)
 
     # -- b-bit signatures ------------------------------------------------------------------
 
