@@ -158,6 +158,32 @@ def timed_steps(ctx, rows, k, sig, opts, steps, warmup, torch):
     return elapsed, walk, build
 
 
+def lsh_bench(ctx, sig, torch, wmh) -> dict:
+    """(K, L) banding index over the headline signatures, queried with 10000 of its rows."""
+    K, L = 10, 50
+    stream = torch.cuda.current_stream()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record(stream)
+    ix = ctx.lsh_index(sig, K, L, stream=stream.cuda_stream)
+    e1.record(stream)
+    q = sig[:10000].contiguous()
+    out, cnt = ix.query(q, 64, stream=stream.cuda_stream)
+    e2.record(stream)
+    e2.synchronize()
+    counts = cnt.cpu().numpy().view(np.uint32)
+    rows_out = out.cpu().numpy().view(np.uint32)
+    listed = [int(c) != 0xFFFFFFFF and q in rows_out[q, :min(int(c), 64)]
+              for q, c in enumerate(counts)]
+    ix.close()
+    ok = counts[counts != 0xFFFFFFFF]
+    return {"K": K, "L": L, "rows": int(sig.shape[0]), "queries": 10000,
+            "build_ms": e0.elapsed_time(e1), "query_ms": e1.elapsed_time(e2),
+            "queries_per_s": 10000 / (e1.elapsed_time(e2) / 1e3),
+            "mean_candidates": float(ok.mean()) if len(ok) else None,
+            "overflowed_queries": int((counts == 0xFFFFFFFF).sum()),
+            "queries_listing_themselves": int(sum(listed))}
+
+
 def heavy_tail_bench(args, torch, synth, wmh) -> dict:
     """Heavy-tail workload (N=200000, D=16384, 1% of bounds inflated 100x, k=500): batched
     (autotuned) vs plain, then exact all-pairs collision counts of rows [0, 10^4) against
@@ -451,6 +477,8 @@ def main():
                                   "plan": batched_plan}
     if tune is not None:
         line["autotune"] = tune
+    if "batched" in result and not args.no_extras:
+        line["lsh"] = lsh_bench(ctx, sig, torch, wmh)
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a sample")
         cb, want = cpu_baseline(ds, k, args.cpu_seconds)
