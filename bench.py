@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--hashes-per-tile", type=int, default=0)
     ap.add_argument("--stream-depth", type=int, default=0)
     ap.add_argument("--waves-per-block", type=int, default=0)
+    ap.add_argument("--steps-per-lane", type=int, default=0)
     ap.add_argument("--walk", type=int, default=0, choices=[0, 1, 2],
                     help="batched walk: 0 planner/autotuner, 1 shared windows, 2 independent rows")
     ap.add_argument("--only", choices=["batched", "plain", "both"], default="both")
@@ -395,7 +396,7 @@ def main():
 
     plan = dict(rows_per_block=args.rows_per_block, hashes_per_tile=args.hashes_per_tile,
                 stream_depth=args.stream_depth, waves_per_block=args.waves_per_block,
-                walk=args.walk)
+                walk=args.walk, steps_per_lane=args.steps_per_lane)
     result = {}
     tune = None
     if args.only in ("batched", "both") and not args.no_tune and not any(plan.values()):

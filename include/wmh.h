@@ -88,8 +88,8 @@ typedef struct {
     uint32_t rows_per_block;   /* R: rows whose dense rows share one walk (1, 2, 4, 8, 16) */
     uint32_t hashes_per_tile;  /* J: hash ids per tile */
     uint32_t stream_depth;     /* T0: steps of the shared position stream built per call
-                                  (rounded up to a multiple of 64, at most 65536); steps beyond
-                                  it are drawn in-lane.  UINT32_MAX: the shortest stream (64) */
+                                  (rounded up to a whole number of windows, at most 65536);
+                                  steps beyond it are drawn in-lane.  UINT32_MAX: one window */
     uint32_t waves_per_block;  /* wavefronts per workgroup (1..16) */
     int32_t profile;           /* 1: time the walk kernels with HIP events on the launch stream
                                   (read back with wmh_last_kernel_ms) */
@@ -97,7 +97,10 @@ typedef struct {
                                   (every window is tested for all R rows of a block until the
                                   block's last row is green); 2 = independent rows (each row of a
                                   block walks its own hash ids; needs R = 4) */
-    uint32_t reserved[4];
+    uint32_t steps_per_lane;   /* batched mode, K: consecutive steps a lane tests per window;
+                                  0 = R; R, or 4 when R < 4.  A window covers 64 / R * K steps
+                                  of each of the block's R rows */
+    uint32_t reserved[3];
 } wmh_opts;
 
 /* Fills *opts with the defaults listed above. */
@@ -214,8 +217,8 @@ wmh_status wmh_last_mode(const wmh_ctx *ctx, int32_t *mode);
 /*
  * wmh_last_plan -- the schedule of the last successful wmh_hash: plan->mode as wmh_last_mode,
  * and for the batched path the tile plan it ran (rows_per_block, hashes_per_tile,
- * stream_depth, waves_per_block, walk; 0 for the other paths).  Other fields are the
- * defaults.
+ * stream_depth, waves_per_block, walk, steps_per_lane; 0 for the other paths).  Other fields
+ * are the defaults.
  * Errors: WMH_E_ARG (null).
  */
 wmh_status wmh_last_plan(const wmh_ctx *ctx, wmh_opts *plan);
@@ -352,13 +355,15 @@ typedef struct {
     uint32_t candidates;       /* plans timed */
     int32_t steps_class;       /* floor(log2(mean capped steps per hash)) of the rows */
     int32_t walk;              /* wmh_opts.walk of the fastest plan (1 or 2) */
-    uint32_t reserved[3];
+    uint32_t steps_per_lane;   /* K of the fastest plan */
+    uint32_t reserved[2];
 } wmh_tune_result;
 
 /*
  * wmh_tune -- times the batched walk on the given rows (device CSR as for wmh_hash) under
  * candidate plans R in {1,2,4,8,16} x W in {4,8,16} x J in {min(k,1024), min(k,512),
- * min(k,256)} with shared windows, plus R = 4 with independent rows for every W and J, each
+ * min(k,256)} with shared windows and K = R, the same with K = 4 for R = 1 and 2, plus R = 4
+ * with independent rows for every W and J, each
  * the best of `reps` (0 = 3) calls after one untimed call, and keeps the
  * fastest in the context under (D, value width, k, step class).  Later wmh_hash calls in the
  * batched or auto mode whose rows fall in the same key and whose plan options are 0 run that
@@ -369,8 +374,8 @@ wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
                     const uint32_t *val, uint64_t n_rows, uint64_t nnz, uint32_t k, uint64_t seed,
                     uint16_t *sig, void *stream, uint32_t reps, wmh_tune_result *out);
 
-/* Writes the context's tuned plans to a text file: a "wmh-tune 2" line, then one line per key
- * "D narrow k steps_class R J W walk ms".  Errors: WMH_E_ARG. */
+/* Writes the context's tuned plans to a text file: a "wmh-tune 3" line, then one line per key
+ * "D narrow k steps_class R J W walk K ms".  Errors: WMH_E_ARG. */
 wmh_status wmh_tune_save(wmh_ctx *ctx, const char *path);
 
 /* Adds the plans of a file written by wmh_tune_save (replacing equal keys); nothing is added

@@ -20,13 +20,14 @@ struct GraphKey {
     const void *row_ptr = nullptr, *col = nullptr, *val = nullptr;
     void *sig = nullptr;
     uint64_t n_rows = 0, nnz = 0, seed = 0;
-    uint32_t k = 0, R = 0, J = 0, depth = 0, waves = 0, grid = 0;
+    uint32_t k = 0, R = 0, K = 0, J = 0, depth = 0, waves = 0, grid = 0;
     bool narrow = false, packed = false, independent_rows = false;
     uint64_t bounds_epoch = 0;
     bool operator==(const GraphKey &o) const
     {
         return row_ptr == o.row_ptr && col == o.col && val == o.val && sig == o.sig &&
                n_rows == o.n_rows && nnz == o.nnz && seed == o.seed && k == o.k && R == o.R &&
+               K == o.K &&
                J == o.J && depth == o.depth && waves == o.waves && grid == o.grid &&
                narrow == o.narrow && packed == o.packed &&
                independent_rows == o.independent_rows && bounds_epoch == o.bounds_epoch;
@@ -72,7 +73,7 @@ struct TuneKey {
 
 struct TuneEntry {
     TuneKey key;
-    uint32_t R = 0, J = 0, W = 0;
+    uint32_t R = 0, J = 0, W = 0, K = 0;
     int32_t walk = 1;  // wmh_opts.walk: 1 shared windows, 2 independent rows
     float ms = 0.f;
 };

@@ -97,7 +97,7 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const w
 {
     wmh_opts o = o_in;
     if (use_tuned && stats.known && !o.rows_per_block && !o.hashes_per_tile &&
-        !o.waves_per_block && !o.walk) {
+        !o.waves_per_block && !o.walk && !o.steps_per_lane) {
         const TuneKey key = tune_key(ctx, k, stats);
         for (const TuneEntry &e : ctx->tuned)
             if (e.key == key) {
@@ -105,6 +105,7 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const w
                 o.hashes_per_tile = e.J;
                 o.waves_per_block = e.W;
                 o.walk = e.walk;
+                o.steps_per_lane = e.K;
                 break;
             }
     }
@@ -124,27 +125,35 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const w
     }
     if (R != 1 && R != 2 && R != 4 && R != 8 && R != 16) return false;
     if (o.walk == 2 && R != 4) return false;
+    // steps per lane: R (a window of 64 steps per row), or 4 for R < 4 (windows of 256 or 128)
+    const uint32_t K = o.steps_per_lane ? o.steps_per_lane : R;
+    if (K != R && !(K == 4 && R < 4)) return false;
+    if (o.walk == 2 && K != 4) return false;
     p.rows_per_block = R;
+    p.steps_per_lane = K;
     p.independent_rows = o.walk == 2;
     if (batched_lds_bytes(ctx->dims, p) > 160 * 1024 - 64) return false;
     p.packed = p.narrow && (uint64_t)ctx->dims * p.scale() <= 65536u;
-    // shared stream depth: cover eight mean step counts of the sparsest row
-    // (the batched kernel always reads at least one window of the stream: depth >= 64)
+    // shared stream depth: cover eight mean step counts of the sparsest row, in whole windows
+    // (the batched kernel always reads at least one window of the stream)
+    const uint32_t win = p.window();  // 64, 128 or 256 steps; divides 65536
+    auto round_up = [&](double steps) {
+        const double w = std::ceil(steps / win) * win;
+        return (uint32_t)std::max<double>(win, std::min(65536.0, w));
+    };
     uint32_t depth;
     if (o.stream_depth == UINT32_MAX) {
-        depth = 64;
+        depth = win;
     } else if (o.stream_depth) {
-        depth = std::min<uint32_t>(65536u, (o.stream_depth + 63u) & ~63u);
+        depth = round_up((double)o.stream_depth);
     } else if (min_green != ~0ull && min_green != 0) {
         const double mean_steps = (double)ctx->total / (double)min_green;
-        const double want = std::min(65536.0, 8.0 * mean_steps + 64.0);
-        depth = std::max<uint32_t>(64u, ((uint32_t)want + 63u) & ~63u);
-        depth = std::min<uint32_t>(depth, 65536u);
+        depth = round_up(std::min(65536.0, 8.0 * mean_steps + 64.0));
     } else {
         depth = 4096;
     }
-    while (depth > 64 && (uint64_t)depth * k * stream_entry_bytes(p.packed) > kStreamBudgetBytes)
-        depth -= 64;
+    while (depth > win && (uint64_t)depth * k * stream_entry_bytes(p.packed) > kStreamBudgetBytes)
+        depth -= win;
     p.stream_depth = depth;
     *plan = p;
     return true;
@@ -613,6 +622,7 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         key.row_ptr = row_ptr; key.col = col; key.val = val; key.sig = sig;
         key.n_rows = n_rows; key.nnz = nnz; key.seed = seed; key.k = k;
         key.R = plan.rows_per_block; key.J = plan.hashes_per_tile; key.depth = plan.stream_depth;
+        key.K = plan.steps_per_lane;
         key.waves = plan.waves_per_block; key.grid = grid; key.narrow = plan.narrow;
         key.packed = plan.packed;
         key.independent_rows = plan.independent_rows;
@@ -688,6 +698,7 @@ wmh_status wmh_last_plan(const wmh_ctx *ctx, wmh_opts *plan)
     plan->rows_per_block = ctx->last_plan.rows_per_block;
     plan->hashes_per_tile = ctx->last_plan.hashes_per_tile;
     plan->stream_depth = ctx->last_plan.stream_depth;
+    plan->steps_per_lane = ctx->last_plan.steps_per_lane;
     plan->waves_per_block = ctx->last_plan.waves_per_block;
     plan->walk = ctx->last_mode == WMH_MODE_BATCHED ? (ctx->last_plan.independent_rows ? 2 : 1) : 0;
     return WMH_OK;

@@ -45,13 +45,15 @@ struct StreamEntry {
 
 struct BatchedPlan {
     uint32_t rows_per_block;   // R
+    uint32_t steps_per_lane;   // K: steps a lane tests per window (R, or 4 when R < 4)
     uint32_t hashes_per_tile;  // J
-    uint32_t stream_depth;     // T0 (multiple of 64, <= 65536), 0 = no shared stream
+    uint32_t stream_depth;     // T0 (a multiple of the window, 64 / R * K steps; <= 65536)
     uint32_t waves_per_block;
     bool narrow;               // dense rows stored as uint16 (every bound < 65536)
     bool packed;               // 4-byte stream entries
     bool independent_rows;     // each row of a block walks its own hash ids (R = 4 only)
     uint32_t scale() const { return rows_per_block * (narrow ? 2u : 4u); }
+    uint32_t window() const { return 64u / rows_per_block * steps_per_lane; }
 };
 
 inline size_t stream_entry_bytes(bool packed) { return packed ? 4 : 8; }

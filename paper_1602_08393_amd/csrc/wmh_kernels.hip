@@ -377,7 +377,7 @@ __device__ __forceinline__ uint32_t group_min_at_last_lane(uint32_t v)
 template <int R>
 constexpr int walk_waves_per_eu() { return R <= 4 ? 8 : 1; }
 
-template <typename XT, int R, bool kPacked>
+template <typename XT, int R, int K, bool kPacked>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves_per_eu<R>()))) void batched_kernel(Bounds b, Rows rows, uint32_t k,
                                                        uint64_t seed, uint16_t *__restrict__ sig,
                                                        uint32_t hashes_per_tile, uint32_t depth,
@@ -385,10 +385,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
                                                        uint32_t *tile_counter)
 {
     // Lane layout of one window: lane l serves row r = l / L (L = 64 / R lanes per row) and
-    // the K = R consecutive steps base + g*K + 1 .. base + g*K + K, g = l mod L; the 64 lanes
-    // cover steps base + 1 .. base + 64 of all R rows.
+    // the K consecutive steps base + g*K + 1 .. base + g*K + K, g = l mod L; the 64 lanes
+    // cover steps base + 1 .. base + kWin of all R rows, kWin = L * K.
     constexpr uint32_t L = kWave / R;
-    constexpr uint32_t K = R;
+    constexpr uint32_t kWin = L * K;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t tile_slot;
     __shared__ uint32_t unit_slot;
@@ -481,14 +481,14 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
             // is scalar; each lane adds its own 32-bit offset.
             const uint32_t *id_entries = reinterpret_cast<const uint32_t *>(entries) +
                                          (uint64_t)j * depth * EntryRun<K, kPacked>::kWordsPerEntry;
-            const uint32_t last_base = depth - kWave;
+            const uint32_t last_base = depth - kWin;
             auto fetch = [&](uint32_t base) {
                 EntryRun<K, kPacked> run;
                 run.load_at(id_entries + (size_t)min(base, last_base) * EntryRun<K, kPacked>::kWordsPerEntry,
                             lane_words);
                 return run;
             };
-            // tests window [base + 1, base + 64] (the caller checks that the walk goes on)
+            // tests window [base + 1, base + kWin] (the caller checks that the walk goes on)
             auto window = [&](const EntryRun<K, kPacked> &run, uint32_t base) {
                 uint32_t c = kNotGreen;  // 1 + position in the window of the lane's first green step
                 if (base < depth) {
@@ -523,16 +523,16 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
                 for (uint32_t d = 1; d < L; d <<= 1) seen |= seen >> d;
                 walking = (seen & need) != need;
             };
-            EntryRun<K, kPacked> e0 = fetch(0), e1 = fetch(kWave), e2 = fetch(2 * kWave);
-            for (uint32_t base = 0; walking && base < kCap; base += 3 * kWave) {
+            EntryRun<K, kPacked> e0 = fetch(0), e1 = fetch(kWin), e2 = fetch(2 * kWin);
+            for (uint32_t base = 0; walking && base < kCap; base += 3 * kWin) {
                 window(e0, base);
-                e0 = fetch(base + 3 * kWave);
-                if (!walking || base + kWave >= kCap) break;
-                window(e1, base + kWave);
-                e1 = fetch(base + 4 * kWave);
-                if (!walking || base + 2 * kWave >= kCap) break;
-                window(e2, base + 2 * kWave);
-                e2 = fetch(base + 5 * kWave);
+                e0 = fetch(base + 3 * kWin);
+                if (!walking || base + kWin >= kCap) break;
+                window(e1, base + kWin);
+                e1 = fetch(base + 4 * kWin);
+                if (!walking || base + 2 * kWin >= kCap) break;
+                window(e2, base + 2 * kWin);
+                e2 = fetch(base + 5 * kWin);
             }
             // smallest lane value of each row, in the row's last lane; above the cap: no green
             // step, the hash saturates
@@ -830,81 +830,81 @@ size_t batched_lds_bytes(uint32_t dims, const BatchedPlan &plan)
     return aligned + ((size_t)plan.rows_per_block * plan.hashes_per_tile + kWave) * 2;
 }
 
-template <typename XT, int R, bool kPacked>
+template <typename XT, int R, int K, bool kPacked>
 static void configure_batched()
 {
     static bool configured = false;
     if (!configured) {
-        hipFuncSetAttribute((const void *)batched_kernel<XT, R, kPacked>,
+        hipFuncSetAttribute((const void *)batched_kernel<XT, R, K, kPacked>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64);
         configured = true;
     }
 }
 
-template <typename XT, int R, bool kPacked>
+template <typename XT, int R, int K, bool kPacked>
 static int batched_occupancy_t(const BatchedPlan &plan, size_t lds)
 {
-    configure_batched<XT, R, kPacked>();
+    configure_batched<XT, R, K, kPacked>();
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<XT, R, kPacked>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<XT, R, K, kPacked>,
                                                      plan.waves_per_block * kWave, lds) != hipSuccess)
         return 1;
     return blocks > 0 ? blocks : 1;
 }
 
-template <typename XT, int R, bool kPacked>
+template <typename XT, int R, int K, bool kPacked>
 static hipError_t launch_batched_t(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
                                    uint16_t *sig, const BatchedPlan &plan, const void *entries,
                                    uint32_t *tile_counter, uint32_t grid, hipStream_t stream)
 {
     const size_t lds = batched_lds_bytes(b.dims, plan);
-    configure_batched<XT, R, kPacked>();
-    batched_kernel<XT, R, kPacked><<<grid, plan.waves_per_block * kWave, lds, stream>>>(
+    configure_batched<XT, R, K, kPacked>();
+    batched_kernel<XT, R, K, kPacked><<<grid, plan.waves_per_block * kWave, lds, stream>>>(
         b, rows, k, seed, sig, plan.hashes_per_tile, plan.stream_depth, entries, tile_counter);
     return hipGetLastError();
 }
 
-// Calls F<XT, R, packed>() for the plan's template parameters.
-template <template <typename, int, bool> class F, typename... Args>
+// Calls F<XT, R, K, packed>() for the plan's template parameters: K = R, or K = 4 for R < 4.
+template <template <typename, int, int, bool> class F, typename... Args>
 static auto dispatch_batched(const BatchedPlan &plan, Args &&...args)
-    -> decltype(F<uint16_t, 1, true>::run(args...))
+    -> decltype(F<uint16_t, 1, 1, true>::run(args...))
 {
-#define WMH_R_CASE(RR)                                                                           \
-    case RR:                                                                                     \
+#define WMH_RK_CASE(RR, KK)                                                                      \
+    if (plan.rows_per_block == RR && plan.steps_per_lane == KK) {                                \
         if (plan.narrow)                                                                         \
-            return plan.packed ? F<uint16_t, RR, true>::run(args...)                             \
-                               : F<uint16_t, RR, false>::run(args...);                           \
-        return plan.packed ? F<uint32_t, RR, true>::run(args...)                                 \
-                           : F<uint32_t, RR, false>::run(args...);
-    switch (plan.rows_per_block) {
-        WMH_R_CASE(1)
-        WMH_R_CASE(2)
-        WMH_R_CASE(4)
-        WMH_R_CASE(8)
-        WMH_R_CASE(16)
-    default:
-        return F<uint16_t, 1, true>::fail();
+            return plan.packed ? F<uint16_t, RR, KK, true>::run(args...)                         \
+                               : F<uint16_t, RR, KK, false>::run(args...);                       \
+        return plan.packed ? F<uint32_t, RR, KK, true>::run(args...)                             \
+                           : F<uint32_t, RR, KK, false>::run(args...);                           \
     }
-#undef WMH_R_CASE
+    WMH_RK_CASE(1, 1)
+    WMH_RK_CASE(1, 4)
+    WMH_RK_CASE(2, 2)
+    WMH_RK_CASE(2, 4)
+    WMH_RK_CASE(4, 4)
+    WMH_RK_CASE(8, 8)
+    WMH_RK_CASE(16, 16)
+#undef WMH_RK_CASE
+    return F<uint16_t, 1, 1, true>::fail();
 }
 
-template <typename XT, int R, bool kPacked>
+template <typename XT, int R, int K, bool kPacked>
 struct LaunchBatched {
     static hipError_t run(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
                           uint16_t *sig, const BatchedPlan &plan, const void *entries,
                           uint32_t *tile_counter, uint32_t grid, hipStream_t stream)
     {
-        return launch_batched_t<XT, R, kPacked>(b, rows, k, seed, sig, plan, entries,
-                                                tile_counter, grid, stream);
+        return launch_batched_t<XT, R, K, kPacked>(b, rows, k, seed, sig, plan, entries,
+                                                   tile_counter, grid, stream);
     }
     static hipError_t fail() { return hipErrorInvalidValue; }
 };
 
-template <typename XT, int R, bool kPacked>
+template <typename XT, int R, int K, bool kPacked>
 struct OccupancyBatched {
     static int run(const BatchedPlan &plan, size_t lds)
     {
-        return batched_occupancy_t<XT, R, kPacked>(plan, lds);
+        return batched_occupancy_t<XT, R, K, kPacked>(plan, lds);
     }
     static int fail() { return 0; }
 };

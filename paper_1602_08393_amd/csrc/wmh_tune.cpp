@@ -20,7 +20,7 @@ using namespace wmh;
 
 namespace {
 
-constexpr char kTuneHeader[] = "wmh-tune 2";
+constexpr char kTuneHeader[] = "wmh-tune 3";
 
 void put_entry(wmh_ctx *ctx, const TuneEntry &e)
 {
@@ -32,10 +32,10 @@ void put_entry(wmh_ctx *ctx, const TuneEntry &e)
     ctx->tuned.push_back(e);
 }
 
-bool valid_plan(uint32_t R, uint32_t J, uint32_t W, int32_t walk)
+bool valid_plan(uint32_t R, uint32_t J, uint32_t W, int32_t walk, uint32_t K)
 {
     return (R == 1 || R == 2 || R == 4 || R == 8 || R == 16) && J >= 1 && W >= 1 && W <= 16 &&
-           (walk == 1 || (walk == 2 && R == 4));
+           (walk == 1 || (walk == 2 && R == 4)) && (K == R || (K == 4 && R < 4));
 }
 
 }  // namespace
@@ -73,9 +73,11 @@ wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         return fail(ctx, WMH_E_DEVICE, "hipEventCreate");
     }
     // best of `reps` timed calls after one untimed call; <0 when the plan does not fit
-    auto time_plan = [&](uint32_t R, uint32_t J, uint32_t W, int32_t walk, float *ms) -> wmh_status {
+    auto time_plan = [&](uint32_t R, uint32_t J, uint32_t W, int32_t walk, uint32_t K,
+                         float *ms) -> wmh_status {
         wmh_opts o = base;
         o.walk = walk;
+        o.steps_per_lane = K;
         o.mode = WMH_MODE_BATCHED;
         o.validate = 0;
         o.use_graph = 0;
@@ -103,38 +105,44 @@ wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
 
     wmh_tune_result res{};
     float default_ms = 0.f;
-    st = time_plan(def.rows_per_block, def.hashes_per_tile, def.waves_per_block, 1, &default_ms);
+    st = time_plan(def.rows_per_block, def.hashes_per_tile, def.waves_per_block, 1,
+                   def.steps_per_lane, &default_ms);
     TuneEntry best;
     best.key = tune_key(ctx, k, stats);
     best.R = def.rows_per_block;
     best.J = def.hashes_per_tile;
     best.W = def.waves_per_block;
     best.walk = 1;
+    best.K = def.steps_per_lane;
     best.ms = default_ms;
     uint32_t tried = 1;
     std::vector<uint32_t> Js{std::min(k, 1024u), std::min(k, 512u), std::min(k, 256u)};
     Js.erase(std::unique(Js.begin(), Js.end()), Js.end());
-    // shared windows for every R; independent rows at R = 4 (walk 2)
-    for (int32_t walk : {1, 2}) {
-        for (uint32_t R : {1u, 2u, 4u, 8u, 16u}) {
-            if (walk == 2 && R != 4) continue;
-            for (uint32_t W : {4u, 8u, 16u}) {
-                for (uint32_t J : Js) {
-                    if (st != WMH_OK) break;
-                    if (walk == 1 && R == def.rows_per_block && J == def.hashes_per_tile &&
-                        W == def.waves_per_block)
-                        continue;
-                    float ms = -1.f;
-                    st = time_plan(R, J, W, walk, &ms);
-                    if (st == WMH_OK && ms >= 0.f) {
-                        ++tried;
-                        if (ms < best.ms) {
-                            best.R = R;
-                            best.J = J;
-                            best.W = W;
-                            best.walk = walk;
-                            best.ms = ms;
-                        }
+    // shared windows for every R with K = R, and K = 4 for R < 4; independent rows at R = 4
+    struct Shape {
+        int32_t walk;
+        uint32_t R, K;
+    };
+    const Shape shapes[] = {{1, 1, 1}, {1, 1, 4}, {1, 2, 2}, {1, 2, 4}, {1, 4, 4},
+                            {1, 8, 8}, {1, 16, 16}, {2, 4, 4}};
+    for (const Shape &sh : shapes) {
+        for (uint32_t W : {4u, 8u, 16u}) {
+            for (uint32_t J : Js) {
+                if (st != WMH_OK) break;
+                if (sh.walk == 1 && sh.R == def.rows_per_block && sh.K == def.steps_per_lane &&
+                    J == def.hashes_per_tile && W == def.waves_per_block)
+                    continue;
+                float ms = -1.f;
+                st = time_plan(sh.R, J, W, sh.walk, sh.K, &ms);
+                if (st == WMH_OK && ms >= 0.f) {
+                    ++tried;
+                    if (ms < best.ms) {
+                        best.R = sh.R;
+                        best.J = J;
+                        best.W = W;
+                        best.walk = sh.walk;
+                        best.K = sh.K;
+                        best.ms = ms;
                     }
                 }
             }
@@ -153,6 +161,7 @@ wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
     res.candidates = tried;
     res.steps_class = best.key.steps_class;
     res.walk = best.walk;
+    res.steps_per_lane = best.K;
     *out = res;
     return WMH_OK;
 }
@@ -164,8 +173,8 @@ wmh_status wmh_tune_save(wmh_ctx *ctx, const char *path)
     if (!f) return fail(ctx, WMH_E_ARG, "cannot write %s", path);
     std::fprintf(f, "%s\n", kTuneHeader);
     for (const TuneEntry &e : ctx->tuned)
-        std::fprintf(f, "%u %d %u %d %u %u %u %d %.6f\n", e.key.dims, e.key.narrow ? 1 : 0,
-                     e.key.k, e.key.steps_class, e.R, e.J, e.W, e.walk, (double)e.ms);
+        std::fprintf(f, "%u %d %u %d %u %u %u %d %u %.6f\n", e.key.dims, e.key.narrow ? 1 : 0,
+                     e.key.k, e.key.steps_class, e.R, e.J, e.W, e.walk, e.K, (double)e.ms);
     const bool ok = std::fclose(f) == 0;
     return ok ? WMH_OK : fail(ctx, WMH_E_ARG, "cannot write %s", path);
 }
@@ -183,9 +192,10 @@ wmh_status wmh_tune_load(wmh_ctx *ctx, const char *path)
         TuneEntry e;
         int narrow = 0;
         double ms = 0;
-        if (std::sscanf(line, "%u %d %u %d %u %u %u %d %lf", &e.key.dims, &narrow, &e.key.k,
-                        &e.key.steps_class, &e.R, &e.J, &e.W, &e.walk, &ms) != 9 ||
-            (narrow != 0 && narrow != 1) || !valid_plan(e.R, e.J, e.W, e.walk) || e.key.k == 0) {
+        if (std::sscanf(line, "%u %d %u %d %u %u %u %d %u %lf", &e.key.dims, &narrow, &e.key.k,
+                        &e.key.steps_class, &e.R, &e.J, &e.W, &e.walk, &e.K, &ms) != 10 ||
+            (narrow != 0 && narrow != 1) || !valid_plan(e.R, e.J, e.W, e.walk, e.K) ||
+            e.key.k == 0) {
             ok = false;
             break;
         }

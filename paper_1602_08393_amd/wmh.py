@@ -40,7 +40,8 @@ class WmhOpts(ctypes.Structure):
                 ("sync", ctypes.c_int32), ("rows_per_block", ctypes.c_uint32),
                 ("hashes_per_tile", ctypes.c_uint32), ("stream_depth", ctypes.c_uint32),
                 ("waves_per_block", ctypes.c_uint32), ("profile", ctypes.c_int32),
-                ("walk", ctypes.c_int32), ("reserved", ctypes.c_uint32 * 4)]
+                ("walk", ctypes.c_int32), ("steps_per_lane", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 3)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -64,7 +65,8 @@ class TuneResult(ctypes.Structure):
                 ("waves_per_block", ctypes.c_uint32), ("stream_depth", ctypes.c_uint32),
                 ("best_ms", ctypes.c_float), ("default_ms", ctypes.c_float),
                 ("candidates", ctypes.c_uint32), ("steps_class", ctypes.c_int32),
-                ("walk", ctypes.c_int32), ("reserved", ctypes.c_uint32 * 3)]
+                ("walk", ctypes.c_int32), ("steps_per_lane", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
 class WMHError(RuntimeError):
@@ -322,7 +324,7 @@ class Context:
     @staticmethod
     def make_opts(mode="auto", batch_rows=0, validate=True, use_graph=True, sync=True,
                   rows_per_block=0, hashes_per_tile=0, stream_depth=0, waves_per_block=0,
-                  profile=False, walk=0) -> WmhOpts:
+                  profile=False, walk=0, steps_per_lane=0) -> WmhOpts:
         o = WmhOpts()
         load().wmh_opts_init(ctypes.byref(o))
         o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
@@ -337,6 +339,7 @@ class Context:
         o.waves_per_block = waves_per_block
         o.profile = int(bool(profile))
         o.walk = WALKS[walk] if isinstance(walk, str) else int(walk)
+        o.steps_per_lane = steps_per_lane
         return o
 
     def last_kernel_ms(self) -> tuple[float, float]:
@@ -359,7 +362,8 @@ class Context:
         return {"mode": {v: k for k, v in MODES.items()}[o.mode],
                 "rows_per_block": o.rows_per_block, "hashes_per_tile": o.hashes_per_tile,
                 "stream_depth": o.stream_depth, "waves_per_block": o.waves_per_block,
-                "walk": {v: k for k, v in WALKS.items()}.get(o.walk, o.walk)}
+                "walk": {v: k for k, v in WALKS.items()}.get(o.walk, o.walk),
+                "steps_per_lane": o.steps_per_lane}
 
     def tune(self, rows: DeviceRows, k: int, seed: int = 0, reps: int = 3, stream=None) -> dict:
         """Autotunes the batched tile plan on these rows (see wmh_tune); returns the result and
@@ -375,7 +379,8 @@ class Context:
                 "waves_per_block": r.waves_per_block, "stream_depth": r.stream_depth,
                 "best_ms": r.best_ms, "default_ms": r.default_ms, "candidates": r.candidates,
                 "steps_class": r.steps_class,
-                "walk": {v: k for k, v in WALKS.items()}.get(r.walk, r.walk)}
+                "walk": {v: k for k, v in WALKS.items()}.get(r.walk, r.walk),
+                "steps_per_lane": r.steps_per_lane}
 
     def tune_save(self, path: str):
         self._check(self._lib.wmh_tune_save(self._ptr, os.fsencode(path)), "wmh_tune_save")

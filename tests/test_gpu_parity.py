@@ -127,6 +127,10 @@ BATCHED_PLANS = [
     dict(rows_per_block=8, waves_per_block=1), dict(rows_per_block=2, waves_per_block=16),
     dict(rows_per_block=4, stream_depth=None),   # every draw made in-lane
     dict(rows_per_block=4, stream_depth=64),     # stream for the first window only
+    # four steps per lane with one or two rows: windows of 256 and 128 steps
+    dict(rows_per_block=1, steps_per_lane=4), dict(rows_per_block=2, steps_per_lane=4),
+    dict(rows_per_block=1, steps_per_lane=4, stream_depth=None),
+    dict(rows_per_block=2, steps_per_lane=4, stream_depth=200, hashes_per_tile=9),
     # independent rows: each row of a block walks its own hash ids
     dict(walk="rows"), dict(walk="rows", hashes_per_tile=7),
     dict(walk="rows", waves_per_block=1), dict(walk="rows", waves_per_block=16),
@@ -173,7 +177,9 @@ def test_full_rows_hash_to_one_and_saturation(ctx):
     for opts in (dict(mode="plain"), dict(mode="batched", rows_per_block=4),
                  dict(mode="batched", rows_per_block=2, stream_depth=128),
                  dict(mode="batched", walk="rows"),
-                 dict(mode="batched", walk="rows", stream_depth=None)):
+                 dict(mode="batched", walk="rows", stream_depth=None),
+                 dict(mode="batched", rows_per_block=1, steps_per_lane=4),
+                 dict(mode="batched", rows_per_block=2, steps_per_lane=4, stream_depth=None)):
         assert_same(gpu_sig(ctx, ds, k, 5, **opts), want, f"saturation {opts}")
 
 
