@@ -372,6 +372,15 @@ __device__ __forceinline__ uint32_t group_min_at_last_lane(uint32_t v)
     return v;
 }
 
+// The top bit of every L-lane segment of a 64-bit lane mask.
+template <uint32_t L>
+__host__ __device__ constexpr uint64_t segment_tops()
+{
+    uint64_t m = 0;
+    for (uint32_t r = 0; r < kWave / L; ++r) m |= 1ull << (r * L + L - 1);
+    return m;
+}
+
 // Up to four rows per block the walk fits eight wavefronts per SIMD (at most 64 VGPRs and a
 // few scalar registers spilled to vector lanes); wider blocks keep their registers.
 template <int R>
@@ -450,10 +459,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
         const uint32_t live = __builtin_amdgcn_readfirstlane(nonempty);
         const bool my_row_live = ((live >> my_row) & 1u) != 0;
         // bit r * L set for every live row r: the walk ends when each of them has a green lane
+        // top bit of every live row's L-lane segment: the walk ends when each of those
+        // segments of the "has a green step" ballot is nonzero
         uint64_t need = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            if ((live >> r) & 1u) need |= 1ull << (r * L);
+            if ((live >> r) & 1u) need |= 1ull << (r * L + L - 1);
         const uint32_t j0 = ht * hashes_per_tile;
         const uint32_t j1 = min(k, j0 + hashes_per_tile);
 
@@ -518,10 +529,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
                 lane_h = min(lane_h, base + c);
                 // done when every live row has a lane with a green step: fold each row's L
                 // lanes of the ballot onto its lowest bit (scalar work)
-                uint64_t seen = __builtin_amdgcn_ballot_w64(lane_h <= kCap);
-#pragma unroll
-                for (uint32_t d = 1; d < L; d <<= 1) seen |= seen >> d;
-                walking = (seen & need) != need;
+                // which rows have a lane with a green step: per L-lane segment of the ballot,
+                // (low L-1 bits + all ones in them) carries into the top bit iff one is set
+                // (no carry leaves a segment); or-ing the ballot covers the top bit itself
+                const uint64_t seen = __builtin_amdgcn_ballot_w64(lane_h <= kCap);
+                const uint64_t low = ~segment_tops<L>();
+                walking = ((((seen & low) + low) | seen) & need) != need;
             };
             EntryRun<K, kPacked> e0 = fetch(0), e1 = fetch(kWin), e2 = fetch(2 * kWin);
             for (uint32_t base = 0; walking && base < kCap; base += 3 * kWin) {
