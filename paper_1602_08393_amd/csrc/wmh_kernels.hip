@@ -73,23 +73,33 @@ __global__ __launch_bounds__(256) void validate_kernel(Rows rows, const uint32_t
         }
         uint64_t sum = 0;
         uint64_t bad = ~0ull;  // (entry << 4) | code of this lane's first bad entry
-        // each lane checks 4 consecutive entries per pass, so a wave has many loads in flight
+        // each lane checks a group of 4 consecutive entries per pass, groups aligned to
+        // multiples of 4 entries so col and val load as 16-byte vectors (entries of the group
+        // outside the row are skipped; at the arrays' end the loads go one by one)
         constexpr uint32_t kPer = 4;
-        for (uint64_t e0 = lo + (uint64_t)lane() * kPer; e0 < hi; e0 += (uint64_t)kWave * kPer) {
+        for (uint64_t g = (lo & ~(uint64_t)(kPer - 1)) + (uint64_t)lane() * kPer; g < hi;
+             g += (uint64_t)kWave * kPer) {
             uint32_t c[kPer], v[kPer], m[kPer];
-            const uint32_t prev = e0 > lo ? rows.col[e0 - 1] : 0u;
+            if (g + kPer <= rows.nnz) {
+                const uint4 cc = *reinterpret_cast<const uint4 *>(rows.col + g);
+                const uint4 vv = *reinterpret_cast<const uint4 *>(rows.val + g);
+                c[0] = cc.x; c[1] = cc.y; c[2] = cc.z; c[3] = cc.w;
+                v[0] = vv.x; v[1] = vv.y; v[2] = vv.z; v[3] = vv.w;
+            } else {
 #pragma unroll
-            for (uint32_t i = 0; i < kPer; ++i) {
-                const bool in = e0 + i < hi;
-                c[i] = in ? rows.col[e0 + i] : 0u;
-                v[i] = in ? rows.val[e0 + i] : 0u;
+                for (uint32_t i = 0; i < kPer; ++i) {
+                    const bool in = g + i < rows.nnz;
+                    c[i] = in ? rows.col[g + i] : 0u;
+                    v[i] = in ? rows.val[g + i] : 0u;
+                }
             }
+            const uint32_t prev = g > lo ? rows.col[g - 1] : 0u;
 #pragma unroll
             for (uint32_t i = 0; i < kPer; ++i) m[i] = c[i] < dims ? bound[c[i]] : 0u;
 #pragma unroll
             for (uint32_t i = 0; i < kPer; ++i) {
-                const uint64_t e = e0 + i;
-                if (e >= hi) break;
+                const uint64_t e = g + i;
+                if (e < lo || e >= hi) continue;
                 const uint32_t before = i ? c[i - 1] : prev;
                 uint32_t code = 0;
                 if (c[i] >= dims) code = kCheckColumn;
