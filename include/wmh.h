@@ -74,8 +74,12 @@ typedef enum {
                               the smallest t among the keys of its nonzero components whose
                               offset is below x_c, else 65535.  The same values as the walk, in
                               O(nnz + k * 65534 * sum x / M) per row: the choice for small
-                              green fractions.  Needs k <= 8192 and k * 65534 * 8 bytes of
-                              device memory */
+                              green fractions.  The lists are kept twice, by offset and by
+                              step: a row whose hashes are small (large sum x / M) reads its
+                              lists in step order up to a bound T with Pr(any hash > T) <= 1e-4
+                              (Theorem 2) and settles any hash id above T in offset order, so
+                              the values stay exact.  Needs k <= 8192 and k * 65534 * 16 bytes
+                              of device memory */
 } wmh_mode;
 
 typedef struct {

@@ -54,7 +54,7 @@ struct OwnedIndex {
     hipEvent_t used = nullptr;  // recorded after each read, awaited before a rebuild
 };
 
-constexpr uint64_t kIndexBudgetBytes = 4ull << 30;  // index entries, at most 4 GiB
+constexpr uint64_t kIndexBudgetBytes = 4ull << 30;  // each key order of the index, at most 4 GiB
 
 enum class Path { kPlain, kBatched, kIndexed };
 

@@ -229,6 +229,7 @@ bool index_fits(uint32_t k)
 void free_index(OwnedIndex *ix)
 {
     if (ix->buf.entries) (void)hipFree(ix->buf.entries);
+    if (ix->buf.by_step) (void)hipFree(ix->buf.by_step);
     if (ix->buf.offsets) (void)hipFree(ix->buf.offsets);
     if (ix->buf.cursor) (void)hipFree(ix->buf.cursor);
     if (ix->buf.block_sums) (void)hipFree(ix->buf.block_sums);
@@ -251,10 +252,13 @@ wmh_status ensure_index(wmh_ctx *ctx, OwnedIndex *ix, uint64_t seed, uint32_t k,
     if (e != hipSuccess) return device_fail(err, e, "index event");
     const uint64_t n = index_entry_count(k);
     if (n > ix->cap_entries) {
-        if (ix->buf.entries) (void)hipFree(ix->buf.entries);
-        ix->buf.entries = nullptr;
+        for (uint64_t **p : {&ix->buf.entries, &ix->buf.by_step}) {
+            if (*p) (void)hipFree(*p);
+            *p = nullptr;
+        }
         ix->cap_entries = 0;
         e = hipMalloc(&ix->buf.entries, n * sizeof(uint64_t));
+        if (e == hipSuccess) e = hipMalloc(&ix->buf.by_step, n * sizeof(uint64_t));
         if (e != hipSuccess) return device_fail(err, e, "index entries");
         ix->cap_entries = n;
     }
@@ -584,7 +588,7 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         if (st != WMH_OK) return st;
         if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[1], s));
         const uint32_t grid = (uint32_t)ctx->cu_count * (uint32_t)index_rows_blocks_per_cu(k);
-        WMH_HIP(ctx, launch_index_rows(rows, ctx->index.buf, ctx->dims, k, sig, grid, s));
+        WMH_HIP(ctx, launch_index_rows(rows, ctx->index.buf, b, k, sig, grid, s));
         if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[2], s));
         WMH_HIP(ctx, hipEventRecord(ctx->index.used, s));
         ctx->profiled = profile;

@@ -21,6 +21,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cmath>
 
 #include "wmh_internal.h"
 
@@ -201,13 +202,87 @@ __global__ __launch_bounds__(256) void sort_chunks_kernel(const uint32_t *__rest
     }
 }
 
+// The same draws keyed by step: (t << 48) | (j << 32) | offset, list by list in place of the
+// offset-ordered copy (sorted afterwards with the same chunks).
+__global__ __launch_bounds__(256) void step_keys_kernel(const uint64_t *__restrict__ by_offset,
+                                                        uint64_t n, uint64_t *__restrict__ by_step)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t key = by_offset[i];
+    const uint64_t t = (key >> 16) & 0xFFFFu, j = key & 0xFFFFu, off = key >> 32;
+    by_step[i] = (t << 48) | (j << 32) | off;
+}
+
 // Hashes of rows from the index: one wavefront per row, the running minimum of each hash id in
-// LDS.  A lane takes one nonzero (c, x_c) at a time and reads c's keys chunk by chunk up to the
-// first offset >= x_c.
+// LDS.  A lane takes one nonzero (c, x_c) at a time.  Offset order: the lane reads c's keys
+// chunk by chunk up to the first offset >= x_c (every green key).  Step order, for rows whose
+// hashes are small: the lane reads c's keys up to the first step > T, where T is chosen so that
+// every hash of the row is at most T with probability 1 - 1e-4 (Theorem 2: Pr(h > T) =
+// (1 - s)^T); a hash id still above T afterwards is settled by an offset-order pass, so the
+// values are exact either way.  The row takes step order when T * sum(m_c) < 65534 * sum(x_c)
+// over its nonzeros (expected keys read: k * T * sum(m_c) / M against k * 65534 * sum(x_c) / M).
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ void offset_scan(const uint64_t *__restrict__ entries, uint32_t a,
+                                            uint32_t z, uint32_t x, uint32_t *hmin)
+{
+    for (uint32_t base = a; base < z; base += kChunk) {
+        const uint32_t end = std::min(z, base + kChunk);
+        // kBatch independent loads per round trip (indices clamped into the chunk; keys past
+        // its end count as red); the chunk is sorted, so the first red key ends it
+        for (uint32_t i = base; i < end; i += kBatch) {
+            uint64_t key[kBatch];
+#pragma unroll
+            for (uint32_t u = 0; u < kBatch; ++u) key[u] = entries[std::min(i + u, end - 1u)];
+            bool all_green = true;
+#pragma unroll
+            for (uint32_t u = 0; u < kBatch; ++u) {
+                const bool green = i + u < end && (uint32_t)(key[u] >> 32) < x;
+                if (green) atomicMin(&hmin[(uint32_t)key[u] & 0xFFFFu], ((uint32_t)key[u]) >> 16);
+                all_green = all_green && green;
+            }
+            if (!all_green) break;
+        }
+    }
+}
+
+__device__ __forceinline__ void step_scan(const uint64_t *__restrict__ by_step, uint32_t a,
+                                          uint32_t z, uint32_t x, uint32_t T, uint32_t *hmin)
+{
+    for (uint32_t base = a; base < z; base += kChunk) {
+        const uint32_t end = std::min(z, base + kChunk);
+        // keys in step order inside the chunk: read up to the first step > T
+        for (uint32_t i = base; i < end; i += kBatch) {
+            uint64_t key[kBatch];
+#pragma unroll
+            for (uint32_t u = 0; u < kBatch; ++u) key[u] = by_step[std::min(i + u, end - 1u)];
+            bool all_in = true;
+#pragma unroll
+            for (uint32_t u = 0; u < kBatch; ++u) {
+                const uint32_t t = (uint32_t)(key[u] >> 48);
+                const bool in = i + u < end && t <= T;
+                if (in && (uint32_t)key[u] < x)
+                    atomicMin(&hmin[(uint32_t)(key[u] >> 32) & 0xFFFFu], t);
+                all_in = all_in && in;
+            }
+            if (!all_in) break;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void index_rows_kernel(Rows rows,
                                                          const uint32_t *__restrict__ offsets,
                                                          const uint64_t *__restrict__ entries,
-                                                         uint32_t dims, uint32_t k,
+                                                         const uint64_t *__restrict__ by_step,
+                                                         const uint32_t *__restrict__ bound,
+                                                         uint64_t total, uint32_t dims, uint32_t k,
+                                                         double log_delta,
                                                          uint16_t *__restrict__ sig)
 {
     extern __shared__ uint32_t lds[];
@@ -220,34 +295,50 @@ __global__ __launch_bounds__(256) void index_rows_kernel(Rows rows,
         for (uint32_t j = ln; j < k; j += kWave) hmin[j] = kCap;
         wave_lds_fence();
         const uint64_t lo = rows.row_ptr[row], hi = rows.row_ptr[row + 1];
-        bool green = false;
+        // the row's sum(x) and sum(m) over its nonzero columns
+        uint64_t sx = 0, sm = 0;
         for (uint64_t e = lo + ln; e < hi; e += kWave) {
             const uint32_t c = rows.col[e];
             const uint32_t x = rows.val[e];
             if (x == 0 || c >= dims) continue;
-            green = true;
-            const uint32_t a = offsets[c], z = offsets[c + 1];
-            for (uint32_t base = a; base < z; base += kChunk) {
-                const uint32_t end = std::min(z, base + kChunk);
-                // kBatch independent loads per round trip (indices clamped into the chunk; keys
-                // past its end count as red); the chunk is sorted, so the first red key ends it
-                for (uint32_t i = base; i < end; i += kBatch) {
-                    uint64_t key[kBatch];
-#pragma unroll
-                    for (uint32_t u = 0; u < kBatch; ++u) key[u] = entries[std::min(i + u, end - 1u)];
-                    bool all_green = true;
-#pragma unroll
-                    for (uint32_t u = 0; u < kBatch; ++u) {
-                        const bool green = i + u < end && (uint32_t)(key[u] >> 32) < x;
-                        if (green) atomicMin(&hmin[(uint32_t)key[u] & 0xFFFFu], ((uint32_t)key[u]) >> 16);
-                        all_green = all_green && green;
-                    }
-                    if (!all_green) break;
+            sx += x;
+            sm += bound[c];
+        }
+        sx = wave_sum64(sx);
+        sm = wave_sum64(sm);
+        const bool live = sx != 0;
+        // step bound T of the row and the cheaper key order (uniform over the wavefront)
+        uint32_t T = kCap;
+        bool by_steps = false;
+        if (live && by_step) {
+            const double s = (double)sx / (double)total;
+            const double t = s >= 1.0 ? 1.0 : ceil(log_delta / log1p(-s));
+            T = t < (double)kCap ? (uint32_t)t : kCap;
+            by_steps = T < kCap - 1u && (double)T * (double)sm < 65534.0 * (double)sx;
+        }
+        for (uint64_t e = lo + ln; e < hi; e += kWave) {
+            const uint32_t c = rows.col[e];
+            const uint32_t x = rows.val[e];
+            if (x == 0 || c >= dims) continue;
+            if (by_steps) step_scan(by_step, offsets[c], offsets[c + 1], x, T, hmin);
+            else offset_scan(entries, offsets[c], offsets[c + 1], x, hmin);
+        }
+        wave_lds_fence();
+        if (by_steps) {
+            // a hash id with no green step up to T: settle the row in offset order (the
+            // step-order minima found so far are green steps, so they stay valid)
+            bool open = false;
+            for (uint32_t j = ln; j < k; j += kWave) open = open || hmin[j] > T;
+            if (__ballot(open) != 0) {
+                for (uint64_t e = lo + ln; e < hi; e += kWave) {
+                    const uint32_t c = rows.col[e];
+                    const uint32_t x = rows.val[e];
+                    if (x == 0 || c >= dims) continue;
+                    offset_scan(entries, offsets[c], offsets[c + 1], x, hmin);
                 }
+                wave_lds_fence();
             }
         }
-        const bool live = __ballot(green) != 0;
-        wave_lds_fence();
         uint16_t *out = sig + row * (uint64_t)k;
         for (uint32_t j = ln; j < k; j += kWave) out[j] = live ? (uint16_t)hmin[j] : (uint16_t)0;
         wave_lds_fence();
@@ -280,6 +371,13 @@ hipError_t launch_index_build(const Bounds &b, uint64_t seed, uint32_t k, const 
     sort_small_kernel<<<sort_grid, 256, 0, stream>>>(ix.offsets, (uint32_t)D, ix.entries);
     sort_chunks_kernel<<<(uint32_t)std::min<uint64_t>(D, 4096), 256, 0, stream>>>(
         ix.offsets, (uint32_t)D, ix.entries);
+    if ((e = hipGetLastError()) != hipSuccess || !ix.by_step) return e;
+    // the step-ordered copy: the same lists and chunks, keys re-packed, then sorted
+    const uint64_t n = (uint64_t)kIndexPairs * 2u * k;
+    step_keys_kernel<<<(uint32_t)((n + 255) / 256), 256, 0, stream>>>(ix.entries, n, ix.by_step);
+    sort_small_kernel<<<sort_grid, 256, 0, stream>>>(ix.offsets, (uint32_t)D, ix.by_step);
+    sort_chunks_kernel<<<(uint32_t)std::min<uint64_t>(D, 4096), 256, 0, stream>>>(
+        ix.offsets, (uint32_t)D, ix.by_step);
     return hipGetLastError();
 }
 
@@ -300,15 +398,17 @@ int index_rows_blocks_per_cu(uint32_t k)
     return std::max(1, n);
 }
 
-hipError_t launch_index_rows(const Rows &rows, const IndexBuffers &ix, uint32_t dims, uint32_t k,
+hipError_t launch_index_rows(const Rows &rows, const IndexBuffers &ix, const Bounds &b, uint32_t k,
                              uint16_t *sig, uint32_t grid, hipStream_t stream)
 {
     if (rows.n_rows == 0) return hipSuccess;
     const uint32_t waves = index_rows_waves(k);
     const uint64_t need = (rows.n_rows + waves - 1) / waves;
     const uint32_t g = (uint32_t)std::min<uint64_t>(need, grid);
-    index_rows_kernel<<<g, waves * kWave, index_rows_lds_bytes(k), stream>>>(rows, ix.offsets,
-                                                                            ix.entries, dims, k, sig);
+    // every hash of a step-order row is <= T with probability >= 1 - 1e-4
+    const double log_delta = std::log(1e-4 / (double)k);
+    index_rows_kernel<<<g, waves * kWave, index_rows_lds_bytes(k), stream>>>(
+        rows, ix.offsets, ix.entries, ix.by_step, b.bound, b.total, b.dims, k, log_delta, sig);
     return hipGetLastError();
 }
 

@@ -93,10 +93,12 @@ hipError_t launch_collisions(const uint16_t *A, uint64_t na, const uint16_t *B, 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t stream);
 
 // Component index of the capped sequence (wmh_index.hip).  entries: k * 65534 keys
-// (offset << 32) | (t << 16) | j grouped by component; offsets: D + 1 list starts; cursor:
+// (offset << 32) | (t << 16) | j grouped by component (by_step: the same lists in step order);
+// offsets: D + 1 list starts; cursor:
 // D + 1 counters; block_sums: ceil((D + 1) / 1024) scan carries.
 struct IndexBuffers {
     uint64_t *entries = nullptr;
+    uint64_t *by_step = nullptr;  // the same lists keyed (t << 48) | (j << 32) | offset; optional
     uint32_t *offsets = nullptr;
     uint32_t *cursor = nullptr;
     uint32_t *block_sums = nullptr;
@@ -111,7 +113,7 @@ inline uint64_t index_scan_blocks(uint32_t dims) { return ((uint64_t)dims + 1 + 
 hipError_t launch_index_build(const Bounds &b, uint64_t seed, uint32_t k, const IndexBuffers &ix,
                               hipStream_t stream);
 
-hipError_t launch_index_rows(const Rows &rows, const IndexBuffers &ix, uint32_t dims, uint32_t k,
+hipError_t launch_index_rows(const Rows &rows, const IndexBuffers &ix, const Bounds &b, uint32_t k,
                              uint16_t *sig, uint32_t grid, hipStream_t stream);
 
 // Resident workgroups per CU of the index row kernel.

@@ -147,7 +147,7 @@ wmh_status wmh_server::launch(Slot &slot, Request &r)
             e = hipStreamSynchronize(s);
         }
         if (e == hipSuccess)
-            e = launch_index_rows(rows, index.buf, ctx->dims, k, slot.d_sig, index_grid, s);
+            e = launch_index_rows(rows, index.buf, b, k, slot.d_sig, index_grid, s);
         if (e == hipSuccess) e = hipEventRecord(index.used, s);
     } else if (e == hipSuccess) {
         if (batched) {
