@@ -60,7 +60,7 @@ def parse():
                     help="only run device-to-device copies of BYTES (scales HBM counters)")
     ap.add_argument("--serve", action="store_true",
                     help="only run the serving workload (corpus of config 5, k=256)")
-    ap.add_argument("--serve-requests", type=int, default=48,
+    ap.add_argument("--serve-requests", type=int, default=200,
                     help="open-loop requests per load level")
     ap.add_argument("--serve-corpus-rows", type=int, default=20_000)
     ap.add_argument("--no-extras", action="store_true",

@@ -40,7 +40,7 @@ struct RowStats {
     uint64_t nonempty = 0;       // rows with sum(x) > 0
     uint64_t min_green = ~0ull;  // smallest sum(x) over non-empty rows
     uint64_t walk_steps = 0;     // sum over non-empty rows of min(M / sum(x), 65535)
-    uint64_t index_keys = 0;     // sum over non-empty rows of ceil(65534 * sum(x) / M)
+    uint64_t index_keys = 0;     // sum over non-empty rows of the index keys read per hash
 };
 
 // A component index owned by a context or a serving loop, rebuilt when its key changes.
@@ -132,12 +132,13 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const w
                   BatchedPlan *plan, bool use_tuned = true);
 TuneKey tune_key(const wmh_ctx *ctx, uint32_t k, const RowStats &stats);
 // Validation pass on the device: checks the rows (when check) and fills *stats; waits.
-wmh_status gather_stats(wmh_ctx *ctx, const Rows &rows, hipStream_t s, bool check,
+wmh_status gather_stats(wmh_ctx *ctx, const Rows &rows, uint32_t k, hipStream_t s, bool check,
                         RowStats *stats);
 // Host-side check of CSR rows against the context's bounds (same rules as the device check);
 // fills *stats (may be NULL) like the device pass.
 wmh_status check_rows_host(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
-                           const uint32_t *val, uint64_t n_rows, uint64_t nnz, RowStats *stats);
+                           const uint32_t *val, uint64_t n_rows, uint64_t nnz, uint32_t k,
+                           RowStats *stats);
 // Whether an index for k hashes is allowed (k and memory limits).
 bool index_fits(uint32_t k);
 // Makes `ix` the index of (ctx's bounds, seed, k), building it on `stream` when stale.

@@ -160,7 +160,8 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const w
 }
 
 wmh_status check_rows_host(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
-                           const uint32_t *val, uint64_t n_rows, uint64_t nnz, RowStats *stats)
+                           const uint32_t *val, uint64_t n_rows, uint64_t nnz, uint32_t k,
+                           RowStats *stats)
 {
     RowStats st;
     st.known = true;
@@ -169,7 +170,7 @@ wmh_status check_rows_host(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t
         if (lo > hi || hi > nnz)
             return fail(ctx, WMH_E_ROW_PTR, "row %llu: row_ptr decreasing or beyond nnz",
                         (unsigned long long)r);
-        uint64_t green = 0;
+        uint64_t green = 0, bounds_sum = 0;
         for (uint64_t e = lo; e < hi; ++e) {
             const uint32_t c = col[e];
             if (c >= ctx->dims)
@@ -182,26 +183,33 @@ wmh_status check_rows_host(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t
                 return fail(ctx, WMH_E_BOUND, "row %llu: value above its bound m_i",
                             (unsigned long long)r);
             green += val[e];
+            bounds_sum += val[e] ? ctx->h_bound[c] : 0u;
         }
         if (green) {
             ++st.nonempty;
             st.min_green = std::min(st.min_green, green);
             st.walk_steps += std::min<uint64_t>(ctx->total / green, kCap);
-            st.index_keys += (uint64_t)std::ceil(65534.0 * ((double)green / (double)ctx->total));
+            const double s = (double)green / (double)ctx->total;
+            const double T = s >= 1.0 ? 1.0 : std::ceil(std::log(1e-4 / (double)k) / std::log1p(-s));
+            const double by_offset = 65534.0 * s;
+            const double by_step = T < 65534.0 ? T * ((double)bounds_sum / (double)ctx->total)
+                                               : by_offset;
+            st.index_keys += (uint64_t)std::ceil(std::min(by_offset, by_step));
         }
     }
     if (stats) *stats = st;
     return WMH_OK;
 }
 
-wmh_status gather_stats(wmh_ctx *ctx, const Rows &rows, hipStream_t s, bool check,
+wmh_status gather_stats(wmh_ctx *ctx, const Rows &rows, uint32_t k, hipStream_t s, bool check,
                         RowStats *stats)
 {
     // first_error and min_green start at ~0, the counters at 0
     uint32_t *words = reinterpret_cast<uint32_t *>(ctx->d_check);
     hipError_t e = launch_fill_u32(words, 0xFFFFFFFFu, 4, s);
     if (e == hipSuccess) e = launch_fill_u32(words + 4, 0u, 6, s);
-    if (e == hipSuccess) e = launch_validate(rows, ctx->d_bound, ctx->dims, ctx->total, ctx->d_check, s);
+    if (e == hipSuccess)
+        e = launch_validate(rows, ctx->d_bound, ctx->dims, ctx->total, k, ctx->d_check, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(ctx->h_check, ctx->d_check, sizeof(CheckWords), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -568,7 +576,7 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
     const bool profile = o.profile != 0;
     ctx->profiled = false;
     if (o.validate || o.mode == WMH_MODE_AUTO) {
-        const wmh_status st = gather_stats(ctx, rows, s, o.validate != 0, &stats);
+        const wmh_status st = gather_stats(ctx, rows, k, s, o.validate != 0, &stats);
         if (st != WMH_OK) return st;
     }
 

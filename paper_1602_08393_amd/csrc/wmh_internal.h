@@ -23,7 +23,7 @@ struct CheckWords {
     unsigned long long min_green;    // smallest sum(x) over non-empty rows; ~0 if none
     unsigned long long n_empty;      // rows with sum(x) == 0
     unsigned long long walk_steps;   // sum over non-empty rows of min(M / sum(x), 65535)
-    unsigned long long index_keys;   // sum over non-empty rows of ceil(65534 * sum(x) / M)
+    unsigned long long index_keys;   // sum over non-empty rows of the index keys read per hash
 };
 
 struct Rows {
@@ -60,7 +60,7 @@ inline size_t stream_entry_bytes(bool packed) { return packed ? 4 : 8; }
 
 // Checks the rows and gathers the statistics of CheckWords (M = total, for the cost estimates).
 hipError_t launch_validate(const Rows &rows, const uint32_t *bound, uint32_t dims, uint64_t total,
-                           CheckWords *words, hipStream_t stream);
+                           uint32_t k, CheckWords *words, hipStream_t stream);
 
 hipError_t launch_plain(const Bounds &b, const Rows &rows, uint64_t row_begin,
                         uint64_t row_end, uint32_t k, uint64_t seed, uint16_t *sig, bool narrow,

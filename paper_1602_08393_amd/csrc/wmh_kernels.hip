@@ -53,7 +53,7 @@ __device__ __forceinline__ uint64_t wave_min(uint64_t v)
 // Validation: one wavefront per row, grid-stride over rows.
 // ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void validate_kernel(Rows rows, const uint32_t *__restrict__ bound,
-                                                       uint32_t dims, uint64_t total,
+                                                       uint32_t dims, uint64_t total, uint32_t k,
                                                        CheckWords *words)
 {
     // per-workgroup partials, so each word gets at most one global atomic per workgroup
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void validate_kernel(Rows rows, const uint32_t
             w_err = min(w_err, (unsigned long long)((r << 4) | kCheckRowPtr));
             continue;
         }
-        uint64_t sum = 0;
+        uint64_t sum = 0, sum_m = 0;  // sum(x) and sum(m_c) over the row's nonzeros
         uint64_t bad = ~0ull;  // (entry << 4) | code of this lane's first bad entry
         // each lane checks a group of 4 consecutive entries per pass, groups aligned to
         // multiples of 4 entries so col and val load as 16-byte vectors (entries of the group
@@ -107,17 +107,25 @@ __global__ __launch_bounds__(256) void validate_kernel(Rows rows, const uint32_t
                 else if (v[i] > m[i]) code = kCheckBound;
                 if (code && bad == ~0ull) bad = ((e - lo) << 4) | code;
                 sum += v[i];
+                sum_m += v[i] ? m[i] : 0u;
             }
         }
         bad = wave_min(bad);
         sum = wave_sum(sum);
+        sum_m = wave_sum(sum_m);
         if (bad != ~0ull) w_err = min(w_err, (unsigned long long)((r << 4) | (bad & 15u)));
         else if (sum == 0) ++w_empty;
         else {
             w_green = min(w_green, (unsigned long long)sum);
-            // mean capped step count ~ min(1/s, cap) (Theorem 2); green keys ~ 65534 * s
+            // mean capped step count ~ min(1/s, cap) (Theorem 2); index keys per hash: the
+            // cheaper of offset order (65534 * s) and step order up to the row's bound T
+            // (T * sum(m) / M), as the index row kernel chooses
             w_walk += min(total / sum, (uint64_t)kCap);
-            w_keys += (uint64_t)ceil(65534.0 * ((double)sum / (double)total));
+            const double s = (double)sum / (double)total;
+            const double T = s >= 1.0 ? 1.0 : ceil(log(1e-4 / (double)k) / log1p(-s));
+            const double by_offset = 65534.0 * s;
+            const double by_step = T < 65534.0 ? T * ((double)sum_m / (double)total) : by_offset;
+            w_keys += (uint64_t)ceil(min(by_offset, by_step));
         }
     }
     const uint32_t wave = wave_index();
@@ -794,12 +802,12 @@ __global__ __launch_bounds__(256) void estimate_kernel(const uint16_t *__restric
 // ---------------------------------------------------------------------------------------------
 
 hipError_t launch_validate(const Rows &rows, const uint32_t *bound, uint32_t dims, uint64_t total,
-                           CheckWords *words, hipStream_t stream)
+                           uint32_t k, CheckWords *words, hipStream_t stream)
 {
     if (rows.n_rows == 0) return hipSuccess;
     const uint64_t waves_needed = rows.n_rows;
     const uint32_t grid = (uint32_t)std::min<uint64_t>((waves_needed + 3) / 4, 2048);
-    validate_kernel<<<grid, 256, 0, stream>>>(rows, bound, dims, total, words);
+    validate_kernel<<<grid, 256, 0, stream>>>(rows, bound, dims, total, k, words);
     return hipGetLastError();
 }
 

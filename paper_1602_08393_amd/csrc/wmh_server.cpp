@@ -310,7 +310,7 @@ wmh_status wmh_server_submit(wmh_server *srv, const uint64_t *row_ptr, const uin
     if (!row_ptr || (n_rows && !sig) || (nnz && (!col || !val)))
         return fail(ctx, WMH_E_ARG, "null buffer");
     RowStats stats;
-    const wmh_status st = check_rows_host(ctx, row_ptr, col, val, n_rows, nnz, &stats);
+    const wmh_status st = check_rows_host(ctx, row_ptr, col, val, n_rows, nnz, srv->cfg.k, &stats);
     if (st != WMH_OK) return st;
     const uint64_t bytes = (n_rows + 1) * 8 + nnz * 8 + n_rows * (uint64_t)srv->cfg.k * 2;
     if (bytes > srv->cfg.mem_budget)
