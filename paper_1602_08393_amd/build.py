@@ -10,10 +10,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwmh.so")
-SOURCES = ["wmh_host.cpp", "wmh_server.cpp", "wmh_kernels.hip", "wmh_collide.hip", "wmh_index.hip",
+SOURCES = ["wmh_host.cpp", "wmh_server.cpp", "wmh_kernels.hip", "wmh_walk.hip", "wmh_collide.hip",
+           "wmh_index.hip",
            "wmh_tune.cpp", "wmh_codec.hip", "wmh_codec_host.cpp",
            "wmh_quantize.hip", "wmh_scale.cpp", "wmh_lsh.hip", "wmh_lsh_host.cpp"]
 ARCH = "gfx950"
+# Per-file options.  The shared-window walk's branches are all scalar; leaving such regions
+# unstructured lets its early loop exits leave the loop directly, which keeps the waits for its
+# prefetched stream windows exact.
+EXTRA = {"wmh_walk.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions"]}
 
 
 def hipcc() -> str:
@@ -39,7 +44,7 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"]
-        cmd = [cc, *lang, *flags(), "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc, *lang, *flags(), *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

@@ -1,0 +1,59 @@
+// Shared position stream entries as the walks read them.  Entry j * depth + t - 1 holds step t
+// of hash j: wide entries are (component c, offset) pairs of 32-bit words; packed entries are
+// one word, (offset << 16) | (c * scale), where c * scale is the LDS byte offset of component
+// c's group of dense-row values.  gfx950 only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wmh {
+
+// K consecutive shared-stream entries of one lane (4-byte packed or 8-byte wide), read with the
+// widest aligned loads: the first entry index is a multiple of K.
+template <int K, bool kPacked>
+struct EntryRun {
+    static constexpr int kWordsPerEntry = kPacked ? 1 : 2;
+    static constexpr int kWords = K * kWordsPerEntry;
+    uint32_t w[kWords];
+
+    // the run starting `lane_word` words after a (wave-uniform) window start
+    __device__ __forceinline__ void load_at(const uint32_t *window, uint32_t lane_word)
+    {
+        load(window + lane_word, 0);
+    }
+
+    __device__ __forceinline__ void load(const void *entries, uint64_t index)
+    {
+        const uint32_t *p = reinterpret_cast<const uint32_t *>(entries) + index * (kPacked ? 1 : 2);
+        if constexpr (kWords == 1) {
+            w[0] = p[0];
+        } else if constexpr (kWords == 2) {
+            const uint2 q = *reinterpret_cast<const uint2 *>(p);
+            w[0] = q.x;
+            w[1] = q.y;
+        } else {
+#pragma unroll
+            for (int i = 0; i < kWords / 4; ++i) {
+                const uint4 q = reinterpret_cast<const uint4 *>(p)[i];
+                w[4 * i] = q.x;
+                w[4 * i + 1] = q.y;
+                w[4 * i + 2] = q.z;
+                w[4 * i + 3] = q.w;
+            }
+        }
+    }
+    // LDS byte offset of the step's component group (c * scale) and the offset in the piece
+    __device__ __forceinline__ void get(int k, uint32_t scale, uint32_t *lds, uint32_t *off) const
+    {
+        if (kPacked) {
+            *lds = w[k] & 0xFFFFu;
+            *off = w[k] >> 16;
+        } else {
+            *lds = w[2 * k] * scale;
+            *off = w[2 * k + 1];
+        }
+    }
+};
+
+}  // namespace wmh

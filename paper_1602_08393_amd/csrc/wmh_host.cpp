@@ -134,26 +134,27 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const w
     p.independent_rows = o.walk == 2;
     if (batched_lds_bytes(ctx->dims, p) > 160 * 1024 - 64) return false;
     p.packed = p.narrow && (uint64_t)ctx->dims * p.scale() <= 65536u;
-    // shared stream depth: cover eight mean step counts of the sparsest row, in whole windows
-    // (the batched kernel always reads at least one window of the stream)
-    const uint32_t win = p.window();  // 64, 128 or 256 steps; divides 65536
+    // shared stream depth: cover eight mean step counts of the sparsest row, in whole cycles of
+    // three windows (the walk's prefetch ring) that stay below the cap
+    const uint32_t cycle = p.cycle();  // 3 x (64, 128 or 256) steps
+    const uint32_t max_depth = 65535u / cycle * cycle;
     auto round_up = [&](double steps) {
-        const double w = std::ceil(steps / win) * win;
-        return (uint32_t)std::max<double>(win, std::min(65536.0, w));
+        const double w = std::ceil(steps / cycle) * cycle;
+        return (uint32_t)std::max<double>(cycle, std::min<double>(max_depth, w));
     };
     uint32_t depth;
     if (o.stream_depth == UINT32_MAX) {
-        depth = win;
+        depth = p.independent_rows ? cycle : 0;  // the independent-rows walk reads the stream
     } else if (o.stream_depth) {
         depth = round_up((double)o.stream_depth);
     } else if (min_green != ~0ull && min_green != 0) {
         const double mean_steps = (double)ctx->total / (double)min_green;
         depth = round_up(std::min(65536.0, 8.0 * mean_steps + 64.0));
     } else {
-        depth = 4096;
+        depth = 4096 / cycle * cycle;
     }
-    while (depth > win && (uint64_t)depth * k * stream_entry_bytes(p.packed) > kStreamBudgetBytes)
-        depth -= win;
+    while (depth > cycle && (uint64_t)depth * k * (p.packed ? 4 : 8) > kStreamBudgetBytes)
+        depth -= cycle;
     p.stream_depth = depth;
     *plan = p;
     return true;
@@ -620,8 +621,7 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         ctx->profiled_stream = false;
     } else {
         {
-            wmh_status st = ensure_stream_capacity(
-                ctx, (size_t)plan.stream_depth * k * stream_entry_bytes(plan.packed));
+            wmh_status st = ensure_stream_capacity(ctx, plan.stream_bytes(k));
             if (st != WMH_OK) return st;
         }
         const int per_cu = std::max(1, batched_blocks_per_cu(ctx->dims, plan));

@@ -47,16 +47,22 @@ struct BatchedPlan {
     uint32_t rows_per_block;   // R
     uint32_t steps_per_lane;   // K: steps a lane tests per window (R, or 4 when R < 4)
     uint32_t hashes_per_tile;  // J
-    uint32_t stream_depth;     // T0 (a multiple of the window, 64 / R * K steps; <= 65536)
+    uint32_t stream_depth;     // T0: 0 (every draw in-lane) or whole cycles of three windows
+                               // (a window is 64 / R * K steps), below the cap
     uint32_t waves_per_block;
     bool narrow;               // dense rows stored as uint16 (every bound < 65536)
     bool packed;               // 4-byte stream entries
     bool independent_rows;     // each row of a block walks its own hash ids (R = 4 only)
     uint32_t scale() const { return rows_per_block * (narrow ? 2u : 4u); }
     uint32_t window() const { return 64u / rows_per_block * steps_per_lane; }
+    // the shared walk prefetches three windows ahead of the one it tests
+    uint32_t cycle() const { return 3u * window(); }
+    // stream of k hash ids, plus the three windows that the last id's prefetches read past it
+    size_t stream_bytes(uint32_t k) const
+    {
+        return stream_depth ? ((size_t)stream_depth * k + cycle()) * (packed ? 4u : 8u) : 0u;
+    }
 };
-
-inline size_t stream_entry_bytes(bool packed) { return packed ? 4 : 8; }
 
 // Checks the rows and gathers the statistics of CheckWords (M = total, for the cost estimates).
 hipError_t launch_validate(const Rows &rows, const uint32_t *bound, uint32_t dims, uint64_t total,
@@ -80,6 +86,12 @@ hipError_t launch_batched(const Bounds &b, const Rows &rows, uint32_t k, uint64_
 
 // Dynamic LDS bytes a batched plan needs.
 size_t batched_lds_bytes(uint32_t dims, const BatchedPlan &plan);
+
+// The shared-window walk (no checks: launch_batched validates the plan) and its occupancy.
+hipError_t launch_shared_walk(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
+                              uint16_t *sig, const BatchedPlan &plan, const void *entries,
+                              uint32_t *tile_counter, uint32_t grid, hipStream_t stream);
+int shared_walk_blocks_per_cu(const BatchedPlan &plan, size_t lds);
 
 // Resident workgroups per CU for a batched plan (0 when it does not fit).
 int batched_blocks_per_cu(uint32_t dims, const BatchedPlan &plan);

@@ -1,5 +1,6 @@
 // HIP kernels of the hash walk for gfx950: input validation, the plain per-lane walk, the
-// shared position stream and the batched persistent walk.
+// shared position stream and the independent-rows walk (the shared-window walk has a file of
+// its own).
 //
 // Work per (row, hash j): draw positions p_1, p_2, ... of hash j, map each to its component c
 // and offset (Algorithm 5 with a uniform bucket table in place of Algorithm 4's per-integer
@@ -11,6 +12,7 @@
 
 #include <algorithm>
 
+#include "wmh_entries.h"
 #include "wmh_internal.h"
 
 namespace wmh {
@@ -296,297 +298,6 @@ __global__ __launch_bounds__(256) void draws_kernel(Bounds b, uint64_t seed, uin
 }
 
 // ---------------------------------------------------------------------------------------------
-// Batched persistent walk.
-//
-// A tile is (row block of R rows) x (block of J hash ids).  Workgroups take tiles from an
-// atomic counter; the R rows of a tile's row block sit in LDS transposed (x[c * R + r]) so one
-// LDS read fetches component c of all R rows.  A wavefront walks one hash id for the whole
-// row block: lane l tests step base + l + 1 of the window [base + 1, base + 64] for every row,
-// a ballot per row gives the first green step of that row in the window, and the walk ends
-// when every row of the block has stopped.  Every row of the block sees the same draw, so one
-// draw serves R rows (the sequence depends only on (seed, j, t), never on the row), and the
-// window replaces the per-lane geometric tail of the plain walk by at most one partly used
-// window per (block, hash).  Draws come from the shared stream for t <= depth and are made
-// in-lane beyond it.
-// ---------------------------------------------------------------------------------------------
-// K consecutive shared-stream entries of one lane (4-byte packed or 8-byte wide), read with the
-// widest aligned loads: the first entry index is a multiple of K.
-template <int K, bool kPacked>
-struct EntryRun {
-    static constexpr int kWordsPerEntry = kPacked ? 1 : 2;
-    static constexpr int kWords = K * kWordsPerEntry;
-    uint32_t w[kWords];
-
-    // the run starting `lane_word` words after a (wave-uniform) window start
-    __device__ __forceinline__ void load_at(const uint32_t *window, uint32_t lane_word)
-    {
-        load(window + lane_word, 0);
-    }
-
-    __device__ __forceinline__ void load(const void *entries, uint64_t index)
-    {
-        const uint32_t *p = reinterpret_cast<const uint32_t *>(entries) + index * (kPacked ? 1 : 2);
-        if constexpr (kWords == 1) {
-            w[0] = p[0];
-        } else if constexpr (kWords == 2) {
-            const uint2 q = *reinterpret_cast<const uint2 *>(p);
-            w[0] = q.x;
-            w[1] = q.y;
-        } else {
-#pragma unroll
-            for (int i = 0; i < kWords / 4; ++i) {
-                const uint4 q = reinterpret_cast<const uint4 *>(p)[i];
-                w[4 * i] = q.x;
-                w[4 * i + 1] = q.y;
-                w[4 * i + 2] = q.z;
-                w[4 * i + 3] = q.w;
-            }
-        }
-    }
-    // LDS byte offset of the step's component group (c * scale) and the offset in the piece
-    __device__ __forceinline__ void get(int k, uint32_t scale, uint32_t *lds, uint32_t *off) const
-    {
-        if (kPacked) {
-            *lds = w[k] & 0xFFFFu;
-            *off = w[k] >> 16;
-        } else {
-            *lds = w[2 * k] * scale;
-            *off = w[2 * k + 1];
-        }
-    }
-};
-
-// Lanes [r * L, (r + 1) * L) of a wavefront, L = 64 / R.
-template <int R>
-__device__ __forceinline__ uint64_t row_lanes(uint32_t r)
-{
-    constexpr uint32_t L = kWave / R;
-    if constexpr (L == kWave) return ~0ull;
-    else return ((1ull << L) - 1ull) << (r * L);
-}
-
-// min(v, v of the lane the DPP control selects); lanes outside the written rows, or whose
-// source lies outside their row, keep v.
-template <int kCtrl, int kRows>
-__device__ __forceinline__ uint32_t dpp_min(uint32_t v)
-{
-    const uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFFu, (int)v, kCtrl,
-                                                             kRows, 0xF, false);
-    return min(v, t);
-}
-
-// Minimum of v over each group of L consecutive lanes (L a power of two <= 64), left in the
-// group's last lane: prefix minima by row shifts inside 16-lane DPP rows, then row broadcasts
-// (lane 15 into the next row, lane 31 into rows 2 and 3) for groups of 32 and 64 lanes.
-template <uint32_t L>
-__device__ __forceinline__ uint32_t group_min_at_last_lane(uint32_t v)
-{
-    if constexpr (L >= 2) v = dpp_min<0x111, 0xF>(v);   // row_shr:1
-    if constexpr (L >= 4) v = dpp_min<0x112, 0xF>(v);   // row_shr:2
-    if constexpr (L >= 8) v = dpp_min<0x114, 0xF>(v);   // row_shr:4
-    if constexpr (L >= 16) v = dpp_min<0x118, 0xF>(v);  // row_shr:8
-    if constexpr (L >= 32) v = dpp_min<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-    if constexpr (L >= 64) v = dpp_min<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
-    return v;
-}
-
-// The top bit of every L-lane segment of a 64-bit lane mask.
-template <uint32_t L>
-__host__ __device__ constexpr uint64_t segment_tops()
-{
-    uint64_t m = 0;
-    for (uint32_t r = 0; r < kWave / L; ++r) m |= 1ull << (r * L + L - 1);
-    return m;
-}
-
-// Up to four rows per block the walk fits eight wavefronts per SIMD (at most 64 VGPRs and a
-// few scalar registers spilled to vector lanes); wider blocks keep their registers.
-template <int R>
-constexpr int walk_waves_per_eu() { return R <= 4 ? 8 : 1; }
-
-template <typename XT, int R, int K, bool kPacked>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves_per_eu<R>()))) void batched_kernel(Bounds b, Rows rows, uint32_t k,
-                                                       uint64_t seed, uint16_t *__restrict__ sig,
-                                                       uint32_t hashes_per_tile, uint32_t depth,
-                                                       const void *__restrict__ entries,
-                                                       uint32_t *tile_counter)
-{
-    // Lane layout of one window: lane l serves row r = l / L (L = 64 / R lanes per row) and
-    // the K consecutive steps base + g*K + 1 .. base + g*K + K, g = l mod L; the 64 lanes
-    // cover steps base + 1 .. base + kWin of all R rows, kWin = L * K.
-    constexpr uint32_t L = kWave / R;
-    constexpr uint32_t kWin = L * K;
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint32_t tile_slot;
-    __shared__ uint32_t unit_slot;
-    __shared__ uint32_t nonempty;
-    const uint32_t D = b.dims;
-    XT *x = reinterpret_cast<XT *>(smem);
-    uint16_t *hbuf = reinterpret_cast<uint16_t *>(smem + (((size_t)D * R * sizeof(XT) + 15) & ~(size_t)15));
-    const uint32_t my_row = lane() / L;
-    const uint32_t my_grp = lane() % L;
-    constexpr uint32_t kScale = R * sizeof(XT);  // LDS bytes per component group
-    const uint32_t row_byte = my_row * sizeof(XT);
-    // 1 + position in a window of each of the lane's K steps; offset of its run in words
-    uint32_t step_in_window[K];
-#pragma unroll
-    for (int q = 0; q < (int)K; ++q) step_in_window[q] = my_grp * K + q + 1u;
-    const uint32_t lane_words = my_grp * K * EntryRun<K, kPacked>::kWordsPerEntry;
-
-    const uint64_t n_blocks = (rows.n_rows + R - 1) / R;
-    const uint32_t n_hash_tiles = (k + hashes_per_tile - 1) / hashes_per_tile;
-    const uint64_t n_tiles = n_blocks * n_hash_tiles;
-    uint64_t staged = ~0ull;
-
-    while (true) {
-        if (threadIdx.x == 0) {
-            tile_slot = atomicAdd(tile_counter, 1u);
-            unit_slot = 0;
-        }
-        __syncthreads();
-        const uint64_t tile = tile_slot;
-        if (tile >= n_tiles) break;
-        const uint64_t blk = tile / n_hash_tiles;
-        const uint32_t ht = (uint32_t)(tile - blk * n_hash_tiles);
-        const uint64_t row0 = blk * R;
-        const uint32_t n_here = (uint32_t)min((uint64_t)R, rows.n_rows - row0);
-
-        if (blk != staged) {
-            // zero the block, then scatter its rows
-            uint32_t *xz = reinterpret_cast<uint32_t *>(x);
-            const uint32_t words = (uint32_t)(((size_t)D * R * sizeof(XT) + 3) / 4);
-            for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) xz[i] = 0u;
-            if (threadIdx.x == 0) nonempty = 0;
-            __syncthreads();
-            uint32_t mine = 0;
-            for (uint32_t r = 0; r < n_here; ++r) {
-                const uint64_t lo = rows.row_ptr[row0 + r], hi = rows.row_ptr[row0 + r + 1];
-                for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-                    const uint32_t v = rows.val[e];
-                    const uint32_t c = rows.col[e];
-                    if (c < D) x[(size_t)c * R + r] = (XT)v;
-                    if (v) mine |= 1u << r;
-                }
-            }
-            if (mine) atomicOr(&nonempty, mine);
-            __syncthreads();
-            staged = blk;
-        }
-        // Wave-uniform values are read into scalar registers so every branch on them is a
-        // scalar branch: no lane-divergent region sits on the unit loop's path.
-        const uint32_t live = __builtin_amdgcn_readfirstlane(nonempty);
-        const bool my_row_live = ((live >> my_row) & 1u) != 0;
-        // bit r * L set for every live row r: the walk ends when each of them has a green lane
-        // top bit of every live row's L-lane segment: the walk ends when each of those
-        // segments of the "has a green step" ballot is nonzero
-        uint64_t need = 0;
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            if ((live >> r) & 1u) need |= 1ull << (r * L + L - 1);
-        const uint32_t j0 = ht * hashes_per_tile;
-        const uint32_t j1 = min(k, j0 + hashes_per_tile);
-
-        while (true) {
-            // claim the next hash id of the tile.  All 64 lanes add 1 (no lane-divergent
-            // region here), so the counter only moves in steps of 64 and every value one
-            // wave instruction returns lies in [64u, 64u + 64): shifting any lane's value by 6
-            // gives the wave's claim u, whatever order the lanes are serviced in.
-            const uint32_t claimed = atomicAdd(&unit_slot, 1u);
-            const uint32_t j = j0 + ((uint32_t)__builtin_amdgcn_readfirstlane(claimed) >> 6);
-            if (j >= j1) break;
-
-            // Each lane keeps the first green step among its own steps (kNoStep: none yet); a
-            // row's hash is the smallest of its lanes' values, since together they cover every
-            // step, and a row whose smallest value is above the cap saturates at 65535.
-            constexpr uint32_t kNoStep = 0xFFFFFFFFu;
-            constexpr uint32_t kNotGreen = 0x10000u;  // base + kNotGreen is past the cap
-            uint32_t lane_h = kNoStep;
-            bool walking = live != 0;
-            // The stream holds depth >= 64 steps per hash id.  Entries are prefetched three
-            // windows ahead into a ring of three register sets, each reloaded in place right
-            // after its window is tested; the loads use clamped, in-bounds indices (windows
-            // past the stream re-read its last window and ignore it) so they stay straight-line
-            // code and no register with a load in flight is ever copied.  The window's address
-            // is scalar; each lane adds its own 32-bit offset.
-            const uint32_t *id_entries = reinterpret_cast<const uint32_t *>(entries) +
-                                         (uint64_t)j * depth * EntryRun<K, kPacked>::kWordsPerEntry;
-            const uint32_t last_base = depth - kWin;
-            auto fetch = [&](uint32_t base) {
-                EntryRun<K, kPacked> run;
-                run.load_at(id_entries + (size_t)min(base, last_base) * EntryRun<K, kPacked>::kWordsPerEntry,
-                            lane_words);
-                return run;
-            };
-            // tests window [base + 1, base + kWin] (the caller checks that the walk goes on)
-            auto window = [&](const EntryRun<K, kPacked> &run, uint32_t base) {
-                uint32_t c = kNotGreen;  // 1 + position in the window of the lane's first green step
-                if (base < depth) {
-                    // all K reads in flight before the first compare
-                    uint32_t xv[K], off[K];
-#pragma unroll
-                    for (int q = 0; q < (int)K; ++q) {
-                        uint32_t lds;
-                        run.get(q, kScale, &lds, &off[q]);
-                        xv[q] = *reinterpret_cast<const XT *>(smem + lds + row_byte);
-                    }
-#pragma unroll
-                    for (int q = K - 1; q >= 0; --q) c = off[q] < xv[q] ? step_in_window[q] : c;
-                } else {
-                    // beyond the stream (rare): draw in-lane, one step at a time
-#pragma unroll 1
-                    for (int q = K - 1; q >= 0; --q) {
-                        const uint32_t t = base + my_grp * K + q + 1u;
-                        const uint64_t p = position(seed, j, t, b.total, b.threshold);
-                        uint64_t o64;
-                        const uint32_t comp = component_of(p, b.prefix, b.bucket, b.shift, &o64);
-                        c = o64 < (uint64_t)x[(size_t)comp * R + my_row] ? my_grp * K + q + 1u : c;
-                    }
-                }
-                // step 65536 of the last window may show up here: it is above the cap like
-                // "no green step", and the walk ends with that window
-                lane_h = min(lane_h, base + c);
-                // done when every live row has a lane with a green step: fold each row's L
-                // lanes of the ballot onto its lowest bit (scalar work)
-                // which rows have a lane with a green step: per L-lane segment of the ballot,
-                // (low L-1 bits + all ones in them) carries into the top bit iff one is set
-                // (no carry leaves a segment); or-ing the ballot covers the top bit itself
-                const uint64_t seen = __builtin_amdgcn_ballot_w64(lane_h <= kCap);
-                const uint64_t low = ~segment_tops<L>();
-                walking = ((((seen & low) + low) | seen) & need) != need;
-            };
-            EntryRun<K, kPacked> e0 = fetch(0), e1 = fetch(kWin), e2 = fetch(2 * kWin);
-            for (uint32_t base = 0; walking && base < kCap; base += 3 * kWin) {
-                window(e0, base);
-                e0 = fetch(base + 3 * kWin);
-                if (!walking || base + kWin >= kCap) break;
-                window(e1, base + kWin);
-                e1 = fetch(base + 4 * kWin);
-                if (!walking || base + 2 * kWin >= kCap) break;
-                window(e2, base + 2 * kWin);
-                e2 = fetch(base + 5 * kWin);
-            }
-            // smallest lane value of each row, in the row's last lane; above the cap: no green
-            // step, the hash saturates
-            const uint32_t best = group_min_at_last_lane<L>(lane_h);
-            // empty rows hash to 0
-            const uint32_t h = !my_row_live ? 0u : min(best, kCap);
-            // every lane stores; only each row's last lane writes a tile value
-            const uint32_t slot = my_grp == L - 1 ? my_row * hashes_per_tile + (j - j0)
-                                                  : R * hashes_per_tile + lane();
-            hbuf[slot] = (uint16_t)h;
-        }
-        __syncthreads();
-        // write the tile's signatures row by row (coalesced along j)
-        const uint32_t width = j1 - j0;
-        for (uint32_t r = 0; r < n_here; ++r) {
-            uint16_t *out = sig + (row0 + r) * (uint64_t)k + j0;
-            for (uint32_t q = threadIdx.x; q < width; q += blockDim.x) out[q] = hbuf[r * hashes_per_tile + q];
-        }
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------------------------------------
 // Independent rows (R = 4): the tiles, LDS rows and shared stream of batched_kernel, but each
 // row of a block walks its own hash ids.  batched_kernel tests every window for all R rows until
 // the block's last row is green, so it tests about E[max of R step counts] per row instead of
@@ -861,85 +572,6 @@ size_t batched_lds_bytes(uint32_t dims, const BatchedPlan &plan)
     return aligned + ((size_t)plan.rows_per_block * plan.hashes_per_tile + kWave) * 2;
 }
 
-template <typename XT, int R, int K, bool kPacked>
-static void configure_batched()
-{
-    static bool configured = false;
-    if (!configured) {
-        hipFuncSetAttribute((const void *)batched_kernel<XT, R, K, kPacked>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64);
-        configured = true;
-    }
-}
-
-template <typename XT, int R, int K, bool kPacked>
-static int batched_occupancy_t(const BatchedPlan &plan, size_t lds)
-{
-    configure_batched<XT, R, K, kPacked>();
-    int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<XT, R, K, kPacked>,
-                                                     plan.waves_per_block * kWave, lds) != hipSuccess)
-        return 1;
-    return blocks > 0 ? blocks : 1;
-}
-
-template <typename XT, int R, int K, bool kPacked>
-static hipError_t launch_batched_t(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
-                                   uint16_t *sig, const BatchedPlan &plan, const void *entries,
-                                   uint32_t *tile_counter, uint32_t grid, hipStream_t stream)
-{
-    const size_t lds = batched_lds_bytes(b.dims, plan);
-    configure_batched<XT, R, K, kPacked>();
-    batched_kernel<XT, R, K, kPacked><<<grid, plan.waves_per_block * kWave, lds, stream>>>(
-        b, rows, k, seed, sig, plan.hashes_per_tile, plan.stream_depth, entries, tile_counter);
-    return hipGetLastError();
-}
-
-// Calls F<XT, R, K, packed>() for the plan's template parameters: K = R, or K = 4 for R < 4.
-template <template <typename, int, int, bool> class F, typename... Args>
-static auto dispatch_batched(const BatchedPlan &plan, Args &&...args)
-    -> decltype(F<uint16_t, 1, 1, true>::run(args...))
-{
-#define WMH_RK_CASE(RR, KK)                                                                      \
-    if (plan.rows_per_block == RR && plan.steps_per_lane == KK) {                                \
-        if (plan.narrow)                                                                         \
-            return plan.packed ? F<uint16_t, RR, KK, true>::run(args...)                         \
-                               : F<uint16_t, RR, KK, false>::run(args...);                       \
-        return plan.packed ? F<uint32_t, RR, KK, true>::run(args...)                             \
-                           : F<uint32_t, RR, KK, false>::run(args...);                           \
-    }
-    WMH_RK_CASE(1, 1)
-    WMH_RK_CASE(1, 4)
-    WMH_RK_CASE(2, 2)
-    WMH_RK_CASE(2, 4)
-    WMH_RK_CASE(4, 4)
-    WMH_RK_CASE(8, 8)
-    WMH_RK_CASE(16, 16)
-#undef WMH_RK_CASE
-    return F<uint16_t, 1, 1, true>::fail();
-}
-
-template <typename XT, int R, int K, bool kPacked>
-struct LaunchBatched {
-    static hipError_t run(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
-                          uint16_t *sig, const BatchedPlan &plan, const void *entries,
-                          uint32_t *tile_counter, uint32_t grid, hipStream_t stream)
-    {
-        return launch_batched_t<XT, R, K, kPacked>(b, rows, k, seed, sig, plan, entries,
-                                                   tile_counter, grid, stream);
-    }
-    static hipError_t fail() { return hipErrorInvalidValue; }
-};
-
-template <typename XT, int R, int K, bool kPacked>
-struct OccupancyBatched {
-    static int run(const BatchedPlan &plan, size_t lds)
-    {
-        return batched_occupancy_t<XT, R, K, kPacked>(plan, lds);
-    }
-    static int fail() { return 0; }
-};
-
 template <typename XT, bool kPacked>
 static void configure_rows()
 {
@@ -980,6 +612,8 @@ hipError_t launch_batched(const Bounds &b, const Rows &rows, uint32_t k, uint64_
 {
     if (batched_lds_bytes(b.dims, plan) > 160 * 1024 - 64) return hipErrorInvalidValue;
     if (plan.packed && !plan.narrow) return hipErrorInvalidValue;
+    // the shared walk reads whole three-window cycles of the stream (plus one spare cycle)
+    if (plan.stream_depth % plan.cycle() != 0 || plan.stream_depth >= kCap) return hipErrorInvalidValue;
     if (plan.independent_rows) {
         if (plan.rows_per_block != 4 || plan.stream_depth < kWave) return hipErrorInvalidValue;
         if (plan.narrow)
@@ -987,8 +621,7 @@ hipError_t launch_batched(const Bounds &b, const Rows &rows, uint32_t k, uint64_
                                : launch_rows_t<uint16_t, false>(b, rows, k, seed, sig, plan, entries, tile_counter, grid, stream);
         return launch_rows_t<uint32_t, false>(b, rows, k, seed, sig, plan, entries, tile_counter, grid, stream);
     }
-    return dispatch_batched<LaunchBatched>(plan, b, rows, k, seed, sig, plan, entries,
-                                           tile_counter, grid, stream);
+    return launch_shared_walk(b, rows, k, seed, sig, plan, entries, tile_counter, grid, stream);
 }
 
 int batched_blocks_per_cu(uint32_t dims, const BatchedPlan &plan)
@@ -1001,7 +634,7 @@ int batched_blocks_per_cu(uint32_t dims, const BatchedPlan &plan)
                                             : rows_occupancy_t<uint16_t, false>(plan, lds);
         return rows_occupancy_t<uint32_t, false>(plan, lds);
     }
-    return dispatch_batched<OccupancyBatched>(plan, plan, lds);
+    return shared_walk_blocks_per_cu(plan, lds);
 }
 
 hipError_t launch_estimate(const uint16_t *A, const uint16_t *B, uint64_t n_pairs, uint32_t k,

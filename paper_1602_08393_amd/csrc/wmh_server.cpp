@@ -276,7 +276,7 @@ wmh_status wmh_server_create(wmh_ctx *ctx, const wmh_server_config *cfg_in, wmh_
     hipError_t e = hipSuccess;
     if (srv->batched) {
         srv->grid = (uint32_t)(ctx->cu_count * std::max(1, batched_blocks_per_cu(ctx->dims, srv->plan)));
-        const size_t bytes = (size_t)srv->plan.stream_depth * cfg.k * stream_entry_bytes(srv->plan.packed);
+        const size_t bytes = srv->plan.stream_bytes(cfg.k);
         e = hipMalloc(&srv->d_stream, bytes);
         if (e == hipSuccess)
             e = launch_stream_build(bounds_view(ctx), cfg.seed, cfg.k, srv->plan.stream_depth,

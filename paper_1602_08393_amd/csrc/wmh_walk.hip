@@ -1,0 +1,368 @@
+// The shared-window walk (batched path) for gfx950: persistent workgroups over (row block,
+// hash block) tiles, one shared position stream for every row, windows of consecutive steps
+// tested by all lanes at once.
+//
+// This file is compiled with uniform regions left unstructured
+// (-structurizecfg-skip-uniform-regions): every branch of the window loop is scalar, and
+// without structurization its early exits leave the loop directly, so the wait for each
+// prefetched window is exact instead of a wait for every load in flight.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wmh_entries.h"
+#include "wmh_internal.h"
+
+namespace wmh {
+
+namespace {
+
+__device__ __forceinline__ uint32_t lane() { return threadIdx.x & (kWave - 1u); }
+
+// ---------------------------------------------------------------------------------------------
+// Batched persistent walk.
+//
+// A tile is (row block of R rows) x (block of J hash ids).  Workgroups take tiles from an
+// atomic counter; the R rows of a tile's row block sit in LDS transposed (x[c * R + r]) so one
+// LDS read fetches component c of all R rows.  A wavefront walks one hash id for the whole
+// row block, a window of L * K consecutive steps at a time (L = 64 / R lanes per row, K steps
+// per lane): lane l serves row l / L and K consecutive steps of the window, keeps the first
+// green one, and a ballot tells which rows have a green step so far; the walk ends when every
+// row of the block has one.  Every row of the block sees the same draw, so one draw serves R
+// rows (the sequence depends only on (seed, j, t), never on the row), and the window replaces
+// the per-lane geometric tail of the plain walk by at most one partly used window per (block,
+// hash).  Draws come from the shared stream for t <= depth and are made in-lane beyond it.
+// ---------------------------------------------------------------------------------------------
+// min(v, v of the lane the DPP control selects); lanes outside the written rows, or whose
+// source lies outside their row, keep v.
+template <int kCtrl, int kRows>
+__device__ __forceinline__ uint32_t dpp_min(uint32_t v)
+{
+    const uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFFu, (int)v, kCtrl,
+                                                             kRows, 0xF, false);
+    return min(v, t);
+}
+
+// Minimum of v over each group of L consecutive lanes (L a power of two <= 64), left in the
+// group's last lane: prefix minima by row shifts inside 16-lane DPP rows, then row broadcasts
+// (lane 15 into the next row, lane 31 into rows 2 and 3) for groups of 32 and 64 lanes.
+template <uint32_t L>
+__device__ __forceinline__ uint32_t group_min_at_last_lane(uint32_t v)
+{
+    if constexpr (L >= 2) v = dpp_min<0x111, 0xF>(v);   // row_shr:1
+    if constexpr (L >= 4) v = dpp_min<0x112, 0xF>(v);   // row_shr:2
+    if constexpr (L >= 8) v = dpp_min<0x114, 0xF>(v);   // row_shr:4
+    if constexpr (L >= 16) v = dpp_min<0x118, 0xF>(v);  // row_shr:8
+    if constexpr (L >= 32) v = dpp_min<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    if constexpr (L >= 64) v = dpp_min<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+// The top bit of every L-lane segment of a 64-bit lane mask.
+template <uint32_t L>
+__host__ __device__ constexpr uint64_t segment_tops()
+{
+    uint64_t m = 0;
+    for (uint32_t r = 0; r < kWave / L; ++r) m |= 1ull << (r * L + L - 1);
+    return m;
+}
+
+// Up to four rows per block the walk fits eight wavefronts per SIMD (at most 64 VGPRs and a
+// few scalar registers spilled to vector lanes); wider blocks keep their registers.
+template <int R>
+constexpr int walk_waves_per_eu() { return R <= 4 ? 8 : 1; }
+
+template <typename XT, int R, int K, bool kPacked>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves_per_eu<R>()))) void batched_kernel(Bounds b, Rows rows, uint32_t k,
+                                                       uint64_t seed, uint16_t *__restrict__ sig,
+                                                       uint32_t hashes_per_tile, uint32_t depth,
+                                                       const void *entries,
+                                                       uint32_t *tile_counter)
+{
+    // Lane layout of one window: lane l serves row r = l / L (L = 64 / R lanes per row) and
+    // the K consecutive steps base + g*K + 1 .. base + g*K + K, g = l mod L; the 64 lanes
+    // cover steps base + 1 .. base + kWin of all R rows, kWin = L * K.
+    constexpr uint32_t L = kWave / R;
+    constexpr uint32_t kWin = L * K;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t tile_slot;
+    __shared__ uint32_t unit_slot;
+    __shared__ uint32_t nonempty;
+    const uint32_t D = b.dims;
+    XT *x = reinterpret_cast<XT *>(smem);
+    uint16_t *hbuf = reinterpret_cast<uint16_t *>(smem + (((size_t)D * R * sizeof(XT) + 15) & ~(size_t)15));
+    const uint32_t my_row = lane() / L;
+    const uint32_t my_grp = lane() % L;
+    constexpr uint32_t kScale = R * sizeof(XT);  // LDS bytes per component group
+    const uint32_t row_byte = my_row * sizeof(XT);
+    // 1 + position in a window of each of the lane's K steps; offset of its run in words
+    uint32_t step_in_window[K];
+#pragma unroll
+    for (int q = 0; q < (int)K; ++q) step_in_window[q] = my_grp * K + q + 1u;
+    const uint32_t lane_words = my_grp * K * EntryRun<K, kPacked>::kWordsPerEntry;
+
+    const uint64_t n_blocks = (rows.n_rows + R - 1) / R;
+    const uint32_t n_hash_tiles = (k + hashes_per_tile - 1) / hashes_per_tile;
+    const uint64_t n_tiles = n_blocks * n_hash_tiles;
+    uint64_t staged = ~0ull;
+
+    while (true) {
+        if (threadIdx.x == 0) {
+            tile_slot = atomicAdd(tile_counter, 1u);
+            unit_slot = 0;
+        }
+        __syncthreads();
+        const uint64_t tile = tile_slot;
+        if (tile >= n_tiles) break;
+        const uint64_t blk = tile / n_hash_tiles;
+        const uint32_t ht = (uint32_t)(tile - blk * n_hash_tiles);
+        const uint64_t row0 = blk * R;
+        const uint32_t n_here = (uint32_t)min((uint64_t)R, rows.n_rows - row0);
+
+        if (blk != staged) {
+            // zero the block, then scatter its rows
+            uint32_t *xz = reinterpret_cast<uint32_t *>(x);
+            const uint32_t words = (uint32_t)(((size_t)D * R * sizeof(XT) + 3) / 4);
+            for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) xz[i] = 0u;
+            if (threadIdx.x == 0) nonempty = 0;
+            __syncthreads();
+            uint32_t mine = 0;
+            for (uint32_t r = 0; r < n_here; ++r) {
+                const uint64_t lo = rows.row_ptr[row0 + r], hi = rows.row_ptr[row0 + r + 1];
+                for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+                    const uint32_t v = rows.val[e];
+                    const uint32_t c = rows.col[e];
+                    if (c < D) x[(size_t)c * R + r] = (XT)v;
+                    if (v) mine |= 1u << r;
+                }
+            }
+            if (mine) atomicOr(&nonempty, mine);
+            __syncthreads();
+            staged = blk;
+        }
+        // Wave-uniform values are read into scalar registers so every branch on them is a
+        // scalar branch: no lane-divergent region sits on the unit loop's path.
+        const uint32_t live = __builtin_amdgcn_readfirstlane(nonempty);
+        const bool my_row_live = ((live >> my_row) & 1u) != 0;
+        // bit r * L set for every live row r: the walk ends when each of them has a green lane
+        // top bit of every live row's L-lane segment: the walk ends when each of those
+        // segments of the "has a green step" ballot is nonzero
+        uint64_t need = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if ((live >> r) & 1u) need |= 1ull << (r * L + L - 1);
+        const uint32_t j0 = ht * hashes_per_tile;
+        const uint32_t j1 = min(k, j0 + hashes_per_tile);
+
+        while (true) {
+            // claim the next hash id of the tile.  All 64 lanes add 1 (no lane-divergent
+            // region here), so the counter only moves in steps of 64 and every value one
+            // wave instruction returns lies in [64u, 64u + 64): shifting any lane's value by 6
+            // gives the wave's claim u, whatever order the lanes are serviced in.
+            const uint32_t claimed = atomicAdd(&unit_slot, 1u);
+            const uint32_t j = j0 + ((uint32_t)__builtin_amdgcn_readfirstlane(claimed) >> 6);
+            if (j >= j1) break;
+
+            // Each lane keeps the first green step among its own steps (kNoStep: none yet); a
+            // row's hash is the smallest of its lanes' values, since together they cover every
+            // step, and a row whose smallest value is above the cap saturates at 65535.  Lanes
+            // of rows with no green unit start at 0, so the stop test sees them as done.
+            constexpr uint32_t kNoStep = 0xFFFFFFFFu;
+            constexpr uint32_t kNotGreen = 0x10000u;  // base + kNotGreen is past the cap
+            uint32_t lane_h = my_row_live ? kNoStep : 0u;
+            // The walk goes on while some row's L-lane segment of the "has a green step" ballot
+            // is zero: the lowest zero segment takes no borrow from below, so it shows its top
+            // bit in (seen - bottoms) & ~seen, and a nonzero segment v shows it only when v - 1
+            // has the top bit, which v then has as well.
+            constexpr uint64_t kTops = segment_tops<L>();
+            constexpr uint64_t kBottoms = kTops >> (L - 1);
+            auto goes_on = [&]() {
+                const uint64_t seen = __builtin_amdgcn_ballot_w64(lane_h <= kCap);
+                return ((seen - kBottoms) & ~seen & kTops) != 0;
+            };
+            // window [base + 1, base + kWin] from the lane's K stream entries
+            auto stream_window = [&](const EntryRun<K, kPacked> &run, uint32_t base) {
+                uint32_t xv[K], off[K];  // all K reads in flight before the first compare
+#pragma unroll
+                for (int q = 0; q < (int)K; ++q) {
+                    uint32_t lds;
+                    run.get(q, kScale, &lds, &off[q]);
+                    xv[q] = *reinterpret_cast<const XT *>(smem + lds + row_byte);
+                }
+                uint32_t c = kNotGreen;  // 1 + position in the window of the lane's first green step
+#pragma unroll
+                for (int q = K - 1; q >= 0; --q) c = off[q] < xv[q] ? step_in_window[q] : c;
+                lane_h = min(lane_h, base + c);
+            };
+            // the same window with the draws made in-lane, one step at a time; step 65536 of
+            // the last window may show up here: it is above the cap like "no green step"
+            auto lane_window = [&](uint32_t base) {
+                uint32_t c = kNotGreen;
+#pragma unroll 1
+                for (int q = K - 1; q >= 0; --q) {
+                    const uint32_t t = base + my_grp * K + q + 1u;
+                    const uint64_t p = position(seed, j, t, b.total, b.threshold);
+                    uint64_t o64;
+                    const uint32_t comp = component_of(p, b.prefix, b.bucket, b.shift, &o64);
+                    c = o64 < (uint64_t)x[(size_t)comp * R + my_row] ? my_grp * K + q + 1u : c;
+                }
+                lane_h = min(lane_h, base + c);
+            };
+
+            // Stream windows.  The depth is a whole number of cycles of three windows below
+            // the cap, so these windows test nothing but the stop condition.  Entries are
+            // prefetched three windows ahead into a ring of three register sets, each reloaded
+            // right after its window is tested; the buffer holds one spare cycle past the last
+            // id's entries for the prefetches of the last cycle (read, never used).  The
+            // window's address is scalar; each lane adds its own 32-bit offset.
+            bool walking = live != 0;
+            uint32_t base = 0;
+            if (walking && depth != 0) {
+                const uint32_t *id_entries =
+                    reinterpret_cast<const uint32_t *>(entries) +
+                    (uint64_t)j * depth * EntryRun<K, kPacked>::kWordsPerEntry;
+                // Each prefetch stays where it is issued: the empty asm after it is a compiler
+                // barrier for memory (entries is not a restrict pointer, so the loads are not
+                // known to read memory that nothing writes; such loads are otherwise sunk to the
+                // window that uses them, which then waits for them).
+                auto fetch = [&](uint32_t at) {
+                    EntryRun<K, kPacked> run;
+                    run.load_at(id_entries + (size_t)at * EntryRun<K, kPacked>::kWordsPerEntry,
+                                lane_words);
+                    asm volatile("" ::: "memory");
+                    return run;
+                };
+                EntryRun<K, kPacked> e0 = fetch(0), e1 = fetch(kWin), e2 = fetch(2 * kWin);
+                for (; base < depth; base += 3 * kWin) {
+                    stream_window(e0, base);
+                    if (!goes_on()) break;
+                    e0 = fetch(base + 3 * kWin);
+                    stream_window(e1, base + kWin);
+                    if (!goes_on()) break;
+                    e1 = fetch(base + 4 * kWin);
+                    stream_window(e2, base + 2 * kWin);
+                    if (!goes_on()) break;
+                    e2 = fetch(base + 5 * kWin);
+                }
+                walking = base >= depth;
+            }
+            // past the stream (rare): draws made in-lane, up to the window that holds the cap
+            for (; walking && base < kCap; base += kWin) {
+                lane_window(base);
+                walking = goes_on();
+            }
+            // smallest lane value of each row, in the row's last lane; above the cap: no green
+            // step, the hash saturates
+            const uint32_t best = group_min_at_last_lane<L>(lane_h);
+            // empty rows hash to 0
+            const uint32_t h = !my_row_live ? 0u : min(best, kCap);
+            // every lane stores; only each row's last lane writes a tile value
+            const uint32_t slot = my_grp == L - 1 ? my_row * hashes_per_tile + (j - j0)
+                                                  : R * hashes_per_tile + lane();
+            hbuf[slot] = (uint16_t)h;
+        }
+        __syncthreads();
+        // write the tile's signatures row by row (coalesced along j)
+        const uint32_t width = j1 - j0;
+        for (uint32_t r = 0; r < n_here; ++r) {
+            uint16_t *out = sig + (row0 + r) * (uint64_t)k + j0;
+            for (uint32_t q = threadIdx.x; q < width; q += blockDim.x) out[q] = hbuf[r * hashes_per_tile + q];
+        }
+        __syncthreads();
+    }
+}
+
+template <typename XT, int R, int K, bool kPacked>
+void configure_batched()
+{
+    static bool configured = false;
+    if (!configured) {
+        hipFuncSetAttribute((const void *)batched_kernel<XT, R, K, kPacked>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64);
+        configured = true;
+    }
+}
+
+template <typename XT, int R, int K, bool kPacked>
+int batched_occupancy_t(const BatchedPlan &plan, size_t lds)
+{
+    configure_batched<XT, R, K, kPacked>();
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<XT, R, K, kPacked>,
+                                                     plan.waves_per_block * kWave, lds) != hipSuccess)
+        return 1;
+    return blocks > 0 ? blocks : 1;
+}
+
+template <typename XT, int R, int K, bool kPacked>
+hipError_t launch_batched_t(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
+                                   uint16_t *sig, const BatchedPlan &plan, const void *entries,
+                                   uint32_t *tile_counter, uint32_t grid, hipStream_t stream)
+{
+    const size_t lds = batched_lds_bytes(b.dims, plan);
+    configure_batched<XT, R, K, kPacked>();
+    batched_kernel<XT, R, K, kPacked><<<grid, plan.waves_per_block * kWave, lds, stream>>>(
+        b, rows, k, seed, sig, plan.hashes_per_tile, plan.stream_depth, entries, tile_counter);
+    return hipGetLastError();
+}
+
+// Calls F<XT, R, K, packed>() for the plan's template parameters: K = R, or K = 4 for R < 4.
+template <template <typename, int, int, bool> class F, typename... Args>
+auto dispatch_batched(const BatchedPlan &plan, Args &&...args)
+    -> decltype(F<uint16_t, 1, 1, true>::run(args...))
+{
+#define WMH_RK_CASE(RR, KK)                                                                      \
+    if (plan.rows_per_block == RR && plan.steps_per_lane == KK) {                                \
+        if (plan.narrow)                                                                         \
+            return plan.packed ? F<uint16_t, RR, KK, true>::run(args...)                         \
+                               : F<uint16_t, RR, KK, false>::run(args...);                       \
+        return plan.packed ? F<uint32_t, RR, KK, true>::run(args...)                             \
+                           : F<uint32_t, RR, KK, false>::run(args...);                           \
+    }
+    WMH_RK_CASE(1, 1)
+    WMH_RK_CASE(1, 4)
+    WMH_RK_CASE(2, 2)
+    WMH_RK_CASE(2, 4)
+    WMH_RK_CASE(4, 4)
+    WMH_RK_CASE(8, 8)
+    WMH_RK_CASE(16, 16)
+#undef WMH_RK_CASE
+    return F<uint16_t, 1, 1, true>::fail();
+}
+
+template <typename XT, int R, int K, bool kPacked>
+struct LaunchBatched {
+    static hipError_t run(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
+                          uint16_t *sig, const BatchedPlan &plan, const void *entries,
+                          uint32_t *tile_counter, uint32_t grid, hipStream_t stream)
+    {
+        return launch_batched_t<XT, R, K, kPacked>(b, rows, k, seed, sig, plan, entries,
+                                                   tile_counter, grid, stream);
+    }
+    static hipError_t fail() { return hipErrorInvalidValue; }
+};
+
+template <typename XT, int R, int K, bool kPacked>
+struct OccupancyBatched {
+    static int run(const BatchedPlan &plan, size_t lds)
+    {
+        return batched_occupancy_t<XT, R, K, kPacked>(plan, lds);
+    }
+    static int fail() { return 0; }
+};
+
+}  // namespace
+
+hipError_t launch_shared_walk(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
+                              uint16_t *sig, const BatchedPlan &plan, const void *entries,
+                              uint32_t *tile_counter, uint32_t grid, hipStream_t stream)
+{
+    return dispatch_batched<LaunchBatched>(plan, b, rows, k, seed, sig, plan, entries,
+                                           tile_counter, grid, stream);
+}
+
+int shared_walk_blocks_per_cu(const BatchedPlan &plan, size_t lds)
+{
+    return dispatch_batched<OccupancyBatched>(plan, plan, lds);
+}
+
+}  // namespace wmh

@@ -175,6 +175,8 @@ def test_full_rows_hash_to_one_and_saturation(ctx):
     want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, k, seed=5)
     assert np.all(want[0] == 1) and np.all(want[1] == 65535)
     for opts in (dict(mode="plain"), dict(mode="batched", rows_per_block=4),
+                 dict(mode="batched", rows_per_block=1), dict(mode="batched", rows_per_block=16),
+                 dict(mode="batched", rows_per_block=8, stream_depth=70000),
                  dict(mode="batched", rows_per_block=2, stream_depth=128),
                  dict(mode="batched", walk="rows"),
                  dict(mode="batched", walk="rows", stream_depth=None),
