@@ -1,13 +1,35 @@
-// Shared position stream entries as the walks read them.  Entry j * depth + t - 1 holds step t
-// of hash j: wide entries are (component c, offset) pairs of 32-bit words; packed entries are
-// one word, (offset << 16) | (c * scale), where c * scale is the LDS byte offset of component
-// c's group of dense-row values.  gfx950 only.
+// What the batched walks share: the layout of a block's dense rows in LDS and the entries of
+// the shared position stream.  Entry j * depth + t - 1 holds step t of hash j: wide entries
+// are (component c, offset) pairs of 32-bit words; packed entries are one word,
+// (offset << 16) | (c * scale), where c * scale is the LDS byte offset of component c's group
+// of dense-row values (scale = RowLayout::kGroup).  gfx950 only.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace wmh {
+
+// LDS layout of the R dense rows of a block (D components each): the value of component c of
+// row r sits at byte c * kGroup + row_byte(r).  Four rows of 16-bit values form two planes of
+// row pairs (rows 0 and 1, then rows 2 and 3), one 4-byte word per component: the 32 lanes of
+// one half-wavefront serve one row pair, so the components they read spread over all 32 banks
+// (with 8-byte groups they would fall on every other bank).  Other blocks keep one group of R
+// values per component.  The host's stream scale is kGroup.
+template <typename XT, int R>
+struct RowLayout {
+    static constexpr bool kPlanes = R == 4 && sizeof(XT) == 2;
+    static constexpr uint32_t kGroup = kPlanes ? 4u : R * (uint32_t)sizeof(XT);
+    __device__ static uint32_t row_byte(uint32_t r, uint32_t dims)
+    {
+        if constexpr (kPlanes) return (r & 1u) * 2u + (r >> 1) * dims * 4u;
+        else return r * (uint32_t)sizeof(XT);
+    }
+    __device__ static XT *at(unsigned char *base, uint32_t c, uint32_t r, uint32_t dims)
+    {
+        return reinterpret_cast<XT *>(base + (size_t)c * kGroup + row_byte(r, dims));
+    }
+};
 
 // K consecutive shared-stream entries of one lane (4-byte packed or 8-byte wide), read with the
 // widest aligned loads: the first entry index is a multiple of K.

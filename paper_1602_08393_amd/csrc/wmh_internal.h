@@ -53,7 +53,12 @@ struct BatchedPlan {
     bool narrow;               // dense rows stored as uint16 (every bound < 65536)
     bool packed;               // 4-byte stream entries
     bool independent_rows;     // each row of a block walks its own hash ids (R = 4 only)
-    uint32_t scale() const { return rows_per_block * (narrow ? 2u : 4u); }
+    // LDS bytes per component of the block's dense rows (RowLayout::kGroup): four rows of
+    // 16-bit values sit in two planes of row pairs, 4 bytes per component
+    uint32_t scale() const
+    {
+        return rows_per_block == 4 && narrow ? 4u : rows_per_block * (narrow ? 2u : 4u);
+    }
     uint32_t window() const { return 64u / rows_per_block * steps_per_lane; }
     // the shared walk prefetches three windows ahead of the one it tests
     uint32_t cycle() const { return 3u * window(); }

@@ -344,8 +344,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     uint16_t *hbuf = reinterpret_cast<uint16_t *>(smem + (((size_t)D * R * sizeof(XT) + 15) & ~(size_t)15));
     const uint32_t my_row = lane() / L;
     const uint32_t gk = (lane() % L) * K;  // first of the lane's K steps inside a window
-    constexpr uint32_t kScale = R * sizeof(XT);
-    const uint32_t row_byte = my_row * sizeof(XT);
+    using Layout = RowLayout<XT, R>;
+    constexpr uint32_t kScale = Layout::kGroup;
+    const uint32_t row_byte = Layout::row_byte(my_row, D);
     const uint32_t waves = blockDim.x / kWave;
     const uint32_t wave = wave_index();
     const uint32_t last_base = depth - kWave;
@@ -377,7 +378,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                 for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
                     const uint32_t v = rows.val[e];
                     const uint32_t c = rows.col[e];
-                    if (c < D) x[(size_t)c * R + r] = (XT)v;
+                    if (c < D) *Layout::at(smem, c, r, D) = (XT)v;
                     if (v) mine |= 1u << r;
                 }
             }
@@ -430,7 +431,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                     const uint64_t p = position(seed, jr, t, b.total, b.threshold);
                     uint64_t o64;
                     const uint32_t comp = component_of(p, b.prefix, b.bucket, b.shift, &o64);
-                    c = o64 < (uint64_t)x[(size_t)comp * R + my_row] ? gk + (uint32_t)q : c;
+                    c = o64 < (uint64_t)*reinterpret_cast<const XT *>(smem + (size_t)comp * kScale + row_byte) ? gk + (uint32_t)q : c;
                 }
             }
             const uint64_t at_last = __ballot(base == kLastBase);

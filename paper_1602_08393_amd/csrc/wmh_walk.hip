@@ -22,8 +22,8 @@ __device__ __forceinline__ uint32_t lane() { return threadIdx.x & (kWave - 1u); 
 // Batched persistent walk.
 //
 // A tile is (row block of R rows) x (block of J hash ids).  Workgroups take tiles from an
-// atomic counter; the R rows of a tile's row block sit in LDS transposed (x[c * R + r]) so one
-// LDS read fetches component c of all R rows.  A wavefront walks one hash id for the whole
+// atomic counter; the R rows of a tile's row block sit in LDS component-major (RowLayout), so
+// one stream entry locates component c for every row.  A wavefront walks one hash id for the whole
 // row block, a window of L * K consecutive steps at a time (L = 64 / R lanes per row, K steps
 // per lane): lane l serves row l / L and K consecutive steps of the window, keeps the first
 // green one, and a ballot tells which rows have a green step so far; the walk ends when every
@@ -92,8 +92,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
     uint16_t *hbuf = reinterpret_cast<uint16_t *>(smem + (((size_t)D * R * sizeof(XT) + 15) & ~(size_t)15));
     const uint32_t my_row = lane() / L;
     const uint32_t my_grp = lane() % L;
-    constexpr uint32_t kScale = R * sizeof(XT);  // LDS bytes per component group
-    const uint32_t row_byte = my_row * sizeof(XT);
+    using Layout = RowLayout<XT, R>;
+    constexpr uint32_t kScale = Layout::kGroup;  // LDS bytes per component group
+    const uint32_t row_byte = Layout::row_byte(my_row, D);
     // 1 + position in a window of each of the lane's K steps; offset of its run in words
     uint32_t step_in_window[K];
 #pragma unroll
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
                 for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
                     const uint32_t v = rows.val[e];
                     const uint32_t c = rows.col[e];
-                    if (c < D) x[(size_t)c * R + r] = (XT)v;
+                    if (c < D) *Layout::at(smem, c, r, D) = (XT)v;
                     if (v) mine |= 1u << r;
                 }
             }
@@ -203,7 +204,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
                     const uint64_t p = position(seed, j, t, b.total, b.threshold);
                     uint64_t o64;
                     const uint32_t comp = component_of(p, b.prefix, b.bucket, b.shift, &o64);
-                    c = o64 < (uint64_t)x[(size_t)comp * R + my_row] ? my_grp * K + q + 1u : c;
+                    c = o64 < (uint64_t)*reinterpret_cast<const XT *>(smem + (size_t)comp * kScale + row_byte) ? my_grp * K + q + 1u : c;
                 }
                 lane_h = min(lane_h, base + c);
             };
