@@ -41,6 +41,7 @@ struct RowStats {
     uint64_t min_green = ~0ull;  // smallest sum(x) over non-empty rows
     uint64_t walk_steps = 0;     // sum over non-empty rows of min(M / sum(x), 65535)
     uint64_t index_keys = 0;     // sum over non-empty rows of the index keys read per hash
+    bool keys_known = false;     // index_keys was estimated
 };
 
 // A component index owned by a context or a serving loop, rebuilt when its key changes.
@@ -132,8 +133,9 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const w
                   BatchedPlan *plan, bool use_tuned = true);
 TuneKey tune_key(const wmh_ctx *ctx, uint32_t k, const RowStats &stats);
 // Validation pass on the device: checks the rows (when check) and fills *stats; waits.
+// want_keys: also estimate index_keys (only the path choice in auto mode reads it)
 wmh_status gather_stats(wmh_ctx *ctx, const Rows &rows, uint32_t k, hipStream_t s, bool check,
-                        RowStats *stats);
+                        bool want_keys, RowStats *stats);
 // Host-side check of CSR rows against the context's bounds (same rules as the device check);
 // fills *stats (may be NULL) like the device pass.
 wmh_status check_rows_host(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,

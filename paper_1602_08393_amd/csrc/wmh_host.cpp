@@ -166,6 +166,7 @@ wmh_status check_rows_host(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t
 {
     RowStats st;
     st.known = true;
+    st.keys_known = true;
     for (uint64_t r = 0; r < n_rows; ++r) {
         const uint64_t lo = row_ptr[r], hi = row_ptr[r + 1];
         if (lo > hi || hi > nnz)
@@ -203,14 +204,14 @@ wmh_status check_rows_host(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t
 }
 
 wmh_status gather_stats(wmh_ctx *ctx, const Rows &rows, uint32_t k, hipStream_t s, bool check,
-                        RowStats *stats)
+                        bool want_keys, RowStats *stats)
 {
     // first_error and min_green start at ~0, the counters at 0
     uint32_t *words = reinterpret_cast<uint32_t *>(ctx->d_check);
     hipError_t e = launch_fill_u32(words, 0xFFFFFFFFu, 4, s);
     if (e == hipSuccess) e = launch_fill_u32(words + 4, 0u, 6, s);
     if (e == hipSuccess)
-        e = launch_validate(rows, ctx->d_bound, ctx->dims, ctx->total, k, ctx->d_check, s);
+        e = launch_validate(rows, ctx->d_bound, ctx->dims, ctx->total, k, want_keys, ctx->d_check, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(ctx->h_check, ctx->d_check, sizeof(CheckWords), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -227,6 +228,7 @@ wmh_status gather_stats(wmh_ctx *ctx, const Rows &rows, uint32_t k, hipStream_t 
     stats->min_green = v.min_green;
     stats->walk_steps = v.walk_steps;
     stats->index_keys = v.index_keys;
+    stats->keys_known = want_keys;
     return WMH_OK;
 }
 
@@ -312,7 +314,7 @@ Path choose_path(const wmh_ctx *ctx, int mode, bool batched_ok, bool index_ready
     if (mode == WMH_MODE_BATCHED) return Path::kBatched;
     if (mode == WMH_MODE_INDEXED) return Path::kIndexed;
     const Path walk_path = batched_ok ? Path::kBatched : Path::kPlain;
-    if (!stats.known || !index_fits(k)) return walk_path;
+    if (!stats.known || !stats.keys_known || !index_fits(k)) return walk_path;
     const bool narrow = ctx->max_bound <= 0xFFFFu;
     const bool dense = (size_t)4 * ctx->dims * (narrow ? 2 : 4) <= 64 * 1024;
     const double step = batched_ok ? 1.0 : (dense ? kCostPlainDenseStep : kCostPlainSparseStep);
@@ -577,7 +579,8 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
     const bool profile = o.profile != 0;
     ctx->profiled = false;
     if (o.validate || o.mode == WMH_MODE_AUTO) {
-        const wmh_status st = gather_stats(ctx, rows, k, s, o.validate != 0, &stats);
+        const bool want_keys = o.mode == WMH_MODE_AUTO && index_fits(k);
+        const wmh_status st = gather_stats(ctx, rows, k, s, o.validate != 0, want_keys, &stats);
         if (st != WMH_OK) return st;
     }
 

@@ -69,9 +69,10 @@ struct BatchedPlan {
     }
 };
 
-// Checks the rows and gathers the statistics of CheckWords (M = total, for the cost estimates).
+// Checks the rows and gathers the statistics of CheckWords (M = total, for the cost estimates);
+// index_keys only with want_keys (it is left at 0 otherwise).
 hipError_t launch_validate(const Rows &rows, const uint32_t *bound, uint32_t dims, uint64_t total,
-                           uint32_t k, CheckWords *words, hipStream_t stream);
+                           uint32_t k, bool want_keys, CheckWords *words, hipStream_t stream);
 
 hipError_t launch_plain(const Bounds &b, const Rows &rows, uint64_t row_begin,
                         uint64_t row_end, uint32_t k, uint64_t seed, uint16_t *sig, bool narrow,

@@ -11,6 +11,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cmath>
 
 #include "wmh_entries.h"
 #include "wmh_internal.h"
@@ -34,11 +35,34 @@ __device__ __forceinline__ uint32_t count_below(uint64_t mask)
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// v of the lane the DPP control selects, or 0 where that lane lies outside the written rows
+template <int kCtrl, int kRows>
+__device__ __forceinline__ uint32_t dpp_or_zero(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, kRows, 0xF, false);
+}
+
+template <int kCtrl, int kRows>
+__device__ __forceinline__ uint64_t dpp_add64(uint64_t v)
+{
+    const uint64_t t = ((uint64_t)dpp_or_zero<kCtrl, kRows>((uint32_t)(v >> 32)) << 32) |
+                       dpp_or_zero<kCtrl, kRows>((uint32_t)v);
+    return v + t;
+}
+
+// Sum over the wavefront, in a scalar register: prefix sums inside 16-lane DPP rows (row
+// shifts), then the row totals carried forward by row broadcasts; lane 63 ends with the sum.
 __device__ __forceinline__ uint64_t wave_sum(uint64_t v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
+    v = dpp_add64<0x111, 0xF>(v);  // row_shr:1
+    v = dpp_add64<0x112, 0xF>(v);  // row_shr:2
+    v = dpp_add64<0x114, 0xF>(v);  // row_shr:4
+    v = dpp_add64<0x118, 0xF>(v);  // row_shr:8
+    v = dpp_add64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_add64<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 __device__ __forceinline__ uint64_t wave_min(uint64_t v)
@@ -52,11 +76,13 @@ __device__ __forceinline__ uint64_t wave_min(uint64_t v)
 }
 
 // ---------------------------------------------------------------------------------------------
-// Validation: one wavefront per row, grid-stride over rows.
+// Validation: one wavefront per row, grid-stride over rows.  kKeys: also estimate the index
+// keys (needed only when the component index is a candidate path).
 // ---------------------------------------------------------------------------------------------
+template <bool kKeys>
 __global__ __launch_bounds__(256) void validate_kernel(Rows rows, const uint32_t *__restrict__ bound,
-                                                       uint32_t dims, uint64_t total, uint32_t k,
-                                                       CheckWords *words)
+                                                       uint32_t dims, uint64_t total,
+                                                       double log_eps, CheckWords *words)
 {
     // per-workgroup partials, so each word gets at most one global atomic per workgroup
     __shared__ unsigned long long part_err[256 / kWave], part_green[256 / kWave],
@@ -66,6 +92,9 @@ __global__ __launch_bounds__(256) void validate_kernel(Rows rows, const uint32_t
     const uint64_t stride = (uint64_t)gridDim.x * waves;
     uint64_t w_err = ~0ull, w_green = ~0ull, w_empty = 0;  // this wave's partials (uniform)
     uint64_t w_walk = 0, w_keys = 0;  // cost statistics: expected walk steps, green index keys
+    // M / sum(x) in double is exact after flooring while M < 2^53 (the rounding error of the
+    // quotient stays below the distance 1 / sum(x) to the next integer)
+    const bool exact_double = total < (1ull << 53);
     for (uint64_t r = first; r < rows.n_rows; r += stride) {
         const uint64_t lo = rows.row_ptr[r];
         const uint64_t hi = rows.row_ptr[r + 1];
@@ -109,22 +138,28 @@ __global__ __launch_bounds__(256) void validate_kernel(Rows rows, const uint32_t
                 else if (v[i] > m[i]) code = kCheckBound;
                 if (code && bad == ~0ull) bad = ((e - lo) << 4) | code;
                 sum += v[i];
-                sum_m += v[i] ? m[i] : 0u;
+                if (kKeys) sum_m += v[i] ? m[i] : 0u;
             }
         }
-        bad = wave_min(bad);
+        if (__builtin_amdgcn_ballot_w64(bad != ~0ull) != 0) {  // some entry of the row is bad
+            w_err = min(w_err, (unsigned long long)((r << 4) | (wave_min(bad) & 15u)));
+            continue;
+        }
         sum = wave_sum(sum);
-        sum_m = wave_sum(sum_m);
-        if (bad != ~0ull) w_err = min(w_err, (unsigned long long)((r << 4) | (bad & 15u)));
-        else if (sum == 0) ++w_empty;
-        else {
-            w_green = min(w_green, (unsigned long long)sum);
-            // mean capped step count ~ min(1/s, cap) (Theorem 2); index keys per hash: the
-            // cheaper of offset order (65534 * s) and step order up to the row's bound T
-            // (T * sum(m) / M), as the index row kernel chooses
-            w_walk += min(total / sum, (uint64_t)kCap);
+        if (sum == 0) {
+            ++w_empty;
+            continue;
+        }
+        w_green = min(w_green, (unsigned long long)sum);
+        // mean capped step count ~ min(1/s, cap) (Theorem 2)
+        const uint64_t q = exact_double ? (uint64_t)floor((double)total / (double)sum) : total / sum;
+        w_walk += min(q, (uint64_t)kCap);
+        if (kKeys) {
+            // index keys per hash: the cheaper of offset order (65534 * s) and step order up
+            // to the row's bound T (T * sum(m) / M), as the index row kernel chooses
+            sum_m = wave_sum(sum_m);
             const double s = (double)sum / (double)total;
-            const double T = s >= 1.0 ? 1.0 : ceil(log(1e-4 / (double)k) / log1p(-s));
+            const double T = s >= 1.0 ? 1.0 : ceil(log_eps / log1p(-s));
             const double by_offset = 65534.0 * s;
             const double by_step = T < 65534.0 ? T * ((double)sum_m / (double)total) : by_offset;
             w_keys += (uint64_t)ceil(min(by_offset, by_step));
@@ -514,12 +549,16 @@ __global__ __launch_bounds__(256) void estimate_kernel(const uint16_t *__restric
 // ---------------------------------------------------------------------------------------------
 
 hipError_t launch_validate(const Rows &rows, const uint32_t *bound, uint32_t dims, uint64_t total,
-                           uint32_t k, CheckWords *words, hipStream_t stream)
+                           uint32_t k, bool want_keys, CheckWords *words, hipStream_t stream)
 {
     if (rows.n_rows == 0) return hipSuccess;
     const uint64_t waves_needed = rows.n_rows;
     const uint32_t grid = (uint32_t)std::min<uint64_t>((waves_needed + 3) / 4, 2048);
-    validate_kernel<<<grid, 256, 0, stream>>>(rows, bound, dims, total, k, words);
+    const double log_eps = std::log(1e-4 / (double)k);  // the index's failure bound per row
+    if (want_keys)
+        validate_kernel<true><<<grid, 256, 0, stream>>>(rows, bound, dims, total, log_eps, words);
+    else
+        validate_kernel<false><<<grid, 256, 0, stream>>>(rows, bound, dims, total, log_eps, words);
     return hipGetLastError();
 }
 

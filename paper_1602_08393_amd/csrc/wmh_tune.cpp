@@ -58,7 +58,7 @@ wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
     hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : ctx->own_stream;
     const Rows rows{row_ptr, col, val, n_rows, nnz};
     RowStats stats;
-    wmh_status st = gather_stats(ctx, rows, k, s, true, &stats);
+    wmh_status st = gather_stats(ctx, rows, k, s, true, false, &stats);
     if (st != WMH_OK) return st;
 
     wmh_opts base;
