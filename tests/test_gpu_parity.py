@@ -161,6 +161,21 @@ def test_random_cases_all_plans(ctx, name):
         assert_same(got, want, f"{name} batched {plan}")
 
 
+def test_two_plane_rows_with_wide_entries(ctx):
+    """Four rows of 16-bit values with D * 4 > 65536: the rows sit in two LDS planes of row
+    pairs (the second plane starts past byte 65536) and the stream entries are wide (8 bytes),
+    for both batched walks and with every draw made in-lane."""
+    ds = synth.random_case(seed=21, n_rows=23, D=16500, density=0.004, max_val=30000,
+                           bound_slack=3000, empty_rows=2, k=37)
+    assert int(ds.m.max()) <= 0xFFFF and ds.D * 4 > 65536
+    k = 37
+    want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, k, seed=9)
+    for opts in (dict(rows_per_block=4), dict(rows_per_block=4, stream_depth=None),
+                 dict(rows_per_block=4, hashes_per_tile=5, waves_per_block=4),
+                 dict(walk="rows"), dict(rows_per_block=2, steps_per_lane=4)):
+        assert_same(gpu_sig(ctx, ds, k, 9, mode="batched", **opts), want, f"D=16500 {opts}")
+
+
 def test_full_rows_hash_to_one_and_saturation(ctx):
     """x = m gives h = 1 everywhere; s = 1/2^40 saturates every hash at 65535."""
     m = np.full(256, 0xFFFFFFFF, dtype=np.uint32)
