@@ -27,6 +27,9 @@
  *     returns, except the bounds, which wmh_set_bounds copies into the context.
  *   - `stream` is a hipStream_t of the context's device, or NULL for the context's own stream.
  *   - A context is not thread-safe: use one context per host thread, or serialize calls.
+ *     Its device scratch (tile counter, shared position stream, captured graph) serves every
+ *     call: asynchronous calls (opts->sync = 0) on different streams must be ordered by the
+ *     caller; a call that reuses a stream built by an earlier call waits for that build.
  *   - On any error the output buffers are left untouched (validation precedes every write),
  *     and wmh_last_error() describes the failure (first offending row / column where known).
  */
@@ -91,9 +94,13 @@ typedef struct {
     /* batched-mode tile plan overrides; 0 = planner / autotuner choice */
     uint32_t rows_per_block;   /* R: rows whose dense rows share one walk (1, 2, 4, 8, 16) */
     uint32_t hashes_per_tile;  /* J: hash ids per tile */
-    uint32_t stream_depth;     /* T0: steps of the shared position stream built per call
-                                  (rounded up to a whole number of windows, at most 65536);
-                                  steps beyond it are drawn in-lane.  UINT32_MAX: one window */
+    uint32_t stream_depth;     /* T0: steps of the shared position stream (the draws and
+                                  their components for steps t <= T0 of every hash id, built
+                                  once per (seed, k, T0, bounds) and kept in the context);
+                                  rounded up to whole cycles of three walk windows and kept
+                                  below 65535; steps beyond it are drawn in-lane.  UINT32_MAX:
+                                  no stream (every step drawn in-lane; the independent-rows
+                                  walk keeps one cycle) */
     uint32_t waves_per_block;  /* wavefronts per workgroup (1..16) */
     int32_t profile;           /* 1: time the walk kernels with HIP events on the launch stream
                                   (read back with wmh_last_kernel_ms) */
@@ -203,8 +210,9 @@ wmh_status wmh_bounds_tables(const uint32_t *m, uint32_t D, uint64_t *prefix, ui
  * wmh_last_kernel_ms -- device time of the last wmh_hash call made with opts->profile = 1,
  * from HIP events recorded on the launch stream.  Direct launches: *walk_ms spans the
  * hash-walk kernels (the batched kernel, or every plain launch), *stream_ms the shared-stream
- * build (0 if none).  hipGraph replays (batched with use_graph): *walk_ms spans the whole
- * graph (counter reset, stream build and walk) and *stream_ms is 0.  Indexed path: *walk_ms
+ * build when that call built it (0 when it reused the stream of an earlier call, or had none).
+ * hipGraph replays (batched with use_graph): *walk_ms spans the whole graph (counter reset
+ * and walk) and *stream_ms is 0.  Indexed path: *walk_ms
  * spans the row kernel, *stream_ms the index build when that call built it (else 0).
  * Requires that call to have completed (opts->sync, or a later synchronization).
  * Errors: WMH_E_ARG (no profiled call yet), WMH_E_DEVICE.

@@ -16,6 +16,19 @@ constexpr uint32_t kMaxDims = 1u << 26;
 constexpr uint32_t kMaxK = 1u << 24;
 constexpr uint64_t kStreamBudgetBytes = 1ull << 30;  // shared position stream, at most 1 GiB
 
+// What the content of the shared position stream depends on.
+struct StreamKey {
+    uint64_t seed = 0;
+    uint32_t k = 0, depth = 0, scale = 0;
+    bool packed = false;
+    uint64_t bounds_epoch = 0;
+    bool operator==(const StreamKey &o) const
+    {
+        return seed == o.seed && k == o.k && depth == o.depth && scale == o.scale &&
+               packed == o.packed && bounds_epoch == o.bounds_epoch;
+    }
+};
+
 struct GraphKey {
     const void *row_ptr = nullptr, *col = nullptr, *val = nullptr;
     void *sig = nullptr;
@@ -107,6 +120,11 @@ struct wmh_ctx {
     unsigned long long *h_codec = nullptr;  // pinned copy
     void *d_stream = nullptr;
     size_t stream_bytes = 0;
+    // the shared position stream is kept between calls: it depends only on (seed, k, depth,
+    // entry layout, bounds); stream_ready is recorded after its build
+    bool stream_valid = false;
+    wmh::StreamKey stream_key{};
+    hipEvent_t stream_ready = nullptr;
     // graph of the batched launch
     hipGraphExec_t graph_exec = nullptr;
     wmh::GraphKey graph_key;

@@ -365,6 +365,7 @@ wmh_status ensure_stream_capacity(wmh_ctx *ctx, size_t bytes)
     if (ctx->d_stream) hipFree(ctx->d_stream);
     ctx->d_stream = nullptr;
     ctx->stream_bytes = 0;
+    ctx->stream_valid = false;
     drop_graph(ctx);
     WMH_HIP(ctx, hipMalloc(&ctx->d_stream, bytes));
     ctx->stream_bytes = bytes;
@@ -425,7 +426,8 @@ wmh_status wmh_create(int device, wmh_ctx **out)
         hipMalloc(&ctx->d_codec, 2 * sizeof(unsigned long long)) != hipSuccess ||
         hipHostMalloc(&ctx->h_codec, 2 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
         hipEventCreate(&ctx->ev[0]) != hipSuccess || hipEventCreate(&ctx->ev[1]) != hipSuccess ||
-        hipEventCreate(&ctx->ev[2]) != hipSuccess) {
+        hipEventCreate(&ctx->ev[2]) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->stream_ready, hipEventDisableTiming) != hipSuccess) {
         wmh_destroy(ctx);
         return WMH_E_DEVICE;
     }
@@ -449,6 +451,7 @@ void wmh_destroy(wmh_ctx *ctx)
     if (ctx->h_codec) hipHostFree(ctx->h_codec);
     for (hipEvent_t &e : ctx->ev)
         if (e) hipEventDestroy(e);
+    if (ctx->stream_ready) hipEventDestroy(ctx->stream_ready);
     if (ctx->own_stream) hipStreamDestroy(ctx->own_stream);
     if (ctx->capture_stream) hipStreamDestroy(ctx->capture_stream);
     delete ctx;
@@ -643,16 +646,30 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         key.independent_rows = plan.independent_rows;
         key.bounds_epoch = ctx->bounds_epoch;
 
-        // events between kernels only on direct launches; a graph is timed as a whole
+        // The shared position stream (cached position stream): built once per (seed, k,
+        // depth, entry layout, bounds) and kept for later calls, which wait for its build.
+        bool stream_built = false;
+        if (plan.stream_depth) {
+            const StreamKey skey{seed, k, plan.stream_depth, plan.scale(), plan.packed,
+                                 ctx->bounds_epoch};
+            if (!(ctx->stream_valid && ctx->stream_key == skey)) {
+                ctx->stream_valid = false;
+                if (profile && !o.use_graph) WMH_HIP(ctx, hipEventRecord(ctx->ev[0], s));
+                WMH_HIP(ctx, launch_stream_build(b, seed, k, plan.stream_depth, plan.packed,
+                                                 plan.scale(), ctx->d_stream, s));
+                WMH_HIP(ctx, hipEventRecord(ctx->stream_ready, s));
+                ctx->stream_key = skey;
+                ctx->stream_valid = true;
+                stream_built = true;
+            } else {
+                WMH_HIP(ctx, hipStreamWaitEvent(s, ctx->stream_ready, 0));
+            }
+        }
+
+        // events around the walk only on direct launches; a graph is timed as a whole
         auto enqueue = [&](hipStream_t q, bool events) -> hipError_t {
             hipError_t e = launch_fill_u32(ctx->d_tile_counter, 0u, 1, q);
             if (e != hipSuccess) return e;
-            if (events && (e = hipEventRecord(ctx->ev[0], q)) != hipSuccess) return e;
-            if (plan.stream_depth) {
-                e = launch_stream_build(b, seed, k, plan.stream_depth, plan.packed,
-                                        plan.scale(), ctx->d_stream, q);
-                if (e != hipSuccess) return e;
-            }
             if (events && (e = hipEventRecord(ctx->ev[1], q)) != hipSuccess) return e;
             e = launch_batched(b, rows, k, seed, sig, plan, ctx->d_stream, ctx->d_tile_counter,
                                grid, q);
@@ -688,7 +705,7 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         } else {
             hipError_t e = enqueue(s, profile);
             if (e != hipSuccess) return device_fail(ctx, e, "batched launch");
-            ctx->profiled_stream = profile && plan.stream_depth != 0;
+            ctx->profiled_stream = profile && stream_built;
         }
         ctx->profiled = profile;
     }

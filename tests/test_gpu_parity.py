@@ -161,6 +161,44 @@ def test_random_cases_all_plans(ctx, name):
         assert_same(got, want, f"{name} batched {plan}")
 
 
+def test_stream_kept_between_calls(ctx):
+    """The shared position stream is built once per (seed, k, depth, bounds) and reused: calls
+    that alternate seeds, k, depth and bounds each give the oracle's values, graph replays and
+    direct launches alike; a call on a second stream reuses the stream the first one built."""
+    ds = synth.random_case(seed=31, n_rows=41, D=700, density=0.05, max_val=9000,
+                           bound_slack=500, empty_rows=1, k=50)
+    rows = None
+    for seed, k, opts in ((3, 50, {}), (4, 50, {}), (3, 50, {}), (3, 20, {}),
+                          (3, 50, dict(stream_depth=1000)), (3, 50, dict(use_graph=False)),
+                          (4, 50, dict(use_graph=False, stream_depth=1000)), (3, 50, {})):
+        ctx.set_bounds(ds.m)
+        rows = wmh.upload_dataset(ds, DEV)
+        got = wmh.sig_to_numpy(ctx.hash(rows, k, seed=seed, mode="batched", rows_per_block=4,
+                                        **opts))
+        want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, k, seed=seed)
+        assert_same(got, want, f"seed {seed} k {k} {opts}")
+    # new bounds with the same seed and k: the stream is rebuilt
+    m2 = ds.m.copy()
+    m2[::3] += 7
+    ctx.set_bounds(m2)
+    got = wmh.sig_to_numpy(ctx.hash(rows, 50, seed=3, mode="batched", rows_per_block=4))
+    assert_same(got, oracle.hash_csr(m2, ds.row_ptr, ds.col, ds.val, 50, seed=3), "new bounds")
+    # asynchronous calls on two streams (ordered, as calls sharing a context must be): the
+    # second reuses the stream the first one built
+    a, b = torch.cuda.Stream(), torch.cuda.Stream()
+    out_a = torch.empty((ds.n_rows, 50), dtype=torch.int16, device=DEV)
+    out_b = torch.empty_like(out_a)
+    ctx.hash_into(rows, 50, 8, out_a, stream=a.cuda_stream,
+                  opts=ctx.make_opts(mode="batched", rows_per_block=4, sync=False))
+    b.wait_stream(a)
+    ctx.hash_into(rows, 50, 8, out_b, stream=b.cuda_stream,
+                  opts=ctx.make_opts(mode="batched", rows_per_block=4, sync=False))
+    torch.cuda.synchronize()
+    want = oracle.hash_csr(m2, ds.row_ptr, ds.col, ds.val, 50, seed=8)
+    assert_same(wmh.sig_to_numpy(out_a), want, "stream a")
+    assert_same(wmh.sig_to_numpy(out_b), want, "stream b")
+
+
 def test_two_plane_rows_with_wide_entries(ctx):
     """Four rows of 16-bit values with D * 4 > 65536: the rows sit in two LDS planes of row
     pairs (the second plane starts past byte 65536) and the stream entries are wide (8 bytes),
