@@ -144,13 +144,6 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
         // scalar branch: no lane-divergent region sits on the unit loop's path.
         const uint32_t live = __builtin_amdgcn_readfirstlane(nonempty);
         const bool my_row_live = ((live >> my_row) & 1u) != 0;
-        // bit r * L set for every live row r: the walk ends when each of them has a green lane
-        // top bit of every live row's L-lane segment: the walk ends when each of those
-        // segments of the "has a green step" ballot is nonzero
-        uint64_t need = 0;
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            if ((live >> r) & 1u) need |= 1ull << (r * L + L - 1);
         const uint32_t j0 = ht * hashes_per_tile;
         const uint32_t j1 = min(k, j0 + hashes_per_tile);
 
