@@ -214,6 +214,59 @@ def test_two_plane_rows_with_wide_entries(ctx):
         assert_same(gpu_sig(ctx, ds, k, 9, mode="batched", **opts), want, f"D=16500 {opts}")
 
 
+def _random_plan(rng):
+    """One random plan among every option the batched path takes."""
+    walk = "rows" if rng.random() < 0.2 else "shared"
+    plan = dict(mode="batched", walk=walk)
+    if walk == "shared":
+        R = int(rng.choice([1, 2, 4, 8, 16]))
+        plan["rows_per_block"] = R
+        if R < 4 and rng.random() < 0.5:
+            plan["steps_per_lane"] = 4
+    if rng.random() < 0.5:
+        plan["hashes_per_tile"] = int(rng.integers(1, 300))
+    if rng.random() < 0.5:
+        plan["waves_per_block"] = int(rng.choice([1, 2, 4, 8, 16]))
+    d = rng.random()
+    if d < 0.2:
+        plan["stream_depth"] = None
+    elif d < 0.6:
+        plan["stream_depth"] = int(rng.integers(1, 3000))
+    if rng.random() < 0.3:
+        plan["use_graph"] = False
+    return plan
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_random_datasets_random_plans(ctx, case):
+    """Seeded random datasets (row count, dimension, density, value width, slack, empty rows,
+    zero-bound dimensions, k) against the oracle, each under the plain walk, auto mode and
+    three random batched plans."""
+    rng = np.random.Generator(np.random.PCG64(1000 + case))
+    n_rows = int(rng.integers(1, 160))
+    D = int(rng.integers(1, 3000))
+    max_val = int(rng.choice([3, 255, 65535, 2 ** 20, 2 ** 32 - 1]))
+    ds = synth.random_case(seed=2000 + case, n_rows=n_rows, D=D,
+                           density=float(rng.uniform(0.002, 0.5)), max_val=max_val,
+                           bound_slack=int(rng.choice([0, 10, 5000,
+                                                       min(2 ** 32 - 1 - max_val, 300 * max_val)])),
+                           empty_rows=int(rng.integers(0, 3)),
+                           zero_bound_dims=int(rng.integers(0, 5)) if D > 5 else 0)
+    k = int(rng.integers(1, 300))
+    seed = int(rng.integers(0, 2 ** 63))
+    want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, k, seed=seed)
+    assert_same(gpu_sig(ctx, ds, k, seed, mode="plain"), want, f"case {case} plain")
+    assert_same(gpu_sig(ctx, ds, k, seed, mode="auto"), want, f"case {case} auto")
+    for _ in range(3):
+        plan = _random_plan(rng)
+        try:
+            got = gpu_sig(ctx, ds, k, seed, **plan)
+        except wmh.WMHError as e:  # a plan that does not fit this dimension in LDS
+            assert e.name == "WMH_E_ARG", (case, plan, e)
+            continue
+        assert_same(got, want, f"case {case} {plan}")
+
+
 def test_full_rows_hash_to_one_and_saturation(ctx):
     """x = m gives h = 1 everywhere; s = 1/2^40 saturates every hash at 65535."""
     m = np.full(256, 0xFFFFFFFF, dtype=np.uint32)
