@@ -267,6 +267,30 @@ def test_random_datasets_random_plans(ctx, case):
         assert_same(got, want, f"case {case} {plan}")
 
 
+def test_packed_entries_at_the_offset_limit(ctx):
+    """D = 16384 with four rows of 16-bit values: packed entries whose LDS offset c * 4 reaches
+    65532, the largest that fits their 16-bit field."""
+    ds = synth.random_case(seed=41, n_rows=10, D=16384, density=0.01, max_val=60000,
+                           bound_slack=5, empty_rows=1, k=45)
+    assert int(ds.m.max()) <= 0xFFFF
+    want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, 45, seed=12)
+    for opts in (dict(rows_per_block=4), dict(rows_per_block=4, use_graph=False),
+                 dict(walk="rows")):
+        assert_same(gpu_sig(ctx, ds, 45, 12, mode="batched", **opts), want, f"D=16384 {opts}")
+
+
+def test_many_hash_ids(ctx):
+    """k above 65536: hash ids past 16 bits in the draws, the stream index and many hash
+    tiles per row block."""
+    ds = synth.random_case(seed=43, n_rows=3, D=40, density=0.6, max_val=900, bound_slack=0,
+                           k=70001)
+    k = 70001
+    want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, k, seed=13)
+    for opts in (dict(mode="batched"), dict(mode="batched", hashes_per_tile=4096),
+                 dict(mode="plain")):
+        assert_same(gpu_sig(ctx, ds, k, 13, **opts), want, f"k={k} {opts}")
+
+
 def test_full_rows_hash_to_one_and_saturation(ctx):
     """x = m gives h = 1 everywhere; s = 1/2^40 saturates every hash at 65535."""
     m = np.full(256, 0xFFFFFFFF, dtype=np.uint32)
