@@ -53,21 +53,25 @@ def parse():
     ap.add_argument("--stream-depth", type=int, default=0)
     ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--steps-per-lane", type=int, default=0)
-    ap.add_argument("--walk", type=int, default=0, choices=[0, 1, 2],
-                    help="batched walk: 0 planner/autotuner, 1 shared windows, 2 independent rows")
+    ap.add_argument("--walk", type=int, default=0, choices=[0, 1, 2, 3],
+                    help="batched walk: 0 planner/autotuner, 1 shared windows, 2 independent "
+                         "rows, 3 ballot walk (one row per block)")
     ap.add_argument("--only", choices=["batched", "plain", "both"], default="both")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run device-to-device copies of BYTES (scales HBM counters)")
     ap.add_argument("--serve", action="store_true",
                     help="only run the serving workload (corpus of config 5, k=256)")
+    ap.add_argument("--heavy-tail", action="store_true",
+                    help="only run the heavy-tail workload (with --only batched: no plain "
+                         "form, no collision counts)")
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="open-loop requests per load level")
-    ap.add_argument("--serve-corpus-rows", type=int, default=20_000)
+    ap.add_argument("--serve-corpus-rows", type=int, default=100_000)
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline workload")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (planner default plan)")
-    ap.add_argument("--text-rows", type=int, default=100_000,
+    ap.add_argument("--text-rows", type=int, default=1_000_000,
                     help="rows of the text-like workload generated for its line")
     ap.add_argument("--serve-max-rows", type=int, default=4096)
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -140,6 +144,13 @@ def copy_calibration(nbytes: int):
     print(json.dumps({"copy_bytes": nbytes, "copies": 3}), flush=True)
 
 
+def plan_args(args) -> dict:
+    """Tile-plan options given on the command line (0: planner or autotuner)."""
+    return dict(rows_per_block=args.rows_per_block, hashes_per_tile=args.hashes_per_tile,
+                stream_depth=args.stream_depth, waves_per_block=args.waves_per_block,
+                walk=args.walk, steps_per_lane=args.steps_per_lane)
+
+
 def timed_steps(ctx, rows, k, sig, opts, steps, warmup, torch):
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
@@ -201,27 +212,32 @@ def heavy_tail_bench(args, torch, synth, wmh) -> dict:
                        "1% of dims with one outlier row at 100*2^24, bounds = dataset max, "
                        "k=500, seed 0",
            "N": ds.n_rows, "D": ds.D, "k": k, "nnz": ds.nnz}
-    if not args.no_tune:
+    if not args.no_tune and not any(plan_args(args).values()):
         out["autotune"] = ctx.tune(rows, k, 0, reps=1)
     sig_b = torch.empty((ds.n_rows, k), dtype=torch.int16, device="cuda:0")
     sig_p = torch.empty_like(sig_b)
-    el_b, walk_b, _ = timed_steps(ctx, rows, k, sig_b, ctx.make_opts(mode="batched", profile=True),
+    el_b, walk_b, _ = timed_steps(ctx, rows, k, sig_b,
+                                  ctx.make_opts(mode="batched", profile=True, **plan_args(args)),
                                   3, 1, torch)
     out["batched_plan"] = ctx.last_plan()
-    el_p, walk_p, _ = timed_steps(ctx, rows, k, sig_p, ctx.make_opts(mode="plain", profile=True),
-                                  2, 1, torch)
     hashes = ds.n_rows * k
     tests = int(wmh.sig_to_numpy(sig_b).astype(np.int64).sum())
     out.update({"batched_hashes_per_s": hashes * 3 / el_b,
                 "batched_ms_per_step": el_b / 3 * 1e3,
                 "batched_walk_ms": float(np.mean(walk_b)),
-                "plain_hashes_per_s": hashes * 2 / el_p,
-                "plain_ms_per_step": el_p / 2 * 1e3,
-                "batched_over_plain": (hashes * 3 / el_b) / (hashes * 2 / el_p),
-                "batched_equals_plain": bool(torch.equal(sig_b, sig_p)),
                 "mean_steps_per_hash": tests / hashes,
                 "walk_frac_of_alu_peak": OPS_PER_TEST * tests / (np.mean(walk_b) / 1e3) / 1e12
                 / PEAK_INT_TOPS})
+    if args.only == "batched":
+        log(f"heavy-tail: batched {out['batched_ms_per_step']:.2f} ms/step")
+        ctx.close()
+        return out
+    el_p, walk_p, _ = timed_steps(ctx, rows, k, sig_p, ctx.make_opts(mode="plain", profile=True),
+                                  2, 1, torch)
+    out.update({"plain_hashes_per_s": hashes * 2 / el_p,
+                "plain_ms_per_step": el_p / 2 * 1e3,
+                "batched_over_plain": (hashes * 3 / el_b) / (hashes * 2 / el_p),
+                "batched_equals_plain": bool(torch.equal(sig_b, sig_p))})
     log(f"heavy-tail: batched {out['batched_ms_per_step']:.2f} ms/step, plain "
         f"{out['plain_ms_per_step']:.2f} ms/step, equal {out['batched_equals_plain']}")
     del sig_p
@@ -299,20 +315,26 @@ def text_like_bench(args, torch, synth, wmh) -> dict:
     el, walk, _ = timed_steps(ctx, rows, k, sig, opts, 3, 0, torch)
     sig_np = wmh.sig_to_numpy(sig)
     head = ds.head(48)
-    walk_sig = wmh.sig_to_numpy(ctx.hash(wmh.upload_dataset(head, "cuda:0"), k, seed=0,
-                                         mode="plain"))
+    head_rows = wmh.upload_dataset(head, "cuda:0")
+    walk_sig = torch.empty((head.n_rows, k), dtype=torch.int16, device="cuda:0")
+    ctx.hash_into(head_rows, k, 0, walk_sig, stream=stream.cuda_stream,
+                  opts=ctx.make_opts(mode="plain", profile=True))
+    head_plain_ms = ctx.last_kernel_ms()[0]
+    walk_sig = wmh.sig_to_numpy(walk_sig)
     hashes = ds.n_rows * k
     capped = float((sig_np == 65535).mean())
-    out = {"workload": f"text-like: first {ds.n_rows} rows of the N=1e6 generator (bounds = "
-                       "max over these rows), D=65536, nnz = clamp(Zipf(1.2), 10, 5000) draws, "
-                       "tf weights 1+ln(Zipf(1.5)) Q16.16, k=1000, seed 0",
+    out = {"workload": f"text-like: N={ds.n_rows} rows (bounds = max over these rows), D=65536, "
+                       "nnz = clamp(Zipf(1.2), 10, 5000) draws, tf weights 1+ln(Zipf(1.5)) "
+                       "Q16.16, k=1000, seed 0",
            "N": ds.n_rows, "D": ds.D, "k": k, "nnz": ds.nnz, "mode": mode,
            "hashes_per_s": hashes * 3 / el, "ms_per_step": el / 3 * 1e3,
            "rows_kernel_ms": float(np.mean(walk)), "index_build_ms": build_ms,
            "first_call_rows_kernel_ms": first_rows_ms,
-           "walk_steps_equivalent": int(sig_np.astype(np.int64).sum()),
+           "walk_steps_equivalent": int(sig_np.sum(dtype=np.int64)),
            "capped_fraction": capped,
-           "head_equals_plain_walk": bool(np.array_equal(sig_np[:48], walk_sig))}
+           "head_equals_plain_walk": bool(np.array_equal(sig_np[:48], walk_sig)),
+           "head_plain_walk_ms": head_plain_ms,
+           "head_plain_walk_rows": head.n_rows}
     log(f"text-like: {mode} {out['ms_per_step']:.2f} ms/step, index build {build_ms:.2f} ms, "
         f"head equals walk {out['head_equals_plain_walk']}")
     ctx.close()
@@ -375,6 +397,10 @@ def main():
         return
     import torch
     from paper_1602_08393_amd import synth, wmh
+    if args.heavy_tail:
+        torch.cuda.set_device(0)
+        print(json.dumps({"heavy_tail": heavy_tail_bench(args, torch, synth, wmh)}), flush=True)
+        return
 
     if not os.path.exists(wmh.LIB_PATH):
         import __graft_entry__
@@ -394,9 +420,7 @@ def main():
     M = int(ds.m.astype(np.uint64).sum())
     hashes = ds.n_rows * k
 
-    plan = dict(rows_per_block=args.rows_per_block, hashes_per_tile=args.hashes_per_tile,
-                stream_depth=args.stream_depth, waves_per_block=args.waves_per_block,
-                walk=args.walk, steps_per_lane=args.steps_per_lane)
+    plan = plan_args(args)
     result = {}
     tune = None
     if args.only in ("batched", "both") and not args.no_tune and not any(plan.values()):

@@ -107,7 +107,10 @@ typedef struct {
     int32_t walk;              /* batched mode: 0 = planner / autotuner choice; 1 = shared windows
                                   (every window is tested for all R rows of a block until the
                                   block's last row is green); 2 = independent rows (each row of a
-                                  block walks its own hash ids; needs R = 4) */
+                                  block walks its own hash ids; needs R = 4); 3 = ballot walk
+                                  (one row per block, a wavefront per hash id, lane l testing
+                                  step l + 1 of each 64-step window; the first green step is the
+                                  lowest set bit of the window's ballot; needs R = 1, K = 1) */
     uint32_t steps_per_lane;   /* batched mode, K: consecutive steps a lane tests per window;
                                   0 = R; R, or 4 when R < 4.  A window covers 64 / R * K steps
                                   of each of the block's R rows */
@@ -366,7 +369,7 @@ typedef struct {
     float default_ms;          /* the same with the planner's default plan */
     uint32_t candidates;       /* plans timed */
     int32_t steps_class;       /* floor(log2(mean capped steps per hash)) of the rows */
-    int32_t walk;              /* wmh_opts.walk of the fastest plan (1 or 2) */
+    int32_t walk;              /* wmh_opts.walk of the fastest plan (1, 2 or 3) */
     uint32_t steps_per_lane;   /* K of the fastest plan */
     uint32_t reserved[2];
 } wmh_tune_result;
@@ -375,7 +378,7 @@ typedef struct {
  * wmh_tune -- times the batched walk on the given rows (device CSR as for wmh_hash) under
  * candidate plans R in {1,2,4,8,16} x W in {4,8,16} x J in {min(k,1024), min(k,512),
  * min(k,256)} with shared windows and K = R, the same with K = 4 for R = 1 and 2, plus R = 4
- * with independent rows for every W and J, each
+ * with independent rows and R = 1 with the ballot walk for every W and J, each
  * the best of `reps` (0 = 3) calls after one untimed call, and keeps the
  * fastest in the context under (D, value width, k, step class).  Later wmh_hash calls in the
  * batched or auto mode whose rows fall in the same key and whose plan options are 0 run that

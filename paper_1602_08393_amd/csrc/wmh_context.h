@@ -34,7 +34,7 @@ struct GraphKey {
     void *sig = nullptr;
     uint64_t n_rows = 0, nnz = 0, seed = 0;
     uint32_t k = 0, R = 0, K = 0, J = 0, depth = 0, waves = 0, grid = 0;
-    bool narrow = false, packed = false, independent_rows = false;
+    bool narrow = false, packed = false, independent_rows = false, ballot = false;
     uint64_t bounds_epoch = 0;
     bool operator==(const GraphKey &o) const
     {
@@ -43,7 +43,8 @@ struct GraphKey {
                K == o.K &&
                J == o.J && depth == o.depth && waves == o.waves && grid == o.grid &&
                narrow == o.narrow && packed == o.packed &&
-               independent_rows == o.independent_rows && bounds_epoch == o.bounds_epoch;
+               independent_rows == o.independent_rows && ballot == o.ballot &&
+               bounds_epoch == o.bounds_epoch;
     }
 };
 

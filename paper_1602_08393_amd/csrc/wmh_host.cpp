@@ -116,22 +116,26 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const w
     p.hashes_per_tile = o.hashes_per_tile ? std::min(o.hashes_per_tile, k) : std::min(k, 1024u);
     const size_t elem = p.narrow ? 2 : 4;
     const size_t lds_target = 48 * 1024;  // keep several workgroups resident per CU
-    if (o.walk < 0 || o.walk > 2) return false;
+    if (o.walk < 0 || o.walk > 3) return false;
     uint32_t R = o.rows_per_block;
     if (R == 0) {
         R = 4;
         while (R > 1 && (size_t)ctx->dims * R * elem > lds_target) R >>= 1;
         if (o.walk == 2) R = 4;
+        if (o.walk == 3) R = 1;
     }
     if (R != 1 && R != 2 && R != 4 && R != 8 && R != 16) return false;
     if (o.walk == 2 && R != 4) return false;
+    if (o.walk == 3 && R != 1) return false;
     // steps per lane: R (a window of 64 steps per row), or 4 for R < 4 (windows of 256 or 128)
     const uint32_t K = o.steps_per_lane ? o.steps_per_lane : R;
     if (K != R && !(K == 4 && R < 4)) return false;
     if (o.walk == 2 && K != 4) return false;
+    if (o.walk == 3 && K != 1) return false;
     p.rows_per_block = R;
     p.steps_per_lane = K;
     p.independent_rows = o.walk == 2;
+    p.ballot = o.walk == 3;
     if (batched_lds_bytes(ctx->dims, p) > 160 * 1024 - 64) return false;
     p.packed = p.narrow && (uint64_t)ctx->dims * p.scale() <= 65536u;
     // shared stream depth: cover eight mean step counts of the sparsest row, in whole cycles of
@@ -644,6 +648,7 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         key.waves = plan.waves_per_block; key.grid = grid; key.narrow = plan.narrow;
         key.packed = plan.packed;
         key.independent_rows = plan.independent_rows;
+        key.ballot = plan.ballot;
         key.bounds_epoch = ctx->bounds_epoch;
 
         // The shared position stream (cached position stream): built once per (seed, k,
@@ -732,7 +737,10 @@ wmh_status wmh_last_plan(const wmh_ctx *ctx, wmh_opts *plan)
     plan->stream_depth = ctx->last_plan.stream_depth;
     plan->steps_per_lane = ctx->last_plan.steps_per_lane;
     plan->waves_per_block = ctx->last_plan.waves_per_block;
-    plan->walk = ctx->last_mode == WMH_MODE_BATCHED ? (ctx->last_plan.independent_rows ? 2 : 1) : 0;
+    plan->walk = ctx->last_mode != WMH_MODE_BATCHED ? 0
+                 : ctx->last_plan.ballot           ? 3
+                 : ctx->last_plan.independent_rows ? 2
+                                                   : 1;
     return WMH_OK;
 }
 

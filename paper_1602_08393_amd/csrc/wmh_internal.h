@@ -53,6 +53,8 @@ struct BatchedPlan {
     bool narrow;               // dense rows stored as uint16 (every bound < 65536)
     bool packed;               // 4-byte stream entries
     bool independent_rows;     // each row of a block walks its own hash ids (R = 4 only)
+    bool ballot;               // one row per block, first green step from the window's ballot
+                               // (R = 1, K = 1 only)
     // LDS bytes per component of the block's dense rows (RowLayout::kGroup): four rows of
     // 16-bit values sit in two planes of row pairs, 4 bytes per component
     uint32_t scale() const
@@ -98,6 +100,12 @@ hipError_t launch_shared_walk(const Bounds &b, const Rows &rows, uint32_t k, uin
                               uint16_t *sig, const BatchedPlan &plan, const void *entries,
                               uint32_t *tile_counter, uint32_t grid, hipStream_t stream);
 int shared_walk_blocks_per_cu(const BatchedPlan &plan, size_t lds);
+
+// The ballot walk (R = 1, K = 1; no checks) and its occupancy.
+hipError_t launch_ballot_walk(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
+                              uint16_t *sig, const BatchedPlan &plan, const void *entries,
+                              uint32_t *tile_counter, uint32_t grid, hipStream_t stream);
+int ballot_walk_blocks_per_cu(const BatchedPlan &plan, size_t lds);
 
 // Resident workgroups per CU for a batched plan (0 when it does not fit).
 int batched_blocks_per_cu(uint32_t dims, const BatchedPlan &plan);

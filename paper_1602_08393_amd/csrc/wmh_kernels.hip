@@ -684,6 +684,11 @@ hipError_t launch_batched(const Bounds &b, const Rows &rows, uint32_t k, uint64_
     if (plan.packed && !plan.narrow) return hipErrorInvalidValue;
     // the shared walk reads whole three-window cycles of the stream (plus one spare cycle)
     if (plan.stream_depth % plan.cycle() != 0 || plan.stream_depth >= kCap) return hipErrorInvalidValue;
+    if (plan.ballot) {
+        if (plan.rows_per_block != 1 || plan.steps_per_lane != 1 || plan.independent_rows)
+            return hipErrorInvalidValue;
+        return launch_ballot_walk(b, rows, k, seed, sig, plan, entries, tile_counter, grid, stream);
+    }
     if (plan.independent_rows) {
         if (plan.rows_per_block != 4 || plan.stream_depth < kWave) return hipErrorInvalidValue;
         if (plan.narrow)
@@ -698,6 +703,10 @@ int batched_blocks_per_cu(uint32_t dims, const BatchedPlan &plan)
 {
     const size_t lds = batched_lds_bytes(dims, plan);
     if (lds > 160 * 1024 - 64) return 0;
+    if (plan.ballot) {
+        if (plan.rows_per_block != 1 || plan.steps_per_lane != 1) return 0;
+        return ballot_walk_blocks_per_cu(plan, lds);
+    }
     if (plan.independent_rows) {
         if (plan.rows_per_block != 4) return 0;
         if (plan.narrow) return plan.packed ? rows_occupancy_t<uint16_t, true>(plan, lds)

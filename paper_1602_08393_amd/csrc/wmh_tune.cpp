@@ -35,7 +35,8 @@ void put_entry(wmh_ctx *ctx, const TuneEntry &e)
 bool valid_plan(uint32_t R, uint32_t J, uint32_t W, int32_t walk, uint32_t K)
 {
     return (R == 1 || R == 2 || R == 4 || R == 8 || R == 16) && J >= 1 && W >= 1 && W <= 16 &&
-           (walk == 1 || (walk == 2 && R == 4)) && (K == R || (K == 4 && R < 4));
+           (walk == 1 || (walk == 2 && R == 4) || (walk == 3 && R == 1 && K == 1)) &&
+           (K == R || (K == 4 && R < 4));
 }
 
 }  // namespace
@@ -118,13 +119,14 @@ wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
     uint32_t tried = 1;
     std::vector<uint32_t> Js{std::min(k, 1024u), std::min(k, 512u), std::min(k, 256u)};
     Js.erase(std::unique(Js.begin(), Js.end()), Js.end());
-    // shared windows for every R with K = R, and K = 4 for R < 4; independent rows at R = 4
+    // shared windows for every R with K = R, and K = 4 for R < 4; independent rows at R = 4;
+    // the ballot walk at R = 1
     struct Shape {
         int32_t walk;
         uint32_t R, K;
     };
     const Shape shapes[] = {{1, 1, 1}, {1, 1, 4}, {1, 2, 2}, {1, 2, 4}, {1, 4, 4},
-                            {1, 8, 8}, {1, 16, 16}, {2, 4, 4}};
+                            {1, 8, 8}, {1, 16, 16}, {2, 4, 4}, {3, 1, 1}};
     for (const Shape &sh : shapes) {
         for (uint32_t W : {4u, 8u, 16u}) {
             for (uint32_t J : Js) {

@@ -66,6 +66,47 @@ __host__ __device__ constexpr uint64_t segment_tops()
     return m;
 }
 
+// Zeroes the LDS rows of a block, then scatters its n_here CSR rows (RowLayout) and sets bit r
+// of *nonempty for every row r with a nonzero value.  Called by the whole workgroup.
+template <typename XT, int R>
+__device__ __forceinline__ void stage_block(unsigned char *smem, const Rows &rows, uint64_t row0,
+                                            uint32_t n_here, uint32_t D, uint32_t *nonempty)
+{
+    using Layout = RowLayout<XT, R>;
+    uint32_t *xz = reinterpret_cast<uint32_t *>(smem);
+    const uint32_t words = (uint32_t)(((size_t)D * R * sizeof(XT) + 3) / 4);
+    for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) xz[i] = 0u;
+    if (threadIdx.x == 0) *nonempty = 0;
+    __syncthreads();
+    uint32_t mine = 0;
+    for (uint32_t r = 0; r < n_here; ++r) {
+        const uint64_t lo = rows.row_ptr[row0 + r], hi = rows.row_ptr[row0 + r + 1];
+        for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+            const uint32_t v = rows.val[e];
+            const uint32_t c = rows.col[e];
+            if (c < D) *Layout::at(smem, c, r, D) = (XT)v;
+            if (v) mine |= 1u << r;
+        }
+    }
+    if (mine) atomicOr(nonempty, mine);
+    __syncthreads();
+}
+
+// Writes a tile's hash values (staged in LDS, row r at hbuf[r * hashes_per_tile]) row by row,
+// coalesced along j.  Called by the whole workgroup; ends with a barrier.
+__device__ __forceinline__ void write_tile(uint16_t *__restrict__ sig, const uint16_t *hbuf,
+                                           uint64_t row0, uint32_t n_here, uint32_t k,
+                                           uint32_t j0, uint32_t j1, uint32_t hashes_per_tile)
+{
+    __syncthreads();
+    const uint32_t width = j1 - j0;
+    for (uint32_t r = 0; r < n_here; ++r) {
+        uint16_t *out = sig + (row0 + r) * (uint64_t)k + j0;
+        for (uint32_t q = threadIdx.x; q < width; q += blockDim.x) out[q] = hbuf[r * hashes_per_tile + q];
+    }
+    __syncthreads();
+}
+
 // Up to four rows per block the walk fits eight wavefronts per SIMD (at most 64 VGPRs and a
 // few scalar registers spilled to vector lanes); wider blocks keep their registers.
 template <int R>
@@ -88,7 +129,6 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
     __shared__ uint32_t unit_slot;
     __shared__ uint32_t nonempty;
     const uint32_t D = b.dims;
-    XT *x = reinterpret_cast<XT *>(smem);
     uint16_t *hbuf = reinterpret_cast<uint16_t *>(smem + (((size_t)D * R * sizeof(XT) + 15) & ~(size_t)15));
     const uint32_t my_row = lane() / L;
     const uint32_t my_grp = lane() % L;
@@ -120,24 +160,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
         const uint32_t n_here = (uint32_t)min((uint64_t)R, rows.n_rows - row0);
 
         if (blk != staged) {
-            // zero the block, then scatter its rows
-            uint32_t *xz = reinterpret_cast<uint32_t *>(x);
-            const uint32_t words = (uint32_t)(((size_t)D * R * sizeof(XT) + 3) / 4);
-            for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) xz[i] = 0u;
-            if (threadIdx.x == 0) nonempty = 0;
-            __syncthreads();
-            uint32_t mine = 0;
-            for (uint32_t r = 0; r < n_here; ++r) {
-                const uint64_t lo = rows.row_ptr[row0 + r], hi = rows.row_ptr[row0 + r + 1];
-                for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-                    const uint32_t v = rows.val[e];
-                    const uint32_t c = rows.col[e];
-                    if (c < D) *Layout::at(smem, c, r, D) = (XT)v;
-                    if (v) mine |= 1u << r;
-                }
-            }
-            if (mine) atomicOr(&nonempty, mine);
-            __syncthreads();
+            stage_block<XT, R>(smem, rows, row0, n_here, D, &nonempty);
             staged = blk;
         }
         // Wave-uniform values are read into scalar registers so every branch on them is a
@@ -254,14 +277,112 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
                                                   : R * hashes_per_tile + lane();
             hbuf[slot] = (uint16_t)h;
         }
-        __syncthreads();
-        // write the tile's signatures row by row (coalesced along j)
-        const uint32_t width = j1 - j0;
-        for (uint32_t r = 0; r < n_here; ++r) {
-            uint16_t *out = sig + (row0 + r) * (uint64_t)k + j0;
-            for (uint32_t q = threadIdx.x; q < width; q += blockDim.x) out[q] = hbuf[r * hashes_per_tile + q];
+        write_tile(sig, hbuf, row0, n_here, k, j0, j1, hashes_per_tile);
+    }
+}
+
+
+// ---------------------------------------------------------------------------------------------
+// Ballot walk: one row per block (R = 1), one hash id per wavefront, lane l testing step
+// base + l + 1 of each 64-step window.  Lanes follow the steps in order, so the row's first
+// green step is the lowest set bit of the window's ballot: the stop test is the ballot itself
+// and the hash is base + ctz(ballot) + 1, both on the scalar unit, with no per-lane state and no
+// cross-lane reduction.  Stream windows come three at a time from a ring prefetched three windows
+// ahead (as in the shared-window walk); steps past the stream are drawn in-lane.
+// ---------------------------------------------------------------------------------------------
+template <typename XT, bool kPacked>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void ballot_kernel(
+    Bounds b, Rows rows, uint32_t k, uint64_t seed, uint16_t *__restrict__ sig,
+    uint32_t hashes_per_tile, uint32_t depth, const void *entries, uint32_t *tile_counter)
+{
+    constexpr uint32_t kWords = EntryRun<1, kPacked>::kWordsPerEntry;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t tile_slot;
+    __shared__ uint32_t unit_slot;
+    __shared__ uint32_t nonempty;
+    const uint32_t D = b.dims;
+    uint16_t *hbuf = reinterpret_cast<uint16_t *>(smem + (((size_t)D * sizeof(XT) + 15) & ~(size_t)15));
+    const uint32_t lane_words = lane() * kWords;
+    const uint32_t n_hash_tiles = (k + hashes_per_tile - 1) / hashes_per_tile;
+    const uint64_t n_tiles = rows.n_rows * n_hash_tiles;
+    uint64_t staged = ~0ull;
+
+    while (true) {
+        if (threadIdx.x == 0) {
+            tile_slot = atomicAdd(tile_counter, 1u);
+            unit_slot = 0;
         }
         __syncthreads();
+        const uint64_t tile = tile_slot;
+        if (tile >= n_tiles) break;
+        const uint64_t row = tile / n_hash_tiles;
+        const uint32_t ht = (uint32_t)(tile - row * n_hash_tiles);
+        if (row != staged) {
+            stage_block<XT, 1>(smem, rows, row, 1u, D, &nonempty);
+            staged = row;
+        }
+        const bool live = __builtin_amdgcn_readfirstlane(nonempty) != 0;
+        const uint32_t j0 = ht * hashes_per_tile;
+        const uint32_t j1 = min(k, j0 + hashes_per_tile);
+
+        while (true) {
+            // claim the next hash id (every lane adds 1, as in the shared-window walk)
+            const uint32_t claimed = atomicAdd(&unit_slot, 1u);
+            const uint32_t j = j0 + ((uint32_t)__builtin_amdgcn_readfirstlane(claimed) >> 6);
+            if (j >= j1) break;
+
+            // ballot of the lanes whose step is green in the window [base + 1, base + 64]
+            auto stream_ballot = [&](const EntryRun<1, kPacked> &run) {
+                uint32_t lds, off;
+                run.get(0, (uint32_t)sizeof(XT), &lds, &off);
+                const uint32_t xv = *reinterpret_cast<const XT *>(smem + lds);
+                return __builtin_amdgcn_ballot_w64(off < xv);
+            };
+            uint32_t h = 0;  // empty rows hash to 0
+            uint32_t base = 0;
+            uint64_t green = 0;
+            if (live && depth != 0) {
+                const uint32_t *id_entries =
+                    reinterpret_cast<const uint32_t *>(entries) + (uint64_t)j * depth * kWords;
+                // each prefetch stays where it is issued (see the shared-window walk)
+                auto fetch = [&](uint32_t at) {
+                    EntryRun<1, kPacked> run;
+                    run.load_at(id_entries + (size_t)at * kWords, lane_words);
+                    asm volatile("" ::: "memory");
+                    return run;
+                };
+                EntryRun<1, kPacked> e0 = fetch(0), e1 = fetch(kWave), e2 = fetch(2 * kWave);
+                for (; base < depth; base += 3 * kWave) {
+                    green = stream_ballot(e0);
+                    if (green) break;
+                    e0 = fetch(base + 3 * kWave);
+                    green = stream_ballot(e1);
+                    if (green) { base += kWave; break; }
+                    e1 = fetch(base + 4 * kWave);
+                    green = stream_ballot(e2);
+                    if (green) { base += 2 * kWave; break; }
+                    e2 = fetch(base + 5 * kWave);
+                }
+            }
+            // past the stream (rare): draws made in-lane, up to the window that holds the cap
+            if (live) {
+                for (; green == 0 && base < kCap; base += kWave) {
+                    const uint32_t t = base + lane() + 1u;
+                    const uint64_t p = position(seed, j, t, b.total, b.threshold);
+                    uint64_t o64;
+                    const uint32_t comp = component_of(p, b.prefix, b.bucket, b.shift, &o64);
+                    green = __builtin_amdgcn_ballot_w64(
+                        o64 < (uint64_t)*reinterpret_cast<const XT *>(smem + (size_t)comp * sizeof(XT)));
+                    if (green) break;
+                }
+                // first green step, or none up to the cap (the hash saturates); a green step
+                // 65536 in the last window is past the cap as well
+                h = green ? min(base + (uint32_t)__builtin_ctzll(green) + 1u, kCap) : kCap;
+            }
+            // every lane stores; only lane 0 writes the tile value
+            hbuf[lane() == 0 ? j - j0 : hashes_per_tile + lane()] = (uint16_t)h;
+        }
+        write_tile(sig, hbuf, row, 1u, k, j0, j1, hashes_per_tile);
     }
 }
 
@@ -295,6 +416,40 @@ hipError_t launch_batched_t(const Bounds &b, const Rows &rows, uint32_t k, uint6
     const size_t lds = batched_lds_bytes(b.dims, plan);
     configure_batched<XT, R, K, kPacked>();
     batched_kernel<XT, R, K, kPacked><<<grid, plan.waves_per_block * kWave, lds, stream>>>(
+        b, rows, k, seed, sig, plan.hashes_per_tile, plan.stream_depth, entries, tile_counter);
+    return hipGetLastError();
+}
+
+template <typename XT, bool kPacked>
+void configure_ballot()
+{
+    static bool configured = false;
+    if (!configured) {
+        hipFuncSetAttribute((const void *)ballot_kernel<XT, kPacked>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64);
+        configured = true;
+    }
+}
+
+template <typename XT, bool kPacked>
+int ballot_occupancy_t(const BatchedPlan &plan, size_t lds)
+{
+    configure_ballot<XT, kPacked>();
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, ballot_kernel<XT, kPacked>,
+                                                     plan.waves_per_block * kWave, lds) != hipSuccess)
+        return 1;
+    return blocks > 0 ? blocks : 1;
+}
+
+template <typename XT, bool kPacked>
+hipError_t launch_ballot_t(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
+                           uint16_t *sig, const BatchedPlan &plan, const void *entries,
+                           uint32_t *tile_counter, uint32_t grid, hipStream_t stream)
+{
+    const size_t lds = batched_lds_bytes(b.dims, plan);
+    configure_ballot<XT, kPacked>();
+    ballot_kernel<XT, kPacked><<<grid, plan.waves_per_block * kWave, lds, stream>>>(
         b, rows, k, seed, sig, plan.hashes_per_tile, plan.stream_depth, entries, tile_counter);
     return hipGetLastError();
 }
@@ -357,6 +512,25 @@ hipError_t launch_shared_walk(const Bounds &b, const Rows &rows, uint32_t k, uin
 int shared_walk_blocks_per_cu(const BatchedPlan &plan, size_t lds)
 {
     return dispatch_batched<OccupancyBatched>(plan, plan, lds);
+}
+
+hipError_t launch_ballot_walk(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
+                              uint16_t *sig, const BatchedPlan &plan, const void *entries,
+                              uint32_t *tile_counter, uint32_t grid, hipStream_t stream)
+{
+    if (plan.narrow)
+        return plan.packed
+                   ? launch_ballot_t<uint16_t, true>(b, rows, k, seed, sig, plan, entries, tile_counter, grid, stream)
+                   : launch_ballot_t<uint16_t, false>(b, rows, k, seed, sig, plan, entries, tile_counter, grid, stream);
+    return launch_ballot_t<uint32_t, false>(b, rows, k, seed, sig, plan, entries, tile_counter, grid, stream);
+}
+
+int ballot_walk_blocks_per_cu(const BatchedPlan &plan, size_t lds)
+{
+    if (plan.narrow)
+        return plan.packed ? ballot_occupancy_t<uint16_t, true>(plan, lds)
+                           : ballot_occupancy_t<uint16_t, false>(plan, lds);
+    return ballot_occupancy_t<uint32_t, false>(plan, lds);
 }
 
 }  // namespace wmh

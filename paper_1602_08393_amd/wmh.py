@@ -20,7 +20,7 @@ STATUS = {0: "WMH_OK", -1: "WMH_E_ARG", -2: "WMH_E_NO_BOUNDS", -3: "WMH_E_COL_RA
           -4: "WMH_E_UNSORTED", -5: "WMH_E_BOUND", -6: "WMH_E_OVERFLOW", -7: "WMH_E_NOMEM",
           -8: "WMH_E_DEVICE", -9: "WMH_E_ROW_PTR"}
 MODES = {"auto": 0, "plain": 1, "batched": 2, "indexed": 3}
-WALKS = {"auto": 0, "shared": 1, "rows": 2}
+WALKS = {"auto": 0, "shared": 1, "rows": 2, "ballot": 3}
 
 EXPORTED = ["wmh_opts_init", "wmh_create", "wmh_destroy", "wmh_set_bounds", "wmh_hash",
             "wmh_estimate", "wmh_collisions", "wmh_bounds_info", "wmh_bounds_tables",

@@ -112,6 +112,8 @@ def test_draws_with_zero_bounds_and_clusters(ctx):
     dict(mode="batched", use_graph=False),
     dict(mode="batched", walk="rows"),
     dict(mode="batched", walk="rows", use_graph=False, hashes_per_tile=17),
+    dict(mode="batched", walk="ballot"),
+    dict(mode="batched", walk="ballot", use_graph=False, hashes_per_tile=13, waves_per_block=3),
     dict(mode="auto"),
 ])
 def test_config1_full(ctx, opts):
@@ -135,6 +137,11 @@ BATCHED_PLANS = [
     dict(walk="rows"), dict(walk="rows", hashes_per_tile=7),
     dict(walk="rows", waves_per_block=1), dict(walk="rows", waves_per_block=16),
     dict(walk="rows", stream_depth=None), dict(walk="rows", stream_depth=128),
+    # ballot walk: one row per block, first green step from the window's ballot
+    dict(walk="ballot"), dict(walk="ballot", hashes_per_tile=7),
+    dict(walk="ballot", waves_per_block=1), dict(walk="ballot", waves_per_block=16),
+    dict(walk="ballot", stream_depth=None), dict(walk="ballot", stream_depth=64),
+    dict(walk="ballot", stream_depth=200, hashes_per_tile=9),
 ]
 
 CASES = {
@@ -210,13 +217,15 @@ def test_two_plane_rows_with_wide_entries(ctx):
     want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, k, seed=9)
     for opts in (dict(rows_per_block=4), dict(rows_per_block=4, stream_depth=None),
                  dict(rows_per_block=4, hashes_per_tile=5, waves_per_block=4),
-                 dict(walk="rows"), dict(rows_per_block=2, steps_per_lane=4)):
+                 dict(walk="rows"), dict(rows_per_block=2, steps_per_lane=4),
+                 dict(walk="ballot"), dict(walk="ballot", stream_depth=None)):
         assert_same(gpu_sig(ctx, ds, k, 9, mode="batched", **opts), want, f"D=16500 {opts}")
 
 
 def _random_plan(rng):
     """One random plan among every option the batched path takes."""
-    walk = "rows" if rng.random() < 0.2 else "shared"
+    w = rng.random()
+    walk = "rows" if w < 0.2 else "ballot" if w < 0.4 else "shared"
     plan = dict(mode="batched", walk=walk)
     if walk == "shared":
         R = int(rng.choice([1, 2, 4, 8, 16]))
@@ -275,7 +284,7 @@ def test_packed_entries_at_the_offset_limit(ctx):
     assert int(ds.m.max()) <= 0xFFFF
     want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, 45, seed=12)
     for opts in (dict(rows_per_block=4), dict(rows_per_block=4, use_graph=False),
-                 dict(walk="rows")):
+                 dict(walk="rows"), dict(walk="ballot")):
         assert_same(gpu_sig(ctx, ds, 45, 12, mode="batched", **opts), want, f"D=16384 {opts}")
 
 
@@ -287,6 +296,7 @@ def test_many_hash_ids(ctx):
     k = 70001
     want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, k, seed=13)
     for opts in (dict(mode="batched"), dict(mode="batched", hashes_per_tile=4096),
+                 dict(mode="batched", walk="ballot", hashes_per_tile=4096),
                  dict(mode="plain")):
         assert_same(gpu_sig(ctx, ds, k, 13, **opts), want, f"k={k} {opts}")
 
@@ -311,7 +321,10 @@ def test_full_rows_hash_to_one_and_saturation(ctx):
                  dict(mode="batched", walk="rows"),
                  dict(mode="batched", walk="rows", stream_depth=None),
                  dict(mode="batched", rows_per_block=1, steps_per_lane=4),
-                 dict(mode="batched", rows_per_block=2, steps_per_lane=4, stream_depth=None)):
+                 dict(mode="batched", rows_per_block=2, steps_per_lane=4, stream_depth=None),
+                 dict(mode="batched", walk="ballot"),
+                 dict(mode="batched", walk="ballot", stream_depth=70000),
+                 dict(mode="batched", walk="ballot", stream_depth=None)):
         assert_same(gpu_sig(ctx, ds, k, 5, **opts), want, f"saturation {opts}")
 
 
@@ -340,6 +353,8 @@ def test_config2_head(ctx):
     assert_same(gpu_sig(ctx, ds, 500, 0, mode="batched"), want, "config2 head batched")
     assert_same(gpu_sig(ctx, ds, 500, 0, mode="batched", walk="rows"), want,
                 "config2 head independent rows")
+    assert_same(gpu_sig(ctx, ds, 500, 0, mode="batched", walk="ballot"), want,
+                "config2 head ballot walk")
 
 
 @pytest.fixture(scope="module")
@@ -351,6 +366,8 @@ def test_config4_head_full_bounds(ctx, config4):
     ds = config4.head(300)
     want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, 500, seed=0)
     assert_same(gpu_sig(ctx, ds, 500, 0, mode="batched"), want, "config4 head batched")
+    assert_same(gpu_sig(ctx, ds, 500, 0, mode="batched", walk="ballot"), want,
+                "config4 head ballot walk")
     assert_same(gpu_sig(ctx, ds, 500, 0, mode="plain"), want, "config4 head plain")
 
 
