@@ -12,6 +12,8 @@ seed (1000 + configuration number).
 """
 from __future__ import annotations
 
+import concurrent.futures
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -179,19 +181,34 @@ def _sparse_rows_with_replacement(rng, lengths, D, weight_fn):
     return cols, vals, kept
 
 
+def _zipf_rows_block(seed: int, b: int, rows: int, D: int, lo: int, hi: int):
+    """Block b of a Zipf-length workload, from its own generator (seed, spawn key b), so blocks
+    can be drawn in any order and any prefix of blocks is the same whatever the total."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed, spawn_key=(b,))))
+    want = _zipf_clipped(rng, 1.2, lo, hi, rows)
+    return _sparse_rows_with_replacement(rng, want, D, _tf_weights)
+
+
+def _zipf_rows(seed: int, n_rows: int, block: int, D: int, lo: int, hi: int):
+    """Blocks of _zipf_rows_block drawn on host threads (numpy's sampling, sorting and
+    logarithms run without the interpreter lock), concatenated in block order."""
+    jobs = [(b, min(block, n_rows - r0)) for b, r0 in enumerate(range(0, n_rows, block))]
+    workers = max(1, min(len(jobs), 16, os.cpu_count() or 1))
+    with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+        parts = list(ex.map(lambda jb: _zipf_rows_block(seed, jb[0], jb[1], D, lo, hi), jobs))
+    cols = [p[0] for p in parts]
+    vals = [p[1] for p in parts]
+    lengths = np.concatenate([p[2] for p in parts]) if parts else np.zeros(0, np.int64)
+    return cols, vals, lengths
+
+
 def config3(n_rows: int = 1_000_000, block: int = 20_000) -> Dataset:
     """Text-like: N=1,000,000, D=65536, nnz = clamp(Zipf(1.2), 10, 5000) column draws per row
     (uniform with replacement, duplicates merged), tf weights 1+ln(count), count ~ Zipf(1.5),
-    Q16.16, m_i = dataset max (floor 1), k=1000, seed 0."""
-    rng = np.random.Generator(np.random.PCG64(1003))
+    Q16.16, m_i = dataset max (floor 1), k=1000, seed 0.  Blocks of `block` rows have their own
+    generators (seed 1003, spawn key = block number)."""
     D = 65536
-    cols, vals, lengths = [], [], []
-    for r0 in range(0, n_rows, block):
-        rows = min(block, n_rows - r0)
-        want = _zipf_clipped(rng, 1.2, 10, 5000, rows)
-        c, v, kept = _sparse_rows_with_replacement(rng, want, D, _tf_weights)
-        cols.append(c); vals.append(v); lengths.append(kept)
-    lengths = np.concatenate(lengths)
+    cols, vals, lengths = _zipf_rows(1003, n_rows, block, D, 10, 5000)
     return _assemble(cols, vals, lengths, D, "config3-text", 1000, 0,
                      {"N": n_rows, "D": D, "nnz": "clamp(Zipf(1.2), 10, 5000) draws",
                       "weights": "1+ln(Zipf(1.5)) Q16.16"})
@@ -234,16 +251,10 @@ def config4(n_rows: int = 200_000) -> Dataset:
 def config5_corpus(n_rows: int = 100_000, block: int = 20_000) -> Dataset:
     """Serving corpus: 100,000 rows, D=2^20, nnz = clamp(Zipf(1.2), 5, 10000) column draws per
     row (with replacement, duplicates merged), tf weights as config 3, m_i = corpus max; k=256.
-    Requests are batches of corpus rows, so every request is within the bounds."""
-    rng = np.random.Generator(np.random.PCG64(1005))
+    Requests are batches of corpus rows, so every request is within the bounds.  Blocks of
+    `block` rows have their own generators (seed 1005, spawn key = block number)."""
     D = 1 << 20
-    cols, vals, lengths = [], [], []
-    for r0 in range(0, n_rows, block):
-        rows = min(block, n_rows - r0)
-        want = _zipf_clipped(rng, 1.2, 5, 10000, rows)
-        c, v, kept = _sparse_rows_with_replacement(rng, want, D, _tf_weights)
-        cols.append(c); vals.append(v); lengths.append(kept)
-    lengths = np.concatenate(lengths)
+    cols, vals, lengths = _zipf_rows(1005, n_rows, block, D, 5, 10000)
     return _assemble(cols, vals, lengths, D, "config5-serving-corpus", 256, 0,
                      {"N": n_rows, "D": D, "nnz": "clamp(Zipf(1.2), 5, 10000) draws"})
 
