@@ -413,7 +413,9 @@ typedef struct {
     int32_t mode;          /* wmh_mode of every request's walk; 0 = auto */
     uint32_t stream_depth; /* steps of the shared position stream built once at creation;
                               0 = 8192 (steps beyond are drawn in-lane) */
-    uint32_t reserved[4];
+    int32_t build_index;   /* 1: build the component index at creation (auto or indexed mode),
+                              so no request waits for it; 0: on the first indexed request */
+    uint32_t reserved[3];
 } wmh_server_config;
 
 typedef struct {
@@ -425,6 +427,7 @@ typedef struct {
     double p50_ms, p99_ms, p999_ms, max_ms, mean_ms; /* arrival -> completion */
     double busy_s;         /* first admission -> last completion */
     double hashes_per_s;   /* hashes / busy_s */
+    uint64_t rejected;     /* requests whose rows failed the device check (not in failed) */
 } wmh_serving_stats;
 
 /*
@@ -440,8 +443,11 @@ wmh_status wmh_server_create(wmh_ctx *ctx, const wmh_server_config *cfg, wmh_ser
 /*
  * wmh_server_submit -- queues one request of N CSR rows (host buffers: row_ptr N+1, col/val
  * nnz) whose signatures go to sig (host, N*k uint16).  The caller keeps all four buffers valid
- * and unchanged until the request completes.  The rows are checked on the host first (same
- * rules and errors as wmh_hash); a request larger than mem_budget is WMH_E_NOMEM.
+ * and unchanged until the request completes.  row_ptr is checked here (WMH_E_ROW_PTR); every
+ * entry is checked on the device by wmh_hash's validation pass before any walk, and a request
+ * that breaks a rule completes with that status (WMH_E_COL_RANGE, WMH_E_UNSORTED,
+ * WMH_E_BOUND) from wmh_server_poll / wmh_server_wait, its sig untouched.  A request larger
+ * than mem_budget is WMH_E_NOMEM.
  * arrival_ns is the request's arrival on wmh_server_now_ns()'s clock (0 = now); latency is
  * measured from it, so an open-loop driver that submits late does not hide queueing delay.
  * Each request's signatures are identical to a wmh_hash call on the same rows.
@@ -464,6 +470,18 @@ wmh_status wmh_server_stats(wmh_server *srv, wmh_serving_stats *out);
 
 /* The steady clock used for arrival times, in nanoseconds. */
 uint64_t wmh_server_now_ns(void);
+
+/*
+ * wmh_host_alloc -- pinned (page-locked) host memory of `bytes` bytes for request buffers.
+ * wmh_server_submit's copies of rows in and signatures out run as asynchronous DMA from and to
+ * such buffers; from pageable buffers the copy in also works, but the loop's worker waits for
+ * it.  *ptr receives the buffer (NULL for bytes = 0); release it with wmh_host_free after every
+ * request using it has completed.  Errors: WMH_E_ARG (ptr NULL), WMH_E_NOMEM.
+ */
+wmh_status wmh_host_alloc(size_t bytes, void **ptr);
+
+/* Releases a wmh_host_alloc buffer; NULL is ignored. */
+void wmh_host_free(void *ptr);
 
 /* Drains, stops the worker and releases every buffer.  NULL is ignored. */
 void wmh_server_destroy(wmh_server *srv);

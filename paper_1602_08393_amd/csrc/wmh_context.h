@@ -144,6 +144,8 @@ struct wmh_ctx {
 namespace wmh {
 
 wmh_status fail(wmh_ctx *ctx, wmh_status st, const char *fmt, ...);
+// Status of a validation-pass error code (the low four bits of CheckWords::first_error).
+wmh_status check_status(uint32_t code);
 wmh_status device_fail(wmh_ctx *ctx, hipError_t e, const char *what);
 Bounds bounds_view(const wmh_ctx *ctx);
 // Tile plan of the batched walk; false when no dense plan fits in LDS.  Options left at 0
@@ -155,11 +157,6 @@ TuneKey tune_key(const wmh_ctx *ctx, uint32_t k, const RowStats &stats);
 // want_keys: also estimate index_keys (only the path choice in auto mode reads it)
 wmh_status gather_stats(wmh_ctx *ctx, const Rows &rows, uint32_t k, hipStream_t s, bool check,
                         bool want_keys, RowStats *stats);
-// Host-side check of CSR rows against the context's bounds (same rules as the device check);
-// fills *stats (may be NULL) like the device pass.
-wmh_status check_rows_host(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
-                           const uint32_t *val, uint64_t n_rows, uint64_t nnz, uint32_t k,
-                           RowStats *stats);
 // Whether an index for k hashes is allowed (k and memory limits).
 bool index_fits(uint32_t k);
 // Makes `ix` the index of (ctx's bounds, seed, k), building it on `stream` when stale.

@@ -164,49 +164,6 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const w
     return true;
 }
 
-wmh_status check_rows_host(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
-                           const uint32_t *val, uint64_t n_rows, uint64_t nnz, uint32_t k,
-                           RowStats *stats)
-{
-    RowStats st;
-    st.known = true;
-    st.keys_known = true;
-    for (uint64_t r = 0; r < n_rows; ++r) {
-        const uint64_t lo = row_ptr[r], hi = row_ptr[r + 1];
-        if (lo > hi || hi > nnz)
-            return fail(ctx, WMH_E_ROW_PTR, "row %llu: row_ptr decreasing or beyond nnz",
-                        (unsigned long long)r);
-        uint64_t green = 0, bounds_sum = 0;
-        for (uint64_t e = lo; e < hi; ++e) {
-            const uint32_t c = col[e];
-            if (c >= ctx->dims)
-                return fail(ctx, WMH_E_COL_RANGE, "row %llu: column index >= D",
-                            (unsigned long long)r);
-            if (e > lo && col[e - 1] >= c)
-                return fail(ctx, WMH_E_UNSORTED, "row %llu: columns not strictly increasing",
-                            (unsigned long long)r);
-            if (val[e] > ctx->h_bound[c])
-                return fail(ctx, WMH_E_BOUND, "row %llu: value above its bound m_i",
-                            (unsigned long long)r);
-            green += val[e];
-            bounds_sum += val[e] ? ctx->h_bound[c] : 0u;
-        }
-        if (green) {
-            ++st.nonempty;
-            st.min_green = std::min(st.min_green, green);
-            st.walk_steps += std::min<uint64_t>(ctx->total / green, kCap);
-            const double s = (double)green / (double)ctx->total;
-            const double T = s >= 1.0 ? 1.0 : std::ceil(std::log(1e-4 / (double)k) / std::log1p(-s));
-            const double by_offset = 65534.0 * s;
-            const double by_step = T < 65534.0 ? T * ((double)bounds_sum / (double)ctx->total)
-                                               : by_offset;
-            st.index_keys += (uint64_t)std::ceil(std::min(by_offset, by_step));
-        }
-    }
-    if (stats) *stats = st;
-    return WMH_OK;
-}
-
 wmh_status gather_stats(wmh_ctx *ctx, const Rows &rows, uint32_t k, hipStream_t s, bool check,
                         bool want_keys, RowStats *stats)
 {

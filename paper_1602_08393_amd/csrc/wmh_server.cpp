@@ -2,10 +2,13 @@
 //
 // Requests are queued by any host thread and admitted, in arrival order, by one worker thread
 // whenever a slot (a HIP stream with its own buffers) is free and the admitted device bytes
-// stay within the budget.  Each admitted request is copied in, walked and copied out on its
-// slot's stream, so requests overlap on the device; the worker completes a request when its
-// slot's event has fired.  The bounds tables and the shared position stream are built once and
-// stay device-resident.  Every request computes the same function as wmh_hash on its rows.
+// stay within the budget.  An admitted request runs in two phases on its slot's stream: its
+// rows are copied in and checked by the device validation pass (which also gathers the
+// planner's statistics); once the check words are back, the worker either completes it with
+// the error or launches the chosen path and the copy out.  Requests overlap on the device and
+// the worker never blocks on one.  The bounds tables and the shared position stream are built
+// once and stay device-resident.  Every request computes the same function as wmh_hash on its
+// rows.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -44,7 +47,7 @@ struct Request {
     uint16_t *sig = nullptr;
     uint64_t arrival_ns = 0, admit_ns = 0, done_ns = 0;
     uint64_t bytes = 0;
-    RowStats stats;  // from the host check, for the planner
+    RowStats stats;  // from the device check, for the planner
     bool done = false;
     wmh_status status = WMH_OK;
 };
@@ -58,7 +61,11 @@ struct Slot {
     uint16_t *h_sig = nullptr;  // pinned staging of the signatures
     uint64_t cap_rows = 0, cap_col = 0, cap_val = 0, cap_sig = 0, cap_h_sig = 0;
     uint32_t *d_tile_counter = nullptr;
+    CheckWords *d_check = nullptr;  // the validation pass's words
+    CheckWords *h_check = nullptr;  // pinned copy, read once `checked` has fired
+    hipEvent_t checked = nullptr;
     Request *req = nullptr;
+    bool computing = false;  // past the check: the walk and the copy out are queued
 };
 
 template <typename T>
@@ -99,17 +106,19 @@ struct wmh_server {
     bool stopping = false;
     std::thread worker;
     // statistics
-    uint64_t submitted = 0, completed = 0, failed = 0, max_queued = 0, peak_bytes = 0;
+    uint64_t submitted = 0, completed = 0, failed = 0, rejected = 0, max_queued = 0, peak_bytes = 0;
     uint64_t hashes = 0;
     std::vector<double> latencies_ms;
     uint64_t first_admit_ns = 0, last_done_ns = 0;
 
-    wmh_status launch(Slot &slot, Request &r);
+    wmh_status launch_check(Slot &slot, Request &r);
+    wmh_status launch_compute(Slot &slot, Request &r);
     void complete(Slot &slot, wmh_status st);
     void run();
 };
 
-wmh_status wmh_server::launch(Slot &slot, Request &r)
+// Phase one: buffers, copy in, validation pass and the copy of its words to the host.
+wmh_status wmh_server::launch_check(Slot &slot, Request &r)
 {
     const uint32_t k = cfg.k;
     const uint64_t sig_elems = r.n_rows * (uint64_t)k;
@@ -134,6 +143,38 @@ wmh_status wmh_server::launch(Slot &slot, Request &r)
         e = hipMemcpyAsync(slot.d_col, r.col, r.nnz * sizeof(uint32_t), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && r.nnz)
         e = hipMemcpyAsync(slot.d_val, r.val, r.nnz * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    const Rows rows{slot.d_row_ptr, slot.d_col, slot.d_val, r.n_rows, r.nnz};
+    // first_error and min_green start at ~0, the counters at 0 (as in wmh_hash's pass); the
+    // index-key estimate only when the planner may take the index
+    uint32_t *words = reinterpret_cast<uint32_t *>(slot.d_check);
+    const bool want_keys = cfg.mode == WMH_MODE_AUTO && index_fits(cfg.k);
+    if (e == hipSuccess) e = launch_fill_u32(words, 0xFFFFFFFFu, 4, s);
+    if (e == hipSuccess) e = launch_fill_u32(words + 4, 0u, 6, s);
+    if (e == hipSuccess)
+        e = launch_validate(rows, ctx->d_bound, ctx->dims, ctx->total, k, want_keys, slot.d_check, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(slot.h_check, slot.d_check, sizeof(CheckWords), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(slot.checked, s);
+    slot.computing = false;
+    return e == hipSuccess ? WMH_OK : WMH_E_DEVICE;
+}
+
+// Phase two, once the check words are on the host: the rows' status, then the chosen path and
+// the copy out (nothing is launched for rows that failed the check).
+wmh_status wmh_server::launch_compute(Slot &slot, Request &r)
+{
+    const CheckWords v = *slot.h_check;
+    if (v.first_error != ~0ull) return check_status((uint32_t)(v.first_error & 15u));
+    r.stats.known = true;
+    r.stats.nonempty = r.n_rows - std::min<uint64_t>(r.n_rows, v.n_empty);
+    r.stats.min_green = v.min_green;
+    r.stats.walk_steps = v.walk_steps;
+    r.stats.index_keys = v.index_keys;
+    r.stats.keys_known = cfg.mode == WMH_MODE_AUTO && index_fits(cfg.k);
+    const uint32_t k = cfg.k;
+    const uint64_t sig_elems = r.n_rows * (uint64_t)k;
+    hipStream_t s = slot.stream;
+    hipError_t e = hipSuccess;
     const Rows rows{slot.d_row_ptr, slot.d_col, slot.d_val, r.n_rows, r.nnz};
     const Bounds b = bounds_view(ctx);
     // the index is built once per loop, so its cost is left out of the comparison
@@ -167,6 +208,7 @@ wmh_status wmh_server::launch(Slot &slot, Request &r)
         e = hipMemcpyAsync(slot.h_sig, slot.d_sig, sig_elems * sizeof(uint16_t),
                            hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipEventRecord(slot.finished, s);
+    slot.computing = true;
     return e == hipSuccess ? WMH_OK : WMH_E_DEVICE;
 }
 
@@ -186,6 +228,9 @@ void wmh_server::complete(Slot &slot, wmh_status st)
         hashes += r.n_rows * (uint64_t)cfg.k;
         latencies_ms.push_back((double)(r.done_ns - r.arrival_ns) * 1e-6);
         last_done_ns = std::max(last_done_ns, r.done_ns);
+    } else if (st == WMH_E_ROW_PTR || st == WMH_E_COL_RANGE || st == WMH_E_UNSORTED ||
+               st == WMH_E_BOUND) {
+        ++rejected;  // the caller's rows, reported by wmh_server_poll / wait
     } else {
         ++failed;
     }
@@ -198,12 +243,22 @@ void wmh_server::run()
     (void)hipSetDevice(ctx->device);
     std::unique_lock<std::mutex> lk(mu);
     while (true) {
-        // completions
+        // checked requests go on to their walk; finished ones complete
         for (Slot &slot : slots) {
             if (!slot.req) continue;
-            const hipError_t q = hipEventQuery(slot.finished);
-            if (q == hipSuccess) complete(slot, WMH_OK);
-            else if (q != hipErrorNotReady) complete(slot, WMH_E_DEVICE);
+            const hipError_t q = hipEventQuery(slot.computing ? slot.finished : slot.checked);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) {
+                complete(slot, WMH_E_DEVICE);
+            } else if (slot.computing) {
+                complete(slot, WMH_OK);
+            } else {
+                Request *r = slot.req;
+                lk.unlock();
+                const wmh_status st = launch_compute(slot, *r);
+                lk.lock();
+                if (st != WMH_OK) complete(slot, st);
+            }
         }
         // admissions, in arrival order
         while (!queue.empty()) {
@@ -224,7 +279,7 @@ void wmh_server::run()
             r->admit_ns = steady_ns();
             if (!first_admit_ns) first_admit_ns = r->admit_ns;
             lk.unlock();
-            const wmh_status st = launch(*free_slot, *r);
+            const wmh_status st = launch_check(*free_slot, *r);
             lk.lock();
             if (st != WMH_OK) complete(*free_slot, st);
         }
@@ -242,6 +297,19 @@ void wmh_server::run()
 extern "C" {
 
 uint64_t wmh_server_now_ns(void) { return steady_ns(); }
+
+wmh_status wmh_host_alloc(size_t bytes, void **ptr)
+{
+    if (!ptr) return WMH_E_ARG;
+    *ptr = nullptr;
+    if (bytes == 0) return WMH_OK;
+    return hipHostMalloc(ptr, bytes, hipHostMallocDefault) == hipSuccess ? WMH_OK : WMH_E_NOMEM;
+}
+
+void wmh_host_free(void *ptr)
+{
+    if (ptr) (void)hipHostFree(ptr);
+}
 
 wmh_status wmh_server_create(wmh_ctx *ctx, const wmh_server_config *cfg_in, wmh_server **out)
 {
@@ -289,11 +357,28 @@ wmh_status wmh_server_create(wmh_ctx *ctx, const wmh_server_config *cfg_in, wmh_
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&slot.finished, hipEventDisableTiming);
         if (e == hipSuccess) e = hipMalloc(&slot.d_tile_counter, sizeof(uint32_t));
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&slot.checked, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&slot.d_check), sizeof(CheckWords));
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void **>(&slot.h_check), sizeof(CheckWords),
+                              hipHostMallocDefault);
     }
     if (e != hipSuccess) {
         wmh_status st = device_fail(ctx, e, "server setup");
         wmh_server_destroy(srv);
         return st;
+    }
+    if (cfg.build_index && cfg.mode != WMH_MODE_BATCHED && cfg.mode != WMH_MODE_PLAIN &&
+        index_fits(cfg.k)) {
+        wmh_status st = ensure_index(ctx, &srv->index, cfg.seed, cfg.k, ctx->own_stream);
+        if (st == WMH_OK) {
+            const hipError_t se = hipStreamSynchronize(ctx->own_stream);
+            if (se != hipSuccess) st = device_fail(ctx, se, "index build");
+        }
+        if (st != WMH_OK) {
+            wmh_server_destroy(srv);
+            return st;
+        }
     }
     ctx->servers++;
     srv->worker = std::thread([srv] { srv->run(); });
@@ -309,9 +394,11 @@ wmh_status wmh_server_submit(wmh_server *srv, const uint64_t *row_ptr, const uin
     wmh_ctx *ctx = srv->ctx;
     if (!row_ptr || (n_rows && !sig) || (nnz && (!col || !val)))
         return fail(ctx, WMH_E_ARG, "null buffer");
-    RowStats stats;
-    const wmh_status st = check_rows_host(ctx, row_ptr, col, val, n_rows, nnz, srv->cfg.k, &stats);
-    if (st != WMH_OK) return st;
+    // row_ptr here (it sizes the copies); every entry is checked on the device
+    for (uint64_t r = 0; r < n_rows; ++r)
+        if (row_ptr[r] > row_ptr[r + 1] || row_ptr[r + 1] > nnz)
+            return fail(ctx, WMH_E_ROW_PTR, "row %llu: row_ptr decreasing or beyond nnz",
+                        (unsigned long long)r);
     const uint64_t bytes = (n_rows + 1) * 8 + nnz * 8 + n_rows * (uint64_t)srv->cfg.k * 2;
     if (bytes > srv->cfg.mem_budget)
         return fail(ctx, WMH_E_NOMEM, "request needs %llu bytes, budget %llu",
@@ -326,7 +413,6 @@ wmh_status wmh_server_submit(wmh_server *srv, const uint64_t *row_ptr, const uin
     r->sig = sig;
     r->arrival_ns = arrival_ns ? arrival_ns : steady_ns();
     r->bytes = bytes;
-    r->stats = stats;
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         r->id = srv->next_id++;
@@ -392,6 +478,7 @@ wmh_status wmh_server_stats(wmh_server *srv, wmh_serving_stats *out)
     out->submitted = srv->submitted;
     out->completed = srv->completed;
     out->failed = srv->failed;
+    out->rejected = srv->rejected;
     out->queued = srv->queue.size();
     out->max_queued = srv->max_queued;
     out->peak_bytes = srv->peak_bytes;
@@ -440,6 +527,9 @@ void wmh_server_destroy(wmh_server *srv)
         if (slot.h_sig) (void)hipHostFree(slot.h_sig);
         if (slot.d_tile_counter) (void)hipFree(slot.d_tile_counter);
         if (slot.finished) (void)hipEventDestroy(slot.finished);
+        if (slot.checked) (void)hipEventDestroy(slot.checked);
+        if (slot.d_check) (void)hipFree(slot.d_check);
+        if (slot.h_check) (void)hipHostFree(slot.h_check);
         if (slot.stream) (void)hipStreamDestroy(slot.stream);
     }
     if (srv->d_stream) (void)hipFree(srv->d_stream);

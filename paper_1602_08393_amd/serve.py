@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import time
-from dataclasses import dataclass
+from dataclasses import dataclass, field
 
 import numpy as np
 
@@ -19,6 +19,40 @@ def now_ns() -> int:
     return int(wmh.load().wmh_server_now_ns())
 
 
+class PinnedBuffer:
+    """Page-locked host memory from wmh_host_alloc, released when the object is collected."""
+
+    def __init__(self, nbytes: int):
+        self._lib = wmh.load()
+        self.ptr = ctypes.c_void_p()
+        st = self._lib.wmh_host_alloc(nbytes, ctypes.byref(self.ptr))
+        if st != 0:
+            raise wmh.WMHError(st, f"wmh_host_alloc of {nbytes} bytes")
+        self.nbytes = nbytes
+
+    def array(self, shape, dtype) -> np.ndarray:
+        dtype = np.dtype(dtype)
+        n = int(np.prod(shape))
+        if n == 0:
+            return np.zeros(shape, dtype=dtype)
+        raw = (ctypes.c_uint8 * (n * dtype.itemsize)).from_address(self.ptr.value)
+        return np.frombuffer(raw, dtype=dtype, count=n).reshape(shape)
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and self.ptr.value:
+            self._lib.wmh_host_free(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+
+def pinned_like(a: np.ndarray, pins: list) -> np.ndarray:
+    """A copy of `a` in page-locked memory; its owner is appended to `pins`."""
+    buf = PinnedBuffer(max(a.nbytes, 1))
+    pins.append(buf)
+    out = buf.array(a.shape, a.dtype)
+    out[...] = a
+    return out
+
+
 @dataclass
 class Request:
     row_ptr: np.ndarray  # u64 [N+1]
@@ -26,6 +60,7 @@ class Request:
     val: np.ndarray      # u32 [nnz]
     sig: np.ndarray      # u16 [N, k], written on completion
     ticket: int = 0
+    pins: list = field(default_factory=list)  # owners of page-locked buffers
 
     @property
     def n_rows(self) -> int:
@@ -36,7 +71,8 @@ class Server:
     """A serving loop on a context's device and bounds."""
 
     def __init__(self, ctx: "wmh.Context", k: int, seed: int = 0, slots: int = 4,
-                 mem_budget: int = 0, mode: str = "auto", stream_depth: int = 0):
+                 mem_budget: int = 0, mode: str = "auto", stream_depth: int = 0,
+                 build_index: bool = False):
         self._lib = wmh.load()
         self.ctx = ctx
         self.k = k
@@ -47,6 +83,7 @@ class Server:
         cfg.mem_budget = mem_budget
         cfg.mode = wmh.MODES[mode]
         cfg.stream_depth = stream_depth
+        cfg.build_index = int(bool(build_index))
         self._ptr = ctypes.c_void_p()
         ctx._check(self._lib.wmh_server_create(ctx._ptr, ctypes.byref(cfg),
                                                ctypes.byref(self._ptr)), "wmh_server_create")
@@ -70,12 +107,18 @@ class Server:
         except Exception:
             pass
 
-    def make_request(self, row_ptr, col, val) -> Request:
+    def make_request(self, row_ptr, col, val, pinned: bool = False) -> Request:
+        """A request over these rows; with `pinned` its buffers are copied to page-locked
+        memory, so the loop's copies in and out are asynchronous DMA."""
         row_ptr = np.ascontiguousarray(row_ptr, dtype=np.uint64)
         col = np.ascontiguousarray(col, dtype=np.uint32)
         val = np.ascontiguousarray(val, dtype=np.uint32)
         sig = np.zeros((len(row_ptr) - 1, self.k), dtype=np.uint16)
-        return Request(row_ptr, col, val, sig)
+        if not pinned:
+            return Request(row_ptr, col, val, sig)
+        pins: list = []
+        return Request(pinned_like(row_ptr, pins), pinned_like(col, pins),
+                       pinned_like(val, pins), pinned_like(sig, pins), pins=pins)
 
     def submit(self, req: Request, arrival_ns: int = 0) -> int:
         t = ctypes.c_uint64()
@@ -115,8 +158,9 @@ class Server:
         return {name: getattr(s, name) for name, _ in wmh.ServingStats._fields_}
 
 
-def requests_from_corpus(ds, row_lists, server: Server) -> list[Request]:
-    """One Request per list of corpus row indices (rows copied out of the corpus)."""
+def requests_from_corpus(ds, row_lists, server: Server, pinned: bool = False) -> list[Request]:
+    """One Request per list of corpus row indices (rows copied out of the corpus, into
+    page-locked buffers with `pinned`)."""
     out = []
     rp = ds.row_ptr.astype(np.int64)
     for rows in row_lists:
@@ -128,7 +172,7 @@ def requests_from_corpus(ds, row_lists, server: Server) -> list[Request]:
             idx = np.concatenate([np.arange(a, b) for a, b in zip(rp[rows], rp[rows + 1])])
         else:
             idx = np.zeros(0, dtype=np.int64)
-        out.append(server.make_request(row_ptr, ds.col[idx], ds.val[idx]))
+        out.append(server.make_request(row_ptr, ds.col[idx], ds.val[idx], pinned=pinned))
     return out
 
 

@@ -31,7 +31,8 @@ EXPORTED = ["wmh_opts_init", "wmh_create", "wmh_destroy", "wmh_set_bounds", "wmh
             "wmh_lsh_destroy",
             "wmh_last_error", "wmh_status_string",
             "wmh_server_create", "wmh_server_submit", "wmh_server_poll", "wmh_server_wait",
-            "wmh_server_drain", "wmh_server_stats", "wmh_server_now_ns", "wmh_server_destroy"]
+            "wmh_server_drain", "wmh_server_stats", "wmh_server_now_ns", "wmh_server_destroy",
+            "wmh_host_alloc", "wmh_host_free"]
 
 
 class WmhOpts(ctypes.Structure):
@@ -47,7 +48,8 @@ class WmhOpts(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("k", ctypes.c_uint32), ("slots", ctypes.c_uint32), ("seed", ctypes.c_uint64),
                 ("mem_budget", ctypes.c_uint64), ("mode", ctypes.c_int32),
-                ("stream_depth", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 4)]
+                ("stream_depth", ctypes.c_uint32), ("build_index", ctypes.c_int32),
+                ("reserved", ctypes.c_uint32 * 3)]
 
 
 class ServingStats(ctypes.Structure):
@@ -57,7 +59,8 @@ class ServingStats(ctypes.Structure):
                 ("hashes", ctypes.c_uint64), ("p50_ms", ctypes.c_double),
                 ("p99_ms", ctypes.c_double), ("p999_ms", ctypes.c_double),
                 ("max_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
-                ("busy_s", ctypes.c_double), ("hashes_per_s", ctypes.c_double)]
+                ("busy_s", ctypes.c_double), ("hashes_per_s", ctypes.c_double),
+                ("rejected", ctypes.c_uint64)]
 
 
 class TuneResult(ctypes.Structure):
@@ -165,6 +168,10 @@ def load() -> ctypes.CDLL:
     L.wmh_server_now_ns.restype = ctypes.c_uint64
     L.wmh_server_destroy.argtypes = [vp]
     L.wmh_server_destroy.restype = None
+    L.wmh_host_alloc.argtypes = [ctypes.c_size_t, ctypes.POINTER(vp)]
+    L.wmh_host_alloc.restype = ctypes.c_int
+    L.wmh_host_free.argtypes = [vp]
+    L.wmh_host_free.restype = None
     L.wmh_last_error.argtypes = [vp]
     L.wmh_last_error.restype = ctypes.c_char_p
     L.wmh_status_string.argtypes = [ctypes.c_int]

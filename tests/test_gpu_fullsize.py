@@ -139,8 +139,8 @@ def test_heavy_tail_full_size(ctx):
 
 
 def test_text_like_rows_full_batch(ctx):
-    """The benchmark's text-like batch (first 100000 rows of the D = 65536 generator, k = 1000),
-    hashed in auto mode as the benchmark does (the planner takes the component index)."""
+    """The first 100000 rows of the text-like workload (D = 65536, k = 1000), hashed in auto
+    mode as the benchmark hashes all 1e6 (the planner takes the component index)."""
     ds = synth.config3(n_rows=100_000, block=20_000)
     k = ds.k
     say(f"text-like N={ds.n_rows} D={ds.D} nnz={ds.nnz} k={k}")
@@ -156,9 +156,10 @@ def test_text_like_rows_full_batch(ctx):
 
 
 def test_serving_on_the_large_corpus(ctx):
-    """Requests drawn from the benchmark's D = 2^20 serving corpus (k = 256), run through the
-    loop with several slots so they overlap; sampled rows of every request equal the oracle,
-    and every request equals wmh_hash on the same rows."""
+    """Requests drawn from the first 20000 rows of the D = 2^20 serving corpus (k = 256), in
+    page-locked buffers as the benchmark sends them, run through the loop with several slots so
+    they overlap; sampled rows of every request equal the oracle, and every request equals
+    wmh_hash on the same rows."""
     corpus = synth.config5_corpus(n_rows=20_000)
     k = corpus.k
     say(f"serving corpus N={corpus.n_rows} D={corpus.D} nnz={corpus.nnz} k={k}")
@@ -166,7 +167,7 @@ def test_serving_on_the_large_corpus(ctx):
     _, sizes, row_lists = synth.serving_requests(12, corpus.n_rows, qps=1.0, seed=3105,
                                                  max_rows=4096)
     with serve.Server(ctx, k, seed=0, slots=4) as srv:
-        reqs = serve.requests_from_corpus(corpus, row_lists, srv)
+        reqs = serve.requests_from_corpus(corpus, row_lists, srv, pinned=True)
         for r in reqs:
             srv.submit(r)
         for r in reqs:

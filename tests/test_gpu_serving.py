@@ -59,6 +59,25 @@ def test_requests_match_oracle(ctx, corpus, mode, slots):
         assert np.array_equal(r.sig, _oracle_sig(corpus, rows, k, seed))
 
 
+def test_index_built_at_creation(ctx, corpus):
+    """build_index: the loop builds the component index before its first request; requests
+    in auto and indexed mode equal the oracle."""
+    k, seed = 40, 5
+    ctx.set_bounds(corpus.m)
+    rng = np.random.Generator(np.random.PCG64(16))
+    row_lists = _rows(rng, corpus.n_rows, [1, 33, 250])
+    for mode in ("auto", "indexed"):
+        print(f"  serving {mode} with the index built at creation", flush=True)
+        with serve.Server(ctx, k, seed=seed, slots=2, mode=mode, build_index=True) as srv:
+            reqs = serve.requests_from_corpus(corpus, row_lists, srv, pinned=True)
+            for r in reqs:
+                srv.submit(r)
+            for r in reqs:
+                srv.wait(r.ticket)
+        for rows, r in zip(row_lists, reqs):
+            assert np.array_equal(r.sig, _oracle_sig(corpus, rows, k, seed))
+
+
 def test_alone_and_in_the_mix_are_identical(ctx, corpus):
     k, seed = 64, 0
     ctx.set_bounds(corpus.m)
@@ -69,7 +88,9 @@ def test_alone_and_in_the_mix_are_identical(ctx, corpus):
         alone = serve.requests_from_corpus(corpus, [probe_rows], srv)[0]
         srv.submit(alone)
         srv.wait(alone.ticket)
-        mix = serve.requests_from_corpus(corpus, others[:4] + [probe_rows] + others[4:], srv)
+        # the mix from page-locked buffers (asynchronous copies), the lone request from pageable
+        mix = serve.requests_from_corpus(corpus, others[:4] + [probe_rows] + others[4:], srv,
+                                         pinned=True)
         for r in mix:
             srv.submit(r)
         srv.drain()
@@ -112,18 +133,40 @@ def test_memory_budget_queues_requests(ctx, corpus):
 
 
 def test_bad_requests_are_refused(ctx, corpus):
+    """row_ptr is checked at submission; the entries on the device, before any walk: such a
+    request completes with the rule's status and leaves its signatures untouched, and the loop
+    goes on serving the requests around it."""
     ctx.set_bounds(corpus.m)
-    with serve.Server(ctx, 8, slots=2) as srv:
-        bad = srv.make_request(np.array([0, 2], np.uint64), np.array([5, 3], np.uint32),
-                               np.array([1, 1], np.uint32))
+    k = 8
+    with serve.Server(ctx, k, slots=2) as srv:
+        broken = srv.make_request(np.array([0, 3, 2], np.uint64), np.array([1, 2, 3], np.uint32),
+                                  np.array([1, 1, 1], np.uint32))
         with pytest.raises(wmh.WMHError) as e:
-            srv.submit(bad)
-        assert e.value.name == "WMH_E_UNSORTED"
+            srv.submit(broken)
+        assert e.value.name == "WMH_E_ROW_PTR"
+        good_rows = [np.arange(0, 5), np.arange(5, 9)]
+        good = serve.requests_from_corpus(corpus, good_rows, srv)
+        unsorted = srv.make_request(np.array([0, 2], np.uint64), np.array([5, 3], np.uint32),
+                                    np.array([1, 1], np.uint32))
         over = srv.make_request(np.array([0, 1], np.uint64), np.array([0], np.uint32),
                                 np.array([int(corpus.m[0]) + 1], np.uint32))
-        with pytest.raises(wmh.WMHError) as e:
-            srv.submit(over)
-        assert e.value.name == "WMH_E_BOUND"
+        far = srv.make_request(np.array([0, 1], np.uint64), np.array([corpus.D], np.uint32),
+                               np.array([1], np.uint32))
+        for r in (unsorted, over, far):
+            r.sig[:] = 777
+        for r in (good[0], unsorted, over, far, good[1]):
+            srv.submit(r)
+        for r, name in ((unsorted, "WMH_E_UNSORTED"), (over, "WMH_E_BOUND"),
+                        (far, "WMH_E_COL_RANGE")):
+            with pytest.raises(wmh.WMHError) as e:
+                srv.wait(r.ticket)
+            assert e.value.name == name
+            assert np.all(r.sig == 777)
+        for rows, r in zip(good_rows, good):
+            srv.wait(r.ticket)
+            assert np.array_equal(r.sig, _oracle_sig(corpus, rows, k, 0))
+        st = srv.stats()
+        assert st["rejected"] == 3 and st["failed"] == 0 and st["completed"] == 2
         # bounds cannot change under a live serving loop
         with pytest.raises(wmh.WMHError) as e:
             ctx.set_bounds(corpus.m)
