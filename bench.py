@@ -229,6 +229,18 @@ def heavy_tail_bench(args, torch, synth, wmh) -> dict:
                 "mean_steps_per_hash": tests / hashes,
                 "walk_frac_of_alu_peak": OPS_PER_TEST * tests / (np.mean(walk_b) / 1e3) / 1e12
                 / PEAK_INT_TOPS})
+    # auto mode: the planner may split the rows between the batched walk and the index
+    sig_a = torch.empty_like(sig_b)
+    timed_steps(ctx, rows, k, sig_a, ctx.make_opts(mode="auto", profile=True), 1, 1, torch)
+    el_a, walk_a, _ = timed_steps(ctx, rows, k, sig_a, ctx.make_opts(mode="auto", profile=True),
+                                  3, 0, torch)
+    out["auto"] = {"mode": ctx.last_mode(), "plan": ctx.last_plan(),
+                   "hashes_per_s": hashes * 3 / el_a, "ms_per_step": el_a / 3 * 1e3,
+                   "kernels_ms": float(np.mean(walk_a)),
+                   "equals_batched": bool(torch.equal(sig_a, sig_b))}
+    log(f"heavy-tail: auto ({out['auto']['mode']}) {out['auto']['ms_per_step']:.2f} ms/step, "
+        f"equal {out['auto']['equals_batched']}")
+    del sig_a
     if args.only == "batched":
         log(f"heavy-tail: batched {out['batched_ms_per_step']:.2f} ms/step")
         ctx.close()

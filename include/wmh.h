@@ -62,7 +62,7 @@ typedef enum {
 
 /* Scheduling of wmh_hash.  Every mode returns identical signatures. */
 typedef enum {
-    WMH_MODE_AUTO = 0,     /* the cheapest of the three below by a cost estimate from the
+    WMH_MODE_AUTO = 0,     /* the cheapest of the four below by a cost estimate from the
                               rows' statistics: expected walk steps min(M / sum x, 65535) per
                               hash (Theorem 2) against the index's nnz + 65534 * k * sum x / M
                               reads (the statistics come from the validation pass, which AUTO
@@ -82,7 +82,14 @@ typedef enum {
                               lists in step order up to a bound T with Pr(any hash > T) <= 1e-4
                               (Theorem 2) and settles any hash id above T in offset order, so
                               the values stay exact.  Needs k <= 8192 and k * 65534 * 16 bytes
-                              of device memory */
+                              of device memory */,
+    WMH_MODE_SPLIT = 4     /* each row on the cheaper of the two: the validation pass classes
+                              every row by its own estimated costs (k * min(M / sum x, 65535)
+                              walk tests against its index keys and list lookups), the batched
+                              walk takes the walk rows (its stream sized for them alone) and
+                              the component index the others.  For batches whose green
+                              fractions spread over orders of magnitude.  Needs what BATCHED
+                              and INDEXED need; the context keeps one byte per row */
 } wmh_mode;
 
 typedef struct {
@@ -217,6 +224,7 @@ wmh_status wmh_bounds_tables(const uint32_t *m, uint32_t D, uint64_t *prefix, ui
  * hipGraph replays (batched with use_graph): *walk_ms spans the whole graph (counter reset
  * and walk) and *stream_ms is 0.  Indexed path: *walk_ms
  * spans the row kernel, *stream_ms the index build when that call built it (else 0).
+ * Split path: *walk_ms spans the walk of the walk rows and the index rows kernel.
  * Requires that call to have completed (opts->sync, or a later synchronization).
  * Errors: WMH_E_ARG (no profiled call yet), WMH_E_DEVICE.
  */
@@ -224,7 +232,8 @@ wmh_status wmh_last_kernel_ms(wmh_ctx *ctx, float *walk_ms, float *stream_ms);
 
 /*
  * wmh_last_mode -- the path the last successful wmh_hash on this context took:
- * WMH_MODE_PLAIN, WMH_MODE_BATCHED or WMH_MODE_INDEXED (WMH_MODE_AUTO before any call).
+ * WMH_MODE_PLAIN, WMH_MODE_BATCHED, WMH_MODE_INDEXED or WMH_MODE_SPLIT (WMH_MODE_AUTO before any
+ * call).
  * Errors: WMH_E_ARG (null).
  */
 wmh_status wmh_last_mode(const wmh_ctx *ctx, int32_t *mode);
@@ -381,8 +390,9 @@ typedef struct {
  * with independent rows and R = 1 with the ballot walk for every W and J, each
  * the best of `reps` (0 = 3) calls after one untimed call, and keeps the
  * fastest in the context under (D, value width, k, step class).  Later wmh_hash calls in the
- * batched or auto mode whose rows fall in the same key and whose plan options are 0 run that
- * plan.  sig (device, N*k uint16) receives the signatures.  Synchronous.
+ * batched, split or auto mode whose plan options are 0 run the plan of their rows' key, or else
+ * of the same (D, width, k) at the nearest step class within two (the walk rows of a split
+ * have a smaller one).  sig (device, N*k uint16) receives the signatures.  Synchronous.
  * Errors: as wmh_hash, plus WMH_E_ARG when no batched plan fits.
  */
 wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
@@ -410,7 +420,8 @@ typedef struct {
     uint64_t seed;         /* key of the random sequence */
     uint64_t mem_budget;   /* device bytes for the admitted requests' rows and signatures
                               ((N+1)*8 + nnz*8 + N*k*2 each); 0 = 4 GiB */
-    int32_t mode;          /* wmh_mode of every request's walk; 0 = auto */
+    int32_t mode;          /* wmh_mode of every request's walk; 0 = auto (a row split is not
+                              available in the loop) */
     uint32_t stream_depth; /* steps of the shared position stream built once at creation;
                               0 = 8192 (steps beyond are drawn in-lane) */
     int32_t build_index;   /* 1: build the component index at creation (auto or indexed mode),

@@ -35,10 +35,13 @@ struct GraphKey {
     uint64_t n_rows = 0, nnz = 0, seed = 0;
     uint32_t k = 0, R = 0, K = 0, J = 0, depth = 0, waves = 0, grid = 0;
     bool narrow = false, packed = false, independent_rows = false, ballot = false;
+    const void *row_class = nullptr;  // row filter of a split walk (nullptr: every row)
+    uint32_t keep = 0;
     uint64_t bounds_epoch = 0;
     bool operator==(const GraphKey &o) const
     {
         return row_ptr == o.row_ptr && col == o.col && val == o.val && sig == o.sig &&
+               row_class == o.row_class && keep == o.keep &&
                n_rows == o.n_rows && nnz == o.nnz && seed == o.seed && k == o.k && R == o.R &&
                K == o.K &&
                J == o.J && depth == o.depth && waves == o.waves && grid == o.grid &&
@@ -56,6 +59,10 @@ struct RowStats {
     uint64_t walk_steps = 0;     // sum over non-empty rows of min(M / sum(x), 65535)
     uint64_t index_keys = 0;     // sum over non-empty rows of the index keys read per hash
     bool keys_known = false;     // index_keys was estimated
+    // row split (per-row classes written to the context's row_class buffer)
+    bool split_known = false;
+    uint64_t walk_rows = 0, walk_min_green = ~0ull, walk_class_steps = 0;
+    uint64_t index_rows = 0, index_nnz = 0, index_class_keys = 0;
 };
 
 // A component index owned by a context or a serving loop, rebuilt when its key changes.
@@ -71,7 +78,7 @@ struct OwnedIndex {
 
 constexpr uint64_t kIndexBudgetBytes = 4ull << 30;  // each key order of the index, at most 4 GiB
 
-enum class Path { kPlain, kBatched, kIndexed };
+enum class Path { kPlain, kBatched, kIndexed, kSplit };
 
 // Autotuned batched plans, per (D, value width, k, step class); step class = floor(log2) of
 // the mean capped step count of the tuned rows.
@@ -116,6 +123,8 @@ struct wmh_ctx {
     // per-call scratch
     wmh::CheckWords *d_check = nullptr;
     wmh::CheckWords *h_check = nullptr;  // pinned
+    uint8_t *d_row_class = nullptr;      // row split: one class byte per row
+    uint64_t row_class_cap = 0;
     uint32_t *d_tile_counter = nullptr;
     unsigned long long *d_codec = nullptr;  // codec counters: saturated values, maximum
     unsigned long long *h_codec = nullptr;  // pinned copy
@@ -154,9 +163,10 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const w
                   BatchedPlan *plan, bool use_tuned = true);
 TuneKey tune_key(const wmh_ctx *ctx, uint32_t k, const RowStats &stats);
 // Validation pass on the device: checks the rows (when check) and fills *stats; waits.
-// want_keys: also estimate index_keys (only the path choice in auto mode reads it)
+// want_keys: also estimate index_keys (only the path choice in auto mode reads it);
+// want_split (with want_keys): also class every row for a row split (ctx->d_row_class).
 wmh_status gather_stats(wmh_ctx *ctx, const Rows &rows, uint32_t k, hipStream_t s, bool check,
-                        bool want_keys, RowStats *stats);
+                        bool want_keys, RowStats *stats, bool want_split = false);
 // Whether an index for k hashes is allowed (k and memory limits).
 bool index_fits(uint32_t k);
 // Makes `ix` the index of (ctx's bounds, seed, k), building it on `stream` when stale.
@@ -165,8 +175,11 @@ bool index_fits(uint32_t k);
 wmh_status ensure_index(wmh_ctx *ctx, OwnedIndex *ix, uint64_t seed, uint32_t k,
                         hipStream_t stream, bool record_error = true);
 void free_index(OwnedIndex *ix);
-// The planner's choice for `mode` (AUTO compares estimated costs; see wmh_mode).
+// The planner's choice for `mode` (AUTO compares estimated costs; see wmh_mode).  split_ok: a
+// batched plan fits for the rows a split would walk (stats.split_known needed).
 Path choose_path(const wmh_ctx *ctx, int mode, bool batched_ok, bool index_ready, uint32_t k,
-                 uint64_t n_rows, uint64_t nnz, const RowStats &stats);
+                 uint64_t n_rows, uint64_t nnz, const RowStats &stats, bool split_ok = false);
+// The statistics of the rows a split walks, as plan_batched reads them.
+RowStats walk_class_stats(const RowStats &stats);
 
 }  // namespace wmh

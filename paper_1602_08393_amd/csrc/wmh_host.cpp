@@ -98,16 +98,26 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const w
     wmh_opts o = o_in;
     if (use_tuned && stats.known && !o.rows_per_block && !o.hashes_per_tile &&
         !o.waves_per_block && !o.walk && !o.steps_per_lane) {
+        // the plan tuned for this key, else for the same (D, width, k) at the nearest step class
+        // within two (a factor of four in mean steps), e.g. the walk rows of a row split
         const TuneKey key = tune_key(ctx, k, stats);
-        for (const TuneEntry &e : ctx->tuned)
-            if (e.key == key) {
-                o.rows_per_block = e.R;
-                o.hashes_per_tile = e.J;
-                o.waves_per_block = e.W;
-                o.walk = e.walk;
-                o.steps_per_lane = e.K;
-                break;
+        const TuneEntry *pick = nullptr;
+        int best = 3;
+        for (const TuneEntry &e : ctx->tuned) {
+            if (e.key.dims != key.dims || e.key.narrow != key.narrow || e.key.k != key.k) continue;
+            const int d = std::abs(e.key.steps_class - key.steps_class);
+            if (d < best) {
+                best = d;
+                pick = &e;
             }
+        }
+        if (pick) {
+            o.rows_per_block = pick->R;
+            o.hashes_per_tile = pick->J;
+            o.waves_per_block = pick->W;
+            o.walk = pick->walk;
+            o.steps_per_lane = pick->K;
+        }
     }
     const uint64_t min_green = stats.known ? stats.min_green : ~0ull;
     BatchedPlan p{};
@@ -164,15 +174,40 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const w
     return true;
 }
 
+// Relative costs in units of one membership test of the batched walk (measured on MI355X:
+// the walk runs about 1.7e12 tests/s; the other figures are per item of the named kind).
+namespace {
+constexpr double kCostPlainDenseStep = 12.0;   // a step of the plain walk, dense row in LDS
+constexpr double kCostPlainSparseStep = 24.0;  // a step of the plain walk, binary search in HBM
+constexpr double kCostPerRowHash = 2.0;        // writing one signature value (either order)
+constexpr double kCostIndexEntry = 64.0;       // building one index key (two draws, sort)
+constexpr double kCostIndexNnz = 64.0;         // a nonzero's list lookup (dependent loads)
+constexpr double kCostIndexKey = 16.0;         // one green key read and its LDS minimum
+}  // namespace
+
 wmh_status gather_stats(wmh_ctx *ctx, const Rows &rows, uint32_t k, hipStream_t s, bool check,
-                        bool want_keys, RowStats *stats)
+                        bool want_keys, RowStats *stats, bool want_split)
 {
-    // first_error and min_green start at ~0, the counters at 0
-    uint32_t *words = reinterpret_cast<uint32_t *>(ctx->d_check);
-    hipError_t e = launch_fill_u32(words, 0xFFFFFFFFu, 4, s);
-    if (e == hipSuccess) e = launch_fill_u32(words + 4, 0u, 6, s);
+    RowSplit split;
+    want_split = want_split && want_keys;
+    if (want_split) {
+        if (ctx->row_class_cap < rows.n_rows) {
+            if (ctx->d_row_class) hipFree(ctx->d_row_class);
+            ctx->d_row_class = nullptr;
+            ctx->row_class_cap = 0;  // a captured split walk keys on the buffer's address
+            const hipError_t ae = hipMalloc(&ctx->d_row_class, std::max<uint64_t>(rows.n_rows, 1));
+            if (ae != hipSuccess) return device_fail(ctx, ae, "row class buffer");
+            ctx->row_class_cap = rows.n_rows;
+        }
+        split.row_class = ctx->d_row_class;
+        split.k = k;
+        split.key_cost = (float)kCostIndexKey;
+        split.nnz_cost = (float)kCostIndexNnz;
+    }
+    hipError_t e = launch_check_init(ctx->d_check, s);
     if (e == hipSuccess)
-        e = launch_validate(rows, ctx->d_bound, ctx->dims, ctx->total, k, want_keys, ctx->d_check, s);
+        e = launch_validate(rows, ctx->d_bound, ctx->dims, ctx->total, k, want_keys, ctx->d_check, s,
+                            want_split ? &split : nullptr);
     if (e == hipSuccess)
         e = hipMemcpyAsync(ctx->h_check, ctx->d_check, sizeof(CheckWords), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -190,7 +225,26 @@ wmh_status gather_stats(wmh_ctx *ctx, const Rows &rows, uint32_t k, hipStream_t 
     stats->walk_steps = v.walk_steps;
     stats->index_keys = v.index_keys;
     stats->keys_known = want_keys;
+    stats->split_known = want_split;
+    if (want_split) {
+        stats->walk_rows = v.walk_rows;
+        stats->walk_min_green = v.walk_min_green;
+        stats->walk_class_steps = v.walk_class_steps;
+        stats->index_rows = v.index_rows;
+        stats->index_nnz = v.index_nnz;
+        stats->index_class_keys = v.index_class_keys;
+    }
     return WMH_OK;
+}
+
+RowStats walk_class_stats(const RowStats &stats)
+{
+    RowStats w;
+    w.known = stats.known;
+    w.nonempty = stats.walk_rows;  // empty rows included: a bound for the mean step count
+    w.min_green = stats.walk_min_green;
+    w.walk_steps = stats.walk_class_steps;
+    return w;
 }
 
 bool index_fits(uint32_t k)
@@ -257,34 +311,33 @@ wmh_status ensure_index(wmh_ctx *ctx, OwnedIndex *ix, uint64_t seed, uint32_t k,
     return WMH_OK;
 }
 
-// Relative costs in units of one membership test of the batched walk (measured on MI355X:
-// the walk runs about 1.7e12 tests/s; the other figures are per item of the named kind).
-namespace {
-constexpr double kCostPlainDenseStep = 12.0;   // a step of the plain walk, dense row in LDS
-constexpr double kCostPlainSparseStep = 24.0;  // a step of the plain walk, binary search in HBM
-constexpr double kCostPerRowHash = 2.0;        // writing one signature value (either order)
-constexpr double kCostIndexEntry = 64.0;       // building one index key (two draws, sort)
-constexpr double kCostIndexNnz = 64.0;         // a nonzero's list lookup (dependent loads)
-constexpr double kCostIndexKey = 16.0;         // one green key read and its LDS minimum
-}  // namespace
-
 Path choose_path(const wmh_ctx *ctx, int mode, bool batched_ok, bool index_ready, uint32_t k,
-                 uint64_t n_rows, uint64_t nnz, const RowStats &stats)
+                 uint64_t n_rows, uint64_t nnz, const RowStats &stats, bool split_ok)
 {
     if (mode == WMH_MODE_PLAIN) return Path::kPlain;
     if (mode == WMH_MODE_BATCHED) return Path::kBatched;
     if (mode == WMH_MODE_INDEXED) return Path::kIndexed;
+    if (mode == WMH_MODE_SPLIT) return Path::kSplit;
     const Path walk_path = batched_ok ? Path::kBatched : Path::kPlain;
     if (!stats.known || !stats.keys_known || !index_fits(k)) return walk_path;
     const bool narrow = ctx->max_bound <= 0xFFFFu;
     const bool dense = (size_t)4 * ctx->dims * (narrow ? 2 : 4) <= 64 * 1024;
     const double step = batched_ok ? 1.0 : (dense ? kCostPlainDenseStep : kCostPlainSparseStep);
     const double walk = (double)k * ((double)stats.walk_steps * step + kCostPerRowHash * n_rows);
-    const double index = (index_ready ? 0.0 : (double)index_entry_count(k) * kCostIndexEntry) +
-                         (double)nnz * kCostIndexNnz +
+    const double build = index_ready ? 0.0 : (double)index_entry_count(k) * kCostIndexEntry;
+    const double index = build + (double)nnz * kCostIndexNnz +
                          (double)k * ((double)stats.index_keys * kCostIndexKey +
                                       kCostPerRowHash * n_rows);
-    return index < walk ? Path::kIndexed : walk_path;
+    const Path best = index < walk ? Path::kIndexed : walk_path;
+    if (!split_ok || !stats.split_known || stats.walk_rows == 0 || stats.index_rows == 0)
+        return best;
+    // each row on its cheaper path: the batched walk for one class, the index for the other
+    const double split =
+        (double)k * ((double)stats.walk_class_steps + kCostPerRowHash * stats.walk_rows) + build +
+        (double)stats.index_nnz * kCostIndexNnz +
+        (double)k * ((double)stats.index_class_keys * kCostIndexKey +
+                     kCostPerRowHash * stats.index_rows);
+    return split < std::min(walk, index) ? Path::kSplit : best;
 }
 
 }  // namespace wmh
@@ -406,6 +459,7 @@ void wmh_destroy(wmh_ctx *ctx)
     free_index(&ctx->index);
     if (ctx->d_stream) hipFree(ctx->d_stream);
     if (ctx->d_check) hipFree(ctx->d_check);
+    if (ctx->d_row_class) hipFree(ctx->d_row_class);
     if (ctx->h_check) hipHostFree(ctx->h_check);
     if (ctx->d_tile_counter) hipFree(ctx->d_tile_counter);
     if (ctx->d_codec) hipFree(ctx->d_codec);
@@ -530,9 +584,9 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
     wmh_opts o;
     if (opts) o = *opts;
     else wmh_opts_init(&o);
-    if (o.mode < WMH_MODE_AUTO || o.mode > WMH_MODE_INDEXED)
+    if (o.mode < WMH_MODE_AUTO || o.mode > WMH_MODE_SPLIT)
         return fail(ctx, WMH_E_ARG, "unknown mode %d", o.mode);
-    if (o.mode == WMH_MODE_INDEXED && !index_fits(k))
+    if ((o.mode == WMH_MODE_INDEXED || o.mode == WMH_MODE_SPLIT) && !index_fits(k))
         return fail(ctx, WMH_E_ARG, "the component index needs k <= %u", kIndexMaxK);
     WMH_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t s = pick_stream(ctx, stream);
@@ -542,9 +596,13 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
     RowStats stats;
     const bool profile = o.profile != 0;
     ctx->profiled = false;
-    if (o.validate || o.mode == WMH_MODE_AUTO) {
-        const bool want_keys = o.mode == WMH_MODE_AUTO && index_fits(k);
-        const wmh_status st = gather_stats(ctx, rows, k, s, o.validate != 0, want_keys, &stats);
+    const bool split_mode = o.mode == WMH_MODE_SPLIT;
+    if (o.validate || o.mode == WMH_MODE_AUTO || split_mode) {
+        const bool want_keys = (o.mode == WMH_MODE_AUTO || split_mode) && index_fits(k);
+        // the row classes of a split (not with the independent-rows walk, which has no filter)
+        const bool want_split = want_keys && o.walk != 2;
+        const wmh_status st =
+            gather_stats(ctx, rows, k, s, o.validate != 0, want_keys, &stats, want_split);
         if (st != WMH_OK) return st;
     }
 
@@ -553,10 +611,23 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
                             plan_batched(ctx, k, stats, o, &plan);
     if (o.mode == WMH_MODE_BATCHED && !batched_ok)
         return fail(ctx, WMH_E_ARG, "no batched plan fits for D=%u with these options", ctx->dims);
+    // a split walks one class with a plan sized for that class alone
+    BatchedPlan split_plan{};
+    const bool split_ok = stats.split_known && stats.walk_rows && stats.index_rows &&
+                          plan_batched(ctx, k, walk_class_stats(stats), o, &split_plan) &&
+                          !split_plan.independent_rows;
     const bool index_ready = ctx->index.valid && ctx->index.seed == seed && ctx->index.k == k &&
                              ctx->index.epoch == ctx->bounds_epoch;
-    const Path path = choose_path(ctx, o.mode, batched_ok, index_ready, k, n_rows, nnz, stats);
-    const bool batched = path == Path::kBatched;
+    Path path = choose_path(ctx, o.mode, batched_ok, index_ready, k, n_rows, nnz, stats, split_ok);
+    if (path == Path::kSplit && !split_ok) {
+        // a forced split whose rows all fall on one side runs that side alone
+        if (stats.index_rows == 0 && plan_batched(ctx, k, stats, o, &plan) && !plan.independent_rows)
+            path = Path::kBatched;
+        else if (stats.walk_rows == 0)
+            path = Path::kIndexed;
+        else
+            return fail(ctx, WMH_E_ARG, "no batched plan fits for the walk rows of a split");
+    }
 
     if (path == Path::kIndexed) {
         if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[0], s));
@@ -574,7 +645,7 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         return WMH_OK;
     }
 
-    if (!batched) {
+    if (path == Path::kPlain) {
         const bool narrow = ctx->max_bound <= 0xFFFFu;
         const bool dense = (size_t)4 * ctx->dims * (narrow ? 2 : 4) <= 64 * 1024;
         const uint64_t step = o.batch_rows ? o.batch_rows : 8192;
@@ -586,39 +657,48 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[2], s));
         ctx->profiled = profile;
         ctx->profiled_stream = false;
-    } else {
+        ctx->last_mode = WMH_MODE_PLAIN;
+        ctx->last_plan = BatchedPlan{};
+        if (o.sync) WMH_HIP(ctx, hipStreamSynchronize(s));
+        return WMH_OK;
+    }
+
+    // The batched walk of `wrows` (every row, or the walk class of a split) under plan `pl`.
+    auto run_batched = [&](const Rows &wrows, const BatchedPlan &pl) -> wmh_status {
         {
-            wmh_status st = ensure_stream_capacity(ctx, plan.stream_bytes(k));
+            wmh_status st = ensure_stream_capacity(ctx, pl.stream_bytes(k));
             if (st != WMH_OK) return st;
         }
-        const int per_cu = std::max(1, batched_blocks_per_cu(ctx->dims, plan));
-        const uint64_t n_blocks = (n_rows + plan.rows_per_block - 1) / plan.rows_per_block;
+        const int per_cu = std::max(1, batched_blocks_per_cu(ctx->dims, pl));
+        const uint64_t n_blocks = (n_rows + pl.rows_per_block - 1) / pl.rows_per_block;
         const uint64_t n_tiles =
-            n_blocks * ((k + plan.hashes_per_tile - 1) / plan.hashes_per_tile);
+            n_blocks * ((k + pl.hashes_per_tile - 1) / pl.hashes_per_tile);
         const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)ctx->cu_count * per_cu, n_tiles);
 
         GraphKey key;
         key.row_ptr = row_ptr; key.col = col; key.val = val; key.sig = sig;
         key.n_rows = n_rows; key.nnz = nnz; key.seed = seed; key.k = k;
-        key.R = plan.rows_per_block; key.J = plan.hashes_per_tile; key.depth = plan.stream_depth;
-        key.K = plan.steps_per_lane;
-        key.waves = plan.waves_per_block; key.grid = grid; key.narrow = plan.narrow;
-        key.packed = plan.packed;
-        key.independent_rows = plan.independent_rows;
-        key.ballot = plan.ballot;
+        key.R = pl.rows_per_block; key.J = pl.hashes_per_tile; key.depth = pl.stream_depth;
+        key.K = pl.steps_per_lane;
+        key.waves = pl.waves_per_block; key.grid = grid; key.narrow = pl.narrow;
+        key.packed = pl.packed;
+        key.independent_rows = pl.independent_rows;
+        key.ballot = pl.ballot;
+        key.row_class = wrows.row_class;
+        key.keep = wrows.keep;
         key.bounds_epoch = ctx->bounds_epoch;
 
         // The shared position stream (cached position stream): built once per (seed, k,
         // depth, entry layout, bounds) and kept for later calls, which wait for its build.
         bool stream_built = false;
-        if (plan.stream_depth) {
-            const StreamKey skey{seed, k, plan.stream_depth, plan.scale(), plan.packed,
+        if (pl.stream_depth) {
+            const StreamKey skey{seed, k, pl.stream_depth, pl.scale(), pl.packed,
                                  ctx->bounds_epoch};
             if (!(ctx->stream_valid && ctx->stream_key == skey)) {
                 ctx->stream_valid = false;
                 if (profile && !o.use_graph) WMH_HIP(ctx, hipEventRecord(ctx->ev[0], s));
-                WMH_HIP(ctx, launch_stream_build(b, seed, k, plan.stream_depth, plan.packed,
-                                                 plan.scale(), ctx->d_stream, s));
+                WMH_HIP(ctx, launch_stream_build(b, seed, k, pl.stream_depth, pl.packed,
+                                                 pl.scale(), ctx->d_stream, s));
                 WMH_HIP(ctx, hipEventRecord(ctx->stream_ready, s));
                 ctx->stream_key = skey;
                 ctx->stream_valid = true;
@@ -633,7 +713,7 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
             hipError_t e = launch_fill_u32(ctx->d_tile_counter, 0u, 1, q);
             if (e != hipSuccess) return e;
             if (events && (e = hipEventRecord(ctx->ev[1], q)) != hipSuccess) return e;
-            e = launch_batched(b, rows, k, seed, sig, plan, ctx->d_stream, ctx->d_tile_counter,
+            e = launch_batched(b, wrows, k, seed, sig, pl, ctx->d_stream, ctx->d_tile_counter,
                                grid, q);
             if (e != hipSuccess) return e;
             if (events) e = hipEventRecord(ctx->ev[2], q);
@@ -669,10 +749,38 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
             if (e != hipSuccess) return device_fail(ctx, e, "batched launch");
             ctx->profiled_stream = profile && stream_built;
         }
+        return WMH_OK;
+    };
+
+    if (path == Path::kSplit) {
+        // the index first (built once per bounds, seed and k), then the walk rows, then the
+        // index rows; each kernel leaves the other class's signatures untouched
+        {
+            const wmh_status st = ensure_index(ctx, &ctx->index, seed, k, s);
+            if (st != WMH_OK) return st;
+        }
+        Rows walk_rows = rows, index_rows = rows;
+        walk_rows.row_class = index_rows.row_class = ctx->d_row_class;
+        walk_rows.keep = 0;
+        index_rows.keep = 1;
+        const wmh_status st = run_batched(walk_rows, split_plan);
+        if (st != WMH_OK) return st;
+        const uint32_t grid = (uint32_t)ctx->cu_count * (uint32_t)index_rows_blocks_per_cu(k);
+        WMH_HIP(ctx, launch_index_rows(index_rows, ctx->index.buf, b, k, sig, grid, s));
+        if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[2], s));  // walk_ms spans both
+        WMH_HIP(ctx, hipEventRecord(ctx->index.used, s));
         ctx->profiled = profile;
+        ctx->last_mode = WMH_MODE_SPLIT;
+        ctx->last_plan = split_plan;
+        if (o.sync) WMH_HIP(ctx, hipStreamSynchronize(s));
+        return WMH_OK;
     }
-    ctx->last_mode = batched ? WMH_MODE_BATCHED : WMH_MODE_PLAIN;
-    ctx->last_plan = batched ? plan : BatchedPlan{};
+
+    const wmh_status st = run_batched(rows, plan);
+    if (st != WMH_OK) return st;
+    ctx->profiled = profile;
+    ctx->last_mode = WMH_MODE_BATCHED;
+    ctx->last_plan = plan;
     if (o.sync) WMH_HIP(ctx, hipStreamSynchronize(s));
     return WMH_OK;
 }
@@ -694,7 +802,7 @@ wmh_status wmh_last_plan(const wmh_ctx *ctx, wmh_opts *plan)
     plan->stream_depth = ctx->last_plan.stream_depth;
     plan->steps_per_lane = ctx->last_plan.steps_per_lane;
     plan->waves_per_block = ctx->last_plan.waves_per_block;
-    plan->walk = ctx->last_mode != WMH_MODE_BATCHED ? 0
+    plan->walk = ctx->last_mode != WMH_MODE_BATCHED && ctx->last_mode != WMH_MODE_SPLIT ? 0
                  : ctx->last_plan.ballot           ? 3
                  : ctx->last_plan.independent_rows ? 2
                                                    : 1;

@@ -292,6 +292,7 @@ __global__ __launch_bounds__(256) void index_rows_kernel(Rows rows,
     uint32_t *hmin = lds + (size_t)wave * k;
     for (uint64_t row = (uint64_t)blockIdx.x * waves + wave; row < rows.n_rows;
          row += (uint64_t)gridDim.x * waves) {
+        if (rows.skips(row)) continue;  // a row another path computes (row filter)
         for (uint32_t j = ln; j < k; j += kWave) hmin[j] = kCap;
         wave_lds_fence();
         const uint64_t lo = rows.row_ptr[row], hi = rows.row_ptr[row + 1];

@@ -19,11 +19,30 @@ enum : uint32_t {
 
 // Device words written by the validation kernel (one allocation, reset before each launch).
 struct CheckWords {
-    unsigned long long first_error;  // (row << 4) | code, minimum over rows; ~0 when valid
-    unsigned long long min_green;    // smallest sum(x) over non-empty rows; ~0 if none
-    unsigned long long n_empty;      // rows with sum(x) == 0
-    unsigned long long walk_steps;   // sum over non-empty rows of min(M / sum(x), 65535)
-    unsigned long long index_keys;   // sum over non-empty rows of the index keys read per hash
+    // minima, starting at ~0 (the first kCheckMinima words)
+    unsigned long long first_error;      // (row << 4) | code, minimum over rows; ~0 when valid
+    unsigned long long min_green;        // smallest sum(x) over non-empty rows; ~0 if none
+    unsigned long long walk_min_green;   // row split: smallest sum(x) of the walk's rows
+    // counters, starting at 0
+    unsigned long long n_empty;          // rows with sum(x) == 0
+    unsigned long long walk_steps;       // sum over non-empty rows of min(M / sum(x), 65535)
+    unsigned long long index_keys;       // sum over non-empty rows of the index keys per hash
+    unsigned long long walk_rows;        // row split: rows classed for the walk (empty ones too)
+    unsigned long long walk_class_steps; // row split: their expected walk steps
+    unsigned long long index_rows;       // row split: rows classed for the index
+    unsigned long long index_nnz;        // row split: their nonzeros
+    unsigned long long index_class_keys; // row split: their index keys per hash
+};
+constexpr uint32_t kCheckMinima = 3;
+
+// Row split: the validation pass writes row_class[r] = 1 for rows whose estimated cost on the
+// component index (k * keys * key_cost + nnz * nnz_cost) is below their walk's (k * steps, in
+// units of one walk test), else 0.
+struct RowSplit {
+    uint8_t *row_class = nullptr;
+    uint32_t k = 0;
+    float key_cost = 0.f;
+    float nnz_cost = 0.f;
 };
 
 struct Rows {
@@ -32,6 +51,12 @@ struct Rows {
     const uint32_t *val;
     uint64_t n_rows;
     uint64_t nnz;
+    // optional row filter: with row_class set, kernels that honour it (the shared-window and
+    // ballot walks, the index rows) process only rows r with row_class[r] == keep and leave
+    // the other rows' signatures untouched
+    const uint8_t *row_class = nullptr;
+    uint32_t keep = 0;
+    __host__ __device__ bool skips(uint64_t r) const { return row_class && row_class[r] != keep; }
 };
 
 // One shared-stream entry: the component c and the offset inside it of one step's position.
@@ -73,8 +98,10 @@ struct BatchedPlan {
 
 // Checks the rows and gathers the statistics of CheckWords (M = total, for the cost estimates);
 // index_keys only with want_keys (it is left at 0 otherwise).
+// With split (want_keys must be set) it also classes every row and fills the per-class words.
 hipError_t launch_validate(const Rows &rows, const uint32_t *bound, uint32_t dims, uint64_t total,
-                           uint32_t k, bool want_keys, CheckWords *words, hipStream_t stream);
+                           uint32_t k, bool want_keys, CheckWords *words, hipStream_t stream,
+                           const RowSplit *split = nullptr);
 
 hipError_t launch_plain(const Bounds &b, const Rows &rows, uint64_t row_begin,
                         uint64_t row_end, uint32_t k, uint64_t seed, uint16_t *sig, bool narrow,
@@ -117,6 +144,8 @@ hipError_t launch_collisions(const uint16_t *A, uint64_t na, const uint16_t *B, 
                              uint32_t k, uint32_t *counts, hipStream_t stream);
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t stream);
+// Starting values of the validation pass's words (minima ~0, counters 0).
+hipError_t launch_check_init(CheckWords *words, hipStream_t stream);
 
 // Component index of the capped sequence (wmh_index.hip).  entries: k * 65534 keys
 // (offset << 32) | (t << 16) | j grouped by component (by_step: the same lists in step order);

@@ -82,11 +82,15 @@ __device__ __forceinline__ uint64_t wave_min(uint64_t v)
 template <bool kKeys, bool kLdsBounds>
 __global__ __launch_bounds__(1024) void validate_kernel(Rows rows, const uint32_t *__restrict__ bound_in,
                                                         uint32_t dims, uint64_t total,
-                                                        double log_eps, CheckWords *words)
+                                                        double log_eps, CheckWords *words,
+                                                        RowSplit split)
 {
     // per-workgroup partials, so each word gets at most one global atomic per workgroup
     __shared__ unsigned long long part_err[1024 / kWave], part_green[1024 / kWave],
         part_empty[1024 / kWave], part_walk[1024 / kWave], part_keys[1024 / kWave];
+    // the per-class words of a row split: walk min green, walk rows, walk steps, index rows,
+    // index nonzeros, index keys
+    __shared__ unsigned long long part_split[6][1024 / kWave];
     // kLdsBounds: the workgroup first copies the bounds to LDS, so the check val <= m[col]
     // gathers from LDS instead of memory
     extern __shared__ uint32_t lds_bound[];
@@ -101,6 +105,8 @@ __global__ __launch_bounds__(1024) void validate_kernel(Rows rows, const uint32_
     const uint64_t stride = (uint64_t)gridDim.x * waves;
     uint64_t w_err = ~0ull, w_green = ~0ull, w_empty = 0;  // this wave's partials (uniform)
     uint64_t w_walk = 0, w_keys = 0;  // cost statistics: expected walk steps, green index keys
+    uint64_t w_split[6] = {~0ull, 0, 0, 0, 0, 0};  // per-class statistics (row split)
+    const bool classify = kKeys && split.row_class != nullptr;
     // M / sum(x) in double is exact after flooring while M < 2^53 (the rounding error of the
     // quotient stays below the distance 1 / sum(x) to the next integer)
     const bool exact_double = total < (1ull << 53);
@@ -157,6 +163,10 @@ __global__ __launch_bounds__(1024) void validate_kernel(Rows rows, const uint32_
         sum = wave_sum(sum);
         if (sum == 0) {
             ++w_empty;
+            if (classify) {
+                ++w_split[1];  // empty rows go with the walk (signature 0)
+                if (lane() == 0) split.row_class[r] = 0;
+            }
             continue;
         }
         w_green = min(w_green, (unsigned long long)sum);
@@ -171,7 +181,27 @@ __global__ __launch_bounds__(1024) void validate_kernel(Rows rows, const uint32_
             const double T = s >= 1.0 ? 1.0 : ceil(log_eps / log1p(-s));
             const double by_offset = 65534.0 * s;
             const double by_step = T < 65534.0 ? T * ((double)sum_m / (double)total) : by_offset;
-            w_keys += (uint64_t)ceil(min(by_offset, by_step));
+            const uint64_t keys = (uint64_t)ceil(min(by_offset, by_step));
+            w_keys += keys;
+            if (classify) {
+                // in units of one walk test: the walk's k * steps against the index's keys and
+                // the nonzeros' list lookups
+                const uint64_t steps = min(q, (uint64_t)kCap);
+                const double walk_cost = (double)split.k * (double)steps;
+                const double index_cost = (double)split.k * (double)keys * split.key_cost +
+                                          (double)(hi - lo) * split.nnz_cost;
+                const bool to_index = index_cost < walk_cost;
+                if (lane() == 0) split.row_class[r] = to_index ? 1 : 0;
+                if (to_index) {
+                    ++w_split[3];
+                    w_split[4] += hi - lo;
+                    w_split[5] += keys;
+                } else {
+                    w_split[0] = min(w_split[0], sum);
+                    ++w_split[1];
+                    w_split[2] += steps;
+                }
+            }
         }
     }
     const uint32_t wave = wave_index();
@@ -181,6 +211,7 @@ __global__ __launch_bounds__(1024) void validate_kernel(Rows rows, const uint32_
         part_empty[wave] = w_empty;
         part_walk[wave] = w_walk;
         part_keys[wave] = w_keys;
+        for (int i = 0; i < 6; ++i) part_split[i][wave] = w_split[i];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -197,6 +228,19 @@ __global__ __launch_bounds__(1024) void validate_kernel(Rows rows, const uint32_
         if (n) atomicAdd(&words->n_empty, n);
         if (wk) atomicAdd(&words->walk_steps, wk);
         if (ky) atomicAdd(&words->index_keys, ky);
+        if (classify) {
+            unsigned long long t[6] = {~0ull, 0, 0, 0, 0, 0};
+            for (uint32_t w = 0; w < waves; ++w) {
+                t[0] = min(t[0], part_split[0][w]);
+                for (int i = 1; i < 6; ++i) t[i] += part_split[i][w];
+            }
+            if (t[0] != ~0ull) atomicMin(&words->walk_min_green, t[0]);
+            if (t[1]) atomicAdd(&words->walk_rows, t[1]);
+            if (t[2]) atomicAdd(&words->walk_class_steps, t[2]);
+            if (t[3]) atomicAdd(&words->index_rows, t[3]);
+            if (t[4]) atomicAdd(&words->index_nnz, t[4]);
+            if (t[5]) atomicAdd(&words->index_class_keys, t[5]);
+        }
     }
 }
 
@@ -558,8 +602,11 @@ __global__ __launch_bounds__(256) void estimate_kernel(const uint16_t *__restric
 // ---------------------------------------------------------------------------------------------
 
 hipError_t launch_validate(const Rows &rows, const uint32_t *bound, uint32_t dims, uint64_t total,
-                           uint32_t k, bool want_keys, CheckWords *words, hipStream_t stream)
+                           uint32_t k, bool want_keys, CheckWords *words, hipStream_t stream,
+                           const RowSplit *split)
 {
+    const RowSplit sp = split ? *split : RowSplit{};
+    if (sp.row_class && !want_keys) return hipErrorInvalidValue;
     if (rows.n_rows == 0) return hipSuccess;
     const double log_eps = std::log(1e-4 / (double)k);  // the index's failure bound per row
     // bounds in LDS up to 76 KB: two workgroups of 16 wavefronts per CU keep it fully
@@ -583,11 +630,11 @@ hipError_t launch_validate(const Rows &rows, const uint32_t *bound, uint32_t dim
                                                        8192 / per_block);
     const size_t shm = lds ? (size_t)dims * 4 : 0;
     if (want_keys) {
-        if (lds) validate_kernel<true, true><<<grid, threads, shm, stream>>>(rows, bound, dims, total, log_eps, words);
-        else validate_kernel<true, false><<<grid, threads, 0, stream>>>(rows, bound, dims, total, log_eps, words);
+        if (lds) validate_kernel<true, true><<<grid, threads, shm, stream>>>(rows, bound, dims, total, log_eps, words, sp);
+        else validate_kernel<true, false><<<grid, threads, 0, stream>>>(rows, bound, dims, total, log_eps, words, sp);
     } else {
-        if (lds) validate_kernel<false, true><<<grid, threads, shm, stream>>>(rows, bound, dims, total, log_eps, words);
-        else validate_kernel<false, false><<<grid, threads, 0, stream>>>(rows, bound, dims, total, log_eps, words);
+        if (lds) validate_kernel<false, true><<<grid, threads, shm, stream>>>(rows, bound, dims, total, log_eps, words, sp);
+        else validate_kernel<false, false><<<grid, threads, 0, stream>>>(rows, bound, dims, total, log_eps, words, sp);
     }
     return hipGetLastError();
 }
@@ -730,6 +777,15 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t 
     if (n == 0) return hipSuccess;
     fill_u32_kernel<<<(uint32_t)((n + 255) / 256), 256, 0, stream>>>(p, value, n);
     return hipGetLastError();
+}
+
+hipError_t launch_check_init(CheckWords *words, hipStream_t stream)
+{
+    uint32_t *w = reinterpret_cast<uint32_t *>(words);
+    constexpr uint32_t kMinWords = 2 * kCheckMinima;
+    hipError_t e = launch_fill_u32(w, 0xFFFFFFFFu, kMinWords, stream);
+    if (e == hipSuccess) e = launch_fill_u32(w + kMinWords, 0u, sizeof(CheckWords) / 4 - kMinWords, stream);
+    return e;
 }
 
 }  // namespace wmh

@@ -146,10 +146,8 @@ wmh_status wmh_server::launch_check(Slot &slot, Request &r)
     const Rows rows{slot.d_row_ptr, slot.d_col, slot.d_val, r.n_rows, r.nnz};
     // first_error and min_green start at ~0, the counters at 0 (as in wmh_hash's pass); the
     // index-key estimate only when the planner may take the index
-    uint32_t *words = reinterpret_cast<uint32_t *>(slot.d_check);
     const bool want_keys = cfg.mode == WMH_MODE_AUTO && index_fits(cfg.k);
-    if (e == hipSuccess) e = launch_fill_u32(words, 0xFFFFFFFFu, 4, s);
-    if (e == hipSuccess) e = launch_fill_u32(words + 4, 0u, 6, s);
+    if (e == hipSuccess) e = launch_check_init(slot.d_check, s);
     if (e == hipSuccess)
         e = launch_validate(rows, ctx->d_bound, ctx->dims, ctx->total, k, want_keys, slot.d_check, s);
     if (e == hipSuccess)

@@ -67,10 +67,12 @@ __host__ __device__ constexpr uint64_t segment_tops()
 }
 
 // Zeroes the LDS rows of a block, then scatters its n_here CSR rows (RowLayout) and sets bit r
-// of *nonempty for every row r with a nonzero value.  Called by the whole workgroup.
+// of *nonempty for every row r with a nonzero value; rows with bit r of `skip` stay zero.
+// Called by the whole workgroup.
 template <typename XT, int R>
 __device__ __forceinline__ void stage_block(unsigned char *smem, const Rows &rows, uint64_t row0,
-                                            uint32_t n_here, uint32_t D, uint32_t *nonempty)
+                                            uint32_t n_here, uint32_t D, uint32_t *nonempty,
+                                            uint32_t skip = 0)
 {
     using Layout = RowLayout<XT, R>;
     uint32_t *xz = reinterpret_cast<uint32_t *>(smem);
@@ -80,6 +82,7 @@ __device__ __forceinline__ void stage_block(unsigned char *smem, const Rows &row
     __syncthreads();
     uint32_t mine = 0;
     for (uint32_t r = 0; r < n_here; ++r) {
+        if ((skip >> r) & 1u) continue;
         const uint64_t lo = rows.row_ptr[row0 + r], hi = rows.row_ptr[row0 + r + 1];
         for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
             const uint32_t v = rows.val[e];
@@ -93,14 +96,17 @@ __device__ __forceinline__ void stage_block(unsigned char *smem, const Rows &row
 }
 
 // Writes a tile's hash values (staged in LDS, row r at hbuf[r * hashes_per_tile]) row by row,
-// coalesced along j.  Called by the whole workgroup; ends with a barrier.
+// coalesced along j, except rows with bit r of `skip`.  Called by the whole workgroup; ends
+// with a barrier.
 __device__ __forceinline__ void write_tile(uint16_t *__restrict__ sig, const uint16_t *hbuf,
                                            uint64_t row0, uint32_t n_here, uint32_t k,
-                                           uint32_t j0, uint32_t j1, uint32_t hashes_per_tile)
+                                           uint32_t j0, uint32_t j1, uint32_t hashes_per_tile,
+                                           uint32_t skip = 0)
 {
     __syncthreads();
     const uint32_t width = j1 - j0;
     for (uint32_t r = 0; r < n_here; ++r) {
+        if ((skip >> r) & 1u) continue;
         uint16_t *out = sig + (row0 + r) * (uint64_t)k + j0;
         for (uint32_t q = threadIdx.x; q < width; q += blockDim.x) out[q] = hbuf[r * hashes_per_tile + q];
     }
@@ -158,9 +164,17 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
         const uint32_t ht = (uint32_t)(tile - blk * n_hash_tiles);
         const uint64_t row0 = blk * R;
         const uint32_t n_here = (uint32_t)min((uint64_t)R, rows.n_rows - row0);
+        // rows another path computes (row filter): not staged, not walked, not written
+        uint32_t skip = 0;
+        if (rows.row_class)
+            for (uint32_t r = 0; r < n_here; ++r) skip |= rows.skips(row0 + r) ? 1u << r : 0u;
+        if (skip == (1u << n_here) - 1u) {
+            __syncthreads();  // every thread has read tile_slot before it is claimed again
+            continue;
+        }
 
         if (blk != staged) {
-            stage_block<XT, R>(smem, rows, row0, n_here, D, &nonempty);
+            stage_block<XT, R>(smem, rows, row0, n_here, D, &nonempty, skip);
             staged = blk;
         }
         // Wave-uniform values are read into scalar registers so every branch on them is a
@@ -277,7 +291,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
                                                   : R * hashes_per_tile + lane();
             hbuf[slot] = (uint16_t)h;
         }
-        write_tile(sig, hbuf, row0, n_here, k, j0, j1, hashes_per_tile);
+        write_tile(sig, hbuf, row0, n_here, k, j0, j1, hashes_per_tile, skip);
     }
 }
 
@@ -317,6 +331,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         if (tile >= n_tiles) break;
         const uint64_t row = tile / n_hash_tiles;
         const uint32_t ht = (uint32_t)(tile - row * n_hash_tiles);
+        if (rows.skips(row)) {  // a row another path computes (row filter)
+            __syncthreads();    // every thread has read tile_slot before it is claimed again
+            continue;
+        }
         if (row != staged) {
             stage_block<XT, 1>(smem, rows, row, 1u, D, &nonempty);
             staged = row;

@@ -19,7 +19,7 @@ CAP = 65535
 STATUS = {0: "WMH_OK", -1: "WMH_E_ARG", -2: "WMH_E_NO_BOUNDS", -3: "WMH_E_COL_RANGE",
           -4: "WMH_E_UNSORTED", -5: "WMH_E_BOUND", -6: "WMH_E_OVERFLOW", -7: "WMH_E_NOMEM",
           -8: "WMH_E_DEVICE", -9: "WMH_E_ROW_PTR"}
-MODES = {"auto": 0, "plain": 1, "batched": 2, "indexed": 3}
+MODES = {"auto": 0, "plain": 1, "batched": 2, "indexed": 3, "split": 4}
 WALKS = {"auto": 0, "shared": 1, "rows": 2, "ballot": 3}
 
 EXPORTED = ["wmh_opts_init", "wmh_create", "wmh_destroy", "wmh_set_bounds", "wmh_hash",
@@ -357,7 +357,8 @@ class Context:
         return w.value, st.value
 
     def last_mode(self) -> str:
-        """Name of the path ("plain", "batched", "indexed") the last wmh_hash call took."""
+        """Name of the path ("plain", "batched", "indexed", "split") the last wmh_hash call
+        took."""
         m = ctypes.c_int32()
         self._check(self._lib.wmh_last_mode(self._ptr, ctypes.byref(m)), "wmh_last_mode")
         return {v: k for k, v in MODES.items()}[m.value]
