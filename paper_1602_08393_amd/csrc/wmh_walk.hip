@@ -297,12 +297,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
 
 
 // ---------------------------------------------------------------------------------------------
-// Ballot walk: one row per block (R = 1), one hash id per wavefront, lane l testing step
-// base + l + 1 of each 64-step window.  Lanes follow the steps in order, so the row's first
+// Ballot walk: one row per block (R = 1), one hash id at a time per wavefront, lane l testing
+// step base + l + 1 of each 64-step window.  Lanes follow the steps in order, so the row's first
 // green step is the lowest set bit of the window's ballot: the stop test is the ballot itself
 // and the hash is base + ctz(ballot) + 1, both on the scalar unit, with no per-lane state and no
 // cross-lane reduction.  Stream windows come three at a time from a ring prefetched three windows
-// ahead (as in the shared-window walk); steps past the stream are drawn in-lane.
+// ahead (as in the shared-window walk); steps past the stream are drawn in-lane.  Hash ids are
+// claimed in pairs whose first windows are requested together (see below).
 // ---------------------------------------------------------------------------------------------
 template <typename XT, bool kPacked>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void ballot_kernel(
@@ -343,62 +344,76 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         const uint32_t j0 = ht * hashes_per_tile;
         const uint32_t j1 = min(k, j0 + hashes_per_tile);
 
-        while (true) {
-            // claim the next hash id (every lane adds 1, as in the shared-window walk)
-            const uint32_t claimed = atomicAdd(&unit_slot, 1u);
-            const uint32_t j = j0 + ((uint32_t)__builtin_amdgcn_readfirstlane(claimed) >> 6);
-            if (j >= j1) break;
-
-            // ballot of the lanes whose step is green in the window [base + 1, base + 64]
-            auto stream_ballot = [&](const EntryRun<1, kPacked> &run) {
-                uint32_t lds, off;
-                run.get(0, (uint32_t)sizeof(XT), &lds, &off);
-                const uint32_t xv = *reinterpret_cast<const XT *>(smem + lds);
-                return __builtin_amdgcn_ballot_w64(off < xv);
-            };
-            uint32_t h = 0;  // empty rows hash to 0
-            uint32_t base = 0;
-            uint64_t green = 0;
-            if (live && depth != 0) {
-                const uint32_t *id_entries =
-                    reinterpret_cast<const uint32_t *>(entries) + (uint64_t)j * depth * kWords;
-                // each prefetch stays where it is issued (see the shared-window walk)
-                auto fetch = [&](uint32_t at) {
-                    EntryRun<1, kPacked> run;
-                    run.load_at(id_entries + (size_t)at * kWords, lane_words);
-                    asm volatile("" ::: "memory");
-                    return run;
-                };
-                EntryRun<1, kPacked> e0 = fetch(0), e1 = fetch(kWave), e2 = fetch(2 * kWave);
-                for (; base < depth; base += 3 * kWave) {
-                    green = stream_ballot(e0);
-                    if (green) break;
-                    e0 = fetch(base + 3 * kWave);
-                    green = stream_ballot(e1);
-                    if (green) { base += kWave; break; }
-                    e1 = fetch(base + 4 * kWave);
-                    green = stream_ballot(e2);
-                    if (green) { base += 2 * kWave; break; }
-                    e2 = fetch(base + 5 * kWave);
-                }
-            }
-            // past the stream (rare): draws made in-lane, up to the window that holds the cap
-            if (live) {
-                for (; green == 0 && base < kCap; base += kWave) {
-                    const uint32_t t = base + lane() + 1u;
-                    const uint64_t p = position(seed, j, t, b.total, b.threshold);
-                    uint64_t o64;
-                    const uint32_t comp = component_of(p, b.prefix, b.bucket, b.shift, &o64);
-                    green = __builtin_amdgcn_ballot_w64(
-                        o64 < (uint64_t)*reinterpret_cast<const XT *>(smem + (size_t)comp * sizeof(XT)));
-                    if (green) break;
-                }
-                // first green step, or none up to the cap (the hash saturates); a green step
-                // 65536 in the last window is past the cap as well
-                h = green ? min(base + (uint32_t)__builtin_ctzll(green) + 1u, kCap) : kCap;
-            }
-            // every lane stores; only lane 0 writes the tile value
+        // ballot of the lanes whose step is green in the window the run holds
+        auto stream_ballot = [&](const EntryRun<1, kPacked> &run) {
+            uint32_t lds, off;
+            run.get(0, (uint32_t)sizeof(XT), &lds, &off);
+            const uint32_t xv = *reinterpret_cast<const XT *>(smem + lds);
+            return __builtin_amdgcn_ballot_w64(off < xv);
+        };
+        // each prefetch stays where it is issued (see the shared-window walk)
+        auto fetch = [&](uint32_t j, uint32_t at) {
+            EntryRun<1, kPacked> run;
+            run.load_at(reinterpret_cast<const uint32_t *>(entries) +
+                            ((uint64_t)j * depth + at) * kWords,
+                        lane_words);
+            asm volatile("" ::: "memory");
+            return run;
+        };
+        // every lane stores; only lane 0 writes the tile value
+        auto store = [&](uint32_t j, uint32_t h) {
             hbuf[lane() == 0 ? j - j0 : hashes_per_tile + lane()] = (uint16_t)h;
+        };
+        // draws made in-lane from step base + 1 up to the window that holds the cap: the first
+        // green step, or the cap (a green step 65536 in the last window is past it as well)
+        auto lane_walk = [&](uint32_t j, uint32_t base) -> uint32_t {
+            for (; base < kCap; base += kWave) {
+                const uint32_t t = base + lane() + 1u;
+                const uint64_t p = position(seed, j, t, b.total, b.threshold);
+                uint64_t o64;
+                const uint32_t comp = component_of(p, b.prefix, b.bucket, b.shift, &o64);
+                const uint64_t green = __builtin_amdgcn_ballot_w64(
+                    o64 < (uint64_t)*reinterpret_cast<const XT *>(smem + (size_t)comp * sizeof(XT)));
+                if (green) return min(base + (uint32_t)__builtin_ctzll(green) + 1u, kCap);
+            }
+            return kCap;
+        };
+        // hash id j from its three requested windows, then the stream, then in-lane draws
+        auto walk_id = [&](uint32_t j, EntryRun<1, kPacked> &e0, EntryRun<1, kPacked> &e1,
+                           EntryRun<1, kPacked> &e2) {
+            for (uint32_t base = 0; base < depth; base += 3 * kWave) {
+                uint64_t green = stream_ballot(e0);
+                if (green) return store(j, base + (uint32_t)__builtin_ctzll(green) + 1u);
+                e0 = fetch(j, base + 3 * kWave);
+                green = stream_ballot(e1);
+                if (green) return store(j, base + kWave + (uint32_t)__builtin_ctzll(green) + 1u);
+                e1 = fetch(j, base + 4 * kWave);
+                green = stream_ballot(e2);
+                if (green) return store(j, base + 2 * kWave + (uint32_t)__builtin_ctzll(green) + 1u);
+                e2 = fetch(j, base + 5 * kWave);
+            }
+            store(j, lane_walk(j, depth));  // past the stream (rare)
+        };
+        // claim u: hash ids 2u and 2u + 1 (every lane adds 1, as in the shared-window walk)
+        auto claim_pair = [&]() {
+            const uint32_t claimed = atomicAdd(&unit_slot, 1u);
+            return j0 + 2u * ((uint32_t)__builtin_amdgcn_readfirstlane(claimed) >> 6);
+        };
+        if (!live || depth == 0) {
+            // empty rows hash to 0; without a stream every draw is made in-lane
+            for (uint32_t ja = claim_pair(); ja < j1; ja = claim_pair())
+                for (uint32_t j = ja; j < min(ja + 2u, j1); ++j) store(j, live ? lane_walk(j, 0) : 0u);
+        } else {
+            // Both ids' first windows are requested at once, each into its own registers, so the
+            // second id starts on entries that arrived while the first was walked.  A pair cut
+            // by the tile's end requests its first id's windows twice (unused the second time).
+            for (uint32_t ja = claim_pair(); ja < j1; ja = claim_pair()) {
+                const uint32_t jb = min(ja + 1u, j1 - 1u);
+                EntryRun<1, kPacked> a0 = fetch(ja, 0), a1 = fetch(ja, kWave), a2 = fetch(ja, 2 * kWave);
+                EntryRun<1, kPacked> b0 = fetch(jb, 0), b1 = fetch(jb, kWave), b2 = fetch(jb, 2 * kWave);
+                walk_id(ja, a0, a1, a2);
+                if (jb != ja) walk_id(jb, b0, b1, b2);
+            }
         }
         write_tile(sig, hbuf, row, 1u, k, j0, j1, hashes_per_tile);
     }
