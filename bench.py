@@ -229,6 +229,10 @@ def heavy_tail_bench(args, torch, synth, wmh) -> dict:
                 "mean_steps_per_hash": tests / hashes,
                 "walk_frac_of_alu_peak": OPS_PER_TEST * tests / (np.mean(walk_b) / 1e3) / 1e12
                 / PEAK_INT_TOPS})
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = oracle_on_head(ds, 4096, k, wmh.sig_to_numpy(sig_b[:4096]))
+        log(f"heavy-tail: oracle {out['cpu_baseline']['value']:.3g} hashes/s on 4096 rows, "
+            f"bit-exact {out['cpu_baseline']['bit_exact']}")
     # auto mode: the planner may split the rows between the batched walk and the index
     sig_a = torch.empty_like(sig_b)
     timed_steps(ctx, rows, k, sig_a, ctx.make_opts(mode="auto", profile=True), 1, 1, torch)
@@ -348,6 +352,10 @@ def text_like_bench(args, torch, synth, wmh) -> dict:
            "head_equals_plain_walk": bool(np.array_equal(sig_np[:48], walk_sig)),
            "head_plain_walk_ms": head_plain_ms,
            "head_plain_walk_rows": head.n_rows}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = oracle_on_head(ds, 48, k, sig_np[:48])
+        log(f"text-like: oracle {out['cpu_baseline']['value']:.3g} hashes/s on 48 rows, "
+            f"bit-exact {out['cpu_baseline']['bit_exact']}")
     log(f"text-like: {mode} {out['ms_per_step']:.2f} ms/step, index build {build_ms:.2f} ms, "
         f"head equals walk {out['head_equals_plain_walk']}")
     ctx.close()
@@ -394,6 +402,23 @@ def cpu_baseline(ds, k, target_s):
             "single_thread_value": n1 * k / dt1,
             "single_thread_sample": f"first {n1} rows, 1 thread, {dt1:.1f} s",
             "host": cpu_model()}, sig
+
+
+def oracle_on_head(ds, n, k, gpu_sig_head):
+    """The oracle timed on the first n rows (host threads as for the headline's baseline), and
+    whether the GPU's signatures of those rows equal it."""
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    head = ds.head(n)
+    t0 = time.perf_counter()
+    sig, steps = oracle.hash_csr(head.m, head.row_ptr, head.col, head.val, k, seed=0,
+                                 threads=threads, return_steps=True)
+    dt = time.perf_counter() - t0
+    return {"value": head.n_rows * k / dt, "unit": "hashes/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {head.n_rows} rows, k={k} ({steps} membership tests, {dt:.1f} s, "
+                      f"{steps / dt:.3g} tests/s)",
+            "bit_exact": bool(np.array_equal(sig, gpu_sig_head))}
 
 
 def main():
