@@ -71,6 +71,8 @@ def parse():
                     help="only the headline workload")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (planner default plan)")
+    ap.add_argument("--text-like", action="store_true",
+                    help="only run the text-like workload (component index)")
     ap.add_argument("--text-rows", type=int, default=1_000_000,
                     help="rows of the text-like workload generated for its line")
     ap.add_argument("--serve-max-rows", type=int, default=4096)
@@ -438,6 +440,10 @@ def main():
     if args.heavy_tail:
         torch.cuda.set_device(0)
         print(json.dumps({"heavy_tail": heavy_tail_bench(args, torch, synth, wmh)}), flush=True)
+        return
+    if args.text_like:
+        torch.cuda.set_device(0)
+        print(json.dumps({"text_like": text_like_bench(args, torch, synth, wmh)}), flush=True)
         return
 
     if not os.path.exists(wmh.LIB_PATH):

@@ -283,8 +283,9 @@ wmh_status ensure_index(wmh_ctx *ctx, OwnedIndex *ix, uint64_t seed, uint32_t k,
             *p = nullptr;
         }
         ix->cap_entries = 0;
-        e = hipMalloc(&ix->buf.entries, n * sizeof(uint64_t));
-        if (e == hipSuccess) e = hipMalloc(&ix->buf.by_step, n * sizeof(uint64_t));
+        const size_t bytes = (n + kIndexPadKeys) * sizeof(uint64_t);
+        e = hipMalloc(&ix->buf.entries, bytes);
+        if (e == hipSuccess) e = hipMalloc(&ix->buf.by_step, bytes);
         if (e != hipSuccess) return device_fail(err, e, "index entries");
         ix->cap_entries = n;
     }

@@ -31,7 +31,7 @@ namespace {
 
 constexpr uint32_t kIndexPairs = (kCap - 1u) / 2u;  // pairs of steps (1,2) ... (65533,65534)
 constexpr uint32_t kChunk = 4096;                   // keys sorted together (32 KB of LDS)
-constexpr uint32_t kBatch = 8;                      // keys a lane loads per round trip
+constexpr uint32_t kBatch = 16;                     // keys a lane loads per round trip
 constexpr uint32_t kScanBlock = 1024;
 
 __device__ __forceinline__ uint32_t lane() { return threadIdx.x & (kWave - 1u); }
@@ -229,17 +229,35 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v)
     return v;
 }
 
+// Keys i .. i + kBatch - 1 of a list buffer, two keys per 16-byte load (global loads need only
+// 4-byte alignment; a key address is 8-byte aligned).
+typedef uint32_t KeyPair __attribute__((ext_vector_type(4), aligned(8)));
+static_assert(kBatch % 2 == 0 && kIndexPadKeys + 1 >= kBatch,
+              "a batch that starts at a list's last key stays inside the padded buffer");
+
+__device__ __forceinline__ void load_batch(const uint64_t *__restrict__ keys, uint32_t i,
+                                           uint64_t (&key)[kBatch])
+{
+    const KeyPair *p = reinterpret_cast<const KeyPair *>(keys + i);
+#pragma unroll
+    for (uint32_t v = 0; v < kBatch / 2; ++v) {
+        const KeyPair q = p[v];
+        key[2 * v] = (uint64_t)q.x | ((uint64_t)q.y << 32);
+        key[2 * v + 1] = (uint64_t)q.z | ((uint64_t)q.w << 32);
+    }
+}
+
 __device__ __forceinline__ void offset_scan(const uint64_t *__restrict__ entries, uint32_t a,
                                             uint32_t z, uint32_t x, uint32_t *hmin)
 {
     for (uint32_t base = a; base < z; base += kChunk) {
         const uint32_t end = std::min(z, base + kChunk);
-        // kBatch independent loads per round trip (indices clamped into the chunk; keys past
-        // its end count as red); the chunk is sorted, so the first red key ends it
+        // kBatch consecutive keys per round trip (keys past the chunk's end, in the next list
+        // or in the buffer's padding, count as red); the chunk is sorted, so the first red key
+        // ends it
         for (uint32_t i = base; i < end; i += kBatch) {
             uint64_t key[kBatch];
-#pragma unroll
-            for (uint32_t u = 0; u < kBatch; ++u) key[u] = entries[std::min(i + u, end - 1u)];
+            load_batch(entries, i, key);
             bool all_green = true;
 #pragma unroll
             for (uint32_t u = 0; u < kBatch; ++u) {
@@ -260,8 +278,7 @@ __device__ __forceinline__ void step_scan(const uint64_t *__restrict__ by_step, 
         // keys in step order inside the chunk: read up to the first step > T
         for (uint32_t i = base; i < end; i += kBatch) {
             uint64_t key[kBatch];
-#pragma unroll
-            for (uint32_t u = 0; u < kBatch; ++u) key[u] = by_step[std::min(i + u, end - 1u)];
+            load_batch(by_step, i, key);
             bool all_in = true;
 #pragma unroll
             for (uint32_t u = 0; u < kBatch; ++u) {

@@ -162,6 +162,8 @@ struct IndexBuffers {
 constexpr uint32_t kIndexSteps = 65534u;  // steps 1 .. cap - 1 decide every capped hash value
 constexpr uint32_t kIndexMaxK = 8192u;    // j fits the key's 16 bits; LDS of the row kernel
 
+constexpr uint32_t kIndexPadKeys = 16u;  // allocated past the last list: row scans load
+                                         // whole batches of keys and mask those past a list
 inline uint64_t index_entry_count(uint32_t k) { return (uint64_t)k * kIndexSteps; }
 inline uint64_t index_scan_blocks(uint32_t dims) { return ((uint64_t)dims + 1 + 1023) / 1024; }
 
