@@ -27,8 +27,8 @@
  *     returns, except the bounds, which wmh_set_bounds copies into the context.
  *   - `stream` is a hipStream_t of the context's device, or NULL for the context's own stream.
  *   - A context is not thread-safe: use one context per host thread, or serialize calls.
- *     Its device scratch (tile counter, shared position stream, row classes of a split,
- *     captured graph) serves every call: asynchronous calls (opts->sync = 0) on different
+ *     Its device scratch (tile and row counters, shared position stream, row classes of a
+ *     split, captured graph) serves every call: asynchronous calls (opts->sync = 0) on different
  *     streams must be ordered by the caller; a call that reuses a stream built by an earlier
  *     call waits for that build.
  *   - On any error the output buffers are left untouched (validation precedes every write),

@@ -438,6 +438,7 @@ wmh_status wmh_create(int device, wmh_ctx **out)
         hipMalloc(&ctx->d_check, sizeof(CheckWords)) != hipSuccess ||
         hipHostMalloc(&ctx->h_check, sizeof(CheckWords), hipHostMallocDefault) != hipSuccess ||
         hipMalloc(&ctx->d_tile_counter, sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&ctx->d_row_counter, sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&ctx->d_codec, 2 * sizeof(unsigned long long)) != hipSuccess ||
         hipHostMalloc(&ctx->h_codec, 2 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
         hipEventCreate(&ctx->ev[0]) != hipSuccess || hipEventCreate(&ctx->ev[1]) != hipSuccess ||
@@ -463,6 +464,7 @@ void wmh_destroy(wmh_ctx *ctx)
     if (ctx->d_row_class) hipFree(ctx->d_row_class);
     if (ctx->h_check) hipHostFree(ctx->h_check);
     if (ctx->d_tile_counter) hipFree(ctx->d_tile_counter);
+    if (ctx->d_row_counter) hipFree(ctx->d_row_counter);
     if (ctx->d_codec) hipFree(ctx->d_codec);
     if (ctx->h_codec) hipHostFree(ctx->h_codec);
     for (hipEvent_t &e : ctx->ev)
@@ -636,7 +638,7 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         if (st != WMH_OK) return st;
         if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[1], s));
         const uint32_t grid = (uint32_t)ctx->cu_count * (uint32_t)index_rows_blocks_per_cu(k);
-        WMH_HIP(ctx, launch_index_rows(rows, ctx->index.buf, b, k, sig, grid, s));
+        WMH_HIP(ctx, launch_index_rows(rows, ctx->index.buf, b, k, sig, ctx->d_row_counter, grid, s));
         if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[2], s));
         WMH_HIP(ctx, hipEventRecord(ctx->index.used, s));
         ctx->profiled = profile;
@@ -767,7 +769,7 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         const wmh_status st = run_batched(walk_rows, split_plan);
         if (st != WMH_OK) return st;
         const uint32_t grid = (uint32_t)ctx->cu_count * (uint32_t)index_rows_blocks_per_cu(k);
-        WMH_HIP(ctx, launch_index_rows(index_rows, ctx->index.buf, b, k, sig, grid, s));
+        WMH_HIP(ctx, launch_index_rows(index_rows, ctx->index.buf, b, k, sig, ctx->d_row_counter, grid, s));
         if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[2], s));  // walk_ms spans both
         WMH_HIP(ctx, hipEventRecord(ctx->index.used, s));
         ctx->profiled = profile;

@@ -300,15 +300,31 @@ __global__ __launch_bounds__(256) void index_rows_kernel(Rows rows,
                                                          const uint32_t *__restrict__ bound,
                                                          uint64_t total, uint32_t dims, uint32_t k,
                                                          double log_delta,
+                                                         unsigned long long *row_counter,
                                                          uint16_t *__restrict__ sig)
 {
     extern __shared__ uint32_t lds[];
-    const uint32_t waves = blockDim.x / kWave;
     const uint32_t wave = wave_index();
     const uint32_t ln = lane();
     uint32_t *hmin = lds + (size_t)wave * k;
-    for (uint64_t row = (uint64_t)blockIdx.x * waves + wave; row < rows.n_rows;
-         row += (uint64_t)gridDim.x * waves) {
+    // Rows are claimed one at a time from a counter that starts at zero, so a wavefront that
+    // drew cheap rows takes more of them (row costs differ by orders of magnitude).  The next
+    // claim is sent before the current row is read, so its latency hides behind the row.
+    // (The counter's address is offset by a lane count that is zero in lane 0: the compiler
+    // then sees a per-lane address and issues the one lane's atomic as written, where for a
+    // uniform address it would combine the wavefront's requests and wait for the result at
+    // once.)
+    unsigned long long *const claim_at = row_counter + __builtin_amdgcn_mbcnt_lo(0u, 0u);
+    auto claim = [&]() {
+        unsigned long long r = 0;
+        if (ln == 0) r = atomicAdd(claim_at, 1ull);
+        return r;  // lane 0's value, read through a broadcast
+    };
+    unsigned long long pending = claim();
+    for (;;) {
+        const uint64_t row = __shfl(pending, 0);
+        if (row >= rows.n_rows) break;
+        pending = claim();
         if (rows.skips(row)) continue;  // a row another path computes (row filter)
         for (uint32_t j = ln; j < k; j += kWave) hmin[j] = kCap;
         wave_lds_fence();
@@ -417,16 +433,20 @@ int index_rows_blocks_per_cu(uint32_t k)
 }
 
 hipError_t launch_index_rows(const Rows &rows, const IndexBuffers &ix, const Bounds &b, uint32_t k,
-                             uint16_t *sig, uint32_t grid, hipStream_t stream)
+                             uint16_t *sig, unsigned long long *row_counter, uint32_t grid,
+                             hipStream_t stream)
 {
     if (rows.n_rows == 0) return hipSuccess;
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(row_counter), 0u, 2, stream);
+    if (e != hipSuccess) return e;
     const uint32_t waves = index_rows_waves(k);
     const uint64_t need = (rows.n_rows + waves - 1) / waves;
     const uint32_t g = (uint32_t)std::min<uint64_t>(need, grid);
     // every hash of a step-order row is <= T with probability >= 1 - 1e-4
     const double log_delta = std::log(1e-4 / (double)k);
     index_rows_kernel<<<g, waves * kWave, index_rows_lds_bytes(k), stream>>>(
-        rows, ix.offsets, ix.entries, ix.by_step, b.bound, b.total, b.dims, k, log_delta, sig);
+        rows, ix.offsets, ix.entries, ix.by_step, b.bound, b.total, b.dims, k, log_delta,
+        row_counter, sig);
     return hipGetLastError();
 }
 

@@ -61,6 +61,7 @@ struct Slot {
     uint16_t *h_sig = nullptr;  // pinned staging of the signatures
     uint64_t cap_rows = 0, cap_col = 0, cap_val = 0, cap_sig = 0, cap_h_sig = 0;
     uint32_t *d_tile_counter = nullptr;
+    unsigned long long *d_row_counter = nullptr;
     CheckWords *d_check = nullptr;  // the validation pass's words
     CheckWords *h_check = nullptr;  // pinned copy, read once `checked` has fired
     hipEvent_t checked = nullptr;
@@ -186,7 +187,8 @@ wmh_status wmh_server::launch_compute(Slot &slot, Request &r)
             e = hipStreamSynchronize(s);
         }
         if (e == hipSuccess)
-            e = launch_index_rows(rows, index.buf, b, k, slot.d_sig, index_grid, s);
+            e = launch_index_rows(rows, index.buf, b, k, slot.d_sig, slot.d_row_counter,
+                                  index_grid, s);
         if (e == hipSuccess) e = hipEventRecord(index.used, s);
     } else if (e == hipSuccess) {
         if (batched) {
@@ -355,6 +357,7 @@ wmh_status wmh_server_create(wmh_ctx *ctx, const wmh_server_config *cfg_in, wmh_
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&slot.finished, hipEventDisableTiming);
         if (e == hipSuccess) e = hipMalloc(&slot.d_tile_counter, sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(&slot.d_row_counter, sizeof(unsigned long long));
         if (e == hipSuccess) e = hipEventCreateWithFlags(&slot.checked, hipEventDisableTiming);
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&slot.d_check), sizeof(CheckWords));
         if (e == hipSuccess)
@@ -524,6 +527,7 @@ void wmh_server_destroy(wmh_server *srv)
         if (slot.d_sig) (void)hipFree(slot.d_sig);
         if (slot.h_sig) (void)hipHostFree(slot.h_sig);
         if (slot.d_tile_counter) (void)hipFree(slot.d_tile_counter);
+        if (slot.d_row_counter) (void)hipFree(slot.d_row_counter);
         if (slot.finished) (void)hipEventDestroy(slot.finished);
         if (slot.checked) (void)hipEventDestroy(slot.checked);
         if (slot.d_check) (void)hipFree(slot.d_check);
