@@ -80,10 +80,11 @@ typedef enum {
                               O(nnz + k * 65534 * sum x / M) per row: the choice for small
                               green fractions.  The lists are kept twice, by offset and by
                               step: a row whose hashes are small (large sum x / M) reads its
-                              lists in step order up to a bound T with Pr(any hash > T) <= 1e-4
-                              (Theorem 2) and settles any hash id above T in offset order, so
-                              the values stay exact.  Needs k <= 8192 and k * 65534 * 16 bytes
-                              of device memory */,
+                              lists in step order up to a bound T1 with Pr(any hash > T1) <=
+                              1/16 (Theorem 2), a row left with a hash id above T1 again up to
+                              T2 with Pr(any hash > T2) <= 1e-4, and settles any hash id above
+                              T2 in offset order, so the values stay exact.  Needs k <= 8192
+                              and (k * 65534 + 16) * 16 bytes of device memory */,
     WMH_MODE_SPLIT = 4     /* each row on the cheaper of the two: the validation pass classes
                               every row by its own estimated costs (k * min(M / sum x, 65535)
                               walk tests against its index keys and list lookups), the batched

@@ -217,11 +217,14 @@ __global__ __launch_bounds__(256) void step_keys_kernel(const uint64_t *__restri
 // Hashes of rows from the index: one wavefront per row, the running minimum of each hash id in
 // LDS.  A lane takes one nonzero (c, x_c) at a time.  Offset order: the lane reads c's keys
 // chunk by chunk up to the first offset >= x_c (every green key).  Step order, for rows whose
-// hashes are small: the lane reads c's keys up to the first step > T, where T is chosen so that
-// every hash of the row is at most T with probability 1 - 1e-4 (Theorem 2: Pr(h > T) =
-// (1 - s)^T); a hash id still above T afterwards is settled by an offset-order pass, so the
-// values are exact either way.  The row takes step order when T * sum(m_c) < 65534 * sum(x_c)
-// over its nonzeros (expected keys read: k * T * sum(m_c) / M against k * 65534 * sum(x_c) / M).
+// hashes are small: the lane reads c's keys up to the first step > T1, where every hash of the
+// row is at most T1 with probability 1 - 1/16 (Theorem 2: Pr(h > T) = (1 - s)^T); a row left
+// with a hash id above T1 is read again up to T2 (probability 1 - 1e-4), then in offset order,
+// so the values are exact either way.  The row takes step order when T2 * sum(m_c) < 65534 *
+// sum(x_c) over its nonzeros (keys read in one pass to T2: k * T2 * sum(m_c) / M, against
+// k * 65534 * sum(x_c) / M in offset order).  The rule leaves rows at the margin in offset order
+// on purpose: a row with few nonzeros waits for its longest list, and step-order lists are as
+// long as their bounds m_c, offset-order ones only as x_c.
 __device__ __forceinline__ uint64_t wave_sum64(uint64_t v)
 {
 #pragma unroll
@@ -299,7 +302,7 @@ __global__ __launch_bounds__(256) void index_rows_kernel(Rows rows,
                                                          const uint64_t *__restrict__ by_step,
                                                          const uint32_t *__restrict__ bound,
                                                          uint64_t total, uint32_t dims, uint32_t k,
-                                                         double log_delta,
+                                                         double log_first, double log_final,
                                                          unsigned long long *row_counter,
                                                          uint16_t *__restrict__ sig)
 {
@@ -341,29 +344,44 @@ __global__ __launch_bounds__(256) void index_rows_kernel(Rows rows,
         sx = wave_sum64(sx);
         sm = wave_sum64(sm);
         const bool live = sx != 0;
-        // step bound T of the row and the cheaper key order (uniform over the wavefront)
-        uint32_t T = kCap;
+        // step bounds T1 <= T2 of the row and the cheaper key order (uniform over the wavefront)
+        uint32_t T1 = kCap, T2 = kCap;
         bool by_steps = false;
         if (live && by_step) {
             const double s = (double)sx / (double)total;
-            const double t = s >= 1.0 ? 1.0 : ceil(log_delta / log1p(-s));
-            T = t < (double)kCap ? (uint32_t)t : kCap;
-            by_steps = T < kCap - 1u && (double)T * (double)sm < 65534.0 * (double)sx;
+            const double t1 = index_step_bound(s, log_first), t2 = index_step_bound(s, log_final);
+            T1 = t1 < (double)kCap ? (uint32_t)t1 : kCap;
+            T2 = t2 < (double)kCap ? (uint32_t)t2 : kCap;
+            by_steps = T2 < kCap - 1u && t2 * (double)sm < 65534.0 * (double)sx;
         }
         for (uint64_t e = lo + ln; e < hi; e += kWave) {
             const uint32_t c = rows.col[e];
             const uint32_t x = rows.val[e];
             if (x == 0 || c >= dims) continue;
-            if (by_steps) step_scan(by_step, offsets[c], offsets[c + 1], x, T, hmin);
+            if (by_steps) step_scan(by_step, offsets[c], offsets[c + 1], x, T1, hmin);
             else offset_scan(entries, offsets[c], offsets[c + 1], x, hmin);
         }
         wave_lds_fence();
-        if (by_steps) {
-            // a hash id with no green step up to T: settle the row in offset order (the
-            // step-order minima found so far are green steps, so they stay valid)
+        // A hash id with no green step up to T1 after the first pass: read the row's lists again
+        // up to T2, then, if one is still open, in offset order.  A minimum found by a pass that
+        // read every key up to its bound is final, and each pass only lowers minima to green
+        // steps, so the values are exact whichever passes run.
+        auto any_open = [&](uint32_t T) {
             bool open = false;
             for (uint32_t j = ln; j < k; j += kWave) open = open || hmin[j] > T;
-            if (__ballot(open) != 0) {
+            return __ballot(open) != 0;
+        };
+        if (by_steps && any_open(T1)) {
+            if (T2 > T1) {
+                for (uint64_t e = lo + ln; e < hi; e += kWave) {
+                    const uint32_t c = rows.col[e];
+                    const uint32_t x = rows.val[e];
+                    if (x == 0 || c >= dims) continue;
+                    step_scan(by_step, offsets[c], offsets[c + 1], x, T2, hmin);
+                }
+                wave_lds_fence();
+            }
+            if (any_open(T2)) {
                 for (uint64_t e = lo + ln; e < hi; e += kWave) {
                     const uint32_t c = rows.col[e];
                     const uint32_t x = rows.val[e];
@@ -442,10 +460,11 @@ hipError_t launch_index_rows(const Rows &rows, const IndexBuffers &ix, const Bou
     const uint32_t waves = index_rows_waves(k);
     const uint64_t need = (rows.n_rows + waves - 1) / waves;
     const uint32_t g = (uint32_t)std::min<uint64_t>(need, grid);
-    // every hash of a step-order row is <= T with probability >= 1 - 1e-4
-    const double log_delta = std::log(1e-4 / (double)k);
+    // every hash of a step-order row is <= T1 with probability >= 1 - 1/16, <= T2 with >= 1 - 1e-4
+    const double log_first = std::log(kIndexFirstMiss / (double)k);
+    const double log_final = std::log(kIndexFinalMiss / (double)k);
     index_rows_kernel<<<g, waves * kWave, index_rows_lds_bytes(k), stream>>>(
-        rows, ix.offsets, ix.entries, ix.by_step, b.bound, b.total, b.dims, k, log_delta,
+        rows, ix.offsets, ix.entries, ix.by_step, b.bound, b.total, b.dims, k, log_first, log_final,
         row_counter, sig);
     return hipGetLastError();
 }

@@ -162,6 +162,17 @@ struct IndexBuffers {
 constexpr uint32_t kIndexSteps = 65534u;  // steps 1 .. cap - 1 decide every capped hash value
 constexpr uint32_t kIndexMaxK = 8192u;    // j fits the key's 16 bits; LDS of the row kernel
 
+// Step-order passes of the component index over a row with green fraction s (Theorem 2: one
+// hash exceeds T with probability (1 - s)^T): a first pass reads every list up to T1, where all
+// k hashes are <= T1 with probability >= 1 - kIndexFirstMiss; a row it leaves open is read again
+// up to T2 (probability >= 1 - kIndexFinalMiss), and a row still open after that in offset order.
+constexpr double kIndexFirstMiss = 1.0 / 16.0;
+constexpr double kIndexFinalMiss = 1e-4;
+// T with (1 - s)^T <= p / k, for log_p_k = log(p / k)
+__host__ __device__ inline double index_step_bound(double s, double log_p_k)
+{
+    return s >= 1.0 ? 1.0 : ceil(log_p_k / log1p(-s));
+}
 constexpr uint32_t kIndexPadKeys = 16u;  // allocated past the last list: row scans load
                                          // whole batches of keys and mask those past a list
 inline uint64_t index_entry_count(uint32_t k) { return (uint64_t)k * kIndexSteps; }

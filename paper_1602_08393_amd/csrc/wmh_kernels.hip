@@ -82,7 +82,7 @@ __device__ __forceinline__ uint64_t wave_min(uint64_t v)
 template <bool kKeys, bool kLdsBounds>
 __global__ __launch_bounds__(1024) void validate_kernel(Rows rows, const uint32_t *__restrict__ bound_in,
                                                         uint32_t dims, uint64_t total,
-                                                        double log_eps, CheckWords *words,
+                                                        double log_final, CheckWords *words,
                                                         RowSplit split)
 {
     // per-workgroup partials, so each word gets at most one global atomic per workgroup
@@ -175,12 +175,14 @@ __global__ __launch_bounds__(1024) void validate_kernel(Rows rows, const uint32_
         w_walk += min(q, (uint64_t)kCap);
         if (kKeys) {
             // index keys per hash: the cheaper of offset order (65534 * s) and step order up
-            // to the row's bound T (T * sum(m) / M), as the index row kernel chooses
+            // to the row's final bound T2 (T2 * sum(m) / M), as the index row kernel chooses
+            // (its first pass to T1 usually settles a step-order row with fewer keys; the
+            // planner's costs were measured with this count)
             sum_m = wave_sum(sum_m);
             const double s = (double)sum / (double)total;
-            const double T = s >= 1.0 ? 1.0 : ceil(log_eps / log1p(-s));
+            const double T2 = index_step_bound(s, log_final);
             const double by_offset = 65534.0 * s;
-            const double by_step = T < 65534.0 ? T * ((double)sum_m / (double)total) : by_offset;
+            const double by_step = T2 < 65534.0 ? T2 * ((double)sum_m / (double)total) : by_offset;
             const uint64_t keys = (uint64_t)ceil(min(by_offset, by_step));
             w_keys += keys;
             if (classify) {
@@ -608,7 +610,8 @@ hipError_t launch_validate(const Rows &rows, const uint32_t *bound, uint32_t dim
     const RowSplit sp = split ? *split : RowSplit{};
     if (sp.row_class && !want_keys) return hipErrorInvalidValue;
     if (rows.n_rows == 0) return hipSuccess;
-    const double log_eps = std::log(1e-4 / (double)k);  // the index's failure bound per row
+    // the index's final step bound per row
+    const double log_final = std::log(kIndexFinalMiss / (double)k);
     // bounds in LDS up to 76 KB: two workgroups of 16 wavefronts per CU keep it fully
     // occupied (measured on the histogram workload: 268 -> 174 us)
     constexpr size_t kLdsBoundsMax = 76 * 1024;
@@ -630,11 +633,11 @@ hipError_t launch_validate(const Rows &rows, const uint32_t *bound, uint32_t dim
                                                        8192 / per_block);
     const size_t shm = lds ? (size_t)dims * 4 : 0;
     if (want_keys) {
-        if (lds) validate_kernel<true, true><<<grid, threads, shm, stream>>>(rows, bound, dims, total, log_eps, words, sp);
-        else validate_kernel<true, false><<<grid, threads, 0, stream>>>(rows, bound, dims, total, log_eps, words, sp);
+        if (lds) validate_kernel<true, true><<<grid, threads, shm, stream>>>(rows, bound, dims, total, log_final, words, sp);
+        else validate_kernel<true, false><<<grid, threads, 0, stream>>>(rows, bound, dims, total, log_final, words, sp);
     } else {
-        if (lds) validate_kernel<false, true><<<grid, threads, shm, stream>>>(rows, bound, dims, total, log_eps, words, sp);
-        else validate_kernel<false, false><<<grid, threads, 0, stream>>>(rows, bound, dims, total, log_eps, words, sp);
+        if (lds) validate_kernel<false, true><<<grid, threads, shm, stream>>>(rows, bound, dims, total, log_final, words, sp);
+        else validate_kernel<false, false><<<grid, threads, 0, stream>>>(rows, bound, dims, total, log_final, words, sp);
     }
     return hipGetLastError();
 }
