@@ -296,6 +296,7 @@ __device__ __forceinline__ void step_scan(const uint64_t *__restrict__ by_step, 
     }
 }
 
+template <bool kFiltered>
 __global__ __launch_bounds__(256) void index_rows_kernel(Rows rows,
                                                          const uint32_t *__restrict__ offsets,
                                                          const uint64_t *__restrict__ entries,
@@ -310,25 +311,23 @@ __global__ __launch_bounds__(256) void index_rows_kernel(Rows rows,
     const uint32_t wave = wave_index();
     const uint32_t ln = lane();
     uint32_t *hmin = lds + (size_t)wave * k;
-    // Rows are claimed one at a time from a counter that starts at zero, so a wavefront that
-    // drew cheap rows takes more of them (row costs differ by orders of magnitude).  The next
-    // claim is sent before the current row is read, so its latency hides behind the row.
-    // (The counter's address is offset by a lane count that is zero in lane 0: the compiler
-    // then sees a per-lane address and issues the one lane's atomic as written, where for a
-    // uniform address it would combine the wavefront's requests and wait for the result at
-    // once.)
+    // Rows are claimed from a counter that starts at zero, so a wavefront that drew cheap rows
+    // takes more of them (row costs differ by orders of magnitude): one row per claim, or,
+    // under a row filter, 64 rows per claim, of which the wavefront picks the rows it keeps
+    // with one ballot (claims on one counter are serialized, and most rows of a filtered batch
+    // belong to the other path).  The next claim is sent before the current rows are read, so
+    // its latency hides behind them.  (The counter's address is offset by a lane count that is
+    // zero in lane 0: the compiler then sees a per-lane address and issues the one lane's
+    // atomic as written, where for a uniform address it would combine the wavefront's requests
+    // and wait for the result at once.)
     unsigned long long *const claim_at = row_counter + __builtin_amdgcn_mbcnt_lo(0u, 0u);
+    constexpr unsigned long long group = kFiltered ? kWave : 1u;
     auto claim = [&]() {
         unsigned long long r = 0;
-        if (ln == 0) r = atomicAdd(claim_at, 1ull);
+        if (ln == 0) r = atomicAdd(claim_at, group);
         return r;  // lane 0's value, read through a broadcast
     };
-    unsigned long long pending = claim();
-    for (;;) {
-        const uint64_t row = __shfl(pending, 0);
-        if (row >= rows.n_rows) break;
-        pending = claim();
-        if (rows.skips(row)) continue;  // a row another path computes (row filter)
+    auto hash_row = [&](uint64_t row) {
         for (uint32_t j = ln; j < k; j += kWave) hmin[j] = kCap;
         wave_lds_fence();
         const uint64_t lo = rows.row_ptr[row], hi = rows.row_ptr[row + 1];
@@ -392,8 +391,31 @@ __global__ __launch_bounds__(256) void index_rows_kernel(Rows rows,
             }
         }
         uint16_t *out = sig + row * (uint64_t)k;
-        for (uint32_t j = ln; j < k; j += kWave) out[j] = live ? (uint16_t)hmin[j] : (uint16_t)0;
+        for (uint32_t j = ln; j < k; j += kWave)
+            out[j] = live ? (uint16_t)hmin[j] : (uint16_t)0;
         wave_lds_fence();
+    };
+    unsigned long long pending = claim();
+    if constexpr (!kFiltered) {
+        for (;;) {
+            const uint64_t row = __shfl(pending, 0);
+            if (row >= rows.n_rows) break;
+            pending = claim();
+            hash_row(row);
+        }
+    } else {
+        for (;;) {
+            const uint64_t first = __shfl(pending, 0);
+            if (first >= rows.n_rows) break;
+            pending = claim();
+            // the claimed rows this path computes, one bit each (uniform over the wavefront)
+            const uint64_t r = first + ln;
+            uint64_t todo = __ballot(r < rows.n_rows && !rows.skips(r));
+            while (todo != 0) {
+                hash_row(first + (uint64_t)__builtin_ctzll(todo));
+                todo &= todo - 1;
+            }
+        }
     }
 }
 
@@ -444,7 +466,8 @@ size_t index_rows_lds_bytes(uint32_t k) { return (size_t)index_rows_waves(k) * k
 int index_rows_blocks_per_cu(uint32_t k)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, index_rows_kernel, index_rows_waves(k) * kWave,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, index_rows_kernel<false>,
+                                                     index_rows_waves(k) * kWave,
                                                      index_rows_lds_bytes(k)) != hipSuccess)
         return 1;
     return std::max(1, n);
@@ -463,9 +486,17 @@ hipError_t launch_index_rows(const Rows &rows, const IndexBuffers &ix, const Bou
     // every hash of a step-order row is <= T1 with probability >= 1 - 1/16, <= T2 with >= 1 - 1e-4
     const double log_first = std::log(kIndexFirstMiss / (double)k);
     const double log_final = std::log(kIndexFinalMiss / (double)k);
-    index_rows_kernel<<<g, waves * kWave, index_rows_lds_bytes(k), stream>>>(
-        rows, ix.offsets, ix.entries, ix.by_step, b.bound, b.total, b.dims, k, log_first, log_final,
-        row_counter, sig);
+    // a filtered launch claims rows 64 at a time: one wavefront takes at most every 64th row
+    const uint64_t need_filtered = (rows.n_rows + kWave * waves - 1) / (kWave * waves);
+    if (rows.row_class)
+        index_rows_kernel<true><<<(uint32_t)std::min<uint64_t>(need_filtered, g), waves * kWave,
+                                  index_rows_lds_bytes(k), stream>>>(
+            rows, ix.offsets, ix.entries, ix.by_step, b.bound, b.total, b.dims, k, log_first,
+            log_final, row_counter, sig);
+    else
+        index_rows_kernel<false><<<g, waves * kWave, index_rows_lds_bytes(k), stream>>>(
+            rows, ix.offsets, ix.entries, ix.by_step, b.bound, b.total, b.dims, k, log_first,
+            log_final, row_counter, sig);
     return hipGetLastError();
 }
 
