@@ -31,7 +31,8 @@ namespace {
 
 constexpr uint32_t kIndexPairs = (kCap - 1u) / 2u;  // pairs of steps (1,2) ... (65533,65534)
 constexpr uint32_t kChunk = 4096;                   // keys sorted together (32 KB of LDS)
-constexpr uint32_t kBatch = 16;                     // keys a lane loads per round trip
+constexpr uint32_t kBatch = 16;      // most keys a lane loads per round trip (long lists)
+constexpr uint32_t kShortBatch = 8;  // keys per round trip where lists are short
 constexpr uint32_t kScanBlock = 1024;
 
 __device__ __forceinline__ uint32_t lane() { return threadIdx.x & (kWave - 1u); }
@@ -235,35 +236,38 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v)
 // Keys i .. i + kBatch - 1 of a list buffer, two keys per 16-byte load (global loads need only
 // 4-byte alignment; a key address is 8-byte aligned).
 typedef uint32_t KeyPair __attribute__((ext_vector_type(4), aligned(8)));
-static_assert(kBatch % 2 == 0 && kIndexPadKeys + 1 >= kBatch,
+static_assert(kBatch % 2 == 0 && kShortBatch % 2 == 0 && kShortBatch <= kBatch &&
+                  kIndexPadKeys + 1 >= kBatch,
               "a batch that starts at a list's last key stays inside the padded buffer");
 
+template <uint32_t B>
 __device__ __forceinline__ void load_batch(const uint64_t *__restrict__ keys, uint32_t i,
-                                           uint64_t (&key)[kBatch])
+                                           uint64_t (&key)[B])
 {
     const KeyPair *p = reinterpret_cast<const KeyPair *>(keys + i);
 #pragma unroll
-    for (uint32_t v = 0; v < kBatch / 2; ++v) {
+    for (uint32_t v = 0; v < B / 2; ++v) {
         const KeyPair q = p[v];
         key[2 * v] = (uint64_t)q.x | ((uint64_t)q.y << 32);
         key[2 * v + 1] = (uint64_t)q.z | ((uint64_t)q.w << 32);
     }
 }
 
+template <uint32_t B>
 __device__ __forceinline__ void offset_scan(const uint64_t *__restrict__ entries, uint32_t a,
                                             uint32_t z, uint32_t x, uint32_t *hmin)
 {
     for (uint32_t base = a; base < z; base += kChunk) {
         const uint32_t end = std::min(z, base + kChunk);
-        // kBatch consecutive keys per round trip (keys past the chunk's end, in the next list
+        // B consecutive keys per round trip (keys past the chunk's end, in the next list
         // or in the buffer's padding, count as red); the chunk is sorted, so the first red key
         // ends it
-        for (uint32_t i = base; i < end; i += kBatch) {
-            uint64_t key[kBatch];
+        for (uint32_t i = base; i < end; i += B) {
+            uint64_t key[B];
             load_batch(entries, i, key);
             bool all_green = true;
 #pragma unroll
-            for (uint32_t u = 0; u < kBatch; ++u) {
+            for (uint32_t u = 0; u < B; ++u) {
                 const bool green = i + u < end && (uint32_t)(key[u] >> 32) < x;
                 if (green) atomicMin(&hmin[(uint32_t)key[u] & 0xFFFFu], ((uint32_t)key[u]) >> 16);
                 all_green = all_green && green;
@@ -273,18 +277,19 @@ __device__ __forceinline__ void offset_scan(const uint64_t *__restrict__ entries
     }
 }
 
+template <uint32_t B>
 __device__ __forceinline__ void step_scan(const uint64_t *__restrict__ by_step, uint32_t a,
                                           uint32_t z, uint32_t x, uint32_t T, uint32_t *hmin)
 {
     for (uint32_t base = a; base < z; base += kChunk) {
         const uint32_t end = std::min(z, base + kChunk);
         // keys in step order inside the chunk: read up to the first step > T
-        for (uint32_t i = base; i < end; i += kBatch) {
-            uint64_t key[kBatch];
+        for (uint32_t i = base; i < end; i += B) {
+            uint64_t key[B];
             load_batch(by_step, i, key);
             bool all_in = true;
 #pragma unroll
-            for (uint32_t u = 0; u < kBatch; ++u) {
+            for (uint32_t u = 0; u < B; ++u) {
                 const uint32_t t = (uint32_t)(key[u] >> 48);
                 const bool in = i + u < end && t <= T;
                 if (in && (uint32_t)key[u] < x)
@@ -296,7 +301,7 @@ __device__ __forceinline__ void step_scan(const uint64_t *__restrict__ by_step, 
     }
 }
 
-template <bool kFiltered>
+template <bool kFiltered, uint32_t B>
 __global__ __launch_bounds__(256) void index_rows_kernel(Rows rows,
                                                          const uint32_t *__restrict__ offsets,
                                                          const uint64_t *__restrict__ entries,
@@ -305,15 +310,16 @@ __global__ __launch_bounds__(256) void index_rows_kernel(Rows rows,
                                                          uint64_t total, uint32_t dims, uint32_t k,
                                                          double log_first, double log_final,
                                                          unsigned long long *row_counter,
+                                                         bool claim_rows,
                                                          uint16_t *__restrict__ sig)
 {
     extern __shared__ uint32_t lds[];
     const uint32_t wave = wave_index();
     const uint32_t ln = lane();
     uint32_t *hmin = lds + (size_t)wave * k;
-    // Rows are claimed from a counter that starts at zero, so a wavefront that drew cheap rows
-    // takes more of them (row costs differ by orders of magnitude): one row per claim, or,
-    // under a row filter, 64 rows per claim, of which the wavefront picks the rows it keeps
+    // In a large batch rows are claimed from a counter that starts at zero, so a wavefront that
+    // drew cheap rows takes more of them (row costs differ by orders of magnitude): one row per
+    // claim, or, under a row filter, 64 rows per claim, of which the wavefront picks the rows it keeps
     // with one ballot (claims on one counter are serialized, and most rows of a filtered batch
     // belong to the other path).  The next claim is sent before the current rows are read, so
     // its latency hides behind them.  (The counter's address is offset by a lane count that is
@@ -357,8 +363,8 @@ __global__ __launch_bounds__(256) void index_rows_kernel(Rows rows,
             const uint32_t c = rows.col[e];
             const uint32_t x = rows.val[e];
             if (x == 0 || c >= dims) continue;
-            if (by_steps) step_scan(by_step, offsets[c], offsets[c + 1], x, T1, hmin);
-            else offset_scan(entries, offsets[c], offsets[c + 1], x, hmin);
+            if (by_steps) step_scan<B>(by_step, offsets[c], offsets[c + 1], x, T1, hmin);
+            else offset_scan<B>(entries, offsets[c], offsets[c + 1], x, hmin);
         }
         wave_lds_fence();
         // A hash id with no green step up to T1 after the first pass: read the row's lists again
@@ -376,7 +382,7 @@ __global__ __launch_bounds__(256) void index_rows_kernel(Rows rows,
                     const uint32_t c = rows.col[e];
                     const uint32_t x = rows.val[e];
                     if (x == 0 || c >= dims) continue;
-                    step_scan(by_step, offsets[c], offsets[c + 1], x, T2, hmin);
+                    step_scan<B>(by_step, offsets[c], offsets[c + 1], x, T2, hmin);
                 }
                 wave_lds_fence();
             }
@@ -385,7 +391,7 @@ __global__ __launch_bounds__(256) void index_rows_kernel(Rows rows,
                     const uint32_t c = rows.col[e];
                     const uint32_t x = rows.val[e];
                     if (x == 0 || c >= dims) continue;
-                    offset_scan(entries, offsets[c], offsets[c + 1], x, hmin);
+                    offset_scan<B>(entries, offsets[c], offsets[c + 1], x, hmin);
                 }
                 wave_lds_fence();
             }
@@ -395,6 +401,13 @@ __global__ __launch_bounds__(256) void index_rows_kernel(Rows rows,
             out[j] = live ? (uint16_t)hmin[j] : (uint16_t)0;
         wave_lds_fence();
     };
+    if (!kFiltered && !claim_rows) {  // a small batch: every G-th row, G the grid's wavefronts
+        const uint32_t waves = blockDim.x / kWave;
+        for (uint64_t row = (uint64_t)blockIdx.x * waves + wave; row < rows.n_rows;
+             row += (uint64_t)gridDim.x * waves)
+            hash_row(row);
+        return;
+    }
     unsigned long long pending = claim();
     if constexpr (!kFiltered) {
         for (;;) {
@@ -466,7 +479,7 @@ size_t index_rows_lds_bytes(uint32_t k) { return (size_t)index_rows_waves(k) * k
 int index_rows_blocks_per_cu(uint32_t k)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, index_rows_kernel<false>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, index_rows_kernel<false, kBatch>,
                                                      index_rows_waves(k) * kWave,
                                                      index_rows_lds_bytes(k)) != hipSuccess)
         return 1;
@@ -478,25 +491,39 @@ hipError_t launch_index_rows(const Rows &rows, const IndexBuffers &ix, const Bou
                              hipStream_t stream)
 {
     if (rows.n_rows == 0) return hipSuccess;
-    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(row_counter), 0u, 2, stream);
-    if (e != hipSuccess) return e;
     const uint32_t waves = index_rows_waves(k);
     const uint64_t need = (rows.n_rows + waves - 1) / waves;
     const uint32_t g = (uint32_t)std::min<uint64_t>(need, grid);
     // every hash of a step-order row is <= T1 with probability >= 1 - 1/16, <= T2 with >= 1 - 1e-4
     const double log_first = std::log(kIndexFirstMiss / (double)k);
     const double log_final = std::log(kIndexFinalMiss / (double)k);
+    // Long lists (text-like: ~1000 keys each) read 16 keys per trip, short ones (~16 keys, as
+    // for D = 2^20 and k = 256) 8; large batches hand out rows from a counter, small ones (a
+    // serving request) by a fixed stride, which measured faster there.
+    const bool long_lists = (double)k * kIndexSteps / (double)b.dims >= 64.0;
+    const bool claim_rows = rows.n_rows >= 16ull * g * waves;
+    if (claim_rows || rows.row_class) {
+        const hipError_t e =
+            launch_fill_u32(reinterpret_cast<uint32_t *>(row_counter), 0u, 2, stream);
+        if (e != hipSuccess) return e;
+    }
     // a filtered launch claims rows 64 at a time: one wavefront takes at most every 64th row
     const uint64_t need_filtered = (rows.n_rows + kWave * waves - 1) / (kWave * waves);
-    if (rows.row_class)
-        index_rows_kernel<true><<<(uint32_t)std::min<uint64_t>(need_filtered, g), waves * kWave,
-                                  index_rows_lds_bytes(k), stream>>>(
-            rows, ix.offsets, ix.entries, ix.by_step, b.bound, b.total, b.dims, k, log_first,
-            log_final, row_counter, sig);
-    else
-        index_rows_kernel<false><<<g, waves * kWave, index_rows_lds_bytes(k), stream>>>(
-            rows, ix.offsets, ix.entries, ix.by_step, b.bound, b.total, b.dims, k, log_first,
-            log_final, row_counter, sig);
+    const uint32_t gf = (uint32_t)std::min<uint64_t>(need_filtered, g);
+    const size_t lds = index_rows_lds_bytes(k);
+    const uint32_t threads = waves * kWave;
+#define WMH_INDEX_ROWS(F, B, G)                                                                    \
+    index_rows_kernel<F, B><<<G, threads, lds, stream>>>(rows, ix.offsets, ix.entries, ix.by_step, \
+                                                         b.bound, b.total, b.dims, k, log_first,  \
+                                                         log_final, row_counter, claim_rows, sig)
+    if (rows.row_class) {
+        if (long_lists) WMH_INDEX_ROWS(true, kBatch, gf);
+        else WMH_INDEX_ROWS(true, kShortBatch, gf);
+    } else {
+        if (long_lists) WMH_INDEX_ROWS(false, kBatch, g);
+        else WMH_INDEX_ROWS(false, kShortBatch, g);
+    }
+#undef WMH_INDEX_ROWS
     return hipGetLastError();
 }
 

@@ -181,7 +181,7 @@ inline uint64_t index_scan_blocks(uint32_t dims) { return ((uint64_t)dims + 1 + 
 hipError_t launch_index_build(const Bounds &b, uint64_t seed, uint32_t k, const IndexBuffers &ix,
                               hipStream_t stream);
 
-// row_counter: one device word, cleared by the launch (rows are claimed from it).
+// row_counter: one device word, cleared by launches that claim rows from it.
 hipError_t launch_index_rows(const Rows &rows, const IndexBuffers &ix, const Bounds &b, uint32_t k,
                              uint16_t *sig, unsigned long long *row_counter, uint32_t grid,
                              hipStream_t stream);
