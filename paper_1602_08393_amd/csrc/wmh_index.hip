@@ -349,12 +349,16 @@ __global__ __launch_bounds__(256) void index_rows_kernel(Rows rows,
         sx = wave_sum64(sx);
         sm = wave_sum64(sm);
         const bool live = sx != 0;
-        // step bounds T1 <= T2 of the row and the cheaper key order (uniform over the wavefront)
+        // step bounds T1 <= T2 of the row and the cheaper key order (uniform over the wavefront).
+        // Where lists are short a pass reads about one batch per nonzero whatever its bound, so
+        // a first pass to T1 saves little and the second costs a whole pass: one pass to T2.
+        constexpr bool kTwoPass = B == kBatch;
         uint32_t T1 = kCap, T2 = kCap;
         bool by_steps = false;
         if (live && by_step) {
             const double s = (double)sx / (double)total;
-            const double t1 = index_step_bound(s, log_first), t2 = index_step_bound(s, log_final);
+            const double t2 = index_step_bound(s, log_final);
+            const double t1 = kTwoPass ? index_step_bound(s, log_first) : t2;
             T1 = t1 < (double)kCap ? (uint32_t)t1 : kCap;
             T2 = t2 < (double)kCap ? (uint32_t)t2 : kCap;
             by_steps = T2 < kCap - 1u && t2 * (double)sm < 65534.0 * (double)sx;
@@ -377,7 +381,7 @@ __global__ __launch_bounds__(256) void index_rows_kernel(Rows rows,
             return __ballot(open) != 0;
         };
         if (by_steps && any_open(T1)) {
-            if (T2 > T1) {
+            if (kTwoPass && T2 > T1) {
                 for (uint64_t e = lo + ln; e < hi; e += kWave) {
                     const uint32_t c = rows.col[e];
                     const uint32_t x = rows.val[e];
