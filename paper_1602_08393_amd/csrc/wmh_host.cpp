@@ -182,7 +182,7 @@ constexpr double kCostPlainSparseStep = 24.0;  // a step of the plain walk, bina
 constexpr double kCostPerRowHash = 2.0;        // writing one signature value (either order)
 constexpr double kCostIndexEntry = 64.0;       // building one index key (two draws, sort)
 constexpr double kCostIndexNnz = 64.0;         // a nonzero's list lookup (dependent loads)
-constexpr double kCostIndexKey = 16.0;         // one green key read and its LDS minimum
+constexpr double kCostIndexKey = 20.0;         // one green key read and its LDS minimum
 }  // namespace
 
 wmh_status gather_stats(wmh_ctx *ctx, const Rows &rows, uint32_t k, hipStream_t s, bool check,
