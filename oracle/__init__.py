@@ -12,8 +12,6 @@ it through ctypes and adds the exact rational quantities the tests compare again
   A collision happens at step t < H when the first t-1 draws miss both green regions and draw t
   hits both; every pair that reaches step H collides.  This tends to eq. 1 as H grows
   (Theorem 1).
-* ``geometric_pmf``      -- Theorem 2: the step count is geometric on {1, 2, ...} with success
-  probability s = sum(x) / M (eq. sparsity).
 """
 from __future__ import annotations
 
@@ -230,13 +228,3 @@ def capped_collision(x: Sequence[int], y: Sequence[int], M: int, cap: int) -> Fr
     n = 1.0 - either / M
     tail = n ** (cap - 1)
     return a * (1.0 - tail) / (1.0 - n) + tail
-
-
-def sparsity(x: Sequence[int], M: int) -> Fraction:
-    """eq. sparsity: the probability that one draw is green."""
-    return Fraction(sum(int(v) for v in x), M)
-
-
-def geometric_pmf(s: float, t: int) -> float:
-    """Theorem 2: Pr(h = t) = (1 - s)^(t-1) s on {1, 2, ...}."""
-    return (1.0 - s) ** (t - 1) * s
