@@ -196,6 +196,17 @@ wmh_status wmh_estimate(wmh_ctx *ctx, const uint16_t *A, const uint16_t *B, uint
                         uint32_t k, uint32_t *count, double *jhat, void *stream);
 
 /*
+ * wmh_estimate_pair -- the estimate for one pair of signatures held in host memory
+ * (eq. Estimator):  *count = #{j < k : a[j] == b[j]},  *jhat = *count / k (IEEE double).
+ *   a, b : host, k uint16 each (signatures as wmh_hash writes them).   count, jhat : host
+ *   outputs (either may be NULL, not both).
+ * Needs no context and touches no device; two empty rows (all-zero signatures) give jhat = 1.
+ * Errors: WMH_E_ARG (null input, k = 0, both outputs NULL).
+ */
+wmh_status wmh_estimate_pair(const uint16_t *a, const uint16_t *b, uint32_t k, uint32_t *count,
+                             double *jhat);
+
+/*
  * wmh_collisions -- all-pairs collision counts (eq. Estimator's numerator):
  *   counts[a*NB + b] = #{j < k : A[a*k + j] == B[b*k + j]}  (exact uint32).
  *   A : device, NA*k uint16.  B : device, NB*k uint16.  counts : device, NA*NB uint32.

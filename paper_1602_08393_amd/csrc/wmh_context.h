@@ -125,7 +125,7 @@ struct wmh_ctx {
     wmh::CheckWords *h_check = nullptr;  // pinned
     uint8_t *d_row_class = nullptr;      // row split: one class byte per row
     uint64_t row_class_cap = 0;
-    uint32_t *d_tile_counter = nullptr;
+    unsigned long long *d_tile_counter = nullptr;
     unsigned long long *d_row_counter = nullptr;  // rows claimed by the index rows kernel
     unsigned long long *d_codec = nullptr;  // codec counters: saturated values, maximum
     unsigned long long *h_codec = nullptr;  // pinned copy

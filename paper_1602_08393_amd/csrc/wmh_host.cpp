@@ -437,7 +437,7 @@ wmh_status wmh_create(int device, wmh_ctx **out)
         hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) != hipSuccess ||
         hipMalloc(&ctx->d_check, sizeof(CheckWords)) != hipSuccess ||
         hipHostMalloc(&ctx->h_check, sizeof(CheckWords), hipHostMallocDefault) != hipSuccess ||
-        hipMalloc(&ctx->d_tile_counter, sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&ctx->d_tile_counter, sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&ctx->d_row_counter, sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&ctx->d_codec, 2 * sizeof(unsigned long long)) != hipSuccess ||
         hipHostMalloc(&ctx->h_codec, 2 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
@@ -713,7 +713,7 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
 
         // events around the walk only on direct launches; a graph is timed as a whole
         auto enqueue = [&](hipStream_t q, bool events) -> hipError_t {
-            hipError_t e = launch_fill_u32(ctx->d_tile_counter, 0u, 1, q);
+            hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->d_tile_counter), 0u, 2, q);
             if (e != hipSuccess) return e;
             if (events && (e = hipEventRecord(ctx->ev[1], q)) != hipSuccess) return e;
             e = launch_batched(b, wrows, k, seed, sig, pl, ctx->d_stream, ctx->d_tile_counter,
@@ -853,6 +853,17 @@ wmh_status wmh_estimate(wmh_ctx *ctx, const uint16_t *A, const uint16_t *B, uint
     hipStream_t s = pick_stream(ctx, stream);
     WMH_HIP(ctx, launch_estimate(A, B, n_pairs, k, count, jhat, s));
     WMH_HIP(ctx, hipStreamSynchronize(s));
+    return WMH_OK;
+}
+
+wmh_status wmh_estimate_pair(const uint16_t *a, const uint16_t *b, uint32_t k, uint32_t *count,
+                             double *jhat)
+{
+    if (!a || !b || k == 0 || (!count && !jhat)) return WMH_E_ARG;
+    uint32_t equal = 0;
+    for (uint32_t j = 0; j < k; ++j) equal += a[j] == b[j];
+    if (count) *count = equal;
+    if (jhat) *jhat = (double)equal / (double)k;
     return WMH_OK;
 }
 

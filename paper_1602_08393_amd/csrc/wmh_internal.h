@@ -117,7 +117,7 @@ hipError_t launch_stream_build(const Bounds &b, uint64_t seed, uint32_t k, uint3
 // Returns hipErrorInvalidValue when the plan does not fit (LDS).
 hipError_t launch_batched(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
                           uint16_t *sig, const BatchedPlan &plan, const void *entries,
-                          uint32_t *tile_counter, uint32_t grid, hipStream_t stream);
+                          unsigned long long *tile_counter, uint32_t grid, hipStream_t stream);
 
 // Dynamic LDS bytes a batched plan needs.
 size_t batched_lds_bytes(uint32_t dims, const BatchedPlan &plan);
@@ -125,13 +125,13 @@ size_t batched_lds_bytes(uint32_t dims, const BatchedPlan &plan);
 // The shared-window walk (no checks: launch_batched validates the plan) and its occupancy.
 hipError_t launch_shared_walk(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
                               uint16_t *sig, const BatchedPlan &plan, const void *entries,
-                              uint32_t *tile_counter, uint32_t grid, hipStream_t stream);
+                              unsigned long long *tile_counter, uint32_t grid, hipStream_t stream);
 int shared_walk_blocks_per_cu(const BatchedPlan &plan, size_t lds);
 
 // The ballot walk (R = 1, K = 1; no checks) and its occupancy.
 hipError_t launch_ballot_walk(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
                               uint16_t *sig, const BatchedPlan &plan, const void *entries,
-                              uint32_t *tile_counter, uint32_t grid, hipStream_t stream);
+                              unsigned long long *tile_counter, uint32_t grid, hipStream_t stream);
 int ballot_walk_blocks_per_cu(const BatchedPlan &plan, size_t lds);
 
 // Resident workgroups per CU for a batched plan (0 when it does not fit).

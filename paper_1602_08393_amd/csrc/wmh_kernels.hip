@@ -115,6 +115,8 @@ __global__ __launch_bounds__(1024) void validate_kernel(Rows rows, const uint32_
         const uint64_t hi = rows.row_ptr[r + 1];
         if (lo > hi || hi > rows.nnz) {
             w_err = min(w_err, (unsigned long long)((r << 4) | kCheckRowPtr));
+            // a row split without the check still runs: the bad row gets a valid class byte
+            if (classify && lane() == 0) split.row_class[r] = 0;
             continue;
         }
         uint64_t sum = 0, sum_m = 0;  // sum(x) and sum(m_c) over the row's nonzeros
@@ -158,6 +160,7 @@ __global__ __launch_bounds__(1024) void validate_kernel(Rows rows, const uint32_
         }
         if (__builtin_amdgcn_ballot_w64(bad != ~0ull) != 0) {  // some entry of the row is bad
             w_err = min(w_err, (unsigned long long)((r << 4) | (wave_min(bad) & 15u)));
+            if (classify && lane() == 0) split.row_class[r] = 0;
             continue;
         }
         sum = wave_sum(sum);
@@ -421,13 +424,13 @@ template <typename XT, bool kPacked>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void rows_kernel(
     Bounds b, Rows rows, uint32_t k, uint64_t seed, uint16_t *__restrict__ sig,
     uint32_t hashes_per_tile, uint32_t depth, const void *__restrict__ entries,
-    uint32_t *tile_counter)
+    unsigned long long *tile_counter)
 {
     constexpr uint32_t R = 4, L = 16, K = 4;
     constexpr uint32_t kLastBase = kCap + 1u - kWave;  // window of steps 65473 .. 65536
     constexpr uint32_t kNone = 0xFFFFu;                // no green step in the lane's steps
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint32_t tile_slot;
+    __shared__ unsigned long long tile_slot;
     __shared__ uint32_t nonempty;
     const uint32_t D = b.dims;
     XT *x = reinterpret_cast<XT *>(smem);
@@ -447,7 +450,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     uint64_t staged = ~0ull;
 
     while (true) {
-        if (threadIdx.x == 0) tile_slot = atomicAdd(tile_counter, 1u);
+        if (threadIdx.x == 0) tile_slot = atomicAdd(tile_counter, 1ull);
         __syncthreads();
         const uint64_t tile = tile_slot;
         if (tile >= n_tiles) break;
@@ -717,7 +720,7 @@ static int rows_occupancy_t(const BatchedPlan &plan, size_t lds)
 template <typename XT, bool kPacked>
 static hipError_t launch_rows_t(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
                                 uint16_t *sig, const BatchedPlan &plan, const void *entries,
-                                uint32_t *tile_counter, uint32_t grid, hipStream_t stream)
+                                unsigned long long *tile_counter, uint32_t grid, hipStream_t stream)
 {
     const size_t lds = batched_lds_bytes(b.dims, plan);
     configure_rows<XT, kPacked>();
@@ -728,7 +731,7 @@ static hipError_t launch_rows_t(const Bounds &b, const Rows &rows, uint32_t k, u
 
 hipError_t launch_batched(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
                           uint16_t *sig, const BatchedPlan &plan, const void *entries,
-                          uint32_t *tile_counter, uint32_t grid, hipStream_t stream)
+                          unsigned long long *tile_counter, uint32_t grid, hipStream_t stream)
 {
     if (batched_lds_bytes(b.dims, plan) > 160 * 1024 - 64) return hipErrorInvalidValue;
     if (plan.packed && !plan.narrow) return hipErrorInvalidValue;

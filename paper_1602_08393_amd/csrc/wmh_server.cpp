@@ -60,7 +60,7 @@ struct Slot {
     uint16_t *d_sig = nullptr;
     uint16_t *h_sig = nullptr;  // pinned staging of the signatures
     uint64_t cap_rows = 0, cap_col = 0, cap_val = 0, cap_sig = 0, cap_h_sig = 0;
-    uint32_t *d_tile_counter = nullptr;
+    unsigned long long *d_tile_counter = nullptr;
     unsigned long long *d_row_counter = nullptr;
     CheckWords *d_check = nullptr;  // the validation pass's words
     CheckWords *h_check = nullptr;  // pinned copy, read once `checked` has fired
@@ -192,7 +192,7 @@ wmh_status wmh_server::launch_compute(Slot &slot, Request &r)
         if (e == hipSuccess) e = hipEventRecord(index.used, s);
     } else if (e == hipSuccess) {
         if (batched) {
-            e = launch_fill_u32(slot.d_tile_counter, 0u, 1, s);
+            e = launch_fill_u32(reinterpret_cast<uint32_t *>(slot.d_tile_counter), 0u, 2, s);
             if (e == hipSuccess)
                 e = launch_batched(b, rows, k, cfg.seed, slot.d_sig, plan, d_stream,
                                    slot.d_tile_counter, grid, s);
@@ -356,7 +356,7 @@ wmh_status wmh_server_create(wmh_ctx *ctx, const wmh_server_config *cfg_in, wmh_
     for (Slot &slot : srv->slots) {
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&slot.finished, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipMalloc(&slot.d_tile_counter, sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(&slot.d_tile_counter, sizeof(unsigned long long));
         if (e == hipSuccess) e = hipMalloc(&slot.d_row_counter, sizeof(unsigned long long));
         if (e == hipSuccess) e = hipEventCreateWithFlags(&slot.checked, hipEventDisableTiming);
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&slot.d_check), sizeof(CheckWords));

@@ -123,7 +123,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
                                                        uint64_t seed, uint16_t *__restrict__ sig,
                                                        uint32_t hashes_per_tile, uint32_t depth,
                                                        const void *entries,
-                                                       uint32_t *tile_counter)
+                                                       unsigned long long *tile_counter)
 {
     // Lane layout of one window: lane l serves row r = l / L (L = 64 / R lanes per row) and
     // the K consecutive steps base + g*K + 1 .. base + g*K + K, g = l mod L; the 64 lanes
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
     constexpr uint32_t L = kWave / R;
     constexpr uint32_t kWin = L * K;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint32_t tile_slot;
+    __shared__ unsigned long long tile_slot;
     __shared__ uint32_t unit_slot;
     __shared__ uint32_t nonempty;
     const uint32_t D = b.dims;
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
 
     while (true) {
         if (threadIdx.x == 0) {
-            tile_slot = atomicAdd(tile_counter, 1u);
+            tile_slot = atomicAdd(tile_counter, 1ull);
             unit_slot = 0;
         }
         __syncthreads();
@@ -308,11 +308,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
 template <typename XT, bool kPacked>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void ballot_kernel(
     Bounds b, Rows rows, uint32_t k, uint64_t seed, uint16_t *__restrict__ sig,
-    uint32_t hashes_per_tile, uint32_t depth, const void *entries, uint32_t *tile_counter)
+    uint32_t hashes_per_tile, uint32_t depth, const void *entries, unsigned long long *tile_counter)
 {
     constexpr uint32_t kWords = EntryRun<1, kPacked>::kWordsPerEntry;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint32_t tile_slot;
+    __shared__ unsigned long long tile_slot;
     __shared__ uint32_t unit_slot;
     __shared__ uint32_t nonempty;
     const uint32_t D = b.dims;
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
 
     while (true) {
         if (threadIdx.x == 0) {
-            tile_slot = atomicAdd(tile_counter, 1u);
+            tile_slot = atomicAdd(tile_counter, 1ull);
             unit_slot = 0;
         }
         __syncthreads();
@@ -444,7 +444,7 @@ int batched_occupancy_t(const BatchedPlan &plan, size_t lds)
 template <typename XT, int R, int K, bool kPacked>
 hipError_t launch_batched_t(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
                                    uint16_t *sig, const BatchedPlan &plan, const void *entries,
-                                   uint32_t *tile_counter, uint32_t grid, hipStream_t stream)
+                                   unsigned long long *tile_counter, uint32_t grid, hipStream_t stream)
 {
     const size_t lds = batched_lds_bytes(b.dims, plan);
     configure_batched<XT, R, K, kPacked>();
@@ -478,7 +478,7 @@ int ballot_occupancy_t(const BatchedPlan &plan, size_t lds)
 template <typename XT, bool kPacked>
 hipError_t launch_ballot_t(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
                            uint16_t *sig, const BatchedPlan &plan, const void *entries,
-                           uint32_t *tile_counter, uint32_t grid, hipStream_t stream)
+                           unsigned long long *tile_counter, uint32_t grid, hipStream_t stream)
 {
     const size_t lds = batched_lds_bytes(b.dims, plan);
     configure_ballot<XT, kPacked>();
@@ -515,7 +515,7 @@ template <typename XT, int R, int K, bool kPacked>
 struct LaunchBatched {
     static hipError_t run(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
                           uint16_t *sig, const BatchedPlan &plan, const void *entries,
-                          uint32_t *tile_counter, uint32_t grid, hipStream_t stream)
+                          unsigned long long *tile_counter, uint32_t grid, hipStream_t stream)
     {
         return launch_batched_t<XT, R, K, kPacked>(b, rows, k, seed, sig, plan, entries,
                                                    tile_counter, grid, stream);
@@ -536,7 +536,7 @@ struct OccupancyBatched {
 
 hipError_t launch_shared_walk(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
                               uint16_t *sig, const BatchedPlan &plan, const void *entries,
-                              uint32_t *tile_counter, uint32_t grid, hipStream_t stream)
+                              unsigned long long *tile_counter, uint32_t grid, hipStream_t stream)
 {
     return dispatch_batched<LaunchBatched>(plan, b, rows, k, seed, sig, plan, entries,
                                            tile_counter, grid, stream);
@@ -549,7 +549,7 @@ int shared_walk_blocks_per_cu(const BatchedPlan &plan, size_t lds)
 
 hipError_t launch_ballot_walk(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
                               uint16_t *sig, const BatchedPlan &plan, const void *entries,
-                              uint32_t *tile_counter, uint32_t grid, hipStream_t stream)
+                              unsigned long long *tile_counter, uint32_t grid, hipStream_t stream)
 {
     if (plan.narrow)
         return plan.packed

@@ -23,7 +23,7 @@ MODES = {"auto": 0, "plain": 1, "batched": 2, "indexed": 3, "split": 4}
 WALKS = {"auto": 0, "shared": 1, "rows": 2, "ballot": 3}
 
 EXPORTED = ["wmh_opts_init", "wmh_create", "wmh_destroy", "wmh_set_bounds", "wmh_hash",
-            "wmh_estimate", "wmh_collisions", "wmh_bounds_info", "wmh_bounds_tables",
+            "wmh_estimate", "wmh_estimate_pair", "wmh_collisions", "wmh_bounds_info", "wmh_bounds_tables",
             "wmh_draws", "wmh_last_kernel_ms", "wmh_last_mode", "wmh_last_plan",
             "wmh_tune", "wmh_tune_save", "wmh_tune_load", "wmh_pack_words", "wmh_sig_bits",
             "wmh_pack", "wmh_unpack", "wmh_packed_collisions", "wmh_packed_estimate",
@@ -104,6 +104,9 @@ def load() -> ctypes.CDLL:
     L.wmh_hash.restype = ctypes.c_int
     L.wmh_estimate.argtypes = [vp, vp, vp, u64, u32, vp, vp, vp]
     L.wmh_estimate.restype = ctypes.c_int
+    L.wmh_estimate_pair.argtypes = [vp, vp, u32, ctypes.POINTER(u32),
+                                    ctypes.POINTER(ctypes.c_double)]
+    L.wmh_estimate_pair.restype = ctypes.c_int
     L.wmh_collisions.argtypes = [vp, vp, u64, vp, u64, u32, vp, vp]
     L.wmh_collisions.restype = ctypes.c_int
     L.wmh_bounds_info.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u64),
@@ -190,6 +193,20 @@ def choose_scale(m, limit: int = 0, components: int = 0, steps: int = 0):
     if st != 0:
         raise WMHError(st, "wmh_choose_scale")
     return a.value, eff.value, mq
+
+
+def estimate_pair(a, b):
+    """Host-only estimate of one pair of host signatures (see wmh_estimate_pair): (count, jhat)."""
+    a = np.ascontiguousarray(a, dtype=np.uint16)
+    b = np.ascontiguousarray(b, dtype=np.uint16)
+    if a.shape != b.shape or a.ndim != 1:
+        raise ValueError("two signatures of the same length expected")
+    count, jhat = ctypes.c_uint32(), ctypes.c_double()
+    st = load().wmh_estimate_pair(a.ctypes.data, b.ctypes.data, len(a), ctypes.byref(count),
+                                  ctypes.byref(jhat))
+    if st != 0:
+        raise WMHError(st, "wmh_estimate_pair")
+    return count.value, jhat.value
 
 
 def bounds_tables(m: np.ndarray) -> dict:

@@ -138,3 +138,19 @@ def test_package_import_does_not_load_native_code():
         text = open(os.path.join(ROOT, "paper_1602_08393_amd", "csrc", name)).read()
         assert "oracle" not in text.lower(), name
     assert sys.modules.get("paper_1602_08393_amd") is not None
+
+
+def test_host_pair_estimate(lib):
+    rng = np.random.Generator(np.random.PCG64(3))
+    for k in (1, 7, 500, 4099):
+        a = rng.integers(0, 6, size=k).astype(np.uint16)
+        b = rng.integers(0, 6, size=k).astype(np.uint16)
+        count, jhat = wmh.estimate_pair(a, b)
+        want = sum(1 for j in range(k) if int(a[j]) == int(b[j]))
+        assert count == want and jhat == want / k
+    z = np.zeros(9, dtype=np.uint16)
+    assert wmh.estimate_pair(z, z) == (9, 1.0)  # two empty rows
+    c = ctypes.c_uint32()
+    assert lib.wmh_estimate_pair(z.ctypes.data, z.ctypes.data, 0, ctypes.byref(c), None) == -1
+    assert lib.wmh_estimate_pair(None, z.ctypes.data, 9, ctypes.byref(c), None) == -1
+    assert lib.wmh_estimate_pair(z.ctypes.data, z.ctypes.data, 9, None, None) == -1
