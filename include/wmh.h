@@ -172,6 +172,32 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
                     uint64_t seed, uint16_t *sig, void *stream, const wmh_opts *opts);
 
 /*
+ * wmh_hash_noalloc -- wmh_hash's batched walk for callers that cannot allocate device memory
+ * during a call: code under hipGraph capture, tight serving loops, harnesses that forbid
+ * allocation.  It allocates nothing (no hipMalloc, no hipFree, no allocating library call):
+ * the tile counter, the validation words and the shared position stream live in one static
+ * device array of WMH_NOALLOC_SCRATCH_BYTES per device, held from the first wmh_create on that
+ * device until the process ends.  Arguments, layouts and results are those of wmh_hash, with
+ * these differences:
+ *   - opts->mode must be WMH_MODE_AUTO or WMH_MODE_BATCHED; both run the batched walk (no
+ *     plain walk, no component index, no row split), launched directly (no graph).  The tile
+ *     plan options and the autotuned plans apply as in wmh_hash.
+ *   - The shared stream is rebuilt on every call inside the static array.  The planner's depth
+ *     shrinks to what fits (steps past it are drawn in-lane, with identical values); a
+ *     stream_depth given in opts, or the independent-rows walk's stream, whose bytes
+ *     ((depth * k + 3 windows) * 4 or 8) exceed the array, is rejected with WMH_E_ARG.
+ *   - Every call on one device shares the array and finds the last call's contents, which it
+ *     re-initialises; calls that overlap on one device (other host threads, other streams with
+ *     opts->sync = 0) race on it and must be ordered by the caller.
+ * Errors: those of wmh_hash, plus WMH_E_ARG for another mode, a plan that does not fit in LDS,
+ * or a stream beyond the array; WMH_E_DEVICE when the array's address could not be found.
+ */
+#define WMH_NOALLOC_SCRATCH_BYTES (16u << 20)
+wmh_status wmh_hash_noalloc(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
+                            const uint32_t *val, uint64_t n_rows, uint64_t nnz, uint32_t k,
+                            uint64_t seed, uint16_t *sig, void *stream, const wmh_opts *opts);
+
+/*
  * wmh_draws -- the position sequence itself and its component lookup (Algorithm 3's draws,
  * Algorithm 5's ISGREEN lookup), as the hash kernels compute them.  For hash ids
  * j0 <= j < j0 + n_hashes and steps 1 <= t <= depth, with i = (j - j0) * depth + t - 1:

@@ -14,7 +14,8 @@ LIB = os.path.join(HERE, "libwmh.so")
 SOURCES = ["wmh_host.cpp", "wmh_server.cpp", "wmh_kernels.hip", "wmh_walk.hip", "wmh_collide.hip",
            "wmh_index.hip",
            "wmh_tune.cpp", "wmh_codec.hip", "wmh_codec_host.cpp",
-           "wmh_quantize.hip", "wmh_scale.cpp", "wmh_lsh.hip", "wmh_lsh_host.cpp"]
+           "wmh_quantize.hip", "wmh_scale.cpp", "wmh_lsh.hip", "wmh_lsh_host.cpp",
+           "wmh_noalloc.hip"]
 ARCH = "gfx950"
 # Per-file options.  The shared-window walk's branches are all scalar; leaving such regions
 # unstructured lets its early loop exits leave the loop directly, which keeps the waits for its

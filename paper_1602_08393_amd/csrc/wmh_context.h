@@ -166,8 +166,10 @@ TuneKey tune_key(const wmh_ctx *ctx, uint32_t k, const RowStats &stats);
 // Validation pass on the device: checks the rows (when check) and fills *stats; waits.
 // want_keys: also estimate index_keys (only the path choice in auto mode reads it);
 // want_split (with want_keys): also class every row for a row split (ctx->d_row_class).
+// words: device words the pass writes (nullptr: the context's own).
 wmh_status gather_stats(wmh_ctx *ctx, const Rows &rows, uint32_t k, hipStream_t s, bool check,
-                        bool want_keys, RowStats *stats, bool want_split = false);
+                        bool want_keys, RowStats *stats, bool want_split = false,
+                        CheckWords *words = nullptr);
 // Whether an index for k hashes is allowed (k and memory limits).
 bool index_fits(uint32_t k);
 // Makes `ix` the index of (ctx's bounds, seed, k), building it on `stream` when stale.
@@ -182,5 +184,9 @@ Path choose_path(const wmh_ctx *ctx, int mode, bool batched_ok, bool index_ready
                  uint64_t n_rows, uint64_t nnz, const RowStats &stats, bool split_ok = false);
 // The statistics of the rows a split walks, as plan_batched reads them.
 RowStats walk_class_stats(const RowStats &stats);
+
+// The static device scratch of wmh_hash_noalloc (wmh_noalloc.hip): looks up its address on
+// `device`, which must be current, once per device; later calls return the first result.
+hipError_t static_scratch_init(int device);
 
 }  // namespace wmh

@@ -186,8 +186,9 @@ constexpr double kCostIndexKey = 20.0;         // one green key read and its LDS
 }  // namespace
 
 wmh_status gather_stats(wmh_ctx *ctx, const Rows &rows, uint32_t k, hipStream_t s, bool check,
-                        bool want_keys, RowStats *stats, bool want_split)
+                        bool want_keys, RowStats *stats, bool want_split, CheckWords *words)
 {
+    if (!words) words = ctx->d_check;
     RowSplit split;
     want_split = want_split && want_keys;
     if (want_split) {
@@ -204,12 +205,12 @@ wmh_status gather_stats(wmh_ctx *ctx, const Rows &rows, uint32_t k, hipStream_t 
         split.key_cost = (float)kCostIndexKey;
         split.nnz_cost = (float)kCostIndexNnz;
     }
-    hipError_t e = launch_check_init(ctx->d_check, s);
+    hipError_t e = launch_check_init(words, s);
     if (e == hipSuccess)
-        e = launch_validate(rows, ctx->d_bound, ctx->dims, ctx->total, k, want_keys, ctx->d_check, s,
+        e = launch_validate(rows, ctx->d_bound, ctx->dims, ctx->total, k, want_keys, words, s,
                             want_split ? &split : nullptr);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(ctx->h_check, ctx->d_check, sizeof(CheckWords), hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync(ctx->h_check, words, sizeof(CheckWords), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return device_fail(ctx, e, "validation pass");
     const CheckWords v = *ctx->h_check;
@@ -448,6 +449,9 @@ wmh_status wmh_create(int device, wmh_ctx **out)
         return WMH_E_DEVICE;
     }
     ctx->cu_count = prop.multiProcessorCount;
+    // the address of the no-allocation entry point's static scratch on this device; a failure
+    // here is reported by that entry point, not by the context
+    (void)static_scratch_init(device);
     *out = ctx;
     return WMH_OK;
 }

@@ -19,10 +19,12 @@ CAP = 65535
 STATUS = {0: "WMH_OK", -1: "WMH_E_ARG", -2: "WMH_E_NO_BOUNDS", -3: "WMH_E_COL_RANGE",
           -4: "WMH_E_UNSORTED", -5: "WMH_E_BOUND", -6: "WMH_E_OVERFLOW", -7: "WMH_E_NOMEM",
           -8: "WMH_E_DEVICE", -9: "WMH_E_ROW_PTR"}
+NOALLOC_SCRATCH_BYTES = 16 << 20  # WMH_NOALLOC_SCRATCH_BYTES: wmh_hash_noalloc's static array
 MODES = {"auto": 0, "plain": 1, "batched": 2, "indexed": 3, "split": 4}
 WALKS = {"auto": 0, "shared": 1, "rows": 2, "ballot": 3}
 
 EXPORTED = ["wmh_opts_init", "wmh_create", "wmh_destroy", "wmh_set_bounds", "wmh_hash",
+            "wmh_hash_noalloc",
             "wmh_estimate", "wmh_estimate_pair", "wmh_collisions", "wmh_bounds_info", "wmh_bounds_tables",
             "wmh_draws", "wmh_last_kernel_ms", "wmh_last_mode", "wmh_last_plan",
             "wmh_tune", "wmh_tune_save", "wmh_tune_load", "wmh_pack_words", "wmh_sig_bits",
@@ -102,6 +104,9 @@ def load() -> ctypes.CDLL:
     L.wmh_set_bounds.restype = ctypes.c_int
     L.wmh_hash.argtypes = [vp, vp, vp, vp, u64, u64, u32, u64, vp, vp, ctypes.POINTER(WmhOpts)]
     L.wmh_hash.restype = ctypes.c_int
+    L.wmh_hash_noalloc.argtypes = [vp, vp, vp, vp, u64, u64, u32, u64, vp, vp,
+                                   ctypes.POINTER(WmhOpts)]
+    L.wmh_hash_noalloc.restype = ctypes.c_int
     L.wmh_estimate.argtypes = [vp, vp, vp, u64, u32, vp, vp, vp]
     L.wmh_estimate.restype = ctypes.c_int
     L.wmh_estimate_pair.argtypes = [vp, vp, u32, ctypes.POINTER(u32),
@@ -422,6 +427,19 @@ class Context:
                                 ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), sig.data_ptr(),
                                 self._stream(stream), ctypes.byref(opts))
         self._check(st, "wmh_hash")
+        return sig
+
+    def hash_noalloc_into(self, rows: DeviceRows, k: int, seed: int, sig, stream=None,
+                          opts=None):
+        """wmh_hash_noalloc (the batched walk with its scratch in the library's static device
+        array; allocates nothing): sig is a device int16 tensor of N*k elements."""
+        if opts is None:
+            opts = self.make_opts(mode="batched")
+        st = self._lib.wmh_hash_noalloc(self._ptr, rows.row_ptr.data_ptr(), rows.col.data_ptr(),
+                                        rows.val.data_ptr(), rows.n_rows, rows.nnz, k,
+                                        ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF),
+                                        sig.data_ptr(), self._stream(stream), ctypes.byref(opts))
+        self._check(st, "wmh_hash_noalloc")
         return sig
 
     def hash(self, rows: DeviceRows, k: int, seed: int = 0, stream=None, **opt_kwargs):
