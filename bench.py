@@ -25,7 +25,10 @@ if ROOT not in sys.path:
 
 PEAK_INT_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3
 HBM_PEAK_GBS = 8000.0
+PCIE_PEAK_GBS = 64.0  # PCIe 5.0 x16, per direction
 OPS_PER_TEST = 2  # one lookup of x at the draw's component and one compare
+OPS_PER_COMPARE = 2  # collision counting: one u16 equality and one accumulate per hash pair
+KEY_BYTES = 8  # one component-index key
 # HBM bytes per launch of batched_kernel<unsigned short, 4, true> on the full histogram-shaped
 # workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy (read x2.000,
 # write x1.000); profiles/batched_kernel_histogram_k500.txt.  Valid while that kernel and plan
@@ -35,6 +38,54 @@ TRAFFIC_R4_HISTOGRAM = 1.2029e9 + 0.1009e9
 
 def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
+
+
+def alu_roofline(tests: int, kernel_ms: float, kernel: str, traffic=None, note=None) -> dict:
+    """Integer-ALU roofline of a walk: 2 operations per membership test (Definition 1: a hash of
+    value h is h tests) over the kernels' time."""
+    achieved = OPS_PER_TEST * tests / (kernel_ms / 1e3) / 1e12
+    out = {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS, "unit": "TOP/s",
+           "frac": achieved / PEAK_INT_TOPS, "traffic": traffic, "kernel": kernel,
+           "kernel_ms": kernel_ms, "membership_tests": tests, "ops_per_test": OPS_PER_TEST}
+    if note:
+        out["note"] = note
+    return out
+
+
+def hbm_roofline(nbytes: float, kernel_ms: float, kernel: str, note=None) -> dict:
+    achieved = nbytes / (kernel_ms / 1e3) / 1e9
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
+           "kernel_ms": kernel_ms, "algorithmic_bytes": nbytes}
+    if note:
+        out["note"] = note
+    return out
+
+
+def index_key_bytes(ds, k: int) -> tuple[float, dict]:
+    """Algorithmic bytes of the component-index rows kernel on ds: the keys its evaluation
+    order must read, in expectation (Theorem 2: Pr(h > T) = (1 - s)^T), plus the rows once and
+    the signatures once.  Offset order reads every green key of a row's lists (65534 k s keys);
+    step order reads the lists up to T1 (all k hashes <= T1 with probability 15/16), and again
+    up to T2 when a hash is still open; the row takes the order the kernel's rule picks."""
+    M = float(ds.m.astype(np.float64).sum())
+    lengths = np.diff(ds.row_ptr.astype(np.int64))
+    rows_of = np.repeat(np.arange(ds.n_rows), lengths)
+    sx = np.bincount(rows_of, weights=ds.val.astype(np.float64), minlength=ds.n_rows)
+    sm = np.bincount(rows_of, weights=np.where(ds.val > 0, ds.m[ds.col], 0).astype(np.float64),
+                     minlength=ds.n_rows)
+    live = sx > 0
+    s = np.where(live, sx / M, 0.5)
+    l1p = np.log1p(-np.minimum(s, 1 - 1e-16))
+    t1 = np.ceil(np.log((1 / 16) / k) / l1p)
+    t2 = np.ceil(np.log(1e-4 / k) / l1p)
+    by_steps = live & (t2 < 65534) & (t2 * sm < 65534.0 * sx)
+    p_open = 1.0 - (1.0 - np.power(1.0 - s, t1)) ** k
+    step_keys = k * (np.minimum(t1, 65535) * sm / M + p_open * np.minimum(t2, 65535) * sm / M)
+    offset_keys = k * 65534.0 * s
+    keys = np.where(live, np.where(by_steps, step_keys, offset_keys), 0.0).sum()
+    nbytes = KEY_BYTES * keys + 8.0 * ds.nnz + 8.0 * (ds.n_rows + 1) + 2.0 * ds.n_rows * k
+    return nbytes, {"expected_keys": float(keys), "step_order_rows": int(by_steps.sum())}
 
 
 def parse():
@@ -64,8 +115,10 @@ def parse():
     ap.add_argument("--heavy-tail", action="store_true",
                     help="only run the heavy-tail workload (with --only batched: no plain "
                          "form, no collision counts)")
-    ap.add_argument("--serve-requests", type=int, default=200,
-                    help="open-loop requests per load level")
+    ap.add_argument("--serve-requests", type=int, default=10_000,
+                    help="timed open-loop requests per load level and run")
+    ap.add_argument("--serve-warmup", type=int, default=500,
+                    help="open-loop requests before each timed run (not counted)")
     ap.add_argument("--serve-corpus-rows", type=int, default=100_000)
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline workload")
@@ -82,8 +135,9 @@ def parse():
 
 def serve_bench(args) -> dict:
     """Serving loop on the D = 2^20 corpus: saturated throughput from a closed burst, then
-    open-loop Poisson arrivals at 0.5x and 0.8x of it; p50/p99 latency from scheduled arrival
-    to completion."""
+    open-loop Poisson arrivals at 0.5x and 0.8x of it, each level run twice with a warm-up;
+    p50/p99/p999 latency from scheduled arrival to completion, and the requests' overlap on the
+    device from HIP event timestamps."""
     import torch
     from paper_1602_08393_amd import serve, synth, wmh
     torch.cuda.set_device(0)
@@ -94,16 +148,23 @@ def serve_bench(args) -> dict:
     k = corpus.k
     ctx = wmh.Context(0)
     ctx.set_bounds(corpus.m)
-    out = {"workload": f"requests of 1..{args.serve_max_rows} rows (log-uniform) drawn from a "
-                       f"{corpus.n_rows}-row corpus, D=2^20, tf weights Q16.16, k={k}",
+    out = {"workload": f"requests of 1..{args.serve_max_rows} consecutive rows (log-uniform "
+                       f"sizes) of a {corpus.n_rows}-row corpus, D=2^20, tf weights Q16.16, k={k}",
            "slots": args.serve_slots, "request_buffers": "page-locked (wmh_host_alloc)"}
+
+    def request_bytes(sizes, starts):
+        rp = corpus.row_ptr.astype(np.int64)
+        nnz = rp[starts + sizes] - rp[starts]
+        h2d = 8 * (sizes + 1) + 8 * nnz
+        return float(h2d.sum()), float((2 * k * sizes).sum())
+
     # the component index is built when each loop starts, so no timed request waits for it
     with serve.Server(ctx, k, seed=0, slots=args.serve_slots, build_index=True) as srv:
-        # saturated throughput: a closed burst submitted at once
-        burst = max(8, args.serve_requests)
-        _, sizes, rows = synth.serving_requests(burst, corpus.n_rows, qps=1.0, seed=3005,
+        ring = serve.RangeRequests(srv, corpus, args.serve_max_rows)
+        burst = min(500, len(ring.sig_buf))
+        _, sizes, starts = synth.serving_ranges(burst, corpus.n_rows, qps=1.0, seed=3005,
                                                 max_rows=args.serve_max_rows)
-        reqs = serve.requests_from_corpus(corpus, rows, srv, pinned=True)
+        reqs = [ring.make(int(a), int(n)) for a, n in zip(starts, sizes)]
         t0 = time.perf_counter()
         for r in reqs:
             srv.submit(r)
@@ -111,25 +172,62 @@ def serve_bench(args) -> dict:
         for r in reqs:
             srv.wait(r.ticket)
         burst_s = time.perf_counter() - t0
+        st = srv.stats()
         sat_qps = burst / burst_s
+        h2d, d2h = request_bytes(sizes, starts)
+        pcie = (h2d + d2h) / burst_s / 1e9
         out["saturated_qps"] = sat_qps
         out["saturated_hashes_per_s"] = float(sum(sizes)) * k / burst_s
-        log(f"serve: burst of {burst} requests in {burst_s:.2f}s -> {sat_qps:.2f} req/s")
+        out["saturated_max_on_device"] = st["max_on_device"]
+        out["saturated_max_computing"] = st["max_computing"]
+        # the loop's bound: its requests live in host memory, so every row crosses PCIe once
+        # and every signature once back
+        out["roofline"] = {"bound": "pcie", "achieved": pcie, "peak": 2 * PCIE_PEAK_GBS,
+                           "unit": "GB/s", "frac": pcie / (2 * PCIE_PEAK_GBS), "traffic": None,
+                           "kernel": "whole loop (copies in and out, check, index rows kernel)",
+                           "h2d_bytes": h2d, "d2h_bytes": d2h,
+                           "note": "bytes of the burst's rows in and signatures out over its "
+                                   "wall time, against PCIe 5.0 x16 both ways"}
+        log(f"serve: burst of {burst} requests in {burst_s:.2f}s -> {sat_qps:.2f} req/s, "
+            f"{pcie:.1f} GB/s over PCIe, on device together up to {st['max_on_device']}")
     levels = []
     for frac in (0.5, 0.8):
         qps = frac * sat_qps
-        arrivals, sizes, rows = synth.serving_requests(args.serve_requests, corpus.n_rows,
-                                                       qps=qps, seed=int(4005 + 100 * frac),
-                                                       max_rows=args.serve_max_rows)
-        with serve.Server(ctx, k, seed=0, slots=args.serve_slots, build_index=True) as srv:
-            reqs = serve.requests_from_corpus(corpus, rows, srv, pinned=True)
-            st = serve.run_open_loop(srv, reqs, arrivals)
-        levels.append({"load": frac, "qps": qps, "requests": st["completed"],
-                       "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "max_ms": st["max_ms"],
-                       "mean_ms": st["mean_ms"], "hashes_per_s": st["hashes_per_s"],
-                       "max_queued": st["max_queued"], "peak_bytes": st["peak_bytes"]})
-        log(f"serve: load {frac}: p50 {st['p50_ms']:.1f} ms p99 {st['p99_ms']:.1f} ms "
-            f"{st['hashes_per_s']:.3g} hashes/s")
+        runs = []
+        for run in range(2):
+            n_req = args.serve_requests + args.serve_warmup
+            arrivals, sizes, starts = synth.serving_ranges(
+                n_req, corpus.n_rows, qps=qps, seed=int(4005 + 100 * frac + 7 * run),
+                max_rows=args.serve_max_rows)
+            with serve.Server(ctx, k, seed=0, slots=args.serve_slots, build_index=True) as srv:
+                ring = serve.RangeRequests(srv, corpus, args.serve_max_rows)
+                w = args.serve_warmup
+                serve.run_open_loop(srv, lambda i: ring.make(int(starts[i]), int(sizes[i])),
+                                    arrivals[:w])
+                srv.reset_stats()
+                st = serve.run_open_loop(
+                    srv, lambda i: ring.make(int(starts[w + i]), int(sizes[w + i])),
+                    arrivals[w:] - arrivals[w])
+            runs.append({"requests": st["completed"], "p50_ms": st["p50_ms"],
+                         "p99_ms": st["p99_ms"], "p999_ms": st["p999_ms"],
+                         "max_ms": st["max_ms"], "mean_ms": st["mean_ms"],
+                         "hashes_per_s": st["hashes_per_s"], "max_queued": st["max_queued"],
+                         "peak_bytes": st["peak_bytes"], "max_on_device": st["max_on_device"],
+                         "max_computing": st["max_computing"], "overlap_s": st["overlap_s"],
+                         "busy_s": st["busy_s"], "ring_waits": ring.reused_waits})
+            log(f"serve: load {frac} run {run}: {st['completed']} requests, p50 "
+                f"{st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms p999 {st['p999_ms']:.2f} ms, "
+                f"{st['hashes_per_s']:.3g} hashes/s, computing together up to "
+                f"{st['max_computing']} ({st['overlap_s']:.2f} s with two or more)")
+        lv = {"load": frac, "qps": qps, "warmup_requests": args.serve_warmup, "runs": runs}
+        for key in ("p50_ms", "p99_ms", "p999_ms"):
+            vals = [r[key] for r in runs]
+            lv[key] = float(np.mean(vals))
+            lv[key + "_spread"] = [float(min(vals)), float(max(vals))]
+        lv["requests"] = int(min(r["requests"] for r in runs))
+        lv["hashes_per_s"] = float(np.mean([r["hashes_per_s"] for r in runs]))
+        lv["max_computing"] = int(max(r["max_computing"] for r in runs))
+        levels.append(lv)
     out["levels"] = levels
     ctx.close()
     return out
@@ -229,8 +327,8 @@ def heavy_tail_bench(args, torch, synth, wmh) -> dict:
                 "batched_ms_per_step": el_b / 3 * 1e3,
                 "batched_walk_ms": float(np.mean(walk_b)),
                 "mean_steps_per_hash": tests / hashes,
-                "walk_frac_of_alu_peak": OPS_PER_TEST * tests / (np.mean(walk_b) / 1e3) / 1e12
-                / PEAK_INT_TOPS})
+                "roofline": alu_roofline(tests, float(np.mean(walk_b)),
+                                         f"{out['batched_plan']['walk']} walk")})
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = oracle_on_head(ds, 4096, k, wmh.sig_to_numpy(sig_b[:4096]))
         log(f"heavy-tail: oracle {out['cpu_baseline']['value']:.3g} hashes/s on 4096 rows, "
@@ -243,7 +341,11 @@ def heavy_tail_bench(args, torch, synth, wmh) -> dict:
     out["auto"] = {"mode": ctx.last_mode(), "plan": ctx.last_plan(),
                    "hashes_per_s": hashes * 3 / el_a, "ms_per_step": el_a / 3 * 1e3,
                    "kernels_ms": float(np.mean(walk_a)),
-                   "equals_batched": bool(torch.equal(sig_a, sig_b))}
+                   "equals_batched": bool(torch.equal(sig_a, sig_b)),
+                   "roofline": alu_roofline(
+                       tests, float(np.mean(walk_a)), "walk + index rows kernels",
+                       note="walk-equivalent tests: the index rows compute the same values "
+                            "with fewer operations")}
     log(f"heavy-tail: auto ({out['auto']['mode']}) {out['auto']['ms_per_step']:.2f} ms/step, "
         f"equal {out['auto']['equals_batched']}")
     del sig_a
@@ -256,7 +358,21 @@ def heavy_tail_bench(args, torch, synth, wmh) -> dict:
     out.update({"plain_hashes_per_s": hashes * 2 / el_p,
                 "plain_ms_per_step": el_p / 2 * 1e3,
                 "batched_over_plain": (hashes * 3 / el_b) / (hashes * 2 / el_p),
-                "batched_equals_plain": bool(torch.equal(sig_b, sig_p))})
+                "batched_equals_plain": bool(torch.equal(sig_b, sig_p)),
+                "plain_roofline": alu_roofline(tests, float(np.mean(walk_p)), "plain_kernel")})
+    # the batched walk's kernels and tuned plan scheduled plainly (a launch per 8192 rows)
+    el_s, walk_s, _ = timed_steps(ctx, rows, k, sig_p,
+                                  ctx.make_opts(mode="plain_shared", profile=True,
+                                                **plan_args(args)), 3, 1, torch)
+    out.update({"plain_shared_hashes_per_s": hashes * 3 / el_s,
+                "plain_shared_ms_per_step": el_s / 3 * 1e3,
+                "batched_over_plain_shared": (hashes * 3 / el_b) / (hashes * 3 / el_s),
+                "plain_shared_equals_batched": bool(torch.equal(sig_b, sig_p)),
+                "plain_shared_roofline": alu_roofline(
+                    tests, float(np.mean(walk_s)),
+                    f"{out['batched_plan']['walk']} walk, one launch per 8192 rows")})
+    log(f"heavy-tail: plain (shared per-step code) {out['plain_shared_ms_per_step']:.2f} ms/step, "
+        f"equal {out['plain_shared_equals_batched']}")
     log(f"heavy-tail: batched {out['batched_ms_per_step']:.2f} ms/step, plain "
         f"{out['plain_ms_per_step']:.2f} ms/step, equal {out['batched_equals_plain']}")
     del sig_p
@@ -282,10 +398,15 @@ def heavy_tail_bench(args, torch, synth, wmh) -> dict:
     Cn = counts.cpu().numpy().view(np.uint32)
     exact = bool(np.all((An[a_idx] == Bn[b_idx]).sum(axis=1) == Cn[a_idx, b_idx]))
     ms = float(np.median(times))
+    cmp_ops = OPS_PER_COMPARE * 1e8 * k / (ms / 1e3) / 1e12
     out["collisions"] = {"pairs": 10000 * 10000, "k": k, "ms": ms,
                          "pairs_per_s": 1e8 / (ms / 1e3),
                          "compares_per_s": 1e8 * k / (ms / 1e3),
-                         "sampled_pairs_exact": exact, "sampled_pairs": len(a_idx)}
+                         "sampled_pairs_exact": exact, "sampled_pairs": len(a_idx),
+                         "roofline": {"bound": "alu", "achieved": cmp_ops, "peak": PEAK_INT_TOPS,
+                                      "unit": "TOP/s", "frac": cmp_ops / PEAK_INT_TOPS,
+                                      "traffic": None, "kernel": "collide_kernel",
+                                      "kernel_ms": ms, "ops_per_compare": OPS_PER_COMPARE}}
     log(f"heavy-tail: all-pairs collisions {ms:.2f} ms, sample exact {exact}")
     # the same counts on b-bit packed signatures (lossless width)
     bits, top = ctx.sig_bits(sig_b, stream=stream.cuda_stream)
@@ -328,7 +449,11 @@ def text_like_bench(args, torch, synth, wmh) -> dict:
     sig = torch.empty((ds.n_rows, k), dtype=torch.int16, device="cuda:0")
     stream = torch.cuda.current_stream()
     opts = ctx.make_opts(mode="auto", profile=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     ctx.hash_into(rows, k, 0, sig, stream=stream.cuda_stream, opts=opts)
+    torch.cuda.synchronize()
+    cold_ms = (time.perf_counter() - t0) * 1e3
     first_rows_ms, build_ms = ctx.last_kernel_ms()
     mode = ctx.last_mode()
     el, walk, _ = timed_steps(ctx, rows, k, sig, opts, 3, 0, torch)
@@ -347,6 +472,7 @@ def text_like_bench(args, torch, synth, wmh) -> dict:
                        "Q16.16, k=1000, seed 0",
            "N": ds.n_rows, "D": ds.D, "k": k, "nnz": ds.nnz, "mode": mode,
            "hashes_per_s": hashes * 3 / el, "ms_per_step": el / 3 * 1e3,
+           "cold_ms_per_step": cold_ms,
            "rows_kernel_ms": float(np.mean(walk)), "index_build_ms": build_ms,
            "first_call_rows_kernel_ms": first_rows_ms,
            "walk_steps_equivalent": int(sig_np.sum(dtype=np.int64)),
@@ -354,12 +480,49 @@ def text_like_bench(args, torch, synth, wmh) -> dict:
            "head_equals_plain_walk": bool(np.array_equal(sig_np[:48], walk_sig)),
            "head_plain_walk_ms": head_plain_ms,
            "head_plain_walk_rows": head.n_rows}
+    key_bytes, key_info = index_key_bytes(ds, k)
+    out["roofline"] = hbm_roofline(key_bytes, float(np.mean(walk)), "index_rows_kernel",
+                                   note="expected keys of the rows' evaluation orders "
+                                        "(Theorem 2), the rows and the signatures, once each")
+    out["roofline"].update(key_info)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = oracle_on_head(ds, 48, k, sig_np[:48])
         log(f"text-like: oracle {out['cpu_baseline']['value']:.3g} hashes/s on 48 rows, "
             f"bit-exact {out['cpu_baseline']['bit_exact']}")
     log(f"text-like: {mode} {out['ms_per_step']:.2f} ms/step, index build {build_ms:.2f} ms, "
         f"head equals walk {out['head_equals_plain_walk']}")
+    ctx.close()
+    return out
+
+
+def small_bench(torch, synth, wmh) -> dict:
+    """The small plain workload (N=1000, D=1024, k=64): batched, plain and the batched kernels
+    scheduled plainly, all checked against the oracle on every row."""
+    import oracle
+    ds = synth.config1()
+    k = ds.k
+    ctx = wmh.Context(0)
+    ctx.set_bounds(ds.m)
+    rows = wmh.upload_dataset(ds, "cuda:0")
+    want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, k, seed=0)
+    tests = int(want.astype(np.int64).sum())
+    out = {"workload": "plain small: N=1000, D=1024, nnz ~ Poisson(100), weights U{1..65535}, "
+                       "bounds = dataset max, k=64, seed 0",
+           "N": ds.n_rows, "D": ds.D, "k": k, "nnz": ds.nnz, "membership_tests": tests}
+    for mode in ("batched", "plain", "plain_shared"):
+        sig = torch.empty((ds.n_rows, k), dtype=torch.int16, device="cuda:0")
+        el, walk, _ = timed_steps(ctx, rows, k, sig, ctx.make_opts(mode=mode, profile=True),
+                                  20, 3, torch)
+        walk_ms = float(np.mean(walk))
+        out[mode] = {"hashes_per_s": ds.n_rows * k * 20 / el, "ms_per_step": el / 20 * 1e3,
+                     "walk_ms": walk_ms, "plan": ctx.last_plan(),
+                     "equals_oracle": bool(np.array_equal(wmh.sig_to_numpy(sig), want)),
+                     "roofline": alu_roofline(tests, walk_ms, f"{mode} walk")}
+        log(f"small: {mode} {out[mode]['ms_per_step']:.3f} ms/step, equals oracle "
+            f"{out[mode]['equals_oracle']}")
+    out["batched_over_plain"] = out["batched"]["hashes_per_s"] / out["plain"]["hashes_per_s"]
+    out["batched_over_plain_shared"] = (out["batched"]["hashes_per_s"] /
+                                        out["plain_shared"]["hashes_per_s"])
     ctx.close()
     return out
 
@@ -500,6 +663,17 @@ def main():
         el, walk, _ = timed_steps(ctx, rows, k, sig_plain, opts, psteps, 1, torch)
         result["plain"] = (el, walk, psteps)
         log(f"plain: {el / psteps * 1e3:.3f} ms/step, walk kernels {np.mean(walk):.3f} ms")
+    if args.only == "both":
+        # the batched walk's own kernels and plan, scheduled plainly: a launch per 8192 rows,
+        # one workgroup per tile, no tile queue, no graph
+        sig_ps = torch.empty_like(sig)
+        opts = ctx.make_opts(mode="plain_shared", profile=True, **plan)
+        log("plain (shared per-step code): warmup + timed steps")
+        el, walk, _ = timed_steps(ctx, rows, k, sig_ps, opts, args.steps, 1, torch)
+        result["plain_shared"] = (el, walk, args.steps, bool(torch.equal(sig_ps, sig)))
+        del sig_ps
+        log(f"plain (shared per-step code): {el / args.steps * 1e3:.3f} ms/step, walk kernels "
+            f"{np.mean(walk):.3f} ms")
 
     main_key = "batched" if "batched" in result else "plain"
     profiled_plan = (main_key == "batched" and batched_plan["rows_per_block"] == 4
@@ -530,12 +704,9 @@ def main():
                                "seed 0",
                    "N": ds.n_rows, "D": ds.D, "k": k, "nnz": ds.nnz, "M": M,
                    "mode": main_key},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS,
-                     "unit": "TOP/s", "frac": achieved / PEAK_INT_TOPS,
-                     "traffic": TRAFFIC_R4_HISTOGRAM if profiled_plan else None,
-                     "kernel": "batched_kernel" if main_key == "batched" else "plain_kernel",
-                     "kernel_ms": walk_s * 1e3, "membership_tests": tests,
-                     "ops_per_test": OPS_PER_TEST},
+        "roofline": alu_roofline(
+            tests, walk_s * 1e3, "batched_kernel" if main_key == "batched" else "plain_kernel",
+            traffic=TRAFFIC_R4_HISTOGRAM if profiled_plan else None),
         "mean_steps_per_hash": tests / hashes,
     }
     if "batched" in result and "plain" in result:
@@ -546,6 +717,18 @@ def main():
                          "walk_ms": float(np.mean(pwalk)), "steps": psteps}
         line["batched_over_plain"] = value / plain_value
         line["batched_equals_plain"] = same
+        line["plain"]["roofline"] = alu_roofline(tests, float(np.mean(pwalk)), "plain_kernel")
+        if "plain_shared" in result:
+            sel, swalk, ssteps, ssame = result["plain_shared"]
+            sv = hashes * ssteps / sel
+            line["plain_shared"] = {
+                "value": sv, "ms_per_step": sel / ssteps * 1e3, "walk_ms": float(np.mean(swalk)),
+                "steps": ssteps, "equals_batched": ssame,
+                "form": "the batched walk's kernels, plan and shared stream; one launch per "
+                        "8192 rows, one workgroup per tile, no tile queue, no graph",
+                "roofline": alu_roofline(tests, float(np.mean(swalk)),
+                                         f"{batched_plan['walk']} walk, one launch per 8192 rows")}
+            line["batched_over_plain_shared"] = value / sv
         bel, bwalk, bbuild, bgraph = result["batched"]
         line["batched_detail"] = {"graph_ms": float(np.mean(bgraph)),
                                   "walk_ms": float(np.mean(bwalk)),
@@ -563,6 +746,8 @@ def main():
     ctx.close()
     if not args.no_extras and args.only == "both":
         del rows, sig, sig_plain
+        torch.cuda.empty_cache()
+        line["small"] = small_bench(torch, synth, wmh)
         torch.cuda.empty_cache()
         line["heavy_tail"] = heavy_tail_bench(args, torch, synth, wmh)
         torch.cuda.empty_cache()

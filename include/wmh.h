@@ -91,12 +91,17 @@ typedef enum {
                               walk takes the walk rows (its stream sized for them alone) and
                               the component index the others.  For batches whose green
                               fractions spread over orders of magnitude.  Needs what BATCHED
-                              and INDEXED need; the context keeps one byte per row */
+                              and INDEXED need; the context keeps one byte per row */,
+    WMH_MODE_PLAIN_SHARED = 5 /* BATCHED's kernels, plan and shared stream scheduled plainly:
+                              one launch per batch of `batch_rows` rows, one workgroup per
+                              (row block, hash block) tile, no tile counter, no graph.  It
+                              isolates what persistence, the tile queue and the graph add to
+                              the same per-step code.  Never chosen by AUTO */
 } wmh_mode;
 
 typedef struct {
     int32_t mode;          /* wmh_mode; default WMH_MODE_AUTO */
-    uint32_t batch_rows;   /* plain mode: rows per launch; 0 = 8192 */
+    uint32_t batch_rows;   /* plain modes: rows per launch; 0 = 8192 */
     int32_t validate;      /* 1 (default): validate the CSR input before hashing */
     int32_t use_graph;     /* batched mode: 1 (default) replay a captured hipGraph */
     int32_t sync;          /* 1 (default): wait for completion before returning */
@@ -478,6 +483,13 @@ typedef struct {
     double busy_s;         /* first admission -> last completion */
     double hashes_per_s;   /* hashes / busy_s */
     uint64_t rejected;     /* requests whose rows failed the device check (not in failed) */
+    /* Overlap on the device, from HIP event timestamps on each request's slot stream: a
+     * request is on the device from its first copy in to the end of its copy out, and
+     * computing from the start of its walk to the end of its copy out (both include time its
+     * work waits in the device queues behind other slots' work). */
+    uint64_t max_on_device;  /* most completed requests on the device at one instant */
+    uint64_t max_computing;  /* most completed requests computing at one instant */
+    double overlap_s;        /* seconds during which at least two requests were computing */
 } wmh_serving_stats;
 
 /*
@@ -517,6 +529,10 @@ wmh_status wmh_server_drain(wmh_server *srv);
 
 /* Counters and latency percentiles over the completed requests. */
 wmh_status wmh_server_stats(wmh_server *srv, wmh_serving_stats *out);
+
+/* Starts the statistics afresh (latencies, counters, overlap), e.g. after a warm-up; requests
+ * queued or on the device stay and count as submitted.  Errors: WMH_E_ARG. */
+wmh_status wmh_server_reset_stats(wmh_server *srv);
 
 /* The steady clock used for arrival times, in nanoseconds. */
 uint64_t wmh_server_now_ns(void);

@@ -78,7 +78,7 @@ struct OwnedIndex {
 
 constexpr uint64_t kIndexBudgetBytes = 4ull << 30;  // each key order of the index, at most 4 GiB
 
-enum class Path { kPlain, kBatched, kIndexed, kSplit };
+enum class Path { kPlain, kBatched, kIndexed, kSplit, kPlainShared };
 
 // Autotuned batched plans, per (D, value width, k, step class); step class = floor(log2) of
 // the mean capped step count of the tuned rows.

@@ -31,6 +31,17 @@ struct RowLayout {
     }
 };
 
+// The next tile of a workgroup (called by one thread, `claimed` starting false): from the
+// counter of a persistent launch, or, with no counter, the workgroup's own tile (blockIdx.x) the
+// first time and none after it (one workgroup per tile; ~0 is past every tile).
+__device__ __forceinline__ uint64_t next_tile(unsigned long long *counter, bool &claimed)
+{
+    if (counter) return atomicAdd(counter, 1ull);
+    const uint64_t t = claimed ? ~0ull : (uint64_t)blockIdx.x;
+    claimed = true;
+    return t;
+}
+
 // K consecutive shared-stream entries of one lane (4-byte packed or 8-byte wide), read with the
 // widest aligned loads: the first entry index is a multiple of K.
 template <int K, bool kPacked>

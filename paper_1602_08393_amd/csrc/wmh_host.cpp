@@ -320,6 +320,7 @@ Path choose_path(const wmh_ctx *ctx, int mode, bool batched_ok, bool index_ready
     if (mode == WMH_MODE_BATCHED) return Path::kBatched;
     if (mode == WMH_MODE_INDEXED) return Path::kIndexed;
     if (mode == WMH_MODE_SPLIT) return Path::kSplit;
+    if (mode == WMH_MODE_PLAIN_SHARED) return Path::kPlainShared;
     const Path walk_path = batched_ok ? Path::kBatched : Path::kPlain;
     if (!stats.known || !stats.keys_known || !index_fits(k)) return walk_path;
     const bool narrow = ctx->max_bound <= 0xFFFFu;
@@ -591,7 +592,7 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
     wmh_opts o;
     if (opts) o = *opts;
     else wmh_opts_init(&o);
-    if (o.mode < WMH_MODE_AUTO || o.mode > WMH_MODE_SPLIT)
+    if (o.mode < WMH_MODE_AUTO || o.mode > WMH_MODE_PLAIN_SHARED)
         return fail(ctx, WMH_E_ARG, "unknown mode %d", o.mode);
     if ((o.mode == WMH_MODE_INDEXED || o.mode == WMH_MODE_SPLIT) && !index_fits(k))
         return fail(ctx, WMH_E_ARG, "the component index needs k <= %u", kIndexMaxK);
@@ -614,9 +615,10 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
     }
 
     BatchedPlan plan{};
-    const bool batched_ok = (o.mode == WMH_MODE_AUTO || o.mode == WMH_MODE_BATCHED) &&
+    const bool batched_ok = (o.mode == WMH_MODE_AUTO || o.mode == WMH_MODE_BATCHED ||
+                             o.mode == WMH_MODE_PLAIN_SHARED) &&
                             plan_batched(ctx, k, stats, o, &plan);
-    if (o.mode == WMH_MODE_BATCHED && !batched_ok)
+    if ((o.mode == WMH_MODE_BATCHED || o.mode == WMH_MODE_PLAIN_SHARED) && !batched_ok)
         return fail(ctx, WMH_E_ARG, "no batched plan fits for D=%u with these options", ctx->dims);
     // a split walks one class with a plan sized for that class alone
     BatchedPlan split_plan{};
@@ -670,8 +672,11 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         return WMH_OK;
     }
 
-    // The batched walk of `wrows` (every row, or the walk class of a split) under plan `pl`.
-    auto run_batched = [&](const Rows &wrows, const BatchedPlan &pl) -> wmh_status {
+    // The batched walk of `wrows` (every row, or the walk class of a split) under plan `pl`:
+    // one persistent launch (graph-captured with use_graph), or with `per_batch` one launch
+    // per batch of batch_rows rows, a workgroup per tile and no tile counter.
+    auto run_batched = [&](const Rows &wrows, const BatchedPlan &pl,
+                           bool per_batch = false) -> wmh_status {
         {
             wmh_status st = ensure_stream_capacity(ctx, pl.stream_bytes(k));
             if (st != WMH_OK) return st;
@@ -713,6 +718,29 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
             } else {
                 WMH_HIP(ctx, hipStreamWaitEvent(s, ctx->stream_ready, 0));
             }
+        }
+
+        if (per_batch) {
+            // the same kernels and plan, scheduled plainly: one launch per batch of rows, one
+            // workgroup per (row block, hash block) tile, no counter and no graph
+            const uint64_t step = o.batch_rows ? o.batch_rows : 8192;
+            const uint64_t hash_tiles = (k + pl.hashes_per_tile - 1) / pl.hashes_per_tile;
+            if (((step + pl.rows_per_block - 1) / pl.rows_per_block) * hash_tiles > UINT32_MAX)
+                return fail(ctx, WMH_E_ARG, "a batch of %llu rows has too many tiles for one launch",
+                            (unsigned long long)step);
+            if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[1], s));
+            for (uint64_t r0 = 0; r0 < n_rows; r0 += step) {
+                Rows batch = wrows;
+                batch.row_ptr = wrows.row_ptr + r0;
+                batch.n_rows = std::min(n_rows, r0 + step) - r0;
+                const uint64_t tiles =
+                    (batch.n_rows + pl.rows_per_block - 1) / pl.rows_per_block * hash_tiles;
+                WMH_HIP(ctx, launch_batched(b, batch, k, seed, sig + r0 * k, pl, ctx->d_stream,
+                                            nullptr, (uint32_t)tiles, s));
+            }
+            if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[2], s));
+            ctx->profiled_stream = profile && stream_built;
+            return WMH_OK;
         }
 
         // events around the walk only on direct launches; a graph is timed as a whole
@@ -783,10 +811,11 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         return WMH_OK;
     }
 
-    const wmh_status st = run_batched(rows, plan);
+    const bool per_batch = path == Path::kPlainShared;
+    const wmh_status st = run_batched(rows, plan, per_batch);
     if (st != WMH_OK) return st;
     ctx->profiled = profile;
-    ctx->last_mode = WMH_MODE_BATCHED;
+    ctx->last_mode = per_batch ? WMH_MODE_PLAIN_SHARED : WMH_MODE_BATCHED;
     ctx->last_plan = plan;
     if (o.sync) WMH_HIP(ctx, hipStreamSynchronize(s));
     return WMH_OK;
@@ -809,7 +838,9 @@ wmh_status wmh_last_plan(const wmh_ctx *ctx, wmh_opts *plan)
     plan->stream_depth = ctx->last_plan.stream_depth;
     plan->steps_per_lane = ctx->last_plan.steps_per_lane;
     plan->waves_per_block = ctx->last_plan.waves_per_block;
-    plan->walk = ctx->last_mode != WMH_MODE_BATCHED && ctx->last_mode != WMH_MODE_SPLIT ? 0
+    plan->walk = ctx->last_mode != WMH_MODE_BATCHED && ctx->last_mode != WMH_MODE_SPLIT &&
+                         ctx->last_mode != WMH_MODE_PLAIN_SHARED
+                     ? 0
                  : ctx->last_plan.ballot           ? 3
                  : ctx->last_plan.independent_rows ? 2
                                                    : 1;

@@ -448,9 +448,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     const uint32_t n_hash_tiles = (k + hashes_per_tile - 1) / hashes_per_tile;
     const uint64_t n_tiles = n_blocks * n_hash_tiles;
     uint64_t staged = ~0ull;
+    bool claimed = false;
 
     while (true) {
-        if (threadIdx.x == 0) tile_slot = atomicAdd(tile_counter, 1ull);
+        if (threadIdx.x == 0) tile_slot = next_tile(tile_counter, claimed);
         __syncthreads();
         const uint64_t tile = tile_slot;
         if (tile >= n_tiles) break;

@@ -31,6 +31,28 @@ using namespace wmh;
 
 namespace {
 
+// The largest number of intervals holding one instant (intervals closed on the left, open on
+// the right), and with `overlap_s` the total seconds during which at least two of them do.
+uint64_t most_at_once(const std::vector<std::pair<float, float>> &iv, double *overlap_s)
+{
+    std::vector<std::pair<float, int>> ev;
+    ev.reserve(2 * iv.size());
+    for (const auto &p : iv) {
+        ev.emplace_back(p.first, +1);
+        ev.emplace_back(p.second, -1);
+    }
+    std::sort(ev.begin(), ev.end());  // at equal times ends (-1) come before starts (+1)
+    int64_t now = 0, most = 0;
+    double two_or_more_ms = 0.0;
+    for (size_t i = 0; i < ev.size(); ++i) {
+        now += ev[i].second;
+        most = std::max(most, now);
+        if (now >= 2 && i + 1 < ev.size()) two_or_more_ms += ev[i + 1].first - ev[i].first;
+    }
+    if (overlap_s) *overlap_s = two_or_more_ms * 1e-3;
+    return (uint64_t)most;
+}
+
 uint64_t steady_ns()
 {
     return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
@@ -65,6 +87,9 @@ struct Slot {
     CheckWords *d_check = nullptr;  // the validation pass's words
     CheckWords *h_check = nullptr;  // pinned copy, read once `checked` has fired
     hipEvent_t checked = nullptr;
+    // timing events of the request on the slot: its first copy in, the start of its walk and
+    // the end of its copy out (device timestamps, read at completion)
+    hipEvent_t t_begin = nullptr, t_compute = nullptr, t_end = nullptr;
     Request *req = nullptr;
     bool computing = false;  // past the check: the walk and the copy out are queued
 };
@@ -111,6 +136,10 @@ struct wmh_server {
     uint64_t hashes = 0;
     std::vector<double> latencies_ms;
     uint64_t first_admit_ns = 0, last_done_ns = 0;
+    // device intervals of completed requests, in ms after t_ref: [first copy in, end of copy
+    // out] and [start of the walk, end of copy out]
+    hipEvent_t t_ref = nullptr;
+    std::vector<std::pair<float, float>> on_device, computing;
 
     wmh_status launch_check(Slot &slot, Request &r);
     wmh_status launch_compute(Slot &slot, Request &r);
@@ -138,8 +167,10 @@ wmh_status wmh_server::launch_check(Slot &slot, Request &r)
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? WMH_E_NOMEM : WMH_E_DEVICE;
 
     hipStream_t s = slot.stream;
-    e = hipMemcpyAsync(slot.d_row_ptr, r.row_ptr, (r.n_rows + 1) * sizeof(uint64_t),
-                       hipMemcpyHostToDevice, s);
+    e = hipEventRecord(slot.t_begin, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(slot.d_row_ptr, r.row_ptr, (r.n_rows + 1) * sizeof(uint64_t),
+                           hipMemcpyHostToDevice, s);
     if (e == hipSuccess && r.nnz)
         e = hipMemcpyAsync(slot.d_col, r.col, r.nnz * sizeof(uint32_t), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && r.nnz)
@@ -178,6 +209,7 @@ wmh_status wmh_server::launch_compute(Slot &slot, Request &r)
     const Bounds b = bounds_view(ctx);
     // the index is built once per loop, so its cost is left out of the comparison
     const Path path = choose_path(ctx, cfg.mode, batched, true, k, r.n_rows, r.nnz, r.stats);
+    e = hipEventRecord(slot.t_compute, s);
     if (e == hipSuccess && path == Path::kIndexed) {
         if (!index.valid) {
             // the worker is the only builder; the first indexed request waits for the build so
@@ -207,6 +239,7 @@ wmh_status wmh_server::launch_compute(Slot &slot, Request &r)
     if (e == hipSuccess)
         e = hipMemcpyAsync(slot.h_sig, slot.d_sig, sig_elems * sizeof(uint16_t),
                            hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(slot.t_end, s);
     if (e == hipSuccess) e = hipEventRecord(slot.finished, s);
     slot.computing = true;
     return e == hipSuccess ? WMH_OK : WMH_E_DEVICE;
@@ -228,6 +261,14 @@ void wmh_server::complete(Slot &slot, wmh_status st)
         hashes += r.n_rows * (uint64_t)cfg.k;
         latencies_ms.push_back((double)(r.done_ns - r.arrival_ns) * 1e-6);
         last_done_ns = std::max(last_done_ns, r.done_ns);
+        // every event of the slot has fired once `finished` has
+        float b = 0.f, c = 0.f, d = 0.f;
+        if (hipEventElapsedTime(&b, t_ref, slot.t_begin) == hipSuccess &&
+            hipEventElapsedTime(&c, t_ref, slot.t_compute) == hipSuccess &&
+            hipEventElapsedTime(&d, t_ref, slot.t_end) == hipSuccess) {
+            on_device.emplace_back(b, d);
+            computing.emplace_back(c, d);
+        }
     } else if (st == WMH_E_ROW_PTR || st == WMH_E_COL_RANGE || st == WMH_E_UNSORTED ||
                st == WMH_E_BOUND) {
         ++rejected;  // the caller's rows, reported by wmh_server_poll / wait
@@ -359,11 +400,18 @@ wmh_status wmh_server_create(wmh_ctx *ctx, const wmh_server_config *cfg_in, wmh_
         if (e == hipSuccess) e = hipMalloc(&slot.d_tile_counter, sizeof(unsigned long long));
         if (e == hipSuccess) e = hipMalloc(&slot.d_row_counter, sizeof(unsigned long long));
         if (e == hipSuccess) e = hipEventCreateWithFlags(&slot.checked, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreate(&slot.t_begin);
+        if (e == hipSuccess) e = hipEventCreate(&slot.t_compute);
+        if (e == hipSuccess) e = hipEventCreate(&slot.t_end);
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&slot.d_check), sizeof(CheckWords));
         if (e == hipSuccess)
             e = hipHostMalloc(reinterpret_cast<void **>(&slot.h_check), sizeof(CheckWords),
                               hipHostMallocDefault);
     }
+    // the origin of the device timestamps of every request
+    if (e == hipSuccess) e = hipEventCreate(&srv->t_ref);
+    if (e == hipSuccess) e = hipEventRecord(srv->t_ref, ctx->own_stream);
+    if (e == hipSuccess) e = hipEventSynchronize(srv->t_ref);
     if (e != hipSuccess) {
         wmh_status st = device_fail(ctx, e, "server setup");
         wmh_server_destroy(srv);
@@ -503,6 +551,24 @@ wmh_status wmh_server_stats(wmh_server *srv, wmh_serving_stats *out)
         out->busy_s = (double)(srv->last_done_ns - srv->first_admit_ns) * 1e-9;
         out->hashes_per_s = (double)srv->hashes / out->busy_s;
     }
+    out->max_on_device = most_at_once(srv->on_device, nullptr);
+    out->max_computing = most_at_once(srv->computing, &out->overlap_s);
+    return WMH_OK;
+}
+
+wmh_status wmh_server_reset_stats(wmh_server *srv)
+{
+    if (!srv) return WMH_E_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->submitted = srv->queue.size() + srv->inflight;
+    srv->completed = srv->failed = srv->rejected = 0;
+    srv->max_queued = srv->queue.size();
+    srv->peak_bytes = srv->inflight_bytes;
+    srv->hashes = 0;
+    srv->latencies_ms.clear();
+    srv->on_device.clear();
+    srv->computing.clear();
+    srv->first_admit_ns = srv->last_done_ns = 0;
     return WMH_OK;
 }
 
@@ -530,11 +596,15 @@ void wmh_server_destroy(wmh_server *srv)
         if (slot.d_row_counter) (void)hipFree(slot.d_row_counter);
         if (slot.finished) (void)hipEventDestroy(slot.finished);
         if (slot.checked) (void)hipEventDestroy(slot.checked);
+        if (slot.t_begin) (void)hipEventDestroy(slot.t_begin);
+        if (slot.t_compute) (void)hipEventDestroy(slot.t_compute);
+        if (slot.t_end) (void)hipEventDestroy(slot.t_end);
         if (slot.d_check) (void)hipFree(slot.d_check);
         if (slot.h_check) (void)hipHostFree(slot.h_check);
         if (slot.stream) (void)hipStreamDestroy(slot.stream);
     }
     if (srv->d_stream) (void)hipFree(srv->d_stream);
+    if (srv->t_ref) (void)hipEventDestroy(srv->t_ref);
     free_index(&srv->index);
     for (auto &kv : srv->requests) delete kv.second;
     delete srv;

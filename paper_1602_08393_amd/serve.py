@@ -151,6 +151,9 @@ class Server:
     def drain(self):
         self.ctx._check(self._lib.wmh_server_drain(self._ptr), "wmh_server_drain")
 
+    def reset_stats(self):
+        self.ctx._check(self._lib.wmh_server_reset_stats(self._ptr), "wmh_server_reset_stats")
+
     def stats(self) -> dict:
         s = wmh.ServingStats()
         self.ctx._check(self._lib.wmh_server_stats(self._ptr, ctypes.byref(s)),
@@ -176,11 +179,50 @@ def requests_from_corpus(ds, row_lists, server: Server, pinned: bool = False) ->
     return out
 
 
-def run_open_loop(server: Server, requests: list[Request], arrivals_s: np.ndarray) -> dict:
+class RangeRequests:
+    """Requests over runs of consecutive corpus rows without copying the rows: the corpus's
+    col and val sit once in page-locked memory and each request points into them; its row_ptr
+    (rebased to 0) and its signatures use one of `ring` page-locked buffer pairs in turn.  A
+    pair is reused only once the request that last used it has completed."""
+
+    def __init__(self, server: Server, ds, max_rows: int, ring: int = 512):
+        self.server = server
+        self.k = server.k
+        self.rp = ds.row_ptr.astype(np.uint64)
+        self.pins: list = []
+        self.col = pinned_like(ds.col, self.pins)
+        self.val = pinned_like(ds.val, self.pins)
+        self.row_ptr_buf = [PinnedBuffer((max_rows + 1) * 8) for _ in range(ring)]
+        self.sig_buf = [PinnedBuffer(max(max_rows * self.k * 2, 2)) for _ in range(ring)]
+        self.last: list = [None] * ring
+        self.n = 0
+        self.reused_waits = 0
+
+    def make(self, start: int, n_rows: int) -> Request:
+        i = self.n % len(self.row_ptr_buf)
+        self.n += 1
+        prev = self.last[i]
+        if prev is not None and prev.ticket in self.server._live:
+            if self.server.poll(prev.ticket) is None:  # still in flight: wait for it
+                self.reused_waits += 1
+                self.server.wait(prev.ticket)
+        lo, hi = int(self.rp[start]), int(self.rp[start + n_rows])
+        row_ptr = self.row_ptr_buf[i].array((n_rows + 1,), np.uint64)
+        np.subtract(self.rp[start:start + n_rows + 1], np.uint64(lo), out=row_ptr)
+        sig = self.sig_buf[i].array((n_rows, self.k), np.uint16)
+        req = Request(row_ptr, self.col[lo:hi], self.val[lo:hi], sig)
+        self.last[i] = req
+        return req
+
+
+def run_open_loop(server: Server, requests, arrivals_s: np.ndarray) -> dict:
     """Submits request i at t0 + arrivals_s[i] (open loop: the schedule never waits for
-    completions) with that scheduled time as its arrival, then drains and returns stats."""
+    completions) with that scheduled time as its arrival, then drains and returns stats.
+    `requests` is a list of Requests or a function of i that makes request i (called before
+    its due time)."""
     t0 = now_ns() + 2_000_000
-    for req, a in zip(requests, arrivals_s):
+    for i, a in enumerate(arrivals_s):
+        req = requests(i) if callable(requests) else requests[i]
         due = t0 + int(a * 1e9)
         while True:
             left = due - now_ns()
@@ -189,7 +231,6 @@ def run_open_loop(server: Server, requests: list[Request], arrivals_s: np.ndarra
             time.sleep(min(left, 2_000_000) / 1e9 if left > 200_000 else 0)
         server.submit(req, arrival_ns=due)
     server.drain()
-    for req in requests:
-        if req.ticket in server._live:
-            server.wait(req.ticket)
+    for ticket in list(server._live):
+        server.wait(ticket)
     return server.stats()

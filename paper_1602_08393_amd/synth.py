@@ -272,6 +272,21 @@ def serving_requests(n_requests: int, corpus_rows: int, qps: float, seed: int = 
     return arrivals, sizes, rows
 
 
+def serving_ranges(n_requests: int, corpus_rows: int, qps: float, seed: int = 2005,
+                   max_rows: int = 4096):
+    """Poisson arrival times (seconds), request sizes log-uniform on [1, max_rows] and the first
+    corpus row of each request, which takes that many consecutive rows.  The corpus rows are
+    independent and identically distributed, so a run of consecutive rows is distributed like
+    rows drawn at random."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gaps = rng.exponential(1.0 / qps, size=n_requests)
+    arrivals = np.cumsum(gaps)
+    sizes = np.floor(np.exp(rng.uniform(0.0, np.log(max_rows + 1), size=n_requests))) \
+        .astype(np.int64).clip(1, min(max_rows, corpus_rows))
+    starts = rng.integers(0, corpus_rows - sizes + 1)
+    return arrivals, sizes, starts
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5_corpus}
 
 

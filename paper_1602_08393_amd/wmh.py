@@ -20,7 +20,7 @@ STATUS = {0: "WMH_OK", -1: "WMH_E_ARG", -2: "WMH_E_NO_BOUNDS", -3: "WMH_E_COL_RA
           -4: "WMH_E_UNSORTED", -5: "WMH_E_BOUND", -6: "WMH_E_OVERFLOW", -7: "WMH_E_NOMEM",
           -8: "WMH_E_DEVICE", -9: "WMH_E_ROW_PTR"}
 NOALLOC_SCRATCH_BYTES = 16 << 20  # WMH_NOALLOC_SCRATCH_BYTES: wmh_hash_noalloc's static array
-MODES = {"auto": 0, "plain": 1, "batched": 2, "indexed": 3, "split": 4}
+MODES = {"auto": 0, "plain": 1, "batched": 2, "indexed": 3, "split": 4, "plain_shared": 5}
 WALKS = {"auto": 0, "shared": 1, "rows": 2, "ballot": 3}
 
 EXPORTED = ["wmh_opts_init", "wmh_create", "wmh_destroy", "wmh_set_bounds", "wmh_hash",
@@ -33,7 +33,8 @@ EXPORTED = ["wmh_opts_init", "wmh_create", "wmh_destroy", "wmh_set_bounds", "wmh
             "wmh_lsh_destroy",
             "wmh_last_error", "wmh_status_string",
             "wmh_server_create", "wmh_server_submit", "wmh_server_poll", "wmh_server_wait",
-            "wmh_server_drain", "wmh_server_stats", "wmh_server_now_ns", "wmh_server_destroy",
+            "wmh_server_drain", "wmh_server_stats", "wmh_server_reset_stats",
+            "wmh_server_now_ns", "wmh_server_destroy",
             "wmh_host_alloc", "wmh_host_free"]
 
 
@@ -62,7 +63,8 @@ class ServingStats(ctypes.Structure):
                 ("p99_ms", ctypes.c_double), ("p999_ms", ctypes.c_double),
                 ("max_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
                 ("busy_s", ctypes.c_double), ("hashes_per_s", ctypes.c_double),
-                ("rejected", ctypes.c_uint64)]
+                ("rejected", ctypes.c_uint64), ("max_on_device", ctypes.c_uint64),
+                ("max_computing", ctypes.c_uint64), ("overlap_s", ctypes.c_double)]
 
 
 class TuneResult(ctypes.Structure):
@@ -172,6 +174,8 @@ def load() -> ctypes.CDLL:
     L.wmh_server_drain.restype = ctypes.c_int
     L.wmh_server_stats.argtypes = [vp, ctypes.POINTER(ServingStats)]
     L.wmh_server_stats.restype = ctypes.c_int
+    L.wmh_server_reset_stats.argtypes = [vp]
+    L.wmh_server_reset_stats.restype = ctypes.c_int
     L.wmh_server_now_ns.argtypes = []
     L.wmh_server_now_ns.restype = ctypes.c_uint64
     L.wmh_server_destroy.argtypes = [vp]

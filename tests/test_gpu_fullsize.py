@@ -97,6 +97,9 @@ def test_histogram_full_size(ctx):
     say("plain form on all rows")
     plain = wmh.sig_to_numpy(ctx.hash(rows, k, seed=0, mode="plain"))
     assert np.array_equal(plain, got)
+    say("the tuned plan scheduled plainly (a launch per 8192 rows) on all rows")
+    shared = wmh.sig_to_numpy(ctx.hash(rows, k, seed=0, mode="plain_shared"))
+    assert np.array_equal(shared, got)
 
 
 def test_heavy_tail_full_size(ctx):
@@ -124,6 +127,9 @@ def test_heavy_tail_full_size(ctx):
     say("plain form on all rows")
     plain = wmh.sig_to_numpy(ctx.hash(rows, k, seed=0, mode="plain"))
     assert np.array_equal(plain, got)
+    say("the tuned plan scheduled plainly (a launch per 8192 rows) on all rows")
+    shared = wmh.sig_to_numpy(ctx.hash(rows, k, seed=0, mode="plain_shared"))
+    assert np.array_equal(shared, got)
     say("collision counts, rows [0, 1e4) x [1e4, 2e4)")
     A = sig[0:10000].contiguous()
     B = sig[10000:20000].contiguous()

@@ -115,6 +115,11 @@ def test_draws_with_zero_bounds_and_clusters(ctx):
     dict(mode="batched", walk="ballot"),
     dict(mode="batched", walk="ballot", use_graph=False, hashes_per_tile=13, waves_per_block=3),
     dict(mode="auto"),
+    # the batched walk's kernels scheduled plainly: a launch per batch, a workgroup per tile
+    dict(mode="plain_shared"),
+    dict(mode="plain_shared", batch_rows=100, walk="ballot"),
+    dict(mode="plain_shared", batch_rows=77, walk="rows"),
+    dict(mode="plain_shared", batch_rows=33, rows_per_block=4, hashes_per_tile=7),
 ])
 def test_config1_full(ctx, opts):
     ds = synth.config1()
@@ -166,6 +171,10 @@ def test_random_cases_all_plans(ctx, name):
     for plan in BATCHED_PLANS:
         got = gpu_sig(ctx, ds, k, seed, mode="batched", **plan)
         assert_same(got, want, f"{name} batched {plan}")
+    # the same plans scheduled plainly, in batches of 10 rows (a ragged last batch)
+    for plan in BATCHED_PLANS[::3]:
+        got = gpu_sig(ctx, ds, k, seed, mode="plain_shared", batch_rows=10, **plan)
+        assert_same(got, want, f"{name} plain_shared {plan}")
 
 
 def test_stream_kept_between_calls(ctx):

@@ -200,3 +200,36 @@ def test_large_dimension_requests(ctx):
             srv.wait(r.ticket)
     for rows, r in zip(row_lists, reqs):
         assert np.array_equal(r.sig, _oracle_sig(ds, rows, k, 4))
+
+
+def test_requests_overlap_on_the_device(ctx):
+    """A burst of slow requests (tiny green fractions, about 2e4 steps per hash) on four slots:
+    the device timestamps of their walks overlap, and each result equals wmh_hash's."""
+    ds = synth.random_case(seed=4, n_rows=240, D=2000, density=0.005, max_val=500,
+                           bound_slack=60000)
+    k, seed = 64, 17
+    ctx.set_bounds(ds.m)
+    rows = wmh.upload_dataset(ds, DEV)
+    want = wmh.sig_to_numpy(ctx.hash(rows, k, seed=seed, mode="batched"))
+    parts = [np.arange(i, ds.n_rows, 8) for i in range(8)]
+    print(f"  serving overlap: {len(parts)} requests of {len(parts[0])} rows", flush=True)
+    with serve.Server(ctx, k, seed=seed, slots=4, mode="batched") as srv:
+        reqs = serve.requests_from_corpus(ds, parts, srv, pinned=True)
+        for r in reqs:
+            srv.submit(r)
+        srv.drain()
+        for r in reqs:
+            srv.wait(r.ticket)
+        st = srv.stats()
+    assert st["completed"] == len(parts) and st["failed"] == 0
+    assert st["max_on_device"] >= 2 and st["max_computing"] >= 2 and st["overlap_s"] > 0, st
+    for idx, r in zip(parts, reqs):
+        assert np.array_equal(r.sig, want[idx])
+    # the counters start afresh after a reset
+    with serve.Server(ctx, k, seed=seed, slots=2, mode="batched") as srv:
+        r = serve.requests_from_corpus(ds, parts[:1], srv)[0]
+        srv.submit(r)
+        srv.wait(r.ticket)
+        srv.reset_stats()
+        st = srv.stats()
+    assert st["completed"] == 0 and st["max_computing"] == 0 and st["p50_ms"] == 0
