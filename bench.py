@@ -456,7 +456,14 @@ def text_like_bench(args, torch, synth, wmh) -> dict:
     cold_ms = (time.perf_counter() - t0) * 1e3
     first_rows_ms, build_ms = ctx.last_kernel_ms()
     mode = ctx.last_mode()
-    el, walk, _ = timed_steps(ctx, rows, k, sig, opts, 3, 0, torch)
+    # the index rows kernel's plan, tuned on these rows (the index is already built), then
+    # steady-state steps replaying it from a graph
+    tune = None
+    if not args.no_tune:
+        tune = ctx.tune(rows, k, 0, reps=1)
+        log(f"text-like: tuned {tune}")
+    el, walk, _ = timed_steps(ctx, rows, k, sig, opts, 3, 1, torch)
+    plan = ctx.last_plan()
     sig_np = wmh.sig_to_numpy(sig)
     head = ds.head(48)
     head_rows = wmh.upload_dataset(head, "cuda:0")
@@ -472,7 +479,7 @@ def text_like_bench(args, torch, synth, wmh) -> dict:
                        "Q16.16, k=1000, seed 0",
            "N": ds.n_rows, "D": ds.D, "k": k, "nnz": ds.nnz, "mode": mode,
            "hashes_per_s": hashes * 3 / el, "ms_per_step": el / 3 * 1e3,
-           "cold_ms_per_step": cold_ms,
+           "cold_ms_per_step": cold_ms, "graph": True, "plan": plan, "autotune": tune,
            "rows_kernel_ms": float(np.mean(walk)), "index_build_ms": build_ms,
            "first_call_rows_kernel_ms": first_rows_ms,
            "walk_steps_equivalent": int(sig_np.sum(dtype=np.int64)),

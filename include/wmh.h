@@ -128,7 +128,12 @@ typedef struct {
     uint32_t steps_per_lane;   /* batched mode, K: consecutive steps a lane tests per window;
                                   0 = R; R, or 4 when R < 4.  A window covers 64 / R * K steps
                                   of each of the block's R rows */
-    uint32_t reserved[3];
+    /* component index rows kernel (indexed mode; waves_per_block above sets its wavefronts
+       per workgroup, 1..16 with waves * k * 4 bytes <= 64 KiB); 0 = autotuned plan or the
+       launcher's choice.  use_graph replays the kernel (and its counter reset) as a graph */
+    uint32_t index_batch;      /* keys a lane loads per round trip: 8 or 16 */
+    uint32_t index_claim;      /* 1: wavefronts claim rows from a counter; 2: a fixed stride */
+    uint32_t reserved[1];
 } wmh_opts;
 
 /* Fills *opts with the defaults listed above. */
@@ -276,8 +281,8 @@ wmh_status wmh_last_kernel_ms(wmh_ctx *ctx, float *walk_ms, float *stream_ms);
 
 /*
  * wmh_last_mode -- the path the last successful wmh_hash on this context took:
- * WMH_MODE_PLAIN, WMH_MODE_BATCHED, WMH_MODE_INDEXED or WMH_MODE_SPLIT (WMH_MODE_AUTO before any
- * call).
+ * WMH_MODE_PLAIN, WMH_MODE_BATCHED, WMH_MODE_INDEXED, WMH_MODE_SPLIT or WMH_MODE_PLAIN_SHARED
+ * (WMH_MODE_AUTO before any call).
  * Errors: WMH_E_ARG (null).
  */
 wmh_status wmh_last_mode(const wmh_ctx *ctx, int32_t *mode);
@@ -285,8 +290,9 @@ wmh_status wmh_last_mode(const wmh_ctx *ctx, int32_t *mode);
 /*
  * wmh_last_plan -- the schedule of the last successful wmh_hash: plan->mode as wmh_last_mode,
  * and for the batched path the tile plan it ran (rows_per_block, hashes_per_tile,
- * stream_depth, waves_per_block, walk, steps_per_lane; 0 for the other paths).  Other fields
- * are the defaults.
+ * stream_depth, waves_per_block, walk, steps_per_lane; 0 for the other paths); for the indexed
+ * path the rows kernel's plan (waves_per_block, index_batch, index_claim; 0 = the launcher's
+ * own choice).  Other fields are the defaults.
  * Errors: WMH_E_ARG (null).
  */
 wmh_status wmh_last_plan(const wmh_ctx *ctx, wmh_opts *plan);
@@ -422,9 +428,13 @@ typedef struct {
     float default_ms;          /* the same with the planner's default plan */
     uint32_t candidates;       /* plans timed */
     int32_t steps_class;       /* floor(log2(mean capped steps per hash)) of the rows */
-    int32_t walk;              /* wmh_opts.walk of the fastest plan (1, 2 or 3) */
+    int32_t walk;              /* wmh_opts.walk of the fastest plan (1, 2 or 3), or 4 when
+                                  the rows go to the component index and the index rows
+                                  kernel's plan was tuned instead (waves_per_block,
+                                  index_batch, index_claim) */
     uint32_t steps_per_lane;   /* K of the fastest plan */
-    uint32_t reserved[2];
+    uint32_t index_batch;      /* walk 4: keys per round trip of the fastest plan */
+    uint32_t index_claim;      /* walk 4: 1 counter, 2 fixed stride */
 } wmh_tune_result;
 
 /*
@@ -436,15 +446,21 @@ typedef struct {
  * fastest in the context under (D, value width, k, step class).  Later wmh_hash calls in the
  * batched, split or auto mode whose plan options are 0 run the plan of their rows' key, or else
  * of the same (D, width, k) at the nearest step class within two (the walk rows of a split
- * have a smaller one).  sig (device, N*k uint16) receives the signatures.  Synchronous.
- * Errors: as wmh_hash, plus WMH_E_ARG when no batched plan fits.
+ * have a smaller one).  When the planner of the auto mode sends these rows to the component
+ * index, the tuner instead builds the index and times its rows kernel under W in
+ * {1,2,4,8,16} (as LDS allows) x keys per trip in {8,16} x row claims by counter or stride,
+ * keeps the fastest under the same key for indexed and auto calls whose index options are 0,
+ * and reports it with walk = 4.  sig (device, N*k uint16) receives the signatures.
+ * Synchronous.  Errors: as wmh_hash, plus WMH_E_ARG when neither a batched plan nor the index
+ * fits.
  */
 wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
                     const uint32_t *val, uint64_t n_rows, uint64_t nnz, uint32_t k, uint64_t seed,
                     uint16_t *sig, void *stream, uint32_t reps, wmh_tune_result *out);
 
-/* Writes the context's tuned plans to a text file: a "wmh-tune 3" line, then one line per key
- * "D narrow k steps_class R J W walk K ms".  Errors: WMH_E_ARG. */
+/* Writes the context's tuned plans to a text file: a "wmh-tune 4" line, then one line per key
+ * "D narrow k steps_class R J W walk K ms"; for a plan of the index rows kernel walk is 4, R
+ * the keys per trip, J the claim (1 counter, 2 stride) and K 0.  Errors: WMH_E_ARG. */
 wmh_status wmh_tune_save(wmh_ctx *ctx, const char *path);
 
 /* Adds the plans of a file written by wmh_tune_save (replacing equal keys); nothing is added

@@ -38,10 +38,17 @@ struct GraphKey {
     const void *row_class = nullptr;  // row filter of a split walk (nullptr: every row)
     uint32_t keep = 0;
     uint64_t bounds_epoch = 0;
+    // the component index's rows kernel (the walk fields above then stay 0)
+    bool indexed = false;
+    const void *index_keys = nullptr, *index_steps = nullptr, *index_offsets = nullptr;
+    uint32_t ix_batch = 0, ix_claim = 0;
     bool operator==(const GraphKey &o) const
     {
         return row_ptr == o.row_ptr && col == o.col && val == o.val && sig == o.sig &&
-               row_class == o.row_class && keep == o.keep &&
+               row_class == o.row_class && keep == o.keep && indexed == o.indexed &&
+               index_keys == o.index_keys && index_steps == o.index_steps &&
+               index_offsets == o.index_offsets && ix_batch == o.ix_batch &&
+               ix_claim == o.ix_claim &&
                n_rows == o.n_rows && nnz == o.nnz && seed == o.seed && k == o.k && R == o.R &&
                K == o.K &&
                J == o.J && depth == o.depth && waves == o.waves && grid == o.grid &&
@@ -96,7 +103,14 @@ struct TuneKey {
 struct TuneEntry {
     TuneKey key;
     uint32_t R = 0, J = 0, W = 0, K = 0;
-    int32_t walk = 1;  // wmh_opts.walk: 1 shared windows, 2 independent rows
+    int32_t walk = 1;  // wmh_opts.walk: 1 shared windows, 2 independent rows, 3 ballot walk
+    float ms = 0.f;
+};
+
+// An autotuned plan of the component index's rows kernel, for rows the planner sends there.
+struct IndexTuneEntry {
+    TuneKey key;
+    IndexPlan plan;
     float ms = 0.f;
 };
 
@@ -147,6 +161,8 @@ struct wmh_ctx {
     int32_t last_mode = 0;  // path of the last successful wmh_hash (wmh_mode)
     wmh::BatchedPlan last_plan{};  // its batched plan (when batched)
     std::vector<wmh::TuneEntry> tuned;  // autotuner results
+    std::vector<wmh::IndexTuneEntry> tuned_index;
+    wmh::IndexPlan last_index_plan{};  // index rows plan of the last indexed call
     int servers = 0;  // live serving loops using this context's bounds
     std::string last_error;
 };
@@ -184,6 +200,12 @@ Path choose_path(const wmh_ctx *ctx, int mode, bool batched_ok, bool index_ready
                  uint64_t n_rows, uint64_t nnz, const RowStats &stats, bool split_ok = false);
 // The statistics of the rows a split walks, as plan_batched reads them.
 RowStats walk_class_stats(const RowStats &stats);
+// Plan of the index rows kernel: the options' (waves_per_block, index_batch, index_claim)
+// when any is set, else the autotuned plan of the rows' key (or the same (D, width, k) at the
+// nearest step class within two), else the launcher's defaults.  False when the options do
+// not fit.
+bool plan_index(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const wmh_opts &o,
+                IndexPlan *plan);
 
 // The static device scratch of wmh_hash_noalloc (wmh_noalloc.hip): looks up its address on
 // `device`, which must be current, once per device; later calls return the first result.

@@ -174,6 +174,33 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const w
     return true;
 }
 
+bool plan_index(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const wmh_opts &o,
+                IndexPlan *plan)
+{
+    IndexPlan p;
+    if (o.waves_per_block || o.index_batch || o.index_claim) {
+        p.waves = o.waves_per_block;
+        p.batch = o.index_batch;
+        p.claim = o.index_claim;
+    } else if (stats.known) {
+        const TuneKey key = tune_key(ctx, k, stats);
+        int best = 3;
+        for (const IndexTuneEntry &e : ctx->tuned_index) {
+            if (e.key.dims != key.dims || e.key.narrow != key.narrow || e.key.k != key.k) continue;
+            const int d = std::abs(e.key.steps_class - key.steps_class);
+            if (d < best) {
+                best = d;
+                p = e.plan;
+            }
+        }
+    }
+    if (index_rows_waves(k, p.waves) == 0 || (p.batch && p.batch != 8 && p.batch != 16) ||
+        p.claim > 2)
+        return false;
+    *plan = p;
+    return true;
+}
+
 // Relative costs in units of one membership test of the batched walk (measured on MI355X:
 // the walk runs about 1.7e12 tests/s; the other figures are per item of the named kind).
 namespace {
@@ -639,13 +666,56 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
     }
 
     if (path == Path::kIndexed) {
+        IndexPlan ip;
+        if (!plan_index(ctx, k, stats, o, &ip))
+            return fail(ctx, WMH_E_ARG, "index rows plan does not fit (waves %u, batch %u, "
+                        "claim %u, k %u)", o.waves_per_block, o.index_batch, o.index_claim, k);
         if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[0], s));
         const wmh_status st = ensure_index(ctx, &ctx->index, seed, k, s);
         if (st != WMH_OK) return st;
-        if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[1], s));
-        const uint32_t grid = (uint32_t)ctx->cu_count * (uint32_t)index_rows_blocks_per_cu(k);
-        WMH_HIP(ctx, launch_index_rows(rows, ctx->index.buf, b, k, sig, ctx->d_row_counter, grid, s));
+        const uint32_t grid =
+            (uint32_t)ctx->cu_count * (uint32_t)index_rows_blocks_per_cu(k, ip.waves);
+        if (o.use_graph) {
+            // the steady state (counter reset and rows kernel) replayed as a graph
+            GraphKey key;
+            key.row_ptr = row_ptr; key.col = col; key.val = val; key.sig = sig;
+            key.n_rows = n_rows; key.nnz = nnz; key.seed = seed; key.k = k;
+            key.waves = ip.waves; key.grid = grid; key.bounds_epoch = ctx->bounds_epoch;
+            key.indexed = true;
+            key.index_keys = ctx->index.buf.entries;
+            key.index_steps = ctx->index.buf.by_step;
+            key.index_offsets = ctx->index.buf.offsets;
+            key.ix_batch = ip.batch;
+            key.ix_claim = ip.claim;
+            if (!(ctx->graph_exec && ctx->graph_key == key)) {
+                drop_graph(ctx);
+                hipGraph_t graph = nullptr;
+                WMH_HIP(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+                hipError_t e = launch_index_rows(rows, ctx->index.buf, b, k, sig,
+                                                 ctx->d_row_counter, grid, ctx->capture_stream, ip);
+                hipError_t e2 = hipStreamEndCapture(ctx->capture_stream, &graph);
+                if (e != hipSuccess) {
+                    if (graph) hipGraphDestroy(graph);
+                    return device_fail(ctx, e, "index rows launch (capture)");
+                }
+                if (e2 != hipSuccess) return device_fail(ctx, e2, "hipStreamEndCapture");
+                e = hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0);
+                hipGraphDestroy(graph);
+                if (e != hipSuccess) {
+                    ctx->graph_exec = nullptr;
+                    return device_fail(ctx, e, "hipGraphInstantiate");
+                }
+                ctx->graph_key = key;
+            }
+            if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[1], s));
+            WMH_HIP(ctx, hipGraphLaunch(ctx->graph_exec, s));
+        } else {
+            if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[1], s));
+            WMH_HIP(ctx, launch_index_rows(rows, ctx->index.buf, b, k, sig, ctx->d_row_counter,
+                                           grid, s, ip));
+        }
         if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[2], s));
+        ctx->last_index_plan = ip;
         WMH_HIP(ctx, hipEventRecord(ctx->index.used, s));
         ctx->profiled = profile;
         ctx->profiled_stream = profile && !index_ready;
@@ -838,6 +908,15 @@ wmh_status wmh_last_plan(const wmh_ctx *ctx, wmh_opts *plan)
     plan->stream_depth = ctx->last_plan.stream_depth;
     plan->steps_per_lane = ctx->last_plan.steps_per_lane;
     plan->waves_per_block = ctx->last_plan.waves_per_block;
+    if (ctx->last_mode == WMH_MODE_INDEXED) {
+        plan->rows_per_block = plan->hashes_per_tile = plan->stream_depth = 0;
+        plan->steps_per_lane = 0;
+        plan->waves_per_block = ctx->last_index_plan.waves;
+        plan->index_batch = ctx->last_index_plan.batch;
+        plan->index_claim = ctx->last_index_plan.claim;
+        plan->walk = 0;
+        return WMH_OK;
+    }
     plan->walk = ctx->last_mode != WMH_MODE_BATCHED && ctx->last_mode != WMH_MODE_SPLIT &&
                          ctx->last_mode != WMH_MODE_PLAIN_SHARED
                      ? 0

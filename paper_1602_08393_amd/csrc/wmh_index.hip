@@ -302,7 +302,7 @@ __device__ __forceinline__ void step_scan(const uint64_t *__restrict__ by_step, 
 }
 
 template <bool kFiltered, uint32_t B>
-__global__ __launch_bounds__(256) void index_rows_kernel(Rows rows,
+__global__ __launch_bounds__(1024) void index_rows_kernel(Rows rows,
                                                          const uint32_t *__restrict__ offsets,
                                                          const uint64_t *__restrict__ entries,
                                                          const uint64_t *__restrict__ by_step,
@@ -472,30 +472,38 @@ hipError_t launch_index_build(const Bounds &b, uint64_t seed, uint32_t k, const 
     return hipGetLastError();
 }
 
-namespace {
+constexpr size_t kIndexRowsLdsMax = 64 * 1024;  // running minima of one workgroup
 
-uint32_t index_rows_waves(uint32_t k) { return k <= 2048 ? 4u : 1u; }
-
-size_t index_rows_lds_bytes(uint32_t k) { return (size_t)index_rows_waves(k) * k * sizeof(uint32_t); }
-
-}  // namespace
-
-int index_rows_blocks_per_cu(uint32_t k)
+uint32_t index_rows_waves(uint32_t k, uint32_t waves)
 {
+    if (waves == 0) waves = k <= 2048 ? 4u : 1u;
+    if (waves > kIndexMaxWaves || (size_t)waves * k * sizeof(uint32_t) > kIndexRowsLdsMax)
+        return 0;
+    return waves;
+}
+
+int index_rows_blocks_per_cu(uint32_t k, uint32_t waves_in)
+{
+    const uint32_t waves = index_rows_waves(k, waves_in);
+    if (waves == 0) return 1;
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, index_rows_kernel<false, kBatch>,
-                                                     index_rows_waves(k) * kWave,
-                                                     index_rows_lds_bytes(k)) != hipSuccess)
+                                                     waves * kWave,
+                                                     (size_t)waves * k * sizeof(uint32_t)) !=
+        hipSuccess)
         return 1;
     return std::max(1, n);
 }
 
 hipError_t launch_index_rows(const Rows &rows, const IndexBuffers &ix, const Bounds &b, uint32_t k,
                              uint16_t *sig, unsigned long long *row_counter, uint32_t grid,
-                             hipStream_t stream)
+                             hipStream_t stream, const IndexPlan &plan)
 {
     if (rows.n_rows == 0) return hipSuccess;
-    const uint32_t waves = index_rows_waves(k);
+    const uint32_t waves = index_rows_waves(k, plan.waves);
+    if (waves == 0 || (plan.batch != 0 && plan.batch != kBatch && plan.batch != kShortBatch) ||
+        plan.claim > 2)
+        return hipErrorInvalidValue;
     const uint64_t need = (rows.n_rows + waves - 1) / waves;
     const uint32_t g = (uint32_t)std::min<uint64_t>(need, grid);
     // every hash of a step-order row is <= T1 with probability >= 1 - 1/16, <= T2 with >= 1 - 1e-4
@@ -504,8 +512,9 @@ hipError_t launch_index_rows(const Rows &rows, const IndexBuffers &ix, const Bou
     // Long lists (text-like: ~1000 keys each) read 16 keys per trip, short ones (~16 keys, as
     // for D = 2^20 and k = 256) 8; large batches hand out rows from a counter, small ones (a
     // serving request) by a fixed stride, which measured faster there.
-    const bool long_lists = (double)k * kIndexSteps / (double)b.dims >= 64.0;
-    const bool claim_rows = rows.n_rows >= 16ull * g * waves;
+    const bool long_lists = plan.batch ? plan.batch == kBatch
+                                       : (double)k * kIndexSteps / (double)b.dims >= 64.0;
+    const bool claim_rows = plan.claim ? plan.claim == 1 : rows.n_rows >= 16ull * g * waves;
     if (claim_rows || rows.row_class) {
         const hipError_t e =
             launch_fill_u32(reinterpret_cast<uint32_t *>(row_counter), 0u, 2, stream);
@@ -514,7 +523,7 @@ hipError_t launch_index_rows(const Rows &rows, const IndexBuffers &ix, const Bou
     // a filtered launch claims rows 64 at a time: one wavefront takes at most every 64th row
     const uint64_t need_filtered = (rows.n_rows + kWave * waves - 1) / (kWave * waves);
     const uint32_t gf = (uint32_t)std::min<uint64_t>(need_filtered, g);
-    const size_t lds = index_rows_lds_bytes(k);
+    const size_t lds = (size_t)waves * k * sizeof(uint32_t);
     const uint32_t threads = waves * kWave;
 #define WMH_INDEX_ROWS(F, B, G)                                                                    \
     index_rows_kernel<F, B><<<G, threads, lds, stream>>>(rows, ix.offsets, ix.entries, ix.by_step, \

@@ -181,13 +181,27 @@ inline uint64_t index_scan_blocks(uint32_t dims) { return ((uint64_t)dims + 1 + 
 hipError_t launch_index_build(const Bounds &b, uint64_t seed, uint32_t k, const IndexBuffers &ix,
                               hipStream_t stream);
 
+// Scheduling of the index rows kernel (it never changes a value); 0 leaves a choice to the
+// launcher.
+struct IndexPlan {
+    uint32_t waves = 0;  // wavefronts per workgroup, 1..16 with waves * k * 4 bytes of LDS
+                         // (0: 4 for k <= 2048, else 1)
+    uint32_t batch = 0;  // keys a lane loads per round trip, 8 or 16 (0: 16 where lists are
+                         // long, 8 where short)
+    uint32_t claim = 0;  // 1: wavefronts claim rows from a counter, 2: a fixed stride over the
+                         // batch (0: the counter for batches of >= 16 rows per wavefront)
+};
+constexpr uint32_t kIndexMaxWaves = 16u;
+// The plan's wavefronts per workgroup for k hashes, or 0 when they do not fit.
+uint32_t index_rows_waves(uint32_t k, uint32_t waves);
+
 // row_counter: one device word, cleared by launches that claim rows from it.
 hipError_t launch_index_rows(const Rows &rows, const IndexBuffers &ix, const Bounds &b, uint32_t k,
                              uint16_t *sig, unsigned long long *row_counter, uint32_t grid,
-                             hipStream_t stream);
+                             hipStream_t stream, const IndexPlan &plan = IndexPlan{});
 
-// Resident workgroups per CU of the index row kernel.
-int index_rows_blocks_per_cu(uint32_t k);
+// Resident workgroups per CU of the index row kernel with `waves` wavefronts (0: default).
+int index_rows_blocks_per_cu(uint32_t k, uint32_t waves = 0);
 
 // b-bit signatures (wmh_codec.hip): f = 32 / bits fields per word, W = ceil(k / f) words a row.
 uint32_t pack_words(uint32_t k, uint32_t bits);  // 0 when bits is not in [1, 16] or k = 0

@@ -21,7 +21,7 @@ STATUS = {0: "WMH_OK", -1: "WMH_E_ARG", -2: "WMH_E_NO_BOUNDS", -3: "WMH_E_COL_RA
           -8: "WMH_E_DEVICE", -9: "WMH_E_ROW_PTR"}
 NOALLOC_SCRATCH_BYTES = 16 << 20  # WMH_NOALLOC_SCRATCH_BYTES: wmh_hash_noalloc's static array
 MODES = {"auto": 0, "plain": 1, "batched": 2, "indexed": 3, "split": 4, "plain_shared": 5}
-WALKS = {"auto": 0, "shared": 1, "rows": 2, "ballot": 3}
+WALKS = {"auto": 0, "shared": 1, "rows": 2, "ballot": 3, "index": 4}
 
 EXPORTED = ["wmh_opts_init", "wmh_create", "wmh_destroy", "wmh_set_bounds", "wmh_hash",
             "wmh_hash_noalloc",
@@ -45,7 +45,8 @@ class WmhOpts(ctypes.Structure):
                 ("hashes_per_tile", ctypes.c_uint32), ("stream_depth", ctypes.c_uint32),
                 ("waves_per_block", ctypes.c_uint32), ("profile", ctypes.c_int32),
                 ("walk", ctypes.c_int32), ("steps_per_lane", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 3)]
+                ("index_batch", ctypes.c_uint32), ("index_claim", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 1)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -73,7 +74,7 @@ class TuneResult(ctypes.Structure):
                 ("best_ms", ctypes.c_float), ("default_ms", ctypes.c_float),
                 ("candidates", ctypes.c_uint32), ("steps_class", ctypes.c_int32),
                 ("walk", ctypes.c_int32), ("steps_per_lane", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 2)]
+                ("index_batch", ctypes.c_uint32), ("index_claim", ctypes.c_uint32)]
 
 
 class WMHError(RuntimeError):
@@ -357,7 +358,8 @@ class Context:
     @staticmethod
     def make_opts(mode="auto", batch_rows=0, validate=True, use_graph=True, sync=True,
                   rows_per_block=0, hashes_per_tile=0, stream_depth=0, waves_per_block=0,
-                  profile=False, walk=0, steps_per_lane=0) -> WmhOpts:
+                  profile=False, walk=0, steps_per_lane=0, index_batch=0,
+                  index_claim=0) -> WmhOpts:
         o = WmhOpts()
         load().wmh_opts_init(ctypes.byref(o))
         o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
@@ -373,6 +375,8 @@ class Context:
         o.profile = int(bool(profile))
         o.walk = WALKS[walk] if isinstance(walk, str) else int(walk)
         o.steps_per_lane = steps_per_lane
+        o.index_batch = index_batch
+        o.index_claim = {"counter": 1, "stride": 2}.get(index_claim, index_claim)
         return o
 
     def last_kernel_ms(self) -> tuple[float, float]:
@@ -397,7 +401,8 @@ class Context:
                 "rows_per_block": o.rows_per_block, "hashes_per_tile": o.hashes_per_tile,
                 "stream_depth": o.stream_depth, "waves_per_block": o.waves_per_block,
                 "walk": {v: k for k, v in WALKS.items()}.get(o.walk, o.walk),
-                "steps_per_lane": o.steps_per_lane}
+                "steps_per_lane": o.steps_per_lane, "index_batch": o.index_batch,
+                "index_claim": o.index_claim}
 
     def tune(self, rows: DeviceRows, k: int, seed: int = 0, reps: int = 3, stream=None) -> dict:
         """Autotunes the batched tile plan on these rows (see wmh_tune); returns the result and
@@ -414,7 +419,8 @@ class Context:
                 "best_ms": r.best_ms, "default_ms": r.default_ms, "candidates": r.candidates,
                 "steps_class": r.steps_class,
                 "walk": {v: k for k, v in WALKS.items()}.get(r.walk, r.walk),
-                "steps_per_lane": r.steps_per_lane}
+                "steps_per_lane": r.steps_per_lane, "index_batch": r.index_batch,
+                "index_claim": r.index_claim}
 
     def tune_save(self, path: str):
         self._check(self._lib.wmh_tune_save(self._ptr, os.fsencode(path)), "wmh_tune_save")

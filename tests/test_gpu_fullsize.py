@@ -152,13 +152,42 @@ def test_text_like_rows_full_batch(ctx):
     say(f"text-like N={ds.n_rows} D={ds.D} nnz={ds.nnz} k={k}")
     ctx.set_bounds(ds.m)
     rows = wmh.upload_dataset(ds, DEV)
-    got = wmh.sig_to_numpy(ctx.hash(rows, k, seed=0, mode="auto"))
+    tuned = ctx.tune(rows, k, 0, reps=1)
+    say(f"tuned plan {tuned}")
+    assert tuned["walk"] == "index"
+    sig = torch.empty((ds.n_rows, k), dtype=torch.int16, device=DEV)
+    opts = ctx.make_opts(mode="auto")  # graph replay of the tuned index rows kernel
+    ctx.hash_into(rows, k, 0, sig, opts=opts)
     assert ctx.last_mode() == "indexed"
-    idx = sample_rows(ds, 12, 14)
+    plan = ctx.last_plan()
+    assert (plan["waves_per_block"], plan["index_batch"], plan["index_claim"]) == \
+        (tuned["waves_per_block"], tuned["index_batch"], tuned["index_claim"])
+    got = wmh.sig_to_numpy(sig)
+    # the rows whose step-order reads left a hash id open past T1 (second pass) or past T2
+    # (offset-order pass), by the kernel's own rule (Theorem 2 bounds)
+    M = float(ds.m.astype(np.float64).sum())
+    rows_of = np.repeat(np.arange(ds.n_rows), np.diff(ds.row_ptr.astype(np.int64)))
+    sx = np.bincount(rows_of, weights=ds.val.astype(np.float64), minlength=ds.n_rows)
+    sm = np.bincount(rows_of, weights=np.where(ds.val > 0, ds.m[ds.col], 0).astype(np.float64),
+                     minlength=ds.n_rows)
+    s = np.maximum(sx, 1) / M
+    t1 = np.ceil(np.log((1 / 16) / k) / np.log1p(-s))
+    t2 = np.ceil(np.log(1e-4 / k) / np.log1p(-s))
+    by_steps = (sx > 0) & (t2 < 65534) & (t2 * sm < 65534.0 * sx)
+    top = got.max(axis=1)
+    second = np.flatnonzero(by_steps & (top > t1))
+    third = np.flatnonzero(by_steps & (top > t2))
+    say(f"{by_steps.sum()} step-order rows; {len(second)} read again to T2, {len(third)} in "
+        f"offset order")
+    assert len(second) > 0
+    idx = sample_rows(ds, 12, 14, extra=np.concatenate([second[:8], third[:8]]))
     say(f"oracle on {len(idx)} sampled rows")
     assert_rows_equal(got[idx], oracle_rows(ds, idx, k), idx, "text-like auto")
-    again = wmh.sig_to_numpy(ctx.hash(rows, k, seed=0, mode="auto"))
-    assert np.array_equal(again, got)
+    for _ in range(2):  # graph replays, with eager work between them
+        sig.zero_()
+        ctx.hash_into(rows, k, 0, sig, opts=opts)
+        torch.cuda.synchronize()
+        assert np.array_equal(wmh.sig_to_numpy(sig), got), "replay differs from the first call"
 
 
 def test_serving_on_the_large_corpus(ctx):

@@ -74,7 +74,7 @@ def test_save_and_load(ctx, ds, tmp_path):
     res = ctx.tune(rows, ds.k, seed=0, reps=1)
     path = tmp_path / "plans.txt"
     ctx.tune_save(str(path))
-    assert path.read_text().startswith("wmh-tune 3\n")
+    assert path.read_text().startswith("wmh-tune 4\n")
     fresh = wmh.Context(0)
     try:
         fresh.set_bounds(ds.m)
@@ -83,7 +83,7 @@ def test_save_and_load(ctx, ds, tmp_path):
         p = fresh.last_plan()
         assert _plan_of(p) == _plan_of(res)
         bad = tmp_path / "bad.txt"
-        bad.write_text("wmh-tune 3\n1024 0 64 4 3 64 8 1 3 0.5\n")  # R = 3 is not a plan
+        bad.write_text("wmh-tune 4\n1024 0 64 4 3 64 8 1 3 0.5\n")  # R = 3 is not a plan
         with pytest.raises(wmh.WMHError) as e:
             fresh.tune_load(str(bad))
         assert e.value.name == "WMH_E_ARG"
@@ -91,3 +91,73 @@ def test_save_and_load(ctx, ds, tmp_path):
             fresh.tune_load(str(tmp_path / "missing.txt"))
     finally:
         fresh.close()
+
+
+def _sparse_rows():
+    """Rows with tiny green fractions (about 2e4 steps per hash): the planner sends them to the
+    component index."""
+    return synth.random_case(seed=4, n_rows=300, D=2000, density=0.005, max_val=500,
+                             bound_slack=60000, k=64)
+
+
+def test_index_rows_plan_is_tuned_and_taken(ctx, tmp_path):
+    ds = _sparse_rows()
+    k = ds.k
+    print("  tune index rows", flush=True)
+    ctx.set_bounds(ds.m)
+    rows = wmh.upload_dataset(ds, DEV)
+    res = ctx.tune(rows, k, seed=3, reps=1)
+    assert res["walk"] == "index", res
+    assert res["index_batch"] in (8, 16) and res["index_claim"] in (1, 2)
+    assert res["candidates"] >= 8 and 0 < res["best_ms"]
+    want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, k, seed=3)
+    for mode in ("indexed", "auto"):
+        got = wmh.sig_to_numpy(ctx.hash(rows, k, seed=3, mode=mode))
+        assert np.array_equal(got, want)
+        plan = ctx.last_plan()
+        assert plan["mode"] == "indexed"
+        assert (plan["waves_per_block"], plan["index_batch"], plan["index_claim"]) == \
+            (res["waves_per_block"], res["index_batch"], res["index_claim"])
+    path = tmp_path / "index_plans.txt"
+    ctx.tune_save(str(path))
+    assert any(line.split()[7] == "4" for line in path.read_text().splitlines()[1:])
+    fresh = wmh.Context(0)
+    try:
+        fresh.set_bounds(ds.m)
+        fresh.tune_load(str(path))
+        assert np.array_equal(wmh.sig_to_numpy(fresh.hash(rows, k, seed=3, mode="indexed")), want)
+        p = fresh.last_plan()
+        assert (p["waves_per_block"], p["index_batch"], p["index_claim"]) == \
+            (res["waves_per_block"], res["index_batch"], res["index_claim"])
+    finally:
+        fresh.close()
+
+
+def test_index_rows_plans_and_graph_replays(ctx):
+    """Every index rows plan gives the oracle's values, launched directly and replayed from a
+    graph (with eager work between replays)."""
+    ds = _sparse_rows()
+    k = ds.k
+    ctx.set_bounds(ds.m)
+    rows = wmh.upload_dataset(ds, DEV)
+    want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, k, seed=8)
+    for W in (1, 2, 4, 8, 16):
+        for B in (8, 16):
+            for C in ("counter", "stride"):
+                for graph in (False, True):
+                    got = wmh.sig_to_numpy(ctx.hash(rows, k, seed=8, mode="indexed",
+                                                    waves_per_block=W, index_batch=B,
+                                                    index_claim=C, use_graph=graph))
+                    assert np.array_equal(got, want), (W, B, C, graph)
+    sig = torch.empty((ds.n_rows, k), dtype=torch.int16, device=DEV)
+    opts = ctx.make_opts(mode="indexed", waves_per_block=4, index_batch=16, index_claim=1)
+    for _ in range(4):
+        sig.fill_(-1)
+        scratch = torch.randn(1 << 16, device=DEV).sum()  # eager work between replays
+        ctx.hash_into(rows, k, 8, sig, opts=opts)
+        torch.cuda.synchronize()
+        assert float(scratch) == float(scratch)
+        assert np.array_equal(wmh.sig_to_numpy(sig), want)
+    with pytest.raises(wmh.WMHError) as e:  # 32 wavefronts do not fit a workgroup
+        ctx.hash(rows, k, seed=8, mode="indexed", waves_per_block=32)
+    assert e.value.name == "WMH_E_ARG"
