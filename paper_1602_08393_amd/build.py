@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import concurrent.futures
+import hashlib
 import os
 import shutil
 import subprocess
@@ -33,25 +34,35 @@ def hipcc() -> str:
 def flags() -> list[str]:
     return [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
             "-Wno-unused-result", "-Wno-unused-value", "-munsafe-fp-atomics",
-            # packed fp32 instructions stay off in every HIP object of this library
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
 
 
-# hipcc forwards -Xclang options to both the device and the host pass of each file, and the
-# host pass reports the device-only feature as unknown (and ignores it).  That one notice is
-# dropped from the build output; every other line of the compiler's output is shown.
-_HOST_FEATURE_NOTICE = "'-packed-fp32-ops' is not a recognized feature for this target"
+# Device-only options: packed fp32 instructions stay off in every HIP object of this library.
+# They are a feature of the GPU target, so they go to the device pass alone.
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
 def _run(cmd: list[str]) -> None:
     r = subprocess.run(cmd, capture_output=True, text=True)
     for stream, text in ((sys.stdout, r.stdout), (sys.stderr, r.stderr)):
-        lines = [ln for ln in text.splitlines() if _HOST_FEATURE_NOTICE not in ln]
-        if lines:
-            print("\n".join(lines), file=stream, flush=True)
+        if text.strip():
+            print(text.rstrip(), file=stream, flush=True)
     if r.returncode != 0:
         raise subprocess.CalledProcessError(r.returncode, cmd)
+
+
+def _compile_cmds(cc: str, src: str, obj: str) -> list[list[str]]:
+    """Two passes per file: the device code (with DEVICE_FLAGS) into a code-object bundle, then
+    the host code with that bundle embedded.  Both passes share one compilation-unit id, which
+    names the file's device symbols on both sides."""
+    base = os.path.splitext(obj)[0]
+    bundle = base + ".hipfb"
+    cuid = hashlib.sha1(os.path.abspath(src).encode()).hexdigest()[:16]
+    common = ["-x", "hip", *flags(), *EXTRA.get(os.path.basename(src), []), f"-cuid={cuid}"]
+    device = [cc, *common, "--offload-device-only", *DEVICE_FLAGS, "-c", src, "-o", bundle]
+    host = [cc, *common, "--offload-host-only", "-Xclang", "-fcuda-include-gpubinary",
+            "-Xclang", bundle, "-c", src, "-o", obj]
+    return [device, host]
 
 
 def build(verbose: bool = False) -> str:
@@ -59,20 +70,24 @@ def build(verbose: bool = False) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     objects = []
-    cmds = []
+    jobs = []
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        lang = ["-x", "hip"]
-        cmds.append([cc, *lang, *flags(), *EXTRA.get(src, []), "-c", os.path.join(CSRC, src),
-                     "-o", obj])
+        jobs.append(_compile_cmds(cc, os.path.join(CSRC, src), obj))
         objects.append(obj)
     if verbose:
-        for cmd in cmds:
-            print(" ".join(cmd), flush=True)
+        for job in jobs:
+            for cmd in job:
+                print(" ".join(cmd), flush=True)
+
+    def run_job(job):
+        for cmd in job:
+            _run(cmd)
+
     # the files compile independently: a few at a time
-    workers = max(1, min(len(cmds), (os.cpu_count() or 1), 8))
+    workers = max(1, min(len(jobs), (os.cpu_count() or 1), 8))
     with concurrent.futures.ThreadPoolExecutor(workers) as pool:
-        for f in [pool.submit(_run, cmd) for cmd in cmds]:
+        for f in [pool.submit(run_job, job) for job in jobs]:
             f.result()
     tmp = LIB + ".tmp"
     cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", *objects, "-o", tmp]
