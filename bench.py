@@ -104,6 +104,8 @@ def parse():
     ap.add_argument("--stream-depth", type=int, default=0)
     ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--steps-per-lane", type=int, default=0)
+    ap.add_argument("--hash-groups", type=int, default=0,
+                    help="ballot walk: hash ids in this many groups (0: planner or autotuner)")
     ap.add_argument("--walk", type=int, default=0, choices=[0, 1, 2, 3],
                     help="batched walk: 0 planner/autotuner, 1 shared windows, 2 independent "
                          "rows, 3 ballot walk (one row per block)")
@@ -249,7 +251,8 @@ def plan_args(args) -> dict:
     """Tile-plan options given on the command line (0: planner or autotuner)."""
     return dict(rows_per_block=args.rows_per_block, hashes_per_tile=args.hashes_per_tile,
                 stream_depth=args.stream_depth, waves_per_block=args.waves_per_block,
-                walk=args.walk, steps_per_lane=args.steps_per_lane)
+                walk=args.walk, steps_per_lane=args.steps_per_lane,
+                hash_groups=args.hash_groups)
 
 
 def timed_steps(ctx, rows, k, sig, opts, steps, warmup, torch):

@@ -133,7 +133,13 @@ typedef struct {
        launcher's choice.  use_graph replays the kernel (and its counter reset) as a graph */
     uint32_t index_batch;      /* keys a lane loads per round trip: 8 or 16 */
     uint32_t index_claim;      /* 1: wavefronts claim rows from a counter; 2: a fixed stride */
-    uint32_t reserved[1];
+    uint32_t hash_groups;      /* ballot walk: 0 = planner / autotuner choice; G in 1..8 cuts
+                                  the hash ids into G blocks of ceil(k / G) (fewer when a block
+                                  would be empty), each with its own tile counter; a workgroup
+                                  starts on block blockIdx mod G, so the workgroups of one XCD
+                                  (dispatched in turn) mostly read one block's part of the
+                                  shared stream from their L2.  Each row is staged once per
+                                  block.  1 = one counter over all tiles */
 } wmh_opts;
 
 /* Fills *opts with the defaults listed above. */
@@ -435,13 +441,16 @@ typedef struct {
     uint32_t steps_per_lane;   /* K of the fastest plan */
     uint32_t index_batch;      /* walk 4: keys per round trip of the fastest plan */
     uint32_t index_claim;      /* walk 4: 1 counter, 2 fixed stride */
+    uint32_t hash_groups;      /* ballot walk: hash groups of the fastest plan (1 otherwise) */
+    uint32_t reserved[3];
 } wmh_tune_result;
 
 /*
  * wmh_tune -- times the batched walk on the given rows (device CSR as for wmh_hash) under
  * candidate plans R in {1,2,4,8,16} x W in {4,8,16} x J in {min(k,1024), min(k,512),
  * min(k,256)} with shared windows and K = R, the same with K = 4 for R = 1 and 2, plus R = 4
- * with independent rows and R = 1 with the ballot walk for every W and J, each
+ * with independent rows and R = 1 with the ballot walk for every W and J (and the ballot walk
+ * with its hash ids in 2, 4 and 8 groups for every W), each
  * the best of `reps` (0 = 3) calls after one untimed call, and keeps the
  * fastest in the context under (D, value width, k, step class).  Later wmh_hash calls in the
  * batched, split or auto mode whose plan options are 0 run the plan of their rows' key, or else
@@ -458,9 +467,10 @@ wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
                     const uint32_t *val, uint64_t n_rows, uint64_t nnz, uint32_t k, uint64_t seed,
                     uint16_t *sig, void *stream, uint32_t reps, wmh_tune_result *out);
 
-/* Writes the context's tuned plans to a text file: a "wmh-tune 4" line, then one line per key
- * "D narrow k steps_class R J W walk K ms"; for a plan of the index rows kernel walk is 4, R
- * the keys per trip, J the claim (1 counter, 2 stride) and K 0.  Errors: WMH_E_ARG. */
+/* Writes the context's tuned plans to a text file: a "wmh-tune 5" line, then one line per key
+ * "D narrow k steps_class R J W walk K G ms" (G: hash groups of the ballot walk); for a plan
+ * of the index rows kernel walk is 4, R the keys per trip, J the claim (1 counter, 2 stride),
+ * K 0 and G 1.  Errors: WMH_E_ARG. */
 wmh_status wmh_tune_save(wmh_ctx *ctx, const char *path);
 
 /* Adds the plans of a file written by wmh_tune_save (replacing equal keys); nothing is added

@@ -33,7 +33,7 @@ struct GraphKey {
     const void *row_ptr = nullptr, *col = nullptr, *val = nullptr;
     void *sig = nullptr;
     uint64_t n_rows = 0, nnz = 0, seed = 0;
-    uint32_t k = 0, R = 0, K = 0, J = 0, depth = 0, waves = 0, grid = 0;
+    uint32_t k = 0, R = 0, K = 0, J = 0, depth = 0, waves = 0, grid = 0, groups = 0;
     bool narrow = false, packed = false, independent_rows = false, ballot = false;
     const void *row_class = nullptr;  // row filter of a split walk (nullptr: every row)
     uint32_t keep = 0;
@@ -52,6 +52,7 @@ struct GraphKey {
                n_rows == o.n_rows && nnz == o.nnz && seed == o.seed && k == o.k && R == o.R &&
                K == o.K &&
                J == o.J && depth == o.depth && waves == o.waves && grid == o.grid &&
+               groups == o.groups &&
                narrow == o.narrow && packed == o.packed &&
                independent_rows == o.independent_rows && ballot == o.ballot &&
                bounds_epoch == o.bounds_epoch;
@@ -102,7 +103,7 @@ struct TuneKey {
 
 struct TuneEntry {
     TuneKey key;
-    uint32_t R = 0, J = 0, W = 0, K = 0;
+    uint32_t R = 0, J = 0, W = 0, K = 0, G = 1;  // G: hash groups of the ballot walk
     int32_t walk = 1;  // wmh_opts.walk: 1 shared windows, 2 independent rows, 3 ballot walk
     float ms = 0.f;
 };

@@ -117,6 +117,7 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const w
             o.waves_per_block = pick->W;
             o.walk = pick->walk;
             o.steps_per_lane = pick->K;
+            o.hash_groups = pick->G;
         }
     }
     const uint64_t min_green = stats.known ? stats.min_green : ~0ull;
@@ -146,6 +147,12 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const w
     p.steps_per_lane = K;
     p.independent_rows = o.walk == 2;
     p.ballot = o.walk == 3;
+    // hash groups (ballot walk): G blocks of ceil(k / G) ids, G lowered until none is empty
+    if (o.hash_groups > kMaxHashGroups || (o.hash_groups > 1 && !p.ballot)) return false;
+    uint32_t G = o.hash_groups ? o.hash_groups : 1;
+    while (G > 1 && (uint64_t)(G - 1) * ((k + G - 1) / G) >= k) --G;
+    p.hash_groups = G;
+    if (G > 1) p.hashes_per_tile = (k + G - 1) / G;
     if (batched_lds_bytes(ctx->dims, p) > 160 * 1024 - 64) return false;
     p.packed = p.narrow && (uint64_t)ctx->dims * p.scale() <= 65536u;
     // shared stream depth: cover eight mean step counts of the sparsest row, in whole cycles of
@@ -466,7 +473,7 @@ wmh_status wmh_create(int device, wmh_ctx **out)
         hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) != hipSuccess ||
         hipMalloc(&ctx->d_check, sizeof(CheckWords)) != hipSuccess ||
         hipHostMalloc(&ctx->h_check, sizeof(CheckWords), hipHostMallocDefault) != hipSuccess ||
-        hipMalloc(&ctx->d_tile_counter, sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&ctx->d_tile_counter, kMaxHashGroups * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&ctx->d_row_counter, sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&ctx->d_codec, 2 * sizeof(unsigned long long)) != hipSuccess ||
         hipHostMalloc(&ctx->h_codec, 2 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
@@ -766,6 +773,7 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         key.packed = pl.packed;
         key.independent_rows = pl.independent_rows;
         key.ballot = pl.ballot;
+        key.groups = pl.hash_groups;
         key.row_class = wrows.row_class;
         key.keep = wrows.keep;
         key.bounds_epoch = ctx->bounds_epoch;
@@ -795,6 +803,8 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
             // workgroup per (row block, hash block) tile, no counter and no graph
             const uint64_t step = o.batch_rows ? o.batch_rows : 8192;
             const uint64_t hash_tiles = (k + pl.hashes_per_tile - 1) / pl.hashes_per_tile;
+            BatchedPlan one = pl;  // static tiles: (row block, hash block) over one index
+            one.hash_groups = 1;
             if (((step + pl.rows_per_block - 1) / pl.rows_per_block) * hash_tiles > UINT32_MAX)
                 return fail(ctx, WMH_E_ARG, "a batch of %llu rows has too many tiles for one launch",
                             (unsigned long long)step);
@@ -805,7 +815,7 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
                 batch.n_rows = std::min(n_rows, r0 + step) - r0;
                 const uint64_t tiles =
                     (batch.n_rows + pl.rows_per_block - 1) / pl.rows_per_block * hash_tiles;
-                WMH_HIP(ctx, launch_batched(b, batch, k, seed, sig + r0 * k, pl, ctx->d_stream,
+                WMH_HIP(ctx, launch_batched(b, batch, k, seed, sig + r0 * k, one, ctx->d_stream,
                                             nullptr, (uint32_t)tiles, s));
             }
             if (profile) WMH_HIP(ctx, hipEventRecord(ctx->ev[2], s));
@@ -815,7 +825,8 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
 
         // events around the walk only on direct launches; a graph is timed as a whole
         auto enqueue = [&](hipStream_t q, bool events) -> hipError_t {
-            hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->d_tile_counter), 0u, 2, q);
+            hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->d_tile_counter), 0u,
+                                           2 * kMaxHashGroups, q);
             if (e != hipSuccess) return e;
             if (events && (e = hipEventRecord(ctx->ev[1], q)) != hipSuccess) return e;
             e = launch_batched(b, wrows, k, seed, sig, pl, ctx->d_stream, ctx->d_tile_counter,
@@ -908,9 +919,11 @@ wmh_status wmh_last_plan(const wmh_ctx *ctx, wmh_opts *plan)
     plan->stream_depth = ctx->last_plan.stream_depth;
     plan->steps_per_lane = ctx->last_plan.steps_per_lane;
     plan->waves_per_block = ctx->last_plan.waves_per_block;
+    plan->hash_groups = ctx->last_plan.hash_groups;
     if (ctx->last_mode == WMH_MODE_INDEXED) {
         plan->rows_per_block = plan->hashes_per_tile = plan->stream_depth = 0;
         plan->steps_per_lane = 0;
+        plan->hash_groups = 0;
         plan->waves_per_block = ctx->last_index_plan.waves;
         plan->index_batch = ctx->last_index_plan.batch;
         plan->index_claim = ctx->last_index_plan.claim;

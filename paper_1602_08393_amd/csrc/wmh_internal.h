@@ -80,6 +80,8 @@ struct BatchedPlan {
     bool independent_rows;     // each row of a block walks its own hash ids (R = 4 only)
     bool ballot;               // one row per block, first green step from the window's ballot
                                // (R = 1, K = 1 only)
+    uint32_t hash_groups = 1;  // ballot walk: hash ids in this many blocks of J ids, one tile
+                               // counter each (1: a single counter over (row, block) tiles)
     // LDS bytes per component of the block's dense rows (RowLayout::kGroup): four rows of
     // 16-bit values sit in two planes of row pairs, 4 bytes per component
     uint32_t scale() const
@@ -113,6 +115,9 @@ hipError_t launch_draws(const Bounds &b, uint64_t seed, uint32_t j0, uint32_t n_
 
 hipError_t launch_stream_build(const Bounds &b, uint64_t seed, uint32_t k, uint32_t depth,
                                bool packed, uint32_t scale, void *entries, hipStream_t stream);
+
+// Tile counters a batched launch may use (one per hash group), u64 each, cleared before it.
+constexpr uint32_t kMaxHashGroups = 8;
 
 // Returns hipErrorInvalidValue when the plan does not fit (LDS).
 hipError_t launch_batched(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,

@@ -738,6 +738,10 @@ hipError_t launch_batched(const Bounds &b, const Rows &rows, uint32_t k, uint64_
     if (plan.packed && !plan.narrow) return hipErrorInvalidValue;
     // the shared walk reads whole three-window cycles of the stream (plus one spare cycle)
     if (plan.stream_depth % plan.cycle() != 0 || plan.stream_depth >= kCap) return hipErrorInvalidValue;
+    if (plan.hash_groups > 1 && (!plan.ballot || plan.hash_groups > kMaxHashGroups ||
+                                 !tile_counter ||
+                                 (uint64_t)(plan.hash_groups - 1) * plan.hashes_per_tile >= k))
+        return hipErrorInvalidValue;
     if (plan.ballot) {
         if (plan.rows_per_block != 1 || plan.steps_per_lane != 1 || plan.independent_rows)
             return hipErrorInvalidValue;

@@ -30,6 +30,8 @@ constexpr size_t kTileCounterAt = 0;
 constexpr size_t kCheckWordsAt = 256;
 constexpr size_t kStreamAt = 512;
 static_assert(sizeof(CheckWords) <= kStreamAt - kCheckWordsAt, "validation words overlap");
+static_assert(kMaxHashGroups * sizeof(unsigned long long) <= kCheckWordsAt - kTileCounterAt,
+              "tile counters overlap");
 
 constexpr int kMaxDevices = 64;
 std::mutex g_lookup;
@@ -148,7 +150,8 @@ extern "C" wmh_status wmh_hash_noalloc(wmh_ctx *ctx, const uint64_t *row_ptr, co
     if (plan.stream_depth)
         WMH_NA_HIP(ctx, launch_stream_build(b, seed, k, plan.stream_depth, plan.packed,
                                             plan.scale(), entries, s));
-    WMH_NA_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(counter), 0u, 2, s));
+    WMH_NA_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(counter), 0u,
+                                    2 * kMaxHashGroups, s));
     if (profile) WMH_NA_HIP(ctx, hipEventRecord(ctx->ev[1], s));
     WMH_NA_HIP(ctx, launch_batched(b, rows, k, seed, sig, plan, entries, counter, grid, s));
     if (profile) WMH_NA_HIP(ctx, hipEventRecord(ctx->ev[2], s));

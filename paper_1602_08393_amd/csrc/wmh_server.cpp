@@ -224,7 +224,8 @@ wmh_status wmh_server::launch_compute(Slot &slot, Request &r)
         if (e == hipSuccess) e = hipEventRecord(index.used, s);
     } else if (e == hipSuccess) {
         if (batched) {
-            e = launch_fill_u32(reinterpret_cast<uint32_t *>(slot.d_tile_counter), 0u, 2, s);
+            e = launch_fill_u32(reinterpret_cast<uint32_t *>(slot.d_tile_counter), 0u,
+                                2 * kMaxHashGroups, s);
             if (e == hipSuccess)
                 e = launch_batched(b, rows, k, cfg.seed, slot.d_sig, plan, d_stream,
                                    slot.d_tile_counter, grid, s);
@@ -397,7 +398,8 @@ wmh_status wmh_server_create(wmh_ctx *ctx, const wmh_server_config *cfg_in, wmh_
     for (Slot &slot : srv->slots) {
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&slot.finished, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipMalloc(&slot.d_tile_counter, sizeof(unsigned long long));
+        if (e == hipSuccess)
+            e = hipMalloc(&slot.d_tile_counter, kMaxHashGroups * sizeof(unsigned long long));
         if (e == hipSuccess) e = hipMalloc(&slot.d_row_counter, sizeof(unsigned long long));
         if (e == hipSuccess) e = hipEventCreateWithFlags(&slot.checked, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreate(&slot.t_begin);

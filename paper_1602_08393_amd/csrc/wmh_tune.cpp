@@ -22,7 +22,7 @@ using namespace wmh;
 
 namespace {
 
-constexpr char kTuneHeader[] = "wmh-tune 4";
+constexpr char kTuneHeader[] = "wmh-tune 5";
 constexpr int32_t kIndexWalk = 4;  // a tuning line of the index rows kernel
 
 void put_entry(wmh_ctx *ctx, const TuneEntry &e)
@@ -51,11 +51,12 @@ bool valid_index_plan(uint32_t batch, uint32_t claim, uint32_t W)
            W <= kIndexMaxWaves;
 }
 
-bool valid_plan(uint32_t R, uint32_t J, uint32_t W, int32_t walk, uint32_t K)
+bool valid_plan(uint32_t R, uint32_t J, uint32_t W, int32_t walk, uint32_t K, uint32_t G)
 {
     return (R == 1 || R == 2 || R == 4 || R == 8 || R == 16) && J >= 1 && W >= 1 && W <= 16 &&
            (walk == 1 || (walk == 2 && R == 4) || (walk == 3 && R == 1 && K == 1)) &&
-           (K == R || (K == 4 && R < 4));
+           (K == R || (K == 4 && R < 4)) && G >= 1 && G <= kMaxHashGroups &&
+           (G == 1 || walk == 3);
 }
 
 }  // namespace
@@ -164,9 +165,10 @@ wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
     }
     // best of `reps` timed calls after one untimed call; <0 when the plan does not fit
     auto time_plan = [&](uint32_t R, uint32_t J, uint32_t W, int32_t walk, uint32_t K,
-                         float *ms) -> wmh_status {
+                         uint32_t G, float *ms) -> wmh_status {
         wmh_opts o = base;
         o.walk = walk;
+        o.hash_groups = G;
         o.steps_per_lane = K;
         o.mode = WMH_MODE_BATCHED;
         o.validate = 0;
@@ -184,7 +186,7 @@ wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
     wmh_tune_result res{};
     float default_ms = 0.f;
     st = time_plan(def.rows_per_block, def.hashes_per_tile, def.waves_per_block, 1,
-                   def.steps_per_lane, &default_ms);
+                   def.steps_per_lane, 1, &default_ms);
     TuneEntry best;
     best.key = tune_key(ctx, k, stats);
     best.R = def.rows_per_block;
@@ -204,24 +206,32 @@ wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
     };
     const Shape shapes[] = {{1, 1, 1}, {1, 1, 4}, {1, 2, 2}, {1, 2, 4}, {1, 4, 4},
                             {1, 8, 8}, {1, 16, 16}, {2, 4, 4}, {3, 1, 1}};
+    // the ballot walk also with its hash ids in 2, 4 or 8 groups (J then follows from G)
+    std::vector<uint32_t> groups_of_ballot{1u};
+    for (uint32_t G : {2u, 4u, 8u})
+        if ((uint64_t)(G - 1) * ((k + G - 1) / G) < k) groups_of_ballot.push_back(G);
     for (const Shape &sh : shapes) {
-        for (uint32_t W : {4u, 8u, 16u}) {
-            for (uint32_t J : Js) {
-                if (st != WMH_OK) break;
-                if (sh.walk == 1 && sh.R == def.rows_per_block && sh.K == def.steps_per_lane &&
-                    J == def.hashes_per_tile && W == def.waves_per_block)
-                    continue;
-                float ms = -1.f;
-                st = time_plan(sh.R, J, W, sh.walk, sh.K, &ms);
-                if (st == WMH_OK && ms >= 0.f) {
-                    ++tried;
-                    if (ms < best.ms) {
-                        best.R = sh.R;
-                        best.J = J;
-                        best.W = W;
-                        best.walk = sh.walk;
-                        best.K = sh.K;
-                        best.ms = ms;
+        for (uint32_t G : sh.walk == 3 ? groups_of_ballot : std::vector<uint32_t>{1u}) {
+            for (uint32_t W : {4u, 8u, 16u}) {
+                for (uint32_t J : G == 1 ? Js : std::vector<uint32_t>{(k + G - 1) / G}) {
+                    if (st != WMH_OK) break;
+                    if (sh.walk == 1 && sh.R == def.rows_per_block &&
+                        sh.K == def.steps_per_lane && J == def.hashes_per_tile &&
+                        W == def.waves_per_block)
+                        continue;
+                    float ms = -1.f;
+                    st = time_plan(sh.R, J, W, sh.walk, sh.K, G, &ms);
+                    if (st == WMH_OK && ms >= 0.f) {
+                        ++tried;
+                        if (ms < best.ms) {
+                            best.R = sh.R;
+                            best.J = J;
+                            best.W = W;
+                            best.walk = sh.walk;
+                            best.K = sh.K;
+                            best.G = G;
+                            best.ms = ms;
+                        }
                     }
                 }
             }
@@ -241,6 +251,7 @@ wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
     res.steps_class = best.key.steps_class;
     res.walk = best.walk;
     res.steps_per_lane = best.K;
+    res.hash_groups = best.G;
     *out = res;
     return WMH_OK;
 }
@@ -252,13 +263,13 @@ wmh_status wmh_tune_save(wmh_ctx *ctx, const char *path)
     if (!f) return fail(ctx, WMH_E_ARG, "cannot write %s", path);
     std::fprintf(f, "%s\n", kTuneHeader);
     for (const TuneEntry &e : ctx->tuned)
-        std::fprintf(f, "%u %d %u %d %u %u %u %d %u %.6f\n", e.key.dims, e.key.narrow ? 1 : 0,
-                     e.key.k, e.key.steps_class, e.R, e.J, e.W, e.walk, e.K, (double)e.ms);
+        std::fprintf(f, "%u %d %u %d %u %u %u %d %u %u %.6f\n", e.key.dims, e.key.narrow ? 1 : 0,
+                     e.key.k, e.key.steps_class, e.R, e.J, e.W, e.walk, e.K, e.G, (double)e.ms);
     // index rows plans: keys per trip and claim in the R and J columns, walk 4
     for (const IndexTuneEntry &e : ctx->tuned_index)
-        std::fprintf(f, "%u %d %u %d %u %u %u %d %u %.6f\n", e.key.dims, e.key.narrow ? 1 : 0,
-                     e.key.k, e.key.steps_class, e.plan.batch, e.plan.claim, e.plan.waves,
-                     kIndexWalk, 0u, (double)e.ms);
+        std::fprintf(f, "%u %d %u %d %u %u %u %d %u %u %.6f\n", e.key.dims,
+                     e.key.narrow ? 1 : 0, e.key.k, e.key.steps_class, e.plan.batch, e.plan.claim,
+                     e.plan.waves, kIndexWalk, 0u, 1u, (double)e.ms);
     const bool ok = std::fclose(f) == 0;
     return ok ? WMH_OK : fail(ctx, WMH_E_ARG, "cannot write %s", path);
 }
@@ -277,8 +288,9 @@ wmh_status wmh_tune_load(wmh_ctx *ctx, const char *path)
         TuneEntry e;
         int narrow = 0;
         double ms = 0;
-        if (std::sscanf(line, "%u %d %u %d %u %u %u %d %u %lf", &e.key.dims, &narrow, &e.key.k,
-                        &e.key.steps_class, &e.R, &e.J, &e.W, &e.walk, &e.K, &ms) != 10 ||
+        if (std::sscanf(line, "%u %d %u %d %u %u %u %d %u %u %lf", &e.key.dims, &narrow,
+                        &e.key.k, &e.key.steps_class, &e.R, &e.J, &e.W, &e.walk, &e.K, &e.G,
+                        &ms) != 11 ||
             (narrow != 0 && narrow != 1) || e.key.k == 0) {
             ok = false;
             break;
@@ -299,7 +311,7 @@ wmh_status wmh_tune_load(wmh_ctx *ctx, const char *path)
             got_index.push_back(x);
             continue;
         }
-        if (!valid_plan(e.R, e.J, e.W, e.walk, e.K)) {
+        if (!valid_plan(e.R, e.J, e.W, e.walk, e.K, e.G)) {
             ok = false;
             break;
         }

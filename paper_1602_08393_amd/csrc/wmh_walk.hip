@@ -95,6 +95,44 @@ __device__ __forceinline__ void stage_block(unsigned char *smem, const Rows &row
     __syncthreads();
 }
 
+// Replaces the one dense row held in LDS (x[0..D)) by CSR row `row`: the previous row's columns
+// (CSR entries [prev_lo, prev_hi)) are set back to zero, or, while LDS holds no row yet
+// (have_row false), the whole row is zero-filled; then the new row's values are scattered and
+// bit 0 of *nonempty tells whether it has a nonzero value.  After the first row a row costs its
+// nonzeros rather than D.  Called by the whole workgroup; records the new row's entry range.
+template <typename XT>
+__device__ __forceinline__ void restage_row(unsigned char *smem, const Rows &rows, uint64_t row,
+                                            uint32_t D, bool &have_row, uint64_t &prev_lo,
+                                            uint64_t &prev_hi, uint32_t *nonempty)
+{
+    XT *x = reinterpret_cast<XT *>(smem);
+    if (!have_row) {
+        uint32_t *xz = reinterpret_cast<uint32_t *>(smem);
+        const uint32_t words = (uint32_t)(((size_t)D * sizeof(XT) + 3) / 4);
+        for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) xz[i] = 0u;
+    } else {
+        for (uint64_t e = prev_lo + threadIdx.x; e < prev_hi; e += blockDim.x) {
+            const uint32_t c = rows.col[e];
+            if (c < D) x[c] = (XT)0;
+        }
+    }
+    if (threadIdx.x == 0) *nonempty = 0;
+    __syncthreads();
+    const uint64_t lo = rows.row_ptr[row], hi = rows.row_ptr[row + 1];
+    uint32_t mine = 0;
+    for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+        const uint32_t v = rows.val[e];
+        const uint32_t c = rows.col[e];
+        if (c < D) x[c] = (XT)v;
+        if (v) mine = 1u;
+    }
+    if (mine) atomicOr(nonempty, mine);
+    __syncthreads();
+    have_row = true;
+    prev_lo = lo;
+    prev_hi = hi;
+}
+
 // Writes a tile's hash values (staged in LDS, row r at hbuf[r * hashes_per_tile]) row by row,
 // coalesced along j, except rows with bit r of `skip`.  Called by the whole workgroup; ends
 // with a barrier.
@@ -305,15 +343,24 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
 // cross-lane reduction.  Stream windows come three at a time from a ring prefetched three windows
 // ahead (as in the shared-window walk); steps past the stream are drawn in-lane.  Hash ids are
 // claimed in pairs whose first windows are requested together (see below).
+//
+// Hash groups (groups = G > 1): the hash ids are cut into G blocks of hashes_per_tile ids, and
+// group g's tiles are (row, block g) for every row, claimed from counter g.  A workgroup starts
+// on group blockIdx.x mod G and moves on to the next group once its own is exhausted.
+// Workgroups are dispatched to the chip's XCDs in turn, so with G = 8 (or a divisor of 8) the
+// workgroups of one XCD mostly walk one block of hash ids, and that XCD's L2 holds only that
+// block's part of the position stream; each row is then staged once per group.
 // ---------------------------------------------------------------------------------------------
 template <typename XT, bool kPacked>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void ballot_kernel(
     Bounds b, Rows rows, uint32_t k, uint64_t seed, uint16_t *__restrict__ sig,
-    uint32_t hashes_per_tile, uint32_t depth, const void *entries, unsigned long long *tile_counter)
+    uint32_t hashes_per_tile, uint32_t depth, const void *entries, unsigned long long *tile_counter,
+    uint32_t groups)
 {
     constexpr uint32_t kWords = EntryRun<1, kPacked>::kWordsPerEntry;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ unsigned long long tile_slot;
+    __shared__ unsigned long long tile_row;
+    __shared__ uint32_t tile_ht;
     __shared__ uint32_t unit_slot;
     __shared__ uint32_t nonempty;
     const uint32_t D = b.dims;
@@ -322,28 +369,55 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     const uint32_t n_hash_tiles = (k + hashes_per_tile - 1) / hashes_per_tile;
     const uint64_t n_tiles = rows.n_rows * n_hash_tiles;
     uint64_t staged = ~0ull;
+    bool have_row = false;
+    uint64_t staged_lo = 0, staged_hi = 0;  // CSR entries of the row in LDS
     bool claimed = false;
+    uint32_t group_step = 0;  // thread 0: groups left behind, counted from the workgroup's own
 
     while (true) {
         if (threadIdx.x == 0) {
-            tile_slot = next_tile(tile_counter, claimed);
+            uint64_t r = ~0ull;
+            uint32_t h = 0;
+            if (groups <= 1) {
+                const uint64_t t = next_tile(tile_counter, claimed);
+                if (t < n_tiles) {
+                    r = t / n_hash_tiles;
+                    h = (uint32_t)(t - r * n_hash_tiles);
+                }
+            } else {
+                // every group's counter passes n_rows at most once per workgroup: the loop ends
+                for (; group_step < groups; ++group_step) {
+                    const uint32_t g = (blockIdx.x + group_step) % groups;
+                    const uint64_t u = atomicAdd(&tile_counter[g], 1ull);
+                    if (u < rows.n_rows) {
+                        r = u;
+                        h = g;
+                        break;
+                    }
+                }
+            }
+            tile_row = r;
+            tile_ht = h;
             unit_slot = 0;
         }
         __syncthreads();
-        const uint64_t tile = tile_slot;
-        if (tile >= n_tiles) break;
-        const uint64_t row = tile / n_hash_tiles;
-        const uint32_t ht = (uint32_t)(tile - row * n_hash_tiles);
+        const uint64_t row = tile_row;
+        if (row == ~0ull) break;
+        const uint32_t ht = tile_ht;
         if (rows.skips(row)) {  // a row another path computes (row filter)
-            __syncthreads();    // every thread has read tile_slot before it is claimed again
+            __syncthreads();    // every thread has read the tile before it is claimed again
             continue;
         }
         if (row != staged) {
-            stage_block<XT, 1>(smem, rows, row, 1u, D, &nonempty);
+            restage_row<XT>(smem, rows, row, D, have_row, staged_lo, staged_hi, &nonempty);
             staged = row;
         }
         const bool live = __builtin_amdgcn_readfirstlane(nonempty) != 0;
         const uint32_t j0 = ht * hashes_per_tile;
+        if (j0 >= k) {  // an empty hash block (the host's plans leave none)
+            __syncthreads();
+            continue;
+        }
         const uint32_t j1 = min(k, j0 + hashes_per_tile);
 
         // ballot of the lanes whose step is green in the window the run holds
@@ -485,7 +559,8 @@ hipError_t launch_ballot_t(const Bounds &b, const Rows &rows, uint32_t k, uint64
     const size_t lds = batched_lds_bytes(b.dims, plan);
     configure_ballot<XT, kPacked>();
     ballot_kernel<XT, kPacked><<<grid, plan.waves_per_block * kWave, lds, stream>>>(
-        b, rows, k, seed, sig, plan.hashes_per_tile, plan.stream_depth, entries, tile_counter);
+        b, rows, k, seed, sig, plan.hashes_per_tile, plan.stream_depth, entries, tile_counter,
+        plan.hash_groups);
     return hipGetLastError();
 }
 

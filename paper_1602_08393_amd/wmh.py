@@ -46,7 +46,7 @@ class WmhOpts(ctypes.Structure):
                 ("waves_per_block", ctypes.c_uint32), ("profile", ctypes.c_int32),
                 ("walk", ctypes.c_int32), ("steps_per_lane", ctypes.c_uint32),
                 ("index_batch", ctypes.c_uint32), ("index_claim", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 1)]
+                ("hash_groups", ctypes.c_uint32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -74,7 +74,8 @@ class TuneResult(ctypes.Structure):
                 ("best_ms", ctypes.c_float), ("default_ms", ctypes.c_float),
                 ("candidates", ctypes.c_uint32), ("steps_class", ctypes.c_int32),
                 ("walk", ctypes.c_int32), ("steps_per_lane", ctypes.c_uint32),
-                ("index_batch", ctypes.c_uint32), ("index_claim", ctypes.c_uint32)]
+                ("index_batch", ctypes.c_uint32), ("index_claim", ctypes.c_uint32),
+                ("hash_groups", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
 
 
 class WMHError(RuntimeError):
@@ -359,7 +360,7 @@ class Context:
     def make_opts(mode="auto", batch_rows=0, validate=True, use_graph=True, sync=True,
                   rows_per_block=0, hashes_per_tile=0, stream_depth=0, waves_per_block=0,
                   profile=False, walk=0, steps_per_lane=0, index_batch=0,
-                  index_claim=0) -> WmhOpts:
+                  index_claim=0, hash_groups=0) -> WmhOpts:
         o = WmhOpts()
         load().wmh_opts_init(ctypes.byref(o))
         o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
@@ -377,6 +378,7 @@ class Context:
         o.steps_per_lane = steps_per_lane
         o.index_batch = index_batch
         o.index_claim = {"counter": 1, "stride": 2}.get(index_claim, index_claim)
+        o.hash_groups = hash_groups
         return o
 
     def last_kernel_ms(self) -> tuple[float, float]:
@@ -402,7 +404,7 @@ class Context:
                 "stream_depth": o.stream_depth, "waves_per_block": o.waves_per_block,
                 "walk": {v: k for k, v in WALKS.items()}.get(o.walk, o.walk),
                 "steps_per_lane": o.steps_per_lane, "index_batch": o.index_batch,
-                "index_claim": o.index_claim}
+                "index_claim": o.index_claim, "hash_groups": o.hash_groups}
 
     def tune(self, rows: DeviceRows, k: int, seed: int = 0, reps: int = 3, stream=None) -> dict:
         """Autotunes the batched tile plan on these rows (see wmh_tune); returns the result and
@@ -420,7 +422,7 @@ class Context:
                 "steps_class": r.steps_class,
                 "walk": {v: k for k, v in WALKS.items()}.get(r.walk, r.walk),
                 "steps_per_lane": r.steps_per_lane, "index_batch": r.index_batch,
-                "index_claim": r.index_claim}
+                "index_claim": r.index_claim, "hash_groups": r.hash_groups}
 
     def tune_save(self, path: str):
         self._check(self._lib.wmh_tune_save(self._ptr, os.fsencode(path)), "wmh_tune_save")

@@ -120,6 +120,10 @@ def test_draws_with_zero_bounds_and_clusters(ctx):
     dict(mode="plain_shared", batch_rows=100, walk="ballot"),
     dict(mode="plain_shared", batch_rows=77, walk="rows"),
     dict(mode="plain_shared", batch_rows=33, rows_per_block=4, hashes_per_tile=7),
+    # the ballot walk with its hash ids in groups, one tile counter each
+    dict(mode="batched", walk="ballot", hash_groups=8),
+    dict(mode="batched", walk="ballot", hash_groups=3, use_graph=False, waves_per_block=5),
+    dict(mode="plain_shared", walk="ballot", hash_groups=4, batch_rows=300),
 ])
 def test_config1_full(ctx, opts):
     ds = synth.config1()
@@ -147,6 +151,9 @@ BATCHED_PLANS = [
     dict(walk="ballot", waves_per_block=1), dict(walk="ballot", waves_per_block=16),
     dict(walk="ballot", stream_depth=None), dict(walk="ballot", stream_depth=64),
     dict(walk="ballot", stream_depth=200, hashes_per_tile=9),
+    dict(walk="ballot", hash_groups=2), dict(walk="ballot", hash_groups=8, waves_per_block=4),
+    dict(walk="ballot", hash_groups=5, stream_depth=64),
+    dict(walk="ballot", hash_groups=8, stream_depth=None),
 ]
 
 CASES = {
@@ -306,6 +313,7 @@ def test_many_hash_ids(ctx):
     want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, k, seed=13)
     for opts in (dict(mode="batched"), dict(mode="batched", hashes_per_tile=4096),
                  dict(mode="batched", walk="ballot", hashes_per_tile=4096),
+                 dict(mode="batched", walk="ballot", hash_groups=8),
                  dict(mode="plain")):
         assert_same(gpu_sig(ctx, ds, k, 13, **opts), want, f"k={k} {opts}")
 
@@ -333,7 +341,8 @@ def test_full_rows_hash_to_one_and_saturation(ctx):
                  dict(mode="batched", rows_per_block=2, steps_per_lane=4, stream_depth=None),
                  dict(mode="batched", walk="ballot"),
                  dict(mode="batched", walk="ballot", stream_depth=70000),
-                 dict(mode="batched", walk="ballot", stream_depth=None)):
+                 dict(mode="batched", walk="ballot", stream_depth=None),
+                 dict(mode="batched", walk="ballot", hash_groups=8)):
         assert_same(gpu_sig(ctx, ds, k, 5, **opts), want, f"saturation {opts}")
 
 

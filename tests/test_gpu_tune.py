@@ -29,7 +29,7 @@ def ds():
 
 def _plan_of(res):
     return (res["rows_per_block"], res["hashes_per_tile"], res["waves_per_block"], res["walk"],
-            res["steps_per_lane"])
+            res["steps_per_lane"], res["hash_groups"])
 
 
 def test_tune_then_hash_uses_the_plan(ctx, ds):
@@ -74,7 +74,7 @@ def test_save_and_load(ctx, ds, tmp_path):
     res = ctx.tune(rows, ds.k, seed=0, reps=1)
     path = tmp_path / "plans.txt"
     ctx.tune_save(str(path))
-    assert path.read_text().startswith("wmh-tune 4\n")
+    assert path.read_text().startswith("wmh-tune 5\n")
     fresh = wmh.Context(0)
     try:
         fresh.set_bounds(ds.m)
@@ -83,7 +83,7 @@ def test_save_and_load(ctx, ds, tmp_path):
         p = fresh.last_plan()
         assert _plan_of(p) == _plan_of(res)
         bad = tmp_path / "bad.txt"
-        bad.write_text("wmh-tune 4\n1024 0 64 4 3 64 8 1 3 0.5\n")  # R = 3 is not a plan
+        bad.write_text("wmh-tune 5\n1024 0 64 4 3 64 8 1 3 1 0.5\n")  # R = 3 is not a plan
         with pytest.raises(wmh.WMHError) as e:
             fresh.tune_load(str(bad))
         assert e.value.name == "WMH_E_ARG"

@@ -51,6 +51,7 @@ def test_plans_and_empty_rows(ctx):
     ds = synth.random_case(11, 300, 512, 0.05, 1000, empty_rows=5)
     for plan in ({}, {"rows_per_block": 1, "walk": "ballot"},
                  {"rows_per_block": 2, "steps_per_lane": 4}, {"walk": "rows"},
+                 {"rows_per_block": 1, "walk": "ballot", "hash_groups": 8},
                  {"stream_depth": None}):
         want, got = both(ctx, ds, 96, seed=3, **plan)
         assert np.array_equal(got, want), plan
