@@ -29,11 +29,18 @@ PCIE_PEAK_GBS = 64.0  # PCIe 5.0 x16, per direction
 OPS_PER_TEST = 2  # one lookup of x at the draw's component and one compare
 OPS_PER_COMPARE = 2  # collision counting: one u16 equality and one accumulate per hash pair
 KEY_BYTES = 8  # one component-index key
-# HBM bytes per launch of batched_kernel<unsigned short, 4, true> on the full histogram-shaped
-# workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy (read x2.000,
-# write x1.000); profiles/batched_kernel_histogram_k500.txt.  Valid while that kernel and plan
-# (R = 4, narrow packed entries) are the ones timed.
-TRAFFIC_R4_HISTOGRAM = 1.2029e9 + 0.1009e9
+# HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the same counters on
+# a 1 GiB device-to-device copy (read x2.000, write x1.000).  Each figure is valid while its
+# kernel and plan are the ones timed; the line carries null otherwise.
+#   batched_kernel<unsigned short, 4, 4, true> on the histogram workload (N = 1e5):
+#     profiles/batched_kernel_histogram_k500.txt
+TRAFFIC_R4_HISTOGRAM = 1.2033e9 + 0.1009e9
+#   ballot_kernel<unsigned int, false>, 16 wavefronts, J = 500, one hash group, on the heavy tail
+#     (depth 40704): profiles/ballot_kernel_heavy_tail_k500.txt
+TRAFFIC_BALLOT_HEAVY_TAIL = 46.2558e9 + 0.2114e9
+#   index_rows_kernel<false, 16>, 16 wavefronts, counter claims, on the 1e6 text-like rows:
+#     profiles/index_rows_kernel_text_like_k1000.txt
+TRAFFIC_INDEX_TEXT_LIKE = 432.1412e9 + 2.0670e9
 
 
 def log(msg: str):
@@ -330,8 +337,14 @@ def heavy_tail_bench(args, torch, synth, wmh) -> dict:
                 "batched_ms_per_step": el_b / 3 * 1e3,
                 "batched_walk_ms": float(np.mean(walk_b)),
                 "mean_steps_per_hash": tests / hashes,
-                "roofline": alu_roofline(tests, float(np.mean(walk_b)),
-                                         f"{out['batched_plan']['walk']} walk")})
+                "roofline": alu_roofline(
+                    tests, float(np.mean(walk_b)), f"{out['batched_plan']['walk']} walk",
+                    traffic=TRAFFIC_BALLOT_HEAVY_TAIL if (
+                        out["batched_plan"]["walk"] == "ballot"
+                        and out["batched_plan"]["waves_per_block"] == 16
+                        and out["batched_plan"]["hashes_per_tile"] == 500
+                        and out["batched_plan"]["hash_groups"] == 1 and ds.n_rows == 200_000)
+                    else None)})
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = oracle_on_head(ds, 4096, k, wmh.sig_to_numpy(sig_b[:4096]))
         log(f"heavy-tail: oracle {out['cpu_baseline']['value']:.3g} hashes/s on 4096 rows, "
@@ -494,6 +507,9 @@ def text_like_bench(args, torch, synth, wmh) -> dict:
     out["roofline"] = hbm_roofline(key_bytes, float(np.mean(walk)), "index_rows_kernel",
                                    note="expected keys of the rows' evaluation orders "
                                         "(Theorem 2), the rows and the signatures, once each")
+    if (plan["waves_per_block"], plan["index_batch"], plan["index_claim"]) == (16, 16, 1) \
+            and ds.n_rows == 1_000_000:
+        out["roofline"]["traffic"] = TRAFFIC_INDEX_TEXT_LIKE
     out["roofline"].update(key_info)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = oracle_on_head(ds, 48, k, sig_np[:48])

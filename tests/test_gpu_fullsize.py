@@ -190,6 +190,45 @@ def test_text_like_rows_full_batch(ctx):
         assert np.array_equal(wmh.sig_to_numpy(sig), got), "replay differs from the first call"
 
 
+def test_text_like_full_million_rows(ctx):
+    """All 1e6 rows of the text-like workload (D = 65536, k = 1000), in the benchmark's launch
+    configuration (index rows plan tuned on these rows, graph replay); the oracle checks the
+    first and last rows, a random spread, the lightest and heaviest rows and rows that ran the
+    index's second and offset-order passes."""
+    ds = synth.config3()
+    k = ds.k
+    say(f"text-like full N={ds.n_rows} D={ds.D} nnz={ds.nnz} k={k}")
+    ctx.set_bounds(ds.m)
+    rows = wmh.upload_dataset(ds, DEV)
+    sig = torch.empty((ds.n_rows, k), dtype=torch.int16, device=DEV)
+    opts = ctx.make_opts(mode="auto")
+    ctx.hash_into(rows, k, 0, sig, opts=opts)  # builds the index
+    tuned = ctx.tune(rows, k, 0, reps=1)
+    say(f"tuned plan {tuned}")
+    ctx.hash_into(rows, k, 0, sig, opts=opts)
+    assert ctx.last_mode() == "indexed"
+    got = wmh.sig_to_numpy(sig)
+    M = float(ds.m.astype(np.float64).sum())
+    rows_of = np.repeat(np.arange(ds.n_rows), np.diff(ds.row_ptr.astype(np.int64)))
+    sx = np.bincount(rows_of, weights=ds.val.astype(np.float64), minlength=ds.n_rows)
+    sm = np.bincount(rows_of, weights=np.where(ds.val > 0, ds.m[ds.col], 0).astype(np.float64),
+                     minlength=ds.n_rows)
+    s = np.maximum(sx, 1) / M
+    t1 = np.ceil(np.log((1 / 16) / k) / np.log1p(-s))
+    t2 = np.ceil(np.log(1e-4 / k) / np.log1p(-s))
+    by_steps = (sx > 0) & (t2 < 65534) & (t2 * sm < 65534.0 * sx)
+    top = got.max(axis=1)
+    second = np.flatnonzero(by_steps & (top > t1))
+    third = np.flatnonzero(by_steps & (top > t2))
+    say(f"{by_steps.sum()} step-order rows; {len(second)} read again to T2, {len(third)} in "
+        f"offset order")
+    idx = sample_rows(ds, 8, 16, extra=np.concatenate([second[:4], third[:4]]))
+    say(f"oracle on {len(idx)} sampled rows")
+    assert_rows_equal(got[idx], oracle_rows(ds, idx, k), idx, "text-like 1e6 rows")
+    del rows, sig
+    torch.cuda.empty_cache()
+
+
 def test_serving_on_the_large_corpus(ctx):
     """Requests drawn from the first 20000 rows of the D = 2^20 serving corpus (k = 256), in
     page-locked buffers as the benchmark sends them, run through the loop with several slots so
