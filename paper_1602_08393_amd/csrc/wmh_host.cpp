@@ -153,7 +153,7 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const w
     while (G > 1 && (uint64_t)(G - 1) * ((k + G - 1) / G) >= k) --G;
     p.hash_groups = G;
     if (G > 1) p.hashes_per_tile = (k + G - 1) / G;
-    if (batched_lds_bytes(ctx->dims, p) > 160 * 1024 - 64) return false;
+    if (batched_lds_bytes(ctx->dims, p) > kMaxDynamicLds) return false;
     p.packed = p.narrow && (uint64_t)ctx->dims * p.scale() <= 65536u;
     // shared stream depth: cover eight mean step counts of the sparsest row, in whole cycles of
     // three windows (the walk's prefetch ring) that stay below the cap

@@ -116,6 +116,10 @@ hipError_t launch_draws(const Bounds &b, uint64_t seed, uint32_t j0, uint32_t n_
 hipError_t launch_stream_build(const Bounds &b, uint64_t seed, uint32_t k, uint32_t depth,
                                bool packed, uint32_t scale, void *entries, hipStream_t stream);
 
+// Dynamic LDS a walk's workgroup may take: the CU's 160 KiB less room for the kernels' static
+// LDS (tile slots and the wavefronts' claim words, under 512 bytes).
+constexpr size_t kMaxDynamicLds = 160 * 1024 - 512;
+
 // Tile counters a batched launch may use (one per hash group), u64 each, cleared before it.
 constexpr uint32_t kMaxHashGroups = 8;
 

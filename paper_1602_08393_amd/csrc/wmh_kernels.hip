@@ -702,7 +702,7 @@ static void configure_rows()
     static bool configured = false;
     if (!configured) {
         hipFuncSetAttribute((const void *)rows_kernel<XT, kPacked>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64);
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynamicLds);
         configured = true;
     }
 }
@@ -734,7 +734,7 @@ hipError_t launch_batched(const Bounds &b, const Rows &rows, uint32_t k, uint64_
                           uint16_t *sig, const BatchedPlan &plan, const void *entries,
                           unsigned long long *tile_counter, uint32_t grid, hipStream_t stream)
 {
-    if (batched_lds_bytes(b.dims, plan) > 160 * 1024 - 64) return hipErrorInvalidValue;
+    if (batched_lds_bytes(b.dims, plan) > kMaxDynamicLds) return hipErrorInvalidValue;
     if (plan.packed && !plan.narrow) return hipErrorInvalidValue;
     // the shared walk reads whole three-window cycles of the stream (plus one spare cycle)
     if (plan.stream_depth % plan.cycle() != 0 || plan.stream_depth >= kCap) return hipErrorInvalidValue;
@@ -760,7 +760,7 @@ hipError_t launch_batched(const Bounds &b, const Rows &rows, uint32_t k, uint64_
 int batched_blocks_per_cu(uint32_t dims, const BatchedPlan &plan)
 {
     const size_t lds = batched_lds_bytes(dims, plan);
-    if (lds > 160 * 1024 - 64) return 0;
+    if (lds > kMaxDynamicLds) return 0;
     if (plan.ballot) {
         if (plan.rows_per_block != 1 || plan.steps_per_lane != 1) return 0;
         return ballot_walk_blocks_per_cu(plan, lds);

@@ -18,6 +18,24 @@ namespace {
 
 __device__ __forceinline__ uint32_t lane() { return threadIdx.x & (kWave - 1u); }
 
+// Claims on a counter shared by a workgroup's wavefronts.  Every lane of the claiming
+// wavefront adds 1 (so no lane-divergent region sits on the loop's path), each to its own
+// word of a 64-word LDS array (one word per bank): the 64 atomics do not queue on one word.
+// Lane 0's word counts the wavefronts' claims; its value before the add, broadcast, is the
+// claim.  Called with every lane active; reset() by threads 0..63 between uses.
+struct WaveClaims {
+    uint32_t word[kWave];
+    __device__ __forceinline__ void reset()
+    {
+        if (threadIdx.x < kWave) word[threadIdx.x] = 0u;
+    }
+    __device__ __forceinline__ uint32_t claim()
+    {
+        const uint32_t before = atomicAdd(&word[threadIdx.x & (kWave - 1u)], 1u);
+        return (uint32_t)__builtin_amdgcn_readfirstlane(before);
+    }
+};
+
 // ---------------------------------------------------------------------------------------------
 // Batched persistent walk.
 //
@@ -170,7 +188,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
     constexpr uint32_t kWin = L * K;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned long long tile_slot;
-    __shared__ uint32_t unit_slot;
+    __shared__ WaveClaims units;
     __shared__ uint32_t nonempty;
     const uint32_t D = b.dims;
     uint16_t *hbuf = reinterpret_cast<uint16_t *>(smem + (((size_t)D * R * sizeof(XT) + 15) & ~(size_t)15));
@@ -194,8 +212,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
     while (true) {
         if (threadIdx.x == 0) {
             tile_slot = next_tile(tile_counter, claimed);
-            unit_slot = 0;
         }
+        units.reset();
         __syncthreads();
         const uint64_t tile = tile_slot;
         if (tile >= n_tiles) break;
@@ -224,12 +242,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
         const uint32_t j1 = min(k, j0 + hashes_per_tile);
 
         while (true) {
-            // claim the next hash id of the tile.  All 64 lanes add 1 (no lane-divergent
-            // region here), so the counter only moves in steps of 64 and every value one
-            // wave instruction returns lies in [64u, 64u + 64): shifting any lane's value by 6
-            // gives the wave's claim u, whatever order the lanes are serviced in.
-            const uint32_t claimed = atomicAdd(&unit_slot, 1u);
-            const uint32_t j = j0 + ((uint32_t)__builtin_amdgcn_readfirstlane(claimed) >> 6);
+            // claim the next hash id of the tile
+            const uint32_t j = j0 + units.claim();
             if (j >= j1) break;
 
             // Each lane keeps the first green step among its own steps (kNoStep: none yet); a
@@ -361,7 +375,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned long long tile_row;
     __shared__ uint32_t tile_ht;
-    __shared__ uint32_t unit_slot;
+    __shared__ WaveClaims units;
     __shared__ uint32_t nonempty;
     const uint32_t D = b.dims;
     uint16_t *hbuf = reinterpret_cast<uint16_t *>(smem + (((size_t)D * sizeof(XT) + 15) & ~(size_t)15));
@@ -398,8 +412,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             }
             tile_row = r;
             tile_ht = h;
-            unit_slot = 0;
         }
+        units.reset();
         __syncthreads();
         const uint64_t row = tile_row;
         if (row == ~0ull) break;
@@ -470,11 +484,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             }
             store(j, lane_walk(j, depth));  // past the stream (rare)
         };
-        // claim u: hash ids 2u and 2u + 1 (every lane adds 1, as in the shared-window walk)
-        auto claim_pair = [&]() {
-            const uint32_t claimed = atomicAdd(&unit_slot, 1u);
-            return j0 + 2u * ((uint32_t)__builtin_amdgcn_readfirstlane(claimed) >> 6);
-        };
+        // claim u: hash ids 2u and 2u + 1
+        auto claim_pair = [&]() { return j0 + 2u * units.claim(); };
         if (!live || depth == 0) {
             // empty rows hash to 0; without a stream every draw is made in-lane
             for (uint32_t ja = claim_pair(); ja < j1; ja = claim_pair())
@@ -501,7 +512,7 @@ void configure_batched()
     static bool configured = false;
     if (!configured) {
         hipFuncSetAttribute((const void *)batched_kernel<XT, R, K, kPacked>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64);
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynamicLds);
         configured = true;
     }
 }
@@ -535,7 +546,7 @@ void configure_ballot()
     static bool configured = false;
     if (!configured) {
         hipFuncSetAttribute((const void *)ballot_kernel<XT, kPacked>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64);
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynamicLds);
         configured = true;
     }
 }
