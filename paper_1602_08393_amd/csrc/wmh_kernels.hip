@@ -696,15 +696,14 @@ size_t batched_lds_bytes(uint32_t dims, const BatchedPlan &plan)
     return aligned + ((size_t)plan.rows_per_block * plan.hashes_per_tile + kWave) * 2;
 }
 
+// Raises the kernel's dynamic LDS limit once per process; its launches return the status.
 template <typename XT, bool kPacked>
-static void configure_rows()
+static hipError_t configure_rows()
 {
-    static bool configured = false;
-    if (!configured) {
+    static const hipError_t status =
         hipFuncSetAttribute((const void *)rows_kernel<XT, kPacked>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynamicLds);
-        configured = true;
-    }
+    return status;
 }
 
 template <typename XT, bool kPacked>
@@ -724,7 +723,8 @@ static hipError_t launch_rows_t(const Bounds &b, const Rows &rows, uint32_t k, u
                                 unsigned long long *tile_counter, uint32_t grid, hipStream_t stream)
 {
     const size_t lds = batched_lds_bytes(b.dims, plan);
-    configure_rows<XT, kPacked>();
+    const hipError_t e = configure_rows<XT, kPacked>();
+    if (e != hipSuccess) return e;
     rows_kernel<XT, kPacked><<<grid, plan.waves_per_block * kWave, lds, stream>>>(
         b, rows, k, seed, sig, plan.hashes_per_tile, plan.stream_depth, entries, tile_counter);
     return hipGetLastError();

@@ -506,15 +506,15 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     }
 }
 
+// Raises the kernel's dynamic LDS limit once per process; the launches return its status, so
+// a limit the runtime refuses fails at the launch that needs it.
 template <typename XT, int R, int K, bool kPacked>
-void configure_batched()
+hipError_t configure_batched()
 {
-    static bool configured = false;
-    if (!configured) {
+    static const hipError_t status =
         hipFuncSetAttribute((const void *)batched_kernel<XT, R, K, kPacked>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynamicLds);
-        configured = true;
-    }
+    return status;
 }
 
 template <typename XT, int R, int K, bool kPacked>
@@ -534,21 +534,20 @@ hipError_t launch_batched_t(const Bounds &b, const Rows &rows, uint32_t k, uint6
                                    unsigned long long *tile_counter, uint32_t grid, hipStream_t stream)
 {
     const size_t lds = batched_lds_bytes(b.dims, plan);
-    configure_batched<XT, R, K, kPacked>();
+    const hipError_t e = configure_batched<XT, R, K, kPacked>();
+    if (e != hipSuccess) return e;
     batched_kernel<XT, R, K, kPacked><<<grid, plan.waves_per_block * kWave, lds, stream>>>(
         b, rows, k, seed, sig, plan.hashes_per_tile, plan.stream_depth, entries, tile_counter);
     return hipGetLastError();
 }
 
 template <typename XT, bool kPacked>
-void configure_ballot()
+hipError_t configure_ballot()
 {
-    static bool configured = false;
-    if (!configured) {
+    static const hipError_t status =
         hipFuncSetAttribute((const void *)ballot_kernel<XT, kPacked>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynamicLds);
-        configured = true;
-    }
+    return status;
 }
 
 template <typename XT, bool kPacked>
@@ -568,7 +567,8 @@ hipError_t launch_ballot_t(const Bounds &b, const Rows &rows, uint32_t k, uint64
                            unsigned long long *tile_counter, uint32_t grid, hipStream_t stream)
 {
     const size_t lds = batched_lds_bytes(b.dims, plan);
-    configure_ballot<XT, kPacked>();
+    const hipError_t e = configure_ballot<XT, kPacked>();
+    if (e != hipSuccess) return e;
     ballot_kernel<XT, kPacked><<<grid, plan.waves_per_block * kWave, lds, stream>>>(
         b, rows, k, seed, sig, plan.hashes_per_tile, plan.stream_depth, entries, tile_counter,
         plan.hash_groups);
