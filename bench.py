@@ -113,6 +113,8 @@ def parse():
     ap.add_argument("--steps-per-lane", type=int, default=0)
     ap.add_argument("--hash-groups", type=int, default=0,
                     help="ballot walk: hash ids in this many groups (0: planner or autotuner)")
+    ap.add_argument("--values", type=int, default=0, choices=[0, 1, 2],
+                    help="dense rows in LDS: 0 planner/autotuner, 1 the values, 2 coarse codes")
     ap.add_argument("--walk", type=int, default=0, choices=[0, 1, 2, 3],
                     help="batched walk: 0 planner/autotuner, 1 shared windows, 2 independent "
                          "rows, 3 ballot walk (one row per block)")
@@ -259,7 +261,7 @@ def plan_args(args) -> dict:
     return dict(rows_per_block=args.rows_per_block, hashes_per_tile=args.hashes_per_tile,
                 stream_depth=args.stream_depth, waves_per_block=args.waves_per_block,
                 walk=args.walk, steps_per_lane=args.steps_per_lane,
-                hash_groups=args.hash_groups)
+                hash_groups=args.hash_groups, values=args.values)
 
 
 def timed_steps(ctx, rows, k, sig, opts, steps, warmup, torch):
@@ -345,6 +347,21 @@ def heavy_tail_bench(args, torch, synth, wmh) -> dict:
                         and out["batched_plan"]["hashes_per_tile"] == 500
                         and out["batched_plan"]["hash_groups"] == 1 and ds.n_rows == 200_000)
                     else None)})
+    bp = out["batched_plan"]
+    if bp.get("values") == "coarse":
+        # the same plan with the exact 32-bit values in LDS (and 8-byte stream entries)
+        exact = {name: bp[name] for name in ("rows_per_block", "steps_per_lane", "waves_per_block",
+                                             "hashes_per_tile", "walk", "hash_groups")}
+        el_x, walk_x, _ = timed_steps(ctx, rows, k, sig_p,
+                                      ctx.make_opts(mode="batched", profile=True, values="exact",
+                                                    **exact), 3, 1, torch)
+        out["exact_values"] = {"plan": ctx.last_plan(), "ms_per_step": el_x / 3 * 1e3,
+                               "walk_ms": float(np.mean(walk_x)),
+                               "coarse_walk_speedup": float(np.mean(walk_x) / np.mean(walk_b)),
+                               "equals_coarse": bool(torch.equal(sig_p, sig_b))}
+        log(f"heavy-tail: exact 32-bit rows {out['exact_values']['walk_ms']:.2f} ms walk against "
+            f"{out['batched_walk_ms']:.2f} ms with coarse codes, equal "
+            f"{out['exact_values']['equals_coarse']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = oracle_on_head(ds, 4096, k, wmh.sig_to_numpy(sig_b[:4096]))
         log(f"heavy-tail: oracle {out['cpu_baseline']['value']:.3g} hashes/s on 4096 rows, "

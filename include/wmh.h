@@ -140,6 +140,21 @@ typedef struct {
                                   (dispatched in turn) mostly read one block's part of the
                                   shared stream from their L2.  Each row is staged once per
                                   block.  1 = one counter over all tiles */
+    int32_t values;            /* shared-window and ballot walks, the dense rows in LDS:
+                                  0 = planner / autotuner choice (coarse codes when some bound
+                                  is 65536 or more and a plan with them fits, else the values);
+                                  1 = the values (uint16 when every bound is below 65536, else
+                                  uint32); 2 = 16-bit coarse codes.  A code of a value and of a
+                                  step's offset, both relative to the piece's bound m and
+                                  ordered like the numbers (floor(y * 2^15 / m), with one bit
+                                  telling the value's code whether the value is the first of
+                                  its code), decides the step unless the two codes tie; a tie
+                                  (probability below 2^-15 per tested step in the row's
+                                  support; none when m <= 2^15) is settled from the row's
+                                  exact value and the step's exact offset, so the hashes are
+                                  identical.  Half the LDS of 32-bit rows and 4-byte stream
+                                  entries; needs D * scale <= 65536 (D <= 32768 at R = 1,
+                                  D <= 16384 at R = 2 or 4) and not the independent-rows walk */
 } wmh_opts;
 
 /* Fills *opts with the defaults listed above. */
@@ -442,7 +457,9 @@ typedef struct {
     uint32_t index_batch;      /* walk 4: keys per round trip of the fastest plan */
     uint32_t index_claim;      /* walk 4: 1 counter, 2 fixed stride */
     uint32_t hash_groups;      /* ballot walk: hash groups of the fastest plan (1 otherwise) */
-    uint32_t reserved[3];
+    int32_t values;            /* wmh_opts.values of the fastest plan: 1 values, 2 coarse
+                                  codes (0 for the index rows kernel) */
+    uint32_t reserved[2];
 } wmh_tune_result;
 
 /*
@@ -467,10 +484,10 @@ wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
                     const uint32_t *val, uint64_t n_rows, uint64_t nnz, uint32_t k, uint64_t seed,
                     uint16_t *sig, void *stream, uint32_t reps, wmh_tune_result *out);
 
-/* Writes the context's tuned plans to a text file: a "wmh-tune 5" line, then one line per key
- * "D narrow k steps_class R J W walk K G ms" (G: hash groups of the ballot walk); for a plan
- * of the index rows kernel walk is 4, R the keys per trip, J the claim (1 counter, 2 stride),
- * K 0 and G 1.  Errors: WMH_E_ARG. */
+/* Writes the context's tuned plans to a text file: a "wmh-tune 6" line, then one line per key
+ * "D narrow k steps_class R J W walk K G V ms" (G: hash groups of the ballot walk, V: values
+ * as in wmh_opts); for a plan of the index rows kernel walk is 4, R the keys per trip, J the
+ * claim (1 counter, 2 stride), K 0, G 1 and V 0.  Errors: WMH_E_ARG. */
 wmh_status wmh_tune_save(wmh_ctx *ctx, const char *path);
 
 /* Adds the plans of a file written by wmh_tune_save (replacing equal keys); nothing is added

@@ -22,10 +22,11 @@ struct StreamKey {
     uint32_t k = 0, depth = 0, scale = 0;
     bool packed = false;
     uint64_t bounds_epoch = 0;
+    bool coarse = false;  // offsets replaced by their coarse codes
     bool operator==(const StreamKey &o) const
     {
         return seed == o.seed && k == o.k && depth == o.depth && scale == o.scale &&
-               packed == o.packed && bounds_epoch == o.bounds_epoch;
+               packed == o.packed && bounds_epoch == o.bounds_epoch && coarse == o.coarse;
     }
 };
 
@@ -35,6 +36,7 @@ struct GraphKey {
     uint64_t n_rows = 0, nnz = 0, seed = 0;
     uint32_t k = 0, R = 0, K = 0, J = 0, depth = 0, waves = 0, grid = 0, groups = 0;
     bool narrow = false, packed = false, independent_rows = false, ballot = false;
+    bool coarse = false;
     const void *row_class = nullptr;  // row filter of a split walk (nullptr: every row)
     uint32_t keep = 0;
     uint64_t bounds_epoch = 0;
@@ -53,7 +55,7 @@ struct GraphKey {
                K == o.K &&
                J == o.J && depth == o.depth && waves == o.waves && grid == o.grid &&
                groups == o.groups &&
-               narrow == o.narrow && packed == o.packed &&
+               narrow == o.narrow && packed == o.packed && coarse == o.coarse &&
                independent_rows == o.independent_rows && ballot == o.ballot &&
                bounds_epoch == o.bounds_epoch;
     }
@@ -104,6 +106,7 @@ struct TuneKey {
 struct TuneEntry {
     TuneKey key;
     uint32_t R = 0, J = 0, W = 0, K = 0, G = 1;  // G: hash groups of the ballot walk
+    int32_t V = 1;  // wmh_opts.values: 1 exact dense rows, 2 coarse codes
     int32_t walk = 1;  // wmh_opts.walk: 1 shared windows, 2 independent rows, 3 ballot walk
     float ms = 0.f;
 };

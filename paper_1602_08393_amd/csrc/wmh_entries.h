@@ -2,11 +2,14 @@
 // the shared position stream.  Entry j * depth + t - 1 holds step t of hash j: wide entries
 // are (component c, offset) pairs of 32-bit words; packed entries are one word,
 // (offset << 16) | (c * scale), where c * scale is the LDS byte offset of component c's group
-// of dense-row values (scale = RowLayout::kGroup).  gfx950 only.
+// of dense-row values (scale = RowLayout::kGroup); coarse entries replace the offset by its
+// 16-bit code (see below) for rows held as 16-bit value codes.  gfx950 only.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "wmh_device.h"
 
 namespace wmh {
 
@@ -30,6 +33,69 @@ struct RowLayout {
         return reinterpret_cast<XT *>(base + (size_t)c * kGroup + row_byte(r, dims));
     }
 };
+
+// Coarse 16-bit codes for pieces whose bounds do not fit 16 bits.  In a piece of size m >= 1,
+// q(y) = floor(y * 2^15 / m) is nondecreasing on 0 <= y <= m, so for an offset o < m and a value
+// x <= m: q(o) < q(x) gives o < x (green) and q(o) > q(x) gives o > x (red).  When q(o) = q(x),
+// o < x is possible only if x is not the smallest y with that code, i.e. when q(x - 1) = q(x),
+// i.e. when the remainder x * 2^15 - q(x) * m is at least 2^15.  A stream entry carries the odd
+// code v = 2 q(o) + 1 and the dense row the value code
+//   z = 0 (x = 0), 0xFFFF (x >= m), else 2 q(x) + [x * 2^15 - q(x) * m >= 2^15],
+// so that v < z means green, v > z red, and v = z a tie, settled from the row's exact value and
+// the step's exact offset (the walks evaluate a window with a tie again with in-lane draws).  For m <= 2^15 the map q is one-to-one and no tie occurs; above, a
+// tested step in the row's support ties with probability below 2^-15.
+constexpr uint32_t kCoarseBits = 15u;
+
+// floor(y * 2^15 / m) and its remainder, for y <= m, 1 <= m: a float estimate (within one of
+// the quotient) made exact by the remainder.
+__device__ __forceinline__ uint32_t coarse_q(uint32_t y, uint32_t m, uint32_t *rem)
+{
+    const float est = (float)y * (32768.0f * __builtin_amdgcn_rcpf((float)m));
+    uint32_t q = (uint32_t)est;
+    int64_t r = (int64_t)((uint64_t)y << kCoarseBits) - (int64_t)q * (int64_t)m;
+    while (r < 0) {
+        --q;
+        r += m;
+    }
+    while (r >= (int64_t)m) {
+        ++q;
+        r -= m;
+    }
+    *rem = (uint32_t)r;
+    return q;
+}
+
+// The code of an offset o < m of a step (odd, at most 0xFFFF).
+__device__ __forceinline__ uint32_t coarse_offset_code(uint32_t o, uint32_t m)
+{
+    uint32_t rem;
+    return 2u * coarse_q(o, m, &rem) + 1u;
+}
+
+// The code of a row's value x in a piece of size m.
+__device__ __forceinline__ uint32_t coarse_value_code(uint32_t x, uint32_t m)
+{
+    if (x == 0) return 0u;
+    if (x >= m) return 0xFFFFu;
+    uint32_t rem;
+    const uint32_t q = coarse_q(x, m, &rem);
+    return 2u * q + (rem >= (1u << kCoarseBits) ? 1u : 0u);
+}
+
+// The exact value of component c in CSR row `row` (columns strictly increasing), 0 if absent.
+__device__ __forceinline__ uint32_t csr_value(const uint64_t *row_ptr, const uint32_t *col,
+                                              const uint32_t *val, uint64_t row, uint32_t c)
+{
+    uint64_t lo = row_ptr[row];
+    const uint64_t end = row_ptr[row + 1];
+    uint64_t hi = end;
+    while (lo < hi) {
+        const uint64_t mid = lo + ((hi - lo) >> 1);
+        if (col[mid] < c) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < end && col[lo] == c ? val[lo] : 0u;
+}
 
 // The next tile of a workgroup (called by one thread, `claimed` starting false): from the
 // counter of a persistent launch, or, with no counter, the workgroup's own tile (blockIdx.x) the

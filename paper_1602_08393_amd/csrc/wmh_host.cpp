@@ -92,6 +92,9 @@ TuneKey tune_key(const wmh_ctx *ctx, uint32_t k, const RowStats &stats)
     return key;
 }
 
+static bool plan_rows(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const wmh_opts &o,
+                      bool coarse, BatchedPlan *plan);
+
 bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const wmh_opts &o_in,
                   BatchedPlan *plan, bool use_tuned)
 {
@@ -118,11 +121,27 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const w
             o.walk = pick->walk;
             o.steps_per_lane = pick->K;
             o.hash_groups = pick->G;
+            if (!o.values) o.values = pick->V;
         }
     }
+    if (o.values < 0 || o.values > 2) return false;
+    // Dense rows as coarse codes: when asked for, or by default when some bound does not fit
+    // 16 bits (half the LDS and stream bytes of exact 32-bit rows), if the plan takes them.
+    if (o.values == 2) return plan_rows(ctx, k, stats, o, true, plan);
+    if (o.values == 0 && ctx->max_bound > 0xFFFFu && o.walk != 2 &&
+        plan_rows(ctx, k, stats, o, true, plan))
+        return true;
+    return plan_rows(ctx, k, stats, o, false, plan);
+}
+
+// The plan of plan_batched with exact or coarse dense rows.
+static bool plan_rows(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const wmh_opts &o,
+                      bool coarse, BatchedPlan *plan)
+{
     const uint64_t min_green = stats.known ? stats.min_green : ~0ull;
     BatchedPlan p{};
-    p.narrow = ctx->max_bound <= 0xFFFFu;
+    p.coarse = coarse;
+    p.narrow = coarse || ctx->max_bound <= 0xFFFFu;
     p.waves_per_block = o.waves_per_block ? std::min<uint32_t>(o.waves_per_block, 16u) : 8u;
     p.hashes_per_tile = o.hashes_per_tile ? std::min(o.hashes_per_tile, k) : std::min(k, 1024u);
     const size_t elem = p.narrow ? 2 : 4;
@@ -155,6 +174,7 @@ bool plan_batched(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, const w
     if (G > 1) p.hashes_per_tile = (k + G - 1) / G;
     if (batched_lds_bytes(ctx->dims, p) > kMaxDynamicLds) return false;
     p.packed = p.narrow && (uint64_t)ctx->dims * p.scale() <= 65536u;
+    if (coarse && (!p.packed || p.independent_rows || R > 4)) return false;
     // shared stream depth: cover eight mean step counts of the sparsest row, in whole cycles of
     // three windows (the walk's prefetch ring) that stay below the cap
     const uint32_t cycle = p.cycle();  // 3 x (64, 128 or 256) steps
@@ -771,6 +791,7 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         key.K = pl.steps_per_lane;
         key.waves = pl.waves_per_block; key.grid = grid; key.narrow = pl.narrow;
         key.packed = pl.packed;
+        key.coarse = pl.coarse;
         key.independent_rows = pl.independent_rows;
         key.ballot = pl.ballot;
         key.groups = pl.hash_groups;
@@ -783,12 +804,12 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         bool stream_built = false;
         if (pl.stream_depth) {
             const StreamKey skey{seed, k, pl.stream_depth, pl.scale(), pl.packed,
-                                 ctx->bounds_epoch};
+                                 ctx->bounds_epoch, pl.coarse};
             if (!(ctx->stream_valid && ctx->stream_key == skey)) {
                 ctx->stream_valid = false;
                 if (profile && !o.use_graph) WMH_HIP(ctx, hipEventRecord(ctx->ev[0], s));
                 WMH_HIP(ctx, launch_stream_build(b, seed, k, pl.stream_depth, pl.packed,
-                                                 pl.scale(), ctx->d_stream, s));
+                                                 pl.scale(), pl.coarse, ctx->d_stream, s));
                 WMH_HIP(ctx, hipEventRecord(ctx->stream_ready, s));
                 ctx->stream_key = skey;
                 ctx->stream_valid = true;
@@ -920,10 +941,12 @@ wmh_status wmh_last_plan(const wmh_ctx *ctx, wmh_opts *plan)
     plan->steps_per_lane = ctx->last_plan.steps_per_lane;
     plan->waves_per_block = ctx->last_plan.waves_per_block;
     plan->hash_groups = ctx->last_plan.hash_groups;
+    plan->values = ctx->last_plan.rows_per_block ? (ctx->last_plan.coarse ? 2 : 1) : 0;
     if (ctx->last_mode == WMH_MODE_INDEXED) {
         plan->rows_per_block = plan->hashes_per_tile = plan->stream_depth = 0;
         plan->steps_per_lane = 0;
         plan->hash_groups = 0;
+        plan->values = 0;
         plan->waves_per_block = ctx->last_index_plan.waves;
         plan->index_batch = ctx->last_index_plan.batch;
         plan->index_claim = ctx->last_index_plan.claim;

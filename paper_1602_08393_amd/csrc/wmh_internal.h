@@ -62,7 +62,8 @@ struct Rows {
 // One shared-stream entry: the component c and the offset inside it of one step's position.
 // Wide entries are (c, offset) as two uint32; packed entries are (offset << 16) | (c * scale)
 // with scale = R * sizeof(dense value), the LDS byte offset of component c's group of R dense
-// values; used when every bound is below 65536 and D * scale <= 65536.
+// values; used when every bound is below 65536 and D * scale <= 65536.  Coarse entries hold the
+// offset's 16-bit coarse code in place of the offset (rows held as coarse value codes).
 struct StreamEntry {
     uint32_t comp;
     uint32_t offset;
@@ -75,8 +76,11 @@ struct BatchedPlan {
     uint32_t stream_depth;     // T0: 0 (every draw in-lane) or whole cycles of three windows
                                // (a window is 64 / R * K steps), below the cap
     uint32_t waves_per_block;
-    bool narrow;               // dense rows stored as uint16 (every bound < 65536)
+    bool narrow;               // dense rows stored as uint16: the values (every bound < 65536)
+                               // or, with coarse, their coarse codes
     bool packed;               // 4-byte stream entries
+    bool coarse = false;       // rows hold coarse value codes, the stream coarse offset codes,
+                               // and ties are settled exactly (shared-window and ballot walks)
     bool independent_rows;     // each row of a block walks its own hash ids (R = 4 only)
     bool ballot;               // one row per block, first green step from the window's ballot
                                // (R = 1, K = 1 only)
@@ -113,8 +117,10 @@ hipError_t launch_draws(const Bounds &b, uint64_t seed, uint32_t j0, uint32_t n_
                         uint32_t depth, uint64_t *pos, uint32_t *comp, uint64_t *off,
                         hipStream_t stream);
 
+// coarse: entries carry the offset's coarse code (needs packed)
 hipError_t launch_stream_build(const Bounds &b, uint64_t seed, uint32_t k, uint32_t depth,
-                               bool packed, uint32_t scale, void *entries, hipStream_t stream);
+                               bool packed, uint32_t scale, bool coarse, void *entries,
+                               hipStream_t stream);
 
 // Dynamic LDS a walk's workgroup may take: the CU's 160 KiB less room for the kernels' static
 // LDS (tile slots and the wavefronts' claim words, under 512 bytes).

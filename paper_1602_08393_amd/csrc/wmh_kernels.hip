@@ -336,14 +336,16 @@ __global__ __launch_bounds__(256) void plain_kernel(Bounds b, Rows rows, uint64_
 // ---------------------------------------------------------------------------------------------
 // Shared position stream: entry j * depth + t - 1 holds step t of hash j, for t <= depth:
 // wide entries (component c, offset); packed entries (offset << 16) | (c * scale), where
-// c * scale is the LDS byte offset of component c's group of dense-row values.  One thread per
+// c * scale is the LDS byte offset of component c's group of dense-row values; coarse entries
+// (code << 16) | (c * scale) with the offset's coarse code (odd, see coarse_q).  One thread per
 // Philox block (two steps).
 // ---------------------------------------------------------------------------------------------
-template <bool kPacked>
+template <bool kPacked, bool kCoarse>
 __global__ __launch_bounds__(256) void stream_kernel(Bounds b, uint64_t seed, uint32_t k,
                                                      uint32_t depth, uint32_t scale,
                                                      void *__restrict__ entries)
 {
+    static_assert(kPacked || !kCoarse, "coarse codes come in packed entries");
     const uint64_t pairs = depth >> 1;
     const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= pairs * k) return;
@@ -355,9 +357,14 @@ __global__ __launch_bounds__(256) void stream_kernel(Bounds b, uint64_t seed, ui
     const uint32_t c1 = component_of(p1, b.prefix, b.bucket, b.shift, &off1);
     const uint64_t at = (uint64_t)j * depth + 2ull * pair;
     if (kPacked) {
+        uint32_t v0 = (uint32_t)off0, v1 = (uint32_t)off1;
+        if (kCoarse) {
+            v0 = coarse_offset_code(v0, b.bound[c0]);
+            v1 = coarse_offset_code(v1, b.bound[c1]);
+        }
         uint32_t *e = reinterpret_cast<uint32_t *>(entries) + at;
-        *reinterpret_cast<uint2 *>(e) = make_uint2(((uint32_t)off0 << 16) | (c0 * scale),
-                                                   ((uint32_t)off1 << 16) | (c1 * scale));
+        *reinterpret_cast<uint2 *>(e) = make_uint2((v0 << 16) | (c0 * scale),
+                                                   (v1 << 16) | (c1 * scale));
     } else {
         StreamEntry *e = reinterpret_cast<StreamEntry *>(entries) + at;
         e[0] = StreamEntry{c0, (uint32_t)off0};
@@ -678,13 +685,16 @@ hipError_t launch_draws(const Bounds &b, uint64_t seed, uint32_t j0, uint32_t n_
 }
 
 hipError_t launch_stream_build(const Bounds &b, uint64_t seed, uint32_t k, uint32_t depth,
-                               bool packed, uint32_t scale, void *entries, hipStream_t stream)
+                               bool packed, uint32_t scale, bool coarse, void *entries,
+                               hipStream_t stream)
 {
     if (depth == 0 || k == 0) return hipSuccess;
+    if (coarse && !packed) return hipErrorInvalidValue;
     const uint64_t threads = (uint64_t)k * (depth / 2);
     const uint32_t grid = (uint32_t)((threads + 255) / 256);
-    if (packed) stream_kernel<true><<<grid, 256, 0, stream>>>(b, seed, k, depth, scale, entries);
-    else stream_kernel<false><<<grid, 256, 0, stream>>>(b, seed, k, depth, scale, entries);
+    if (coarse) stream_kernel<true, true><<<grid, 256, 0, stream>>>(b, seed, k, depth, scale, entries);
+    else if (packed) stream_kernel<true, false><<<grid, 256, 0, stream>>>(b, seed, k, depth, scale, entries);
+    else stream_kernel<false, false><<<grid, 256, 0, stream>>>(b, seed, k, depth, scale, entries);
     return hipGetLastError();
 }
 
@@ -736,6 +746,9 @@ hipError_t launch_batched(const Bounds &b, const Rows &rows, uint32_t k, uint64_
 {
     if (batched_lds_bytes(b.dims, plan) > kMaxDynamicLds) return hipErrorInvalidValue;
     if (plan.packed && !plan.narrow) return hipErrorInvalidValue;
+    // coarse codes: 16-bit rows, packed entries, the shared-window or ballot walk
+    if (plan.coarse && (!plan.narrow || !plan.packed || plan.independent_rows))
+        return hipErrorInvalidValue;
     // the shared walk reads whole three-window cycles of the stream (plus one spare cycle)
     if (plan.stream_depth % plan.cycle() != 0 || plan.stream_depth >= kCap) return hipErrorInvalidValue;
     if (plan.hash_groups > 1 && (!plan.ballot || plan.hash_groups > kMaxHashGroups ||
@@ -766,7 +779,7 @@ int batched_blocks_per_cu(uint32_t dims, const BatchedPlan &plan)
         return ballot_walk_blocks_per_cu(plan, lds);
     }
     if (plan.independent_rows) {
-        if (plan.rows_per_block != 4) return 0;
+        if (plan.rows_per_block != 4 || plan.coarse) return 0;
         if (plan.narrow) return plan.packed ? rows_occupancy_t<uint16_t, true>(plan, lds)
                                             : rows_occupancy_t<uint16_t, false>(plan, lds);
         return rows_occupancy_t<uint32_t, false>(plan, lds);

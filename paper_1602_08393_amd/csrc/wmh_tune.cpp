@@ -22,7 +22,7 @@ using namespace wmh;
 
 namespace {
 
-constexpr char kTuneHeader[] = "wmh-tune 5";
+constexpr char kTuneHeader[] = "wmh-tune 6";
 constexpr int32_t kIndexWalk = 4;  // a tuning line of the index rows kernel
 
 void put_entry(wmh_ctx *ctx, const TuneEntry &e)
@@ -51,12 +51,13 @@ bool valid_index_plan(uint32_t batch, uint32_t claim, uint32_t W)
            W <= kIndexMaxWaves;
 }
 
-bool valid_plan(uint32_t R, uint32_t J, uint32_t W, int32_t walk, uint32_t K, uint32_t G)
+bool valid_plan(uint32_t R, uint32_t J, uint32_t W, int32_t walk, uint32_t K, uint32_t G,
+                int32_t V)
 {
     return (R == 1 || R == 2 || R == 4 || R == 8 || R == 16) && J >= 1 && W >= 1 && W <= 16 &&
            (walk == 1 || (walk == 2 && R == 4) || (walk == 3 && R == 1 && K == 1)) &&
            (K == R || (K == 4 && R < 4)) && G >= 1 && G <= kMaxHashGroups &&
-           (G == 1 || walk == 3);
+           (G == 1 || walk == 3) && (V == 1 || (V == 2 && walk != 2 && R <= 4));
 }
 
 }  // namespace
@@ -165,10 +166,11 @@ wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
     }
     // best of `reps` timed calls after one untimed call; <0 when the plan does not fit
     auto time_plan = [&](uint32_t R, uint32_t J, uint32_t W, int32_t walk, uint32_t K,
-                         uint32_t G, float *ms) -> wmh_status {
+                         uint32_t G, int32_t V, float *ms) -> wmh_status {
         wmh_opts o = base;
         o.walk = walk;
         o.hash_groups = G;
+        o.values = V;
         o.steps_per_lane = K;
         o.mode = WMH_MODE_BATCHED;
         o.validate = 0;
@@ -185,8 +187,9 @@ wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
 
     wmh_tune_result res{};
     float default_ms = 0.f;
+    const int32_t def_values = def.coarse ? 2 : 1;
     st = time_plan(def.rows_per_block, def.hashes_per_tile, def.waves_per_block, 1,
-                   def.steps_per_lane, 1, &default_ms);
+                   def.steps_per_lane, 1, def_values, &default_ms);
     TuneEntry best;
     best.key = tune_key(ctx, k, stats);
     best.R = def.rows_per_block;
@@ -194,6 +197,7 @@ wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
     best.W = def.waves_per_block;
     best.walk = 1;
     best.K = def.steps_per_lane;
+    best.V = def_values;
     best.ms = default_ms;
     uint32_t tried = 1;
     std::vector<uint32_t> Js{std::min(k, 1024u), std::min(k, 512u), std::min(k, 256u)};
@@ -210,27 +214,35 @@ wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
     std::vector<uint32_t> groups_of_ballot{1u};
     for (uint32_t G : {2u, 4u, 8u})
         if ((uint64_t)(G - 1) * ((k + G - 1) / G) < k) groups_of_ballot.push_back(G);
+    // rows with a bound of 65536 or more: every plan with exact 32-bit rows and with coarse
+    // codes (the latter without hash groups)
+    std::vector<int32_t> values{1};
+    if (ctx->max_bound > 0xFFFFu) values.push_back(2);
     for (const Shape &sh : shapes) {
-        for (uint32_t G : sh.walk == 3 ? groups_of_ballot : std::vector<uint32_t>{1u}) {
-            for (uint32_t W : {4u, 8u, 16u}) {
-                for (uint32_t J : G == 1 ? Js : std::vector<uint32_t>{(k + G - 1) / G}) {
-                    if (st != WMH_OK) break;
-                    if (sh.walk == 1 && sh.R == def.rows_per_block &&
-                        sh.K == def.steps_per_lane && J == def.hashes_per_tile &&
-                        W == def.waves_per_block)
-                        continue;
-                    float ms = -1.f;
-                    st = time_plan(sh.R, J, W, sh.walk, sh.K, G, &ms);
-                    if (st == WMH_OK && ms >= 0.f) {
-                        ++tried;
-                        if (ms < best.ms) {
-                            best.R = sh.R;
-                            best.J = J;
-                            best.W = W;
-                            best.walk = sh.walk;
-                            best.K = sh.K;
-                            best.G = G;
-                            best.ms = ms;
+        for (int32_t V : values) {
+            if (V == 2 && (sh.walk == 2 || sh.R > 4)) continue;
+            for (uint32_t G : sh.walk == 3 && V == 1 ? groups_of_ballot : std::vector<uint32_t>{1u}) {
+                for (uint32_t W : {4u, 8u, 16u}) {
+                    for (uint32_t J : G == 1 ? Js : std::vector<uint32_t>{(k + G - 1) / G}) {
+                        if (st != WMH_OK) break;
+                        if (sh.walk == 1 && sh.R == def.rows_per_block &&
+                            sh.K == def.steps_per_lane && J == def.hashes_per_tile &&
+                            W == def.waves_per_block && V == def_values)
+                            continue;
+                        float ms = -1.f;
+                        st = time_plan(sh.R, J, W, sh.walk, sh.K, G, V, &ms);
+                        if (st == WMH_OK && ms >= 0.f) {
+                            ++tried;
+                            if (ms < best.ms) {
+                                best.R = sh.R;
+                                best.J = J;
+                                best.W = W;
+                                best.walk = sh.walk;
+                                best.K = sh.K;
+                                best.G = G;
+                                best.V = V;
+                                best.ms = ms;
+                            }
                         }
                     }
                 }
@@ -252,6 +264,7 @@ wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
     res.walk = best.walk;
     res.steps_per_lane = best.K;
     res.hash_groups = best.G;
+    res.values = best.V;
     *out = res;
     return WMH_OK;
 }
@@ -263,13 +276,14 @@ wmh_status wmh_tune_save(wmh_ctx *ctx, const char *path)
     if (!f) return fail(ctx, WMH_E_ARG, "cannot write %s", path);
     std::fprintf(f, "%s\n", kTuneHeader);
     for (const TuneEntry &e : ctx->tuned)
-        std::fprintf(f, "%u %d %u %d %u %u %u %d %u %u %.6f\n", e.key.dims, e.key.narrow ? 1 : 0,
-                     e.key.k, e.key.steps_class, e.R, e.J, e.W, e.walk, e.K, e.G, (double)e.ms);
+        std::fprintf(f, "%u %d %u %d %u %u %u %d %u %u %d %.6f\n", e.key.dims,
+                     e.key.narrow ? 1 : 0, e.key.k, e.key.steps_class, e.R, e.J, e.W, e.walk, e.K,
+                     e.G, e.V, (double)e.ms);
     // index rows plans: keys per trip and claim in the R and J columns, walk 4
     for (const IndexTuneEntry &e : ctx->tuned_index)
-        std::fprintf(f, "%u %d %u %d %u %u %u %d %u %u %.6f\n", e.key.dims,
+        std::fprintf(f, "%u %d %u %d %u %u %u %d %u %u %d %.6f\n", e.key.dims,
                      e.key.narrow ? 1 : 0, e.key.k, e.key.steps_class, e.plan.batch, e.plan.claim,
-                     e.plan.waves, kIndexWalk, 0u, 1u, (double)e.ms);
+                     e.plan.waves, kIndexWalk, 0u, 1u, 0, (double)e.ms);
     const bool ok = std::fclose(f) == 0;
     return ok ? WMH_OK : fail(ctx, WMH_E_ARG, "cannot write %s", path);
 }
@@ -288,9 +302,9 @@ wmh_status wmh_tune_load(wmh_ctx *ctx, const char *path)
         TuneEntry e;
         int narrow = 0;
         double ms = 0;
-        if (std::sscanf(line, "%u %d %u %d %u %u %u %d %u %u %lf", &e.key.dims, &narrow,
+        if (std::sscanf(line, "%u %d %u %d %u %u %u %d %u %u %d %lf", &e.key.dims, &narrow,
                         &e.key.k, &e.key.steps_class, &e.R, &e.J, &e.W, &e.walk, &e.K, &e.G,
-                        &ms) != 11 ||
+                        &e.V, &ms) != 12 ||
             (narrow != 0 && narrow != 1) || e.key.k == 0) {
             ok = false;
             break;
@@ -311,7 +325,7 @@ wmh_status wmh_tune_load(wmh_ctx *ctx, const char *path)
             got_index.push_back(x);
             continue;
         }
-        if (!valid_plan(e.R, e.J, e.W, e.walk, e.K, e.G)) {
+        if (!valid_plan(e.R, e.J, e.W, e.walk, e.K, e.G, e.V)) {
             ok = false;
             break;
         }

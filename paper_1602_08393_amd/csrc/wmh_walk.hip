@@ -84,13 +84,38 @@ __host__ __device__ constexpr uint64_t segment_tops()
     return m;
 }
 
-// Zeroes the LDS rows of a block, then scatters its n_here CSR rows (RowLayout) and sets bit r
-// of *nonempty for every row r with a nonzero value; rows with bit r of `skip` stay zero.
-// Called by the whole workgroup.
-template <typename XT, int R>
+// The LDS value of a row's nonzero x at component c: x itself, or its coarse code.
+template <typename XT, bool kCoarse>
+__device__ __forceinline__ XT lds_value(uint32_t x, uint32_t c, const uint32_t *bound)
+{
+    if constexpr (kCoarse) return (XT)coarse_value_code(x, bound[c]);
+    else return (XT)x;
+}
+
+// Green test of a step drawn in-lane (exact offset o at component c) against the LDS value
+// lv of CSR row `row`: o < x, with x itself in LDS, or from the coarse codes (a tie reads the
+// row's exact value).
+template <bool kCoarse>
+__device__ __forceinline__ bool lane_green(uint64_t o, uint32_t lv, uint32_t c, const Bounds &b,
+                                           const Rows &rows, uint64_t row)
+{
+    if constexpr (kCoarse) {
+        if (lv == 0) return false;
+        const uint32_t v = coarse_offset_code((uint32_t)o, b.bound[c]);
+        if (v != lv) return v < lv;
+        return o < (uint64_t)csr_value(rows.row_ptr, rows.col, rows.val, row, c);
+    } else {
+        return o < (uint64_t)lv;
+    }
+}
+
+// Zeroes the LDS rows of a block, then scatters its n_here CSR rows (RowLayout; coarse codes
+// with kCoarse) and sets bit r of *nonempty for every row r with a nonzero value; rows with bit
+// r of `skip` stay zero.  Called by the whole workgroup.
+template <typename XT, int R, bool kCoarse>
 __device__ __forceinline__ void stage_block(unsigned char *smem, const Rows &rows, uint64_t row0,
-                                            uint32_t n_here, uint32_t D, uint32_t *nonempty,
-                                            uint32_t skip = 0)
+                                            uint32_t n_here, uint32_t D, const uint32_t *bound,
+                                            uint32_t *nonempty, uint32_t skip = 0)
 {
     using Layout = RowLayout<XT, R>;
     uint32_t *xz = reinterpret_cast<uint32_t *>(smem);
@@ -105,7 +130,7 @@ __device__ __forceinline__ void stage_block(unsigned char *smem, const Rows &row
         for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
             const uint32_t v = rows.val[e];
             const uint32_t c = rows.col[e];
-            if (c < D) *Layout::at(smem, c, r, D) = (XT)v;
+            if (c < D) *Layout::at(smem, c, r, D) = lds_value<XT, kCoarse>(v, c, bound);
             if (v) mine |= 1u << r;
         }
     }
@@ -115,13 +140,15 @@ __device__ __forceinline__ void stage_block(unsigned char *smem, const Rows &row
 
 // Replaces the one dense row held in LDS (x[0..D)) by CSR row `row`: the previous row's columns
 // (CSR entries [prev_lo, prev_hi)) are set back to zero, or, while LDS holds no row yet
-// (have_row false), the whole row is zero-filled; then the new row's values are scattered and
-// bit 0 of *nonempty tells whether it has a nonzero value.  After the first row a row costs its
-// nonzeros rather than D.  Called by the whole workgroup; records the new row's entry range.
-template <typename XT>
+// (have_row false), the whole row is zero-filled; then the new row's values (coarse codes with
+// kCoarse) are scattered and bit 0 of *nonempty tells whether it has a nonzero value.  After
+// the first row a row costs its nonzeros rather than D.  Called by the whole workgroup; records
+// the new row's entry range.
+template <typename XT, bool kCoarse>
 __device__ __forceinline__ void restage_row(unsigned char *smem, const Rows &rows, uint64_t row,
-                                            uint32_t D, bool &have_row, uint64_t &prev_lo,
-                                            uint64_t &prev_hi, uint32_t *nonempty)
+                                            uint32_t D, const uint32_t *bound, bool &have_row,
+                                            uint64_t &prev_lo, uint64_t &prev_hi,
+                                            uint32_t *nonempty)
 {
     XT *x = reinterpret_cast<XT *>(smem);
     if (!have_row) {
@@ -141,7 +168,7 @@ __device__ __forceinline__ void restage_row(unsigned char *smem, const Rows &row
     for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
         const uint32_t v = rows.val[e];
         const uint32_t c = rows.col[e];
-        if (c < D) x[c] = (XT)v;
+        if (c < D) x[c] = lds_value<XT, kCoarse>(v, c, bound);
         if (v) mine = 1u;
     }
     if (mine) atomicOr(nonempty, mine);
@@ -174,7 +201,7 @@ __device__ __forceinline__ void write_tile(uint16_t *__restrict__ sig, const uin
 template <int R>
 constexpr int walk_waves_per_eu() { return R <= 4 ? 8 : 1; }
 
-template <typename XT, int R, int K, bool kPacked>
+template <typename XT, int R, int K, bool kPacked, bool kCoarse>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves_per_eu<R>()))) void batched_kernel(Bounds b, Rows rows, uint32_t k,
                                                        uint64_t seed, uint16_t *__restrict__ sig,
                                                        uint32_t hashes_per_tile, uint32_t depth,
@@ -231,7 +258,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
         }
 
         if (blk != staged) {
-            stage_block<XT, R>(smem, rows, row0, n_here, D, &nonempty, skip);
+            stage_block<XT, R, kCoarse>(smem, rows, row0, n_here, D, b.bound, &nonempty, skip);
             staged = blk;
         }
         // Wave-uniform values are read into scalar registers so every branch on them is a
@@ -263,8 +290,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
                 const uint64_t seen = __builtin_amdgcn_ballot_w64(lane_h <= kCap);
                 return ((seen - kBottoms) & ~seen & kTops) != 0;
             };
-            // window [base + 1, base + kWin] from the lane's K stream entries
-            auto stream_window = [&](const EntryRun<K, kPacked> &run, uint32_t base) {
+            // window [base + 1, base + kWin] from the lane's K stream entries; with coarse
+            // codes, true when some step of the wavefront's window tied (the caller then tests
+            // the window again with in-lane draws, which are exact; ties count as red here)
+            auto stream_window = [&](const EntryRun<K, kPacked> &run, uint32_t base) -> bool {
                 uint32_t xv[K], off[K];  // all K reads in flight before the first compare
 #pragma unroll
                 for (int q = 0; q < (int)K; ++q) {
@@ -276,6 +305,14 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
 #pragma unroll
                 for (int q = K - 1; q >= 0; --q) c = off[q] < xv[q] ? step_in_window[q] : c;
                 lane_h = min(lane_h, base + c);
+                if constexpr (kCoarse) {
+                    bool tie = false;
+#pragma unroll
+                    for (int q = 0; q < (int)K; ++q) tie = tie || off[q] == xv[q];
+                    return __builtin_amdgcn_ballot_w64(tie) != 0;
+                } else {
+                    return false;
+                }
             };
             // the same window with the draws made in-lane, one step at a time; step 65536 of
             // the last window may show up here: it is above the cap like "no green step"
@@ -287,7 +324,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
                     const uint64_t p = position(seed, j, t, b.total, b.threshold);
                     uint64_t o64;
                     const uint32_t comp = component_of(p, b.prefix, b.bucket, b.shift, &o64);
-                    c = o64 < (uint64_t)*reinterpret_cast<const XT *>(smem + (size_t)comp * kScale + row_byte) ? my_grp * K + q + 1u : c;
+                    const uint32_t lv = *reinterpret_cast<const XT *>(smem + (size_t)comp * kScale + row_byte);
+                    c = lane_green<kCoarse>(o64, lv, comp, b, rows, row0 + my_row) ? my_grp * K + q + 1u : c;
                 }
                 lane_h = min(lane_h, base + c);
             };
@@ -317,13 +355,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
                 };
                 EntryRun<K, kPacked> e0 = fetch(0), e1 = fetch(kWin), e2 = fetch(2 * kWin);
                 for (; base < depth; base += 3 * kWin) {
-                    stream_window(e0, base);
+                    if (stream_window(e0, base)) lane_window(base);
                     if (!goes_on()) break;
                     e0 = fetch(base + 3 * kWin);
-                    stream_window(e1, base + kWin);
+                    if (stream_window(e1, base + kWin)) lane_window(base + kWin);
                     if (!goes_on()) break;
                     e1 = fetch(base + 4 * kWin);
-                    stream_window(e2, base + 2 * kWin);
+                    if (stream_window(e2, base + 2 * kWin)) lane_window(base + 2 * kWin);
                     if (!goes_on()) break;
                     e2 = fetch(base + 5 * kWin);
                 }
@@ -365,7 +403,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
 // workgroups of one XCD mostly walk one block of hash ids, and that XCD's L2 holds only that
 // block's part of the position stream; each row is then staged once per group.
 // ---------------------------------------------------------------------------------------------
-template <typename XT, bool kPacked>
+template <typename XT, bool kPacked, bool kCoarse>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void ballot_kernel(
     Bounds b, Rows rows, uint32_t k, uint64_t seed, uint16_t *__restrict__ sig,
     uint32_t hashes_per_tile, uint32_t depth, const void *entries, unsigned long long *tile_counter,
@@ -423,7 +461,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             continue;
         }
         if (row != staged) {
-            restage_row<XT>(smem, rows, row, D, have_row, staged_lo, staged_hi, &nonempty);
+            restage_row<XT, kCoarse>(smem, rows, row, D, b.bound, have_row, staged_lo, staged_hi,
+                                     &nonempty);
             staged = row;
         }
         const bool live = __builtin_amdgcn_readfirstlane(nonempty) != 0;
@@ -434,12 +473,21 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         }
         const uint32_t j1 = min(k, j0 + hashes_per_tile);
 
-        // ballot of the lanes whose step is green in the window the run holds
-        auto stream_ballot = [&](const EntryRun<1, kPacked> &run) {
+        // ballot of the lanes whose step is green in the window the run holds; with coarse
+        // codes, *tied tells whether a lane below the lowest green one tied (that window is then
+        // walked on with in-lane draws, which are exact)
+        auto stream_ballot = [&](const EntryRun<1, kPacked> &run, bool *tied) {
             uint32_t lds, off;
             run.get(0, (uint32_t)sizeof(XT), &lds, &off);
             const uint32_t xv = *reinterpret_cast<const XT *>(smem + lds);
-            return __builtin_amdgcn_ballot_w64(off < xv);
+            const uint64_t green = __builtin_amdgcn_ballot_w64(off < xv);
+            if constexpr (kCoarse) {
+                const uint64_t below = green ? (green & (0ull - green)) - 1ull : ~0ull;
+                *tied = (__builtin_amdgcn_ballot_w64(off == xv) & below) != 0;
+            } else {
+                *tied = false;
+            }
+            return green;
         };
         // each prefetch stays where it is issued (see the shared-window walk)
         auto fetch = [&](uint32_t j, uint32_t at) {
@@ -462,8 +510,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                 const uint64_t p = position(seed, j, t, b.total, b.threshold);
                 uint64_t o64;
                 const uint32_t comp = component_of(p, b.prefix, b.bucket, b.shift, &o64);
-                const uint64_t green = __builtin_amdgcn_ballot_w64(
-                    o64 < (uint64_t)*reinterpret_cast<const XT *>(smem + (size_t)comp * sizeof(XT)));
+                const uint32_t lv = *reinterpret_cast<const XT *>(smem + (size_t)comp * sizeof(XT));
+                const uint64_t green =
+                    __builtin_amdgcn_ballot_w64(lane_green<kCoarse>(o64, lv, comp, b, rows, row));
                 if (green) return min(base + (uint32_t)__builtin_ctzll(green) + 1u, kCap);
             }
             return kCap;
@@ -471,14 +520,18 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         // hash id j from its three requested windows, then the stream, then in-lane draws
         auto walk_id = [&](uint32_t j, EntryRun<1, kPacked> &e0, EntryRun<1, kPacked> &e1,
                            EntryRun<1, kPacked> &e2) {
+            bool tied = false;
             for (uint32_t base = 0; base < depth; base += 3 * kWave) {
-                uint64_t green = stream_ballot(e0);
+                uint64_t green = stream_ballot(e0, &tied);
+                if (tied) return store(j, lane_walk(j, base));
                 if (green) return store(j, base + (uint32_t)__builtin_ctzll(green) + 1u);
                 e0 = fetch(j, base + 3 * kWave);
-                green = stream_ballot(e1);
+                green = stream_ballot(e1, &tied);
+                if (tied) return store(j, lane_walk(j, base + kWave));
                 if (green) return store(j, base + kWave + (uint32_t)__builtin_ctzll(green) + 1u);
                 e1 = fetch(j, base + 4 * kWave);
-                green = stream_ballot(e2);
+                green = stream_ballot(e2, &tied);
+                if (tied) return store(j, lane_walk(j, base + 2 * kWave));
                 if (green) return store(j, base + 2 * kWave + (uint32_t)__builtin_ctzll(green) + 1u);
                 e2 = fetch(j, base + 5 * kWave);
             }
@@ -508,114 +561,120 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
 
 // Raises the kernel's dynamic LDS limit once per process; the launches return its status, so
 // a limit the runtime refuses fails at the launch that needs it.
-template <typename XT, int R, int K, bool kPacked>
+template <typename XT, int R, int K, bool kPacked, bool kCoarse>
 hipError_t configure_batched()
 {
     static const hipError_t status =
-        hipFuncSetAttribute((const void *)batched_kernel<XT, R, K, kPacked>,
+        hipFuncSetAttribute((const void *)batched_kernel<XT, R, K, kPacked, kCoarse>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynamicLds);
     return status;
 }
 
-template <typename XT, int R, int K, bool kPacked>
+template <typename XT, int R, int K, bool kPacked, bool kCoarse>
 int batched_occupancy_t(const BatchedPlan &plan, size_t lds)
 {
-    configure_batched<XT, R, K, kPacked>();
+    configure_batched<XT, R, K, kPacked, kCoarse>();
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<XT, R, K, kPacked>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<XT, R, K, kPacked, kCoarse>,
                                                      plan.waves_per_block * kWave, lds) != hipSuccess)
         return 1;
     return blocks > 0 ? blocks : 1;
 }
 
-template <typename XT, int R, int K, bool kPacked>
+template <typename XT, int R, int K, bool kPacked, bool kCoarse>
 hipError_t launch_batched_t(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
                                    uint16_t *sig, const BatchedPlan &plan, const void *entries,
                                    unsigned long long *tile_counter, uint32_t grid, hipStream_t stream)
 {
     const size_t lds = batched_lds_bytes(b.dims, plan);
-    const hipError_t e = configure_batched<XT, R, K, kPacked>();
+    const hipError_t e = configure_batched<XT, R, K, kPacked, kCoarse>();
     if (e != hipSuccess) return e;
-    batched_kernel<XT, R, K, kPacked><<<grid, plan.waves_per_block * kWave, lds, stream>>>(
+    batched_kernel<XT, R, K, kPacked, kCoarse><<<grid, plan.waves_per_block * kWave, lds, stream>>>(
         b, rows, k, seed, sig, plan.hashes_per_tile, plan.stream_depth, entries, tile_counter);
     return hipGetLastError();
 }
 
-template <typename XT, bool kPacked>
+template <typename XT, bool kPacked, bool kCoarse>
 hipError_t configure_ballot()
 {
     static const hipError_t status =
-        hipFuncSetAttribute((const void *)ballot_kernel<XT, kPacked>,
+        hipFuncSetAttribute((const void *)ballot_kernel<XT, kPacked, kCoarse>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynamicLds);
     return status;
 }
 
-template <typename XT, bool kPacked>
+template <typename XT, bool kPacked, bool kCoarse>
 int ballot_occupancy_t(const BatchedPlan &plan, size_t lds)
 {
-    configure_ballot<XT, kPacked>();
+    configure_ballot<XT, kPacked, kCoarse>();
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, ballot_kernel<XT, kPacked>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, ballot_kernel<XT, kPacked, kCoarse>,
                                                      plan.waves_per_block * kWave, lds) != hipSuccess)
         return 1;
     return blocks > 0 ? blocks : 1;
 }
 
-template <typename XT, bool kPacked>
+template <typename XT, bool kPacked, bool kCoarse>
 hipError_t launch_ballot_t(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
                            uint16_t *sig, const BatchedPlan &plan, const void *entries,
                            unsigned long long *tile_counter, uint32_t grid, hipStream_t stream)
 {
     const size_t lds = batched_lds_bytes(b.dims, plan);
-    const hipError_t e = configure_ballot<XT, kPacked>();
+    const hipError_t e = configure_ballot<XT, kPacked, kCoarse>();
     if (e != hipSuccess) return e;
-    ballot_kernel<XT, kPacked><<<grid, plan.waves_per_block * kWave, lds, stream>>>(
+    ballot_kernel<XT, kPacked, kCoarse><<<grid, plan.waves_per_block * kWave, lds, stream>>>(
         b, rows, k, seed, sig, plan.hashes_per_tile, plan.stream_depth, entries, tile_counter,
         plan.hash_groups);
     return hipGetLastError();
 }
 
-// Calls F<XT, R, K, packed>() for the plan's template parameters: K = R, or K = 4 for R < 4.
-template <template <typename, int, int, bool> class F, typename... Args>
+// Calls F<XT, R, K, packed, coarse>() for the plan's template parameters: K = R, or K = 4 for
+// R < 4; coarse codes for R <= 4 only.
+template <template <typename, int, int, bool, bool> class F, typename... Args>
 auto dispatch_batched(const BatchedPlan &plan, Args &&...args)
-    -> decltype(F<uint16_t, 1, 1, true>::run(args...))
+    -> decltype(F<uint16_t, 1, 1, true, false>::run(args...))
 {
-#define WMH_RK_CASE(RR, KK)                                                                      \
+#define WMH_RK_CASE(RR, KK, COARSE)                                                              \
     if (plan.rows_per_block == RR && plan.steps_per_lane == KK) {                                \
+        if (plan.coarse) {                                                                       \
+            if (COARSE && plan.narrow && plan.packed)                                            \
+                return F<uint16_t, RR, KK, true, COARSE>::run(args...);                          \
+            return F<uint16_t, 1, 1, true, false>::fail();                                       \
+        }                                                                                        \
         if (plan.narrow)                                                                         \
-            return plan.packed ? F<uint16_t, RR, KK, true>::run(args...)                         \
-                               : F<uint16_t, RR, KK, false>::run(args...);                       \
-        return plan.packed ? F<uint32_t, RR, KK, true>::run(args...)                             \
-                           : F<uint32_t, RR, KK, false>::run(args...);                           \
+            return plan.packed ? F<uint16_t, RR, KK, true, false>::run(args...)                  \
+                               : F<uint16_t, RR, KK, false, false>::run(args...);                \
+        return plan.packed ? F<uint32_t, RR, KK, true, false>::run(args...)                      \
+                           : F<uint32_t, RR, KK, false, false>::run(args...);                    \
     }
-    WMH_RK_CASE(1, 1)
-    WMH_RK_CASE(1, 4)
-    WMH_RK_CASE(2, 2)
-    WMH_RK_CASE(2, 4)
-    WMH_RK_CASE(4, 4)
-    WMH_RK_CASE(8, 8)
-    WMH_RK_CASE(16, 16)
+    WMH_RK_CASE(1, 1, true)
+    WMH_RK_CASE(1, 4, true)
+    WMH_RK_CASE(2, 2, true)
+    WMH_RK_CASE(2, 4, true)
+    WMH_RK_CASE(4, 4, true)
+    WMH_RK_CASE(8, 8, false)
+    WMH_RK_CASE(16, 16, false)
 #undef WMH_RK_CASE
-    return F<uint16_t, 1, 1, true>::fail();
+    return F<uint16_t, 1, 1, true, false>::fail();
 }
 
-template <typename XT, int R, int K, bool kPacked>
+template <typename XT, int R, int K, bool kPacked, bool kCoarse>
 struct LaunchBatched {
     static hipError_t run(const Bounds &b, const Rows &rows, uint32_t k, uint64_t seed,
                           uint16_t *sig, const BatchedPlan &plan, const void *entries,
                           unsigned long long *tile_counter, uint32_t grid, hipStream_t stream)
     {
-        return launch_batched_t<XT, R, K, kPacked>(b, rows, k, seed, sig, plan, entries,
-                                                   tile_counter, grid, stream);
+        return launch_batched_t<XT, R, K, kPacked, kCoarse>(b, rows, k, seed, sig, plan, entries,
+                                                            tile_counter, grid, stream);
     }
     static hipError_t fail() { return hipErrorInvalidValue; }
 };
 
-template <typename XT, int R, int K, bool kPacked>
+template <typename XT, int R, int K, bool kPacked, bool kCoarse>
 struct OccupancyBatched {
     static int run(const BatchedPlan &plan, size_t lds)
     {
-        return batched_occupancy_t<XT, R, K, kPacked>(plan, lds);
+        return batched_occupancy_t<XT, R, K, kPacked, kCoarse>(plan, lds);
     }
     static int fail() { return 0; }
 };
@@ -639,19 +698,24 @@ hipError_t launch_ballot_walk(const Bounds &b, const Rows &rows, uint32_t k, uin
                               uint16_t *sig, const BatchedPlan &plan, const void *entries,
                               unsigned long long *tile_counter, uint32_t grid, hipStream_t stream)
 {
+    if (plan.coarse) {
+        if (!plan.narrow || !plan.packed) return hipErrorInvalidValue;
+        return launch_ballot_t<uint16_t, true, true>(b, rows, k, seed, sig, plan, entries, tile_counter, grid, stream);
+    }
     if (plan.narrow)
         return plan.packed
-                   ? launch_ballot_t<uint16_t, true>(b, rows, k, seed, sig, plan, entries, tile_counter, grid, stream)
-                   : launch_ballot_t<uint16_t, false>(b, rows, k, seed, sig, plan, entries, tile_counter, grid, stream);
-    return launch_ballot_t<uint32_t, false>(b, rows, k, seed, sig, plan, entries, tile_counter, grid, stream);
+                   ? launch_ballot_t<uint16_t, true, false>(b, rows, k, seed, sig, plan, entries, tile_counter, grid, stream)
+                   : launch_ballot_t<uint16_t, false, false>(b, rows, k, seed, sig, plan, entries, tile_counter, grid, stream);
+    return launch_ballot_t<uint32_t, false, false>(b, rows, k, seed, sig, plan, entries, tile_counter, grid, stream);
 }
 
 int ballot_walk_blocks_per_cu(const BatchedPlan &plan, size_t lds)
 {
+    if (plan.coarse) return plan.narrow && plan.packed ? ballot_occupancy_t<uint16_t, true, true>(plan, lds) : 0;
     if (plan.narrow)
-        return plan.packed ? ballot_occupancy_t<uint16_t, true>(plan, lds)
-                           : ballot_occupancy_t<uint16_t, false>(plan, lds);
-    return ballot_occupancy_t<uint32_t, false>(plan, lds);
+        return plan.packed ? ballot_occupancy_t<uint16_t, true, false>(plan, lds)
+                           : ballot_occupancy_t<uint16_t, false, false>(plan, lds);
+    return ballot_occupancy_t<uint32_t, false, false>(plan, lds);
 }
 
 }  // namespace wmh

@@ -22,6 +22,7 @@ STATUS = {0: "WMH_OK", -1: "WMH_E_ARG", -2: "WMH_E_NO_BOUNDS", -3: "WMH_E_COL_RA
 NOALLOC_SCRATCH_BYTES = 16 << 20  # WMH_NOALLOC_SCRATCH_BYTES: wmh_hash_noalloc's static array
 MODES = {"auto": 0, "plain": 1, "batched": 2, "indexed": 3, "split": 4, "plain_shared": 5}
 WALKS = {"auto": 0, "shared": 1, "rows": 2, "ballot": 3, "index": 4}
+VALUES = {"auto": 0, "exact": 1, "coarse": 2}  # wmh_opts.values: dense rows in LDS
 
 EXPORTED = ["wmh_opts_init", "wmh_create", "wmh_destroy", "wmh_set_bounds", "wmh_hash",
             "wmh_hash_noalloc",
@@ -46,7 +47,7 @@ class WmhOpts(ctypes.Structure):
                 ("waves_per_block", ctypes.c_uint32), ("profile", ctypes.c_int32),
                 ("walk", ctypes.c_int32), ("steps_per_lane", ctypes.c_uint32),
                 ("index_batch", ctypes.c_uint32), ("index_claim", ctypes.c_uint32),
-                ("hash_groups", ctypes.c_uint32)]
+                ("hash_groups", ctypes.c_uint32), ("values", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -75,7 +76,8 @@ class TuneResult(ctypes.Structure):
                 ("candidates", ctypes.c_uint32), ("steps_class", ctypes.c_int32),
                 ("walk", ctypes.c_int32), ("steps_per_lane", ctypes.c_uint32),
                 ("index_batch", ctypes.c_uint32), ("index_claim", ctypes.c_uint32),
-                ("hash_groups", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+                ("hash_groups", ctypes.c_uint32), ("values", ctypes.c_int32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
 class WMHError(RuntimeError):
@@ -360,7 +362,7 @@ class Context:
     def make_opts(mode="auto", batch_rows=0, validate=True, use_graph=True, sync=True,
                   rows_per_block=0, hashes_per_tile=0, stream_depth=0, waves_per_block=0,
                   profile=False, walk=0, steps_per_lane=0, index_batch=0,
-                  index_claim=0, hash_groups=0) -> WmhOpts:
+                  index_claim=0, hash_groups=0, values=0) -> WmhOpts:
         o = WmhOpts()
         load().wmh_opts_init(ctypes.byref(o))
         o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
@@ -379,6 +381,7 @@ class Context:
         o.index_batch = index_batch
         o.index_claim = {"counter": 1, "stride": 2}.get(index_claim, index_claim)
         o.hash_groups = hash_groups
+        o.values = VALUES[values] if isinstance(values, str) else int(values)
         return o
 
     def last_kernel_ms(self) -> tuple[float, float]:
@@ -404,7 +407,8 @@ class Context:
                 "stream_depth": o.stream_depth, "waves_per_block": o.waves_per_block,
                 "walk": {v: k for k, v in WALKS.items()}.get(o.walk, o.walk),
                 "steps_per_lane": o.steps_per_lane, "index_batch": o.index_batch,
-                "index_claim": o.index_claim, "hash_groups": o.hash_groups}
+                "index_claim": o.index_claim, "hash_groups": o.hash_groups,
+                "values": {1: "exact", 2: "coarse"}.get(o.values)}
 
     def tune(self, rows: DeviceRows, k: int, seed: int = 0, reps: int = 3, stream=None) -> dict:
         """Autotunes the batched tile plan on these rows (see wmh_tune); returns the result and
@@ -422,7 +426,8 @@ class Context:
                 "steps_class": r.steps_class,
                 "walk": {v: k for k, v in WALKS.items()}.get(r.walk, r.walk),
                 "steps_per_lane": r.steps_per_lane, "index_batch": r.index_batch,
-                "index_claim": r.index_claim, "hash_groups": r.hash_groups}
+                "index_claim": r.index_claim, "hash_groups": r.hash_groups,
+                "values": {1: "exact", 2: "coarse"}.get(r.values)}
 
     def tune_save(self, path: str):
         self._check(self._lib.wmh_tune_save(self._ptr, os.fsencode(path)), "wmh_tune_save")

@@ -45,7 +45,8 @@ def test_opts_defaults(lib):
     lib.wmh_opts_init(ctypes.byref(o))
     assert (o.mode, o.batch_rows, o.validate, o.use_graph, o.sync) == (0, 8192, 1, 1, 1)
     assert (o.rows_per_block, o.hashes_per_tile, o.stream_depth, o.waves_per_block) == (0, 0, 0, 0)
-    assert ctypes.sizeof(wmh.WmhOpts) == 4 * 15
+    assert o.values == 0
+    assert ctypes.sizeof(wmh.WmhOpts) == 4 * 16
 
 
 def test_status_strings(lib):

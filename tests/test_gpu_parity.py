@@ -154,6 +154,17 @@ BATCHED_PLANS = [
     dict(walk="ballot", hash_groups=2), dict(walk="ballot", hash_groups=8, waves_per_block=4),
     dict(walk="ballot", hash_groups=5, stream_depth=64),
     dict(walk="ballot", hash_groups=8, stream_depth=None),
+    # dense rows as 16-bit coarse codes (ties settled from the exact value and offset)
+    dict(values="coarse", rows_per_block=1), dict(values="coarse", rows_per_block=2),
+    dict(values="coarse", rows_per_block=4), dict(values="coarse", rows_per_block=4,
+                                                  hashes_per_tile=7, waves_per_block=3),
+    dict(values="coarse", rows_per_block=1, steps_per_lane=4),
+    dict(values="coarse", rows_per_block=2, steps_per_lane=4, stream_depth=200),
+    dict(values="coarse", rows_per_block=4, stream_depth=None),
+    dict(values="coarse", rows_per_block=4, stream_depth=64),
+    dict(values="coarse", walk="ballot"), dict(values="coarse", walk="ballot", stream_depth=64),
+    dict(values="coarse", walk="ballot", stream_depth=None, hashes_per_tile=9),
+    dict(values="exact", rows_per_block=2),
 ]
 
 CASES = {
@@ -166,6 +177,12 @@ CASES = {
                       13),
     "sparse-slow": (dict(seed=4, n_rows=19, D=2000, density=0.005, max_val=500,
                          bound_slack=60000), 40, 14),
+    # bounds a little above 2^16: each coarse code covers two to four integers, so many tested
+    # steps tie and are settled exactly
+    "coarse-ties": (dict(seed=5, n_rows=45, D=400, density=0.1, max_val=70000,
+                         bound_slack=60000, empty_rows=2), 60, 15),
+    "coarse-ties-dense": (dict(seed=6, n_rows=23, D=5, density=0.8, max_val=131000,
+                               bound_slack=3), 70, 16),
 }
 
 

@@ -29,7 +29,7 @@ def ds():
 
 def _plan_of(res):
     return (res["rows_per_block"], res["hashes_per_tile"], res["waves_per_block"], res["walk"],
-            res["steps_per_lane"], res["hash_groups"])
+            res["steps_per_lane"], res["hash_groups"], res["values"])
 
 
 def test_tune_then_hash_uses_the_plan(ctx, ds):
@@ -74,7 +74,7 @@ def test_save_and_load(ctx, ds, tmp_path):
     res = ctx.tune(rows, ds.k, seed=0, reps=1)
     path = tmp_path / "plans.txt"
     ctx.tune_save(str(path))
-    assert path.read_text().startswith("wmh-tune 5\n")
+    assert path.read_text().startswith("wmh-tune 6\n")
     fresh = wmh.Context(0)
     try:
         fresh.set_bounds(ds.m)
@@ -83,12 +83,40 @@ def test_save_and_load(ctx, ds, tmp_path):
         p = fresh.last_plan()
         assert _plan_of(p) == _plan_of(res)
         bad = tmp_path / "bad.txt"
-        bad.write_text("wmh-tune 5\n1024 0 64 4 3 64 8 1 3 1 0.5\n")  # R = 3 is not a plan
+        bad.write_text("wmh-tune 6\n1024 0 64 4 3 64 8 1 3 1 1 0.5\n")  # R = 3 is not a plan
         with pytest.raises(wmh.WMHError) as e:
             fresh.tune_load(str(bad))
         assert e.value.name == "WMH_E_ARG"
         with pytest.raises(wmh.WMHError):
             fresh.tune_load(str(tmp_path / "missing.txt"))
+    finally:
+        fresh.close()
+
+
+def test_wide_bounds_tune_both_value_forms(ctx, tmp_path):
+    """Bounds above 16 bits: the tuner times exact 32-bit rows and coarse codes; whichever it
+    keeps is taken by later calls, survives a save/load round trip and gives the oracle's
+    values."""
+    ds = synth.random_case(seed=17, n_rows=96, D=3000, density=0.05, max_val=3_000_000,
+                           bound_slack=500_000, k=40)
+    print("  tune wide bounds", flush=True)
+    ctx.set_bounds(ds.m)
+    rows = wmh.upload_dataset(ds, DEV)
+    res = ctx.tune(rows, ds.k, seed=5, reps=1)
+    assert res["values"] in ("exact", "coarse")
+    want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, ds.k, seed=5)
+    got = wmh.sig_to_numpy(ctx.hash(rows, ds.k, seed=5, mode="batched"))
+    assert np.array_equal(got, want)
+    assert _plan_of(ctx.last_plan()) == _plan_of(res)
+    path = tmp_path / "wide.txt"
+    ctx.tune_save(str(path))
+    fresh = wmh.Context(0)
+    try:
+        fresh.set_bounds(ds.m)
+        fresh.tune_load(str(path))
+        assert np.array_equal(wmh.sig_to_numpy(fresh.hash(rows, ds.k, seed=5, mode="batched")),
+                              want)
+        assert _plan_of(fresh.last_plan()) == _plan_of(res)
     finally:
         fresh.close()
 
