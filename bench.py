@@ -34,13 +34,13 @@ KEY_BYTES = 8  # one component-index key
 # kernel and plan are the ones timed; the line carries null otherwise.
 #   batched_kernel<unsigned short, 4, 4, true> on the histogram workload (N = 1e5):
 #     profiles/batched_kernel_histogram_k500.txt
-TRAFFIC_R4_HISTOGRAM = 1.2033e9 + 0.1009e9
-#   ballot_kernel<unsigned int, false>, 16 wavefronts, J = 500, one hash group, on the heavy tail
-#     (depth 40704): profiles/ballot_kernel_heavy_tail_k500.txt
-TRAFFIC_BALLOT_HEAVY_TAIL = 46.2558e9 + 0.2114e9
-#   index_rows_kernel<false, 16>, 16 wavefronts, counter claims, on the 1e6 text-like rows:
+TRAFFIC_R4_HISTOGRAM = 1.1969e9 + 0.1009e9
+#   ballot_kernel<unsigned short, true, true> (coarse codes), 8 wavefronts, J = 500, one hash
+#     group, on the heavy tail (depth 40704): profiles/ballot_kernel_heavy_tail_k500.txt
+TRAFFIC_BALLOT_HEAVY_TAIL = 15.0449e9 + 0.2115e9
+#   index_rows_kernel<false, 16>, 8 wavefronts, counter claims, on the 1e6 text-like rows:
 #     profiles/index_rows_kernel_text_like_k1000.txt
-TRAFFIC_INDEX_TEXT_LIKE = 432.1412e9 + 2.0670e9
+TRAFFIC_INDEX_TEXT_LIKE = 432.0701e9 + 2.0670e9
 
 
 def log(msg: str):
@@ -343,7 +343,8 @@ def heavy_tail_bench(args, torch, synth, wmh) -> dict:
                     tests, float(np.mean(walk_b)), f"{out['batched_plan']['walk']} walk",
                     traffic=TRAFFIC_BALLOT_HEAVY_TAIL if (
                         out["batched_plan"]["walk"] == "ballot"
-                        and out["batched_plan"]["waves_per_block"] == 16
+                        and out["batched_plan"]["waves_per_block"] == 8
+                        and out["batched_plan"]["values"] == "coarse"
                         and out["batched_plan"]["hashes_per_tile"] == 500
                         and out["batched_plan"]["hash_groups"] == 1 and ds.n_rows == 200_000)
                     else None)})
@@ -524,7 +525,7 @@ def text_like_bench(args, torch, synth, wmh) -> dict:
     out["roofline"] = hbm_roofline(key_bytes, float(np.mean(walk)), "index_rows_kernel",
                                    note="expected keys of the rows' evaluation orders "
                                         "(Theorem 2), the rows and the signatures, once each")
-    if (plan["waves_per_block"], plan["index_batch"], plan["index_claim"]) == (16, 16, 1) \
+    if (plan["waves_per_block"], plan["index_batch"], plan["index_claim"]) == (8, 16, 1) \
             and ds.n_rows == 1_000_000:
         out["roofline"]["traffic"] = TRAFFIC_INDEX_TEXT_LIKE
     out["roofline"].update(key_info)

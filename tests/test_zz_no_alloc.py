@@ -58,18 +58,26 @@ def test_plans_and_empty_rows(ctx):
 
 
 def test_stream_shrinks_to_the_static_array(ctx):
-    # tiny green fractions: the planner's stream (about 65000 steps x 128 ids x 8 bytes) is
-    # larger than the static array, so the call walks a shorter stream and draws in-lane beyond
+    # tiny green fractions: the planner's stream (about 65000 steps x 128 ids x 4 or 8 bytes)
+    # is larger than the static array, so the call walks a shorter stream and draws in-lane
+    # beyond
     D = 1024
     rng = np.random.Generator(np.random.PCG64(5))
     cols = [np.sort(rng.choice(D, 5, replace=False)) for _ in range(40)]
     vals = [rng.integers(1, 1 << 18, 5, dtype=np.uint64) for _ in range(40)]
     m = np.full(D, 1 << 24, dtype=np.uint32)
     ds = synth.csr_from_lists(cols, vals, D, m=m, name="sparse-green", k=128)
-    want, got = both(ctx, ds, 128)
-    assert np.array_equal(got, want)
-    # bounds above 65535: 8-byte stream entries
-    assert 0 < ctx.last_plan()["stream_depth"] * 128 * 8 <= wmh.NOALLOC_SCRATCH_BYTES
+    # bounds above 65535: coarse codes in 4-byte entries (the default), or the exact values in
+    # 8-byte entries
+    exact = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, 128, seed=0)
+    for values, entry in (("auto", 4), ("coarse", 4), ("exact", 8)):
+        want, got = both(ctx, ds, 128, values=values)
+        assert np.array_equal(got, want), values
+        assert np.array_equal(got, exact), values
+        plan = ctx.last_plan()
+        assert plan["values"] == ("coarse" if entry == 4 else "exact")
+        assert 0 < plan["stream_depth"] < 65000
+        assert plan["stream_depth"] * 128 * entry <= wmh.NOALLOC_SCRATCH_BYTES
 
 
 def test_rejections_leave_the_output_untouched(ctx):
