@@ -570,6 +570,16 @@ wmh_status wmh_server_wait(wmh_server *srv, uint64_t ticket, double *latency_ms)
 /* Blocks until every submitted request has completed. */
 wmh_status wmh_server_drain(wmh_server *srv);
 
+/*
+ * wmh_server_reserve -- sizes every slot's device buffers and page-locked signature buffer for
+ * requests of up to max_rows rows and max_nnz nonzeros, so that admitting such a request
+ * allocates nothing.  Without it a slot grows its buffers (by at least half) when a larger
+ * request arrives, and freeing the old ones waits for the device, which delays every request
+ * in flight.  Waits until every submitted request has completed.  Errors: WMH_E_ARG,
+ * WMH_E_NOMEM (beyond mem_budget or device memory), WMH_E_DEVICE.
+ */
+wmh_status wmh_server_reserve(wmh_server *srv, uint64_t max_rows, uint64_t max_nnz);
+
 /* Counters and latency percentiles over the completed requests. */
 wmh_status wmh_server_stats(wmh_server *srv, wmh_serving_stats *out);
 

@@ -94,16 +94,39 @@ struct Slot {
     bool computing = false;  // past the check: the walk and the copy out are queued
 };
 
+// Grows a slot buffer to hold `want` elements, by at least half its size each time: freeing
+// the old buffer waits for the device, so growth must stay rare (wmh_server_reserve sizes the
+// buffers up front).
 template <typename T>
 hipError_t grow_device(T **p, uint64_t *cap, uint64_t want)
 {
     if (want <= *cap && *p) return hipSuccess;
+    const uint64_t n = std::max<uint64_t>({want, 1, *cap + *cap / 2});
     if (*p) (void)hipFree(*p);
     *p = nullptr;
     *cap = 0;
-    const uint64_t n = std::max<uint64_t>(want, 1);
     hipError_t e = hipMalloc(reinterpret_cast<void **>(p), n * sizeof(T));
     if (e == hipSuccess) *cap = n;
+    return e;
+}
+
+// The slot's buffers for a request of n_rows rows and nnz nonzeros with k hashes per row.
+hipError_t grow_slot(Slot &slot, uint64_t n_rows, uint64_t nnz, uint32_t k)
+{
+    const uint64_t sig_elems = n_rows * (uint64_t)k;
+    hipError_t e = grow_device(&slot.d_row_ptr, &slot.cap_rows, n_rows + 1);
+    if (e == hipSuccess) e = grow_device(&slot.d_col, &slot.cap_col, nnz);
+    if (e == hipSuccess) e = grow_device(&slot.d_val, &slot.cap_val, nnz);
+    if (e == hipSuccess) e = grow_device(&slot.d_sig, &slot.cap_sig, sig_elems);
+    if (e == hipSuccess && (slot.cap_h_sig < sig_elems || !slot.h_sig)) {
+        const uint64_t n = std::max<uint64_t>({sig_elems, 1, slot.cap_h_sig + slot.cap_h_sig / 2});
+        if (slot.h_sig) (void)hipHostFree(slot.h_sig);
+        slot.h_sig = nullptr;
+        slot.cap_h_sig = 0;
+        e = hipHostMalloc(reinterpret_cast<void **>(&slot.h_sig), n * sizeof(uint16_t),
+                          hipHostMallocDefault);
+        if (e == hipSuccess) slot.cap_h_sig = n;
+    }
     return e;
 }
 
@@ -151,19 +174,7 @@ struct wmh_server {
 wmh_status wmh_server::launch_check(Slot &slot, Request &r)
 {
     const uint32_t k = cfg.k;
-    const uint64_t sig_elems = r.n_rows * (uint64_t)k;
-    hipError_t e = grow_device(&slot.d_row_ptr, &slot.cap_rows, r.n_rows + 1);
-    if (e == hipSuccess) e = grow_device(&slot.d_col, &slot.cap_col, r.nnz);
-    if (e == hipSuccess) e = grow_device(&slot.d_val, &slot.cap_val, r.nnz);
-    if (e == hipSuccess) e = grow_device(&slot.d_sig, &slot.cap_sig, sig_elems);
-    if (e == hipSuccess && (slot.cap_h_sig < sig_elems || !slot.h_sig)) {
-        if (slot.h_sig) (void)hipHostFree(slot.h_sig);
-        slot.h_sig = nullptr;
-        slot.cap_h_sig = 0;
-        e = hipHostMalloc(reinterpret_cast<void **>(&slot.h_sig),
-                          std::max<uint64_t>(sig_elems, 1) * sizeof(uint16_t), hipHostMallocDefault);
-        if (e == hipSuccess) slot.cap_h_sig = std::max<uint64_t>(sig_elems, 1);
-    }
+    hipError_t e = grow_slot(slot, r.n_rows, r.nnz, k);
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? WMH_E_NOMEM : WMH_E_DEVICE;
 
     hipStream_t s = slot.stream;
@@ -520,6 +531,25 @@ wmh_status wmh_server_drain(wmh_server *srv)
     std::unique_lock<std::mutex> lk(srv->mu);
     srv->cv_done.wait(lk, [&] { return srv->queue.empty() && srv->inflight == 0; });
     return srv->failed ? WMH_E_DEVICE : WMH_OK;
+}
+
+wmh_status wmh_server_reserve(wmh_server *srv, uint64_t max_rows, uint64_t max_nnz)
+{
+    if (!srv) return WMH_E_ARG;
+    wmh_ctx *ctx = srv->ctx;
+    const uint64_t bytes = (max_rows + 1) * 8 + max_nnz * 8 + max_rows * (uint64_t)srv->cfg.k * 2;
+    if (bytes > srv->cfg.mem_budget)
+        return fail(ctx, WMH_E_NOMEM, "a request of %llu rows and %llu nonzeros exceeds the budget",
+                    (unsigned long long)max_rows, (unsigned long long)max_nnz);
+    std::unique_lock<std::mutex> lk(srv->mu);
+    // with nothing queued or admitted the worker touches no slot while the lock is held
+    srv->cv_done.wait(lk, [&] { return srv->queue.empty() && srv->inflight == 0; });
+    if (hipSetDevice(ctx->device) != hipSuccess) return WMH_E_DEVICE;
+    for (Slot &slot : srv->slots) {
+        const hipError_t e = grow_slot(slot, max_rows, max_nnz, srv->cfg.k);
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? WMH_E_NOMEM : WMH_E_DEVICE;
+    }
+    return WMH_OK;
 }
 
 wmh_status wmh_server_stats(wmh_server *srv, wmh_serving_stats *out)

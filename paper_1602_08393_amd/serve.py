@@ -7,6 +7,7 @@ and, for benchmarking, submits requests at their scheduled (Poisson) arrival tim
 from __future__ import annotations
 
 import ctypes
+import gc
 import time
 from dataclasses import dataclass, field
 
@@ -38,10 +39,11 @@ class PinnedBuffer:
         raw = (ctypes.c_uint8 * (n * dtype.itemsize)).from_address(self.ptr.value)
         return np.frombuffer(raw, dtype=dtype, count=n).reshape(shape)
 
-    def __del__(self):
+    def __del__(self, _void=ctypes.c_void_p):
+        # _void is bound at definition: at interpreter exit the module's globals may be gone
         if getattr(self, "ptr", None) and self.ptr.value:
             self._lib.wmh_host_free(self.ptr)
-            self.ptr = ctypes.c_void_p()
+            self.ptr = _void()
 
 
 def pinned_like(a: np.ndarray, pins: list) -> np.ndarray:
@@ -151,6 +153,13 @@ class Server:
     def drain(self):
         self.ctx._check(self._lib.wmh_server_drain(self._ptr), "wmh_server_drain")
 
+    def reserve(self, max_rows: int, max_nnz: int):
+        """Sizes every slot's buffers for requests of up to max_rows rows and max_nnz
+        nonzeros (wmh_server_reserve), so that admitting them allocates nothing."""
+        self.ctx._check(self._lib.wmh_server_reserve(self._ptr, ctypes.c_uint64(max_rows),
+                                                     ctypes.c_uint64(max_nnz)),
+                        "wmh_server_reserve")
+
     def reset_stats(self):
         self.ctx._check(self._lib.wmh_server_reset_stats(self._ptr), "wmh_server_reset_stats")
 
@@ -217,20 +226,36 @@ class RangeRequests:
 
 def run_open_loop(server: Server, requests, arrivals_s: np.ndarray) -> dict:
     """Submits request i at t0 + arrivals_s[i] (open loop: the schedule never waits for
-    completions) with that scheduled time as its arrival, then drains and returns stats.
-    `requests` is a list of Requests or a function of i that makes request i (called before
-    its due time)."""
-    t0 = now_ns() + 2_000_000
-    for i, a in enumerate(arrivals_s):
-        req = requests(i) if callable(requests) else requests[i]
-        due = t0 + int(a * 1e9)
-        while True:
-            left = due - now_ns()
-            if left <= 0:
-                break
-            time.sleep(min(left, 2_000_000) / 1e9 if left > 200_000 else 0)
-        server.submit(req, arrival_ns=due)
-    server.drain()
-    for ticket in list(server._live):
-        server.wait(ticket)
-    return server.stats()
+    completions) with that scheduled time as its arrival, then drains and returns stats, with
+    the driver's own lateness (actual submission after the scheduled time) added: latencies
+    count from the scheduled time, so a late driver shows up as queueing.  Python's cyclic
+    garbage collector is paused while requests are submitted, so none of its passes delays
+    the schedule.  `requests` is a list of Requests or a function of i that makes request i
+    (called before its due time)."""
+    late = np.zeros(len(arrivals_s))
+    gc_was_on = gc.isenabled()
+    gc.collect()
+    gc.disable()
+    try:
+        t0 = now_ns() + 2_000_000
+        for i, a in enumerate(arrivals_s):
+            req = requests(i) if callable(requests) else requests[i]
+            due = t0 + int(a * 1e9)
+            while True:
+                left = due - now_ns()
+                if left <= 0:
+                    break
+                time.sleep(min(left, 2_000_000) / 1e9 if left > 200_000 else 0)
+            late[i] = (now_ns() - due) * 1e-6
+            server.submit(req, arrival_ns=due)
+        server.drain()
+        for ticket in list(server._live):
+            server.wait(ticket)
+    finally:
+        if gc_was_on:
+            gc.enable()
+    st = server.stats()
+    if len(late):
+        st["driver_late_p99_ms"] = float(np.quantile(late, 0.99))
+        st["driver_late_max_ms"] = float(late.max())
+    return st

@@ -35,6 +35,7 @@ EXPORTED = ["wmh_opts_init", "wmh_create", "wmh_destroy", "wmh_set_bounds", "wmh
             "wmh_last_error", "wmh_status_string",
             "wmh_server_create", "wmh_server_submit", "wmh_server_poll", "wmh_server_wait",
             "wmh_server_drain", "wmh_server_stats", "wmh_server_reset_stats",
+            "wmh_server_reserve",
             "wmh_server_now_ns", "wmh_server_destroy",
             "wmh_host_alloc", "wmh_host_free"]
 

@@ -233,3 +233,32 @@ def test_requests_overlap_on_the_device(ctx):
         srv.reset_stats()
         st = srv.stats()
     assert st["completed"] == 0 and st["max_computing"] == 0 and st["p50_ms"] == 0
+
+
+def test_reserved_buffers(ctx, corpus):
+    """wmh_server_reserve sizes the slots for the largest request up front: requests up to it,
+    and a larger one after it (the slot then grows), all equal the oracle; a reservation beyond
+    the memory budget is refused."""
+    k, seed = 32, 9
+    ctx.set_bounds(corpus.m)
+    rng = np.random.Generator(np.random.PCG64(23))
+    row_lists = _rows(rng, corpus.n_rows, [300, 5, 299, 1, 120])
+    rp = corpus.row_ptr.astype(np.int64)
+    max_nnz = max(int((rp[r + 1] - rp[r]).sum()) for r in row_lists)
+    print(f"  serving with reserved buffers: 300 rows, {max_nnz} nonzeros", flush=True)
+    with serve.Server(ctx, k, seed=seed, slots=3, mode="batched", mem_budget=64 << 20) as srv:
+        srv.reserve(300, max_nnz)
+        reqs = serve.requests_from_corpus(corpus, row_lists, srv, pinned=True)
+        for r in reqs:
+            srv.submit(r)
+        for r in reqs:
+            srv.wait(r.ticket)
+        bigger = serve.requests_from_corpus(corpus, [np.arange(700)], srv)[0]
+        srv.submit(bigger)
+        srv.wait(bigger.ticket)
+        with pytest.raises(wmh.WMHError) as e:
+            srv.reserve(10 ** 6, 10 ** 8)
+        assert e.value.name == "WMH_E_NOMEM"
+    for rows, r in zip(row_lists, reqs):
+        assert np.array_equal(r.sig, _oracle_sig(corpus, rows, k, seed))
+    assert np.array_equal(bigger.sig, _oracle_sig(corpus, np.arange(700), k, seed))
