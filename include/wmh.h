@@ -155,6 +155,10 @@ typedef struct {
                                   identical.  Half the LDS of 32-bit rows and 4-byte stream
                                   entries; needs D * scale <= 65536 (D <= 32768 at R = 1,
                                   D <= 16384 at R = 2 or 4) and not the independent-rows walk */
+    uint32_t coarse_bits;      /* resolution B of the coarse codes, 1..15; 0 = 15.  Codes are
+                                  floor(y * 2^B / m); a tested step in the row's support ties
+                                  with probability below 2^-B, so fewer bits only make ties (and
+                                  their exact settling) frequent: the hashes stay identical */
 } wmh_opts;
 
 /* Fills *opts with the defaults listed above. */

@@ -14,6 +14,7 @@ namespace wmh {
 
 constexpr uint32_t kMaxDims = 1u << 26;
 constexpr uint32_t kMaxK = 1u << 24;
+constexpr uint32_t kCoarseCodeBits = 15;  // default (and largest) resolution of coarse codes
 constexpr uint64_t kStreamBudgetBytes = 1ull << 30;  // shared position stream, at most 1 GiB
 
 // What the content of the shared position stream depends on.
@@ -22,11 +23,12 @@ struct StreamKey {
     uint32_t k = 0, depth = 0, scale = 0;
     bool packed = false;
     uint64_t bounds_epoch = 0;
-    bool coarse = false;  // offsets replaced by their coarse codes
+    uint32_t coarse_bits = 0;  // offsets replaced by their coarse codes of this many bits
     bool operator==(const StreamKey &o) const
     {
         return seed == o.seed && k == o.k && depth == o.depth && scale == o.scale &&
-               packed == o.packed && bounds_epoch == o.bounds_epoch && coarse == o.coarse;
+               packed == o.packed && bounds_epoch == o.bounds_epoch &&
+               coarse_bits == o.coarse_bits;
     }
 };
 
@@ -36,7 +38,7 @@ struct GraphKey {
     uint64_t n_rows = 0, nnz = 0, seed = 0;
     uint32_t k = 0, R = 0, K = 0, J = 0, depth = 0, waves = 0, grid = 0, groups = 0;
     bool narrow = false, packed = false, independent_rows = false, ballot = false;
-    bool coarse = false;
+    uint32_t coarse_bits = 0;  // 0: exact dense rows
     const void *row_class = nullptr;  // row filter of a split walk (nullptr: every row)
     uint32_t keep = 0;
     uint64_t bounds_epoch = 0;
@@ -55,7 +57,7 @@ struct GraphKey {
                K == o.K &&
                J == o.J && depth == o.depth && waves == o.waves && grid == o.grid &&
                groups == o.groups &&
-               narrow == o.narrow && packed == o.packed && coarse == o.coarse &&
+               narrow == o.narrow && packed == o.packed && coarse_bits == o.coarse_bits &&
                independent_rows == o.independent_rows && ballot == o.ballot &&
                bounds_epoch == o.bounds_epoch;
     }

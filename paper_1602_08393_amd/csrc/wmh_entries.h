@@ -34,25 +34,27 @@ struct RowLayout {
     }
 };
 
-// Coarse 16-bit codes for pieces whose bounds do not fit 16 bits.  In a piece of size m >= 1,
-// q(y) = floor(y * 2^15 / m) is nondecreasing on 0 <= y <= m, so for an offset o < m and a value
-// x <= m: q(o) < q(x) gives o < x (green) and q(o) > q(x) gives o > x (red).  When q(o) = q(x),
-// o < x is possible only if x is not the smallest y with that code, i.e. when q(x - 1) = q(x),
-// i.e. when the remainder x * 2^15 - q(x) * m is at least 2^15.  A stream entry carries the odd
-// code v = 2 q(o) + 1 and the dense row the value code
-//   z = 0 (x = 0), 0xFFFF (x >= m), else 2 q(x) + [x * 2^15 - q(x) * m >= 2^15],
+// Coarse 16-bit codes for pieces whose bounds do not fit 16 bits.  With B code bits (B <= 15;
+// 15 by default), in a piece of size m >= 1, q(y) = floor(y * 2^B / m) is nondecreasing on
+// 0 <= y <= m, so for an offset o < m and a value x <= m: q(o) < q(x) gives o < x (green) and
+// q(o) > q(x) gives o > x (red).  When q(o) = q(x), o < x is possible only if x is not the
+// smallest y with that code, i.e. when q(x - 1) = q(x), i.e. when the remainder
+// x * 2^B - q(x) * m is at least 2^B.  A stream entry carries the odd code v = 2 q(o) + 1 and
+// the dense row the value code
+//   z = 0 (x = 0), 0xFFFF (x >= m), else 2 q(x) + [x * 2^B - q(x) * m >= 2^B],
 // so that v < z means green, v > z red, and v = z a tie, settled from the row's exact value and
-// the step's exact offset (the walks evaluate a window with a tie again with in-lane draws).  For m <= 2^15 the map q is one-to-one and no tie occurs; above, a
-// tested step in the row's support ties with probability below 2^-15.
+// the step's exact offset (the walks test a window with a tie again with in-lane draws).  For
+// m <= 2^B the map q is one-to-one and no tie occurs; above, a tested step in the row's support
+// ties with probability below 2^-B (fewer bits make ties frequent, which tests use).
 constexpr uint32_t kCoarseBits = 15u;
 
-// floor(y * 2^15 / m) and its remainder, for y <= m, 1 <= m: a float estimate (within one of
-// the quotient) made exact by the remainder.
-__device__ __forceinline__ uint32_t coarse_q(uint32_t y, uint32_t m, uint32_t *rem)
+// floor(y * 2^B / m) and its remainder, for y <= m, 1 <= m, B <= 15: a float estimate (within
+// one of the quotient) made exact by the remainder.
+__device__ __forceinline__ uint32_t coarse_q(uint32_t y, uint32_t m, uint32_t bits, uint32_t *rem)
 {
-    const float est = (float)y * (32768.0f * __builtin_amdgcn_rcpf((float)m));
+    const float est = (float)y * ((float)(1u << bits) * __builtin_amdgcn_rcpf((float)m));
     uint32_t q = (uint32_t)est;
-    int64_t r = (int64_t)((uint64_t)y << kCoarseBits) - (int64_t)q * (int64_t)m;
+    int64_t r = (int64_t)((uint64_t)y << bits) - (int64_t)q * (int64_t)m;
     while (r < 0) {
         --q;
         r += m;
@@ -65,21 +67,21 @@ __device__ __forceinline__ uint32_t coarse_q(uint32_t y, uint32_t m, uint32_t *r
     return q;
 }
 
-// The code of an offset o < m of a step (odd, at most 0xFFFF).
-__device__ __forceinline__ uint32_t coarse_offset_code(uint32_t o, uint32_t m)
+// The code of an offset o < m of a step (odd, at most 2^(B+1) - 1).
+__device__ __forceinline__ uint32_t coarse_offset_code(uint32_t o, uint32_t m, uint32_t bits)
 {
     uint32_t rem;
-    return 2u * coarse_q(o, m, &rem) + 1u;
+    return 2u * coarse_q(o, m, bits, &rem) + 1u;
 }
 
 // The code of a row's value x in a piece of size m.
-__device__ __forceinline__ uint32_t coarse_value_code(uint32_t x, uint32_t m)
+__device__ __forceinline__ uint32_t coarse_value_code(uint32_t x, uint32_t m, uint32_t bits)
 {
     if (x == 0) return 0u;
     if (x >= m) return 0xFFFFu;
     uint32_t rem;
-    const uint32_t q = coarse_q(x, m, &rem);
-    return 2u * q + (rem >= (1u << kCoarseBits) ? 1u : 0u);
+    const uint32_t q = coarse_q(x, m, bits, &rem);
+    return 2u * q + (rem >= (1u << bits) ? 1u : 0u);
 }
 
 // The exact value of component c in CSR row `row` (columns strictly increasing), 0 if absent.

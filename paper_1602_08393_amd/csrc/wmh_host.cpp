@@ -141,6 +141,8 @@ static bool plan_rows(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, con
     const uint64_t min_green = stats.known ? stats.min_green : ~0ull;
     BatchedPlan p{};
     p.coarse = coarse;
+    if (o.coarse_bits > kCoarseCodeBits) return false;
+    p.coarse_bits = o.coarse_bits ? o.coarse_bits : kCoarseCodeBits;
     p.narrow = coarse || ctx->max_bound <= 0xFFFFu;
     p.waves_per_block = o.waves_per_block ? std::min<uint32_t>(o.waves_per_block, 16u) : 8u;
     p.hashes_per_tile = o.hashes_per_tile ? std::min(o.hashes_per_tile, k) : std::min(k, 1024u);
@@ -791,7 +793,7 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         key.K = pl.steps_per_lane;
         key.waves = pl.waves_per_block; key.grid = grid; key.narrow = pl.narrow;
         key.packed = pl.packed;
-        key.coarse = pl.coarse;
+        key.coarse_bits = pl.coarse ? pl.coarse_bits : 0u;
         key.independent_rows = pl.independent_rows;
         key.ballot = pl.ballot;
         key.groups = pl.hash_groups;
@@ -804,12 +806,13 @@ wmh_status wmh_hash(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
         bool stream_built = false;
         if (pl.stream_depth) {
             const StreamKey skey{seed, k, pl.stream_depth, pl.scale(), pl.packed,
-                                 ctx->bounds_epoch, pl.coarse};
+                                 ctx->bounds_epoch, pl.coarse ? pl.coarse_bits : 0u};
             if (!(ctx->stream_valid && ctx->stream_key == skey)) {
                 ctx->stream_valid = false;
                 if (profile && !o.use_graph) WMH_HIP(ctx, hipEventRecord(ctx->ev[0], s));
                 WMH_HIP(ctx, launch_stream_build(b, seed, k, pl.stream_depth, pl.packed,
-                                                 pl.scale(), pl.coarse, ctx->d_stream, s));
+                                                 pl.scale(), pl.coarse ? pl.coarse_bits : 0u,
+                                                 ctx->d_stream, s));
                 WMH_HIP(ctx, hipEventRecord(ctx->stream_ready, s));
                 ctx->stream_key = skey;
                 ctx->stream_valid = true;
@@ -942,11 +945,13 @@ wmh_status wmh_last_plan(const wmh_ctx *ctx, wmh_opts *plan)
     plan->waves_per_block = ctx->last_plan.waves_per_block;
     plan->hash_groups = ctx->last_plan.hash_groups;
     plan->values = ctx->last_plan.rows_per_block ? (ctx->last_plan.coarse ? 2 : 1) : 0;
+    plan->coarse_bits = ctx->last_plan.coarse ? ctx->last_plan.coarse_bits : 0;
     if (ctx->last_mode == WMH_MODE_INDEXED) {
         plan->rows_per_block = plan->hashes_per_tile = plan->stream_depth = 0;
         plan->steps_per_lane = 0;
         plan->hash_groups = 0;
         plan->values = 0;
+        plan->coarse_bits = 0;
         plan->waves_per_block = ctx->last_index_plan.waves;
         plan->index_batch = ctx->last_index_plan.batch;
         plan->index_claim = ctx->last_index_plan.claim;

@@ -81,6 +81,7 @@ struct BatchedPlan {
     bool packed;               // 4-byte stream entries
     bool coarse = false;       // rows hold coarse value codes, the stream coarse offset codes,
                                // and ties are settled exactly (shared-window and ballot walks)
+    uint32_t coarse_bits = 15; // resolution of the coarse codes (1..15)
     bool independent_rows;     // each row of a block walks its own hash ids (R = 4 only)
     bool ballot;               // one row per block, first green step from the window's ballot
                                // (R = 1, K = 1 only)
@@ -117,9 +118,9 @@ hipError_t launch_draws(const Bounds &b, uint64_t seed, uint32_t j0, uint32_t n_
                         uint32_t depth, uint64_t *pos, uint32_t *comp, uint64_t *off,
                         hipStream_t stream);
 
-// coarse: entries carry the offset's coarse code (needs packed)
+// coarse_bits > 0: entries carry the offset's coarse code of that many bits (needs packed)
 hipError_t launch_stream_build(const Bounds &b, uint64_t seed, uint32_t k, uint32_t depth,
-                               bool packed, uint32_t scale, bool coarse, void *entries,
+                               bool packed, uint32_t scale, uint32_t coarse_bits, void *entries,
                                hipStream_t stream);
 
 // Dynamic LDS a walk's workgroup may take: the CU's 160 KiB less room for the kernels' static

@@ -343,7 +343,8 @@ __global__ __launch_bounds__(256) void plain_kernel(Bounds b, Rows rows, uint64_
 template <bool kPacked, bool kCoarse>
 __global__ __launch_bounds__(256) void stream_kernel(Bounds b, uint64_t seed, uint32_t k,
                                                      uint32_t depth, uint32_t scale,
-                                                     void *__restrict__ entries)
+                                                     void *__restrict__ entries,
+                                                     uint32_t coarse_bits)
 {
     static_assert(kPacked || !kCoarse, "coarse codes come in packed entries");
     const uint64_t pairs = depth >> 1;
@@ -359,8 +360,8 @@ __global__ __launch_bounds__(256) void stream_kernel(Bounds b, uint64_t seed, ui
     if (kPacked) {
         uint32_t v0 = (uint32_t)off0, v1 = (uint32_t)off1;
         if (kCoarse) {
-            v0 = coarse_offset_code(v0, b.bound[c0]);
-            v1 = coarse_offset_code(v1, b.bound[c1]);
+            v0 = coarse_offset_code(v0, b.bound[c0], coarse_bits);
+            v1 = coarse_offset_code(v1, b.bound[c1], coarse_bits);
         }
         uint32_t *e = reinterpret_cast<uint32_t *>(entries) + at;
         *reinterpret_cast<uint2 *>(e) = make_uint2((v0 << 16) | (c0 * scale),
@@ -685,16 +686,19 @@ hipError_t launch_draws(const Bounds &b, uint64_t seed, uint32_t j0, uint32_t n_
 }
 
 hipError_t launch_stream_build(const Bounds &b, uint64_t seed, uint32_t k, uint32_t depth,
-                               bool packed, uint32_t scale, bool coarse, void *entries,
+                               bool packed, uint32_t scale, uint32_t coarse_bits, void *entries,
                                hipStream_t stream)
 {
     if (depth == 0 || k == 0) return hipSuccess;
-    if (coarse && !packed) return hipErrorInvalidValue;
+    if (coarse_bits > kCoarseBits || (coarse_bits && !packed)) return hipErrorInvalidValue;
     const uint64_t threads = (uint64_t)k * (depth / 2);
     const uint32_t grid = (uint32_t)((threads + 255) / 256);
-    if (coarse) stream_kernel<true, true><<<grid, 256, 0, stream>>>(b, seed, k, depth, scale, entries);
-    else if (packed) stream_kernel<true, false><<<grid, 256, 0, stream>>>(b, seed, k, depth, scale, entries);
-    else stream_kernel<false, false><<<grid, 256, 0, stream>>>(b, seed, k, depth, scale, entries);
+    if (coarse_bits)
+        stream_kernel<true, true><<<grid, 256, 0, stream>>>(b, seed, k, depth, scale, entries, coarse_bits);
+    else if (packed)
+        stream_kernel<true, false><<<grid, 256, 0, stream>>>(b, seed, k, depth, scale, entries, 0u);
+    else
+        stream_kernel<false, false><<<grid, 256, 0, stream>>>(b, seed, k, depth, scale, entries, 0u);
     return hipGetLastError();
 }
 
@@ -747,7 +751,8 @@ hipError_t launch_batched(const Bounds &b, const Rows &rows, uint32_t k, uint64_
     if (batched_lds_bytes(b.dims, plan) > kMaxDynamicLds) return hipErrorInvalidValue;
     if (plan.packed && !plan.narrow) return hipErrorInvalidValue;
     // coarse codes: 16-bit rows, packed entries, the shared-window or ballot walk
-    if (plan.coarse && (!plan.narrow || !plan.packed || plan.independent_rows))
+    if (plan.coarse && (!plan.narrow || !plan.packed || plan.independent_rows ||
+                        plan.coarse_bits == 0 || plan.coarse_bits > kCoarseBits))
         return hipErrorInvalidValue;
     // the shared walk reads whole three-window cycles of the stream (plus one spare cycle)
     if (plan.stream_depth % plan.cycle() != 0 || plan.stream_depth >= kCap) return hipErrorInvalidValue;

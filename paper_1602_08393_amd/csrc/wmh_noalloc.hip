@@ -149,7 +149,8 @@ extern "C" wmh_status wmh_hash_noalloc(wmh_ctx *ctx, const uint64_t *row_ptr, co
     ctx->profiled = false;
     if (plan.stream_depth)
         WMH_NA_HIP(ctx, launch_stream_build(b, seed, k, plan.stream_depth, plan.packed,
-                                            plan.scale(), plan.coarse, entries, s));
+                                            plan.scale(), plan.coarse ? plan.coarse_bits : 0u,
+                                            entries, s));
     WMH_NA_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(counter), 0u,
                                     2 * kMaxHashGroups, s));
     if (profile) WMH_NA_HIP(ctx, hipEventRecord(ctx->ev[1], s));

@@ -401,8 +401,8 @@ wmh_status wmh_server_create(wmh_ctx *ctx, const wmh_server_config *cfg_in, wmh_
         e = hipMalloc(&srv->d_stream, bytes);
         if (e == hipSuccess)
             e = launch_stream_build(bounds_view(ctx), cfg.seed, cfg.k, srv->plan.stream_depth,
-                                    srv->plan.packed, srv->plan.scale(), srv->plan.coarse,
-                                    srv->d_stream,
+                                    srv->plan.packed, srv->plan.scale(),
+                                    srv->plan.coarse ? srv->plan.coarse_bits : 0u, srv->d_stream,
                                     ctx->own_stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->own_stream);
     }

@@ -84,11 +84,17 @@ __host__ __device__ constexpr uint64_t segment_tops()
     return m;
 }
 
+// What coarse codes are made from: the bounds m and the code bits.
+struct Codes {
+    const uint32_t *bound;
+    uint32_t bits;
+};
+
 // The LDS value of a row's nonzero x at component c: x itself, or its coarse code.
 template <typename XT, bool kCoarse>
-__device__ __forceinline__ XT lds_value(uint32_t x, uint32_t c, const uint32_t *bound)
+__device__ __forceinline__ XT lds_value(uint32_t x, uint32_t c, const Codes &codes)
 {
-    if constexpr (kCoarse) return (XT)coarse_value_code(x, bound[c]);
+    if constexpr (kCoarse) return (XT)coarse_value_code(x, codes.bound[c], codes.bits);
     else return (XT)x;
 }
 
@@ -96,12 +102,12 @@ __device__ __forceinline__ XT lds_value(uint32_t x, uint32_t c, const uint32_t *
 // lv of CSR row `row`: o < x, with x itself in LDS, or from the coarse codes (a tie reads the
 // row's exact value).
 template <bool kCoarse>
-__device__ __forceinline__ bool lane_green(uint64_t o, uint32_t lv, uint32_t c, const Bounds &b,
+__device__ __forceinline__ bool lane_green(uint64_t o, uint32_t lv, uint32_t c, const Codes &codes,
                                            const Rows &rows, uint64_t row)
 {
     if constexpr (kCoarse) {
         if (lv == 0) return false;
-        const uint32_t v = coarse_offset_code((uint32_t)o, b.bound[c]);
+        const uint32_t v = coarse_offset_code((uint32_t)o, codes.bound[c], codes.bits);
         if (v != lv) return v < lv;
         return o < (uint64_t)csr_value(rows.row_ptr, rows.col, rows.val, row, c);
     } else {
@@ -114,7 +120,7 @@ __device__ __forceinline__ bool lane_green(uint64_t o, uint32_t lv, uint32_t c, 
 // r of `skip` stay zero.  Called by the whole workgroup.
 template <typename XT, int R, bool kCoarse>
 __device__ __forceinline__ void stage_block(unsigned char *smem, const Rows &rows, uint64_t row0,
-                                            uint32_t n_here, uint32_t D, const uint32_t *bound,
+                                            uint32_t n_here, uint32_t D, const Codes &codes,
                                             uint32_t *nonempty, uint32_t skip = 0)
 {
     using Layout = RowLayout<XT, R>;
@@ -130,7 +136,7 @@ __device__ __forceinline__ void stage_block(unsigned char *smem, const Rows &row
         for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
             const uint32_t v = rows.val[e];
             const uint32_t c = rows.col[e];
-            if (c < D) *Layout::at(smem, c, r, D) = lds_value<XT, kCoarse>(v, c, bound);
+            if (c < D) *Layout::at(smem, c, r, D) = lds_value<XT, kCoarse>(v, c, codes);
             if (v) mine |= 1u << r;
         }
     }
@@ -146,7 +152,7 @@ __device__ __forceinline__ void stage_block(unsigned char *smem, const Rows &row
 // the new row's entry range.
 template <typename XT, bool kCoarse>
 __device__ __forceinline__ void restage_row(unsigned char *smem, const Rows &rows, uint64_t row,
-                                            uint32_t D, const uint32_t *bound, bool &have_row,
+                                            uint32_t D, const Codes &codes, bool &have_row,
                                             uint64_t &prev_lo, uint64_t &prev_hi,
                                             uint32_t *nonempty)
 {
@@ -168,7 +174,7 @@ __device__ __forceinline__ void restage_row(unsigned char *smem, const Rows &row
     for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
         const uint32_t v = rows.val[e];
         const uint32_t c = rows.col[e];
-        if (c < D) x[c] = lds_value<XT, kCoarse>(v, c, bound);
+        if (c < D) x[c] = lds_value<XT, kCoarse>(v, c, codes);
         if (v) mine = 1u;
     }
     if (mine) atomicOr(nonempty, mine);
@@ -206,8 +212,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
                                                        uint64_t seed, uint16_t *__restrict__ sig,
                                                        uint32_t hashes_per_tile, uint32_t depth,
                                                        const void *entries,
-                                                       unsigned long long *tile_counter)
+                                                       unsigned long long *tile_counter,
+                                                       uint32_t coarse_bits)
 {
+    const Codes codes{b.bound, coarse_bits};
     // Lane layout of one window: lane l serves row r = l / L (L = 64 / R lanes per row) and
     // the K consecutive steps base + g*K + 1 .. base + g*K + K, g = l mod L; the 64 lanes
     // cover steps base + 1 .. base + kWin of all R rows, kWin = L * K.
@@ -258,7 +266,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
         }
 
         if (blk != staged) {
-            stage_block<XT, R, kCoarse>(smem, rows, row0, n_here, D, b.bound, &nonempty, skip);
+            stage_block<XT, R, kCoarse>(smem, rows, row0, n_here, D, codes, &nonempty, skip);
             staged = blk;
         }
         // Wave-uniform values are read into scalar registers so every branch on them is a
@@ -325,7 +333,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
                     uint64_t o64;
                     const uint32_t comp = component_of(p, b.prefix, b.bucket, b.shift, &o64);
                     const uint32_t lv = *reinterpret_cast<const XT *>(smem + (size_t)comp * kScale + row_byte);
-                    c = lane_green<kCoarse>(o64, lv, comp, b, rows, row0 + my_row) ? my_grp * K + q + 1u : c;
+                    c = lane_green<kCoarse>(o64, lv, comp, codes, rows, row0 + my_row) ? my_grp * K + q + 1u : c;
                 }
                 lane_h = min(lane_h, base + c);
             };
@@ -407,8 +415,9 @@ template <typename XT, bool kPacked, bool kCoarse>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void ballot_kernel(
     Bounds b, Rows rows, uint32_t k, uint64_t seed, uint16_t *__restrict__ sig,
     uint32_t hashes_per_tile, uint32_t depth, const void *entries, unsigned long long *tile_counter,
-    uint32_t groups)
+    uint32_t groups, uint32_t coarse_bits)
 {
+    const Codes codes{b.bound, coarse_bits};
     constexpr uint32_t kWords = EntryRun<1, kPacked>::kWordsPerEntry;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned long long tile_row;
@@ -461,7 +470,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             continue;
         }
         if (row != staged) {
-            restage_row<XT, kCoarse>(smem, rows, row, D, b.bound, have_row, staged_lo, staged_hi,
+            restage_row<XT, kCoarse>(smem, rows, row, D, codes, have_row, staged_lo, staged_hi,
                                      &nonempty);
             staged = row;
         }
@@ -512,7 +521,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                 const uint32_t comp = component_of(p, b.prefix, b.bucket, b.shift, &o64);
                 const uint32_t lv = *reinterpret_cast<const XT *>(smem + (size_t)comp * sizeof(XT));
                 const uint64_t green =
-                    __builtin_amdgcn_ballot_w64(lane_green<kCoarse>(o64, lv, comp, b, rows, row));
+                    __builtin_amdgcn_ballot_w64(lane_green<kCoarse>(o64, lv, comp, codes, rows, row));
                 if (green) return min(base + (uint32_t)__builtin_ctzll(green) + 1u, kCap);
             }
             return kCap;
@@ -590,7 +599,8 @@ hipError_t launch_batched_t(const Bounds &b, const Rows &rows, uint32_t k, uint6
     const hipError_t e = configure_batched<XT, R, K, kPacked, kCoarse>();
     if (e != hipSuccess) return e;
     batched_kernel<XT, R, K, kPacked, kCoarse><<<grid, plan.waves_per_block * kWave, lds, stream>>>(
-        b, rows, k, seed, sig, plan.hashes_per_tile, plan.stream_depth, entries, tile_counter);
+        b, rows, k, seed, sig, plan.hashes_per_tile, plan.stream_depth, entries, tile_counter,
+        plan.coarse_bits);
     return hipGetLastError();
 }
 
@@ -624,7 +634,7 @@ hipError_t launch_ballot_t(const Bounds &b, const Rows &rows, uint32_t k, uint64
     if (e != hipSuccess) return e;
     ballot_kernel<XT, kPacked, kCoarse><<<grid, plan.waves_per_block * kWave, lds, stream>>>(
         b, rows, k, seed, sig, plan.hashes_per_tile, plan.stream_depth, entries, tile_counter,
-        plan.hash_groups);
+        plan.hash_groups, plan.coarse_bits);
     return hipGetLastError();
 }
 

@@ -48,7 +48,8 @@ class WmhOpts(ctypes.Structure):
                 ("waves_per_block", ctypes.c_uint32), ("profile", ctypes.c_int32),
                 ("walk", ctypes.c_int32), ("steps_per_lane", ctypes.c_uint32),
                 ("index_batch", ctypes.c_uint32), ("index_claim", ctypes.c_uint32),
-                ("hash_groups", ctypes.c_uint32), ("values", ctypes.c_int32)]
+                ("hash_groups", ctypes.c_uint32), ("values", ctypes.c_int32),
+                ("coarse_bits", ctypes.c_uint32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -363,7 +364,7 @@ class Context:
     def make_opts(mode="auto", batch_rows=0, validate=True, use_graph=True, sync=True,
                   rows_per_block=0, hashes_per_tile=0, stream_depth=0, waves_per_block=0,
                   profile=False, walk=0, steps_per_lane=0, index_batch=0,
-                  index_claim=0, hash_groups=0, values=0) -> WmhOpts:
+                  index_claim=0, hash_groups=0, values=0, coarse_bits=0) -> WmhOpts:
         o = WmhOpts()
         load().wmh_opts_init(ctypes.byref(o))
         o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
@@ -383,6 +384,7 @@ class Context:
         o.index_claim = {"counter": 1, "stride": 2}.get(index_claim, index_claim)
         o.hash_groups = hash_groups
         o.values = VALUES[values] if isinstance(values, str) else int(values)
+        o.coarse_bits = coarse_bits
         return o
 
     def last_kernel_ms(self) -> tuple[float, float]:
@@ -409,7 +411,8 @@ class Context:
                 "walk": {v: k for k, v in WALKS.items()}.get(o.walk, o.walk),
                 "steps_per_lane": o.steps_per_lane, "index_batch": o.index_batch,
                 "index_claim": o.index_claim, "hash_groups": o.hash_groups,
-                "values": {1: "exact", 2: "coarse"}.get(o.values)}
+                "values": {1: "exact", 2: "coarse"}.get(o.values),
+                "coarse_bits": o.coarse_bits}
 
     def tune(self, rows: DeviceRows, k: int, seed: int = 0, reps: int = 3, stream=None) -> dict:
         """Autotunes the batched tile plan on these rows (see wmh_tune); returns the result and

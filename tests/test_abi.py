@@ -46,7 +46,8 @@ def test_opts_defaults(lib):
     assert (o.mode, o.batch_rows, o.validate, o.use_graph, o.sync) == (0, 8192, 1, 1, 1)
     assert (o.rows_per_block, o.hashes_per_tile, o.stream_depth, o.waves_per_block) == (0, 0, 0, 0)
     assert o.values == 0
-    assert ctypes.sizeof(wmh.WmhOpts) == 4 * 16
+    assert o.coarse_bits == 0
+    assert ctypes.sizeof(wmh.WmhOpts) == 4 * 17
 
 
 def test_status_strings(lib):

@@ -165,6 +165,14 @@ BATCHED_PLANS = [
     dict(values="coarse", walk="ballot"), dict(values="coarse", walk="ballot", stream_depth=64),
     dict(values="coarse", walk="ballot", stream_depth=None, hashes_per_tile=9),
     dict(values="exact", rows_per_block=2),
+    # codes of 1 to 4 bits: most tested steps in a row's support tie and are settled exactly
+    # (in-lane draws, the row's CSR value), in the stream windows and past the stream
+    dict(values="coarse", coarse_bits=1, rows_per_block=4),
+    dict(values="coarse", coarse_bits=2, rows_per_block=2, steps_per_lane=4),
+    dict(values="coarse", coarse_bits=3, rows_per_block=1, steps_per_lane=4, stream_depth=256),
+    dict(values="coarse", coarse_bits=1, walk="ballot"),
+    dict(values="coarse", coarse_bits=4, walk="ballot", stream_depth=64, hashes_per_tile=5),
+    dict(values="coarse", coarse_bits=2, rows_per_block=4, stream_depth=None),
 ]
 
 CASES = {
@@ -177,12 +185,12 @@ CASES = {
                       13),
     "sparse-slow": (dict(seed=4, n_rows=19, D=2000, density=0.005, max_val=500,
                          bound_slack=60000), 40, 14),
-    # bounds a little above 2^16: each coarse code covers two to four integers, so many tested
-    # steps tie and are settled exactly
-    "coarse-ties": (dict(seed=5, n_rows=45, D=400, density=0.1, max_val=70000,
-                         bound_slack=60000, empty_rows=2), 60, 15),
-    "coarse-ties-dense": (dict(seed=6, n_rows=23, D=5, density=0.8, max_val=131000,
-                               bound_slack=3), 70, 16),
+    # bounds a little above 2^16, where the default coarse codes cover two to four integers
+    # each (ties stay rare: the plans with few code bits below make them frequent)
+    "coarse-near-16-bits": (dict(seed=5, n_rows=45, D=400, density=0.1, max_val=70000,
+                                 bound_slack=60000, empty_rows=2), 60, 15),
+    "coarse-dense-few-dims": (dict(seed=6, n_rows=23, D=5, density=0.8, max_val=131000,
+                                   bound_slack=3), 70, 16),
 }
 
 
