@@ -483,20 +483,20 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         const uint32_t j1 = min(k, j0 + hashes_per_tile);
 
         // ballot of the lanes whose step is green in the window the run holds; with coarse
-        // codes, *tied tells whether a lane below the lowest green one tied (that window is then
-        // walked on with in-lane draws, which are exact)
-        auto stream_ballot = [&](const EntryRun<1, kPacked> &run, bool *tied) {
+        // codes *tie is the ballot of the lanes whose codes tie (0 otherwise)
+        auto stream_ballot = [&](const EntryRun<1, kPacked> &run, uint64_t *tie) {
             uint32_t lds, off;
             run.get(0, (uint32_t)sizeof(XT), &lds, &off);
             const uint32_t xv = *reinterpret_cast<const XT *>(smem + lds);
-            const uint64_t green = __builtin_amdgcn_ballot_w64(off < xv);
-            if constexpr (kCoarse) {
-                const uint64_t below = green ? (green & (0ull - green)) - 1ull : ~0ull;
-                *tied = (__builtin_amdgcn_ballot_w64(off == xv) & below) != 0;
-            } else {
-                *tied = false;
-            }
-            return green;
+            if constexpr (kCoarse) *tie = __builtin_amdgcn_ballot_w64(off == xv);
+            else *tie = 0;
+            return __builtin_amdgcn_ballot_w64(off < xv);
+        };
+        // whether a tie lies below the lowest green lane (the window is then walked on with
+        // in-lane draws, which are exact); tested only when the window has a green or tied lane
+        auto tie_first = [](uint64_t green, uint64_t tie) {
+            const uint64_t below = green ? (green & (0ull - green)) - 1ull : ~0ull;
+            return (tie & below) != 0;
         };
         // each prefetch stays where it is issued (see the shared-window walk)
         auto fetch = [&](uint32_t j, uint32_t at) {
@@ -529,19 +529,27 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         // hash id j from its three requested windows, then the stream, then in-lane draws
         auto walk_id = [&](uint32_t j, EntryRun<1, kPacked> &e0, EntryRun<1, kPacked> &e1,
                            EntryRun<1, kPacked> &e2) {
-            bool tied = false;
+            uint64_t tie = 0;
             for (uint32_t base = 0; base < depth; base += 3 * kWave) {
-                uint64_t green = stream_ballot(e0, &tied);
-                if (tied) return store(j, lane_walk(j, base));
-                if (green) return store(j, base + (uint32_t)__builtin_ctzll(green) + 1u);
+                uint64_t green = stream_ballot(e0, &tie);
+                if (green | tie) {
+                    if (tie && tie_first(green, tie)) return store(j, lane_walk(j, base));
+                    if (green) return store(j, base + (uint32_t)__builtin_ctzll(green) + 1u);
+                }
                 e0 = fetch(j, base + 3 * kWave);
-                green = stream_ballot(e1, &tied);
-                if (tied) return store(j, lane_walk(j, base + kWave));
-                if (green) return store(j, base + kWave + (uint32_t)__builtin_ctzll(green) + 1u);
+                green = stream_ballot(e1, &tie);
+                if (green | tie) {
+                    if (tie && tie_first(green, tie)) return store(j, lane_walk(j, base + kWave));
+                    if (green) return store(j, base + kWave + (uint32_t)__builtin_ctzll(green) + 1u);
+                }
                 e1 = fetch(j, base + 4 * kWave);
-                green = stream_ballot(e2, &tied);
-                if (tied) return store(j, lane_walk(j, base + 2 * kWave));
-                if (green) return store(j, base + 2 * kWave + (uint32_t)__builtin_ctzll(green) + 1u);
+                green = stream_ballot(e2, &tie);
+                if (green | tie) {
+                    if (tie && tie_first(green, tie))
+                        return store(j, lane_walk(j, base + 2 * kWave));
+                    if (green)
+                        return store(j, base + 2 * kWave + (uint32_t)__builtin_ctzll(green) + 1u);
+                }
                 e2 = fetch(j, base + 5 * kWave);
             }
             store(j, lane_walk(j, depth));  // past the stream (rare)
