@@ -118,7 +118,8 @@ typedef struct {
     uint32_t waves_per_block;  /* wavefronts per workgroup (1..16) */
     int32_t profile;           /* 1: time the walk kernels with HIP events on the launch stream
                                   (read back with wmh_last_kernel_ms) */
-    int32_t walk;              /* batched mode: 0 = planner / autotuner choice; 1 = shared windows
+    int32_t walk;              /* batched mode: 0 = planner / autotuner choice (the planner takes
+                                  the ballot walk when its blocks hold one row); 1 = shared windows
                                   (every window is tested for all R rows of a block until the
                                   block's last row is green); 2 = independent rows (each row of a
                                   block walks its own hash ids; needs R = 4); 3 = ballot walk

@@ -150,24 +150,28 @@ static bool plan_rows(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, con
     const size_t lds_target = 48 * 1024;  // keep several workgroups resident per CU
     if (o.walk < 0 || o.walk > 3) return false;
     uint32_t R = o.rows_per_block;
+    int32_t walk = o.walk;
     if (R == 0) {
         R = 4;
         while (R > 1 && (size_t)ctx->dims * R * elem > lds_target) R >>= 1;
-        if (o.walk == 2) R = 4;
-        if (o.walk == 3) R = 1;
+        if (walk == 2) R = 4;
+        if (walk == 3) R = 1;
+        // one row per block: the ballot walk (measured faster than one-row shared windows on
+        // every workload here)
+        if (walk == 0 && R == 1 && !o.steps_per_lane) walk = 3;
     }
     if (R != 1 && R != 2 && R != 4 && R != 8 && R != 16) return false;
-    if (o.walk == 2 && R != 4) return false;
-    if (o.walk == 3 && R != 1) return false;
+    if (walk == 2 && R != 4) return false;
+    if (walk == 3 && R != 1) return false;
     // steps per lane: R (a window of 64 steps per row), or 4 for R < 4 (windows of 256 or 128)
     const uint32_t K = o.steps_per_lane ? o.steps_per_lane : R;
     if (K != R && !(K == 4 && R < 4)) return false;
-    if (o.walk == 2 && K != 4) return false;
-    if (o.walk == 3 && K != 1) return false;
+    if (walk == 2 && K != 4) return false;
+    if (walk == 3 && K != 1) return false;
     p.rows_per_block = R;
     p.steps_per_lane = K;
-    p.independent_rows = o.walk == 2;
-    p.ballot = o.walk == 3;
+    p.independent_rows = walk == 2;
+    p.ballot = walk == 3;
     // hash groups (ballot walk): G blocks of ceil(k / G) ids, G lowered until none is empty
     if (o.hash_groups > kMaxHashGroups || (o.hash_groups > 1 && !p.ballot)) return false;
     uint32_t G = o.hash_groups ? o.hash_groups : 1;

@@ -188,14 +188,15 @@ wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
     wmh_tune_result res{};
     float default_ms = 0.f;
     const int32_t def_values = def.coarse ? 2 : 1;
-    st = time_plan(def.rows_per_block, def.hashes_per_tile, def.waves_per_block, 1,
+    const int32_t def_walk = def.ballot ? 3 : def.independent_rows ? 2 : 1;
+    st = time_plan(def.rows_per_block, def.hashes_per_tile, def.waves_per_block, def_walk,
                    def.steps_per_lane, 1, def_values, &default_ms);
     TuneEntry best;
     best.key = tune_key(ctx, k, stats);
     best.R = def.rows_per_block;
     best.J = def.hashes_per_tile;
     best.W = def.waves_per_block;
-    best.walk = 1;
+    best.walk = def_walk;
     best.K = def.steps_per_lane;
     best.V = def_values;
     best.ms = default_ms;
@@ -225,9 +226,9 @@ wmh_status wmh_tune(wmh_ctx *ctx, const uint64_t *row_ptr, const uint32_t *col,
                 for (uint32_t W : {4u, 8u, 16u}) {
                     for (uint32_t J : G == 1 ? Js : std::vector<uint32_t>{(k + G - 1) / G}) {
                         if (st != WMH_OK) break;
-                        if (sh.walk == 1 && sh.R == def.rows_per_block &&
+                        if (sh.walk == def_walk && sh.R == def.rows_per_block &&
                             sh.K == def.steps_per_lane && J == def.hashes_per_tile &&
-                            W == def.waves_per_block && V == def_values)
+                            W == def.waves_per_block && V == def_values && G == 1)
                             continue;
                         float ms = -1.f;
                         st = time_plan(sh.R, J, W, sh.walk, sh.K, G, V, &ms);
