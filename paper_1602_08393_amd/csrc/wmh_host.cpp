@@ -337,7 +337,12 @@ wmh_status ensure_index(wmh_ctx *ctx, OwnedIndex *ix, uint64_t seed, uint32_t k,
     if (!ix->used) e = hipEventCreateWithFlags(&ix->used, hipEventDisableTiming);
     else e = hipStreamWaitEvent(stream, ix->used, 0);  // earlier readers, on any stream
     if (e != hipSuccess) return device_fail(err, e, "index event");
-    const uint64_t n = index_entry_count(k);
+    // lists start on 128-byte lines when the padding fits the budget
+    const uint32_t align =
+        index_padded_count(k, ctx->dims, kIndexListAlign) * sizeof(uint64_t) <= kIndexBudgetBytes
+            ? kIndexListAlign
+            : 1u;
+    const uint64_t n = index_padded_count(k, ctx->dims, align);
     if (n > ix->cap_entries) {
         for (uint64_t **p : {&ix->buf.entries, &ix->buf.by_step}) {
             if (*p) (void)hipFree(*p);
@@ -364,6 +369,7 @@ wmh_status ensure_index(wmh_ctx *ctx, OwnedIndex *ix, uint64_t seed, uint32_t k,
         if (e != hipSuccess) return device_fail(err, e, "index offsets");
         ix->cap_dims = ctx->dims;
     }
+    ix->buf.align = align;
     e = launch_index_build(bounds_view(ctx), seed, k, ix->buf, stream);
     if (e != hipSuccess) return device_fail(err, e, "index build");
     ix->valid = true;

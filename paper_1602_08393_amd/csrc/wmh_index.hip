@@ -12,9 +12,11 @@
 // k * min(1/s, 65535), which wins by orders of magnitude when s is small (Theorem 2 gives the
 // walk's 1/s; Sec. 4 discusses the small-s regime).  Both orders compute the same values.
 //
-// Build, once per (bounds, seed, k): count draws per component, exclusive scan, draw again and
-// scatter the keys, sort each chunk (a wavefront per list of at most 64 keys, a workgroup in
-// LDS for longer chunks).  The order in which draws land in a list varies between builds, so
+// Build, once per (bounds, seed, k): count draws per component, round each count up to whole
+// 128-byte lines of keys, exclusive scan, fill the buffer with ~0 keys (red in both orders),
+// draw again and scatter the keys, sort each chunk (a wavefront per list of at most 64 keys, a
+// workgroup in LDS for longer chunks; the ~0 pads sort last).  A row reads each of its lists
+// from the list's start, so aligned starts save the partly used first line of every read.  The order in which draws land in a list varies between builds, so
 // which keys share a chunk of a list longer than kChunk may vary too: that changes the cost of
 // reading the list, never a hash value.
 #include <hip/hip_runtime.h>
@@ -121,6 +123,14 @@ __global__ __launch_bounds__(kScanBlock) void scan_sums_kernel(uint32_t *__restr
         if (threadIdx.x == kScanBlock - 1) carry += s[threadIdx.x];
         __syncthreads();
     }
+}
+
+// counts[i] rounded up to a multiple of align (a power of two), for i < n.
+__global__ __launch_bounds__(256) void round_counts_kernel(uint32_t *__restrict__ counts,
+                                                           uint64_t n, uint32_t align)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) counts[i] = (counts[i] + align - 1u) & ~(align - 1u);
 }
 
 // offsets[i] += block carry; cursor[i] = offsets[i] (the scatter pass's claim counters).
@@ -446,10 +456,21 @@ hipError_t launch_index_build(const Bounds &b, uint64_t seed, uint32_t k, const 
     const uint32_t n_blocks = (uint32_t)((n_scan + kScanBlock - 1) / kScanBlock);
     hipError_t e = launch_fill_u32(ix.cursor, 0u, n_scan, stream);
     if (e != hipSuccess) return e;
+    const uint32_t align = ix.align;
+    if (align != 1 && align != kIndexListAlign) return hipErrorInvalidValue;
     const uint64_t threads = (uint64_t)kIndexPairs * k;
     const uint32_t grid = (uint32_t)((threads + 255) / 256);
     index_draw_kernel<false><<<grid, 256, 0, stream>>>(b, seed, k, ix.cursor, nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    // the buffer's keys: the lists (padded) and kIndexPadKeys past them, all ~0 until scattered
+    const uint64_t capacity = index_padded_count(k, (uint32_t)D, align) + kIndexPadKeys;
+    if (align > 1) {
+        round_counts_kernel<<<(uint32_t)((D + 255) / 256), 256, 0, stream>>>(ix.cursor, D, align);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        e = launch_fill_u32(reinterpret_cast<uint32_t *>(ix.entries), 0xFFFFFFFFu, 2 * capacity,
+                            stream);
+        if (e != hipSuccess) return e;
+    }
     scan_blocks_kernel<<<n_blocks, kScanBlock, 0, stream>>>(ix.cursor, ix.offsets, ix.block_sums,
                                                           n_scan);
     scan_sums_kernel<<<1, kScanBlock, 0, stream>>>(ix.block_sums, n_blocks);
@@ -463,8 +484,9 @@ hipError_t launch_index_build(const Bounds &b, uint64_t seed, uint32_t k, const 
     sort_chunks_kernel<<<(uint32_t)std::min<uint64_t>(D, 4096), 256, 0, stream>>>(
         ix.offsets, (uint32_t)D, ix.entries);
     if ((e = hipGetLastError()) != hipSuccess || !ix.by_step) return e;
-    // the step-ordered copy: the same lists and chunks, keys re-packed, then sorted
-    const uint64_t n = (uint64_t)kIndexPairs * 2u * k;
+    // the step-ordered copy: the same lists and chunks, keys re-packed (a ~0 pad stays ~0),
+    // then sorted
+    const uint64_t n = align > 1 ? capacity : (uint64_t)kIndexPairs * 2u * k;
     step_keys_kernel<<<(uint32_t)((n + 255) / 256), 256, 0, stream>>>(ix.entries, n, ix.by_step);
     sort_small_kernel<<<sort_grid, 256, 0, stream>>>(ix.offsets, (uint32_t)D, ix.by_step);
     sort_chunks_kernel<<<(uint32_t)std::min<uint64_t>(D, 4096), 256, 0, stream>>>(

@@ -163,16 +163,19 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t 
 // Starting values of the validation pass's words (minima ~0, counters 0).
 hipError_t launch_check_init(CheckWords *words, hipStream_t stream);
 
-// Component index of the capped sequence (wmh_index.hip).  entries: k * 65534 keys
-// (offset << 32) | (t << 16) | j grouped by component (by_step: the same lists in step order);
-// offsets: D + 1 list starts; cursor:
-// D + 1 counters; block_sums: ceil((D + 1) / 1024) scan carries.
+// Component index of the capped sequence (wmh_index.hip).  entries: the k * 65534 keys
+// (offset << 32) | (t << 16) | j grouped by component (by_step: the same lists in step order),
+// each list padded to a multiple of `align` keys with ~0 keys (red in both orders: offset
+// 2^32 - 1, step 65535), so that with align = 16 every list starts on a 128-byte line;
+// offsets: D + 1 list starts; cursor: D + 1 counters; block_sums: ceil((D + 1) / 1024) scan
+// carries.
 struct IndexBuffers {
     uint64_t *entries = nullptr;
     uint64_t *by_step = nullptr;  // the same lists keyed (t << 48) | (j << 32) | offset; optional
     uint32_t *offsets = nullptr;
     uint32_t *cursor = nullptr;
     uint32_t *block_sums = nullptr;
+    uint32_t align = 1;  // keys per list are a multiple of this (1 or kIndexListAlign)
 };
 
 constexpr uint32_t kIndexSteps = 65534u;  // steps 1 .. cap - 1 decide every capped hash value
@@ -192,8 +195,17 @@ __host__ __device__ inline double index_step_bound(double s, double log_p_k)
 constexpr uint32_t kIndexPadKeys = 16u;  // allocated past the last list: row scans load
                                          // whole batches of keys and mask those past a list
 inline uint64_t index_entry_count(uint32_t k) { return (uint64_t)k * kIndexSteps; }
+constexpr uint32_t kIndexListAlign = 16u;  // keys per 128-byte line
+// Keys a buffer holds for k hashes over `dims` lists padded to multiples of `align` (an upper
+// bound: each list adds at most align - 1 pads), without the kIndexPadKeys past the end.
+inline uint64_t index_padded_count(uint32_t k, uint32_t dims, uint32_t align)
+{
+    return index_entry_count(k) + (uint64_t)(align - 1) * dims;
+}
 inline uint64_t index_scan_blocks(uint32_t dims) { return ((uint64_t)dims + 1 + 1023) / 1024; }
 
+// ix.align sets the lists' padding; the buffers hold index_padded_count(k, D, ix.align) +
+// kIndexPadKeys keys.
 hipError_t launch_index_build(const Bounds &b, uint64_t seed, uint32_t k, const IndexBuffers &ix,
                               hipStream_t stream);
 
