@@ -35,13 +35,13 @@ KEY_BYTES = 8  # one component-index key
 # kernel and plan are the ones timed; the line carries null otherwise.
 #   batched_kernel<unsigned short, 4, 4, true> on the histogram workload (N = 1e5):
 #     profiles/batched_kernel_histogram_k500.txt
-TRAFFIC_R4_HISTOGRAM = 1.1969e9 + 0.1009e9
+TRAFFIC_R4_HISTOGRAM = 1.1953e9 + 0.1009e9
 #   ballot_kernel<unsigned short, true, true> (coarse codes), 8 wavefronts, J = 500, one hash
 #     group, on the heavy tail (depth 40704): profiles/ballot_kernel_heavy_tail_k500.txt
-TRAFFIC_BALLOT_HEAVY_TAIL = 15.0449e9 + 0.2115e9
-#   index_rows_kernel<false, 16>, 8 wavefronts, counter claims, on the 1e6 text-like rows:
-#     profiles/index_rows_kernel_text_like_k1000.txt
-TRAFFIC_INDEX_TEXT_LIKE = None
+TRAFFIC_BALLOT_HEAVY_TAIL = 15.0460e9 + 0.2115e9
+#   index_rows_kernel<false, 16>, 8 wavefronts, counter claims, lists aligned to 128-byte lines,
+#     on the 1e6 text-like rows: profiles/index_rows_kernel_text_like_k1000.txt
+TRAFFIC_INDEX_TEXT_LIKE = 281.1556e9 + 2.0506e9
 
 
 def log(msg: str):
@@ -542,8 +542,7 @@ def text_like_bench(args, torch, synth, wmh) -> dict:
     out["roofline"] = hbm_roofline(key_bytes, float(np.mean(walk)), "index_rows_kernel",
                                    note="expected keys of the rows' evaluation orders "
                                         "(Theorem 2), the rows and the signatures, once each")
-    if TRAFFIC_INDEX_TEXT_LIKE is not None and \
-            (plan["waves_per_block"], plan["index_batch"], plan["index_claim"]) == (8, 16, 1) \
+    if (plan["waves_per_block"], plan["index_batch"], plan["index_claim"]) == (8, 16, 1) \
             and ds.n_rows == 1_000_000:
         out["roofline"]["traffic"] = TRAFFIC_INDEX_TEXT_LIKE
     out["roofline"].update(key_info)
