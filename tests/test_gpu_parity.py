@@ -284,6 +284,13 @@ def _random_plan(rng):
         plan["stream_depth"] = int(rng.integers(1, 3000))
     if rng.random() < 0.3:
         plan["use_graph"] = False
+    c = rng.random()
+    if c < 0.3:
+        plan["values"] = "coarse"
+        if c < 0.15:
+            plan["coarse_bits"] = int(rng.integers(1, 16))
+    elif c < 0.45:
+        plan["values"] = "exact"
     return plan
 
 
@@ -327,6 +334,31 @@ def test_packed_entries_at_the_offset_limit(ctx):
     for opts in (dict(rows_per_block=4), dict(rows_per_block=4, use_graph=False),
                  dict(walk="rows"), dict(walk="ballot")):
         assert_same(gpu_sig(ctx, ds, 45, 12, mode="batched", **opts), want, f"D=16384 {opts}")
+
+
+def test_coarse_codes_at_their_limits(ctx):
+    """Coarse codes at the packed entry's limit (one row of 16-bit codes per block, D = 32768:
+    LDS offsets up to 65534); one dimension more and the planner keeps the exact 32-bit rows
+    (asking for codes is then an argument error), as it does for code widths above 15 bits."""
+    k = 29
+    for D, fits in ((32768, True), (32769, False)):
+        ds = synth.random_case(seed=47, n_rows=9, D=D, density=0.003, max_val=2 ** 20,
+                               bound_slack=1000, empty_rows=1, k=k)
+        want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, k, seed=5)
+        assert_same(gpu_sig(ctx, ds, k, 5, mode="batched", walk="ballot"), want, f"D={D} auto")
+        assert ctx.last_plan()["values"] == ("coarse" if fits else "exact")
+        if fits:
+            for opts in (dict(values="coarse", walk="ballot"),
+                         dict(values="coarse", rows_per_block=1, coarse_bits=2),
+                         dict(values="coarse", walk="ballot", coarse_bits=1, stream_depth=None)):
+                assert_same(gpu_sig(ctx, ds, k, 5, mode="batched", **opts), want, f"D={D} {opts}")
+            with pytest.raises(wmh.WMHError) as e:
+                gpu_sig(ctx, ds, k, 5, mode="batched", values="coarse", coarse_bits=16)
+            assert e.value.name == "WMH_E_ARG"
+        else:
+            with pytest.raises(wmh.WMHError) as e:
+                gpu_sig(ctx, ds, k, 5, mode="batched", values="coarse", walk="ballot")
+            assert e.value.name == "WMH_E_ARG"
 
 
 def test_many_hash_ids(ctx):
