@@ -262,3 +262,23 @@ def test_reserved_buffers(ctx, corpus):
     for rows, r in zip(row_lists, reqs):
         assert np.array_equal(r.sig, _oracle_sig(corpus, rows, k, seed))
     assert np.array_equal(bigger.sig, _oracle_sig(corpus, np.arange(700), k, seed))
+
+
+def test_wide_bounds_take_coarse_codes_in_the_loop(ctx):
+    """Bounds above 16 bits: the loop's batched walk runs on coarse codes (and on exact rows
+    when asked), and every request equals the oracle."""
+    ds = synth.random_case(seed=61, n_rows=300, D=900, density=0.05, max_val=5_000_000,
+                           bound_slack=100_000, empty_rows=3, k=36)
+    k, seed = 36, 13
+    ctx.set_bounds(ds.m)
+    rng = np.random.Generator(np.random.PCG64(62))
+    row_lists = _rows(rng, ds.n_rows, [1, 40, 299, 7])
+    print("  serving wide bounds (coarse codes)", flush=True)
+    with serve.Server(ctx, k, seed=seed, slots=3, mode="batched") as srv:
+        reqs = serve.requests_from_corpus(ds, row_lists, srv, pinned=True)
+        for r in reqs:
+            srv.submit(r)
+        for r in reqs:
+            srv.wait(r.ticket)
+    for rows, r in zip(row_lists, reqs):
+        assert np.array_equal(r.sig, _oracle_sig(ds, rows, k, seed))
