@@ -38,7 +38,10 @@ KEY_BYTES = 8  # one component-index key
 TRAFFIC_R4_HISTOGRAM = 1.1953e9 + 0.1009e9
 #   ballot_kernel<unsigned short, true, true> (coarse codes), 8 wavefronts, J = 500, one hash
 #     group, on the heavy tail (depth 40704): profiles/ballot_kernel_heavy_tail_k500.txt
-TRAFFIC_BALLOT_HEAVY_TAIL = 15.0460e9 + 0.2115e9
+TRAFFIC_BALLOT_HEAVY_TAIL = 14.8824e9 + 0.2115e9
+#   the row split on the heavy tail (auto: the coarse ballot walk, 8 wavefronts, over the walk rows,
+#     then index_rows_kernel over the others), per call: the same profile
+TRAFFIC_SPLIT_HEAVY_TAIL = 5.9609e9
 #   index_rows_kernel<false, 16>, 8 wavefronts, counter claims, lists aligned to 128-byte lines,
 #     on the 1e6 text-like rows: profiles/index_rows_kernel_text_like_k1000.txt
 TRAFFIC_INDEX_TEXT_LIKE = 281.1556e9 + 2.0506e9
@@ -389,12 +392,17 @@ def heavy_tail_bench(args, torch, synth, wmh) -> dict:
     timed_steps(ctx, rows, k, sig_a, ctx.make_opts(mode="auto", profile=True), 1, 1, torch)
     el_a, walk_a, _ = timed_steps(ctx, rows, k, sig_a, ctx.make_opts(mode="auto", profile=True),
                                   3, 0, torch)
-    out["auto"] = {"mode": ctx.last_mode(), "plan": ctx.last_plan(),
+    ap = ctx.last_plan()
+    profiled_split = (ap["mode"] == "split" and ap["walk"] == "ballot"
+                      and ap["waves_per_block"] == 8 and ap["values"] == "coarse"
+                      and ds.n_rows == 200_000)
+    out["auto"] = {"mode": ctx.last_mode(), "plan": ap,
                    "hashes_per_s": hashes * 3 / el_a, "ms_per_step": el_a / 3 * 1e3,
                    "kernels_ms": float(np.mean(walk_a)),
                    "equals_batched": bool(torch.equal(sig_a, sig_b)),
                    "roofline": alu_roofline(
                        tests, float(np.mean(walk_a)), "walk + index rows kernels",
+                       traffic=TRAFFIC_SPLIT_HEAVY_TAIL if profiled_split else None,
                        note="walk-equivalent tests: the index rows compute the same values "
                             "with fewer operations")}
     log(f"heavy-tail: auto ({out['auto']['mode']}) {out['auto']['ms_per_step']:.2f} ms/step, "
