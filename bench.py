@@ -42,9 +42,10 @@ TRAFFIC_BALLOT_HEAVY_TAIL = 14.8824e9 + 0.2115e9
 #   the row split on the heavy tail (auto: the coarse ballot walk, 8 wavefronts, over the walk rows,
 #     then index_rows_kernel over the others), per call: the same profile
 TRAFFIC_SPLIT_HEAVY_TAIL = 5.9609e9
-#   index_rows_kernel<false, 16>, 8 wavefronts, counter claims, lists aligned to 128-byte lines,
-#     on the 1e6 text-like rows: profiles/index_rows_kernel_text_like_k1000.txt
-TRAFFIC_INDEX_TEXT_LIKE = 281.1556e9 + 2.0506e9
+#   index_rows_kernel<false, 16>, counter claims, lists aligned to 128-byte lines, on the 1e6
+#     text-like rows, by wavefronts per workgroup (the tuner picks 8 or 16 on different boxes):
+#     profiles/index_rows_kernel_text_like_k1000.txt
+TRAFFIC_INDEX_TEXT_LIKE = {8: 281.1099e9 + 2.0506e9, 16: 281.1544e9 + 2.0505e9}
 
 
 def log(msg: str):
@@ -117,6 +118,9 @@ def parse():
     ap.add_argument("--steps-per-lane", type=int, default=0)
     ap.add_argument("--hash-groups", type=int, default=0,
                     help="ballot walk: hash ids in this many groups (0: planner or autotuner)")
+    ap.add_argument("--index-waves", type=int, default=0,
+                    help="text-like leg: wavefronts per workgroup of the index rows kernel "
+                         "(with 16 keys per trip and counter claims; 0: autotuned)")
     ap.add_argument("--values", type=int, default=0, choices=[0, 1, 2],
                     help="dense rows in LDS: 0 planner/autotuner, 1 the values, 2 coarse codes")
     ap.add_argument("--walk", type=int, default=0, choices=[0, 1, 2, 3],
@@ -515,10 +519,13 @@ def text_like_bench(args, torch, synth, wmh) -> dict:
     cold_ms = (time.perf_counter() - t0) * 1e3
     first_rows_ms, build_ms = ctx.last_kernel_ms()
     mode = ctx.last_mode()
-    # the index rows kernel's plan, tuned on these rows (the index is already built), then
-    # steady-state steps replaying it from a graph
+    # the index rows kernel's plan, tuned on these rows (the index is already built) unless
+    # given, then steady-state steps replaying it from a graph
     tune = None
-    if not args.no_tune:
+    if args.index_waves:
+        opts = ctx.make_opts(mode="auto", profile=True, waves_per_block=args.index_waves,
+                             index_batch=16, index_claim="counter")
+    elif not args.no_tune:
         tune = ctx.tune(rows, k, 0, reps=1)
         log(f"text-like: tuned {tune}")
     el, walk, _ = timed_steps(ctx, rows, k, sig, opts, 3, 1, torch)
@@ -550,9 +557,8 @@ def text_like_bench(args, torch, synth, wmh) -> dict:
     out["roofline"] = hbm_roofline(key_bytes, float(np.mean(walk)), "index_rows_kernel",
                                    note="expected keys of the rows' evaluation orders "
                                         "(Theorem 2), the rows and the signatures, once each")
-    if (plan["waves_per_block"], plan["index_batch"], plan["index_claim"]) == (8, 16, 1) \
-            and ds.n_rows == 1_000_000:
-        out["roofline"]["traffic"] = TRAFFIC_INDEX_TEXT_LIKE
+    if plan["index_batch"] == 16 and plan["index_claim"] == 1 and ds.n_rows == 1_000_000:
+        out["roofline"]["traffic"] = TRAFFIC_INDEX_TEXT_LIKE.get(plan["waves_per_block"])
     out["roofline"].update(key_info)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = oracle_on_head(ds, 48, k, sig_np[:48])
