@@ -32,16 +32,17 @@ OPS_PER_COMPARE = 2  # collision counting: one u16 equality and one accumulate p
 KEY_BYTES = 8  # one component-index key
 # HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the same counters on
 # a 1 GiB device-to-device copy (read x2.000, write x1.000).  Each figure is valid while its
-# kernel and plan are the ones timed; the line carries null otherwise.
-#   batched_kernel<unsigned short, 4, 4, true> on the histogram workload (N = 1e5):
-#     profiles/batched_kernel_histogram_k500.txt
-TRAFFIC_R4_HISTOGRAM = 1.1953e9 + 0.1009e9
-#   ballot_kernel<unsigned short, true, true> (coarse codes), 8 wavefronts, J = 500, one hash
-#     group, on the heavy tail (depth 40704): profiles/ballot_kernel_heavy_tail_k500.txt
-TRAFFIC_BALLOT_HEAVY_TAIL = 14.8824e9 + 0.2115e9
-#   the row split on the heavy tail (auto: the coarse ballot walk, 8 wavefronts, over the walk rows,
-#     then index_rows_kernel over the others), per call: the same profile
-TRAFFIC_SPLIT_HEAVY_TAIL = 5.9609e9
+# kernel and plan are the ones timed; the line carries null otherwise.  Keyed by wavefronts per
+# workgroup where the autotuner picks 8 or 16 on different machines.
+#   batched_kernel<unsigned short, 4, 4, true, false> (R = 4, K = 4, J = 500) on the histogram
+#     workload (N = 1e5): profiles/batched_kernel_histogram_k500.txt
+TRAFFIC_R4_HISTOGRAM = {8: 1.1953e9 + 0.1009e9, 16: 1.1913e9 + 0.1009e9}
+#   ballot_kernel<unsigned short, true, true> (coarse codes), J = 500, one hash group, on the
+#     heavy tail (depth 40704): profiles/ballot_kernel_heavy_tail_k500.txt
+TRAFFIC_BALLOT_HEAVY_TAIL = {8: 14.8824e9 + 0.2115e9, 16: 14.9603e9 + 0.2114e9}
+#   the row split on the heavy tail (auto: the coarse ballot walk over the walk rows, then
+#     index_rows_kernel over the others), per call: the same profile
+TRAFFIC_SPLIT_HEAVY_TAIL = {8: 5.9609e9, 16: 5.9604e9}
 #   index_rows_kernel<false, 16>, counter claims, lists aligned to 128-byte lines, on the 1e6
 #     text-like rows, by wavefronts per workgroup (the tuner picks 8 or 16 on different boxes):
 #     profiles/index_rows_kernel_text_like_k1000.txt
@@ -365,9 +366,8 @@ def heavy_tail_bench(args, torch, synth, wmh) -> dict:
                 "mean_steps_per_hash": tests / hashes,
                 "roofline": alu_roofline(
                     tests, float(np.mean(walk_b)), f"{out['batched_plan']['walk']} walk",
-                    traffic=TRAFFIC_BALLOT_HEAVY_TAIL if (
+                    traffic=TRAFFIC_BALLOT_HEAVY_TAIL.get(out["batched_plan"]["waves_per_block"]) if (
                         out["batched_plan"]["walk"] == "ballot"
-                        and out["batched_plan"]["waves_per_block"] == 8
                         and out["batched_plan"]["values"] == "coarse"
                         and out["batched_plan"]["hashes_per_tile"] == 500
                         and out["batched_plan"]["hash_groups"] == 1 and ds.n_rows == 200_000)
@@ -398,7 +398,7 @@ def heavy_tail_bench(args, torch, synth, wmh) -> dict:
                                   3, 0, torch)
     ap = ctx.last_plan()
     profiled_split = (ap["mode"] == "split" and ap["walk"] == "ballot"
-                      and ap["waves_per_block"] == 8 and ap["values"] == "coarse"
+                      and ap["values"] == "coarse" and ap["hashes_per_tile"] == 500
                       and ds.n_rows == 200_000)
     out["auto"] = {"mode": ctx.last_mode(), "plan": ap,
                    "hashes_per_s": hashes * 3 / el_a, "ms_per_step": el_a / 3 * 1e3,
@@ -406,7 +406,8 @@ def heavy_tail_bench(args, torch, synth, wmh) -> dict:
                    "equals_batched": bool(torch.equal(sig_a, sig_b)),
                    "roofline": alu_roofline(
                        tests, float(np.mean(walk_a)), "walk + index rows kernels",
-                       traffic=TRAFFIC_SPLIT_HEAVY_TAIL if profiled_split else None,
+                       traffic=TRAFFIC_SPLIT_HEAVY_TAIL.get(ap["waves_per_block"])
+                       if profiled_split else None,
                        note="walk-equivalent tests: the index rows compute the same values "
                             "with fewer operations")}
     log(f"heavy-tail: auto ({out['auto']['mode']}) {out['auto']['ms_per_step']:.2f} ms/step, "
@@ -752,7 +753,8 @@ def main():
 
     main_key = "batched" if "batched" in result else "plain"
     profiled_plan = (main_key == "batched" and batched_plan["rows_per_block"] == 4
-                     and ds.n_rows == 100_000)
+                     and batched_plan["steps_per_lane"] == 4
+                     and batched_plan["hashes_per_tile"] == 500 and ds.n_rows == 100_000)
     steps = args.steps if main_key == "batched" else result["plain"][2]
     el, walk, _ = result[main_key][:3]
     value = hashes * steps / el
@@ -781,7 +783,8 @@ def main():
                    "mode": main_key},
         "roofline": alu_roofline(
             tests, walk_s * 1e3, "batched_kernel" if main_key == "batched" else "plain_kernel",
-            traffic=TRAFFIC_R4_HISTOGRAM if profiled_plan else None),
+            traffic=TRAFFIC_R4_HISTOGRAM.get(batched_plan["waves_per_block"])
+            if profiled_plan else None),
         "mean_steps_per_hash": tests / hashes,
     }
     if "batched" in result and "plain" in result:
