@@ -149,7 +149,7 @@ def parse():
     ap.add_argument("--text-rows", type=int, default=1_000_000,
                     help="rows of the text-like workload generated for its line")
     ap.add_argument("--serve-max-rows", type=int, default=4096)
-    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-slots", type=int, default=8)
     return ap.parse_args()
 
 

@@ -508,7 +508,7 @@ typedef struct wmh_server wmh_server;
 typedef struct {
     uint32_t k;            /* hashes per row, 1 <= k <= 2^24 */
     uint32_t slots;        /* requests on the device at once, each on its own HIP stream;
-                              1..64, 0 = 4 */
+                              1..64, 0 = 8 */
     uint64_t seed;         /* key of the random sequence */
     uint64_t mem_budget;   /* device bytes for the admitted requests' rows and signatures
                               ((N+1)*8 + nnz*8 + N*k*2 each); 0 = 4 GiB */

@@ -371,7 +371,7 @@ wmh_status wmh_server_create(wmh_ctx *ctx, const wmh_server_config *cfg_in, wmh_
     if (!ctx->has_bounds) return fail(ctx, WMH_E_NO_BOUNDS, "wmh_set_bounds was not called");
     wmh_server_config cfg = *cfg_in;
     if (cfg.k == 0 || cfg.k > kMaxK) return fail(ctx, WMH_E_ARG, "k must be in [1, 2^24]");
-    if (cfg.slots == 0) cfg.slots = 4;
+    if (cfg.slots == 0) cfg.slots = 8;
     if (cfg.slots > 64) return fail(ctx, WMH_E_ARG, "slots must be in [1, 64]");
     if (cfg.mem_budget == 0) cfg.mem_budget = 4ull << 30;
     if (cfg.mode < WMH_MODE_AUTO || cfg.mode > WMH_MODE_INDEXED)

@@ -72,7 +72,7 @@ class Request:
 class Server:
     """A serving loop on a context's device and bounds."""
 
-    def __init__(self, ctx: "wmh.Context", k: int, seed: int = 0, slots: int = 4,
+    def __init__(self, ctx: "wmh.Context", k: int, seed: int = 0, slots: int = 8,
                  mem_budget: int = 0, mode: str = "auto", stream_depth: int = 0,
                  build_index: bool = False):
         self._lib = wmh.load()
