@@ -150,6 +150,12 @@ def parse():
                     help="rows of the text-like workload generated for its line")
     ap.add_argument("--serve-max-rows", type=int, default=4096)
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="requests/s the load levels are fractions of (0: the saturated rate "
+                         "measured by the burst)")
+    ap.add_argument("--serve-group-rows", type=int, default=0,
+                    help="rows admitted together into one slot (0: the loop's 2048; 1: one "
+                         "request per slot)")
     return ap.parse_args()
 
 
@@ -170,7 +176,8 @@ def serve_bench(args) -> dict:
     ctx.set_bounds(corpus.m)
     out = {"workload": f"requests of 1..{args.serve_max_rows} consecutive rows (log-uniform "
                        f"sizes) of a {corpus.n_rows}-row corpus, D=2^20, tf weights Q16.16, k={k}",
-           "slots": args.serve_slots, "request_buffers": "page-locked (wmh_host_alloc)"}
+           "slots": args.serve_slots, "group_rows": args.serve_group_rows or 2048,
+           "request_buffers": "page-locked (wmh_host_alloc)"}
 
     def request_bytes(sizes, starts):
         rp = corpus.row_ptr.astype(np.int64)
@@ -178,13 +185,21 @@ def serve_bench(args) -> dict:
         h2d = 8 * (sizes + 1) + 8 * nnz
         return float(h2d.sum()), float((2 * k * sizes).sum())
 
+    group_rows = args.serve_group_rows or 2048
+    row_len = np.diff(corpus.row_ptr.astype(np.int64))
+    # the most nonzeros a group of up to group_rows rows can hold
+    group_nnz = int(np.sort(row_len)[::-1][:group_rows].sum())
+
     def reserve(srv, sizes, starts):
-        # slot buffers sized up front for the largest request, so no admission allocates
+        # slot buffers sized up front for the largest request or group, so no admission
+        # allocates
         rp = corpus.row_ptr.astype(np.int64)
-        srv.reserve(int(sizes.max()), int((rp[starts + sizes] - rp[starts]).max()))
+        srv.reserve(max(int(sizes.max()), group_rows),
+                    max(int((rp[starts + sizes] - rp[starts]).max()), group_nnz))
 
     # the component index is built when each loop starts, so no timed request waits for it
-    with serve.Server(ctx, k, seed=0, slots=args.serve_slots, build_index=True) as srv:
+    with serve.Server(ctx, k, seed=0, slots=args.serve_slots, build_index=True,
+                          group_rows=args.serve_group_rows) as srv:
         ring = serve.RangeRequests(srv, corpus, args.serve_max_rows)
         burst = min(500, len(ring.sig_buf))
         _, sizes, starts = synth.serving_ranges(burst, corpus.n_rows, qps=1.0, seed=3005,
@@ -206,6 +221,7 @@ def serve_bench(args) -> dict:
         out["saturated_hashes_per_s"] = float(sum(sizes)) * k / burst_s
         out["saturated_max_on_device"] = st["max_on_device"]
         out["saturated_max_computing"] = st["max_computing"]
+        out["saturated_requests_per_load"] = st["completed"] / max(1, st["loads"])
         # the loop's bound: its requests live in host memory, so every row crosses PCIe once
         # and every signature once back
         out["roofline"] = {"bound": "pcie", "achieved": pcie, "peak": 2 * PCIE_PEAK_GBS,
@@ -219,15 +235,18 @@ def serve_bench(args) -> dict:
     del ring, reqs
     gc.collect()
     levels = []
+    base_qps = args.serve_rate or sat_qps
+    out["load_base_qps"] = base_qps
     for frac in (0.5, 0.8):
-        qps = frac * sat_qps
+        qps = frac * base_qps
         runs = []
         for run in range(2):
             n_req = args.serve_requests + args.serve_warmup
             arrivals, sizes, starts = synth.serving_ranges(
                 n_req, corpus.n_rows, qps=qps, seed=int(4005 + 100 * frac + 7 * run),
                 max_rows=args.serve_max_rows)
-            with serve.Server(ctx, k, seed=0, slots=args.serve_slots, build_index=True) as srv:
+            with serve.Server(ctx, k, seed=0, slots=args.serve_slots, build_index=True,
+                          group_rows=args.serve_group_rows) as srv:
                 reserve(srv, sizes, starts)
                 ring = serve.RangeRequests(srv, corpus, args.serve_max_rows)
                 w = args.serve_warmup
@@ -248,6 +267,7 @@ def serve_bench(args) -> dict:
                          "peak_bytes": st["peak_bytes"], "max_on_device": st["max_on_device"],
                          "max_computing": st["max_computing"], "overlap_s": st["overlap_s"],
                          "busy_s": st["busy_s"], "ring_waits": waits,
+                         "requests_per_load": st["completed"] / max(1, st["loads"]),
                          "driver_late_p99_ms": st.get("driver_late_p99_ms"),
                          "driver_late_max_ms": st.get("driver_late_max_ms")})
             log(f"serve: load {frac} run {run}: {st['completed']} requests, p50 "

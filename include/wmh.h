@@ -518,7 +518,12 @@ typedef struct {
                               0 = 8192 (steps beyond are drawn in-lane) */
     int32_t build_index;   /* 1: build the component index at creation (auto or indexed mode),
                               so no request waits for it; 0: on the first indexed request */
-    uint32_t reserved[3];
+    uint32_t group_rows;   /* queued requests admitted together into one slot while their rows
+                              add up to at most this (one validation pass, one walk or index
+                              launch and one copy out for the group; every request's
+                              signatures are the same as alone); 0 = 2048, 1 = one request
+                              per slot */
+    uint32_t reserved[2];
 } wmh_server_config;
 
 typedef struct {
@@ -535,17 +540,22 @@ typedef struct {
      * request is on the device from its first copy in to the end of its copy out, and
      * computing from the start of its walk to the end of its copy out (both include time its
      * work waits in the device queues behind other slots' work). */
-    uint64_t max_on_device;  /* most completed requests on the device at one instant */
-    uint64_t max_computing;  /* most completed requests computing at one instant */
-    double overlap_s;        /* seconds during which at least two requests were computing */
+    uint64_t max_on_device;  /* most completed slot loads (a request, or requests admitted
+                                together) on the device at one instant */
+    uint64_t max_computing;  /* most completed slot loads computing at one instant */
+    double overlap_s;        /* seconds during which at least two slot loads were computing */
+    uint64_t loads;          /* completed slot loads (completed / loads: requests per load) */
 } wmh_serving_stats;
 
 /*
  * wmh_server_create -- starts a serving loop on ctx's device using ctx's bounds (which must
  * not change while the loop exists).  A worker thread admits queued requests in arrival order
- * whenever a slot is free and the admitted bytes stay within mem_budget, runs each request's
- * walk on its slot's stream (so requests overlap on the device), and completes them as their
- * results arrive.  Bounds, bucket table and the shared position stream stay device-resident.
+ * whenever a slot is free and the admitted bytes stay within mem_budget (consecutive requests
+ * up to group_rows rows together, as one group), runs each group's walk on its slot's stream
+ * (so groups overlap on the device), and completes the requests as their results arrive.  A
+ * group whose rows fail the device check completes the request with the first bad row with
+ * that status and checks each of the others again alone.  Bounds, bucket table and the shared
+ * position stream stay device-resident.
  * Errors: WMH_E_ARG, WMH_E_NO_BOUNDS, WMH_E_NOMEM, WMH_E_DEVICE.
  */
 wmh_status wmh_server_create(wmh_ctx *ctx, const wmh_server_config *cfg, wmh_server **out);
@@ -576,9 +586,9 @@ wmh_status wmh_server_wait(wmh_server *srv, uint64_t ticket, double *latency_ms)
 wmh_status wmh_server_drain(wmh_server *srv);
 
 /*
- * wmh_server_reserve -- sizes every slot's device buffers and page-locked signature buffer for
- * requests of up to max_rows rows and max_nnz nonzeros, so that admitting such a request
- * allocates nothing.  Without it a slot grows its buffers (by at least half) when a larger
+ * wmh_server_reserve -- sizes every slot's device buffers and page-locked staging buffers for
+ * requests (or groups of requests) of up to max_rows rows and max_nnz nonzeros, so that
+ * admitting them allocates nothing.  Without it a slot grows its buffers (by at least half) when a larger
  * request arrives, and freeing the old ones waits for the device, which delays every request
  * in flight.  Waits until every submitted request has completed.  Errors: WMH_E_ARG,
  * WMH_E_NOMEM (beyond mem_budget or device memory), WMH_E_DEVICE.

@@ -2,10 +2,15 @@
 //
 // Requests are queued by any host thread and admitted, in arrival order, by one worker thread
 // whenever a slot (a HIP stream with its own buffers) is free and the admitted device bytes
-// stay within the budget.  An admitted request runs in two phases on its slot's stream: its
-// rows are copied in and checked by the device validation pass (which also gathers the
-// planner's statistics); once the check words are back, the worker either completes it with
-// the error or launches the chosen path and the copy out.  Requests overlap on the device and
+// stay within the budget.  Consecutive queued requests whose rows add up to at most
+// group_rows are admitted together into one slot as a group: their rows are laid end to end
+// and go through one validation pass, one walk or index launch and one copy out, which small
+// requests would otherwise each pay for.  An admitted group runs in two phases on its slot's
+// stream: its rows are copied in and checked by the device validation pass (which also
+// gathers the planner's statistics); once the check words are back, the worker either
+// completes the group (a group whose rows fail the check completes the request holding the
+// first bad row with the error and queues the others again, alone) or launches the chosen
+// path and the copy out.  Requests overlap on the device and
 // the worker never blocks on one.  The bounds tables and the shared position stream are built
 // once and stay device-resident.  Every request computes the same function as wmh_hash on its
 // rows.
@@ -69,14 +74,18 @@ struct Request {
     uint16_t *sig = nullptr;
     uint64_t arrival_ns = 0, admit_ns = 0, done_ns = 0;
     uint64_t bytes = 0;
-    RowStats stats;  // from the device check, for the planner
+    bool retried = false;  // back in the queue after its group failed the check: admitted alone
     bool done = false;
     wmh_status status = WMH_OK;
 };
 
+constexpr size_t kMaxGroup = 64;  // requests admitted together into one slot
+
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t finished = nullptr;
+    uint64_t *h_row_ptr = nullptr;  // pinned: a group's row_ptr, requests laid end to end
+    uint64_t cap_h_rows = 0;
     uint64_t *d_row_ptr = nullptr;
     uint32_t *d_col = nullptr, *d_val = nullptr;
     uint16_t *d_sig = nullptr;
@@ -87,10 +96,11 @@ struct Slot {
     CheckWords *d_check = nullptr;  // the validation pass's words
     CheckWords *h_check = nullptr;  // pinned copy, read once `checked` has fired
     hipEvent_t checked = nullptr;
-    // timing events of the request on the slot: its first copy in, the start of its walk and
-    // the end of its copy out (device timestamps, read at completion)
+    // timing events of the group on the slot: its first copy in, the start of its walk and the
+    // end of its copy out (device timestamps, read at completion)
     hipEvent_t t_begin = nullptr, t_compute = nullptr, t_end = nullptr;
-    Request *req = nullptr;
+    std::vector<Request *> reqs;  // the admitted group, in arrival order (empty: slot free)
+    uint64_t rows = 0, nnz = 0;   // the group's rows and nonzeros
     bool computing = false;  // past the check: the walk and the copy out are queued
 };
 
@@ -127,6 +137,15 @@ hipError_t grow_slot(Slot &slot, uint64_t n_rows, uint64_t nnz, uint32_t k)
                           hipHostMallocDefault);
         if (e == hipSuccess) slot.cap_h_sig = n;
     }
+    if (e == hipSuccess && (slot.cap_h_rows < n_rows + 1 || !slot.h_row_ptr)) {
+        const uint64_t n = std::max<uint64_t>({n_rows + 1, 2, slot.cap_h_rows + slot.cap_h_rows / 2});
+        if (slot.h_row_ptr) (void)hipHostFree(slot.h_row_ptr);
+        slot.h_row_ptr = nullptr;
+        slot.cap_h_rows = 0;
+        e = hipHostMalloc(reinterpret_cast<void **>(&slot.h_row_ptr), n * sizeof(uint64_t),
+                          hipHostMallocDefault);
+        if (e == hipSuccess) slot.cap_h_rows = n;
+    }
     return e;
 }
 
@@ -156,37 +175,71 @@ struct wmh_server {
     std::thread worker;
     // statistics
     uint64_t submitted = 0, completed = 0, failed = 0, rejected = 0, max_queued = 0, peak_bytes = 0;
-    uint64_t hashes = 0;
+    uint64_t hashes = 0, loads = 0;
     std::vector<double> latencies_ms;
     uint64_t first_admit_ns = 0, last_done_ns = 0;
-    // device intervals of completed requests, in ms after t_ref: [first copy in, end of copy
+    // device intervals of completed groups, in ms after t_ref: [first copy in, end of copy
     // out] and [start of the walk, end of copy out]
     hipEvent_t t_ref = nullptr;
     std::vector<std::pair<float, float>> on_device, computing;
 
-    wmh_status launch_check(Slot &slot, Request &r);
-    wmh_status launch_compute(Slot &slot, Request &r);
+    wmh_status launch_check(Slot &slot);
+    wmh_status launch_compute(Slot &slot, uint64_t *bad_row);
+    void complete_one(Slot &slot, Request &r, uint64_t row0, wmh_status st);
     void complete(Slot &slot, wmh_status st);
+    void release(Slot &slot, Request *culprit, wmh_status st);
     void run();
 };
 
-// Phase one: buffers, copy in, validation pass and the copy of its words to the host.
-wmh_status wmh_server::launch_check(Slot &slot, Request &r)
+// Phase one: buffers, copy in, validation pass and the copy of its words to the host.  A lone
+// request is copied as given; a group's requests are laid end to end, each contributing the
+// nonzeros its rows cover (row_ptr[0] up to row_ptr[n_rows]), with its row_ptr rebased on the
+// host in pinned memory.
+wmh_status wmh_server::launch_check(Slot &slot)
 {
     const uint32_t k = cfg.k;
-    hipError_t e = grow_slot(slot, r.n_rows, r.nnz, k);
+    const bool group = slot.reqs.size() > 1;
+    slot.rows = slot.nnz = 0;
+    for (const Request *r : slot.reqs) {
+        slot.rows += r->n_rows;
+        slot.nnz += group ? r->row_ptr[r->n_rows] - r->row_ptr[0] : r->nnz;
+    }
+    hipError_t e = grow_slot(slot, slot.rows, slot.nnz, k);
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? WMH_E_NOMEM : WMH_E_DEVICE;
 
     hipStream_t s = slot.stream;
     e = hipEventRecord(slot.t_begin, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(slot.d_row_ptr, r.row_ptr, (r.n_rows + 1) * sizeof(uint64_t),
-                           hipMemcpyHostToDevice, s);
-    if (e == hipSuccess && r.nnz)
-        e = hipMemcpyAsync(slot.d_col, r.col, r.nnz * sizeof(uint32_t), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess && r.nnz)
-        e = hipMemcpyAsync(slot.d_val, r.val, r.nnz * sizeof(uint32_t), hipMemcpyHostToDevice, s);
-    const Rows rows{slot.d_row_ptr, slot.d_col, slot.d_val, r.n_rows, r.nnz};
+    if (!group) {
+        const Request &r = *slot.reqs[0];
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(slot.d_row_ptr, r.row_ptr, (r.n_rows + 1) * sizeof(uint64_t),
+                               hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && r.nnz)
+            e = hipMemcpyAsync(slot.d_col, r.col, r.nnz * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && r.nnz)
+            e = hipMemcpyAsync(slot.d_val, r.val, r.nnz * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    } else {
+        // the slot is free, so no copy still reads its staging buffer
+        uint64_t row0 = 0, nz0 = 0;
+        for (const Request *r : slot.reqs) {
+            const uint64_t lo = r->row_ptr[0], used = r->row_ptr[r->n_rows] - lo;
+            for (uint64_t i = 0; i < r->n_rows; ++i)
+                slot.h_row_ptr[row0 + i] = r->row_ptr[i] - lo + nz0;
+            if (e == hipSuccess && used)
+                e = hipMemcpyAsync(slot.d_col + nz0, r->col + lo, used * sizeof(uint32_t),
+                                   hipMemcpyHostToDevice, s);
+            if (e == hipSuccess && used)
+                e = hipMemcpyAsync(slot.d_val + nz0, r->val + lo, used * sizeof(uint32_t),
+                                   hipMemcpyHostToDevice, s);
+            row0 += r->n_rows;
+            nz0 += used;
+        }
+        slot.h_row_ptr[row0] = nz0;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(slot.d_row_ptr, slot.h_row_ptr, (row0 + 1) * sizeof(uint64_t),
+                               hipMemcpyHostToDevice, s);
+    }
+    const Rows rows{slot.d_row_ptr, slot.d_col, slot.d_val, slot.rows, slot.nnz};
     // first_error and min_green start at ~0, the counters at 0 (as in wmh_hash's pass); the
     // index-key estimate only when the planner may take the index
     const bool want_keys = cfg.mode == WMH_MODE_AUTO && index_fits(cfg.k);
@@ -201,25 +254,31 @@ wmh_status wmh_server::launch_check(Slot &slot, Request &r)
 }
 
 // Phase two, once the check words are on the host: the rows' status, then the chosen path and
-// the copy out (nothing is launched for rows that failed the check).
-wmh_status wmh_server::launch_compute(Slot &slot, Request &r)
+// the copy out (nothing is launched for rows that failed the check; *bad_row is then the
+// group's first bad row).
+wmh_status wmh_server::launch_compute(Slot &slot, uint64_t *bad_row)
 {
     const CheckWords v = *slot.h_check;
-    if (v.first_error != ~0ull) return check_status((uint32_t)(v.first_error & 15u));
-    r.stats.known = true;
-    r.stats.nonempty = r.n_rows - std::min<uint64_t>(r.n_rows, v.n_empty);
-    r.stats.min_green = v.min_green;
-    r.stats.walk_steps = v.walk_steps;
-    r.stats.index_keys = v.index_keys;
-    r.stats.keys_known = cfg.mode == WMH_MODE_AUTO && index_fits(cfg.k);
+    if (v.first_error != ~0ull) {
+        *bad_row = v.first_error >> 4;
+        return check_status((uint32_t)(v.first_error & 15u));
+    }
+    RowStats stats;
+    stats.known = true;
+    stats.nonempty = slot.rows - std::min<uint64_t>(slot.rows, v.n_empty);
+    stats.min_green = v.min_green;
+    stats.walk_steps = v.walk_steps;
+    stats.index_keys = v.index_keys;
+    stats.keys_known = cfg.mode == WMH_MODE_AUTO && index_fits(cfg.k);
     const uint32_t k = cfg.k;
-    const uint64_t sig_elems = r.n_rows * (uint64_t)k;
+    const uint64_t n_rows = slot.rows;
+    const uint64_t sig_elems = n_rows * (uint64_t)k;
     hipStream_t s = slot.stream;
     hipError_t e = hipSuccess;
-    const Rows rows{slot.d_row_ptr, slot.d_col, slot.d_val, r.n_rows, r.nnz};
+    const Rows rows{slot.d_row_ptr, slot.d_col, slot.d_val, n_rows, slot.nnz};
     const Bounds b = bounds_view(ctx);
     // the index is built once per loop, so its cost is left out of the comparison
-    const Path path = choose_path(ctx, cfg.mode, batched, true, k, r.n_rows, r.nnz, r.stats);
+    const Path path = choose_path(ctx, cfg.mode, batched, true, k, n_rows, slot.nnz, stats);
     e = hipEventRecord(slot.t_compute, s);
     if (e == hipSuccess && path == Path::kIndexed) {
         if (!index.valid) {
@@ -243,8 +302,8 @@ wmh_status wmh_server::launch_compute(Slot &slot, Request &r)
         } else {
             const bool narrow = ctx->max_bound <= 0xFFFFu;
             const bool dense = (size_t)4 * ctx->dims * (narrow ? 2 : 4) <= 64 * 1024;
-            for (uint64_t r0 = 0; r0 < r.n_rows && e == hipSuccess; r0 += 8192)
-                e = launch_plain(b, rows, r0, std::min(r.n_rows, r0 + 8192), k, cfg.seed,
+            for (uint64_t r0 = 0; r0 < n_rows && e == hipSuccess; r0 += 8192)
+                e = launch_plain(b, rows, r0, std::min(n_rows, r0 + 8192), k, cfg.seed,
                                  slot.d_sig, narrow, dense, s);
         }
     }
@@ -257,12 +316,12 @@ wmh_status wmh_server::launch_compute(Slot &slot, Request &r)
     return e == hipSuccess ? WMH_OK : WMH_E_DEVICE;
 }
 
-// Called with mu held.
-void wmh_server::complete(Slot &slot, wmh_status st)
+// One request of a slot's group, whose rows start at group row row0.  Called with mu held.
+void wmh_server::complete_one(Slot &slot, Request &r, uint64_t row0, wmh_status st)
 {
-    Request &r = *slot.req;
     if (st == WMH_OK)
-        std::memcpy(r.sig, slot.h_sig, r.n_rows * (uint64_t)cfg.k * sizeof(uint16_t));
+        std::memcpy(r.sig, slot.h_sig + row0 * (uint64_t)cfg.k,
+                    r.n_rows * (uint64_t)cfg.k * sizeof(uint16_t));
     r.done_ns = steady_ns();
     r.status = st;
     r.done = true;
@@ -273,6 +332,20 @@ void wmh_server::complete(Slot &slot, wmh_status st)
         hashes += r.n_rows * (uint64_t)cfg.k;
         latencies_ms.push_back((double)(r.done_ns - r.arrival_ns) * 1e-6);
         last_done_ns = std::max(last_done_ns, r.done_ns);
+    } else if (st == WMH_E_ROW_PTR || st == WMH_E_COL_RANGE || st == WMH_E_UNSORTED ||
+               st == WMH_E_BOUND) {
+        ++rejected;  // the caller's rows, reported by wmh_server_poll / wait
+    } else {
+        ++failed;
+    }
+}
+
+// Every request of the slot's group with status st, and the group's device intervals.  Called
+// with mu held.
+void wmh_server::complete(Slot &slot, wmh_status st)
+{
+    if (st == WMH_OK) {
+        ++loads;
         // every event of the slot has fired once `finished` has
         float b = 0.f, c = 0.f, d = 0.f;
         if (hipEventElapsedTime(&b, t_ref, slot.t_begin) == hipSuccess &&
@@ -281,13 +354,31 @@ void wmh_server::complete(Slot &slot, wmh_status st)
             on_device.emplace_back(b, d);
             computing.emplace_back(c, d);
         }
-    } else if (st == WMH_E_ROW_PTR || st == WMH_E_COL_RANGE || st == WMH_E_UNSORTED ||
-               st == WMH_E_BOUND) {
-        ++rejected;  // the caller's rows, reported by wmh_server_poll / wait
-    } else {
-        ++failed;
     }
-    slot.req = nullptr;
+    uint64_t row0 = 0;
+    for (Request *r : slot.reqs) {
+        complete_one(slot, *r, row0, st);
+        row0 += r->n_rows;
+    }
+    slot.reqs.clear();
+    cv_done.notify_all();
+}
+
+// A group whose rows failed the check: the request holding the first bad row completes with
+// the check's status, the others go back to the front of the queue in arrival order, marked to
+// be admitted alone (their rows are checked again by themselves).  Called with mu held.
+void wmh_server::release(Slot &slot, Request *culprit, wmh_status st)
+{
+    for (size_t i = slot.reqs.size(); i-- > 0;) {
+        Request *r = slot.reqs[i];
+        if (r == culprit) continue;
+        inflight_bytes -= r->bytes;
+        --inflight;
+        r->retried = true;
+        queue.push_front(r);
+    }
+    complete_one(slot, *culprit, 0, st);
+    slot.reqs.clear();
     cv_done.notify_all();
 }
 
@@ -295,10 +386,11 @@ void wmh_server::run()
 {
     (void)hipSetDevice(ctx->device);
     std::unique_lock<std::mutex> lk(mu);
+    const uint64_t group_rows = cfg.group_rows ? cfg.group_rows : 2048;
     while (true) {
-        // checked requests go on to their walk; finished ones complete
+        // checked groups go on to their walk; finished ones complete
         for (Slot &slot : slots) {
-            if (!slot.req) continue;
+            if (slot.reqs.empty()) continue;
             const hipError_t q = hipEventQuery(slot.computing ? slot.finished : slot.checked);
             if (q == hipErrorNotReady) continue;
             if (q != hipSuccess) {
@@ -306,33 +398,57 @@ void wmh_server::run()
             } else if (slot.computing) {
                 complete(slot, WMH_OK);
             } else {
-                Request *r = slot.req;
+                uint64_t bad_row = ~0ull;
                 lk.unlock();
-                const wmh_status st = launch_compute(slot, *r);
+                const wmh_status st = launch_compute(slot, &bad_row);
                 lk.lock();
-                if (st != WMH_OK) complete(slot, st);
+                if (st == WMH_OK) continue;
+                // the request holding the first bad row; every other request of a group is
+                // checked again by itself
+                Request *culprit = nullptr;
+                uint64_t row0 = 0;
+                for (Request *r : slot.reqs) {
+                    if (bad_row >= row0 && bad_row < row0 + r->n_rows) culprit = r;
+                    row0 += r->n_rows;
+                }
+                if (slot.reqs.size() > 1 && culprit) release(slot, culprit, st);
+                else complete(slot, st);
             }
         }
-        // admissions, in arrival order
+        // admissions, in arrival order: the front request and the queued requests after it
+        // while their rows add up to at most group_rows
         while (!queue.empty()) {
-            Request *r = queue.front();
             Slot *free_slot = nullptr;
             for (Slot &slot : slots)
-                if (!slot.req) {
+                if (slot.reqs.empty()) {
                     free_slot = &slot;
                     break;
                 }
             if (!free_slot) break;
-            if (inflight > 0 && inflight_bytes + r->bytes > cfg.mem_budget) break;
+            Request *first = queue.front();
+            if (inflight > 0 && inflight_bytes + first->bytes > cfg.mem_budget) break;
             queue.pop_front();
-            free_slot->req = r;
-            inflight_bytes += r->bytes;
-            ++inflight;
+            free_slot->reqs.push_back(first);
+            uint64_t rows = first->n_rows, bytes = first->bytes;
+            // a request retried after its group failed the check goes alone, and joins none
+            while (!first->retried && !queue.empty() && free_slot->reqs.size() < kMaxGroup) {
+                Request *r = queue.front();
+                if (r->retried || rows + r->n_rows > group_rows ||
+                    inflight_bytes + bytes + r->bytes > cfg.mem_budget)
+                    break;
+                queue.pop_front();
+                free_slot->reqs.push_back(r);
+                rows += r->n_rows;
+                bytes += r->bytes;
+            }
+            const uint64_t now = steady_ns();
+            for (Request *r : free_slot->reqs) r->admit_ns = now;
+            if (!first_admit_ns) first_admit_ns = now;
+            inflight_bytes += bytes;
+            inflight += (uint32_t)free_slot->reqs.size();
             peak_bytes = std::max(peak_bytes, inflight_bytes);
-            r->admit_ns = steady_ns();
-            if (!first_admit_ns) first_admit_ns = r->admit_ns;
             lk.unlock();
-            const wmh_status st = launch_check(*free_slot, *r);
+            const wmh_status st = launch_check(*free_slot);
             lk.lock();
             if (st != WMH_OK) complete(*free_slot, st);
         }
@@ -565,6 +681,7 @@ wmh_status wmh_server_stats(wmh_server *srv, wmh_serving_stats *out)
     out->max_queued = srv->max_queued;
     out->peak_bytes = srv->peak_bytes;
     out->hashes = srv->hashes;
+    out->loads = srv->loads;
     std::vector<double> v = srv->latencies_ms;
     if (!v.empty()) {
         std::sort(v.begin(), v.end());
@@ -597,7 +714,7 @@ wmh_status wmh_server_reset_stats(wmh_server *srv)
     srv->completed = srv->failed = srv->rejected = 0;
     srv->max_queued = srv->queue.size();
     srv->peak_bytes = srv->inflight_bytes;
-    srv->hashes = 0;
+    srv->hashes = srv->loads = 0;
     srv->latencies_ms.clear();
     srv->on_device.clear();
     srv->computing.clear();
@@ -625,6 +742,7 @@ void wmh_server_destroy(wmh_server *srv)
         if (slot.d_val) (void)hipFree(slot.d_val);
         if (slot.d_sig) (void)hipFree(slot.d_sig);
         if (slot.h_sig) (void)hipHostFree(slot.h_sig);
+        if (slot.h_row_ptr) (void)hipHostFree(slot.h_row_ptr);
         if (slot.d_tile_counter) (void)hipFree(slot.d_tile_counter);
         if (slot.d_row_counter) (void)hipFree(slot.d_row_counter);
         if (slot.finished) (void)hipEventDestroy(slot.finished);

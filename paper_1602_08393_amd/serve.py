@@ -74,7 +74,7 @@ class Server:
 
     def __init__(self, ctx: "wmh.Context", k: int, seed: int = 0, slots: int = 8,
                  mem_budget: int = 0, mode: str = "auto", stream_depth: int = 0,
-                 build_index: bool = False):
+                 build_index: bool = False, group_rows: int = 0):
         self._lib = wmh.load()
         self.ctx = ctx
         self.k = k
@@ -86,6 +86,7 @@ class Server:
         cfg.mode = wmh.MODES[mode]
         cfg.stream_depth = stream_depth
         cfg.build_index = int(bool(build_index))
+        cfg.group_rows = group_rows
         self._ptr = ctypes.c_void_p()
         ctx._check(self._lib.wmh_server_create(ctx._ptr, ctypes.byref(cfg),
                                                ctypes.byref(self._ptr)), "wmh_server_create")

@@ -56,7 +56,7 @@ class ServerConfig(ctypes.Structure):
     _fields_ = [("k", ctypes.c_uint32), ("slots", ctypes.c_uint32), ("seed", ctypes.c_uint64),
                 ("mem_budget", ctypes.c_uint64), ("mode", ctypes.c_int32),
                 ("stream_depth", ctypes.c_uint32), ("build_index", ctypes.c_int32),
-                ("reserved", ctypes.c_uint32 * 3)]
+                ("group_rows", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 2)]
 
 
 class ServingStats(ctypes.Structure):
@@ -68,7 +68,8 @@ class ServingStats(ctypes.Structure):
                 ("max_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
                 ("busy_s", ctypes.c_double), ("hashes_per_s", ctypes.c_double),
                 ("rejected", ctypes.c_uint64), ("max_on_device", ctypes.c_uint64),
-                ("max_computing", ctypes.c_uint64), ("overlap_s", ctypes.c_double)]
+                ("max_computing", ctypes.c_uint64), ("overlap_s", ctypes.c_double),
+                ("loads", ctypes.c_uint64)]
 
 
 class TuneResult(ctypes.Structure):

@@ -156,3 +156,27 @@ def test_host_pair_estimate(lib):
     assert lib.wmh_estimate_pair(z.ctypes.data, z.ctypes.data, 0, ctypes.byref(c), None) == -1
     assert lib.wmh_estimate_pair(None, z.ctypes.data, 9, ctypes.byref(c), None) == -1
     assert lib.wmh_estimate_pair(z.ctypes.data, z.ctypes.data, 9, None, None) == -1
+
+
+@pytest.mark.parametrize("cname,py", [("wmh_opts", "WmhOpts"), ("wmh_server_config", "ServerConfig"),
+                                      ("wmh_serving_stats", "ServingStats"),
+                                      ("wmh_tune_result", "TuneResult")])
+def test_structure_layouts_match_the_header(cname, py, tmp_path):
+    """Every field of the binding's ctypes mirror sits at the offset, with the size, that a C
+    compiler gives the header's struct (a field added on one side only shifts the rest)."""
+    st = getattr(wmh, py)
+    fields = [f[0] for f in st._fields_]
+    lines = [f'printf("%zu\\n", sizeof({cname}));']
+    for f in fields:
+        lines.append(f'printf("%zu %zu\\n", offsetof({cname}, {f}), sizeof((({cname} *)0)->{f}));')
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"wmh.h\"\nint main(void) {\n"
+                   + "\n".join(lines) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    assert int(out[0]) == ctypes.sizeof(st)
+    for f, line in zip(fields, out[1:]):
+        off, size = map(int, line.split())
+        assert (getattr(st, f).offset, getattr(st, f).size) == (off, size), f

@@ -213,7 +213,8 @@ def test_requests_overlap_on_the_device(ctx):
     want = wmh.sig_to_numpy(ctx.hash(rows, k, seed=seed, mode="batched"))
     parts = [np.arange(i, ds.n_rows, 8) for i in range(8)]
     print(f"  serving overlap: {len(parts)} requests of {len(parts[0])} rows", flush=True)
-    with serve.Server(ctx, k, seed=seed, slots=4, mode="batched") as srv:
+    # one request per slot load, so that the requests themselves overlap
+    with serve.Server(ctx, k, seed=seed, slots=4, mode="batched", group_rows=1) as srv:
         reqs = serve.requests_from_corpus(ds, parts, srv, pinned=True)
         for r in reqs:
             srv.submit(r)
@@ -282,3 +283,106 @@ def test_wide_bounds_take_coarse_codes_in_the_loop(ctx):
             srv.wait(r.ticket)
     for rows, r in zip(row_lists, reqs):
         assert np.array_equal(r.sig, _oracle_sig(ds, rows, k, seed))
+
+
+def _offset_request(srv, req, lead, trail, D):
+    """The same rows with `lead` entries before them and `trail` after them in col and val
+    (out-of-range columns and huge values, which no check or walk may read): row_ptr starts at
+    `lead` and ends before the trailing entries."""
+    junk_c = np.full(lead, D + 7, np.uint32), np.full(trail, D + 9, np.uint32)
+    junk_v = np.full(lead, 0xFFFFFFFF, np.uint32), np.full(trail, 0xFFFFFFFF, np.uint32)
+    return srv.make_request(req.row_ptr + np.uint64(lead),
+                            np.concatenate([junk_c[0], req.col, junk_c[1]]),
+                            np.concatenate([junk_v[0], req.val, junk_v[1]]))
+
+
+def test_grouped_requests_equal_alone(ctx, corpus):
+    """Requests queued behind a busy slot are admitted together, their rows end to end: each
+    request's signatures equal the oracle's on its own rows, also for requests whose row_ptr
+    starts past 0 and ends before the last entry, and for requests of empty rows."""
+    k, seed = 32, 9
+    ctx.set_bounds(corpus.m)
+    rng = np.random.Generator(np.random.PCG64(19))
+    row_lists = [rng.integers(0, corpus.n_rows, size=2000)] + _rows(
+        rng, corpus.n_rows, rng.integers(1, 21, size=40))
+    with serve.Server(ctx, k, seed=seed, slots=1) as srv:
+        reqs = serve.requests_from_corpus(corpus, row_lists, srv)
+        reqs = [_offset_request(srv, r, i % 4, (i * 3) % 5, corpus.D) if i % 3 == 1 else r
+                for i, r in enumerate(reqs)]
+        empty = srv.make_request(np.zeros(4, np.uint64), np.zeros(0, np.uint32),
+                                 np.zeros(0, np.uint32))
+        reqs.insert(20, empty)
+        row_lists.insert(20, None)
+        print(f"  serving groups: {len(reqs)} requests on one slot", flush=True)
+        for r in reqs:
+            srv.submit(r)
+        srv.drain()
+        for r in reqs:
+            srv.wait(r.ticket)
+        st = srv.stats()
+    assert st["completed"] == len(reqs) and st["failed"] == 0 and st["rejected"] == 0
+    assert st["loads"] < st["completed"] // 4, st
+    for rows, r in zip(row_lists, reqs):
+        if rows is None:
+            want = oracle.hash_csr(corpus.m, np.zeros(4, np.uint64), np.zeros(0, np.uint32),
+                                   np.zeros(0, np.uint32), k, seed=seed)
+        else:
+            want = _oracle_sig(corpus, rows, k, seed)
+        assert np.array_equal(r.sig, want)
+
+
+def test_group_rows_limit(ctx, corpus):
+    """group_rows bounds the rows admitted together: with 8, requests of three rows go at
+    most two to a load; with 1, one each."""
+    k, seed = 16, 2
+    ctx.set_bounds(corpus.m)
+    rng = np.random.Generator(np.random.PCG64(23))
+    row_lists = _rows(rng, corpus.n_rows, [3] * 24)
+    for group_rows, most in ((8, 2), (1, 1)):
+        print(f"  serving group_rows={group_rows}", flush=True)
+        with serve.Server(ctx, k, seed=seed, slots=1, group_rows=group_rows) as srv:
+            reqs = serve.requests_from_corpus(corpus, row_lists, srv)
+            for r in reqs:
+                srv.submit(r)
+            srv.drain()
+            for r in reqs:
+                srv.wait(r.ticket)
+            st = srv.stats()
+        assert st["completed"] == len(reqs)
+        assert st["loads"] * most >= len(reqs), st
+        for rows, r in zip(row_lists, reqs):
+            assert np.array_equal(r.sig, _oracle_sig(corpus, rows, k, seed))
+
+
+def test_bad_request_inside_a_group(ctx, corpus):
+    """A group whose rows fail the check: the request holding the first bad row completes
+    with its rule's status, a second bad request with its own after being checked alone, and
+    every good request of the group with the oracle's signatures."""
+    k, seed = 24, 6
+    ctx.set_bounds(corpus.m)
+    rng = np.random.Generator(np.random.PCG64(29))
+    row_lists = [rng.integers(0, corpus.n_rows, size=1500)] + _rows(
+        rng, corpus.n_rows, rng.integers(1, 13, size=16))
+    with serve.Server(ctx, k, seed=seed, slots=1) as srv:
+        good = serve.requests_from_corpus(corpus, row_lists, srv)
+        far = srv.make_request(np.array([0, 1, 2], np.uint64), np.array([3, corpus.D], np.uint32),
+                               np.array([1, 1], np.uint32))
+        unsorted = srv.make_request(np.array([0, 2], np.uint64), np.array([5, 3], np.uint32),
+                                    np.array([1, 1], np.uint32))
+        for r in (far, unsorted):
+            r.sig[:] = 777
+        order = good[:6] + [far] + good[6:11] + [unsorted] + good[11:]
+        print(f"  serving a group with bad requests: {len(order)} requests", flush=True)
+        for r in order:
+            srv.submit(r)
+        for r, name in ((far, "WMH_E_COL_RANGE"), (unsorted, "WMH_E_UNSORTED")):
+            with pytest.raises(wmh.WMHError) as e:
+                srv.wait(r.ticket)
+            assert e.value.name == name
+            assert np.all(r.sig == 777)
+        for r in good:
+            srv.wait(r.ticket)
+        st = srv.stats()
+    assert st["rejected"] == 2 and st["failed"] == 0 and st["completed"] == len(good)
+    for rows, r in zip(row_lists, good):
+        assert np.array_equal(r.sig, _oracle_sig(corpus, rows, k, seed))
