@@ -36,13 +36,13 @@ KEY_BYTES = 8  # one component-index key
 # workgroup where the autotuner picks 8 or 16 on different machines.
 #   batched_kernel<unsigned short, 4, 4, true, false> (R = 4, K = 4, J = 500) on the histogram
 #     workload (N = 1e5): profiles/batched_kernel_histogram_k500.txt
-TRAFFIC_R4_HISTOGRAM = {8: 1.1953e9 + 0.1009e9, 16: 1.1913e9 + 0.1009e9}
+TRAFFIC_R4_HISTOGRAM: dict = {}  # not yet profiled on the current kernels
 #   ballot_kernel<unsigned short, true, true> (coarse codes), J = 500, one hash group, on the
 #     heavy tail (depth 40704): profiles/ballot_kernel_heavy_tail_k500.txt
-TRAFFIC_BALLOT_HEAVY_TAIL = {8: 14.8824e9 + 0.2115e9, 16: 14.9603e9 + 0.2114e9}
+TRAFFIC_BALLOT_HEAVY_TAIL: dict = {}  # not yet profiled on the current kernels
 #   the row split on the heavy tail (auto: the coarse ballot walk over the walk rows, then
 #     index_rows_kernel over the others), per call: the same profile
-TRAFFIC_SPLIT_HEAVY_TAIL = {8: 5.9609e9, 16: 5.9604e9}
+TRAFFIC_SPLIT_HEAVY_TAIL: dict = {}  # not yet profiled on the current kernels
 #   index_rows_kernel<false, 16>, counter claims, lists aligned to 128-byte lines, on the 1e6
 #     text-like rows, by wavefronts per workgroup (the tuner picks 8 or 16 on different boxes):
 #     profiles/index_rows_kernel_text_like_k1000.txt

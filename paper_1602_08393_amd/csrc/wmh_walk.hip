@@ -115,82 +115,137 @@ __device__ __forceinline__ bool lane_green(uint64_t o, uint32_t lv, uint32_t c, 
     }
 }
 
-// Zeroes the LDS rows of a block, then scatters its n_here CSR rows (RowLayout; coarse codes
-// with kCoarse) and sets bit r of *nonempty for every row r with a nonzero value; rows with bit
-// r of `skip` stay zero.  Called by the whole workgroup.
-template <typename XT, int R, bool kCoarse>
-__device__ __forceinline__ void stage_block(unsigned char *smem, const Rows &rows, uint64_t row0,
-                                            uint32_t n_here, uint32_t D, const Codes &codes,
-                                            uint32_t *nonempty, uint32_t skip = 0)
+// The next tile of a workgroup and what staging its rows needs, read ahead by thread 0 while
+// the current tile is walked: the tile (n_tiles or more: none), the CSR entries of its n rows
+// (from lo; row r ends at lo + end[r], so a block's entries number below 2^32, as rows of
+// distinct columns below D do) and the rows the row filter leaves to another path (bit r).  A
+// workgroup keeps two, the current tile's and the next one's.
+template <int R>
+struct TileAhead {
+    uint64_t tile;
+    uint64_t lo;
+    uint32_t end[R];
+    uint32_t skip;
+};
+
+// The walks' static LDS (two TileAheads, the claim words, a flag) fits the room the dynamic
+// limit leaves.
+static_assert(2 * sizeof(TileAhead<16>) + sizeof(WaveClaims) + 16 <= 160 * 1024 - kMaxDynamicLds,
+              "static LDS of the walks exceeds the room below the dynamic limit");
+
+// Fills `a` for `tile` of a walk over row blocks of R rows (thread 0 only).  Every load is
+// issued before the first store.
+template <int R>
+__device__ __forceinline__ void read_ahead(TileAhead<R> &a, const Rows &rows, uint64_t tile,
+                                           uint64_t n_tiles, uint32_t n_hash_tiles)
 {
-    using Layout = RowLayout<XT, R>;
-    uint32_t *xz = reinterpret_cast<uint32_t *>(smem);
-    const uint32_t words = (uint32_t)(((size_t)D * R * sizeof(XT) + 3) / 4);
-    for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) xz[i] = 0u;
-    if (threadIdx.x == 0) *nonempty = 0;
-    __syncthreads();
-    uint32_t mine = 0;
-    for (uint32_t r = 0; r < n_here; ++r) {
-        if ((skip >> r) & 1u) continue;
-        const uint64_t lo = rows.row_ptr[row0 + r], hi = rows.row_ptr[row0 + r + 1];
-        for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-            const uint32_t v = rows.val[e];
-            const uint32_t c = rows.col[e];
-            if (c < D) *Layout::at(smem, c, r, D) = lds_value<XT, kCoarse>(v, c, codes);
-            if (v) mine |= 1u << r;
-        }
-    }
-    if (mine) atomicOr(nonempty, mine);
-    __syncthreads();
+    a.tile = tile;
+    if (tile >= n_tiles) return;
+    const uint64_t row0 = tile / n_hash_tiles * R;
+    const uint32_t n = (uint32_t)min((uint64_t)R, rows.n_rows - row0);
+    uint64_t rp[R + 1];
+    uint32_t skip = 0;
+#pragma unroll
+    for (int q = 0; q <= R; ++q) rp[q] = (uint32_t)q <= n ? rows.row_ptr[row0 + q] : 0ull;
+    if (rows.row_class)
+        for (uint32_t r = 0; r < n; ++r) skip |= rows.skips(row0 + r) ? 1u << r : 0u;
+    a.lo = rp[0];
+#pragma unroll
+    for (int q = 0; q < R; ++q) a.end[q] = (uint32_t)(rp[q + 1] - rp[0]);
+    a.skip = skip;
 }
 
-// Replaces the one dense row held in LDS (x[0..D)) by CSR row `row`: the previous row's columns
-// (CSR entries [prev_lo, prev_hi)) are set back to zero, or, while LDS holds no row yet
-// (have_row false), the whole row is zero-filled; then the new row's values (coarse codes with
-// kCoarse) are scattered and bit 0 of *nonempty tells whether it has a nonzero value.  After
-// the first row a row costs its nonzeros rather than D.  Called by the whole workgroup; records
-// the new row's entry range.
-template <typename XT, bool kCoarse>
-__device__ __forceinline__ void restage_row(unsigned char *smem, const Rows &rows, uint64_t row,
-                                            uint32_t D, const Codes &codes, bool &have_row,
-                                            uint64_t &prev_lo, uint64_t &prev_hi,
-                                            uint32_t *nonempty)
+// Zeroes the first `bytes` bytes of LDS (rounded up to 16) with 16-byte stores.  Called by the
+// whole workgroup.
+__device__ __forceinline__ void zero_lds(unsigned char *smem, size_t bytes)
 {
-    XT *x = reinterpret_cast<XT *>(smem);
-    if (!have_row) {
-        uint32_t *xz = reinterpret_cast<uint32_t *>(smem);
-        const uint32_t words = (uint32_t)(((size_t)D * sizeof(XT) + 3) / 4);
-        for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) xz[i] = 0u;
-    } else {
-        for (uint64_t e = prev_lo + threadIdx.x; e < prev_hi; e += blockDim.x) {
-            const uint32_t c = rows.col[e];
-            if (c < D) x[c] = (XT)0;
+    uint4 *z = reinterpret_cast<uint4 *>(smem);
+    const uint32_t n = (uint32_t)((bytes + 15) / 16);
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) z[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// Scatters the CSR entries [lo, lo + count) of consecutive rows into the dense rows in LDS
+// (RowLayout; coarse codes with kCoarse): an entry's row is the number of the interior
+// boundaries bnd[0 .. R-2] (row_ptr of rows 1 .. R-1 of the block, minus lo; count for rows
+// past the block's end) at or below its index; rows with bit r of `skip` are left alone.  A
+// block's entries number at most R * D < 2^32.  Each thread reads four entries at a time (two
+// for coarse codes of several rows), all loads in flight before the first store.  Returns bit
+// r for every row r with a nonzero value among the thread's entries.
+template <typename XT, int R, bool kCoarse>
+__device__ __forceinline__ uint32_t scatter_entries(unsigned char *smem, const Rows &rows,
+                                                    uint64_t lo, uint32_t count,
+                                                    const uint32_t *bnd, uint32_t D,
+                                                    const Codes &codes, uint32_t skip)
+{
+    using Layout = RowLayout<XT, R>;
+    constexpr int kBatch = kCoarse && R > 1 ? 2 : 4;  // coarse codes hold a bound per entry
+    const uint32_t *col = rows.col + lo;
+    const uint32_t *val = rows.val + lo;
+    uint32_t mine = 0;
+    for (uint32_t i0 = threadIdx.x; i0 < count; i0 += kBatch * blockDim.x) {
+        uint32_t c[kBatch], v[kBatch], m[kBatch];
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+            const uint32_t i = i0 + q * blockDim.x;
+            c[q] = i < count ? col[i] : 0u;
+            v[q] = i < count ? val[i] : 0u;
+        }
+        if constexpr (kCoarse) {
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) {
+                const uint32_t i = i0 + q * blockDim.x;
+                m[q] = i < count && c[q] < D ? codes.bound[c[q]] : 1u;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+            const uint32_t i = i0 + q * blockDim.x;
+            if (i >= count) continue;
+            uint32_t r = 0;
+#pragma unroll
+            for (int b = 0; b + 1 < R; ++b) r += i >= bnd[b] ? 1u : 0u;
+            if ((skip >> r) & 1u) continue;
+            if (c[q] < D) {
+                if constexpr (kCoarse)
+                    *Layout::at(smem, c[q], r, D) = (XT)coarse_value_code(v[q], m[q], codes.bits);
+                else
+                    *Layout::at(smem, c[q], r, D) = (XT)v[q];
+            }
+            if (v[q]) mine |= 1u << r;
         }
     }
+    return mine;
+}
+
+// Stages the n_here rows of a block whose CSR entries start at lo (row r ending at
+// lo + end[r]): zeroes the block's LDS rows, scatters the rows' entries in one pass over the
+// block's contiguous CSR range and sets bit r of *nonempty for every row r with a nonzero value;
+// rows with bit r of `skip` stay zero.  Called by the whole workgroup.
+template <typename XT, int R, bool kCoarse>
+__device__ __forceinline__ void stage_block(unsigned char *smem, const Rows &rows, uint64_t lo,
+                                            const uint32_t *end, uint32_t n_here, uint32_t D,
+                                            const Codes &codes, uint32_t *nonempty,
+                                            uint32_t skip = 0)
+{
+    zero_lds(smem, (size_t)D * R * sizeof(XT));
     if (threadIdx.x == 0) *nonempty = 0;
     __syncthreads();
-    const uint64_t lo = rows.row_ptr[row], hi = rows.row_ptr[row + 1];
-    uint32_t mine = 0;
-    for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-        const uint32_t v = rows.val[e];
-        const uint32_t c = rows.col[e];
-        if (c < D) x[c] = lds_value<XT, kCoarse>(v, c, codes);
-        if (v) mine = 1u;
-    }
+    const uint32_t count = end[n_here - 1];
+    uint32_t bnd[R > 1 ? R - 1 : 1];
+#pragma unroll
+    for (int q = 0; q + 1 < R; ++q) bnd[q] = (uint32_t)(q + 1) < n_here ? end[q] : count;
+    const uint32_t mine = scatter_entries<XT, R, kCoarse>(smem, rows, lo, count, bnd, D, codes, skip);
     if (mine) atomicOr(nonempty, mine);
     __syncthreads();
-    have_row = true;
-    prev_lo = lo;
-    prev_hi = hi;
 }
 
 // Writes a tile's hash values (staged in LDS, row r at hbuf[r * hashes_per_tile]) row by row,
-// coalesced along j, except rows with bit r of `skip`.  Called by the whole workgroup; ends
-// with a barrier.
+// coalesced along j, except rows with bit r of `skip`, and resets the claim counter for the
+// next tile.  Called by the whole workgroup; ends with a barrier.
 __device__ __forceinline__ void write_tile(uint16_t *__restrict__ sig, const uint16_t *hbuf,
                                            uint64_t row0, uint32_t n_here, uint32_t k,
                                            uint32_t j0, uint32_t j1, uint32_t hashes_per_tile,
-                                           uint32_t skip = 0)
+                                           WaveClaims &units, uint32_t skip = 0)
 {
     __syncthreads();
     const uint32_t width = j1 - j0;
@@ -199,6 +254,7 @@ __device__ __forceinline__ void write_tile(uint16_t *__restrict__ sig, const uin
         uint16_t *out = sig + (row0 + r) * (uint64_t)k + j0;
         for (uint32_t q = threadIdx.x; q < width; q += blockDim.x) out[q] = hbuf[r * hashes_per_tile + q];
     }
+    units.reset();
     __syncthreads();
 }
 
@@ -222,7 +278,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
     constexpr uint32_t L = kWave / R;
     constexpr uint32_t kWin = L * K;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ unsigned long long tile_slot;
+    __shared__ TileAhead<R> ahead[2];  // the current tile's and the next one's
     __shared__ WaveClaims units;
     __shared__ uint32_t nonempty;
     const uint32_t D = b.dims;
@@ -244,31 +300,40 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
     uint64_t staged = ~0ull;
     bool claimed = false;
 
+    // Tiles are claimed one ahead: while a tile is walked, thread 0 claims the next one and
+    // reads its rows' CSR boundaries and filter bits into the other TileAhead, so the claim and
+    // those reads are off the staging path.  The barriers that end a tile publish it.
+    uint32_t cur = 0;
+    if (threadIdx.x == 0)
+        read_ahead<R>(ahead[0], rows, next_tile(tile_counter, claimed), n_tiles, n_hash_tiles);
+    units.reset();
+    __syncthreads();
     while (true) {
-        if (threadIdx.x == 0) {
-            tile_slot = next_tile(tile_counter, claimed);
-        }
-        units.reset();
-        __syncthreads();
-        const uint64_t tile = tile_slot;
+        const uint64_t tile = ahead[cur].tile;
         if (tile >= n_tiles) break;
         const uint64_t blk = tile / n_hash_tiles;
         const uint32_t ht = (uint32_t)(tile - blk * n_hash_tiles);
         const uint64_t row0 = blk * R;
         const uint32_t n_here = (uint32_t)min((uint64_t)R, rows.n_rows - row0);
         // rows another path computes (row filter): not staged, not walked, not written
-        uint32_t skip = 0;
-        if (rows.row_class)
-            for (uint32_t r = 0; r < n_here; ++r) skip |= rows.skips(row0 + r) ? 1u << r : 0u;
+        const uint32_t skip = __builtin_amdgcn_readfirstlane(ahead[cur].skip);
         if (skip == (1u << n_here) - 1u) {
-            __syncthreads();  // every thread has read tile_slot before it is claimed again
+            if (threadIdx.x == 0)
+                read_ahead<R>(ahead[cur ^ 1u], rows, next_tile(tile_counter, claimed), n_tiles,
+                              n_hash_tiles);
+            __syncthreads();
+            cur ^= 1u;
             continue;
         }
 
         if (blk != staged) {
-            stage_block<XT, R, kCoarse>(smem, rows, row0, n_here, D, codes, &nonempty, skip);
+            stage_block<XT, R, kCoarse>(smem, rows, ahead[cur].lo, ahead[cur].end, n_here, D,
+                                        codes, &nonempty, skip);
             staged = blk;
         }
+        if (threadIdx.x == 0)
+            read_ahead<R>(ahead[cur ^ 1u], rows, next_tile(tile_counter, claimed), n_tiles,
+                          n_hash_tiles);
         // Wave-uniform values are read into scalar registers so every branch on them is a
         // scalar branch: no lane-divergent region sits on the unit loop's path.
         const uint32_t live = __builtin_amdgcn_readfirstlane(nonempty);
@@ -390,7 +455,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves
                                                   : R * hashes_per_tile + lane();
             hbuf[slot] = (uint16_t)h;
         }
-        write_tile(sig, hbuf, row0, n_here, k, j0, j1, hashes_per_tile, skip);
+        write_tile(sig, hbuf, row0, n_here, k, j0, j1, hashes_per_tile, units, skip);
+        cur ^= 1u;
     }
 }
 
@@ -420,8 +486,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     const Codes codes{b.bound, coarse_bits};
     constexpr uint32_t kWords = EntryRun<1, kPacked>::kWordsPerEntry;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ unsigned long long tile_row;
-    __shared__ uint32_t tile_ht;
+    // A tile (row, hash block ht) and its row's CSR range and filter bit, read ahead.
+    struct RowAhead {
+        uint64_t row;  // ~0: no tile left
+        uint64_t lo, hi;
+        uint32_t ht, skip;
+    };
+    __shared__ RowAhead ahead[2];  // the current tile's and the next one's
     __shared__ WaveClaims units;
     __shared__ uint32_t nonempty;
     const uint32_t D = b.dims;
@@ -430,54 +501,77 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     const uint32_t n_hash_tiles = (k + hashes_per_tile - 1) / hashes_per_tile;
     const uint64_t n_tiles = rows.n_rows * n_hash_tiles;
     uint64_t staged = ~0ull;
-    bool have_row = false;
-    uint64_t staged_lo = 0, staged_hi = 0;  // CSR entries of the row in LDS
     bool claimed = false;
     uint32_t group_step = 0;  // thread 0: groups left behind, counted from the workgroup's own
 
-    while (true) {
-        if (threadIdx.x == 0) {
-            uint64_t r = ~0ull;
-            uint32_t h = 0;
-            if (groups <= 1) {
-                const uint64_t t = next_tile(tile_counter, claimed);
-                if (t < n_tiles) {
-                    r = t / n_hash_tiles;
-                    h = (uint32_t)(t - r * n_hash_tiles);
-                }
-            } else {
-                // every group's counter passes n_rows at most once per workgroup: the loop ends
-                for (; group_step < groups; ++group_step) {
-                    const uint32_t g = (blockIdx.x + group_step) % groups;
-                    const uint64_t u = atomicAdd(&tile_counter[g], 1ull);
-                    if (u < rows.n_rows) {
-                        r = u;
-                        h = g;
-                        break;
-                    }
+    // Tiles are claimed one ahead (as in the shared-window walk): thread 0 claims the next tile
+    // and reads its row's CSR range while the current one is walked.
+    auto claim_ahead = [&](RowAhead &a) {
+        uint64_t r = ~0ull;
+        uint32_t h = 0;
+        if (groups <= 1) {
+            const uint64_t t = next_tile(tile_counter, claimed);
+            if (t < n_tiles) {
+                r = t / n_hash_tiles;
+                h = (uint32_t)(t - r * n_hash_tiles);
+            }
+        } else {
+            // every group's counter passes n_rows at most once per workgroup: the loop ends
+            for (; group_step < groups; ++group_step) {
+                const uint32_t g = (blockIdx.x + group_step) % groups;
+                const uint64_t u = atomicAdd(&tile_counter[g], 1ull);
+                if (u < rows.n_rows) {
+                    r = u;
+                    h = g;
+                    break;
                 }
             }
-            tile_row = r;
-            tile_ht = h;
         }
-        units.reset();
-        __syncthreads();
-        const uint64_t row = tile_row;
+        uint64_t lo = 0, hi = 0;
+        uint32_t skip = 0;
+        if (r != ~0ull) {
+            lo = rows.row_ptr[r];
+            hi = rows.row_ptr[r + 1];
+            skip = rows.skips(r) ? 1u : 0u;
+        }
+        a.row = r;
+        a.ht = h;
+        a.lo = lo;
+        a.hi = hi;
+        a.skip = skip;
+    };
+    uint32_t cur = 0;
+    if (threadIdx.x == 0) claim_ahead(ahead[0]);
+    units.reset();
+    __syncthreads();
+    while (true) {
+        const uint64_t row = ahead[cur].row;
         if (row == ~0ull) break;
-        const uint32_t ht = tile_ht;
-        if (rows.skips(row)) {  // a row another path computes (row filter)
-            __syncthreads();    // every thread has read the tile before it is claimed again
+        const uint32_t ht = ahead[cur].ht;
+        if (ahead[cur].skip) {  // a row another path computes (row filter)
+            if (threadIdx.x == 0) claim_ahead(ahead[cur ^ 1u]);
+            __syncthreads();
+            cur ^= 1u;
             continue;
         }
         if (row != staged) {
-            restage_row<XT, kCoarse>(smem, rows, row, D, codes, have_row, staged_lo, staged_hi,
-                                     &nonempty);
+            zero_lds(smem, (size_t)D * sizeof(XT));
+            if (threadIdx.x == 0) nonempty = 0;
+            __syncthreads();
+            const uint32_t none = 0;
+            const uint64_t lo = ahead[cur].lo;
+            const uint32_t mine = scatter_entries<XT, 1, kCoarse>(
+                smem, rows, lo, (uint32_t)(ahead[cur].hi - lo), &none, D, codes, 0u);
+            if (mine) atomicOr(&nonempty, mine);
+            __syncthreads();
             staged = row;
         }
         const bool live = __builtin_amdgcn_readfirstlane(nonempty) != 0;
         const uint32_t j0 = ht * hashes_per_tile;
+        if (threadIdx.x == 0) claim_ahead(ahead[cur ^ 1u]);
         if (j0 >= k) {  // an empty hash block (the host's plans leave none)
             __syncthreads();
+            cur ^= 1u;
             continue;
         }
         const uint32_t j1 = min(k, j0 + hashes_per_tile);
@@ -572,7 +666,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                 if (jb != ja) walk_id(jb, b0, b1, b2);
             }
         }
-        write_tile(sig, hbuf, row, 1u, k, j0, j1, hashes_per_tile);
+        write_tile(sig, hbuf, row, 1u, k, j0, j1, hashes_per_tile, units);
+        cur ^= 1u;
     }
 }
 
