@@ -35,14 +35,17 @@ KEY_BYTES = 8  # one component-index key
 # kernel and plan are the ones timed; the line carries null otherwise.  Keyed by wavefronts per
 # workgroup where the autotuner picks 8 or 16 on different machines.
 #   batched_kernel<unsigned short, 4, 4, true, false> (R = 4, K = 4, J = 500) on the histogram
-#     workload (N = 1e5): profiles/batched_kernel_histogram_k500.txt
-TRAFFIC_R4_HISTOGRAM: dict = {}  # not yet profiled on the current kernels
+#     workload (N = 1e5): profiles/batched_and_ballot_kernels_histogram_k500.txt
+TRAFFIC_R4_HISTOGRAM = {8: 1.2016e9 + 0.1009e9, 16: 1.1880e9 + 0.1009e9}
+#   ballot_kernel<unsigned short, true, false> (exact 16-bit rows), J = 500, one hash group, on
+#     the same workload (the autotuner picks it there on some boxes): the same profile
+TRAFFIC_BALLOT_HISTOGRAM = {8: 1.1479e9 + 0.1055e9, 16: 1.1475e9 + 0.1054e9}
 #   ballot_kernel<unsigned short, true, true> (coarse codes), J = 500, one hash group, on the
 #     heavy tail (depth 40704): profiles/ballot_kernel_heavy_tail_k500.txt
-TRAFFIC_BALLOT_HEAVY_TAIL: dict = {}  # not yet profiled on the current kernels
+TRAFFIC_BALLOT_HEAVY_TAIL = {8: 13.7591e9 + 0.2114e9, 16: 13.8838e9 + 0.2115e9}
 #   the row split on the heavy tail (auto: the coarse ballot walk over the walk rows, then
 #     index_rows_kernel over the others), per call: the same profile
-TRAFFIC_SPLIT_HEAVY_TAIL: dict = {}  # not yet profiled on the current kernels
+TRAFFIC_SPLIT_HEAVY_TAIL = {8: 5.0659e9, 16: 5.0617e9}
 #   index_rows_kernel<false, 16>, counter claims, lists aligned to 128-byte lines, on the 1e6
 #     text-like rows, by wavefronts per workgroup (the tuner picks 8 or 16 on different boxes):
 #     profiles/index_rows_kernel_text_like_k1000.txt
@@ -772,9 +775,18 @@ def main():
             f"{np.mean(walk):.3f} ms")
 
     main_key = "batched" if "batched" in result else "plain"
-    profiled_plan = (main_key == "batched" and batched_plan["rows_per_block"] == 4
-                     and batched_plan["steps_per_lane"] == 4
-                     and batched_plan["hashes_per_tile"] == 500 and ds.n_rows == 100_000)
+    # the walk kernel of the plan, and its HBM traffic when profiled for this workload
+    walk_kernel, traffic = "plain_kernel", None
+    if main_key == "batched":
+        walk_kernel = {"shared": "batched_kernel", "ballot": "ballot_kernel",
+                       "rows": "rows_kernel"}.get(batched_plan["walk"], "batched_kernel")
+        full_size = batched_plan["hashes_per_tile"] == 500 and ds.n_rows == 100_000
+        if (full_size and batched_plan["walk"] == "shared" and batched_plan["rows_per_block"] == 4
+                and batched_plan["steps_per_lane"] == 4):
+            traffic = TRAFFIC_R4_HISTOGRAM.get(batched_plan["waves_per_block"])
+        if (full_size and batched_plan["walk"] == "ballot" and batched_plan["values"] == "exact"
+                and batched_plan["hash_groups"] == 1):
+            traffic = TRAFFIC_BALLOT_HISTOGRAM.get(batched_plan["waves_per_block"])
     steps = args.steps if main_key == "batched" else result["plain"][2]
     el, walk, _ = result[main_key][:3]
     value = hashes * steps / el
@@ -801,10 +813,7 @@ def main():
                                "seed 0",
                    "N": ds.n_rows, "D": ds.D, "k": k, "nnz": ds.nnz, "M": M,
                    "mode": main_key},
-        "roofline": alu_roofline(
-            tests, walk_s * 1e3, "batched_kernel" if main_key == "batched" else "plain_kernel",
-            traffic=TRAFFIC_R4_HISTOGRAM.get(batched_plan["waves_per_block"])
-            if profiled_plan else None),
+        "roofline": alu_roofline(tests, walk_s * 1e3, walk_kernel, traffic=traffic),
         "mean_steps_per_hash": tests / hashes,
     }
     if "batched" in result and "plain" in result:
