@@ -364,9 +364,10 @@ void wmh_server::complete(Slot &slot, wmh_status st)
     cv_done.notify_all();
 }
 
-// A group whose rows failed the check: the request holding the first bad row completes with
-// the check's status, the others go back to the front of the queue in arrival order, marked to
-// be admitted alone (their rows are checked again by themselves).  Called with mu held.
+// A group that cannot go on together: the culprit, if any (the request holding the first bad
+// row of a failed check), completes with status st; the others go back to the front of the
+// queue in arrival order, marked to be admitted alone (their rows are checked again by
+// themselves).  Called with mu held.
 void wmh_server::release(Slot &slot, Request *culprit, wmh_status st)
 {
     for (size_t i = slot.reqs.size(); i-- > 0;) {
@@ -377,7 +378,7 @@ void wmh_server::release(Slot &slot, Request *culprit, wmh_status st)
         r->retried = true;
         queue.push_front(r);
     }
-    complete_one(slot, *culprit, 0, st);
+    if (culprit) complete_one(slot, *culprit, 0, st);
     slot.reqs.clear();
     cv_done.notify_all();
 }
@@ -450,7 +451,9 @@ void wmh_server::run()
             lk.unlock();
             const wmh_status st = launch_check(*free_slot);
             lk.lock();
-            if (st != WMH_OK) complete(*free_slot, st);
+            // a group whose buffers do not fit is admitted again one request at a time
+            if (st == WMH_E_NOMEM && free_slot->reqs.size() > 1) release(*free_slot, nullptr, st);
+            else if (st != WMH_OK) complete(*free_slot, st);
         }
         if (stopping && queue.empty() && inflight == 0) break;
         if (inflight > 0) {
