@@ -33,13 +33,16 @@ KEY_BYTES = 8  # one component-index key
 # HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the same counters on
 # a 1 GiB device-to-device copy (read x2.000, write x1.000).  Each figure is valid while its
 # kernel and plan are the ones timed; the line carries null otherwise.  Keyed by wavefronts per
-# workgroup where the autotuner picks 8 or 16 on different machines.
-#   batched_kernel<unsigned short, 4, 4, true, false> (R = 4, K = 4, J = 500) on the histogram
-#     workload (N = 1e5): profiles/batched_and_ballot_kernels_histogram_k500.txt
-TRAFFIC_R4_HISTOGRAM = {8: 1.2016e9 + 0.1009e9, 16: 1.1880e9 + 0.1009e9}
-#   ballot_kernel<unsigned short, true, false> (exact 16-bit rows), J = 500, one hash group, on
-#     the same workload (the autotuner picks it there on some boxes): the same profile
-TRAFFIC_BALLOT_HISTOGRAM = {8: 1.1479e9 + 0.1055e9, 16: 1.1475e9 + 0.1054e9}
+# workgroup (and, on the histogram, hash ids per tile) where the autotuner picks differently on
+# different machines.
+#   batched_kernel<unsigned short, 4, 4, true, false> (R = 4, K = 4), by (J, W), on the
+#     histogram workload (N = 1e5): profiles/batched_and_ballot_kernels_histogram_k500.txt
+#     (J = 256 stages every row block twice, so it reads the rows twice)
+TRAFFIC_R4_HISTOGRAM = {(500, 8): 1.3025e9, (500, 16): 1.2889e9, (256, 8): 2.2311e9,
+                        (256, 16): 2.1878e9}
+#   ballot_kernel<unsigned short, true, false> (exact 16-bit rows), one hash group, by (J, W),
+#     on the same workload (the autotuner picks it there on some boxes): the same profile
+TRAFFIC_BALLOT_HISTOGRAM = {(500, 8): 1.2534e9, (500, 16): 1.2529e9, (256, 8): 2.2060e9}
 #   ballot_kernel<unsigned short, true, true> (coarse codes), J = 500, one hash group, on the
 #     heavy tail (depth 40704): profiles/ballot_kernel_heavy_tail_k500.txt
 TRAFFIC_BALLOT_HEAVY_TAIL = {8: 13.7591e9 + 0.2114e9, 16: 13.8838e9 + 0.2115e9}
@@ -780,13 +783,14 @@ def main():
     if main_key == "batched":
         walk_kernel = {"shared": "batched_kernel", "ballot": "ballot_kernel",
                        "rows": "rows_kernel"}.get(batched_plan["walk"], "batched_kernel")
-        full_size = batched_plan["hashes_per_tile"] == 500 and ds.n_rows == 100_000
+        full_size = ds.n_rows == 100_000 and k == 500
+        jw = (batched_plan["hashes_per_tile"], batched_plan["waves_per_block"])
         if (full_size and batched_plan["walk"] == "shared" and batched_plan["rows_per_block"] == 4
                 and batched_plan["steps_per_lane"] == 4):
-            traffic = TRAFFIC_R4_HISTOGRAM.get(batched_plan["waves_per_block"])
+            traffic = TRAFFIC_R4_HISTOGRAM.get(jw)
         if (full_size and batched_plan["walk"] == "ballot" and batched_plan["values"] == "exact"
                 and batched_plan["hash_groups"] == 1):
-            traffic = TRAFFIC_BALLOT_HISTOGRAM.get(batched_plan["waves_per_block"])
+            traffic = TRAFFIC_BALLOT_HISTOGRAM.get(jw)
     steps = args.steps if main_key == "batched" else result["plain"][2]
     el, walk, _ = result[main_key][:3]
     value = hashes * steps / el
