@@ -536,10 +536,10 @@ typedef struct {
     double busy_s;         /* first admission -> last completion */
     double hashes_per_s;   /* hashes / busy_s */
     uint64_t rejected;     /* requests whose rows failed the device check (not in failed) */
-    /* Overlap on the device, from HIP event timestamps on each request's slot stream: a
-     * request is on the device from its first copy in to the end of its copy out, and
-     * computing from the start of its walk to the end of its copy out (both include time its
-     * work waits in the device queues behind other slots' work). */
+    /* Overlap on the device, from HIP event timestamps on each slot's stream: a slot load (a
+     * request, or requests admitted together) is on the device from its first copy in to the
+     * end of its copy out, and computing from the start of its walk to the end of its copy
+     * out (both include time its work waits in the device queues behind other slots' work). */
     uint64_t max_on_device;  /* most completed slot loads (a request, or requests admitted
                                 together) on the device at one instant */
     uint64_t max_computing;  /* most completed slot loads computing at one instant */
@@ -554,7 +554,8 @@ typedef struct {
  * up to group_rows rows together, as one group), runs each group's walk on its slot's stream
  * (so groups overlap on the device), and completes the requests as their results arrive.  A
  * group whose rows fail the device check completes the request with the first bad row with
- * that status and checks each of the others again alone.  Bounds, bucket table and the shared
+ * that status and checks each of the others again alone; a group whose slot buffers cannot be
+ * allocated is admitted again one request at a time.  Bounds, bucket table and the shared
  * position stream stay device-resident.
  * Errors: WMH_E_ARG, WMH_E_NO_BOUNDS, WMH_E_NOMEM, WMH_E_DEVICE.
  */
