@@ -489,6 +489,60 @@ def test_validation_errors_leave_output_untouched(ctx, rp, col, val, status):
         assert "row" in ctx.last_error()
 
 
+def test_large_dimension_validation(ctx):
+    """Bounds too large for LDS (D = 70000: the validation pass gathers them from memory):
+    values at their bound, between a small block neighbour's bound and their own, and small
+    ones pass and hash as the oracle does in every mode that holds such rows (plain walk,
+    index, auto); a value one above its bound fails with WMH_E_BOUND at the right row, as do a
+    column out of range and unsorted columns, and the output stays untouched."""
+    rng = np.random.Generator(np.random.PCG64(70))
+    D = 70000
+    m = rng.integers(1000, 200000, size=D).astype(np.uint32)
+    m[::7] = 5  # small bounds between large ones
+    ctx.set_bounds(m)
+    N, k, seed = 40, 32, 11
+    cols, vals = [], []
+    for r in range(N):
+        c = np.sort(rng.choice(D, size=int(rng.integers(1, 300)), replace=False)).astype(np.uint32)
+        kind = r % 3
+        if kind == 0:
+            v = m[c]  # at the bound
+        elif kind == 1:
+            v = np.maximum(1, m[c] // 2)
+        else:
+            v = np.minimum(m[c], 5)
+        cols.append(c)
+        vals.append(v.astype(np.uint32))
+    ds = synth.csr_from_lists(cols, vals, D)
+    ds.m[:] = m
+    want = oracle.hash_csr(m, ds.row_ptr, ds.col, ds.val, k, seed=seed)
+    # (no batched plan holds 70000 dense components in LDS)
+    for mode in ("plain", "indexed", "auto"):
+        assert_same(gpu_sig(ctx, ds, k, seed, mode=mode), want, f"D={D} {mode}")
+
+    big = np.flatnonzero(m > 10000)
+    c_bad = int(big[len(big) // 2])
+    bad_cols = [c.copy() for c in cols]
+    bad_vals = [v.copy() for v in vals]
+    bad_cols[17] = np.array([c_bad], np.uint32)
+    bad_vals[17] = np.array([int(m[c_bad]) + 1], np.uint32)
+    for cc, vv, status, row in (
+            (bad_cols, bad_vals, "WMH_E_BOUND", 17),
+            ([np.array([3, D], np.uint32)] + cols[1:], [np.array([1, 1], np.uint32)] + vals[1:],
+             "WMH_E_COL_RANGE", 0),
+            (cols[:5] + [np.array([9, 4], np.uint32)] + cols[6:],
+             vals[:5] + [np.array([1, 1], np.uint32)] + vals[6:], "WMH_E_UNSORTED", 5)):
+        bad = synth.csr_from_lists(cc, vv, D, m=m)
+        rows = wmh.upload_dataset(bad, DEV)
+        for mode in ("plain", "indexed", "auto"):
+            sig = torch.full((N, k), 0x5A5A, dtype=torch.int16, device=DEV)
+            with pytest.raises(wmh.WMHError) as e:
+                ctx.hash_into(rows, k, seed, sig, opts=ctx.make_opts(mode=mode))
+            assert e.value.name == status, ctx.last_error()
+            assert f"row {row}" in ctx.last_error(), ctx.last_error()
+            assert torch.all(sig == 0x5A5A)
+
+
 def test_empty_rows_and_empty_batch(ctx):
     m = np.array([3, 4], dtype=np.uint32)
     ds = synth.csr_from_dense(np.zeros((5, 2), dtype=np.uint32), m=m)
