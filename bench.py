@@ -691,8 +691,9 @@ def oracle_on_head(ds, n, k, gpu_sig_head):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the hash walk "
-              "shards by rows with no exchange step, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the walk shards "
+              "by rows, each GPU hashing its own rows against replicated bounds tables with no "
+              "exchange step, so one GPU's figure is its share", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
