@@ -57,6 +57,20 @@ def test_plans_and_empty_rows(ctx):
         assert np.array_equal(got, want), plan
 
 
+def test_coarse_code_ties_without_allocation(ctx):
+    """Coarse codes of 2 bits make most tested steps in a row's support tie: the no-allocation
+    walk settles them exactly (in-lane draws and the row's CSR value), as wmh_hash and the
+    oracle do, with the ballot walk and the shared windows."""
+    ds = synth.random_case(23, 200, 2048, 0.05, 1 << 20, bound_slack=1 << 18)
+    exact = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, 64, seed=9)
+    for plan in ({"values": "coarse", "coarse_bits": 2, "walk": "ballot"},
+                 {"values": "coarse", "coarse_bits": 2, "rows_per_block": 4}):
+        want, got = both(ctx, ds, 64, seed=9, **plan)
+        assert np.array_equal(got, want), plan
+        assert np.array_equal(got, exact), plan
+        assert ctx.last_plan()["coarse_bits"] == 2
+
+
 def test_stream_shrinks_to_the_static_array(ctx):
     # tiny green fractions: the planner's stream (about 65000 steps x 128 ids x 4 or 8 bytes)
     # is larger than the static array, so the call walks a shorter stream and draws in-lane
