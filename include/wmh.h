@@ -112,7 +112,10 @@ typedef struct {
                                   their components for steps t <= T0 of every hash id, built
                                   once per (seed, k, T0, bounds) and kept in the context);
                                   rounded up to whole cycles of three walk windows and kept
-                                  below 65535; steps beyond it are drawn in-lane.  UINT32_MAX:
+                                  below 65535; steps beyond it are drawn in-lane.  The
+                                  planner's depth (0) keeps the stream within 1 GiB, and is 0
+                                  when one cycle of k hash ids would exceed it (except for the
+                                  independent-rows walk, which keeps one cycle).  UINT32_MAX:
                                   no stream (every step drawn in-lane; the independent-rows
                                   walk keeps one cycle) */
     uint32_t waves_per_block;  /* wavefronts per workgroup (1..16) */

@@ -200,8 +200,13 @@ static bool plan_rows(const wmh_ctx *ctx, uint32_t k, const RowStats &stats, con
     } else {
         depth = 4096 / cycle * cycle;
     }
-    while (depth > cycle && (uint64_t)depth * k * (p.packed ? 4 : 8) > kStreamBudgetBytes)
-        depth -= cycle;
+    const uint64_t entry = p.packed ? 4 : 8;
+    while (depth > cycle && (uint64_t)depth * k * entry > kStreamBudgetBytes) depth -= cycle;
+    // the planner's stream stays within the budget: with so many hash ids that one cycle does
+    // not fit, every step is drawn in-lane (the independent-rows walk reads the stream)
+    if (o.stream_depth == 0 && !p.independent_rows &&
+        (uint64_t)depth * k * entry > kStreamBudgetBytes)
+        depth = 0;
     p.stream_depth = depth;
     *plan = p;
     return true;

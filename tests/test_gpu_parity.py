@@ -553,6 +553,26 @@ def test_empty_rows_and_empty_batch(ctx):
     ctx.hash_into(rows, 10, 0, torch.empty(0, dtype=torch.int16, device=DEV))
 
 
+def test_largest_k(ctx):
+    """k at its largest, 2^24, on a row with x = m in every dimension: every position is green,
+    so every hash is 1 (Def. 1), under the plain walk, the batched walk and auto.  The batched
+    planner keeps no shared stream here (one cycle of 2^24 hash ids would exceed its 1 GiB), so
+    every step is drawn in-lane.  One more hash id is refused."""
+    m = np.array([5, 1, 300, 7, 65535], dtype=np.uint32)
+    ds = synth.csr_from_dense(m[None, :].copy(), m=m)
+    k = 1 << 24
+    for mode in ("plain", "batched", "auto"):
+        got = gpu_sig(ctx, ds, k, 3, mode=mode)
+        assert got.shape == (1, k), mode
+        assert np.all(got == 1), (mode, np.flatnonzero(got != 1)[:5])
+        if mode == "batched":
+            assert ctx.last_plan()["stream_depth"] == 0, ctx.last_plan()
+    rows = wmh.upload_dataset(ds, DEV)
+    with pytest.raises(wmh.WMHError) as e:
+        ctx.hash(rows, k + 1)
+    assert e.value.name == "WMH_E_ARG"
+
+
 def test_bad_arguments(ctx):
     fresh = wmh.Context(0)
     rows = _rows([0, 1], [0], [1])
