@@ -553,6 +553,38 @@ def test_empty_rows_and_empty_batch(ctx):
     ctx.hash_into(rows, 10, 0, torch.empty(0, dtype=torch.int16, device=DEV))
 
 
+def test_largest_dimension(ctx):
+    """D at its largest, 2^26, with the last bound at 2^32 - 1 (the last piece, the end of the
+    prefix P and of the bucket table): a row of 2^20 + 2 nonzeros spread over the whole range,
+    a row holding only the last component (green fraction about 1/18), an empty row and a row
+    too light to find a green step (every hash saturates) equal the oracle under the plain
+    walk, the component index (lists of 2^26 components) and auto; no batched plan holds such
+    rows, and D = 2^26 + 1 is refused."""
+    D = 1 << 26
+    rng = np.random.Generator(np.random.PCG64(77))
+    m = rng.integers(1, 1000, size=D, dtype=np.uint32)
+    m[D - 1] = 0xFFFFFFFF
+    c0 = np.unique(np.concatenate([rng.choice(D - 1, size=1 << 20, replace=False),
+                                   [0, D - 1]])).astype(np.uint32)
+    c3 = np.array([0, 1, 2, D - 3, D - 2], np.uint32)
+    ds = synth.csr_from_lists(
+        [c0, np.array([D - 1], np.uint32), np.zeros(0, np.uint32), c3],
+        [m[c0] // 2 + 1, np.array([1 << 31], np.uint32), np.zeros(0, np.uint32), m[c3]],
+        D, m=m, name="largest-D", k=16)
+    k, seed = 16, 21
+    want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, k, seed=seed)
+    assert np.all(want[3] == 65535) and np.all(want[2] == 0) and want[1].max() < 1000
+    for mode in ("plain", "indexed", "auto"):
+        assert_same(gpu_sig(ctx, ds, k, seed, mode=mode), want, f"D=2^26 {mode}")
+    rows = wmh.upload_dataset(ds, DEV)
+    with pytest.raises(wmh.WMHError) as e:
+        ctx.hash(rows, k, seed=seed, mode="batched")
+    assert e.value.name == "WMH_E_ARG"
+    with pytest.raises(wmh.WMHError) as e:
+        ctx.set_bounds(np.ones(D + 1, dtype=np.uint32))
+    assert e.value.name == "WMH_E_ARG"
+
+
 def test_largest_k(ctx):
     """k at its largest, 2^24, on a row with x = m in every dimension: every position is green,
     so every hash is 1 (Def. 1), under the plain walk, the batched walk and auto.  The batched
