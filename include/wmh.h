@@ -518,7 +518,8 @@ typedef struct {
     int32_t mode;          /* wmh_mode of every request's walk; 0 = auto (a row split is not
                               available in the loop) */
     uint32_t stream_depth; /* steps of the shared position stream built once at creation;
-                              0 = 8192 (steps beyond are drawn in-lane) */
+                              0 = 8192, cut to stay within 1 GiB, and no stream when one cycle
+                              of k hash ids exceeds that (steps beyond are drawn in-lane) */
     int32_t build_index;   /* 1: build the component index at creation (auto or indexed mode),
                               so no request waits for it; 0: on the first indexed request */
     uint32_t group_rows;   /* queued requests admitted together into one slot while their rows

@@ -513,17 +513,22 @@ wmh_status wmh_server_create(wmh_ctx *ctx, const wmh_server_config *cfg_in, wmh_
         delete srv;
         return fail(ctx, WMH_E_ARG, "no batched plan fits for D=%u", ctx->dims);
     }
+    // the default depth keeps the stream within the planner's budget: with so many hash ids
+    // that one cycle of them does not fit, every step is drawn in-lane
+    if (srv->batched && !cfg.stream_depth && srv->plan.stream_bytes(cfg.k) > kStreamBudgetBytes)
+        srv->plan.stream_depth = 0;
     hipError_t e = hipSuccess;
     if (srv->batched) {
         srv->grid = (uint32_t)(ctx->cu_count * std::max(1, batched_blocks_per_cu(ctx->dims, srv->plan)));
-        const size_t bytes = srv->plan.stream_bytes(cfg.k);
-        e = hipMalloc(&srv->d_stream, bytes);
-        if (e == hipSuccess)
-            e = launch_stream_build(bounds_view(ctx), cfg.seed, cfg.k, srv->plan.stream_depth,
-                                    srv->plan.packed, srv->plan.scale(),
-                                    srv->plan.coarse ? srv->plan.coarse_bits : 0u, srv->d_stream,
-                                    ctx->own_stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(ctx->own_stream);
+        if (srv->plan.stream_depth) {
+            e = hipMalloc(&srv->d_stream, srv->plan.stream_bytes(cfg.k));
+            if (e == hipSuccess)
+                e = launch_stream_build(bounds_view(ctx), cfg.seed, cfg.k, srv->plan.stream_depth,
+                                        srv->plan.packed, srv->plan.scale(),
+                                        srv->plan.coarse ? srv->plan.coarse_bits : 0u,
+                                        srv->d_stream, ctx->own_stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(ctx->own_stream);
+        }
     }
     srv->slots.resize(cfg.slots);
     for (Slot &slot : srv->slots) {

@@ -386,3 +386,22 @@ def test_bad_request_inside_a_group(ctx, corpus):
     assert st["rejected"] == 2 and st["failed"] == 0 and st["completed"] == len(good)
     for rows, r in zip(row_lists, good):
         assert np.array_equal(r.sig, _oracle_sig(corpus, rows, k, seed))
+
+
+def test_largest_k_request(ctx):
+    """A serving loop at k = 2^24 keeps no shared stream (one cycle of its hash ids would exceed
+    the stream's 1 GiB) and draws every step in-lane: rows with x = m in every dimension hash to
+    1 everywhere (Def. 1), and a later request is served the same way."""
+    m = np.array([5, 1, 300, 7, 65535], dtype=np.uint32)
+    ds = synth.csr_from_dense(np.stack([m, m, m]), m=m)
+    ctx.set_bounds(m)
+    k = 1 << 24
+    with serve.Server(ctx, k, seed=3, slots=2, mode="batched") as srv:
+        reqs = serve.requests_from_corpus(ds, [np.array([0, 2]), np.array([1])], srv)
+        for r in reqs:
+            srv.submit(r)
+        for r in reqs:
+            assert srv.wait(r.ticket) >= 0
+    for r, n in zip(reqs, (2, 1)):
+        assert r.sig.shape == (n, k)
+        assert np.all(r.sig == 1)
