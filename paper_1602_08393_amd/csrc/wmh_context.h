@@ -140,6 +140,10 @@ struct wmh_ctx {
     uint64_t *d_prefix = nullptr;
     uint32_t *d_bucket = nullptr;
     uint32_t *d_bound = nullptr;
+    // per block of kBoundBlock components: the smallest bound, then (after all minima) the
+    // rounded mean bound; for the validation pass when m does not fit in LDS (nullptr when D
+    // is small enough for m itself, or too large for the table)
+    uint32_t *d_bound_blocks = nullptr;
     // per-call scratch
     wmh::CheckWords *d_check = nullptr;
     wmh::CheckWords *h_check = nullptr;  // pinned

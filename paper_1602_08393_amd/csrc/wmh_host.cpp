@@ -273,7 +273,7 @@ wmh_status gather_stats(wmh_ctx *ctx, const Rows &rows, uint32_t k, hipStream_t 
     hipError_t e = launch_check_init(words, s);
     if (e == hipSuccess)
         e = launch_validate(rows, ctx->d_bound, ctx->dims, ctx->total, k, want_keys, words, s,
-                            want_split ? &split : nullptr);
+                            want_split ? &split : nullptr, ctx->d_bound_blocks);
     if (e == hipSuccess)
         e = hipMemcpyAsync(ctx->h_check, words, sizeof(CheckWords), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -429,9 +429,11 @@ void release_bounds(wmh_ctx *ctx)
     if (ctx->d_prefix) hipFree(ctx->d_prefix);
     if (ctx->d_bucket) hipFree(ctx->d_bucket);
     if (ctx->d_bound) hipFree(ctx->d_bound);
+    if (ctx->d_bound_blocks) hipFree(ctx->d_bound_blocks);
     ctx->d_prefix = nullptr;
     ctx->d_bucket = nullptr;
     ctx->d_bound = nullptr;
+    ctx->d_bound_blocks = nullptr;
     ctx->has_bounds = false;
 }
 
@@ -622,6 +624,25 @@ wmh_status wmh_set_bounds(wmh_ctx *ctx, const uint32_t *m, uint32_t D)
     WMH_HIP(ctx, hipMemcpy(ctx->d_bucket, bucket.data(), bucket.size() * sizeof(uint32_t),
                            hipMemcpyHostToDevice));
     WMH_HIP(ctx, hipMemcpy(ctx->d_bound, m, (size_t)D * sizeof(uint32_t), hipMemcpyHostToDevice));
+    if (bound_blocks_wanted(D)) {
+        // per block of kBoundBlock components: the smallest bound, then the rounded mean
+        const uint32_t nb = (D + kBoundBlock - 1) / kBoundBlock;
+        std::vector<uint32_t> blocks(2 * (size_t)nb);
+        for (uint32_t b = 0; b < nb; ++b) {
+            const uint32_t lo = b * kBoundBlock, hi = std::min(D, lo + kBoundBlock);
+            uint32_t mn = m[lo];
+            uint64_t sum = 0;
+            for (uint32_t i = lo; i < hi; ++i) {
+                mn = std::min(mn, m[i]);
+                sum += m[i];
+            }
+            blocks[b] = mn;
+            blocks[nb + b] = (uint32_t)((sum + (hi - lo) / 2) / (hi - lo));
+        }
+        WMH_HIP(ctx, hipMalloc(&ctx->d_bound_blocks, blocks.size() * sizeof(uint32_t)));
+        WMH_HIP(ctx, hipMemcpy(ctx->d_bound_blocks, blocks.data(), blocks.size() * sizeof(uint32_t),
+                               hipMemcpyHostToDevice));
+    }
     ctx->dims = D;
     ctx->total = total;
     ctx->threshold = threshold;

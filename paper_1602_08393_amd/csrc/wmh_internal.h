@@ -106,9 +106,21 @@ struct BatchedPlan {
 // Checks the rows and gathers the statistics of CheckWords (M = total, for the cost estimates);
 // index_keys only with want_keys (it is left at 0 otherwise).
 // With split (want_keys must be set) it also classes every row and fills the per-class words.
+// bound_blocks: the per-block minima and means of the bounds (bound_block_table), or nullptr.
 hipError_t launch_validate(const Rows &rows, const uint32_t *bound, uint32_t dims, uint64_t total,
                            uint32_t k, bool want_keys, CheckWords *words, hipStream_t stream,
-                           const RowSplit *split = nullptr);
+                           const RowSplit *split = nullptr,
+                           const uint32_t *bound_blocks = nullptr);
+
+// Components per block of the validation pass's block table, and whether a table is kept for
+// D components: when m does not fit in the pass's LDS but the table (two words per block) does.
+constexpr uint32_t kBoundBlock = 32;
+constexpr size_t kValidateLdsMax = 76 * 1024;
+inline bool bound_blocks_wanted(uint32_t dims)
+{
+    const uint64_t blocks = ((uint64_t)dims + kBoundBlock - 1) / kBoundBlock;
+    return (uint64_t)dims * 4 > kValidateLdsMax && blocks * 8 <= kValidateLdsMax;
+}
 
 hipError_t launch_plain(const Bounds &b, const Rows &rows, uint64_t row_begin,
                         uint64_t row_end, uint32_t k, uint64_t seed, uint16_t *sig, bool narrow,

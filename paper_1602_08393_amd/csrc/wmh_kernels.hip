@@ -77,10 +77,18 @@ __device__ __forceinline__ uint64_t wave_min(uint64_t v)
 
 // ---------------------------------------------------------------------------------------------
 // Validation: one wavefront per row, grid-stride over rows.  kKeys: also estimate the index
-// keys (needed only when the component index is a candidate path).
+// keys (needed only when the component index is a candidate path).  Where the bounds m come
+// from (kBounds): kBoundsGlobal gathers them from memory, kBoundsLds copies m to LDS first,
+// kBoundsBlocks copies the per-block table (the smallest and the mean bound of each block of
+// kBoundBlock components) to LDS: a value at or below its block's smallest bound passes without
+// its own bound, only larger values gather theirs, and the index-key estimate takes the block
+// means in place of the row's bounds (an estimate that only steers the path choice).
 // ---------------------------------------------------------------------------------------------
-template <bool kKeys, bool kLdsBounds>
+constexpr int kBoundsGlobal = 0, kBoundsLds = 1, kBoundsBlocks = 2;
+
+template <bool kKeys, int kBounds>
 __global__ __launch_bounds__(1024) void validate_kernel(Rows rows, const uint32_t *__restrict__ bound_in,
+                                                        const uint32_t *__restrict__ blocks_in,
                                                         uint32_t dims, uint64_t total,
                                                         double log_final, CheckWords *words,
                                                         RowSplit split)
@@ -91,15 +99,20 @@ __global__ __launch_bounds__(1024) void validate_kernel(Rows rows, const uint32_
     // the per-class words of a row split: walk min green, walk rows, walk steps, index rows,
     // index nonzeros, index keys
     __shared__ unsigned long long part_split[6][1024 / kWave];
-    // kLdsBounds: the workgroup first copies the bounds to LDS, so the check val <= m[col]
-    // gathers from LDS instead of memory
+    // kBoundsLds: the workgroup first copies the bounds to LDS, so the check val <= m[col]
+    // gathers from LDS instead of memory; kBoundsBlocks: the same for the block table
     extern __shared__ uint32_t lds_bound[];
     const uint32_t *bound = bound_in;
-    if constexpr (kLdsBounds) {
+    const uint32_t n_blocks = (dims + kBoundBlock - 1) / kBoundBlock;
+    if constexpr (kBounds == kBoundsLds) {
         for (uint32_t i = threadIdx.x; i < dims; i += blockDim.x) lds_bound[i] = bound_in[i];
         __syncthreads();
         bound = lds_bound;
+    } else if constexpr (kBounds == kBoundsBlocks) {
+        for (uint32_t i = threadIdx.x; i < 2 * n_blocks; i += blockDim.x) lds_bound[i] = blocks_in[i];
+        __syncthreads();
     }
+    const uint32_t *block_min = lds_bound, *block_mean = lds_bound + n_blocks;
     const uint32_t waves = blockDim.x / kWave;
     const uint64_t first = (uint64_t)blockIdx.x * waves + wave_index();
     const uint64_t stride = (uint64_t)gridDim.x * waves;
@@ -142,8 +155,19 @@ __global__ __launch_bounds__(1024) void validate_kernel(Rows rows, const uint32_
                 }
             }
             const uint32_t prev = g > lo ? rows.col[g - 1] : 0u;
+            uint32_t mk[kPer];  // the bound the index-key estimate takes
+            if constexpr (kBounds == kBoundsBlocks) {
+                // a value above its block's smallest bound gathers its own bound
 #pragma unroll
-            for (uint32_t i = 0; i < kPer; ++i) m[i] = c[i] < dims ? bound[c[i]] : 0u;
+                for (uint32_t i = 0; i < kPer; ++i) {
+                    const uint32_t b = c[i] < dims ? block_min[c[i] / kBoundBlock] : 0u;
+                    m[i] = c[i] < dims && v[i] > b ? bound_in[c[i]] : b;
+                    mk[i] = c[i] < dims ? block_mean[c[i] / kBoundBlock] : 0u;
+                }
+            } else {
+#pragma unroll
+                for (uint32_t i = 0; i < kPer; ++i) mk[i] = m[i] = c[i] < dims ? bound[c[i]] : 0u;
+            }
 #pragma unroll
             for (uint32_t i = 0; i < kPer; ++i) {
                 const uint64_t e = g + i;
@@ -155,7 +179,7 @@ __global__ __launch_bounds__(1024) void validate_kernel(Rows rows, const uint32_
                 else if (v[i] > m[i]) code = kCheckBound;
                 if (code && bad == ~0ull) bad = ((e - lo) << 4) | code;
                 sum += v[i];
-                if (kKeys) sum_m += v[i] ? m[i] : 0u;
+                if (kKeys) sum_m += v[i] ? mk[i] : 0u;
             }
         }
         if (__builtin_amdgcn_ballot_w64(bad != ~0ull) != 0) {  // some entry of the row is bad
@@ -617,40 +641,52 @@ __global__ __launch_bounds__(256) void estimate_kernel(const uint16_t *__restric
 
 hipError_t launch_validate(const Rows &rows, const uint32_t *bound, uint32_t dims, uint64_t total,
                            uint32_t k, bool want_keys, CheckWords *words, hipStream_t stream,
-                           const RowSplit *split)
+                           const RowSplit *split, const uint32_t *bound_blocks)
 {
     const RowSplit sp = split ? *split : RowSplit{};
     if (sp.row_class && !want_keys) return hipErrorInvalidValue;
     if (rows.n_rows == 0) return hipSuccess;
     // the index's final step bound per row
     const double log_final = std::log(kIndexFinalMiss / (double)k);
-    // bounds in LDS up to 76 KB: two workgroups of 16 wavefronts per CU keep it fully
-    // occupied (measured on the histogram workload: 268 -> 174 us)
-    constexpr size_t kLdsBoundsMax = 76 * 1024;
-    const bool lds = (size_t)dims * 4 <= kLdsBoundsMax;
+    // bounds (or the block table) in LDS up to 76 KB: two workgroups of 16 wavefronts per CU
+    // keep it fully occupied (measured on the histogram workload: 268 -> 174 us)
+    const uint32_t n_blocks = (dims + kBoundBlock - 1) / kBoundBlock;
+    const int mode = (size_t)dims * 4 <= kValidateLdsMax ? kBoundsLds
+                     : bound_blocks && (size_t)n_blocks * 8 <= kValidateLdsMax ? kBoundsBlocks
+                                                                               : kBoundsGlobal;
     static bool configured = false;
-    if (lds && !configured) {
-        for (const void *f : {(const void *)validate_kernel<true, true>,
-                              (const void *)validate_kernel<false, true>}) {
-            const hipError_t e =
-                hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBoundsMax);
+    if (mode != kBoundsGlobal && !configured) {
+        for (const void *f : {(const void *)validate_kernel<true, kBoundsLds>,
+                              (const void *)validate_kernel<false, kBoundsLds>,
+                              (const void *)validate_kernel<true, kBoundsBlocks>,
+                              (const void *)validate_kernel<false, kBoundsBlocks>}) {
+            const hipError_t e = hipFuncSetAttribute(
+                f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kValidateLdsMax);
             if (e != hipSuccess) return e;
         }
         configured = true;
     }
-    const uint32_t threads = lds ? 1024 : 256;
+    const uint32_t threads = mode != kBoundsGlobal ? 1024 : 256;
     const uint64_t waves_needed = rows.n_rows;
     const uint32_t per_block = threads / kWave;
     const uint32_t grid = (uint32_t)std::min<uint64_t>((waves_needed + per_block - 1) / per_block,
                                                        8192 / per_block);
-    const size_t shm = lds ? (size_t)dims * 4 : 0;
+    const size_t shm = mode == kBoundsLds      ? (size_t)dims * 4
+                       : mode == kBoundsBlocks ? (size_t)n_blocks * 8
+                                               : 0;
+#define WMH_VALIDATE(KEYS, MODE)                                                                  \
+    validate_kernel<KEYS, MODE><<<grid, threads, shm, stream>>>(rows, bound, bound_blocks, dims,  \
+                                                                total, log_final, words, sp)
     if (want_keys) {
-        if (lds) validate_kernel<true, true><<<grid, threads, shm, stream>>>(rows, bound, dims, total, log_final, words, sp);
-        else validate_kernel<true, false><<<grid, threads, 0, stream>>>(rows, bound, dims, total, log_final, words, sp);
+        if (mode == kBoundsLds) WMH_VALIDATE(true, kBoundsLds);
+        else if (mode == kBoundsBlocks) WMH_VALIDATE(true, kBoundsBlocks);
+        else WMH_VALIDATE(true, kBoundsGlobal);
     } else {
-        if (lds) validate_kernel<false, true><<<grid, threads, shm, stream>>>(rows, bound, dims, total, log_final, words, sp);
-        else validate_kernel<false, false><<<grid, threads, 0, stream>>>(rows, bound, dims, total, log_final, words, sp);
+        if (mode == kBoundsLds) WMH_VALIDATE(false, kBoundsLds);
+        else if (mode == kBoundsBlocks) WMH_VALIDATE(false, kBoundsBlocks);
+        else WMH_VALIDATE(false, kBoundsGlobal);
     }
+#undef WMH_VALIDATE
     return hipGetLastError();
 }
 

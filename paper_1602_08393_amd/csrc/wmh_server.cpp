@@ -245,7 +245,8 @@ wmh_status wmh_server::launch_check(Slot &slot)
     const bool want_keys = cfg.mode == WMH_MODE_AUTO && index_fits(cfg.k);
     if (e == hipSuccess) e = launch_check_init(slot.d_check, s);
     if (e == hipSuccess)
-        e = launch_validate(rows, ctx->d_bound, ctx->dims, ctx->total, k, want_keys, slot.d_check, s);
+        e = launch_validate(rows, ctx->d_bound, ctx->dims, ctx->total, k, want_keys, slot.d_check, s,
+                            nullptr, ctx->d_bound_blocks);
     if (e == hipSuccess)
         e = hipMemcpyAsync(slot.h_check, slot.d_check, sizeof(CheckWords), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipEventRecord(slot.checked, s);
