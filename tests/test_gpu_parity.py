@@ -553,6 +553,44 @@ def test_empty_rows_and_empty_batch(ctx):
     ctx.hash_into(rows, 10, 0, torch.empty(0, dtype=torch.int16, device=DEV))
 
 
+@pytest.mark.parametrize("D", [19456, 19457, 311296, 311297])
+def test_validation_bound_modes(ctx, D):
+    """The validation pass takes the bounds from LDS up to D = 19456, from a per-block table
+    of their minima and means (blocks of 32 components) up to D = 311296, and from memory above:
+    at both edges, values at their bound, at the block's smallest bound and between it and
+    their own hash as the oracle does under the plain walk and auto, and a value one above its
+    bound fails with WMH_E_BOUND at its row in both modes, the output untouched."""
+    rng = np.random.Generator(np.random.PCG64(D))
+    m = rng.integers(50, 100000, size=D).astype(np.uint32)
+    m[::5] = 7  # small bounds beside large ones in every block
+    N, k, seed = 24, 24, 3
+    cols, vals = [], []
+    for r in range(N):
+        c = np.sort(rng.choice(D, size=int(rng.integers(1, 400)), replace=False)).astype(np.uint32)
+        kind = r % 3
+        v = m[c] if kind == 0 else np.minimum(m[c], 7) if kind == 1 else np.maximum(1, m[c] // 3)
+        cols.append(c)
+        vals.append(v.astype(np.uint32))
+    ds = synth.csr_from_lists(cols, vals, D, m=m, name=f"modes-{D}", k=k)
+    want = oracle.hash_csr(ds.m, ds.row_ptr, ds.col, ds.val, k, seed=seed)
+    for mode in ("plain", "auto"):
+        assert_same(gpu_sig(ctx, ds, k, seed, mode=mode), want, f"D={D} {mode}")
+    big = np.flatnonzero(m > 1000)
+    c_bad = int(big[len(big) // 2])
+    bad = synth.csr_from_lists(cols[:9] + [np.array([c_bad], np.uint32)] + cols[10:],
+                               vals[:9] + [np.array([int(m[c_bad]) + 1], np.uint32)] + vals[10:],
+                               D, m=m)
+    ctx.set_bounds(m)
+    rows = wmh.upload_dataset(bad, DEV)
+    for mode in ("plain", "auto"):
+        sig = torch.full((N, k), 0x5A5A, dtype=torch.int16, device=DEV)
+        with pytest.raises(wmh.WMHError) as e:
+            ctx.hash_into(rows, k, seed, sig, opts=ctx.make_opts(mode=mode))
+        assert e.value.name == "WMH_E_BOUND", ctx.last_error()
+        assert "row 9" in ctx.last_error(), ctx.last_error()
+        assert torch.all(sig == 0x5A5A)
+
+
 def test_largest_dimension(ctx):
     """D at its largest, 2^26, with the last bound at 2^32 - 1 (the last piece, the end of the
     prefix P and of the bucket table): a row of 2^20 + 2 nonzeros spread over the whole range,
