@@ -181,7 +181,9 @@ void wmh_destroy(wmh_ctx *ctx);
  *   D : number of dimensions, 1 <= D <= 2^26.
  * Builds on the device the prefix sums P[0..D] (uint64), the total M = P[D] (must be >= 1),
  * the uniform bucket table T over [0, M) used for the O(1) position-to-component lookup
- * (Algorithm 5), and the bounded-draw threshold 2^64 mod M.  Replaces earlier bounds; bounds
+ * (Algorithm 5), and the bounded-draw threshold 2^64 mod M; for 19456 < D <= 311296 also the
+ * smallest and the mean bound of each block of 32 dimensions, which the validation pass keeps
+ * in LDS when m itself does not fit there.  Replaces earlier bounds; bounds
  * identical to the current ones change nothing (cached graphs and indexes stay valid).
  * Synchronous.  Errors: WMH_E_ARG (null, D out of range, a serving loop of this context is
  * alive), WMH_E_OVERFLOW (M = 0), WMH_E_NOMEM, WMH_E_DEVICE.
